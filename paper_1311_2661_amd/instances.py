@@ -1,0 +1,370 @@
+"""Seeded synthetic LP instances shaped like the paper's workloads.
+
+This module only draws graphs and writes the LP relaxations of Section 2 and
+Appendix B (vertex cover, independent set as set packing, multiway cut) in a
+plain row-compressed form.  It holds none of the solver's arithmetic: both
+the HIP path and the oracle consume what it returns.
+
+Every draw goes through ``numpy.random.Generator(Philox(seed))`` so a seed
+fixes an instance on every machine.
+
+LP convention (the problem statement of Section 3.1 plus bounds and
+inequality rows, Appendix C):
+
+    minimise  c^T x
+    subject to  A_i x  (>= | <= | =)  b_i      per row, ``sense`` +1 / -1 / 0
+                0 <= x_j <= u_j                (u_j may be +inf)
+                optional simplex blocks: x_B in Delta_k, some blocks fixed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "LPInstance", "rng_for", "er_edges", "ba_edges", "regular_edges",
+    "grid_edges", "vc_lp", "mis_lp", "mc_grid_lp", "vc_er", "vc_ba",
+    "mis_regular", "mc_grid", "serving_trace",
+]
+
+
+@dataclass
+class LPInstance:
+    m: int                      # rows
+    n: int                      # structural columns
+    row_ptr: np.ndarray         # int64[m+1]
+    col_idx: np.ndarray         # int32[nnz], ascending inside each row
+    val: Optional[np.ndarray]   # float64[nnz] or None (all entries are 1)
+    b: np.ndarray               # float64[m]
+    c: np.ndarray               # float64[n]
+    u: np.ndarray               # float64[n] (np.inf allowed)
+    sense: np.ndarray           # int8[m]: +1 '>=', -1 '<=', 0 '='
+    # simplex blocks (multiway cut): block t owns columns
+    # block_first_col[t] .. block_first_col[t]+k-1
+    block_first_col: Optional[np.ndarray] = None   # int64[nblocks]
+    block_k: int = 0
+    fixed_label: Optional[np.ndarray] = None       # int32[nblocks], -1 = free
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+
+def rng_for(seed: int, stream: int = 0) -> np.random.Generator:
+    """Philox-backed generator; ``stream`` separates independent draws."""
+    return np.random.Generator(np.random.Philox(key=np.array([seed, stream], dtype=np.uint64)))
+
+
+# ----------------------------------------------------------------------------
+# graphs
+# ----------------------------------------------------------------------------
+
+def er_edges(n: int, m: int, seed: int) -> np.ndarray:
+    """G(n, m): m distinct unordered pairs u<v drawn without replacement.
+
+    Returns int64[m, 2] sorted by (u, v)."""
+    total = n * (n - 1) // 2
+    if m > total:
+        raise ValueError("m exceeds the number of vertex pairs")
+    rng = rng_for(seed, 1)
+    k = np.sort(rng.choice(total, size=m, replace=False))
+    # pair index k enumerates (0,1),(0,2)..(0,n-1),(1,2).. ; row u starts at
+    # start[u] = u*n - u*(u+1)/2
+    u_all = np.arange(n, dtype=np.int64)
+    start = u_all * n - u_all * (u_all + 1) // 2
+    u = np.searchsorted(start, k, side="right") - 1
+    v = k - start[u] + u + 1
+    return np.stack([u, v], axis=1).astype(np.int64)
+
+
+def _resolve_refs(val: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Pointer jumping: entries with ref>=0 copy val of the entry they point
+    to (which may itself point further back)."""
+    val = val.copy()
+    ref = ref.copy()
+    pending = np.nonzero(ref >= 0)[0]
+    while pending.size:
+        r = ref[pending]
+        nxt = ref[r]
+        done = nxt < 0
+        hit = pending[done]
+        val[hit] = val[r[done]]
+        miss = pending[~done]
+        ref[hit] = -1
+        ref[miss] = nxt[~done]
+        pending = miss
+    return val
+
+
+def ba_edges(n: int, seed: int, m_per_node: int = 3) -> np.ndarray:
+    """Barabasi-Albert graph with preferential attachment.
+
+    Start from the complete graph on m_per_node+1 vertices; every later
+    vertex t attaches to m_per_node distinct earlier vertices, each picked
+    proportionally to degree by drawing a uniform position in the endpoint
+    list of all edges created before t (duplicates are re-drawn).  Edges are
+    numbered in creation order and stored as (t, target), so the rows of a
+    new vertex are contiguous.
+
+    The endpoint-list positions are drawn up front and resolved by pointer
+    jumping (a position that lands on an earlier target copies that
+    target), which keeps the 2M-vertex case vectorised."""
+    q = m_per_node
+    s0 = q + 1
+    if n < s0:
+        raise ValueError("n too small")
+    seed_edges = [(i, j) for i in range(s0) for j in range(i + 1, s0)]
+    E0 = len(seed_edges)
+    E = E0 + q * (n - s0)
+    src = np.empty(E, dtype=np.int64)
+    dst = np.empty(E, dtype=np.int64)
+    src[:E0] = [e[0] for e in seed_edges]
+    dst[:E0] = [e[1] for e in seed_edges]
+    k = np.arange(E0, E, dtype=np.int64)
+    t = s0 + (k - E0) // q
+    src[E0:] = t
+    # endpoint-list length before vertex t's edges
+    avail = 2 * (E0 + q * (t - s0))
+    rng = rng_for(seed, 2)
+    todo = np.arange(E0, E, dtype=np.int64)
+    pos = np.zeros(E, dtype=np.int64)
+    while True:
+        pos[todo] = np.floor(rng.random(todo.size) * avail[todo - E0]).astype(np.int64)
+        val = dst.copy()
+        ref = np.full(E, -1, dtype=np.int64)
+        p = pos[E0:]
+        even = (p & 1) == 0
+        idx = np.arange(E0, E)
+        val[idx[even]] = src[p[even] >> 1]
+        ref[idx[~even]] = p[~even] >> 1
+        dst_new = _resolve_refs(val, ref)
+        d3 = dst_new[E0:].reshape(-1, q)
+        # duplicates within a vertex's targets: re-draw every later copy
+        bad = np.zeros_like(d3, dtype=bool)
+        for a in range(q):
+            for b in range(a + 1, q):
+                bad[:, b] |= d3[:, a] == d3[:, b]
+        if not bad.any():
+            dst = dst_new
+            break
+        todo = E0 + np.nonzero(bad.reshape(-1))[0]
+    return np.stack([src, dst], axis=1)
+
+
+def regular_edges(n: int, d: int, seed: int) -> np.ndarray:
+    """Random simple d-regular graph (n*d even): a random pairing of the n*d
+    stubs, then every self-loop or repeated pair is removed by a double-edge
+    swap with a uniformly chosen edge, accepted only if it creates no new
+    defect."""
+    if (n * d) % 2:
+        raise ValueError("n*d must be even")
+    rng = rng_for(seed, 3)
+    stubs = np.repeat(np.arange(n, dtype=np.int64), d)
+    rng.shuffle(stubs)
+    e = stubs.reshape(-1, 2)
+    e.sort(axis=1)
+    M = e.shape[0]
+    key = e[:, 0] * n + e[:, 1]
+    from collections import Counter
+    cnt = Counter(key.tolist())
+
+    def is_bad(i):
+        return e[i, 0] == e[i, 1] or cnt[int(e[i, 0] * n + e[i, 1])] > 1
+
+    bad = [i for i in range(M) if is_bad(i)]
+    guard = 0
+    while bad:
+        guard += 1
+        if guard > 200 * M + 10000:
+            raise RuntimeError("regular graph repair did not converge")
+        i = bad.pop()
+        if not is_bad(i):
+            continue
+        j = int(rng.integers(M))
+        if j == i:
+            bad.append(i)
+            continue
+        a, b = int(e[i, 0]), int(e[i, 1])
+        c_, d_ = int(e[j, 0]), int(e[j, 1])
+        if rng.random() < 0.5:
+            c_, d_ = d_, c_
+        n1 = (min(a, c_), max(a, c_))
+        n2 = (min(b, d_), max(b, d_))
+        if n1[0] == n1[1] or n2[0] == n2[1] or n1 == n2:
+            bad.append(i)
+            continue
+        k1 = n1[0] * n + n1[1]
+        k2 = n2[0] * n + n2[1]
+        if cnt.get(k1, 0) > 0 or cnt.get(k2, 0) > 0:
+            bad.append(i)
+            continue
+        for kk in (a * n + b if a <= b else b * n + a, min(c_, d_) * n + max(c_, d_)):
+            cnt[kk] -= 1
+        cnt[k1] = cnt.get(k1, 0) + 1
+        cnt[k2] = cnt.get(k2, 0) + 1
+        e[i] = n1
+        e[j] = n2
+        if is_bad(i):
+            bad.append(i)
+        if is_bad(j):
+            bad.append(j)
+        # the removed pair (a, b) may have been a duplicate of another edge
+    order = np.lexsort((e[:, 1], e[:, 0]))
+    return e[order]
+
+
+def grid_edges(side: int) -> np.ndarray:
+    """4-connected side x side grid, pixel p = i*side + j.  Horizontal edges
+    first (row-major), then vertical edges."""
+    i, j = np.meshgrid(np.arange(side), np.arange(side - 1), indexing="ij")
+    p = (i * side + j).reshape(-1)
+    h = np.stack([p, p + 1], axis=1)
+    i, j = np.meshgrid(np.arange(side - 1), np.arange(side), indexing="ij")
+    p = (i * side + j).reshape(-1)
+    v = np.stack([p, p + side], axis=1)
+    return np.concatenate([h, v]).astype(np.int64)
+
+
+# ----------------------------------------------------------------------------
+# LP relaxations
+# ----------------------------------------------------------------------------
+
+def _edge_rows(edges: np.ndarray):
+    e = np.sort(edges, axis=1)
+    M = e.shape[0]
+    row_ptr = np.arange(0, 2 * M + 1, 2, dtype=np.int64)
+    col_idx = e.reshape(-1).astype(np.int32)
+    return M, row_ptr, col_idx
+
+
+def vc_lp(n: int, edges: np.ndarray, weights: np.ndarray, meta=None) -> LPInstance:
+    """Vertex-cover LP relaxation (Section 2): min c^T x,
+    x_u + x_v >= 1 per edge, 0 <= x <= 1."""
+    M, row_ptr, col_idx = _edge_rows(edges)
+    return LPInstance(m=M, n=n, row_ptr=row_ptr, col_idx=col_idx, val=None,
+                      b=np.ones(M), c=np.asarray(weights, dtype=np.float64).copy(),
+                      u=np.ones(n), sense=np.ones(M, dtype=np.int8),
+                      meta=dict(meta or {}, kind="vc", edges=edges))
+
+
+def mis_lp(n: int, edges: np.ndarray, weights: np.ndarray, meta=None) -> LPInstance:
+    """Independent-set LP (set packing, Appendix B) written as a minimisation:
+    min -w^T x, x_u + x_v <= 1 per edge, 0 <= x <= 1."""
+    M, row_ptr, col_idx = _edge_rows(edges)
+    return LPInstance(m=M, n=n, row_ptr=row_ptr, col_idx=col_idx, val=None,
+                      b=np.ones(M), c=-np.asarray(weights, dtype=np.float64),
+                      u=np.ones(n), sense=-np.ones(M, dtype=np.int8),
+                      meta=dict(meta or {}, kind="mis", edges=edges))
+
+
+def mc_grid_lp(n_vertices: int, edges: np.ndarray, edge_w: np.ndarray,
+               terminals: np.ndarray, meta=None) -> LPInstance:
+    """Linearised multiway-cut LP (Appendix B).
+
+    Columns: x_v^i at v*k+i (simplex block of vertex v), then z_e^i at
+    n_vertices*k + e*k + i.  Per edge e=(u,v), u<v, and label i two rows
+        z - x_u^i + x_v^i >= 0      and      z + x_u^i - x_v^i >= 0,
+    objective 1/2 c_e per z_e^i, z in [0,1], x_v in Delta_k, terminal
+    block t_i fixed at the i-th unit vector."""
+    k = len(terminals)
+    E = edges.shape[0]
+    e = np.sort(edges, axis=1)
+    nx = n_vertices * k
+    n = nx + E * k
+    M = 2 * E * k
+    lab = np.arange(k, dtype=np.int64)
+    xu = (e[:, 0:1] * k + lab).reshape(-1)           # [E*k]
+    xv = (e[:, 1:2] * k + lab).reshape(-1)
+    z = nx + np.arange(E * k, dtype=np.int64)
+    cols = np.empty((E * k, 2, 3), dtype=np.int64)
+    vals = np.empty((E * k, 2, 3), dtype=np.float64)
+    cols[:, 0] = np.stack([xu, xv, z], axis=1)
+    vals[:, 0] = [-1.0, 1.0, 1.0]
+    cols[:, 1] = np.stack([xu, xv, z], axis=1)
+    vals[:, 1] = [1.0, -1.0, 1.0]
+    row_ptr = np.arange(0, 3 * M + 1, 3, dtype=np.int64)
+    c = np.zeros(n)
+    c[nx:] = 0.5 * np.repeat(np.asarray(edge_w, dtype=np.float64), k)
+    fixed = np.full(n_vertices, -1, dtype=np.int32)
+    fixed[np.asarray(terminals)] = np.arange(k, dtype=np.int32)
+    return LPInstance(m=M, n=n, row_ptr=row_ptr, col_idx=cols.reshape(-1).astype(np.int32),
+                      val=vals.reshape(-1), b=np.zeros(M), c=c, u=np.ones(n),
+                      sense=np.ones(M, dtype=np.int8),
+                      block_first_col=np.arange(n_vertices, dtype=np.int64) * k,
+                      block_k=k, fixed_label=fixed,
+                      meta=dict(meta or {}, kind="mc", edges=edges, edge_w=edge_w,
+                                terminals=np.asarray(terminals), n_vertices=n_vertices))
+
+
+# ----------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------
+
+def vc_er(n: int = 1000, m: int = 5000, seed: int = 0) -> LPInstance:
+    """Vertex cover on G(n, m), weights uniform[1,10]."""
+    edges = er_edges(n, m, seed)
+    w = rng_for(seed, 10).uniform(1.0, 10.0, n)
+    return vc_lp(n, edges, w, meta=dict(graph="er", seed=seed))
+
+
+def vc_ba(n: int = 2_000_000, seed: int = 0, m_per_node: int = 3) -> LPInstance:
+    """Vertex cover on a Barabasi-Albert graph, weights uniform[1,10]."""
+    edges = ba_edges(n, seed, m_per_node)
+    w = rng_for(seed, 10).uniform(1.0, 10.0, n)
+    return vc_lp(n, edges, w, meta=dict(graph="ba", seed=seed))
+
+
+def mis_regular(n: int, d: int, seed: int) -> LPInstance:
+    """Weighted independent set on a random d-regular graph, weights
+    uniform[1,5] (n is bumped by one when n*d is odd)."""
+    if (n * d) % 2:
+        n += 1
+    edges = regular_edges(n, d, seed)
+    w = rng_for(seed, 11).uniform(1.0, 5.0, n)
+    return mis_lp(n, edges, w, meta=dict(graph="regular", d=d, seed=seed))
+
+
+def mc_grid(side: int = 1024, k: int = 8, seed: int = 0) -> LPInstance:
+    """Multiway cut on a side x side 4-connected grid with k terminals at
+    distinct random pixels; edge weight exp(-d^2), d ~ N(0,1)."""
+    edges = grid_edges(side)
+    rng = rng_for(seed, 12)
+    d = rng.standard_normal(edges.shape[0])
+    w = np.exp(-d * d)
+    terminals = rng.choice(side * side, size=k, replace=False)
+    return mc_grid_lp(side * side, edges, w, terminals, meta=dict(graph="grid", side=side, seed=seed))
+
+
+def serving_trace(n_requests: int, rate: float, seed: int,
+                  min_edges: float = 1e3, max_edges: float = 1e6):
+    """Poisson arrivals (exponential gaps) of mixed requests.
+
+    Returns a list of dicts {t_arrival, kind, edges, seed}: kind uniform over
+    vc / mis / mc, edge count log-uniform in [min_edges, max_edges]."""
+    rng = rng_for(seed, 13)
+    gaps = rng.exponential(1.0 / rate, n_requests)
+    t = np.cumsum(gaps)
+    kinds = rng.integers(0, 3, n_requests)
+    m = np.exp(rng.uniform(np.log(min_edges), np.log(max_edges), n_requests))
+    names = ["vc", "mis", "mc"]
+    return [dict(t_arrival=float(t[i]), kind=names[kinds[i]], edges=int(m[i]),
+                 seed=int(seed * 1_000_003 + i)) for i in range(n_requests)]
+
+
+def serving_instance(req: dict) -> LPInstance:
+    """Materialise one serving request: VC on G(m/5, m), independent set on a
+    6-regular graph with n = m/3, or multiway cut (k=8) on a grid with about
+    m/2 pixels per side squared."""
+    m = req["edges"]
+    s = req["seed"]
+    if req["kind"] == "vc":
+        n = max(10, m // 5)
+        return vc_er(n, min(m, n * (n - 1) // 2), s)
+    if req["kind"] == "mis":
+        n = max(10, m // 3)
+        return mis_regular(n, 6, s)
+    side = max(4, int(round(np.sqrt(m / 2.0))))
+    return mc_grid(side, 8, s)
