@@ -1,0 +1,249 @@
+/*
+ * thetis.h -- C ABI of libthetis, an MI355X (gfx950) implementation of the
+ * solve step of "An Approximate, Efficient LP Solver for LP Rounding"
+ * (Sridhar, Bittorf, Liu, Zhang, Re, Wright): stochastic coordinate descent
+ * on the quadratic-penalty form of a sparse LP relaxation, followed by the
+ * pre-rounding scaling, the rounding and the feasibility check.
+ *
+ * Conventions for every call:
+ *   - Every call returns a thetis_status: THETIS_OK (0) or a negative code.
+ *     thetis_last_error() gives a message for the calling thread's last
+ *     failure.  No C++ exception crosses this boundary.
+ *   - Pointers named *_host are host memory owned by the caller; the library
+ *     copies what it needs before the call returns and keeps no reference.
+ *   - Device work is enqueued on the solver's stream (a hipStream_t passed
+ *     as void*, NULL = the null stream).  Calls that hand host values back
+ *     synchronise that stream before they return.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - After an error the handle stays valid, except after THETIS_EDEVICE.
+ */
+#ifndef THETIS_H
+#define THETIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t thetis_status;
+enum {
+    THETIS_OK = 0,
+    THETIS_EINVAL = -1,       /* bad argument or malformed instance          */
+    THETIS_ENOMEM = -2,       /* host or device allocation failed, or the
+                                 caller's workspace is too small              */
+    THETIS_EDEVICE = -3,      /* HIP runtime error; the handle is unusable     */
+    THETIS_EDIVERGED = -4,    /* NaN or Inf in a residual/objective reduction  */
+    THETIS_EBUSY = -5,        /* a handle is in use by a batch                 */
+    THETIS_EBUDGET = -6,      /* device-memory budget exceeded (serving)       */
+    THETIS_EUNSUPPORTED = -7  /* valid request outside what this build does    */
+};
+
+typedef struct thetis_inst thetis_inst;       /* host-side instance, library owned */
+typedef struct thetis_solver thetis_solver;   /* device state of one solve         */
+typedef struct thetis_batch thetis_batch;     /* several solvers run as one launch */
+
+/* step rules of Section 3.3 */
+enum {
+    THETIS_STEP_PER_COORD = 0,    /* 1/L_j, L_j = beta ||A_j||^2 + rho: the exact
+                                     minimiser along coordinate j             */
+    THETIS_STEP_GLOBAL_LMAX = 1   /* 1/Lmax, Lmax of eq. (Lmax), as in Algorithm 1 */
+};
+/* update schedules (Section 3.4, asynchronous parallel SCD) */
+enum {
+    THETIS_SCHED_DET = 0,   /* colour classes of units with disjoint rows, the
+                               class order drawn per epoch; race-free and
+                               reproducible: equal to serial SCD in that order */
+    THETIS_SCHED_ASYNC = 1  /* all units of an epoch at once, residual updated
+                               with hardware float atomics (lock-free)        */
+};
+/* storage precision of y = (x, s) and of the running residual r */
+enum {
+    THETIS_PREC_FP32 = 0,   /* x, s, r in FP32; refresh and reductions in FP64 */
+    THETIS_PREC_FP64 = 1,   /* everything in FP64 (validation build)          */
+    THETIS_PREC_BF16X = 2   /* x in BF16, s and r in FP32                     */
+};
+/* rounding rules */
+enum {
+    THETIS_ROUND_VC_THRESH = 1,   /* vertex cover: keep v iff x_v >= T,
+                                     T = min(1/2, min_e (x_u+x_v)/2)           */
+    THETIS_ROUND_MIS_THRESH = 2,  /* independent set: keep v iff x_v > T',
+                                     T' = max(1/2, max_e (x_u+x_v)/2)          */
+    THETIS_ROUND_MIS_RAND = 3,    /* independent set: scale by 1/(1+alpha), keep
+                                     v with probability x~_v, drop conflicts    */
+    THETIS_ROUND_MC_CKR = 4       /* multiway cut: region growing from terminals */
+};
+
+/* Solver parameters.  The penalty function is eq. (QP) of Section 3.2 with
+ * slacks for inequality rows:
+ *   F(y) = c^T x - ubar^T (A y - b) + beta/2 ||A y - b||^2 + rho/2 ||y - ybar||^2
+ * with rho = 0 (prox off) or rho = 1/beta (prox on), y in the box / simplex. */
+typedef struct {
+    double beta;            /* penalty parameter, > 0                               */
+    int32_t step_rule;      /* THETIS_STEP_*                                         */
+    double step_scale;      /* gamma in (0, 1]: step gamma/L                          */
+    int32_t prox;           /* 0: rho = 0; 1: rho = 1/beta                            */
+    const double *ybar;     /* host, n+m entries (x then one slack per row), or NULL = 0 */
+    const double *ubar;     /* host, m entries, or NULL = 0                          */
+    int32_t schedule;       /* THETIS_SCHED_*                                        */
+    int32_t precision;      /* THETIS_PREC_*                                         */
+    int32_t refresh_every;  /* epochs between FP64 recomputations of r = Ay - b (>=1) */
+    uint64_t seed;          /* Philox key for the class order and the rounding draws */
+} thetis_params;
+
+/* Fills the defaults: beta 10, per-coordinate step, gamma 1, prox off, DET,
+ * FP32, refresh every 5 epochs, seed 0. */
+thetis_status thetis_params_default(thetis_params *p);
+
+/* --------------------------------------------------------------- instance */
+
+/* Creates an LP instance (standard form of Section 3.1 with bounds and
+ * inequality rows, Appendix C):
+ *     min c^T x   s.t.  A_i x (>= | <= | =) b_i,   0 <= x_j <= u_j.
+ * m rows, n columns, CSR with nnz entries: row_ptr_host[m+1] (int64,
+ * row_ptr[0] = 0, non-decreasing), col_idx_host[nnz] in [0, n) with no
+ * repeated column inside a row, val_host[nnz] (NULL: every entry is 1),
+ * b_host[m], c_host[n], u_host[n] (NULL: +inf; entries >= 0 or +inf),
+ * sense_host[m] (+1 '>=', -1 '<=', 0 '='; NULL: all '=').  One slack column
+ * is appended per inequality row (-1 for '>=', +1 for '<='), bounded below
+ * by 0.  All inputs are copied.  Limits: nnz < 2^31, n + m < 2^31.
+ * Errors: THETIS_EINVAL for non-finite data, indices out of range or a bad
+ * row_ptr; THETIS_ENOMEM. */
+thetis_status thetis_inst_create_csr(int64_t m, int64_t n, int64_t nnz,
+                                     const int64_t *row_ptr_host, const int32_t *col_idx_host,
+                                     const double *val_host, const double *b_host,
+                                     const double *c_host, const double *u_host,
+                                     const int8_t *sense_host, thetis_inst **out);
+
+/* Declares simplex blocks (multiway cut, Appendix B; block coordinate
+ * descent with projection onto the k-simplex, Appendix E): block t owns the
+ * k consecutive columns first_col_host[t] .. first_col_host[t]+k-1, which
+ * must not overlap.  fixed_label_host[t] >= 0 pins block t at the unit
+ * vector of that label (a terminal); -1 leaves it free; NULL = all free.
+ * 1 <= k <= 64.  Must be called before any solver is created. */
+thetis_status thetis_inst_set_simplex_blocks(thetis_inst *inst, int64_t nblocks, int32_t k,
+                                             const int64_t *first_col_host,
+                                             const int32_t *fixed_label_host);
+
+/* Number of colour classes of the DET schedule (greedy colouring of the
+ * update units in index order, all slack units in one last class) and the
+ * class of every unit: units are the free simplex blocks and the columns
+ * outside blocks in increasing column order, then the slack of every
+ * inequality row in row order.  class_host may be NULL; otherwise it needs
+ * room for thetis_inst_num_units() entries. */
+thetis_status thetis_inst_classes(const thetis_inst *inst, int32_t *nclasses, int64_t *nunits,
+                                  int32_t *class_host);
+
+thetis_status thetis_inst_destroy(thetis_inst *inst);
+
+/* ----------------------------------------------------------------- solver */
+
+/* Device bytes a solver of this instance and these parameters needs. */
+thetis_status thetis_solver_workspace_bytes(const thetis_inst *inst, const thetis_params *p,
+                                            size_t *bytes);
+
+/* Creates a solver: uploads the instance layout to the current HIP device
+ * and sets y = 0 (fixed blocks at their unit vector), r = A y - b.
+ * dev_workspace: caller-owned device memory of ws_bytes >= the size above
+ * (for example a torch tensor), kept for the solver's life; NULL = the
+ * library allocates and frees it.  stream: hipStream_t or NULL.
+ * Errors: THETIS_EINVAL (bad parameters), THETIS_ENOMEM, THETIS_EDEVICE. */
+thetis_status thetis_solver_create(const thetis_inst *inst, const thetis_params *p,
+                                   void *dev_workspace, size_t ws_bytes, void *stream,
+                                   thetis_solver **out);
+
+/* Back to the starting point (y = 0, epoch 0) without re-uploading. */
+thetis_status thetis_solver_reset(thetis_solver *s);
+
+/* Changes beta (recomputes every L_j) or the step rule between epochs. */
+thetis_status thetis_set_beta(thetis_solver *s, double beta);
+thetis_status thetis_set_step_rule(thetis_solver *s, int32_t rule, double step_scale);
+
+/* Runs up to max_epochs epochs of SCD (Algorithm 1; an epoch updates every
+ * unit once).  Every refresh_every epochs r is recomputed from y in FP64
+ * and, when gap_tol > 0, the run stops once the certified relative gap
+ * (F - Phi)/max(1,|F|) <= gap_tol (Phi is the dual bound of the penalty
+ * problem).  epochs_done (may be NULL) receives the count.
+ * THETIS_EDIVERGED if a refresh sees NaN or Inf. */
+thetis_status thetis_run_epochs(thetis_solver *s, int32_t max_epochs, double gap_tol,
+                                int32_t *epochs_done);
+
+/* Residual norms of the slack form, ||A y - b||_inf and ||.||_2, and the
+ * largest violation of an original row by x (Definition of an
+ * (eps,delta)-approximate solution, Section 3.1).  Computed in FP64 from
+ * y; does not change the solver state. */
+thetis_status thetis_residual(thetis_solver *s, double *linf, double *l2,
+                              double *max_row_violation);
+
+/* c^T x, the penalty value F(y) and the dual bound Phi <= min F (FP64). */
+thetis_status thetis_objective(thetis_solver *s, double *lp_value, double *penalty,
+                               double *dual_bound);
+
+/* Copies y to the host: x_host[n] (structural) and, if s_host is not NULL,
+ * s_host[m] (slacks), converted to double. */
+thetis_status thetis_get_x(thetis_solver *s, double *x_host, double *s_host);
+
+/* Replaces y by y_host[n+m] (rounded to the storage precision) and
+ * recomputes r.  Entries are clipped to their bounds. */
+thetis_status thetis_set_y(thetis_solver *s, const double *y_host);
+
+/* Epochs run since creation or reset. */
+thetis_status thetis_epoch(const thetis_solver *s, int64_t *epoch);
+
+/* Pre-rounding pass and rounding of the current x (Section 2, Lemma
+ * infeasible:rounded:vc, Appendix B and C) into sol_host: 0/1 per column
+ * for the VC and MIS rules (n entries), a label per simplex block for
+ * MC_CKR (nblocks entries); sol_host may be NULL.  reps >= 1 draws for the
+ * randomised rules, keeping the cheapest (ties: first).  cost = c^T sol
+ * (for MC: the cut weight).  aux_host (NULL or 2 doubles) gets the
+ * threshold T (or alpha, or the region radius) and the winning repetition.
+ * THETIS_EINVAL when the instance does not have the rule's shape (VC/MIS:
+ * every row x_u + x_v with b = 1 and the rule's sense; MC: blocks). */
+thetis_status thetis_round(thetis_solver *s, int32_t rule, uint64_t seed, int32_t reps,
+                           int32_t *sol_host, double *cost, double *aux_host);
+
+/* Feasibility of an integer solution for the original problem: every row
+ * of A (VC, MIS: A sol vs b by sense) or every label valid and every
+ * terminal on its own label (MC).  sol_host = NULL checks the solution of
+ * the last thetis_round on the device. */
+thetis_status thetis_check_feasible(thetis_solver *s, int32_t rule, const int32_t *sol_host,
+                                    int32_t *feasible, int64_t *n_violated);
+
+/* Kernel groups for timing and traffic figures. */
+enum {
+    THETIS_K_SWEEP_GROUP = 0,   /* lane-group coordinate kernel (columns <= 64 entries) */
+    THETIS_K_SWEEP_HUB = 1,     /* workgroup-per-column kernel (columns > 64 entries)  */
+    THETIS_K_SWEEP_BLOCK = 2,   /* simplex-block kernel                                */
+    THETIS_K_SWEEP_SLACK = 3,   /* slack kernel                                        */
+    THETIS_K_REFRESH = 4,       /* FP64 refresh + reductions (three launches)          */
+    THETIS_K_NKINDS = 5
+};
+
+/* Turns per-launch HIP-event timing on or off (events are recorded on the
+ * solver's stream around every launch of thetis_run_epochs). */
+thetis_status thetis_set_timing(thetis_solver *s, int32_t enable);
+
+/* For kernel group `kind`, over the last thetis_run_epochs with timing on:
+ * the summed device time of its launches (ms), the launch count, and the
+ * algorithmic bytes those launches moved (the traffic a perfect cache would
+ * see: column pointers, row indices, residual entries read and written,
+ * y read and written, costs).  Average bytes/launch over average
+ * time/launch is the kernel's achieved algorithmic bandwidth. */
+thetis_status thetis_get_timing(const thetis_solver *s, int32_t kind, double *ms, int64_t *launches,
+                                double *alg_bytes);
+
+/* Algorithmic bytes of one epoch's coordinate updates (all sweep kernels)
+ * and of one refresh, and the coordinate updates per epoch. */
+thetis_status thetis_epoch_traffic(const thetis_solver *s, double *sweep_bytes,
+                                   double *refresh_bytes, int64_t *updates_per_epoch);
+
+thetis_status thetis_solver_destroy(thetis_solver *s);
+
+/* Message describing the calling thread's last failed call ("" if none). */
+const char *thetis_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* THETIS_H */

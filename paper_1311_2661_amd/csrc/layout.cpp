@@ -1,0 +1,322 @@
+// Host-side instance layout of libthetis: validation, slack augmentation,
+// the column-compressed copy of A, the update units and their greedy
+// colouring into conflict-free classes, and the per-class work plan that
+// the class-sweep kernels execute.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "thetis_internal.h"
+
+namespace thetis {
+
+static thread_local std::string g_last_error;
+
+thetis_status fail(thetis_status code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+void clear_error() { g_last_error.clear(); }
+
+// ------------------------------------------------------------------ Philox
+void philox_host(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round) { k0 += Philox4x64::W0; k1 += Philox4x64::W1; }
+        const unsigned __int128 p0 = (unsigned __int128)Philox4x64::M0 * x0;
+        const unsigned __int128 p1 = (unsigned __int128)Philox4x64::M1 * x2;
+        const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        x0 = hi1 ^ x1 ^ k0; x1 = lo1; x2 = hi0 ^ x3 ^ k1; x3 = lo0;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+uint64_t philox_word_host(uint64_t seed, uint64_t stream, uint64_t c0, uint64_t c1, uint64_t c2) {
+    const uint64_t ctr[4] = {c0, c1, c2, 0}, key[2] = {seed, stream};
+    uint64_t out[4];
+    philox_host(ctr, key, out);
+    return out[0];
+}
+
+void class_order(int32_t nclasses, uint64_t seed, int64_t epoch, int32_t *order) {
+    std::vector<std::pair<uint64_t, int32_t>> k(nclasses);
+    for (int32_t c = 0; c < nclasses; ++c)
+        k[c] = {philox_word_host(seed, RNG_CLASS_ORDER, (uint64_t)epoch, (uint64_t)c, 0), c};
+    std::sort(k.begin(), k.end());
+    for (int32_t c = 0; c < nclasses; ++c) order[c] = k[c].second;
+}
+
+// ------------------------------------------------------------------ layout
+
+static void build_csc(Inst &in) {
+    in.col_ptr.assign(in.n + 1, 0);
+    for (int64_t e = 0; e < in.nnz; ++e) in.col_ptr[in.col_idx[e] + 1]++;
+    for (int64_t j = 0; j < in.n; ++j) in.col_ptr[j + 1] += in.col_ptr[j];
+    in.row_idx.resize(in.nnz);
+    if (!in.unit_vals) in.cval.resize(in.nnz);
+    std::vector<int32_t> fill(in.col_ptr.begin(), in.col_ptr.end() - 1);
+    for (int64_t i = 0; i < in.m; ++i)
+        for (int32_t e = in.row_ptr[i]; e < in.row_ptr[i + 1]; ++e) {
+            const int32_t j = in.col_idx[e];
+            in.row_idx[fill[j]] = (int32_t)i;
+            if (!in.unit_vals) in.cval[fill[j]] = in.val[e];
+            fill[j]++;
+        }
+    in.max_col_degree = 0;
+    for (int64_t j = 0; j < in.n; ++j)
+        in.max_col_degree = std::max<int64_t>(in.max_col_degree, in.col_ptr[j + 1] - in.col_ptr[j]);
+}
+
+// Units in unit order and a greedy colouring: unit t takes the smallest
+// colour not held by an earlier unit that shares a row with it.  Slack
+// units (one per inequality row) all go to one extra, last class: they
+// touch one row each, all different.
+static void colour_units(Inst &in) {
+    const int64_t n = in.n, m = in.m;
+    in.ukind.clear(); in.uid.clear(); in.ucolour.clear();
+    std::vector<int32_t> unit_of_col(n, -1);
+    for (int64_t j = 0; j < n; ++j) {
+        const int32_t bl = in.nblocks ? in.col_block[j] : -1;
+        if (bl >= 0) {
+            if (in.fixed[bl] >= 0) continue;
+            if (j == in.bfirst[bl]) { in.ukind.push_back(1); in.uid.push_back(bl); }
+            unit_of_col[j] = (int32_t)in.ukind.size() - 1;
+        } else {
+            in.ukind.push_back(0); in.uid.push_back((int32_t)j);
+            unit_of_col[j] = (int32_t)in.ukind.size() - 1;
+        }
+    }
+    in.nstruct_units = (int64_t)in.ukind.size();
+    in.ucolour.assign(in.nstruct_units, 0);
+    std::vector<int64_t> stamp(64, -1);
+    int32_t ncol = 0;
+    for (int64_t t = 0; t < in.nstruct_units; ++t) {
+        int64_t j0, j1;
+        if (in.ukind[t] == 1) { j0 = in.bfirst[in.uid[t]]; j1 = j0 + in.k; }
+        else { j0 = in.uid[t]; j1 = j0 + 1; }
+        for (int64_t j = j0; j < j1; ++j)
+            for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e) {
+                const int32_t i = in.row_idx[e];
+                for (int32_t q = in.row_ptr[i]; q < in.row_ptr[i + 1]; ++q) {
+                    const int32_t o = unit_of_col[in.col_idx[q]];
+                    if (o >= 0 && o < t) stamp[in.ucolour[o]] = t;
+                }
+            }
+        int32_t cc = 0;
+        while (cc < (int32_t)stamp.size() && stamp[cc] == t) ++cc;
+        if (cc == (int32_t)stamp.size()) stamp.resize(stamp.size() * 2, -1);
+        in.ucolour[t] = cc;
+        ncol = std::max(ncol, cc + 1);
+    }
+    bool any_slack = false;
+    in.all_rows_slack = true;
+    for (int64_t i = 0; i < m; ++i) {
+        if (in.sense[i] != 0) {
+            in.ukind.push_back(2); in.uid.push_back((int32_t)i); in.ucolour.push_back(ncol);
+            any_slack = true;
+        } else {
+            in.all_rows_slack = false;
+        }
+    }
+    in.nunits = (int64_t)in.ukind.size();
+    in.nclasses = ncol + (any_slack ? 1 : 0);
+}
+
+static int32_t column_kind(int64_t d) {
+    if (d >= kHubMinDegree) return SEG_HUB;
+    for (int g = 0; g < kGroupKinds; ++g)
+        if (d <= kGroupLanes[g]) return g;
+    return SEG_HUB;
+}
+
+// Splits a list of units into per-kind segments (unit order kept inside
+// each kind) appended to `sched`.
+static ClassPlan plan_units(const Inst &in, const std::vector<int64_t> &units,
+                            std::vector<int32_t> &sched) {
+    ClassPlan cp;
+    std::vector<std::vector<int32_t>> by(SEG_NKIND);
+    for (int64_t t : units) {
+        const int8_t kd = in.ukind[t];
+        const int32_t id = in.uid[t];
+        int32_t sk;
+        if (kd == 2) sk = SEG_SLACK;
+        else if (kd == 1) sk = SEG_BLOCK;
+        else sk = column_kind(in.col_ptr[id + 1] - in.col_ptr[id]);
+        by[sk].push_back(id);
+    }
+    for (int32_t sk = 0; sk < SEG_NKIND; ++sk) {
+        if (by[sk].empty()) continue;
+        Segment s;
+        s.kind = sk;
+        s.first = (int64_t)sched.size();
+        s.count = (int64_t)by[sk].size();
+        sched.insert(sched.end(), by[sk].begin(), by[sk].end());
+        cp.segs.push_back(s);
+    }
+    return cp;
+}
+
+thetis_status build_layout(Inst &in) {
+    try {
+        build_csc(in);
+        colour_units(in);
+        in.sched.clear();
+        in.classes.assign(in.nclasses, ClassPlan());
+        std::vector<std::vector<int64_t>> members(in.nclasses);
+        for (int64_t t = 0; t < in.nunits; ++t) members[in.ucolour[t]].push_back(t);
+        for (int32_t c = 0; c < in.nclasses; ++c) in.classes[c] = plan_units(in, members[c], in.sched);
+        in.async_sched.clear();
+        std::vector<int64_t> st, sl;
+        for (int64_t t = 0; t < in.nunits; ++t) (in.ukind[t] == 2 ? sl : st).push_back(t);
+        in.async_struct = plan_units(in, st, in.async_sched);
+        in.async_slack = plan_units(in, sl, in.async_sched);
+        in.planned = true;
+    } catch (const std::bad_alloc &) {
+        return fail(THETIS_ENOMEM, "host allocation failed while building the layout");
+    }
+    return THETIS_OK;
+}
+
+}  // namespace thetis
+
+using namespace thetis;
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" const char *thetis_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" thetis_status thetis_params_default(thetis_params *p) {
+    if (!p) return fail(THETIS_EINVAL, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->beta = 10.0;
+    p->step_rule = THETIS_STEP_PER_COORD;
+    p->step_scale = 1.0;
+    p->prox = 0;
+    p->schedule = THETIS_SCHED_DET;
+    p->precision = THETIS_PREC_FP32;
+    p->refresh_every = 5;
+    p->seed = 0;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_inst_create_csr(int64_t m, int64_t n, int64_t nnz,
+                                                const int64_t *row_ptr, const int32_t *col_idx,
+                                                const double *val, const double *b,
+                                                const double *c, const double *u,
+                                                const int8_t *sense, thetis_inst **out) {
+    clear_error();
+    if (!out) return fail(THETIS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (m < 0 || n < 0 || nnz < 0) return fail(THETIS_EINVAL, "negative size");
+    if (nnz >= (int64_t(1) << 31) || n + m >= (int64_t(1) << 31))
+        return fail(THETIS_EUNSUPPORTED, "nnz and n+m must stay below 2^31");
+    if (!row_ptr || (nnz && !col_idx) || (m && !b) || (n && !c))
+        return fail(THETIS_EINVAL, "missing array");
+    if (row_ptr[0] != 0 || row_ptr[m] != nnz) return fail(THETIS_EINVAL, "row_ptr must run from 0 to nnz");
+    thetis_inst *h = new (std::nothrow) thetis_inst;
+    if (!h) return fail(THETIS_ENOMEM, "host allocation failed");
+    Inst &in = h->in;
+    try {
+        in.m = m; in.n = n; in.nnz = nnz;
+        in.row_ptr.resize(m + 1);
+        for (int64_t i = 0; i <= m; ++i) {
+            if (i && row_ptr[i] < row_ptr[i - 1]) { delete h; return fail(THETIS_EINVAL, "row_ptr decreases"); }
+            in.row_ptr[i] = (int32_t)row_ptr[i];
+        }
+        in.col_idx.assign(col_idx, col_idx + nnz);
+        std::vector<int64_t> seen(n, -1);
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                const int32_t j = col_idx[e];
+                if (j < 0 || j >= n) { delete h; return fail(THETIS_EINVAL, "column index out of range"); }
+                if (seen[j] == i) { delete h; return fail(THETIS_EINVAL, "column repeated inside a row"); }
+                seen[j] = i;
+            }
+        in.unit_vals = true;
+        if (val) {
+            for (int64_t e = 0; e < nnz; ++e) {
+                if (!std::isfinite(val[e])) { delete h; return fail(THETIS_EINVAL, "non-finite matrix entry"); }
+                if (val[e] != 1.0) in.unit_vals = false;
+            }
+            if (!in.unit_vals) in.val.assign(val, val + nnz);
+        }
+        in.b.assign(b, b + m);
+        in.c.assign(c, c + n);
+        for (int64_t i = 0; i < m; ++i)
+            if (!std::isfinite(b[i])) { delete h; return fail(THETIS_EINVAL, "non-finite b"); }
+        for (int64_t j = 0; j < n; ++j)
+            if (!std::isfinite(c[j])) { delete h; return fail(THETIS_EINVAL, "non-finite c"); }
+        in.u.assign(n, INFINITY);
+        if (u) {
+            for (int64_t j = 0; j < n; ++j) {
+                if (std::isnan(u[j]) || u[j] < 0) { delete h; return fail(THETIS_EINVAL, "upper bounds must be >= 0 or +inf"); }
+                in.u[j] = u[j];
+            }
+        }
+        in.uniform_ub = true;
+        in.ub_value = n ? in.u[0] : 1.0;
+        for (int64_t j = 1; j < n; ++j) if (in.u[j] != in.ub_value) in.uniform_ub = false;
+        in.sense.assign(m, 0);
+        if (sense)
+            for (int64_t i = 0; i < m; ++i) {
+                if (sense[i] < -1 || sense[i] > 1) { delete h; return fail(THETIS_EINVAL, "sense must be -1, 0 or +1"); }
+                in.sense[i] = sense[i];
+            }
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return fail(THETIS_ENOMEM, "host allocation failed");
+    }
+    thetis_status st = build_layout(in);
+    if (st != THETIS_OK) { delete h; return st; }
+    *out = h;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_inst_set_simplex_blocks(thetis_inst *h, int64_t nblocks, int32_t k,
+                                                        const int64_t *first,
+                                                        const int32_t *fixed_label) {
+    clear_error();
+    if (!h) return fail(THETIS_EINVAL, "instance is NULL");
+    Inst &in = h->in;
+    if (in.has_solver) return fail(THETIS_EBUSY, "blocks must be set before any solver is created");
+    if (k < 1 || k > 64) return fail(THETIS_EUNSUPPORTED, "block size k must be in [1, 64]");
+    if (nblocks < 0 || (nblocks && !first)) return fail(THETIS_EINVAL, "bad block list");
+    std::vector<int32_t> cb(in.n, -1), bf(nblocks), fx(nblocks, -1);
+    for (int64_t t = 0; t < nblocks; ++t) {
+        if (first[t] < 0 || first[t] + k > in.n) return fail(THETIS_EINVAL, "block out of range");
+        bf[t] = (int32_t)first[t];
+        if (fixed_label) {
+            if (fixed_label[t] < -1 || fixed_label[t] >= k) return fail(THETIS_EINVAL, "fixed label out of range");
+            fx[t] = fixed_label[t];
+        }
+        for (int32_t i = 0; i < k; ++i) {
+            if (cb[first[t] + i] != -1) return fail(THETIS_EINVAL, "blocks overlap");
+            cb[first[t] + i] = (int32_t)t;
+        }
+    }
+    for (int64_t t = 0; t < nblocks; ++t)
+        for (int32_t i = 0; i < k; ++i)
+            if (in.u[bf[t] + i] < 1.0)
+                return fail(THETIS_EINVAL, "simplex block columns need an upper bound of at least 1");
+    in.nblocks = nblocks; in.k = k;
+    in.bfirst.swap(bf); in.fixed.swap(fx); in.col_block.swap(cb);
+    return build_layout(in);
+}
+
+extern "C" thetis_status thetis_inst_classes(const thetis_inst *h, int32_t *nclasses, int64_t *nunits,
+                                             int32_t *class_host) {
+    clear_error();
+    if (!h) return fail(THETIS_EINVAL, "instance is NULL");
+    if (nclasses) *nclasses = h->in.nclasses;
+    if (nunits) *nunits = h->in.nunits;
+    if (class_host) std::copy(h->in.ucolour.begin(), h->in.ucolour.end(), class_host);
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_inst_destroy(thetis_inst *h) {
+    delete h;
+    return THETIS_OK;
+}

@@ -1,0 +1,1675 @@
+// libthetis device path for MI355X (gfx950, CDNA4, 64-lane wavefronts).
+//
+// The solve step of "An Approximate, Efficient LP Solver for LP Rounding":
+// stochastic coordinate descent (Algorithm 1, Section 3.3) on the penalty
+// function of eq. (QP) (Section 3.2), in the asynchronous-parallel spirit of
+// Section 3.4, followed by the pre-rounding scalings (Lemma
+// infeasible:rounded:vc; Appendix C), the roundings (Section 2, Appendix B)
+// and the feasibility check.
+//
+// Kernels (all 256-thread workgroups):
+//   k_sweep_group  coordinate update of plain columns, G lanes per column
+//                  (G = 4..64 by degree): gather A_j^T r with a coalesced
+//                  index read, reduce with a lane butterfly, projected step,
+//                  scatter delta*A_j into r (plain stores inside a colour
+//                  class, hardware float atomics in the ASYNC schedule)
+//   k_sweep_hub    the same for columns above 64 entries, one workgroup per
+//                  column, residual entries staged in LDS between gather and
+//                  scatter
+//   k_sweep_block  block update with projection onto the k-simplex
+//                  (multiway cut, Appendix E), one wavefront per block
+//   k_sweep_slack  slack coordinates, one lane per inequality row
+//   k_rows / k_cols / k_finalize   FP64 residual refresh r = Ay - b fused with
+//                  the residual norms, row violation, penalty value F and the
+//                  dual bound Phi, reduced in a fixed order (deterministic)
+//   k_round_* / k_check_*          pre-rounding pass, roundings, check
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "thetis_internal.h"
+
+using namespace thetis;
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(THETIS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+// ---------------------------------------------------------------- precision
+struct PF32 { using X = float;  using R = float;  static constexpr int32_t id = THETIS_PREC_FP32; };
+struct PF64 { using X = double; using R = double; static constexpr int32_t id = THETIS_PREC_FP64; };
+
+// ---------------------------------------------------------------- device arguments
+template <class P>
+struct Dev {
+    using X = typename P::X;
+    using R = typename P::R;
+    // matrix
+    const int32_t *col_ptr, *row_idx;
+    const R *cval;            // CSC values, null when every entry is 1
+    const int32_t *row_ptr, *csr_col;
+    const R *csr_val;
+    const double *b;
+    const int8_t *sense;
+    const double *c;          // objective (FP64, for the reductions)
+    const R *ctil;            // c - A^T ubar over n + m (null: equals c, slacks 0)
+    const R *ub;              // null: every structural bound is ub_value
+    const R *norm2;           // ||A_j||^2, null when every entry is 1
+    const R *ybar;            // prox centre over n + m (null: prox off or 0)
+    const double *ubar;       // null: 0
+    const int32_t *bfirst, *fixed, *col_block;
+    const R *LB;              // block curvature bound (Gershgorin), per block
+    // state
+    X *x;
+    R *s, *r, *udual;
+    // scalars
+    R beta, rho, gamma, Lmax, ub_value;
+    int32_t global_lmax, async_mode, prox_on;
+    int64_t n, m, nblocks;
+    int32_t k;
+};
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nwg) {
+    // Workgroups are dispatched to the 8 XCDs round-robin; give each XCD a
+    // contiguous run of logical workgroups so neighbouring columns (which
+    // share residual cache lines) stay in one L2.
+    const int64_t q = nwg >> 3, rem = nwg & 7, xcd = b & 7, idx = b >> 3;
+    return xcd * q + (xcd < rem ? xcd : rem) + idx;
+}
+
+template <int G, class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const T w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <class P>
+__device__ __forceinline__ typename P::R col_bound(const Dev<P> &a, int64_t j) {
+    return a.ub ? a.ub[j] : a.ub_value;
+}
+
+// projected coordinate step, same operation order as Algorithm 1 step 4:
+// y' = clip(y - gamma g / L, 0, U); an empty column without prox moves to
+// its cheaper bound
+template <class R>
+__device__ __forceinline__ R coord_step(R y, R g, R L, R gamma, R U) {
+    R yn;
+    if (L > R(0)) yn = y - gamma * g / L;
+    else yn = g > R(0) ? R(0) : (g < R(0) ? U : y);
+    if (yn < R(0)) yn = R(0);
+    if (yn > U) yn = U;
+    return yn;
+}
+
+template <class R>
+__device__ __forceinline__ void r_add(R *p, R cur, R d, bool async_mode) {
+    if (async_mode) unsafeAtomicAdd(p, d);
+    else *p = cur + d;
+}
+
+// one plain column per group of G lanes
+template <class P, bool VALS, int G>
+__device__ __forceinline__ void sweep_group(const Dev<P> &a, const int32_t *__restrict__ list,
+                                            int64_t count, int64_t lwg) {
+    using R = typename P::R;
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t u = lwg * (kWG / G) + (threadIdx.x / G);
+    if (u >= count) return;           // the whole group leaves together
+    const int32_t j = list[u];
+    const int32_t e0 = a.col_ptr[j], e1 = a.col_ptr[j + 1];
+    R acc = R(0), r0 = R(0), v0 = R(1);
+    int32_t row0 = -1;
+    for (int32_t e = e0 + lane; e < e1; e += G) {
+        const int32_t row = a.row_idx[e];
+        const R rv = a.r[row];
+        const R v = VALS ? a.cval[e] : R(1);
+        if (row0 < 0) { row0 = row; r0 = rv; v0 = v; }
+        acc += VALS ? v * rv : rv;
+    }
+    acc = group_sum<G>(acc);
+    const R y = (R)a.x[j];
+    R g = (a.ctil ? a.ctil[j] : (R)a.c[j]) + a.beta * acc;
+    if (a.prox_on) g += a.rho * (y - (a.ybar ? a.ybar[j] : R(0)));
+    R L;
+    if (a.global_lmax) L = a.Lmax;
+    else L = a.beta * (VALS ? a.norm2[j] : (R)(e1 - e0)) + a.rho;
+    const R yn = coord_step(y, g, L, a.gamma, col_bound(a, j));
+    const R d = yn - y;
+    if (lane == 0) a.x[j] = yn;
+    if (d != R(0)) {
+        bool first = true;
+        for (int32_t e = e0 + lane; e < e1; e += G) {
+            if (first) {
+                r_add(a.r + row0, r0, VALS ? d * v0 : d, a.async_mode);
+                first = false;
+            } else {
+                const int32_t row = a.row_idx[e];
+                const R v = VALS ? a.cval[e] : R(1);
+                R *p = a.r + row;
+                r_add(p, a.async_mode ? R(0) : *p, VALS ? d * v : d, a.async_mode);
+            }
+        }
+    }
+}
+
+struct GroupPlan {
+    int64_t first[kGroupKinds];
+    int64_t count[kGroupKinds];
+    int64_t wg_start[kGroupKinds + 1];
+};
+
+template <class P, bool VALS>
+__global__ __launch_bounds__(kWG) void k_sweep_group(Dev<P> a, const int32_t *__restrict__ sched,
+                                                     GroupPlan gp) {
+    const int64_t nwg = gp.wg_start[kGroupKinds];
+    const int64_t L = xcd_remap(blockIdx.x, nwg);
+    int s = 0;
+    while (s < kGroupKinds - 1 && L >= gp.wg_start[s + 1]) ++s;
+    const int32_t *list = sched + gp.first[s];
+    const int64_t lw = L - gp.wg_start[s];
+    switch (s) {
+        case 0: sweep_group<P, VALS, 4>(a, list, gp.count[0], lw); break;
+        case 1: sweep_group<P, VALS, 8>(a, list, gp.count[1], lw); break;
+        case 2: sweep_group<P, VALS, 16>(a, list, gp.count[2], lw); break;
+        case 3: sweep_group<P, VALS, 32>(a, list, gp.count[3], lw); break;
+        default: sweep_group<P, VALS, 64>(a, list, gp.count[4], lw); break;
+    }
+}
+
+// High-degree columns: one workgroup each; the gathered residual entries and
+// their rows are staged in LDS so the scatter does not re-read global memory.
+constexpr int kHubTile = 2048;
+
+template <class P, bool VALS>
+__global__ __launch_bounds__(kWG) void k_sweep_hub(Dev<P> a, const int32_t *__restrict__ list,
+                                                   int64_t count) {
+    using R = typename P::R;
+    __shared__ R st_r[kHubTile];
+    __shared__ int32_t st_row[kHubTile];
+    __shared__ R red[kWG / 64];
+    const int tid = threadIdx.x;
+    for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
+        const int32_t j = list[u];
+        const int32_t e0 = a.col_ptr[j], e1 = a.col_ptr[j + 1];
+        R acc = R(0);
+        for (int32_t e = e0 + tid; e < e1; e += kWG) {
+            const int32_t row = a.row_idx[e];
+            const R rv = a.r[row];
+            const int32_t q = e - e0;
+            if (q < kHubTile) { st_r[q] = rv; st_row[q] = row; }
+            acc += VALS ? a.cval[e] * rv : rv;
+        }
+        acc = group_sum<64>(acc);
+        if ((tid & 63) == 0) red[tid >> 6] = acc;
+        __syncthreads();
+        R tot = red[0];
+#pragma unroll
+        for (int w = 1; w < kWG / 64; ++w) tot += red[w];
+        __syncthreads();
+        const R y = (R)a.x[j];
+        R g = (a.ctil ? a.ctil[j] : (R)a.c[j]) + a.beta * tot;
+        if (a.prox_on) g += a.rho * (y - (a.ybar ? a.ybar[j] : R(0)));
+        R L;
+        if (a.global_lmax) L = a.Lmax;
+        else L = a.beta * (VALS ? a.norm2[j] : (R)(e1 - e0)) + a.rho;
+        const R yn = coord_step(y, g, L, a.gamma, col_bound(a, j));
+        const R d = yn - y;
+        if (tid == 0) a.x[j] = yn;
+        if (d != R(0)) {
+            for (int32_t e = e0 + tid; e < e1; e += kWG) {
+                const int32_t q = e - e0;
+                const R dv = VALS ? d * a.cval[e] : d;
+                if (q < kHubTile) r_add(a.r + st_row[q], st_r[q], dv, a.async_mode);
+                else {
+                    R *p = a.r + a.row_idx[e];
+                    r_add(p, a.async_mode ? R(0) : *p, dv, a.async_mode);
+                }
+            }
+        }
+    }
+}
+
+// Simplex block (k columns of one pixel): one wavefront.  Lanes are split
+// into k groups of LPC lanes (LPC = largest power of two <= 64/k); group i
+// forms the gradient of column i.  The projection onto the simplex uses
+// theta = max_j (P_j - 1)/c_j over the prefixes of the values sorted
+// downwards (Held, Wolfe & Crowder; Duchi et al.), every lane evaluating
+// one candidate j without sorting.
+template <class P, bool VALS>
+__global__ __launch_bounds__(kWG) void k_sweep_block(Dev<P> a, const int32_t *__restrict__ list,
+                                                     int64_t count, int32_t lpc) {
+    using R = typename P::R;
+    const int lane = threadIdx.x & 63;
+    const int64_t u = xcd_remap(blockIdx.x, gridDim.x) * (kWG / 64) + (threadIdx.x >> 6);
+    if (u >= count) return;
+    const int32_t blk = list[u];
+    const int32_t k = a.k;
+    const int ci = lane / lpc, sub = lane % lpc;
+    const bool own = ci < k;
+    const int32_t j = a.bfirst[blk] + (own ? ci : 0);
+    const int32_t e0 = own ? a.col_ptr[j] : 0, e1 = own ? a.col_ptr[j + 1] : 0;
+    R acc = R(0);
+    for (int32_t e = e0 + sub; e < e1; e += lpc) {
+        const R rv = a.r[a.row_idx[e]];
+        acc += VALS ? a.cval[e] * rv : rv;
+    }
+    for (int o = lpc / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    const R L = a.global_lmax ? a.Lmax : a.LB[blk];
+    R y = R(0), v = R(0);
+    if (own) {
+        y = (R)a.x[j];
+        R g = (a.ctil ? a.ctil[j] : (R)a.c[j]) + a.beta * acc;
+        if (a.prox_on) g += a.rho * (y - (a.ybar ? a.ybar[j] : R(0)));
+        v = L > R(0) ? y - a.gamma * g / L : y;
+    }
+    // lane q < k takes the value of column q; every shuffle runs with the
+    // whole wavefront active
+    const R vq = __shfl(v, (lane < k ? lane : 0) * lpc, 64);
+    R psum = R(0);
+    int cnt = 0;
+    for (int l = 0; l < k; ++l) {
+        const R vl = __shfl(v, l * lpc, 64);
+        if (vl > vq || (vl == vq && l <= lane)) { psum += vl; ++cnt; }
+    }
+    const R cand = lane < k ? (psum - R(1)) / (R)cnt : R(-INFINITY);
+    const R theta = wave_max(cand);
+    R w = v - theta;
+    if (w < R(0)) w = R(0);
+    const R d = own ? w - y : R(0);
+    if (own && sub == 0) a.x[j] = w;
+    if (own && d != R(0)) {
+        for (int32_t e = e0 + sub; e < e1; e += lpc) {
+            R *p = a.r + a.row_idx[e];
+            const R dv = VALS ? d * a.cval[e] : d;
+            r_add(p, a.async_mode ? R(0) : *p, dv, a.async_mode);
+        }
+    }
+}
+
+// slack s_i of an inequality row: column -e_i ('>=') or +e_i ('<='), s >= 0
+template <class P>
+__global__ __launch_bounds__(kWG) void k_sweep_slack(Dev<P> a, const int32_t *__restrict__ list,
+                                                     int64_t count) {
+    using R = typename P::R;
+    const int64_t q = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (q >= count) return;
+    const int64_t i = list ? list[q] : q;
+    const R sg = a.sense[i] > 0 ? R(-1) : R(1);
+    const R sv = a.s[i], rv = a.r[i];
+    R g = (a.ctil ? a.ctil[a.n + i] : R(0)) + a.beta * (sg * rv);
+    if (a.prox_on) g += a.rho * (sv - (a.ybar ? a.ybar[a.n + i] : R(0)));
+    const R L = a.global_lmax ? a.Lmax : a.beta + a.rho;
+    R sn = L > R(0) ? sv - a.gamma * g / L : (g > R(0) ? R(0) : sv);
+    if (sn < R(0)) sn = R(0);
+    const R d = sn - sv;
+    a.s[i] = sn;
+    if (d != R(0)) {
+        if (a.async_mode) unsafeAtomicAdd(a.r + i, sg * d);
+        else a.r[i] = rv + sg * d;
+    }
+}
+
+// ---------------------------------------------------------------- reductions
+constexpr int kRowSlots = 6;   // sum w^2, max |w|, max violation, sum b u, sum (u-ubar)^2, sum -ubar w
+constexpr int kColSlots = 3;   // sum of minima (Phi), c^T x, prox part of F
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// block reduction in fixed order into out[slot]; op 0 = sum, 1 = max
+template <int NS>
+__device__ void block_reduce(const double (&v)[NS], const int (&op)[NS], double *out) {
+    __shared__ double sh[kWG / 64][NS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const double t = op[q] ? wmax(v[q]) : wsum(v[q]);
+        if (lane == 0) sh[w][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < NS) {
+        const int q = threadIdx.x;
+        double t = sh[0][q];
+        for (int ww = 1; ww < kWG / 64; ++ww) t = op[q] ? fmax(t, sh[ww][q]) : t + sh[ww][q];
+        out[q] = t;
+    }
+}
+
+// min over [0,U] of red*y + rho/2 (y - yb)^2
+__device__ __forceinline__ double box_min(double red, double U, double rho, double yb) {
+    if (rho > 0.0) {
+        double y = yb - red / rho;
+        if (y < 0.0) y = 0.0;
+        if (y > U) y = U;
+        return red * y + 0.5 * rho * (y - yb) * (y - yb);
+    }
+    if (red >= 0.0) return 0.0;
+    return isinf(U) ? -INFINITY : red * U;
+}
+
+// Row pass: w = A x + slack - b in FP64, optionally stored as the new
+// running residual; the dual estimate u = ubar - beta w (clipped so the
+// unbounded slack columns keep a non-negative reduced cost when rho = 0),
+// rounded once to storage precision and used for every term of Phi.
+template <class P>
+__global__ __launch_bounds__(kWG) void k_rows(Dev<P> a, int32_t write_r, double *part) {
+    using R = typename P::R;
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v[kRowSlots] = {0, 0, 0, 0, 0, 0};
+    const int op[kRowSlots] = {0, 1, 1, 0, 0, 0};
+    if (i < a.m) {
+        double ax = 0.0;
+        for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
+            ax += (a.csr_val ? (double)a.csr_val[e] : 1.0) * (double)a.x[a.csr_col[e]];
+        const int8_t sn = a.sense[i];
+        double acc = ax;
+        if (sn > 0) acc -= (double)a.s[i];
+        else if (sn < 0) acc += (double)a.s[i];
+        const double w = acc - a.b[i];
+        if (write_r) a.r[i] = (R)w;
+        const double ub = a.ubar ? a.ubar[i] : 0.0;
+        double ui = ub - (double)a.beta * w;
+        if (!a.prox_on) {
+            if (sn > 0 && ui < 0.0) ui = 0.0;
+            if (sn < 0 && ui > 0.0) ui = 0.0;
+        }
+        const R ur = (R)ui;
+        a.udual[i] = ur;
+        const double ud = (double)ur;
+        v[0] = w * w;
+        v[1] = fabs(w);
+        v[2] = sn > 0 ? a.b[i] - ax : (sn < 0 ? ax - a.b[i] : fabs(ax - a.b[i]));
+        if (v[2] < 0.0) v[2] = 0.0;
+        v[3] = a.b[i] * ud;
+        v[4] = (ud - ub) * (ud - ub);
+        v[5] = -ub * w;
+    }
+    block_reduce<kRowSlots>(v, op, part + (int64_t)blockIdx.x * kRowSlots);
+}
+
+// Column pass over [columns | blocks | slacks]: c^T x, the prox part of F,
+// and per variable the minimum of its reduced-cost term over its feasible
+// set (the inner minimisation of the dual function Phi).
+template <class P>
+__global__ __launch_bounds__(kWG) void k_cols(Dev<P> a, double *part) {
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v[kColSlots] = {0, 0, 0};
+    const int op[kColSlots] = {0, 0, 0};
+    const double rho = (double)a.rho;
+    if (t < a.n) {
+        const int64_t j = t;
+        const double xj = (double)a.x[j];
+        v[1] = a.c[j] * xj;
+        const double yb = a.ybar ? (double)a.ybar[j] : 0.0;
+        if (a.prox_on) v[2] = 0.5 * rho * (xj - yb) * (xj - yb);
+        if (!(a.col_block && a.col_block[j] >= 0)) {
+            double red = a.c[j];
+            for (int32_t e = a.col_ptr[j]; e < a.col_ptr[j + 1]; ++e)
+                red -= (a.cval ? (double)a.cval[e] : 1.0) * (double)a.udual[a.row_idx[e]];
+            const double U = a.ub ? (double)a.ub[j] : (double)a.ub_value;
+            v[0] = box_min(red, U, rho, yb);
+        }
+    } else if (t < a.n + a.nblocks) {
+        const int64_t bl = t - a.n;
+        const int32_t j0 = a.bfirst[bl], k = a.k;
+        double red[64], yb[64];
+        for (int i = 0; i < k; ++i) {
+            const int32_t j = j0 + i;
+            double rr = a.c[j];
+            for (int32_t e = a.col_ptr[j]; e < a.col_ptr[j + 1]; ++e)
+                rr -= (a.cval ? (double)a.cval[e] : 1.0) * (double)a.udual[a.row_idx[e]];
+            red[i] = rr;
+            yb[i] = a.ybar ? (double)a.ybar[j] : 0.0;
+        }
+        if (a.fixed[bl] >= 0) {
+            const int f = a.fixed[bl];
+            double val = red[f];
+            if (a.prox_on)
+                for (int i = 0; i < k; ++i) {
+                    const double d = (i == f ? 1.0 : 0.0) - yb[i];
+                    val += 0.5 * rho * d * d;
+                }
+            v[0] = val;
+        } else if (a.prox_on) {
+            // minimiser of red^T y + rho/2||y - yb||^2 over the simplex:
+            // projection of yb - red/rho, theta from the sorted prefixes
+            double w[64];
+            for (int i = 0; i < k; ++i) w[i] = yb[i] - red[i] / rho;
+            double theta = -INFINITY;
+            for (int q = 0; q < k; ++q) {
+                double ps = 0.0;
+                int cnt = 0;
+                for (int l = 0; l < k; ++l)
+                    if (w[l] > w[q] || (w[l] == w[q] && l <= q)) { ps += w[l]; ++cnt; }
+                theta = fmax(theta, (ps - 1.0) / cnt);
+            }
+            double val = 0.0;
+            for (int i = 0; i < k; ++i) {
+                const double yi = fmax(w[i] - theta, 0.0);
+                val += red[i] * yi + 0.5 * rho * (yi - yb[i]) * (yi - yb[i]);
+            }
+            v[0] = val;
+        } else {
+            double mn = red[0];
+            for (int i = 1; i < k; ++i) mn = fmin(mn, red[i]);
+            v[0] = mn;
+        }
+    } else if (t < a.n + a.nblocks + a.m) {
+        const int64_t i = t - a.n - a.nblocks;
+        const int8_t sn = a.sense[i];
+        if (sn != 0) {
+            const double sv = (double)a.s[i];
+            const double yb = a.ybar ? (double)a.ybar[a.n + i] : 0.0;
+            if (a.prox_on) v[2] = 0.5 * rho * (sv - yb) * (sv - yb);
+            const double red = (sn > 0 ? 1.0 : -1.0) * (double)a.udual[i];
+            v[0] = box_min(red, INFINITY, rho, yb);
+        }
+    }
+    block_reduce<kColSlots>(v, op, part + (int64_t)blockIdx.x * kColSlots);
+}
+
+// metrics slots
+enum { MT_F = 0, MT_CX, MT_LINF, MT_L2, MT_VIOL, MT_PHI, MT_GAP, MT_BAD, MT_NSLOT = 16 };
+
+__global__ __launch_bounds__(kWG) void k_finalize(const double *rp, int64_t nr, const double *cp,
+                                                  int64_t nc, double beta, double *mt) {
+    __shared__ double sh[kWG][kRowSlots + kColSlots];
+    const int t = threadIdx.x;
+    double acc[kRowSlots + kColSlots];
+    for (int q = 0; q < kRowSlots + kColSlots; ++q) acc[q] = 0.0;
+    for (int64_t b = t; b < nr; b += kWG)
+        for (int q = 0; q < kRowSlots; ++q)
+            acc[q] = (q == 1 || q == 2) ? fmax(acc[q], rp[b * kRowSlots + q]) : acc[q] + rp[b * kRowSlots + q];
+    for (int64_t b = t; b < nc; b += kWG)
+        for (int q = 0; q < kColSlots; ++q) acc[kRowSlots + q] += cp[b * kColSlots + q];
+    for (int q = 0; q < kRowSlots + kColSlots; ++q) sh[t][q] = acc[q];
+    __syncthreads();
+    if (t == 0) {
+        double s[kRowSlots + kColSlots];
+        for (int q = 0; q < kRowSlots + kColSlots; ++q) s[q] = sh[0][q];
+        for (int u = 1; u < kWG; ++u)
+            for (int q = 0; q < kRowSlots + kColSlots; ++q)
+                s[q] = (q == 1 || q == 2) ? fmax(s[q], sh[u][q]) : s[q] + sh[u][q];
+        const double F = s[kRowSlots + 1] + s[5] + 0.5 * beta * s[0] + s[kRowSlots + 2];
+        const double phi = s[3] - s[4] / (2.0 * beta) + s[kRowSlots + 0];
+        mt[MT_F] = F;
+        mt[MT_CX] = s[kRowSlots + 1];
+        mt[MT_LINF] = s[1];
+        mt[MT_L2] = sqrt(s[0]);
+        mt[MT_VIOL] = s[2];
+        mt[MT_PHI] = phi;
+        const double den = fabs(F) > 1.0 ? fabs(F) : 1.0;
+        mt[MT_GAP] = (F - phi) / den;
+        mt[MT_BAD] = (isfinite(F) && isfinite(s[0])) ? 0.0 : 1.0;
+    }
+}
+
+// ---------------------------------------------------------------- rounding
+// edge pass for the two-entry rows: op 0 min (x_u+x_v)/2, 1 max (x_u+x_v)/2,
+// 2 max (x_u+x_v-1)
+template <class P>
+__global__ __launch_bounds__(kWG) void k_edge_extreme(Dev<P> a, int32_t op, double *part) {
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v = op == 0 ? INFINITY : -INFINITY;
+    if (i < a.m) {
+        const int32_t e = a.row_ptr[i];
+        const double xu = (double)a.x[a.csr_col[e]], xv = (double)a.x[a.csr_col[e + 1]];
+        v = op == 2 ? (xu + xv) - 1.0 : (xu + xv) * 0.5;
+    }
+    if (op == 0) v = -v;
+    v = wmax(v);
+    __shared__ double sh[kWG / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int w = 1; w < kWG / 64; ++w) t = fmax(t, sh[w]);
+        part[blockIdx.x] = op == 0 ? -t : t;
+    }
+}
+
+// 1-thread fold of the edge partials into the threshold (VC: min(1/2, m),
+// MIS: max(1/2, m), alpha: max(0, m))
+__global__ void k_edge_fold(const double *part, int64_t nb, int32_t op, double *out) {
+    if (threadIdx.x || blockIdx.x) return;
+    double t = op == 0 ? 0.5 : (op == 1 ? 0.5 : 0.0);
+    for (int64_t b = 0; b < nb; ++b) t = op == 0 ? fmin(t, part[b]) : fmax(t, part[b]);
+    *out = t;
+}
+
+__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+__device__ __forceinline__ double unit53_dev(uint64_t w) { return (double)(w >> 11) * (1.0 / 9007199254740992.0); }
+
+__device__ uint64_t philox_word_dev(uint64_t seed, uint64_t stream, uint64_t c0, uint64_t c1, uint64_t c2) {
+    uint64_t x0 = c0, x1 = c1, x2 = c2, x3 = 0, k0 = seed, k1 = stream;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round) { k0 += Philox4x64::W0; k1 += Philox4x64::W1; }
+        const uint64_t hi0 = mulhi64(Philox4x64::M0, x0), lo0 = Philox4x64::M0 * x0;
+        const uint64_t hi1 = mulhi64(Philox4x64::M1, x2), lo1 = Philox4x64::M1 * x2;
+        const uint64_t n0 = hi1 ^ x1 ^ k0, n2 = hi0 ^ x3 ^ k1;
+        x0 = n0; x1 = lo1; x2 = n2; x3 = lo0;
+    }
+    return x0;
+}
+
+// rule 1: x >= T, rule 2: x > T, rule 3: U_v < x/(1+alpha); writes 0/1 and
+// the cost partial
+template <class P>
+__global__ __launch_bounds__(kWG) void k_pick(Dev<P> a, int32_t rule, const double *thr,
+                                              uint64_t seed, int32_t rep, int32_t *sol, double *part) {
+    const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v = 0.0;
+    if (j < a.n) {
+        const double xj = (double)a.x[j];
+        int32_t keep;
+        if (rule == THETIS_ROUND_VC_THRESH) keep = xj >= *thr;
+        else if (rule == THETIS_ROUND_MIS_THRESH) keep = xj > *thr;
+        else {
+            const double xt = xj / (1.0 + *thr);
+            keep = unit53_dev(philox_word_dev(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)j, 0)) < xt;
+        }
+        sol[j] = keep;
+        v = keep ? a.c[j] : 0.0;
+    }
+    v = wsum(v);
+    __shared__ double sh[kWG / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int w = 1; w < kWG / 64; ++w) t += sh[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+// alteration: mark both ends of every row whose two vertices were picked
+template <class P>
+__global__ __launch_bounds__(kWG) void k_conflicts(Dev<P> a, const int32_t *pick, int32_t *drop) {
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= a.m) return;
+    const int32_t e = a.row_ptr[i];
+    const int32_t u = a.csr_col[e], v = a.csr_col[e + 1];
+    if (pick[u] && pick[v]) { drop[u] = 1; drop[v] = 1; }
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_apply_drop(Dev<P> a, int32_t *sol, const int32_t *drop,
+                                                    double *part) {
+    const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v = 0.0;
+    if (j < a.n) {
+        const int32_t keep = sol[j] && !drop[j];
+        sol[j] = keep;
+        v = keep ? a.c[j] : 0.0;
+    }
+    v = wsum(v);
+    __shared__ double sh[kWG / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int w = 1; w < kWG / 64; ++w) t += sh[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+// region growing: block t takes the first label of the order whose entry
+// reaches 1 - rad, else the last label of the order
+template <class P>
+__global__ __launch_bounds__(kWG) void k_ckr_label(Dev<P> a, double rad, const int32_t *order,
+                                                   int32_t *lab) {
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (t >= a.nblocks) return;
+    const int32_t j0 = a.bfirst[t], k = a.k;
+    int32_t l = order[k - 1];
+    for (int q = 0; q < k - 1; ++q) {
+        const int32_t i = order[q];
+        if ((double)a.x[j0 + i] >= 1.0 - rad) { l = i; break; }
+    }
+    lab[t] = l;
+}
+
+// cut cost read off the rows: a row holding two block columns of label li
+// and one free column charges that column's cost when exactly one of the
+// two blocks carries label li; every (edge, label) pair owns two rows
+template <class P>
+__global__ __launch_bounds__(kWG) void k_ckr_cost(Dev<P> a, const int32_t *lab, double *part) {
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v = 0.0;
+    if (i < a.m) {
+        int32_t zc = -1, b1 = -1, b2 = -1, li = -1;
+        for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e) {
+            const int32_t j = a.csr_col[e];
+            const int32_t bl = a.col_block[j];
+            if (bl < 0) zc = j;
+            else if (b1 < 0) { b1 = bl; li = j - a.bfirst[bl]; }
+            else b2 = bl;
+        }
+        if (zc >= 0 && b1 >= 0 && b2 >= 0 && ((lab[b1] == li) != (lab[b2] == li))) v = a.c[zc];
+    }
+    v = wsum(v);
+    __shared__ double sh[kWG / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int w = 1; w < kWG / 64; ++w) t += sh[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+// cost fold + keep-best decision: out[0] cost of this repetition, out[1]
+// best cost so far, out[2] 1 when this repetition became the best, out[3]
+// the best repetition (ties keep the earlier one)
+__global__ void k_cost_fold(const double *part, int64_t nb, double scale, int32_t rep, double *out) {
+    if (threadIdx.x || blockIdx.x) return;
+    double t = 0.0;
+    for (int64_t b = 0; b < nb; ++b) t += part[b];
+    t *= scale;
+    out[0] = t;
+    const int better = rep == 0 || t < out[1];
+    if (better) { out[1] = t; out[3] = (double)rep; }
+    out[2] = better ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(kWG) void k_copy_if(const double *flag, const int32_t *src, int32_t *dst,
+                                                 int64_t n) {
+    const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (j < n && flag[2] != 0.0) dst[j] = src[j];
+}
+
+// feasibility of a 0/1 solution: A sol against b, row by row
+template <class P>
+__global__ __launch_bounds__(kWG) void k_check_rows(Dev<P> a, const int32_t *sol, double *part) {
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v = 0.0;
+    if (i < a.m) {
+        double ax = 0.0;
+        for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
+            ax += (a.csr_val ? (double)a.csr_val[e] : 1.0) * (double)sol[a.csr_col[e]];
+        const int8_t sn = a.sense[i];
+        const bool ok = sn > 0 ? ax >= a.b[i] : (sn < 0 ? ax <= a.b[i] : ax == a.b[i]);
+        v = ok ? 0.0 : 1.0;
+    }
+    if (i < a.n) {
+        const int32_t sv = sol[i];
+        if (sv != 0 && sv != 1) v += 1.0;
+    }
+    v = wsum(v);
+    __shared__ double sh[kWG / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int w = 1; w < kWG / 64; ++w) t += sh[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_check_labels(Dev<P> a, const int32_t *lab, double *part) {
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v = 0.0;
+    if (t < a.nblocks) {
+        const int32_t l = lab[t];
+        if (l < 0 || l >= a.k) v = 1.0;
+        else if (a.fixed[t] >= 0 && l != a.fixed[t]) v = 1.0;
+    }
+    v = wsum(v);
+    __shared__ double sh[kWG / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t2 = sh[0];
+        for (int w = 1; w < kWG / 64; ++w) t2 += sh[w];
+        part[blockIdx.x] = t2;
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_set_start(Dev<P> a) {
+    // y = 0, fixed blocks at their unit vector; each entry is written by
+    // exactly one thread
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (t < a.n) {
+        const int32_t bl = a.col_block ? a.col_block[t] : -1;
+        const bool one = bl >= 0 && a.fixed[bl] >= 0 && t == (int64_t)a.bfirst[bl] + a.fixed[bl];
+        a.x[t] = one ? 1 : 0;
+    }
+    if (t < a.m) a.s[t] = 0;
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_load_y(Dev<P> a, const double *y) {
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    using R = typename P::R;
+    if (t < a.n) {
+        double v = y[t];
+        const double U = a.ub ? (double)a.ub[t] : (double)a.ub_value;
+        if (v < 0.0) v = 0.0;
+        if (v > U) v = U;
+        a.x[t] = (typename P::X)v;
+    }
+    if (t < a.m) {
+        double v = y[a.n + t];
+        if (v < 0.0 || a.sense[t] == 0) v = 0.0;
+        a.s[t] = (R)v;
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_store_y(Dev<P> a, double *x, double *s) {
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (t < a.n) x[t] = (double)a.x[t];
+    if (s && t < a.m) s[t] = (double)a.s[t];
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+constexpr int32_t kMaxReps = 64;
+
+}  // namespace
+
+// ==================================================================== solver
+
+struct thetis_solver {
+    // host copy of what the launches need
+    int64_t m = 0, n = 0, nnz = 0, nblocks = 0;
+    int32_t k = 0, nclasses = 0;
+    bool unit_vals = true, uniform_ub = true, all_rows_slack = true;
+    double ub_value = 1.0;
+    std::vector<ClassPlan> classes;
+    ClassPlan async_struct, async_slack;
+    int64_t sched_len = 0, async_len = 0;
+    bool edge_shape_cover = false, edge_shape_pack = false;
+    std::vector<int32_t> col_deg;     // for traffic figures
+    int64_t nunits = 0;
+    // parameters
+    thetis_params p{};
+    double rho = 0.0, Lmax = 0.0;
+    bool has_ybar = false, has_ubar = false;
+    // device
+    hipStream_t stream = nullptr;
+    bool own_ws = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    // device pointers (typed at launch)
+    void *col_ptr, *row_idx, *cval, *row_ptr, *csr_col, *csr_val, *b, *sense, *c, *ctil, *ub,
+        *norm2, *ybar, *ubar, *bfirst, *fixed, *col_block, *LB, *x, *s, *r, *udual, *sched,
+        *async_sched, *rpart, *cpart, *metrics, *sol, *best, *drop, *ckr_order, *thr, *costbuf,
+        *chkbuf, *ystage;
+    int64_t nwg_rows = 0, nwg_cols = 0;
+    int64_t epoch = 0;
+    bool metrics_fresh = false;
+    double mt[MT_NSLOT] = {0};
+    bool have_round = false;
+    int32_t last_rule = 0;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    // per kernel group: (start, stop) event indices and the algorithmic
+    // bytes of each timed launch
+    std::vector<std::pair<int, int>> ev[THETIS_K_NKINDS];
+    std::vector<double> ev_bytes[THETIS_K_NKINDS];
+    double ms[THETIS_K_NKINDS] = {0}, bytes[THETIS_K_NKINDS] = {0};
+    int64_t launches[THETIS_K_NKINDS] = {0};
+    // algorithmic bytes per launch of each class segment, by class (DET) and
+    // for the ASYNC plans
+    std::vector<std::vector<double>> seg_bytes;
+    std::vector<double> async_struct_bytes, async_slack_bytes;
+    double refresh_bytes = 0;
+};
+
+namespace {
+
+struct Carver {
+    size_t off = 0;
+    char *base = nullptr;
+    void *take(size_t bytes) {
+        off = (off + 255) & ~size_t(255);
+        void *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+size_t prec_bytes(int32_t prec) { return prec == THETIS_PREC_FP64 ? 8 : 4; }
+
+// carve the workspace in a fixed order; with base == nullptr it only sizes
+void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
+    Carver cv;
+    cv.base = base;
+    const size_t R = prec_bytes(S.p.precision), X = R;
+    const int64_t n = in.n, m = in.m, nnz = in.nnz, nb = in.nblocks;
+    S.col_ptr = cv.take(4 * (n + 1));
+    S.row_idx = cv.take(4 * std::max<int64_t>(nnz, 1));
+    S.cval = in.unit_vals ? nullptr : cv.take(R * nnz);
+    S.norm2 = in.unit_vals ? nullptr : cv.take(R * n);
+    S.row_ptr = cv.take(4 * (m + 1));
+    S.csr_col = cv.take(4 * std::max<int64_t>(nnz, 1));
+    S.csr_val = in.unit_vals ? nullptr : cv.take(R * nnz);
+    S.b = cv.take(8 * std::max<int64_t>(m, 1));
+    S.sense = cv.take(std::max<int64_t>(m, 1));
+    S.c = cv.take(8 * std::max<int64_t>(n, 1));
+    S.ctil = S.has_ubar ? cv.take(R * (n + m)) : nullptr;
+    S.ub = in.uniform_ub ? nullptr : cv.take(R * n);
+    S.ybar = S.has_ybar ? cv.take(R * (n + m)) : nullptr;
+    S.ubar = S.has_ubar ? cv.take(8 * m) : nullptr;
+    S.bfirst = nb ? cv.take(4 * nb) : nullptr;
+    S.fixed = nb ? cv.take(4 * nb) : nullptr;
+    S.col_block = nb ? cv.take(4 * n) : nullptr;
+    S.LB = nb ? cv.take(R * nb) : nullptr;
+    S.x = cv.take(X * std::max<int64_t>(n, 1));
+    S.s = cv.take(R * std::max<int64_t>(m, 1));
+    S.r = cv.take(R * std::max<int64_t>(m, 1));
+    S.udual = cv.take(R * std::max<int64_t>(m, 1));
+    S.sched = cv.take(4 * std::max<size_t>(in.sched.size(), 1));
+    S.async_sched = cv.take(4 * std::max<size_t>(in.async_sched.size(), 1));
+    S.nwg_rows = std::max<int64_t>(cdiv(std::max(m, n), kWG), 1);
+    S.nwg_cols = std::max<int64_t>(cdiv(n + nb + m, kWG), 1);
+    S.rpart = cv.take(8 * kRowSlots * S.nwg_rows);
+    S.cpart = cv.take(8 * kColSlots * S.nwg_cols);
+    S.metrics = cv.take(8 * MT_NSLOT);
+    const int64_t ns = std::max<int64_t>(std::max(n, nb), 1);
+    S.sol = cv.take(4 * ns);
+    S.best = cv.take(4 * ns);
+    S.drop = cv.take(4 * ns);
+    S.ckr_order = cv.take(4 * 64 * kMaxReps);
+    S.thr = cv.take(8 * 4);
+    S.costbuf = cv.take(8 * 4);
+    S.chkbuf = cv.take(8 * 4);
+    S.ystage = cv.take(8 * std::max<int64_t>(n + m, 1));
+    *total = cv.off + 256;
+}
+
+template <class P>
+Dev<P> make_dev(const thetis_solver &S) {
+    using R = typename P::R;
+    Dev<P> a;
+    a.col_ptr = (const int32_t *)S.col_ptr;
+    a.row_idx = (const int32_t *)S.row_idx;
+    a.cval = (const R *)S.cval;
+    a.row_ptr = (const int32_t *)S.row_ptr;
+    a.csr_col = (const int32_t *)S.csr_col;
+    a.csr_val = (const R *)S.csr_val;
+    a.b = (const double *)S.b;
+    a.sense = (const int8_t *)S.sense;
+    a.c = (const double *)S.c;
+    a.ctil = (const R *)S.ctil;
+    a.ub = (const R *)S.ub;
+    a.norm2 = (const R *)S.norm2;
+    a.ybar = (const R *)S.ybar;
+    a.ubar = (const double *)S.ubar;
+    a.bfirst = (const int32_t *)S.bfirst;
+    a.fixed = (const int32_t *)S.fixed;
+    a.col_block = (const int32_t *)S.col_block;
+    a.LB = (const R *)S.LB;
+    a.x = (typename P::X *)S.x;
+    a.s = (R *)S.s;
+    a.r = (R *)S.r;
+    a.udual = (R *)S.udual;
+    a.beta = (R)S.p.beta;
+    a.rho = (R)S.rho;
+    a.gamma = (R)S.p.step_scale;
+    a.Lmax = (R)S.Lmax;
+    a.ub_value = (R)S.ub_value;
+    a.global_lmax = S.p.step_rule == THETIS_STEP_GLOBAL_LMAX;
+    a.async_mode = S.p.schedule == THETIS_SCHED_ASYNC;
+    a.prox_on = S.p.prox != 0;
+    a.n = S.n;
+    a.m = S.m;
+    a.nblocks = S.nblocks;
+    a.k = S.k;
+    return a;
+}
+
+hipEvent_t next_event(thetis_solver &S, int *idx) {
+    if (S.ev_used == S.ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        S.ev_pool.push_back(e);
+    }
+    *idx = (int)S.ev_used;
+    return S.ev_pool[S.ev_used++];
+}
+
+struct TimedScope {
+    thetis_solver &S;
+    int kind;
+    double bytes;
+    int i0 = -1;
+    TimedScope(thetis_solver &s, int k, double b) : S(s), kind(k), bytes(b) {
+        if (S.timing) {
+            hipEvent_t e = next_event(S, &i0);
+            if (e) (void)hipEventRecord(e, S.stream);
+        }
+    }
+    ~TimedScope() {
+        if (S.timing && i0 >= 0) {
+            int i1;
+            hipEvent_t e = next_event(S, &i1);
+            if (e) {
+                (void)hipEventRecord(e, S.stream);
+                S.ev[kind].push_back({i0, i1});
+                S.ev_bytes[kind].push_back(bytes);
+            }
+        }
+    }
+};
+
+// launches the kernels of one class plan; sb[q] = algorithmic bytes of
+// segment q of the plan
+template <class P>
+void launch_plan(thetis_solver &S, const Dev<P> &a, const ClassPlan &cp, const int32_t *sched,
+                 const std::vector<double> &sb) {
+    double group_bytes = 0.0;
+    for (size_t q = 0; q < cp.segs.size(); ++q)
+        if (cp.segs[q].kind < kGroupKinds) group_bytes += sb[q];
+    GroupPlan gp;
+    int64_t wg = 0;
+    bool any_group = false;
+    for (int g = 0; g < kGroupKinds; ++g) { gp.first[g] = 0; gp.count[g] = 0; }
+    for (const Segment &sg : cp.segs)
+        if (sg.kind < kGroupKinds) { gp.first[sg.kind] = sg.first; gp.count[sg.kind] = sg.count; any_group = true; }
+    for (int g = 0; g < kGroupKinds; ++g) {
+        gp.wg_start[g] = wg;
+        wg += cdiv(gp.count[g], kWG / kGroupLanes[g]);
+    }
+    gp.wg_start[kGroupKinds] = wg;
+    const bool vals = !S.unit_vals;
+    if (any_group) {
+        TimedScope ts(S, THETIS_K_SWEEP_GROUP, group_bytes);
+        if (vals) hipLaunchKernelGGL((k_sweep_group<P, true>), dim3(wg), dim3(kWG), 0, S.stream, a, sched, gp);
+        else hipLaunchKernelGGL((k_sweep_group<P, false>), dim3(wg), dim3(kWG), 0, S.stream, a, sched, gp);
+    }
+    for (size_t q = 0; q < cp.segs.size(); ++q) {
+        const Segment &sg = cp.segs[q];
+        if (sg.kind == SEG_HUB) {
+            TimedScope ts(S, THETIS_K_SWEEP_HUB, sb[q]);
+            const int64_t grid = std::min<int64_t>(sg.count, 4096);
+            if (vals) hipLaunchKernelGGL((k_sweep_hub<P, true>), dim3(grid), dim3(kWG), 0, S.stream, a, sched + sg.first, sg.count);
+            else hipLaunchKernelGGL((k_sweep_hub<P, false>), dim3(grid), dim3(kWG), 0, S.stream, a, sched + sg.first, sg.count);
+        } else if (sg.kind == SEG_BLOCK) {
+            TimedScope ts(S, THETIS_K_SWEEP_BLOCK, sb[q]);
+            int lpc = 1;
+            while (lpc * 2 * S.k <= 64) lpc *= 2;
+            const int64_t grid = cdiv(sg.count, kWG / 64);
+            if (vals) hipLaunchKernelGGL((k_sweep_block<P, true>), dim3(grid), dim3(kWG), 0, S.stream, a, sched + sg.first, sg.count, lpc);
+            else hipLaunchKernelGGL((k_sweep_block<P, false>), dim3(grid), dim3(kWG), 0, S.stream, a, sched + sg.first, sg.count, lpc);
+        } else if (sg.kind == SEG_SLACK) {
+            TimedScope ts(S, THETIS_K_SWEEP_SLACK, sb[q]);
+            const int32_t *list = S.all_rows_slack ? nullptr : sched + sg.first;
+            hipLaunchKernelGGL((k_sweep_slack<P>), dim3(cdiv(sg.count, kWG)), dim3(kWG), 0, S.stream, a, list, sg.count);
+        }
+    }
+}
+
+// FP64 refresh: row pass (+ new r when write_r), column pass, fold
+template <class P>
+thetis_status refresh(thetis_solver &S, bool write_r) {
+    Dev<P> a = make_dev<P>(S);
+    {
+        TimedScope ts(S, THETIS_K_REFRESH, S.refresh_bytes);
+        hipLaunchKernelGGL((k_rows<P>), dim3(cdiv(std::max<int64_t>(S.m, 1), kWG)), dim3(kWG), 0, S.stream, a,
+                           (int32_t)write_r, (double *)S.rpart);
+        hipLaunchKernelGGL((k_cols<P>), dim3(cdiv(S.n + S.nblocks + S.m, kWG) > 0 ? cdiv(S.n + S.nblocks + S.m, kWG) : 1),
+                           dim3(kWG), 0, S.stream, a, (double *)S.cpart);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kWG), 0, S.stream, (const double *)S.rpart,
+                           cdiv(std::max<int64_t>(S.m, 1), kWG), (const double *)S.cpart,
+                           cdiv(S.n + S.nblocks + S.m, kWG) > 0 ? cdiv(S.n + S.nblocks + S.m, kWG) : 1,
+                           S.p.beta, (double *)S.metrics);
+    }
+    HIP_TRY(hipGetLastError());
+    return THETIS_OK;
+}
+
+template <class P>
+thetis_status read_metrics(thetis_solver &S) {
+    if (!S.metrics_fresh) {
+        thetis_status st = refresh<P>(S, false);
+        if (st) return st;
+    }
+    HIP_TRY(hipMemcpyAsync(S.mt, S.metrics, sizeof(S.mt), hipMemcpyDeviceToHost, S.stream));
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    S.metrics_fresh = true;
+    if (S.mt[MT_BAD] != 0.0) return fail(THETIS_EDIVERGED, "NaN or Inf in the penalty reductions");
+    return THETIS_OK;
+}
+
+template <class P>
+thetis_status run_epochs_impl(thetis_solver &S, int32_t max_epochs, double gap_tol, int32_t *done) {
+    Dev<P> a = make_dev<P>(S);
+    const int32_t *sched = (const int32_t *)S.sched;
+    const int32_t *asched = (const int32_t *)S.async_sched;
+    std::vector<int32_t> order(std::max(S.nclasses, 1));
+    S.ev_used = 0;
+    for (int q = 0; q < THETIS_K_NKINDS; ++q) { S.ev[q].clear(); S.ev_bytes[q].clear(); }
+    int32_t e = 0;
+    thetis_status st = THETIS_OK;
+    for (; e < max_epochs; ++e) {
+        if (S.p.schedule == THETIS_SCHED_DET) {
+            class_order(S.nclasses, S.p.seed, S.epoch, order.data());
+            for (int32_t q = 0; q < S.nclasses; ++q)
+                launch_plan<P>(S, a, S.classes[order[q]], sched, S.seg_bytes[order[q]]);
+        } else {
+            launch_plan<P>(S, a, S.async_struct, asched, S.async_struct_bytes);
+            launch_plan<P>(S, a, S.async_slack, asched, S.async_slack_bytes);
+        }
+        S.epoch++;
+        S.metrics_fresh = false;
+        if (S.p.refresh_every > 0 && S.epoch % S.p.refresh_every == 0) {
+            st = refresh<P>(S, true);
+            if (st) break;
+            S.metrics_fresh = true;
+            if (gap_tol > 0.0) {
+                HIP_TRY(hipMemcpyAsync(S.mt, S.metrics, sizeof(S.mt), hipMemcpyDeviceToHost, S.stream));
+                HIP_TRY(hipStreamSynchronize(S.stream));
+                if (S.mt[MT_BAD] != 0.0) { ++e; st = fail(THETIS_EDIVERGED, "NaN or Inf in the refresh"); break; }
+                if (S.mt[MT_GAP] <= gap_tol) { ++e; break; }
+            }
+        }
+    }
+    if (done) *done = e;
+    HIP_TRY(hipGetLastError());
+    if (S.timing) {
+        HIP_TRY(hipStreamSynchronize(S.stream));
+        for (int q = 0; q < THETIS_K_NKINDS; ++q) {
+            S.ms[q] = 0;
+            S.bytes[q] = 0;
+            for (size_t t = 0; t < S.ev[q].size(); ++t) {
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, S.ev_pool[S.ev[q][t].first], S.ev_pool[S.ev[q][t].second]));
+                S.ms[q] += ms;
+                S.bytes[q] += S.ev_bytes[q][t];
+            }
+            S.launches[q] = (int64_t)S.ev[q].size();
+        }
+    }
+    return st;
+}
+
+template <class P>
+thetis_status reset_impl(thetis_solver &S) {
+    Dev<P> a = make_dev<P>(S);
+    const int64_t N = std::max<int64_t>(std::max(S.n, S.m), 1);
+    hipLaunchKernelGGL((k_set_start<P>), dim3(cdiv(N, kWG)), dim3(kWG), 0, S.stream, a);
+    S.epoch = 0;
+    S.have_round = false;
+    HIP_TRY(hipGetLastError());
+    thetis_status st = refresh<P>(S, true);
+    S.metrics_fresh = true;
+    return st;
+}
+
+template <class P>
+thetis_status set_y_impl(thetis_solver &S, const double *y) {
+    HIP_TRY(hipMemcpyAsync(S.ystage, y, 8 * (S.n + S.m), hipMemcpyHostToDevice, S.stream));
+    Dev<P> a = make_dev<P>(S);
+    const int64_t N = std::max<int64_t>(std::max(S.n, S.m), 1);
+    hipLaunchKernelGGL((k_load_y<P>), dim3(cdiv(N, kWG)), dim3(kWG), 0, S.stream, a, (const double *)S.ystage);
+    HIP_TRY(hipGetLastError());
+    thetis_status st = refresh<P>(S, true);
+    S.metrics_fresh = true;
+    S.have_round = false;
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    return THETIS_OK;
+}
+
+template <class P>
+thetis_status get_x_impl(thetis_solver &S, double *x, double *s) {
+    Dev<P> a = make_dev<P>(S);
+    double *dx = (double *)S.ystage, *ds = dx + S.n;
+    const int64_t N = std::max<int64_t>(std::max(S.n, S.m), 1);
+    hipLaunchKernelGGL((k_store_y<P>), dim3(cdiv(N, kWG)), dim3(kWG), 0, S.stream, a, dx, s ? ds : nullptr);
+    HIP_TRY(hipGetLastError());
+    if (x) HIP_TRY(hipMemcpyAsync(x, dx, 8 * S.n, hipMemcpyDeviceToHost, S.stream));
+    if (s) HIP_TRY(hipMemcpyAsync(s, ds, 8 * S.m, hipMemcpyDeviceToHost, S.stream));
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    return THETIS_OK;
+}
+
+template <class P>
+thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t reps, int32_t *sol_host,
+                         double *cost, double *aux) {
+    Dev<P> a = make_dev<P>(S);
+    const int64_t gm = std::max<int64_t>(cdiv(S.m, kWG), 1), gn = std::max<int64_t>(cdiv(S.n, kWG), 1);
+    double *part = (double *)S.rpart;
+    double *thr = (double *)S.thr, *cb = (double *)S.costbuf;
+    int32_t *sol = (int32_t *)S.sol, *best = (int32_t *)S.best, *drop = (int32_t *)S.drop;
+    double auxv[2] = {0, 0};
+    int64_t nsol = S.n;
+    if (rule == THETIS_ROUND_VC_THRESH || rule == THETIS_ROUND_MIS_THRESH) {
+        if (rule == THETIS_ROUND_VC_THRESH && !S.edge_shape_cover)
+            return fail(THETIS_EINVAL, "VC rounding needs rows x_u + x_v >= 1");
+        if (rule == THETIS_ROUND_MIS_THRESH && !S.edge_shape_pack)
+            return fail(THETIS_EINVAL, "MIS rounding needs rows x_u + x_v <= 1");
+        const int32_t op = rule == THETIS_ROUND_VC_THRESH ? 0 : 1;
+        hipLaunchKernelGGL((k_edge_extreme<P>), dim3(gm), dim3(kWG), 0, S.stream, a, op, part);
+        hipLaunchKernelGGL(k_edge_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, gm, op, thr);
+        hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, 0, best, part);
+        hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, gn, 1.0, 0, cb);
+        HIP_TRY(hipMemcpyAsync(auxv, thr, 8, hipMemcpyDeviceToHost, S.stream));
+    } else if (rule == THETIS_ROUND_MIS_RAND) {
+        if (!S.edge_shape_pack) return fail(THETIS_EINVAL, "MIS rounding needs rows x_u + x_v <= 1");
+        if (reps < 1) return fail(THETIS_EINVAL, "reps must be >= 1");
+        hipLaunchKernelGGL((k_edge_extreme<P>), dim3(gm), dim3(kWG), 0, S.stream, a, 2, part);
+        hipLaunchKernelGGL(k_edge_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, gm, 2, thr);
+        for (int32_t rep = 0; rep < reps; ++rep) {
+            HIP_TRY(hipMemsetAsync(drop, 0, 4 * S.n, S.stream));
+            hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, rep, sol, part);
+            hipLaunchKernelGGL((k_conflicts<P>), dim3(gm), dim3(kWG), 0, S.stream, a, (const int32_t *)sol, drop);
+            hipLaunchKernelGGL((k_apply_drop<P>), dim3(gn), dim3(kWG), 0, S.stream, a, sol, (const int32_t *)drop, part);
+            hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, gn, 1.0, rep, cb);
+            hipLaunchKernelGGL(k_copy_if, dim3(gn), dim3(kWG), 0, S.stream, (const double *)cb, (const int32_t *)sol, best, S.n);
+        }
+        HIP_TRY(hipMemcpyAsync(auxv, thr, 8, hipMemcpyDeviceToHost, S.stream));
+    } else if (rule == THETIS_ROUND_MC_CKR) {
+        if (S.nblocks <= 0) return fail(THETIS_EINVAL, "MC rounding needs simplex blocks");
+        if (reps < 1 || reps > kMaxReps) return fail(THETIS_EINVAL, "reps must be in [1, 64]");
+        nsol = S.nblocks;
+        const int64_t gb = std::max<int64_t>(cdiv(S.nblocks, kWG), 1);
+        std::vector<int32_t> orders(64 * (size_t)reps);  // one label order per repetition
+        std::vector<double> rads(reps);
+        for (int32_t rep = 0; rep < reps; ++rep) {
+            rads[rep] = unit53(philox_word_host(seed, RNG_ROUND, (uint64_t)rep, 0, 1));
+            std::vector<std::pair<uint64_t, int32_t>> ks(S.k);
+            for (int32_t i = 0; i < S.k; ++i) ks[i] = {philox_word_host(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)i, 2), i};
+            std::sort(ks.begin(), ks.end());
+            for (int32_t i = 0; i < S.k; ++i) orders[64 * (size_t)rep + i] = ks[i].second;
+        }
+        HIP_TRY(hipMemcpyAsync(S.ckr_order, orders.data(), 4 * orders.size(), hipMemcpyHostToDevice, S.stream));
+        for (int32_t rep = 0; rep < reps; ++rep) {
+            hipLaunchKernelGGL((k_ckr_label<P>), dim3(gb), dim3(kWG), 0, S.stream, a, rads[rep],
+                               (const int32_t *)S.ckr_order + 64 * (size_t)rep, sol);
+            hipLaunchKernelGGL((k_ckr_cost<P>), dim3(gm), dim3(kWG), 0, S.stream, a, (const int32_t *)sol, part);
+            hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, gm, 0.5, rep, cb);
+            hipLaunchKernelGGL(k_copy_if, dim3(gb), dim3(kWG), 0, S.stream, (const double *)cb, (const int32_t *)sol, best, S.nblocks);
+        }
+        auxv[0] = -1.0;   // radius of the winning repetition, filled below
+    } else {
+        return fail(THETIS_EINVAL, "unknown rounding rule");
+    }
+    HIP_TRY(hipGetLastError());
+    double cbh[4];
+    HIP_TRY(hipMemcpyAsync(cbh, cb, 32, hipMemcpyDeviceToHost, S.stream));
+    if (sol_host) HIP_TRY(hipMemcpyAsync(sol_host, best, 4 * nsol, hipMemcpyDeviceToHost, S.stream));
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    if (cost) *cost = cbh[1];
+    auxv[1] = cbh[3];
+    if (rule == THETIS_ROUND_MC_CKR)
+        auxv[0] = unit53(philox_word_host(seed, RNG_ROUND, (uint64_t)cbh[3], 0, 1));
+    if (aux) { aux[0] = auxv[0]; aux[1] = auxv[1]; }
+    S.have_round = true;
+    S.last_rule = rule;
+    return THETIS_OK;
+}
+
+template <class P>
+thetis_status check_impl(thetis_solver &S, int32_t rule, const int32_t *sol_host, int32_t *feasible,
+                         int64_t *nviol) {
+    Dev<P> a = make_dev<P>(S);
+    const int32_t *sol = (const int32_t *)S.best;
+    const bool labels = rule == THETIS_ROUND_MC_CKR;
+    if (labels && S.nblocks <= 0) return fail(THETIS_EINVAL, "MC check needs simplex blocks");
+    if (!labels && (rule < THETIS_ROUND_VC_THRESH || rule > THETIS_ROUND_MIS_RAND))
+        return fail(THETIS_EINVAL, "unknown rule");
+    const int64_t nsol = labels ? S.nblocks : S.n;
+    if (sol_host) {
+        HIP_TRY(hipMemcpyAsync(S.drop, sol_host, 4 * nsol, hipMemcpyHostToDevice, S.stream));
+        sol = (const int32_t *)S.drop;
+    } else if (!S.have_round) {
+        return fail(THETIS_EINVAL, "no rounded solution on the device");
+    }
+    double *part = (double *)S.rpart;
+    int64_t g;
+    if (labels) {
+        g = std::max<int64_t>(cdiv(S.nblocks, kWG), 1);
+        hipLaunchKernelGGL((k_check_labels<P>), dim3(g), dim3(kWG), 0, S.stream, a, sol, part);
+    } else {
+        g = std::max<int64_t>(cdiv(std::max(S.m, S.n), kWG), 1);
+        hipLaunchKernelGGL((k_check_rows<P>), dim3(g), dim3(kWG), 0, S.stream, a, sol, part);
+    }
+    double *cb = (double *)S.chkbuf;
+    hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, g, 1.0, 0, cb);
+    HIP_TRY(hipGetLastError());
+    double h[4];
+    HIP_TRY(hipMemcpyAsync(h, cb, 32, hipMemcpyDeviceToHost, S.stream));
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    const int64_t bad = (int64_t)h[0];
+    if (nviol) *nviol = bad;
+    if (feasible) *feasible = bad == 0;
+    return THETIS_OK;
+}
+
+#define DISPATCH(S, CALL)                                                       \
+    ((S).p.precision == THETIS_PREC_FP64 ? CALL<PF64> : CALL<PF32>)
+
+bool edge_shape(const Inst &in, int8_t want) {
+    if (in.m == 0) return false;
+    for (int64_t i = 0; i < in.m; ++i) {
+        if (in.row_ptr[i + 1] - in.row_ptr[i] != 2) return false;
+        if (in.sense[i] != want || in.b[i] != 1.0) return false;
+        if (!in.unit_vals) {
+            if (in.val[in.row_ptr[i]] != 1.0 || in.val[in.row_ptr[i] + 1] != 1.0) return false;
+        }
+    }
+    return true;
+}
+
+// curvature of every unit and the largest one (eq. Lmax with the prox
+// weight rho in place of 1/beta)
+void compute_curvatures(thetis_solver &S, const Inst &in, std::vector<double> &norm2, std::vector<double> &LB) {
+    norm2.assign(in.n, 0.0);
+    for (int64_t j = 0; j < in.n; ++j) {
+        double a2 = 0.0;
+        for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e) {
+            const double v = in.unit_vals ? 1.0 : in.cval[e];
+            a2 += v * v;
+        }
+        norm2[j] = a2;
+    }
+    LB.assign(in.nblocks, 0.0);
+    double Lmax = 0.0;
+    for (int64_t t = 0; t < in.nblocks; ++t) {
+        if (in.fixed[t] >= 0) continue;
+        double best = 0.0;
+        for (int32_t i = 0; i < in.k; ++i) {
+            const int32_t j = in.bfirst[t] + i;
+            double acc = 0.0;
+            for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e) {
+                const int32_t row = in.row_idx[e];
+                double rs = 0.0;
+                for (int32_t q = in.row_ptr[row]; q < in.row_ptr[row + 1]; ++q)
+                    if (in.col_block[in.col_idx[q]] == t) rs += std::fabs(in.unit_vals ? 1.0 : in.val[q]);
+                acc += std::fabs(in.unit_vals ? 1.0 : in.cval[e]) * rs;
+            }
+            best = std::max(best, acc);
+        }
+        LB[t] = S.p.beta * best + S.rho;
+        Lmax = std::max(Lmax, LB[t]);
+    }
+    for (int64_t j = 0; j < in.n; ++j) {
+        if (in.nblocks && in.col_block[j] >= 0) continue;
+        Lmax = std::max(Lmax, S.p.beta * norm2[j] + S.rho);
+    }
+    for (int64_t i = 0; i < in.m; ++i)
+        if (in.sense[i] != 0) Lmax = std::max(Lmax, S.p.beta + S.rho);
+    S.Lmax = Lmax;
+}
+
+template <class T>
+thetis_status upload(thetis_solver &S, void *dst, const std::vector<T> &src) {
+    if (src.empty() || !dst) return THETIS_OK;
+    HIP_TRY(hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, S.stream));
+    return THETIS_OK;
+}
+
+template <class R>
+thetis_status upload_conv(thetis_solver &S, void *dst, const std::vector<double> &src) {
+    if (src.empty() || !dst) return THETIS_OK;
+    std::vector<R> tmp(src.begin(), src.end());
+    HIP_TRY(hipMemcpyAsync(dst, tmp.data(), sizeof(R) * tmp.size(), hipMemcpyHostToDevice, S.stream));
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    return THETIS_OK;
+}
+
+thetis_status upload_real(thetis_solver &S, void *dst, const std::vector<double> &src) {
+    return S.p.precision == THETIS_PREC_FP64 ? upload_conv<double>(S, dst, src) : upload_conv<float>(S, dst, src);
+}
+
+// Algorithmic bytes of one launch of a segment (R = bytes of a stored
+// real).  Plain column j with d entries: list entry 4, column pointers 8,
+// per entry row index 4 + residual read R + write R (+ value R), x read and
+// write 2R, cost R (+ bound R, + ||A_j||^2 R when not implied).  Simplex
+// block: the same per column plus the block's first column and curvature.
+// Slack: s and r read and written (+ row list 4 when not every row has one).
+double segment_bytes(const thetis_solver &S, const Inst &in, const std::vector<int32_t> &sched,
+                     const Segment &sg) {
+    const double R = (double)prec_bytes(S.p.precision);
+    const double V = in.unit_vals ? 0.0 : R;
+    const double per_col = 8 + 3 * R + (in.uniform_ub ? 0 : R) + (in.unit_vals ? 0 : R) +
+                           (S.has_ubar ? 0 : 0) + (S.has_ybar ? R : 0);
+    double b = 0.0;
+    if (sg.kind == SEG_SLACK) return (double)sg.count * (4 * R + (in.all_rows_slack ? 0.0 : 4.0));
+    for (int64_t q = 0; q < sg.count; ++q) {
+        const int32_t id = sched[sg.first + q];
+        b += 4;
+        if (sg.kind == SEG_BLOCK) {
+            b += 4 + R;
+            for (int32_t i = 0; i < in.k; ++i) {
+                const int32_t j = in.bfirst[id] + i;
+                const double d = in.col_ptr[j + 1] - in.col_ptr[j];
+                b += per_col + d * (4 + 2 * R + V);
+            }
+        } else {
+            const double d = in.col_ptr[id + 1] - in.col_ptr[id];
+            b += per_col + d * (4 + 2 * R + V);
+        }
+    }
+    return b;
+}
+
+// one refresh: row pass (row pointers, indices, x gathered, s, b, sense, r
+// and the dual estimate written) and column pass (column pointers, indices,
+// dual estimate gathered, c, x, s, sense)
+double refresh_traffic(const thetis_solver &S) {
+    const double R = (double)prec_bytes(S.p.precision);
+    const double V = S.unit_vals ? 0.0 : R;
+    const double rows = 4.0 * (S.m + 1) + S.nnz * (4 + R + V) + S.m * (R + 8 + 1 + 2 * R);
+    const double cols = 4.0 * (S.n + 1) + S.nnz * (4 + R + V) + S.n * (8 + R) + S.m * (1 + 2 * R);
+    return rows + cols;
+}
+
+thetis_status check_params(const thetis_params *p) {
+    if (!p) return fail(THETIS_EINVAL, "params is NULL");
+    if (!(p->beta > 0.0) || !std::isfinite(p->beta)) return fail(THETIS_EINVAL, "beta must be positive and finite");
+    if (p->step_rule != THETIS_STEP_PER_COORD && p->step_rule != THETIS_STEP_GLOBAL_LMAX)
+        return fail(THETIS_EINVAL, "unknown step rule");
+    if (!(p->step_scale > 0.0 && p->step_scale <= 1.0)) return fail(THETIS_EINVAL, "step_scale must be in (0, 1]");
+    if (p->schedule != THETIS_SCHED_DET && p->schedule != THETIS_SCHED_ASYNC)
+        return fail(THETIS_EINVAL, "unknown schedule");
+    if (p->precision == THETIS_PREC_BF16X) return fail(THETIS_EUNSUPPORTED, "BF16 x storage is not built in this version");
+    if (p->precision != THETIS_PREC_FP32 && p->precision != THETIS_PREC_FP64)
+        return fail(THETIS_EINVAL, "unknown precision");
+    if (p->refresh_every < 1) return fail(THETIS_EINVAL, "refresh_every must be >= 1");
+    return THETIS_OK;
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+
+extern "C" thetis_status thetis_solver_workspace_bytes(const thetis_inst *h, const thetis_params *p,
+                                                       size_t *bytes) {
+    clear_error();
+    if (!h || !bytes) return fail(THETIS_EINVAL, "NULL argument");
+    thetis_status st = check_params(p);
+    if (st) return st;
+    thetis_solver S;
+    S.p = *p;
+    S.has_ybar = p->prox && p->ybar;
+    S.has_ubar = p->ubar != nullptr;
+    carve(S, h->in, nullptr, bytes);
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis_params *p,
+                                              void *dev_workspace, size_t ws_bytes, void *stream,
+                                              thetis_solver **out) {
+    clear_error();
+    if (!h || !out) return fail(THETIS_EINVAL, "NULL argument");
+    *out = nullptr;
+    thetis_status st = check_params(p);
+    if (st) return st;
+    const Inst &in = h->in;
+    thetis_solver *Sp = new (std::nothrow) thetis_solver;
+    if (!Sp) return fail(THETIS_ENOMEM, "host allocation failed");
+    thetis_solver &S = *Sp;
+    S.p = *p;
+    S.p.ybar = nullptr;
+    S.p.ubar = nullptr;
+    S.rho = p->prox ? 1.0 / p->beta : 0.0;
+    S.has_ybar = p->prox && p->ybar;
+    S.has_ubar = p->ubar != nullptr;
+    S.m = in.m; S.n = in.n; S.nnz = in.nnz; S.nblocks = in.nblocks; S.k = in.k;
+    S.nclasses = in.nclasses; S.nunits = in.nunits;
+    S.unit_vals = in.unit_vals; S.uniform_ub = in.uniform_ub; S.ub_value = in.ub_value;
+    S.all_rows_slack = in.all_rows_slack;
+    S.classes = in.classes; S.async_struct = in.async_struct; S.async_slack = in.async_slack;
+    S.edge_shape_cover = edge_shape(in, 1);
+    S.edge_shape_pack = edge_shape(in, -1);
+    S.col_deg.resize(in.n);
+    for (int64_t j = 0; j < in.n; ++j) S.col_deg[j] = in.col_ptr[j + 1] - in.col_ptr[j];
+    S.seg_bytes.resize(in.classes.size());
+    for (size_t c = 0; c < in.classes.size(); ++c)
+        for (const Segment &sg : in.classes[c].segs) S.seg_bytes[c].push_back(segment_bytes(S, in, in.sched, sg));
+    for (const Segment &sg : in.async_struct.segs) S.async_struct_bytes.push_back(segment_bytes(S, in, in.async_sched, sg));
+    for (const Segment &sg : in.async_slack.segs) S.async_slack_bytes.push_back(segment_bytes(S, in, in.async_sched, sg));
+    S.refresh_bytes = refresh_traffic(S);
+    S.stream = (hipStream_t)stream;
+    size_t need = 0;
+    carve(S, in, nullptr, &need);
+    if (dev_workspace) {
+        if (ws_bytes < need) { delete Sp; return fail(THETIS_ENOMEM, "workspace smaller than thetis_solver_workspace_bytes"); }
+        S.ws = (char *)dev_workspace;
+        S.ws_bytes = ws_bytes;
+    } else {
+        if (hipMalloc(&S.ws, need) != hipSuccess) { delete Sp; (void)hipGetLastError(); return fail(THETIS_ENOMEM, "hipMalloc of the workspace failed"); }
+        S.own_ws = true;
+        S.ws_bytes = need;
+    }
+    char *base = (char *)(((uintptr_t)S.ws + 255) & ~uintptr_t(255));
+    size_t dummy;
+    carve(S, in, base, &dummy);
+    std::vector<double> norm2, LB;
+    compute_curvatures(S, in, norm2, LB);
+#define UP(expr) do { thetis_status s_ = (expr); if (s_) { thetis_solver_destroy(Sp); return s_; } } while (0)
+    UP(upload(S, S.col_ptr, in.col_ptr));
+    UP(upload(S, S.row_idx, in.row_idx));
+    UP(upload(S, S.row_ptr, in.row_ptr));
+    UP(upload(S, S.csr_col, in.col_idx));
+    UP(upload(S, S.b, in.b));
+    UP(upload(S, S.sense, in.sense));
+    UP(upload(S, S.c, in.c));
+    UP(upload(S, S.sched, in.sched));
+    UP(upload(S, S.async_sched, in.async_sched));
+    if (!in.unit_vals) {
+        UP(upload_real(S, S.cval, in.cval));
+        UP(upload_real(S, S.csr_val, in.val));
+        UP(upload_real(S, S.norm2, norm2));
+    }
+    if (!in.uniform_ub) UP(upload_real(S, S.ub, in.u));
+    if (in.nblocks) {
+        UP(upload(S, S.bfirst, in.bfirst));
+        UP(upload(S, S.fixed, in.fixed));
+        UP(upload(S, S.col_block, in.col_block));
+        UP(upload_real(S, S.LB, LB));
+    }
+    if (S.has_ybar) {
+        std::vector<double> yb(p->ybar, p->ybar + in.n + in.m);
+        UP(upload_real(S, S.ybar, yb));
+    }
+    if (S.has_ubar) {
+        std::vector<double> ub(p->ubar, p->ubar + in.m);
+        UP(upload(S, S.ubar, ub));
+        // ctil = c - A^T ubar over the structural columns, -sign * ubar_i for slacks
+        std::vector<double> ct(in.n + in.m, 0.0);
+        for (int64_t j = 0; j < in.n; ++j) {
+            double acc = 0.0;
+            for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e)
+                acc += (in.unit_vals ? 1.0 : in.cval[e]) * ub[in.row_idx[e]];
+            ct[j] = in.c[j] - acc;
+        }
+        for (int64_t i = 0; i < in.m; ++i) {
+            const double sg = in.sense[i] > 0 ? -1.0 : (in.sense[i] < 0 ? 1.0 : 0.0);
+            ct[in.n + i] = -sg * ub[i];
+        }
+        UP(upload_real(S, S.ctil, ct));
+    }
+    const_cast<thetis_inst *>(h)->in.has_solver = true;
+    st = DISPATCH(S, reset_impl)(S);
+    if (st) { thetis_solver_destroy(Sp); return st; }
+    if (hipStreamSynchronize(S.stream) != hipSuccess) {
+        thetis_solver_destroy(Sp);
+        return fail(THETIS_EDEVICE, "device error while creating the solver");
+    }
+#undef UP
+    *out = Sp;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_solver_reset(thetis_solver *s) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    return DISPATCH(*s, reset_impl)(*s);
+}
+
+extern "C" thetis_status thetis_set_beta(thetis_solver *s, double beta) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    if (!(beta > 0.0) || !std::isfinite(beta)) return fail(THETIS_EINVAL, "beta must be positive");
+    if (s->nblocks) return fail(THETIS_EUNSUPPORTED, "changing beta with simplex blocks needs a new solver");
+    const double old = s->p.beta;
+    s->p.beta = beta;
+    s->rho = s->p.prox ? 1.0 / beta : 0.0;
+    // every curvature is beta * ||A_j||^2 + rho; Lmax scales the same way
+    const double oldrho = s->p.prox ? 1.0 / old : 0.0;
+    s->Lmax = (s->Lmax - oldrho) / old * beta + s->rho;
+    s->metrics_fresh = false;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_set_step_rule(thetis_solver *s, int32_t rule, double scale) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    if (rule != THETIS_STEP_PER_COORD && rule != THETIS_STEP_GLOBAL_LMAX) return fail(THETIS_EINVAL, "unknown step rule");
+    if (!(scale > 0.0 && scale <= 1.0)) return fail(THETIS_EINVAL, "step_scale must be in (0, 1]");
+    s->p.step_rule = rule;
+    s->p.step_scale = scale;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_run_epochs(thetis_solver *s, int32_t max_epochs, double gap_tol,
+                                           int32_t *epochs_done) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    if (max_epochs < 0) return fail(THETIS_EINVAL, "max_epochs < 0");
+    s->have_round = false;
+    return DISPATCH(*s, run_epochs_impl)(*s, max_epochs, gap_tol, epochs_done);
+}
+
+extern "C" thetis_status thetis_residual(thetis_solver *s, double *linf, double *l2, double *viol) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    thetis_status st = DISPATCH(*s, read_metrics)(*s);
+    if (st) return st;
+    if (linf) *linf = s->mt[MT_LINF];
+    if (l2) *l2 = s->mt[MT_L2];
+    if (viol) *viol = s->mt[MT_VIOL];
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_objective(thetis_solver *s, double *lp_value, double *penalty,
+                                          double *dual_bound) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    thetis_status st = DISPATCH(*s, read_metrics)(*s);
+    if (st) return st;
+    if (lp_value) *lp_value = s->mt[MT_CX];
+    if (penalty) *penalty = s->mt[MT_F];
+    if (dual_bound) *dual_bound = s->mt[MT_PHI];
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_get_x(thetis_solver *s, double *x, double *sl) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    return DISPATCH(*s, get_x_impl)(*s, x, sl);
+}
+
+extern "C" thetis_status thetis_set_y(thetis_solver *s, const double *y) {
+    clear_error();
+    if (!s || !y) return fail(THETIS_EINVAL, "NULL argument");
+    for (int64_t j = 0; j < s->n + s->m; ++j)
+        if (!std::isfinite(y[j])) return fail(THETIS_EINVAL, "non-finite y");
+    return DISPATCH(*s, set_y_impl)(*s, y);
+}
+
+extern "C" thetis_status thetis_epoch(const thetis_solver *s, int64_t *epoch) {
+    clear_error();
+    if (!s || !epoch) return fail(THETIS_EINVAL, "NULL argument");
+    *epoch = s->epoch;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_round(thetis_solver *s, int32_t rule, uint64_t seed, int32_t reps,
+                                      int32_t *sol_host, double *cost, double *aux) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    return DISPATCH(*s, round_impl)(*s, rule, seed, reps, sol_host, cost, aux);
+}
+
+extern "C" thetis_status thetis_check_feasible(thetis_solver *s, int32_t rule, const int32_t *sol_host,
+                                               int32_t *feasible, int64_t *n_violated) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    return DISPATCH(*s, check_impl)(*s, rule, sol_host, feasible, n_violated);
+}
+
+extern "C" thetis_status thetis_set_timing(thetis_solver *s, int32_t enable) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    s->timing = enable != 0;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_get_timing(const thetis_solver *s, int32_t kind, double *ms,
+                                           int64_t *launches, double *alg_bytes) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    if (kind < 0 || kind >= THETIS_K_NKINDS) return fail(THETIS_EINVAL, "unknown kernel group");
+    if (ms) *ms = s->ms[kind];
+    if (launches) *launches = s->launches[kind];
+    if (alg_bytes) *alg_bytes = s->bytes[kind];
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_epoch_traffic(const thetis_solver *s, double *sweep_bytes,
+                                              double *refresh_bytes, int64_t *updates) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    double sw = 0.0;
+    for (const auto &v : s->seg_bytes)
+        for (double b : v) sw += b;
+    if (s->p.schedule == THETIS_SCHED_ASYNC) {
+        sw = 0.0;
+        for (double b : s->async_struct_bytes) sw += b;
+        for (double b : s->async_slack_bytes) sw += b;
+    }
+    int64_t nupd = 0;
+    for (const ClassPlan &cp : s->classes)
+        for (const Segment &sg : cp.segs) nupd += sg.kind == SEG_BLOCK ? sg.count * s->k : sg.count;
+    if (sweep_bytes) *sweep_bytes = sw;
+    if (refresh_bytes) *refresh_bytes = s->refresh_bytes;
+    if (updates) *updates = nupd;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_solver_destroy(thetis_solver *s) {
+    if (!s) return THETIS_OK;
+    (void)hipStreamSynchronize(s->stream);
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    if (s->own_ws && s->ws) (void)hipFree(s->ws);
+    delete s;
+    return THETIS_OK;
+}

@@ -1,0 +1,100 @@
+// Internal declarations of libthetis shared by the host layout code
+// (layout.cpp) and the HIP translation unit (thetis.hip).  Not installed.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/thetis.h"
+
+namespace thetis {
+
+// error plumbing: every C entry point funnels failures through fail()
+thetis_status fail(thetis_status code, const std::string &msg);
+void clear_error();
+
+// Work kinds of the class sweep.  Plain columns are grouped by degree into
+// lane groups of G lanes per column (G divides the 64-lane wavefront);
+// columns above 64 entries get a whole 256-thread workgroup with the
+// residual entries staged in LDS; simplex blocks get one wavefront each;
+// slacks one lane each.
+enum SegKind : int32_t {
+    SEG_G4 = 0, SEG_G8, SEG_G16, SEG_G32, SEG_G64,   // lane groups
+    SEG_HUB,                                        // workgroup per column
+    SEG_BLOCK,                                      // wavefront per simplex block
+    SEG_SLACK,                                      // lane per slack row
+    SEG_NKIND
+};
+constexpr int kGroupKinds = 5;
+constexpr int kGroupLanes[kGroupKinds] = {4, 8, 16, 32, 64};
+constexpr int kWG = 256;              // threads per workgroup, every kernel
+constexpr int kHubMinDegree = 65;     // columns with more entries go to SEG_HUB
+
+struct Segment {
+    int32_t kind;
+    int64_t first;   // offset into Inst::sched
+    int64_t count;   // units in this segment
+};
+
+struct ClassPlan {
+    std::vector<Segment> segs;   // at most one segment per kind
+};
+
+// Host copy of an instance plus everything derived from it once.
+struct Inst {
+    int64_t m = 0, n = 0, nnz = 0;
+    // CSR of A (structural columns only)
+    std::vector<int32_t> row_ptr, col_idx;
+    std::vector<double> val;            // empty: all entries are 1
+    std::vector<double> b, c, u;
+    std::vector<int8_t> sense;
+    bool unit_vals = true;
+    bool uniform_ub = true;             // every structural u_j equal
+    double ub_value = 1.0;
+    bool all_rows_slack = true;         // every row is an inequality
+    // CSC of A
+    std::vector<int32_t> col_ptr, row_idx;
+    std::vector<double> cval;           // empty when unit_vals
+    // simplex blocks
+    int64_t nblocks = 0;
+    int32_t k = 0;
+    std::vector<int32_t> bfirst, fixed, col_block;   // col_block[j] = block or -1
+    // update units, in unit order: free blocks and free columns (by first
+    // column), then slack rows
+    int64_t nunits = 0, nstruct_units = 0;
+    std::vector<int8_t> ukind;          // 0 column, 1 block, 2 slack
+    std::vector<int32_t> uid;           // column / block / row
+    std::vector<int32_t> ucolour;
+    int32_t nclasses = 0;
+    // DET schedule: units of each class, grouped by segment kind
+    std::vector<int32_t> sched;
+    std::vector<ClassPlan> classes;
+    // ASYNC schedule: every structural unit (one "class"), then the slacks
+    std::vector<int32_t> async_sched;
+    ClassPlan async_struct, async_slack;
+    bool planned = false;
+    bool has_solver = false;
+    int64_t max_col_degree = 0;
+};
+
+thetis_status build_layout(Inst &in);   // CSC, units, colouring, plans
+
+// Philox4x64-10 (Salmon et al., SC'11), host and device.
+struct Philox4x64 {
+    static constexpr uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    static constexpr uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+};
+enum : uint64_t { RNG_CLASS_ORDER = 1, RNG_ROUND = 4 };
+
+void philox_host(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+uint64_t philox_word_host(uint64_t seed, uint64_t stream, uint64_t c0, uint64_t c1, uint64_t c2);
+inline double unit53(uint64_t w) { return (double)(w >> 11) * (1.0 / 9007199254740992.0); }
+// order of the classes in epoch e: sorted by (Philox word, class id)
+void class_order(int32_t nclasses, uint64_t seed, int64_t epoch, int32_t *order);
+
+}  // namespace thetis
+
+struct thetis_inst {
+    thetis::Inst in;
+};

@@ -1,0 +1,377 @@
+"""Python binding of libthetis (ctypes).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  The functions carry the names of the C entry points declared
+in ``include/thetis.h``; ``Instance`` and ``Solver`` wrap them with
+ownership.  PyTorch supplies the device workspace (a uint8 tensor on the
+current device) and the stream (torch's current stream).
+
+There is no fallback: if the library is missing or no GPU is present the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+try:
+    import torch  # loads the HIP runtime that libthetis binds to
+except ImportError:  # pragma: no cover - torch is part of the image
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libthetis.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EDIVERGED, EBUSY, EBUDGET, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+STEP_PER_COORD, STEP_GLOBAL_LMAX = 0, 1
+SCHED_DET, SCHED_ASYNC = 0, 1
+PREC_FP32, PREC_FP64, PREC_BF16X = 0, 1, 2
+ROUND_VC_THRESH, ROUND_MIS_THRESH, ROUND_MIS_RAND, ROUND_MC_CKR = 1, 2, 3, 4
+
+EXPORTED = [
+    "thetis_params_default", "thetis_inst_create_csr", "thetis_inst_set_simplex_blocks",
+    "thetis_inst_classes", "thetis_inst_destroy", "thetis_solver_workspace_bytes",
+    "thetis_solver_create", "thetis_solver_reset", "thetis_set_beta", "thetis_set_step_rule",
+    "thetis_run_epochs", "thetis_residual", "thetis_objective", "thetis_get_x", "thetis_set_y",
+    "thetis_epoch", "thetis_round", "thetis_check_feasible", "thetis_set_timing",
+    "thetis_get_timing", "thetis_epoch_traffic", "thetis_solver_destroy", "thetis_last_error",
+]
+
+
+class ThetisError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"thetis error {code}: {msg}")
+        self.code = code
+
+
+class thetis_params(C.Structure):
+    _fields_ = [("beta", C.c_double), ("step_rule", C.c_int32), ("step_scale", C.c_double),
+                ("prox", C.c_int32), ("ybar", C.c_void_p), ("ubar", C.c_void_p),
+                ("schedule", C.c_int32), ("precision", C.c_int32),
+                ("refresh_every", C.c_int32), ("seed", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libthetis.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1311_2661_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint64
+        P = C.POINTER
+        sig = {
+            "thetis_params_default": [P(thetis_params)],
+            "thetis_inst_create_csr": [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, P(vp)],
+            "thetis_inst_set_simplex_blocks": [vp, i64, i32, vp, vp],
+            "thetis_inst_classes": [vp, P(i32), P(i64), vp],
+            "thetis_inst_destroy": [vp],
+            "thetis_solver_workspace_bytes": [vp, P(thetis_params), P(C.c_size_t)],
+            "thetis_solver_create": [vp, P(thetis_params), vp, C.c_size_t, vp, P(vp)],
+            "thetis_solver_reset": [vp],
+            "thetis_set_beta": [vp, dbl],
+            "thetis_set_step_rule": [vp, i32, dbl],
+            "thetis_run_epochs": [vp, i32, dbl, P(i32)],
+            "thetis_residual": [vp, P(dbl), P(dbl), P(dbl)],
+            "thetis_objective": [vp, P(dbl), P(dbl), P(dbl)],
+            "thetis_get_x": [vp, vp, vp],
+            "thetis_set_y": [vp, vp],
+            "thetis_epoch": [vp, P(i64)],
+            "thetis_round": [vp, i32, u64, i32, vp, P(dbl), vp],
+            "thetis_check_feasible": [vp, i32, vp, P(i32), P(i64)],
+            "thetis_set_timing": [vp, i32],
+            "thetis_get_timing": [vp, i32, P(dbl), P(i64), P(dbl)],
+            "thetis_epoch_traffic": [vp, P(dbl), P(dbl), P(i64)],
+            "thetis_solver_destroy": [vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = i32
+        L.thetis_last_error.argtypes = []
+        L.thetis_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code: int) -> None:
+    if code != OK:
+        raise ThetisError(code, lib().thetis_last_error().decode(errors="replace"))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _c(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+# ------------------------------------------------------------ C-named calls
+
+def thetis_last_error() -> str:
+    return lib().thetis_last_error().decode(errors="replace")
+
+
+def thetis_params_default() -> thetis_params:
+    p = thetis_params()
+    _check(lib().thetis_params_default(C.byref(p)))
+    return p
+
+
+def thetis_inst_create_csr(m, n, nnz, row_ptr, col_idx, val, b, c, u, sense):
+    keep = [_c(row_ptr, np.int64), _c(col_idx, np.int32), _c(val, np.float64), _c(b, np.float64),
+            _c(c, np.float64), _c(u, np.float64), _c(sense, np.int8)]
+    h = C.c_void_p()
+    _check(lib().thetis_inst_create_csr(m, n, nnz, *[_ptr(a) for a in keep], C.byref(h)))
+    return h
+
+
+def thetis_inst_set_simplex_blocks(h, nblocks, k, first_col, fixed_label=None):
+    f = _c(first_col, np.int64)
+    fx = _c(fixed_label, np.int32)
+    _check(lib().thetis_inst_set_simplex_blocks(h, nblocks, k, _ptr(f), _ptr(fx)))
+
+
+def thetis_inst_classes(h):
+    nc, nu = C.c_int32(), C.c_int64()
+    _check(lib().thetis_inst_classes(h, C.byref(nc), C.byref(nu), None))
+    out = np.zeros(nu.value, np.int32)
+    _check(lib().thetis_inst_classes(h, None, None, _ptr(out)))
+    return nc.value, nu.value, out
+
+
+def thetis_inst_destroy(h):
+    _check(lib().thetis_inst_destroy(h))
+
+
+def thetis_solver_workspace_bytes(h, params: thetis_params) -> int:
+    b = C.c_size_t()
+    _check(lib().thetis_solver_workspace_bytes(h, C.byref(params), C.byref(b)))
+    return b.value
+
+
+def thetis_solver_create(h, params: thetis_params, workspace_ptr: int, ws_bytes: int, stream_ptr: int):
+    s = C.c_void_p()
+    _check(lib().thetis_solver_create(h, C.byref(params), C.c_void_p(workspace_ptr or None), ws_bytes,
+                                      C.c_void_p(stream_ptr or None), C.byref(s)))
+    return s
+
+
+def thetis_solver_reset(s):
+    _check(lib().thetis_solver_reset(s))
+
+
+def thetis_set_beta(s, beta: float):
+    _check(lib().thetis_set_beta(s, beta))
+
+
+def thetis_set_step_rule(s, rule: int, scale: float = 1.0):
+    _check(lib().thetis_set_step_rule(s, rule, scale))
+
+
+def thetis_run_epochs(s, max_epochs: int, gap_tol: float = 0.0) -> int:
+    done = C.c_int32()
+    _check(lib().thetis_run_epochs(s, max_epochs, gap_tol, C.byref(done)))
+    return done.value
+
+
+def thetis_residual(s):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().thetis_residual(s, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def thetis_objective(s):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().thetis_objective(s, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def thetis_get_x(s, n: int, m: int = 0, slacks: bool = False):
+    x = np.zeros(n)
+    sl = np.zeros(m) if slacks else None
+    _check(lib().thetis_get_x(s, _ptr(x), _ptr(sl)))
+    return (x, sl) if slacks else x
+
+
+def thetis_set_y(s, y):
+    y = _c(y, np.float64)
+    _check(lib().thetis_set_y(s, _ptr(y)))
+
+
+def thetis_epoch(s) -> int:
+    e = C.c_int64()
+    _check(lib().thetis_epoch(s, C.byref(e)))
+    return e.value
+
+
+def thetis_round(s, rule: int, seed: int, reps: int, nsol: int):
+    sol = np.zeros(nsol, np.int32)
+    cost = C.c_double()
+    aux = np.zeros(2)
+    _check(lib().thetis_round(s, rule, seed, reps, _ptr(sol), C.byref(cost), _ptr(aux)))
+    return sol, cost.value, aux
+
+
+def thetis_check_feasible(s, rule: int, sol=None):
+    sl = _c(sol, np.int32)
+    f, nv = C.c_int32(), C.c_int64()
+    _check(lib().thetis_check_feasible(s, rule, _ptr(sl), C.byref(f), C.byref(nv)))
+    return bool(f.value), nv.value
+
+
+def thetis_set_timing(s, enable: bool):
+    _check(lib().thetis_set_timing(s, int(enable)))
+
+
+K_SWEEP_GROUP, K_SWEEP_HUB, K_SWEEP_BLOCK, K_SWEEP_SLACK, K_REFRESH = 0, 1, 2, 3, 4
+KERNEL_NAMES = {K_SWEEP_GROUP: "k_sweep_group", K_SWEEP_HUB: "k_sweep_hub",
+                K_SWEEP_BLOCK: "k_sweep_block", K_SWEEP_SLACK: "k_sweep_slack",
+                K_REFRESH: "refresh (k_rows+k_cols+k_finalize)"}
+
+
+def thetis_get_timing(s, kind: int):
+    a, b, c = C.c_double(), C.c_int64(), C.c_double()
+    _check(lib().thetis_get_timing(s, kind, C.byref(a), C.byref(b), C.byref(c)))
+    return dict(ms=a.value, launches=b.value, alg_bytes=c.value)
+
+
+def thetis_epoch_traffic(s):
+    a, b, c = C.c_double(), C.c_double(), C.c_int64()
+    _check(lib().thetis_epoch_traffic(s, C.byref(a), C.byref(b), C.byref(c)))
+    return dict(sweep_bytes=a.value, refresh_bytes=b.value, updates_per_epoch=c.value)
+
+
+def thetis_solver_destroy(s):
+    _check(lib().thetis_solver_destroy(s))
+
+
+# ------------------------------------------------------------ owning wrappers
+
+class Instance:
+    """An LP instance (``instances.LPInstance``) handed to the library."""
+
+    def __init__(self, inst):
+        self.inst = inst
+        self.h = thetis_inst_create_csr(inst.m, inst.n, inst.nnz, inst.row_ptr, inst.col_idx,
+                                        inst.val, inst.b, inst.c, inst.u, inst.sense)
+        if inst.block_first_col is not None:
+            thetis_inst_set_simplex_blocks(self.h, len(inst.block_first_col), inst.block_k,
+                                           inst.block_first_col, inst.fixed_label)
+        self.m, self.n = inst.m, inst.n
+
+    def classes(self):
+        return thetis_inst_classes(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            thetis_inst_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    """Device state of one solve.  The workspace is a torch uint8 tensor on
+    the current device; launches go to torch's current stream."""
+
+    def __init__(self, instance: Instance, beta: float = 10.0, step_rule: int = STEP_PER_COORD,
+                 step_scale: float = 1.0, prox: bool = False, ybar=None, ubar=None,
+                 schedule: int = SCHED_DET, precision: int = PREC_FP32, refresh_every: int = 5,
+                 seed: int = 0, device=None):
+        if torch is None or not torch.cuda.is_available():
+            raise RuntimeError("libthetis needs a HIP device")
+        self.instance = instance
+        p = thetis_params_default()
+        p.beta, p.step_rule, p.step_scale, p.prox = beta, step_rule, step_scale, int(prox)
+        self._yb = _c(ybar, np.float64)
+        self._ub = _c(ubar, np.float64)
+        p.ybar = None if self._yb is None else self._yb.ctypes.data
+        p.ubar = None if self._ub is None else self._ub.ctypes.data
+        p.schedule, p.precision, p.refresh_every, p.seed = schedule, precision, refresh_every, seed
+        self.params = p
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = thetis_solver_workspace_bytes(instance.h, p)
+        with torch.cuda.device(dev):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            self.stream = torch.cuda.current_stream(dev)
+            self.h = thetis_solver_create(instance.h, p, self.workspace.data_ptr(), nbytes,
+                                          self.stream.cuda_stream)
+        self.n, self.m = instance.n, instance.m
+
+    # thin forwards
+    def reset(self):
+        thetis_solver_reset(self.h)
+
+    def run(self, epochs: int, gap_tol: float = 0.0) -> int:
+        return thetis_run_epochs(self.h, epochs, gap_tol)
+
+    def residual(self):
+        linf, l2, viol = thetis_residual(self.h)
+        return dict(linf=linf, l2=l2, max_viol=viol)
+
+    def objective(self):
+        lp, F, phi = thetis_objective(self.h)
+        return dict(lp_value=lp, F=F, dual_bound=phi)
+
+    def metrics(self) -> dict:
+        d = self.objective()
+        d.update(self.residual())
+        d["gap"] = (d["F"] - d["dual_bound"]) / max(1.0, abs(d["F"]))
+        return d
+
+    @property
+    def x(self) -> np.ndarray:
+        return thetis_get_x(self.h, self.n)
+
+    @property
+    def y(self) -> np.ndarray:
+        x, s = thetis_get_x(self.h, self.n, self.m, slacks=True)
+        return np.concatenate([x, s])
+
+    @y.setter
+    def y(self, v):
+        thetis_set_y(self.h, v)
+
+    @property
+    def epoch(self) -> int:
+        return thetis_epoch(self.h)
+
+    def round(self, rule: int, seed: int = 0, reps: int = 1):
+        inst = self.instance.inst
+        nsol = len(inst.block_first_col) if rule == ROUND_MC_CKR else self.n
+        return thetis_round(self.h, rule, seed, reps, nsol)
+
+    def check(self, rule: int, sol=None):
+        return thetis_check_feasible(self.h, rule, sol)
+
+    def set_timing(self, on: bool = True):
+        thetis_set_timing(self.h, on)
+
+    def timing(self) -> dict:
+        return {KERNEL_NAMES[k]: thetis_get_timing(self.h, k) for k in KERNEL_NAMES}
+
+    def traffic(self) -> dict:
+        return thetis_epoch_traffic(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            thetis_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
