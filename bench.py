@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "coord updates/s + HBM GB/s; batched solves/s and p99 latency at 1e-4 LP gap"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sweep_group_vc_ba2m.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sweep_vc_ba2m.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1311_2661_amd", "csrc", "thetis.hip")
 
 
@@ -154,7 +154,7 @@ def main():
 
     total_updates = args.steps * args.epochs * upd_per_epoch
     value = total_updates / elapsed
-    g = acc["k_sweep_group"]
+    g = acc["k_sweep"]
     avg_ms = g["ms"] / max(g["launches"], 1)
     avg_bytes = g["alg_bytes"] / max(g["launches"], 1)
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -183,7 +183,7 @@ def main():
                    "beta": 10.0, "refresh_every": 5, "schedule": args.schedule,
                    "colour_classes": nclasses, "seed": args.seed},
         "hbm_gbs_algorithmic_step": step_bytes / (elapsed / args.steps) / 1e9,
-        "roofline": {"bound": "hbm", "kernel": "k_sweep_group", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": tr, "alg_bytes_per_launch": avg_bytes, "avg_launch_us": 1e3 * avg_ms},
         "kernels": kernels,

@@ -212,12 +212,14 @@ thetis_status thetis_check_feasible(thetis_solver *s, int32_t rule, const int32_
 
 /* Kernel groups for timing and traffic figures. */
 enum {
-    THETIS_K_SWEEP_GROUP = 0,   /* lane-group coordinate kernel (columns <= 64 entries) */
-    THETIS_K_SWEEP_HUB = 1,     /* workgroup-per-column kernel (columns > 64 entries)  */
-    THETIS_K_SWEEP_BLOCK = 2,   /* simplex-block kernel                                */
-    THETIS_K_SWEEP_SLACK = 3,   /* slack kernel                                        */
-    THETIS_K_REFRESH = 4,       /* FP64 refresh + reductions (three launches)          */
-    THETIS_K_NKINDS = 5
+    THETIS_K_SWEEP_COLUMNS = 0, /* k_sweep: the plain columns of one class (or of a
+                                   whole ASYNC epoch) -- LDS-staged hub workgroups
+                                   and lane groups in one launch                  */
+    THETIS_K_SWEEP_BLOCK = 1,   /* k_sweep_block: simplex blocks of one class       */
+    THETIS_K_SWEEP_SLACK = 2,   /* k_sweep_slack: the slack class                   */
+    THETIS_K_REFRESH = 3,       /* FP64 refresh + reductions (k_rows, k_dual,
+                                   k_finalize)                                      */
+    THETIS_K_NKINDS = 4
 };
 
 /* Turns per-launch HIP-event timing on or off (events are recorded on the

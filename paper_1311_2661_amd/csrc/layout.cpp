@@ -159,6 +159,31 @@ static ClassPlan plan_units(const Inst &in, const std::vector<int64_t> &units,
     return cp;
 }
 
+static void pack(const Inst &in, const std::vector<int32_t> &sched,
+                 const std::vector<const ClassPlan *> &plans, Packed &pk) {
+    std::vector<int8_t> plain(sched.size(), 0);
+    for (const ClassPlan *cp : plans)
+        for (const Segment &sg : cp->segs)
+            if (sg.kind < kGroupKinds || sg.kind == SEG_HUB)
+                for (int64_t q = 0; q < sg.count; ++q) plain[sg.first + q] = 1;
+    pk.ptr.assign(sched.size() + 1, 0);
+    for (size_t q = 0; q < sched.size(); ++q) {
+        const int32_t j = sched[q];
+        pk.ptr[q + 1] = pk.ptr[q] + (plain[q] ? in.col_ptr[j + 1] - in.col_ptr[j] : 0);
+    }
+    pk.row.resize(pk.ptr.back());
+    if (!in.unit_vals) pk.val.resize(pk.ptr.back());
+    for (size_t q = 0; q < sched.size(); ++q) {
+        if (!plain[q]) continue;
+        const int32_t j = sched[q];
+        int32_t w = pk.ptr[q];
+        for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e, ++w) {
+            pk.row[w] = in.row_idx[e];
+            if (!in.unit_vals) pk.val[w] = in.cval[e];
+        }
+    }
+}
+
 thetis_status build_layout(Inst &in) {
     try {
         build_csc(in);
@@ -173,6 +198,10 @@ thetis_status build_layout(Inst &in) {
         for (int64_t t = 0; t < in.nunits; ++t) (in.ukind[t] == 2 ? sl : st).push_back(t);
         in.async_struct = plan_units(in, st, in.async_sched);
         in.async_slack = plan_units(in, sl, in.async_sched);
+        std::vector<const ClassPlan *> det;
+        for (const ClassPlan &cp : in.classes) det.push_back(&cp);
+        pack(in, in.sched, det, in.pk_det);
+        pack(in, in.async_sched, {&in.async_struct, &in.async_slack}, in.pk_async);
         in.planned = true;
     } catch (const std::bad_alloc &) {
         return fail(THETIS_ENOMEM, "host allocation failed while building the layout");

@@ -127,123 +127,155 @@ __device__ __forceinline__ void r_add(R *p, R cur, R d, bool async_mode) {
     else *p = cur + d;
 }
 
+// A schedule as the kernels see it: unit ids in plan order and, for plain
+// columns, their entries packed in the same order.
+template <class R>
+struct Sched {
+    const int32_t *ids;
+    const int32_t *ptr;
+    const int32_t *row;
+    const R *val;          // null when every entry is 1
+};
+
+// Grid layout of one fused launch: the workgroup ranges of the segment
+// kinds in this order (hubs first so their long gathers start early).
+constexpr int kGridKinds = SEG_NKIND + 1;   // + the per-column terms of the dual pass
+// grid position -> segment kind: HUB, G4..G64, BLOCK, SLACK, column terms
+__host__ __device__ constexpr int grid_kind(int p) {
+    return p == 0 ? SEG_HUB : (p <= kGroupKinds ? p - 1 : (p == 6 ? SEG_BLOCK : (p == 7 ? SEG_SLACK : SEG_NKIND)));
+}
+__host__ __device__ constexpr int grid_pos(int kind) {
+    return kind == SEG_HUB ? 0 : (kind < kGroupKinds ? kind + 1 : (kind == SEG_BLOCK ? 6 : (kind == SEG_SLACK ? 7 : 8)));
+}
+struct LaunchPlan {
+    int64_t wg_start[kGridKinds + 1];   // by grid position
+    int64_t first[kGridKinds];          // offset of the segment in its schedule
+    int64_t count[kGridKinds];          // units of the segment
+    int64_t hub_wg;                     // hub workgroups, a multiple of 8
+    int64_t nwg;
+};
+
+__device__ __forceinline__ int locate(const LaunchPlan &pl, int64_t b, int64_t *local) {
+    const int64_t L = b < pl.hub_wg ? b : pl.hub_wg + xcd_remap(b - pl.hub_wg, pl.nwg - pl.hub_wg);
+    int p = 0;
+    while (p < kGridKinds - 1 && L >= pl.wg_start[p + 1]) ++p;
+    *local = L - pl.wg_start[p];
+    return p;
+}
+
+template <class P>
+__device__ __forceinline__ typename P::R gradient(const Dev<P> &a, int64_t j, typename P::R y,
+                                                  typename P::R dot) {
+    using R = typename P::R;
+    R g = (a.ctil ? a.ctil[j] : (R)a.c[j]) + a.beta * dot;
+    if (a.prox_on) g += a.rho * (y - (a.ybar ? a.ybar[j] : R(0)));
+    return g;
+}
+
+template <class P, bool VALS>
+__device__ __forceinline__ typename P::R curvature(const Dev<P> &a, int64_t j, int32_t d) {
+    using R = typename P::R;
+    if (a.global_lmax) return a.Lmax;
+    return a.beta * (VALS ? a.norm2[j] : (R)d) + a.rho;
+}
+
 // one plain column per group of G lanes
 template <class P, bool VALS, int G>
-__device__ __forceinline__ void sweep_group(const Dev<P> &a, const int32_t *__restrict__ list,
-                                            int64_t count, int64_t lwg) {
+__device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typename P::R> &sc,
+                                            int64_t first, int64_t count, int64_t lwg) {
     using R = typename P::R;
     const int lane = threadIdx.x & (G - 1);
     const int64_t u = lwg * (kWG / G) + (threadIdx.x / G);
     if (u >= count) return;           // the whole group leaves together
-    const int32_t j = list[u];
-    const int32_t e0 = a.col_ptr[j], e1 = a.col_ptr[j + 1];
+    const int64_t q = first + u;
+    const int32_t j = sc.ids[q];
+    const int32_t e0 = sc.ptr[q], e1 = sc.ptr[q + 1];
     R acc = R(0), r0 = R(0), v0 = R(1);
     int32_t row0 = -1;
     for (int32_t e = e0 + lane; e < e1; e += G) {
-        const int32_t row = a.row_idx[e];
+        const int32_t row = sc.row[e];
         const R rv = a.r[row];
-        const R v = VALS ? a.cval[e] : R(1);
+        const R v = VALS ? sc.val[e] : R(1);
         if (row0 < 0) { row0 = row; r0 = rv; v0 = v; }
         acc += VALS ? v * rv : rv;
     }
     acc = group_sum<G>(acc);
     const R y = (R)a.x[j];
-    R g = (a.ctil ? a.ctil[j] : (R)a.c[j]) + a.beta * acc;
-    if (a.prox_on) g += a.rho * (y - (a.ybar ? a.ybar[j] : R(0)));
-    R L;
-    if (a.global_lmax) L = a.Lmax;
-    else L = a.beta * (VALS ? a.norm2[j] : (R)(e1 - e0)) + a.rho;
-    const R yn = coord_step(y, g, L, a.gamma, col_bound(a, j));
+    const R g = gradient(a, j, y, acc);
+    const R yn = coord_step(y, g, curvature<P, VALS>(a, j, e1 - e0), a.gamma, col_bound(a, j));
     const R d = yn - y;
     if (lane == 0) a.x[j] = yn;
     if (d != R(0)) {
-        bool first = true;
+        bool first_e = true;
         for (int32_t e = e0 + lane; e < e1; e += G) {
-            if (first) {
+            if (first_e) {
                 r_add(a.r + row0, r0, VALS ? d * v0 : d, a.async_mode);
-                first = false;
+                first_e = false;
             } else {
-                const int32_t row = a.row_idx[e];
-                const R v = VALS ? a.cval[e] : R(1);
-                R *p = a.r + row;
-                r_add(p, a.async_mode ? R(0) : *p, VALS ? d * v : d, a.async_mode);
+                R *p = a.r + sc.row[e];
+                r_add(p, a.async_mode ? R(0) : *p, VALS ? d * sc.val[e] : d, a.async_mode);
             }
         }
     }
 }
 
-struct GroupPlan {
-    int64_t first[kGroupKinds];
-    int64_t count[kGroupKinds];
-    int64_t wg_start[kGroupKinds + 1];
+// High-degree column: one workgroup.  The gather is unrolled four deep so
+// each thread keeps four residual loads in flight; the gathered entries and
+// their rows are staged in LDS so the scatter does not re-read global memory.
+template <class P>
+struct HubTile {
+    static constexpr int n = sizeof(typename P::R) == 4 ? 2048 : 1024;
 };
 
 template <class P, bool VALS>
-__global__ __launch_bounds__(kWG) void k_sweep_group(Dev<P> a, const int32_t *__restrict__ sched,
-                                                     GroupPlan gp) {
-    const int64_t nwg = gp.wg_start[kGroupKinds];
-    const int64_t L = xcd_remap(blockIdx.x, nwg);
-    int s = 0;
-    while (s < kGroupKinds - 1 && L >= gp.wg_start[s + 1]) ++s;
-    const int32_t *list = sched + gp.first[s];
-    const int64_t lw = L - gp.wg_start[s];
-    switch (s) {
-        case 0: sweep_group<P, VALS, 4>(a, list, gp.count[0], lw); break;
-        case 1: sweep_group<P, VALS, 8>(a, list, gp.count[1], lw); break;
-        case 2: sweep_group<P, VALS, 16>(a, list, gp.count[2], lw); break;
-        case 3: sweep_group<P, VALS, 32>(a, list, gp.count[3], lw); break;
-        default: sweep_group<P, VALS, 64>(a, list, gp.count[4], lw); break;
-    }
-}
-
-// High-degree columns: one workgroup each; the gathered residual entries and
-// their rows are staged in LDS so the scatter does not re-read global memory.
-constexpr int kHubTile = 2048;
-
-template <class P, bool VALS>
-__global__ __launch_bounds__(kWG) void k_sweep_hub(Dev<P> a, const int32_t *__restrict__ list,
-                                                   int64_t count) {
+__device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename P::R> &sc,
+                                          int64_t q, typename P::R *st_r, int32_t *st_row,
+                                          typename P::R *red) {
     using R = typename P::R;
-    __shared__ R st_r[kHubTile];
-    __shared__ int32_t st_row[kHubTile];
-    __shared__ R red[kWG / 64];
+    constexpr int TILE = HubTile<P>::n;
     const int tid = threadIdx.x;
-    for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
-        const int32_t j = list[u];
-        const int32_t e0 = a.col_ptr[j], e1 = a.col_ptr[j + 1];
-        R acc = R(0);
-        for (int32_t e = e0 + tid; e < e1; e += kWG) {
-            const int32_t row = a.row_idx[e];
-            const R rv = a.r[row];
-            const int32_t q = e - e0;
-            if (q < kHubTile) { st_r[q] = rv; st_row[q] = row; }
-            acc += VALS ? a.cval[e] * rv : rv;
-        }
-        acc = group_sum<64>(acc);
-        if ((tid & 63) == 0) red[tid >> 6] = acc;
-        __syncthreads();
-        R tot = red[0];
+    const int32_t j = sc.ids[q];
+    const int32_t e0 = sc.ptr[q], e1 = sc.ptr[q + 1];
+    R acc = R(0);
+    for (int32_t base = e0; base < e1; base += 4 * kWG) {
+        int32_t rw[4];
+        R rv[4];
 #pragma unroll
-        for (int w = 1; w < kWG / 64; ++w) tot += red[w];
-        __syncthreads();
-        const R y = (R)a.x[j];
-        R g = (a.ctil ? a.ctil[j] : (R)a.c[j]) + a.beta * tot;
-        if (a.prox_on) g += a.rho * (y - (a.ybar ? a.ybar[j] : R(0)));
-        R L;
-        if (a.global_lmax) L = a.Lmax;
-        else L = a.beta * (VALS ? a.norm2[j] : (R)(e1 - e0)) + a.rho;
-        const R yn = coord_step(y, g, L, a.gamma, col_bound(a, j));
-        const R d = yn - y;
-        if (tid == 0) a.x[j] = yn;
-        if (d != R(0)) {
-            for (int32_t e = e0 + tid; e < e1; e += kWG) {
-                const int32_t q = e - e0;
-                const R dv = VALS ? d * a.cval[e] : d;
-                if (q < kHubTile) r_add(a.r + st_row[q], st_r[q], dv, a.async_mode);
-                else {
-                    R *p = a.r + a.row_idx[e];
-                    r_add(p, a.async_mode ? R(0) : *p, dv, a.async_mode);
-                }
+        for (int t = 0; t < 4; ++t) {
+            const int32_t e = base + t * kWG + tid;
+            rw[t] = e < e1 ? sc.row[e] : -1;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) rv[t] = rw[t] >= 0 ? a.r[rw[t]] : R(0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int32_t e = base + t * kWG + tid;
+            if (rw[t] >= 0) {
+                const int32_t o = e - e0;
+                if (o < TILE) { st_r[o] = rv[t]; st_row[o] = rw[t]; }
+                acc += VALS ? sc.val[e] * rv[t] : rv[t];
+            }
+        }
+    }
+    acc = group_sum<64>(acc);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    R tot = red[0];
+#pragma unroll
+    for (int w = 1; w < kWG / 64; ++w) tot += red[w];
+    const R y = (R)a.x[j];
+    const R g = gradient(a, j, y, tot);
+    const R yn = coord_step(y, g, curvature<P, VALS>(a, j, e1 - e0), a.gamma, col_bound(a, j));
+    const R d = yn - y;
+    if (tid == 0) a.x[j] = yn;
+    if (d != R(0)) {
+        for (int32_t e = e0 + tid; e < e1; e += kWG) {
+            const int32_t o = e - e0;
+            const R dv = VALS ? d * sc.val[e] : d;
+            if (o < TILE) r_add(a.r + st_row[o], st_r[o], dv, a.async_mode);
+            else {
+                R *p = a.r + sc.row[e];
+                r_add(p, a.async_mode ? R(0) : *p, dv, a.async_mode);
             }
         }
     }
@@ -256,13 +288,9 @@ __global__ __launch_bounds__(kWG) void k_sweep_hub(Dev<P> a, const int32_t *__re
 // downwards (Held, Wolfe & Crowder; Duchi et al.), every lane evaluating
 // one candidate j without sorting.
 template <class P, bool VALS>
-__global__ __launch_bounds__(kWG) void k_sweep_block(Dev<P> a, const int32_t *__restrict__ list,
-                                                     int64_t count, int32_t lpc) {
+__device__ __forceinline__ void sweep_block(const Dev<P> &a, int32_t blk, int lpc) {
     using R = typename P::R;
     const int lane = threadIdx.x & 63;
-    const int64_t u = xcd_remap(blockIdx.x, gridDim.x) * (kWG / 64) + (threadIdx.x >> 6);
-    if (u >= count) return;
-    const int32_t blk = list[u];
     const int32_t k = a.k;
     const int ci = lane / lpc, sub = lane % lpc;
     const bool own = ci < k;
@@ -278,8 +306,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_block(Dev<P> a, const int32_t *__
     R y = R(0), v = R(0);
     if (own) {
         y = (R)a.x[j];
-        R g = (a.ctil ? a.ctil[j] : (R)a.c[j]) + a.beta * acc;
-        if (a.prox_on) g += a.rho * (y - (a.ybar ? a.ybar[j] : R(0)));
+        const R g = gradient(a, j, y, acc);
         v = L > R(0) ? y - a.gamma * g / L : y;
     }
     // lane q < k takes the value of column q; every shuffle runs with the
@@ -308,12 +335,8 @@ __global__ __launch_bounds__(kWG) void k_sweep_block(Dev<P> a, const int32_t *__
 
 // slack s_i of an inequality row: column -e_i ('>=') or +e_i ('<='), s >= 0
 template <class P>
-__global__ __launch_bounds__(kWG) void k_sweep_slack(Dev<P> a, const int32_t *__restrict__ list,
-                                                     int64_t count) {
+__device__ __forceinline__ void sweep_slack(const Dev<P> &a, int64_t i) {
     using R = typename P::R;
-    const int64_t q = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (q >= count) return;
-    const int64_t i = list ? list[q] : q;
     const R sg = a.sense[i] > 0 ? R(-1) : R(1);
     const R sv = a.s[i], rv = a.r[i];
     R g = (a.ctil ? a.ctil[a.n + i] : R(0)) + a.beta * (sg * rv);
@@ -327,6 +350,47 @@ __global__ __launch_bounds__(kWG) void k_sweep_slack(Dev<P> a, const int32_t *__
         if (a.async_mode) unsafeAtomicAdd(a.r + i, sg * d);
         else a.r[i] = rv + sg * d;
     }
+}
+
+// One class (DET) or one whole epoch part (ASYNC) in a single launch.
+// The plain columns of one class (DET) or of a whole epoch (ASYNC) in one
+// launch: hub workgroups first, then the lane-group ranges.
+template <class P, bool VALS>
+__global__ __launch_bounds__(kWG) void k_sweep(Dev<P> a, Sched<typename P::R> sc, LaunchPlan pl) {
+    using R = typename P::R;
+    __shared__ R st_r[HubTile<P>::n];
+    __shared__ int32_t st_row[HubTile<P>::n];
+    __shared__ R red[kWG / 64];
+    int64_t local;
+    const int p = locate(pl, blockIdx.x, &local);
+    const int64_t first = pl.first[p], count = pl.count[p];
+    switch (grid_kind(p)) {
+        case SEG_HUB:
+            if (local < count) sweep_hub<P, VALS>(a, sc, first + local, st_r, st_row, red);
+            break;
+        case SEG_G4: sweep_group<P, VALS, 4>(a, sc, first, count, local); break;
+        case SEG_G8: sweep_group<P, VALS, 8>(a, sc, first, count, local); break;
+        case SEG_G16: sweep_group<P, VALS, 16>(a, sc, first, count, local); break;
+        case SEG_G32: sweep_group<P, VALS, 32>(a, sc, first, count, local); break;
+        case SEG_G64: sweep_group<P, VALS, 64>(a, sc, first, count, local); break;
+        default: break;
+    }
+}
+
+// the simplex blocks of one class: one wavefront per block
+template <class P, bool VALS>
+__global__ __launch_bounds__(kWG) void k_sweep_block(Dev<P> a, const int32_t *__restrict__ list,
+                                                     int64_t count, int32_t lpc) {
+    const int64_t u = xcd_remap(blockIdx.x, gridDim.x) * (kWG / 64) + (threadIdx.x >> 6);
+    if (u < count) sweep_block<P, VALS>(a, list[u], lpc);
+}
+
+// the slack class: one lane per inequality row
+template <class P>
+__global__ __launch_bounds__(kWG) void k_sweep_slack(Dev<P> a, const int32_t *__restrict__ list,
+                                                     int64_t count) {
+    const int64_t u = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (u < count) sweep_slack<P>(a, list ? list[u] : u);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -380,7 +444,7 @@ __device__ __forceinline__ double box_min(double red, double U, double rho, doub
 // unbounded slack columns keep a non-negative reduced cost when rho = 0),
 // rounded once to storage precision and used for every term of Phi.
 template <class P>
-__global__ __launch_bounds__(kWG) void k_rows(Dev<P> a, int32_t write_r, double *part) {
+__global__ __launch_bounds__(kWG) void k_rows(Dev<P> a, int32_t write_r, int32_t with_dual, double *part) {
     using R = typename P::R;
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
     double v[kRowSlots] = {0, 0, 0, 0, 0, 0};
@@ -402,7 +466,7 @@ __global__ __launch_bounds__(kWG) void k_rows(Dev<P> a, int32_t write_r, double 
             if (sn < 0 && ui > 0.0) ui = 0.0;
         }
         const R ur = (R)ui;
-        a.udual[i] = ur;
+        if (with_dual) a.udual[i] = ur;
         const double ud = (double)ur;
         v[0] = w * w;
         v[1] = fabs(w);
@@ -415,82 +479,141 @@ __global__ __launch_bounds__(kWG) void k_rows(Dev<P> a, int32_t write_r, double 
     block_reduce<kRowSlots>(v, op, part + (int64_t)blockIdx.x * kRowSlots);
 }
 
-// Column pass over [columns | blocks | slacks]: c^T x, the prox part of F,
-// and per variable the minimum of its reduced-cost term over its feasible
-// set (the inner minimisation of the dual function Phi).
+// Workgroup sum of one double, returned to every thread (fixed order).
+__device__ double block_sum_all(double v, double *sh) {
+    v = wsum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = sh[0];
+    for (int w = 1; w < kWG / 64; ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
 template <class P>
-__global__ __launch_bounds__(kWG) void k_cols(Dev<P> a, double *part) {
-    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+__device__ __forceinline__ double col_ubound(const Dev<P> &a, int64_t j) {
+    return a.ub ? (double)a.ub[j] : (double)a.ub_value;
+}
+
+// Column pass of the refresh, on the ASYNC plan (every structural unit in
+// degree buckets, then the slacks) plus one range over all columns for
+// c^T x and the prox part of F.  Per variable: the minimum over its
+// feasible set of its reduced-cost term (the inner minimisation of the dual
+// function Phi), with the reduced cost gathered lane-group parallel like the
+// sweep.  Every workgroup writes kColSlots partials.
+template <class P, bool VALS>
+__global__ __launch_bounds__(kWG) void k_dual(Dev<P> a, Sched<typename P::R> sc, LaunchPlan pl,
+                                              int32_t slack_identity, double *part) {
+    __shared__ double sh[kWG / 64];
+    int64_t local;
+    const int p = locate(pl, blockIdx.x, &local);
+    const int64_t first = pl.first[p], count = pl.count[p];
+    const int kind = grid_kind(p);
+    const double rho = (double)a.rho;
     double v[kColSlots] = {0, 0, 0};
     const int op[kColSlots] = {0, 0, 0};
-    const double rho = (double)a.rho;
-    if (t < a.n) {
-        const int64_t j = t;
-        const double xj = (double)a.x[j];
-        v[1] = a.c[j] * xj;
-        const double yb = a.ybar ? (double)a.ybar[j] : 0.0;
-        if (a.prox_on) v[2] = 0.5 * rho * (xj - yb) * (xj - yb);
-        if (!(a.col_block && a.col_block[j] >= 0)) {
-            double red = a.c[j];
-            for (int32_t e = a.col_ptr[j]; e < a.col_ptr[j + 1]; ++e)
-                red -= (a.cval ? (double)a.cval[e] : 1.0) * (double)a.udual[a.row_idx[e]];
-            const double U = a.ub ? (double)a.ub[j] : (double)a.ub_value;
-            v[0] = box_min(red, U, rho, yb);
+    if (kind == SEG_HUB) {
+        const bool valid = local < count;
+        double acc = 0.0;
+        int32_t j = 0;
+        if (valid) {
+            const int64_t q = first + local;
+            j = sc.ids[q];
+            for (int32_t e = sc.ptr[q] + threadIdx.x; e < sc.ptr[q + 1]; e += kWG)
+                acc += (VALS ? (double)sc.val[e] : 1.0) * (double)a.udual[sc.row[e]];
         }
-    } else if (t < a.n + a.nblocks) {
-        const int64_t bl = t - a.n;
-        const int32_t j0 = a.bfirst[bl], k = a.k;
-        double red[64], yb[64];
-        for (int i = 0; i < k; ++i) {
-            const int32_t j = j0 + i;
-            double rr = a.c[j];
-            for (int32_t e = a.col_ptr[j]; e < a.col_ptr[j + 1]; ++e)
-                rr -= (a.cval ? (double)a.cval[e] : 1.0) * (double)a.udual[a.row_idx[e]];
-            red[i] = rr;
-            yb[i] = a.ybar ? (double)a.ybar[j] : 0.0;
+        acc = block_sum_all(acc, sh);
+        if (valid && threadIdx.x == 0)
+            v[0] = box_min(a.c[j] - acc, col_ubound(a, j), rho, a.ybar ? (double)a.ybar[j] : 0.0);
+    } else if (kind < kGroupKinds) {
+        const int G = 4 << kind;
+        const int lane = threadIdx.x & (G - 1);
+        const int64_t u = local * (kWG / G) + threadIdx.x / G;
+        const bool valid = u < count;
+        double acc = 0.0;
+        int32_t j = 0;
+        if (valid) {
+            const int64_t q = first + u;
+            j = sc.ids[q];
+            for (int32_t e = sc.ptr[q] + lane; e < sc.ptr[q + 1]; e += G)
+                acc += (VALS ? (double)sc.val[e] : 1.0) * (double)a.udual[sc.row[e]];
         }
-        if (a.fixed[bl] >= 0) {
-            const int f = a.fixed[bl];
-            double val = red[f];
-            if (a.prox_on)
-                for (int i = 0; i < k; ++i) {
-                    const double d = (i == f ? 1.0 : 0.0) - yb[i];
-                    val += 0.5 * rho * d * d;
-                }
-            v[0] = val;
-        } else if (a.prox_on) {
-            // minimiser of red^T y + rho/2||y - yb||^2 over the simplex:
-            // projection of yb - red/rho, theta from the sorted prefixes
-            double w[64];
-            for (int i = 0; i < k; ++i) w[i] = yb[i] - red[i] / rho;
-            double theta = -INFINITY;
-            for (int q = 0; q < k; ++q) {
-                double ps = 0.0;
-                int cnt = 0;
-                for (int l = 0; l < k; ++l)
-                    if (w[l] > w[q] || (w[l] == w[q] && l <= q)) { ps += w[l]; ++cnt; }
-                theta = fmax(theta, (ps - 1.0) / cnt);
-            }
-            double val = 0.0;
+        for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (valid && lane == 0)
+            v[0] = box_min(a.c[j] - acc, col_ubound(a, j), rho, a.ybar ? (double)a.ybar[j] : 0.0);
+    } else if (kind == SEG_BLOCK) {
+        const int64_t u = local * kWG + threadIdx.x;
+        if (u < count) {
+            const int32_t bl = sc.ids[first + u];
+            const int32_t j0 = a.bfirst[bl], k = a.k;
+            double red[64], yb[64];
             for (int i = 0; i < k; ++i) {
-                const double yi = fmax(w[i] - theta, 0.0);
-                val += red[i] * yi + 0.5 * rho * (yi - yb[i]) * (yi - yb[i]);
+                const int32_t j = j0 + i;
+                double rr = a.c[j];
+                for (int32_t e = a.col_ptr[j]; e < a.col_ptr[j + 1]; ++e)
+                    rr -= (VALS ? (double)a.cval[e] : 1.0) * (double)a.udual[a.row_idx[e]];
+                red[i] = rr;
+                yb[i] = a.ybar ? (double)a.ybar[j] : 0.0;
             }
-            v[0] = val;
-        } else {
-            double mn = red[0];
-            for (int i = 1; i < k; ++i) mn = fmin(mn, red[i]);
-            v[0] = mn;
+            if (a.prox_on) {
+                // minimiser of red^T y + rho/2||y - yb||^2 over the simplex:
+                // projection of yb - red/rho
+                double w[64];
+                for (int i = 0; i < k; ++i) w[i] = yb[i] - red[i] / rho;
+                double theta = -INFINITY;
+                for (int q = 0; q < k; ++q) {
+                    double ps = 0.0;
+                    int cnt = 0;
+                    for (int l = 0; l < k; ++l)
+                        if (w[l] > w[q] || (w[l] == w[q] && l <= q)) { ps += w[l]; ++cnt; }
+                    theta = fmax(theta, (ps - 1.0) / cnt);
+                }
+                double val = 0.0;
+                for (int i = 0; i < k; ++i) {
+                    const double yi = fmax(w[i] - theta, 0.0);
+                    val += red[i] * yi + 0.5 * rho * (yi - yb[i]) * (yi - yb[i]);
+                }
+                v[0] = val;
+            } else {
+                double mn = red[0];
+                for (int i = 1; i < k; ++i) mn = fmin(mn, red[i]);
+                v[0] = mn;
+            }
         }
-    } else if (t < a.n + a.nblocks + a.m) {
-        const int64_t i = t - a.n - a.nblocks;
-        const int8_t sn = a.sense[i];
-        if (sn != 0) {
+    } else if (kind == SEG_SLACK) {
+        const int64_t u = local * kWG + threadIdx.x;
+        if (u < count) {
+            const int64_t i = slack_identity ? u : sc.ids[first + u];
+            const int8_t sn = a.sense[i];
             const double sv = (double)a.s[i];
             const double yb = a.ybar ? (double)a.ybar[a.n + i] : 0.0;
             if (a.prox_on) v[2] = 0.5 * rho * (sv - yb) * (sv - yb);
-            const double red = (sn > 0 ? 1.0 : -1.0) * (double)a.udual[i];
-            v[0] = box_min(red, INFINITY, rho, yb);
+            v[0] = box_min((sn > 0 ? 1.0 : -1.0) * (double)a.udual[i], INFINITY, rho, yb);
+        }
+    } else {
+        // every structural column: c^T x, the prox part of F, and the fixed
+        // simplex blocks' contribution to Phi (their first column's thread)
+        const int64_t j = local * kWG + threadIdx.x;
+        if (j < a.n) {
+            const double xj = (double)a.x[j];
+            v[1] = a.c[j] * xj;
+            const double yb = a.ybar ? (double)a.ybar[j] : 0.0;
+            if (a.prox_on) v[2] = 0.5 * rho * (xj - yb) * (xj - yb);
+            const int32_t bl = a.col_block ? a.col_block[j] : -1;
+            if (bl >= 0 && a.fixed[bl] >= 0 && j == a.bfirst[bl]) {
+                const int f = a.fixed[bl], k = a.k;
+                const int32_t jf = a.bfirst[bl] + f;
+                double val = a.c[jf];
+                for (int32_t e = a.col_ptr[jf]; e < a.col_ptr[jf + 1]; ++e)
+                    val -= (VALS ? (double)a.cval[e] : 1.0) * (double)a.udual[a.row_idx[e]];
+                if (a.prox_on)
+                    for (int i = 0; i < k; ++i) {
+                        const double ybi = a.ybar ? (double)a.ybar[a.bfirst[bl] + i] : 0.0;
+                        const double d = (i == f ? 1.0 : 0.0) - ybi;
+                        val += 0.5 * rho * d * d;
+                    }
+                v[0] = val;
+            }
         }
     }
     block_reduce<kColSlots>(v, op, part + (int64_t)blockIdx.x * kColSlots);
@@ -499,36 +622,57 @@ __global__ __launch_bounds__(kWG) void k_cols(Dev<P> a, double *part) {
 // metrics slots
 enum { MT_F = 0, MT_CX, MT_LINF, MT_L2, MT_VIOL, MT_PHI, MT_GAP, MT_BAD, MT_NSLOT = 16 };
 
-__global__ __launch_bounds__(kWG) void k_finalize(const double *rp, int64_t nr, const double *cp,
-                                                  int64_t nc, double beta, double *mt) {
-    __shared__ double sh[kWG][kRowSlots + kColSlots];
+// One workgroup folds nb records of NS partial slots in a fixed order:
+// thread t takes records t, t+256, ..., then a pairwise tree.  op: 0 sum,
+// 1 max, 2 min.  The result is valid in thread 0.
+template <int NS>
+__device__ void fold_records(const double *part, int64_t nb, const int (&op)[NS], double (&out)[NS]) {
+    __shared__ double sh[kWG][NS];
     const int t = threadIdx.x;
-    double acc[kRowSlots + kColSlots];
-    for (int q = 0; q < kRowSlots + kColSlots; ++q) acc[q] = 0.0;
-    for (int64_t b = t; b < nr; b += kWG)
-        for (int q = 0; q < kRowSlots; ++q)
-            acc[q] = (q == 1 || q == 2) ? fmax(acc[q], rp[b * kRowSlots + q]) : acc[q] + rp[b * kRowSlots + q];
-    for (int64_t b = t; b < nc; b += kWG)
-        for (int q = 0; q < kColSlots; ++q) acc[kRowSlots + q] += cp[b * kColSlots + q];
-    for (int q = 0; q < kRowSlots + kColSlots; ++q) sh[t][q] = acc[q];
+    double acc[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) acc[q] = op[q] == 0 ? 0.0 : (op[q] == 1 ? -INFINITY : INFINITY);
+    for (int64_t b = t; b < nb; b += kWG)
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const double x = part[b * NS + q];
+            acc[q] = op[q] == 0 ? acc[q] + x : (op[q] == 1 ? fmax(acc[q], x) : fmin(acc[q], x));
+        }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) sh[t][q] = acc[q];
     __syncthreads();
-    if (t == 0) {
-        double s[kRowSlots + kColSlots];
-        for (int q = 0; q < kRowSlots + kColSlots; ++q) s[q] = sh[0][q];
-        for (int u = 1; u < kWG; ++u)
-            for (int q = 0; q < kRowSlots + kColSlots; ++q)
-                s[q] = (q == 1 || q == 2) ? fmax(s[q], sh[u][q]) : s[q] + sh[u][q];
-        const double F = s[kRowSlots + 1] + s[5] + 0.5 * beta * s[0] + s[kRowSlots + 2];
-        const double phi = s[3] - s[4] / (2.0 * beta) + s[kRowSlots + 0];
+    for (int w = kWG / 2; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const double x = sh[t + w][q];
+                sh[t][q] = op[q] == 0 ? sh[t][q] + x : (op[q] == 1 ? fmax(sh[t][q], x) : fmin(sh[t][q], x));
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) out[q] = sh[0][q];
+}
+
+__global__ __launch_bounds__(kWG) void k_finalize(const double *rp, int64_t nr, const double *cp,
+                                                  int64_t nc, double beta, int32_t with_dual, double *mt) {
+    const int rop[kRowSlots] = {0, 1, 1, 0, 0, 0};
+    const int cop[kColSlots] = {0, 0, 0};
+    double rs[kRowSlots], cs[kColSlots];
+    fold_records<kRowSlots>(rp, nr, rop, rs);
+    fold_records<kColSlots>(cp, nc, cop, cs);
+    if (threadIdx.x == 0) {
+        const double F = cs[1] + rs[5] + 0.5 * beta * rs[0] + cs[2];
+        const double phi = rs[3] - rs[4] / (2.0 * beta) + cs[0];
         mt[MT_F] = F;
-        mt[MT_CX] = s[kRowSlots + 1];
-        mt[MT_LINF] = s[1];
-        mt[MT_L2] = sqrt(s[0]);
-        mt[MT_VIOL] = s[2];
-        mt[MT_PHI] = phi;
+        mt[MT_CX] = cs[1];
+        mt[MT_LINF] = rs[1];
+        mt[MT_L2] = sqrt(rs[0]);
+        mt[MT_VIOL] = rs[2];
         const double den = fabs(F) > 1.0 ? fabs(F) : 1.0;
-        mt[MT_GAP] = (F - phi) / den;
-        mt[MT_BAD] = (isfinite(F) && isfinite(s[0])) ? 0.0 : 1.0;
+        mt[MT_PHI] = with_dual ? phi : NAN;
+        mt[MT_GAP] = with_dual ? (F - phi) / den : NAN;
+        mt[MT_BAD] = (isfinite(F) && isfinite(rs[0])) ? 0.0 : 1.0;
     }
 }
 
@@ -556,13 +700,13 @@ __global__ __launch_bounds__(kWG) void k_edge_extreme(Dev<P> a, int32_t op, doub
     }
 }
 
-// 1-thread fold of the edge partials into the threshold (VC: min(1/2, m),
-// MIS: max(1/2, m), alpha: max(0, m))
-__global__ void k_edge_fold(const double *part, int64_t nb, int32_t op, double *out) {
-    if (threadIdx.x || blockIdx.x) return;
-    double t = op == 0 ? 0.5 : (op == 1 ? 0.5 : 0.0);
-    for (int64_t b = 0; b < nb; ++b) t = op == 0 ? fmin(t, part[b]) : fmax(t, part[b]);
-    *out = t;
+// fold of the edge partials into the threshold (VC: min(1/2, m), MIS:
+// max(1/2, m), alpha: max(0, m)); one workgroup
+__global__ __launch_bounds__(kWG) void k_edge_fold(const double *part, int64_t nb, int32_t op, double *out) {
+    const int o[1] = {op == 0 ? 2 : 1};
+    double r[1];
+    fold_records<1>(part, nb, o, r);
+    if (threadIdx.x == 0) *out = op == 0 ? fmin(0.5, r[0]) : (op == 1 ? fmax(0.5, r[0]) : fmax(0.0, r[0]));
 }
 
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
@@ -689,16 +833,19 @@ __global__ __launch_bounds__(kWG) void k_ckr_cost(Dev<P> a, const int32_t *lab, 
 
 // cost fold + keep-best decision: out[0] cost of this repetition, out[1]
 // best cost so far, out[2] 1 when this repetition became the best, out[3]
-// the best repetition (ties keep the earlier one)
-__global__ void k_cost_fold(const double *part, int64_t nb, double scale, int32_t rep, double *out) {
-    if (threadIdx.x || blockIdx.x) return;
-    double t = 0.0;
-    for (int64_t b = 0; b < nb; ++b) t += part[b];
-    t *= scale;
-    out[0] = t;
-    const int better = rep == 0 || t < out[1];
-    if (better) { out[1] = t; out[3] = (double)rep; }
-    out[2] = better ? 1.0 : 0.0;
+// the best repetition (ties keep the earlier one); one workgroup
+__global__ __launch_bounds__(kWG) void k_cost_fold(const double *part, int64_t nb, double scale, int32_t rep,
+                                                   double *out) {
+    const int o[1] = {0};
+    double r[1];
+    fold_records<1>(part, nb, o, r);
+    if (threadIdx.x == 0) {
+        const double t = r[0] * scale;
+        out[0] = t;
+        const int better = rep == 0 || t < out[1];
+        if (better) { out[1] = t; out[3] = (double)rep; }
+        out[2] = better ? 1.0 : 0.0;
+    }
 }
 
 __global__ __launch_bounds__(kWG) void k_copy_if(const double *flag, const int32_t *src, int32_t *dst,
@@ -800,18 +947,29 @@ constexpr int32_t kMaxReps = 64;
 
 // ==================================================================== solver
 
+// launches of one class (DET) or one epoch part (ASYNC)
+struct ClassLaunch {
+    bool has_cols = false;
+    LaunchPlan cols{};                      // hub + lane-group ranges (k_sweep)
+    int64_t block_first = 0, block_count = 0;
+    int64_t slack_first = 0, slack_count = 0;
+    double bytes_cols = 0, bytes_block = 0, bytes_slack = 0;   // algorithmic, per launch
+};
+
 struct thetis_solver {
     // host copy of what the launches need
     int64_t m = 0, n = 0, nnz = 0, nblocks = 0;
     int32_t k = 0, nclasses = 0;
     bool unit_vals = true, uniform_ub = true, all_rows_slack = true;
     double ub_value = 1.0;
-    std::vector<ClassPlan> classes;
-    ClassPlan async_struct, async_slack;
-    int64_t sched_len = 0, async_len = 0;
+    std::vector<ClassLaunch> det;              // per colour class
+    ClassLaunch async_launch;                  // ASYNC: everything of one epoch
+    LaunchPlan dual{};                         // column pass of the refresh, with the dual bound
+    LaunchPlan colterms{};                     // column pass without it (c^T x, prox part of F)
+    bool metrics_dual = false;                 // the fresh metrics include the dual bound
     bool edge_shape_cover = false, edge_shape_pack = false;
-    std::vector<int32_t> col_deg;     // for traffic figures
-    int64_t nunits = 0;
+    int64_t nunits = 0, updates_per_epoch = 0;
+    int32_t lpc = 1;                           // lanes per column of a simplex block
     // parameters
     thetis_params p{};
     double rho = 0.0, Lmax = 0.0;
@@ -824,7 +982,8 @@ struct thetis_solver {
     // device pointers (typed at launch)
     void *col_ptr, *row_idx, *cval, *row_ptr, *csr_col, *csr_val, *b, *sense, *c, *ctil, *ub,
         *norm2, *ybar, *ubar, *bfirst, *fixed, *col_block, *LB, *x, *s, *r, *udual, *sched,
-        *async_sched, *rpart, *cpart, *metrics, *sol, *best, *drop, *ckr_order, *thr, *costbuf,
+        *async_sched, *pk_det_ptr, *pk_det_row, *pk_det_val, *pk_async_ptr, *pk_async_row,
+        *pk_async_val, *rpart, *cpart, *metrics, *sol, *best, *drop, *ckr_order, *thr, *costbuf,
         *chkbuf, *ystage;
     int64_t nwg_rows = 0, nwg_cols = 0;
     int64_t epoch = 0;
@@ -842,11 +1001,7 @@ struct thetis_solver {
     std::vector<double> ev_bytes[THETIS_K_NKINDS];
     double ms[THETIS_K_NKINDS] = {0}, bytes[THETIS_K_NKINDS] = {0};
     int64_t launches[THETIS_K_NKINDS] = {0};
-    // algorithmic bytes per launch of each class segment, by class (DET) and
-    // for the ASYNC plans
-    std::vector<std::vector<double>> seg_bytes;
-    std::vector<double> async_struct_bytes, async_slack_bytes;
-    double refresh_bytes = 0;
+    double refresh_bytes = 0, refresh_bytes_nodual = 0;
 };
 
 namespace {
@@ -863,6 +1018,36 @@ struct Carver {
 };
 
 size_t prec_bytes(int32_t prec) { return prec == THETIS_PREC_FP64 ? 8 : 4; }
+
+int64_t units_per_wg(int kind, bool dual) {
+    if (kind == SEG_HUB) return 1;
+    if (kind < kGroupKinds) return kWG / (4 << kind);
+    if (kind == SEG_BLOCK) return dual ? kWG : kWG / 64;
+    return kWG;
+}
+
+// Workgroup ranges of one fused launch over the given segments (at most one
+// segment per kind) plus, for the dual pass, ncolterms per-column threads.
+LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolterms) {
+    LaunchPlan pl{};
+    for (const Segment &sg : segs) {
+        const int p = grid_pos(sg.kind);
+        pl.first[p] = sg.first;
+        pl.count[p] = sg.count;
+    }
+    pl.count[kGridKinds - 1] = ncolterms;
+    int64_t wg = 0;
+    for (int p = 0; p < kGridKinds; ++p) {
+        pl.wg_start[p] = wg;
+        const int kind = grid_kind(p);
+        int64_t w = pl.count[p] ? cdiv(pl.count[p], kind == SEG_NKIND ? kWG : units_per_wg(kind, dual)) : 0;
+        if (kind == SEG_HUB) { w = cdiv(w, 8) * 8; pl.hub_wg = w; }
+        wg += w;
+    }
+    pl.wg_start[kGridKinds] = wg;
+    pl.nwg = wg;
+    return pl;
+}
 
 // carve the workspace in a fixed order; with base == nullptr it only sizes
 void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
@@ -894,8 +1079,18 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.udual = cv.take(R * std::max<int64_t>(m, 1));
     S.sched = cv.take(4 * std::max<size_t>(in.sched.size(), 1));
     S.async_sched = cv.take(4 * std::max<size_t>(in.async_sched.size(), 1));
+    S.pk_det_ptr = cv.take(4 * in.pk_det.ptr.size());
+    S.pk_det_row = cv.take(4 * std::max<size_t>(in.pk_det.row.size(), 1));
+    S.pk_det_val = in.unit_vals ? nullptr : cv.take(R * std::max<size_t>(in.pk_det.val.size(), 1));
+    S.pk_async_ptr = cv.take(4 * in.pk_async.ptr.size());
+    S.pk_async_row = cv.take(4 * std::max<size_t>(in.pk_async.row.size(), 1));
+    S.pk_async_val = in.unit_vals ? nullptr : cv.take(R * std::max<size_t>(in.pk_async.val.size(), 1));
     S.nwg_rows = std::max<int64_t>(cdiv(std::max(m, n), kWG), 1);
-    S.nwg_cols = std::max<int64_t>(cdiv(n + nb + m, kWG), 1);
+    std::vector<Segment> dsegs = in.async_struct.segs;
+    dsegs.insert(dsegs.end(), in.async_slack.segs.begin(), in.async_slack.segs.end());
+    S.dual = make_plan(dsegs, true, n);
+    S.colterms = make_plan({}, true, n);
+    S.nwg_cols = std::max<int64_t>(S.dual.nwg, 1);
     S.rpart = cv.take(8 * kRowSlots * S.nwg_rows);
     S.cpart = cv.take(8 * kColSlots * S.nwg_cols);
     S.metrics = cv.take(8 * MT_NSLOT);
@@ -952,6 +1147,17 @@ Dev<P> make_dev(const thetis_solver &S) {
     return a;
 }
 
+template <class P>
+Sched<typename P::R> det_sched(const thetis_solver &S) {
+    return {(const int32_t *)S.sched, (const int32_t *)S.pk_det_ptr, (const int32_t *)S.pk_det_row,
+            (const typename P::R *)S.pk_det_val};
+}
+template <class P>
+Sched<typename P::R> async_sched(const thetis_solver &S) {
+    return {(const int32_t *)S.async_sched, (const int32_t *)S.pk_async_ptr, (const int32_t *)S.pk_async_row,
+            (const typename P::R *)S.pk_async_val};
+}
+
 hipEvent_t next_event(thetis_solver &S, int *idx) {
     if (S.ev_used == S.ev_pool.size()) {
         hipEvent_t e;
@@ -986,76 +1192,61 @@ struct TimedScope {
     }
 };
 
-// launches the kernels of one class plan; sb[q] = algorithmic bytes of
-// segment q of the plan
+// the launches of one class: plain columns (hubs + lane groups) in one
+// fused launch, simplex blocks, slacks; all conflict-free among themselves
 template <class P>
-void launch_plan(thetis_solver &S, const Dev<P> &a, const ClassPlan &cp, const int32_t *sched,
-                 const std::vector<double> &sb) {
-    double group_bytes = 0.0;
-    for (size_t q = 0; q < cp.segs.size(); ++q)
-        if (cp.segs[q].kind < kGroupKinds) group_bytes += sb[q];
-    GroupPlan gp;
-    int64_t wg = 0;
-    bool any_group = false;
-    for (int g = 0; g < kGroupKinds; ++g) { gp.first[g] = 0; gp.count[g] = 0; }
-    for (const Segment &sg : cp.segs)
-        if (sg.kind < kGroupKinds) { gp.first[sg.kind] = sg.first; gp.count[sg.kind] = sg.count; any_group = true; }
-    for (int g = 0; g < kGroupKinds; ++g) {
-        gp.wg_start[g] = wg;
-        wg += cdiv(gp.count[g], kWG / kGroupLanes[g]);
-    }
-    gp.wg_start[kGroupKinds] = wg;
+void launch_class(thetis_solver &S, const Dev<P> &a, const ClassLaunch &cl, const Sched<typename P::R> &sc) {
     const bool vals = !S.unit_vals;
-    if (any_group) {
-        TimedScope ts(S, THETIS_K_SWEEP_GROUP, group_bytes);
-        if (vals) hipLaunchKernelGGL((k_sweep_group<P, true>), dim3(wg), dim3(kWG), 0, S.stream, a, sched, gp);
-        else hipLaunchKernelGGL((k_sweep_group<P, false>), dim3(wg), dim3(kWG), 0, S.stream, a, sched, gp);
+    if (cl.has_cols) {
+        TimedScope ts(S, THETIS_K_SWEEP_COLUMNS, cl.bytes_cols);
+        if (vals) hipLaunchKernelGGL((k_sweep<P, true>), dim3(cl.cols.nwg), dim3(kWG), 0, S.stream, a, sc, cl.cols);
+        else hipLaunchKernelGGL((k_sweep<P, false>), dim3(cl.cols.nwg), dim3(kWG), 0, S.stream, a, sc, cl.cols);
     }
-    for (size_t q = 0; q < cp.segs.size(); ++q) {
-        const Segment &sg = cp.segs[q];
-        if (sg.kind == SEG_HUB) {
-            TimedScope ts(S, THETIS_K_SWEEP_HUB, sb[q]);
-            const int64_t grid = std::min<int64_t>(sg.count, 4096);
-            if (vals) hipLaunchKernelGGL((k_sweep_hub<P, true>), dim3(grid), dim3(kWG), 0, S.stream, a, sched + sg.first, sg.count);
-            else hipLaunchKernelGGL((k_sweep_hub<P, false>), dim3(grid), dim3(kWG), 0, S.stream, a, sched + sg.first, sg.count);
-        } else if (sg.kind == SEG_BLOCK) {
-            TimedScope ts(S, THETIS_K_SWEEP_BLOCK, sb[q]);
-            int lpc = 1;
-            while (lpc * 2 * S.k <= 64) lpc *= 2;
-            const int64_t grid = cdiv(sg.count, kWG / 64);
-            if (vals) hipLaunchKernelGGL((k_sweep_block<P, true>), dim3(grid), dim3(kWG), 0, S.stream, a, sched + sg.first, sg.count, lpc);
-            else hipLaunchKernelGGL((k_sweep_block<P, false>), dim3(grid), dim3(kWG), 0, S.stream, a, sched + sg.first, sg.count, lpc);
-        } else if (sg.kind == SEG_SLACK) {
-            TimedScope ts(S, THETIS_K_SWEEP_SLACK, sb[q]);
-            const int32_t *list = S.all_rows_slack ? nullptr : sched + sg.first;
-            hipLaunchKernelGGL((k_sweep_slack<P>), dim3(cdiv(sg.count, kWG)), dim3(kWG), 0, S.stream, a, list, sg.count);
-        }
+    if (cl.block_count) {
+        TimedScope ts(S, THETIS_K_SWEEP_BLOCK, cl.bytes_block);
+        const int64_t grid = cdiv(cl.block_count, kWG / 64);
+        const int32_t *list = sc.ids + cl.block_first;
+        if (vals) hipLaunchKernelGGL((k_sweep_block<P, true>), dim3(grid), dim3(kWG), 0, S.stream, a, list, cl.block_count, S.lpc);
+        else hipLaunchKernelGGL((k_sweep_block<P, false>), dim3(grid), dim3(kWG), 0, S.stream, a, list, cl.block_count, S.lpc);
+    }
+    if (cl.slack_count) {
+        TimedScope ts(S, THETIS_K_SWEEP_SLACK, cl.bytes_slack);
+        const int32_t *list = S.all_rows_slack ? nullptr : sc.ids + cl.slack_first;
+        hipLaunchKernelGGL((k_sweep_slack<P>), dim3(cdiv(cl.slack_count, kWG)), dim3(kWG), 0, S.stream, a, list, cl.slack_count);
     }
 }
 
-// FP64 refresh: row pass (+ new r when write_r), column pass, fold
+// FP64 refresh: row pass (+ new r when write_r), column pass, fold.  The
+// dual bound needs a gather of the dual estimate over every column; it is
+// computed only when asked for (stop test, metric queries).  Without it the
+// column pass covers just c^T x and the prox part of F.
 template <class P>
-thetis_status refresh(thetis_solver &S, bool write_r) {
+thetis_status refresh(thetis_solver &S, bool write_r, bool with_dual) {
     Dev<P> a = make_dev<P>(S);
+    const int64_t gr = cdiv(std::max<int64_t>(S.m, 1), kWG);
+    const LaunchPlan &pl = with_dual ? S.dual : S.colterms;
     {
-        TimedScope ts(S, THETIS_K_REFRESH, S.refresh_bytes);
-        hipLaunchKernelGGL((k_rows<P>), dim3(cdiv(std::max<int64_t>(S.m, 1), kWG)), dim3(kWG), 0, S.stream, a,
-                           (int32_t)write_r, (double *)S.rpart);
-        hipLaunchKernelGGL((k_cols<P>), dim3(cdiv(S.n + S.nblocks + S.m, kWG) > 0 ? cdiv(S.n + S.nblocks + S.m, kWG) : 1),
-                           dim3(kWG), 0, S.stream, a, (double *)S.cpart);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kWG), 0, S.stream, (const double *)S.rpart,
-                           cdiv(std::max<int64_t>(S.m, 1), kWG), (const double *)S.cpart,
-                           cdiv(S.n + S.nblocks + S.m, kWG) > 0 ? cdiv(S.n + S.nblocks + S.m, kWG) : 1,
-                           S.p.beta, (double *)S.metrics);
+        TimedScope ts(S, THETIS_K_REFRESH, with_dual ? S.refresh_bytes : S.refresh_bytes_nodual);
+        hipLaunchKernelGGL((k_rows<P>), dim3(gr), dim3(kWG), 0, S.stream, a, (int32_t)write_r, (int32_t)with_dual,
+                           (double *)S.rpart);
+        const int32_t ident = S.all_rows_slack ? 1 : 0;
+        if (pl.nwg > 0) {
+            if (S.unit_vals) hipLaunchKernelGGL((k_dual<P, false>), dim3(pl.nwg), dim3(kWG), 0, S.stream, a, async_sched<P>(S), pl, ident, (double *)S.cpart);
+            else hipLaunchKernelGGL((k_dual<P, true>), dim3(pl.nwg), dim3(kWG), 0, S.stream, a, async_sched<P>(S), pl, ident, (double *)S.cpart);
+        }
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kWG), 0, S.stream, (const double *)S.rpart, gr,
+                           (const double *)S.cpart, pl.nwg, S.p.beta, (int32_t)with_dual, (double *)S.metrics);
     }
     HIP_TRY(hipGetLastError());
+    S.metrics_fresh = true;
+    S.metrics_dual = with_dual;
     return THETIS_OK;
 }
 
 template <class P>
 thetis_status read_metrics(thetis_solver &S) {
-    if (!S.metrics_fresh) {
-        thetis_status st = refresh<P>(S, false);
+    if (!S.metrics_fresh || !S.metrics_dual) {
+        thetis_status st = refresh<P>(S, false, true);
         if (st) return st;
     }
     HIP_TRY(hipMemcpyAsync(S.mt, S.metrics, sizeof(S.mt), hipMemcpyDeviceToHost, S.stream));
@@ -1068,8 +1259,7 @@ thetis_status read_metrics(thetis_solver &S) {
 template <class P>
 thetis_status run_epochs_impl(thetis_solver &S, int32_t max_epochs, double gap_tol, int32_t *done) {
     Dev<P> a = make_dev<P>(S);
-    const int32_t *sched = (const int32_t *)S.sched;
-    const int32_t *asched = (const int32_t *)S.async_sched;
+    const Sched<typename P::R> dsc = det_sched<P>(S), asc = async_sched<P>(S);
     std::vector<int32_t> order(std::max(S.nclasses, 1));
     S.ev_used = 0;
     for (int q = 0; q < THETIS_K_NKINDS; ++q) { S.ev[q].clear(); S.ev_bytes[q].clear(); }
@@ -1078,18 +1268,15 @@ thetis_status run_epochs_impl(thetis_solver &S, int32_t max_epochs, double gap_t
     for (; e < max_epochs; ++e) {
         if (S.p.schedule == THETIS_SCHED_DET) {
             class_order(S.nclasses, S.p.seed, S.epoch, order.data());
-            for (int32_t q = 0; q < S.nclasses; ++q)
-                launch_plan<P>(S, a, S.classes[order[q]], sched, S.seg_bytes[order[q]]);
+            for (int32_t q = 0; q < S.nclasses; ++q) launch_class<P>(S, a, S.det[order[q]], dsc);
         } else {
-            launch_plan<P>(S, a, S.async_struct, asched, S.async_struct_bytes);
-            launch_plan<P>(S, a, S.async_slack, asched, S.async_slack_bytes);
+            launch_class<P>(S, a, S.async_launch, asc);
         }
         S.epoch++;
         S.metrics_fresh = false;
         if (S.p.refresh_every > 0 && S.epoch % S.p.refresh_every == 0) {
-            st = refresh<P>(S, true);
+            st = refresh<P>(S, true, gap_tol > 0.0);
             if (st) break;
-            S.metrics_fresh = true;
             if (gap_tol > 0.0) {
                 HIP_TRY(hipMemcpyAsync(S.mt, S.metrics, sizeof(S.mt), hipMemcpyDeviceToHost, S.stream));
                 HIP_TRY(hipStreamSynchronize(S.stream));
@@ -1125,9 +1312,7 @@ thetis_status reset_impl(thetis_solver &S) {
     S.epoch = 0;
     S.have_round = false;
     HIP_TRY(hipGetLastError());
-    thetis_status st = refresh<P>(S, true);
-    S.metrics_fresh = true;
-    return st;
+    return refresh<P>(S, true, false);
 }
 
 template <class P>
@@ -1137,8 +1322,7 @@ thetis_status set_y_impl(thetis_solver &S, const double *y) {
     const int64_t N = std::max<int64_t>(std::max(S.n, S.m), 1);
     hipLaunchKernelGGL((k_load_y<P>), dim3(cdiv(N, kWG)), dim3(kWG), 0, S.stream, a, (const double *)S.ystage);
     HIP_TRY(hipGetLastError());
-    thetis_status st = refresh<P>(S, true);
-    S.metrics_fresh = true;
+    thetis_status st = refresh<P>(S, true, false);
     S.have_round = false;
     if (st) return st;
     HIP_TRY(hipStreamSynchronize(S.stream));
@@ -1175,21 +1359,21 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
             return fail(THETIS_EINVAL, "MIS rounding needs rows x_u + x_v <= 1");
         const int32_t op = rule == THETIS_ROUND_VC_THRESH ? 0 : 1;
         hipLaunchKernelGGL((k_edge_extreme<P>), dim3(gm), dim3(kWG), 0, S.stream, a, op, part);
-        hipLaunchKernelGGL(k_edge_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, gm, op, thr);
+        hipLaunchKernelGGL(k_edge_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gm, op, thr);
         hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, 0, best, part);
-        hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, gn, 1.0, 0, cb);
+        hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gn, 1.0, 0, cb);
         HIP_TRY(hipMemcpyAsync(auxv, thr, 8, hipMemcpyDeviceToHost, S.stream));
     } else if (rule == THETIS_ROUND_MIS_RAND) {
         if (!S.edge_shape_pack) return fail(THETIS_EINVAL, "MIS rounding needs rows x_u + x_v <= 1");
         if (reps < 1) return fail(THETIS_EINVAL, "reps must be >= 1");
         hipLaunchKernelGGL((k_edge_extreme<P>), dim3(gm), dim3(kWG), 0, S.stream, a, 2, part);
-        hipLaunchKernelGGL(k_edge_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, gm, 2, thr);
+        hipLaunchKernelGGL(k_edge_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gm, 2, thr);
         for (int32_t rep = 0; rep < reps; ++rep) {
             HIP_TRY(hipMemsetAsync(drop, 0, 4 * S.n, S.stream));
             hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, rep, sol, part);
             hipLaunchKernelGGL((k_conflicts<P>), dim3(gm), dim3(kWG), 0, S.stream, a, (const int32_t *)sol, drop);
             hipLaunchKernelGGL((k_apply_drop<P>), dim3(gn), dim3(kWG), 0, S.stream, a, sol, (const int32_t *)drop, part);
-            hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, gn, 1.0, rep, cb);
+            hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gn, 1.0, rep, cb);
             hipLaunchKernelGGL(k_copy_if, dim3(gn), dim3(kWG), 0, S.stream, (const double *)cb, (const int32_t *)sol, best, S.n);
         }
         HIP_TRY(hipMemcpyAsync(auxv, thr, 8, hipMemcpyDeviceToHost, S.stream));
@@ -1212,7 +1396,7 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
             hipLaunchKernelGGL((k_ckr_label<P>), dim3(gb), dim3(kWG), 0, S.stream, a, rads[rep],
                                (const int32_t *)S.ckr_order + 64 * (size_t)rep, sol);
             hipLaunchKernelGGL((k_ckr_cost<P>), dim3(gm), dim3(kWG), 0, S.stream, a, (const int32_t *)sol, part);
-            hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, gm, 0.5, rep, cb);
+            hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gm, 0.5, rep, cb);
             hipLaunchKernelGGL(k_copy_if, dim3(gb), dim3(kWG), 0, S.stream, (const double *)cb, (const int32_t *)sol, best, S.nblocks);
         }
         auxv[0] = -1.0;   // radius of the winning repetition, filled below
@@ -1260,7 +1444,7 @@ thetis_status check_impl(thetis_solver &S, int32_t rule, const int32_t *sol_host
         hipLaunchKernelGGL((k_check_rows<P>), dim3(g), dim3(kWG), 0, S.stream, a, sol, part);
     }
     double *cb = (double *)S.chkbuf;
-    hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(64), 0, S.stream, (const double *)part, g, 1.0, 0, cb);
+    hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, g, 1.0, 0, cb);
     HIP_TRY(hipGetLastError());
     double h[4];
     HIP_TRY(hipMemcpyAsync(h, cb, 32, hipMemcpyDeviceToHost, S.stream));
@@ -1379,14 +1563,33 @@ double segment_bytes(const thetis_solver &S, const Inst &in, const std::vector<i
     return b;
 }
 
+ClassLaunch make_class_launch(const thetis_solver &S, const Inst &in, const std::vector<int32_t> &sched,
+                              const std::vector<Segment> &segs) {
+    ClassLaunch cl;
+    std::vector<Segment> cols;
+    for (const Segment &sg : segs) {
+        const double b = segment_bytes(S, in, sched, sg);
+        if (sg.kind == SEG_BLOCK) { cl.block_first = sg.first; cl.block_count = sg.count; cl.bytes_block = b; }
+        else if (sg.kind == SEG_SLACK) { cl.slack_first = sg.first; cl.slack_count = sg.count; cl.bytes_slack = b; }
+        else { cols.push_back(sg); cl.bytes_cols += b; }
+    }
+    if (!cols.empty()) {
+        cl.has_cols = true;
+        cl.cols = make_plan(cols, false, 0);
+    }
+    return cl;
+}
+
 // one refresh: row pass (row pointers, indices, x gathered, s, b, sense, r
-// and the dual estimate written) and column pass (column pointers, indices,
-// dual estimate gathered, c, x, s, sense)
-double refresh_traffic(const thetis_solver &S) {
+// written, and the dual estimate written when the bound is wanted) and
+// column pass (c and x; with the bound also the packed pointers, indices,
+// dual estimate gathered, and s and sense of the slacks)
+double refresh_traffic(const thetis_solver &S, bool with_dual) {
     const double R = (double)prec_bytes(S.p.precision);
     const double V = S.unit_vals ? 0.0 : R;
-    const double rows = 4.0 * (S.m + 1) + S.nnz * (4 + R + V) + S.m * (R + 8 + 1 + 2 * R);
-    const double cols = 4.0 * (S.n + 1) + S.nnz * (4 + R + V) + S.n * (8 + R) + S.m * (1 + 2 * R);
+    const double rows = 4.0 * (S.m + 1) + S.nnz * (4 + R + V) + S.m * (R + 8 + 1 + R + (with_dual ? R : 0));
+    double cols = S.n * (8 + R);
+    if (with_dual) cols += 4.0 * (S.n + 1) + S.nnz * (4 + R + V) + S.m * (1 + 2 * R);
     return rows + cols;
 }
 
@@ -1445,17 +1648,20 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     S.nclasses = in.nclasses; S.nunits = in.nunits;
     S.unit_vals = in.unit_vals; S.uniform_ub = in.uniform_ub; S.ub_value = in.ub_value;
     S.all_rows_slack = in.all_rows_slack;
-    S.classes = in.classes; S.async_struct = in.async_struct; S.async_slack = in.async_slack;
+    while (S.lpc * 2 * std::max(S.k, 1) <= 64) S.lpc *= 2;
     S.edge_shape_cover = edge_shape(in, 1);
     S.edge_shape_pack = edge_shape(in, -1);
-    S.col_deg.resize(in.n);
-    for (int64_t j = 0; j < in.n; ++j) S.col_deg[j] = in.col_ptr[j + 1] - in.col_ptr[j];
-    S.seg_bytes.resize(in.classes.size());
-    for (size_t c = 0; c < in.classes.size(); ++c)
-        for (const Segment &sg : in.classes[c].segs) S.seg_bytes[c].push_back(segment_bytes(S, in, in.sched, sg));
-    for (const Segment &sg : in.async_struct.segs) S.async_struct_bytes.push_back(segment_bytes(S, in, in.async_sched, sg));
-    for (const Segment &sg : in.async_slack.segs) S.async_slack_bytes.push_back(segment_bytes(S, in, in.async_sched, sg));
-    S.refresh_bytes = refresh_traffic(S);
+    for (const ClassPlan &cp : in.classes) S.det.push_back(make_class_launch(S, in, in.sched, cp.segs));
+    {
+        std::vector<Segment> all = in.async_struct.segs;
+        all.insert(all.end(), in.async_slack.segs.begin(), in.async_slack.segs.end());
+        S.async_launch = make_class_launch(S, in, in.async_sched, all);
+    }
+    S.updates_per_epoch = 0;
+    for (const ClassPlan &cp : in.classes)
+        for (const Segment &sg : cp.segs) S.updates_per_epoch += sg.kind == SEG_BLOCK ? sg.count * in.k : sg.count;
+    S.refresh_bytes = refresh_traffic(S, true);
+    S.refresh_bytes_nodual = refresh_traffic(S, false);
     S.stream = (hipStream_t)stream;
     size_t need = 0;
     carve(S, in, nullptr, &need);
@@ -1483,10 +1689,16 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     UP(upload(S, S.c, in.c));
     UP(upload(S, S.sched, in.sched));
     UP(upload(S, S.async_sched, in.async_sched));
+    UP(upload(S, S.pk_det_ptr, in.pk_det.ptr));
+    UP(upload(S, S.pk_det_row, in.pk_det.row));
+    UP(upload(S, S.pk_async_ptr, in.pk_async.ptr));
+    UP(upload(S, S.pk_async_row, in.pk_async.row));
     if (!in.unit_vals) {
         UP(upload_real(S, S.cval, in.cval));
         UP(upload_real(S, S.csr_val, in.val));
         UP(upload_real(S, S.norm2, norm2));
+        UP(upload_real(S, S.pk_det_val, in.pk_det.val));
+        UP(upload_real(S, S.pk_async_val, in.pk_async.val));
     }
     if (!in.uniform_ub) UP(upload_real(S, S.ub, in.u));
     if (in.nblocks) {
@@ -1649,19 +1861,14 @@ extern "C" thetis_status thetis_epoch_traffic(const thetis_solver *s, double *sw
     clear_error();
     if (!s) return fail(THETIS_EINVAL, "solver is NULL");
     double sw = 0.0;
-    for (const auto &v : s->seg_bytes)
-        for (double b : v) sw += b;
     if (s->p.schedule == THETIS_SCHED_ASYNC) {
-        sw = 0.0;
-        for (double b : s->async_struct_bytes) sw += b;
-        for (double b : s->async_slack_bytes) sw += b;
+        sw = s->async_launch.bytes_cols + s->async_launch.bytes_block + s->async_launch.bytes_slack;
+    } else {
+        for (const ClassLaunch &cl : s->det) sw += cl.bytes_cols + cl.bytes_block + cl.bytes_slack;
     }
-    int64_t nupd = 0;
-    for (const ClassPlan &cp : s->classes)
-        for (const Segment &sg : cp.segs) nupd += sg.kind == SEG_BLOCK ? sg.count * s->k : sg.count;
     if (sweep_bytes) *sweep_bytes = sw;
     if (refresh_bytes) *refresh_bytes = s->refresh_bytes;
-    if (updates) *updates = nupd;
+    if (updates) *updates = s->updates_per_epoch;
     return THETIS_OK;
 }
 

@@ -41,6 +41,15 @@ struct ClassPlan {
     std::vector<Segment> segs;   // at most one segment per kind
 };
 
+// Column entries packed in schedule order: entry q of a schedule (a plain
+// column of a hub or lane-group segment) owns row[ptr[q] .. ptr[q+1]);
+// block and slack entries own empty ranges.  A class's columns are thus
+// contiguous in memory and a lane group reads its indices coalesced.
+struct Packed {
+    std::vector<int32_t> ptr, row;
+    std::vector<double> val;   // empty when every entry is 1
+};
+
 // Host copy of an instance plus everything derived from it once.
 struct Inst {
     int64_t m = 0, n = 0, nnz = 0;
@@ -73,6 +82,7 @@ struct Inst {
     // ASYNC schedule: every structural unit (one "class"), then the slacks
     std::vector<int32_t> async_sched;
     ClassPlan async_struct, async_slack;
+    Packed pk_det, pk_async;
     bool planned = false;
     bool has_solver = false;
     int64_t max_col_degree = 0;

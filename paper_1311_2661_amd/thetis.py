@@ -231,10 +231,9 @@ def thetis_set_timing(s, enable: bool):
     _check(lib().thetis_set_timing(s, int(enable)))
 
 
-K_SWEEP_GROUP, K_SWEEP_HUB, K_SWEEP_BLOCK, K_SWEEP_SLACK, K_REFRESH = 0, 1, 2, 3, 4
-KERNEL_NAMES = {K_SWEEP_GROUP: "k_sweep_group", K_SWEEP_HUB: "k_sweep_hub",
-                K_SWEEP_BLOCK: "k_sweep_block", K_SWEEP_SLACK: "k_sweep_slack",
-                K_REFRESH: "refresh (k_rows+k_cols+k_finalize)"}
+K_SWEEP_COLUMNS, K_SWEEP_BLOCK, K_SWEEP_SLACK, K_REFRESH = 0, 1, 2, 3
+KERNEL_NAMES = {K_SWEEP_COLUMNS: "k_sweep", K_SWEEP_BLOCK: "k_sweep_block",
+                K_SWEEP_SLACK: "k_sweep_slack", K_REFRESH: "refresh (k_rows+k_dual+k_finalize)"}
 
 
 def thetis_get_timing(s, kind: int):
