@@ -242,6 +242,45 @@ thetis_status thetis_epoch_traffic(const thetis_solver *s, double *sweep_bytes,
 
 thetis_status thetis_solver_destroy(thetis_solver *s);
 
+/* ----------------------------------------------------------------- batches */
+
+/* Groups `count` solvers (DET schedule, same precision, same kind of matrix
+ * values -- all ones or not -- created on the current device) so that
+ * thetis_batch_run advances all of them in one sequence of launches per
+ * epoch: the class of step q of every instance (its own Philox class order)
+ * in one launch, instance by instance refresh and stop.  Each solver
+ * computes exactly what thetis_run_epochs would compute for it alone (same
+ * classes, same order, same kernels): results are bit-identical.  The batch
+ * borrows the solvers (they must outlive it and must not be run alone while
+ * a batch call is in progress).  stream: hipStream_t for the batch's
+ * launches, or NULL.  Errors: THETIS_EINVAL (mixed precision or value kind,
+ * ASYNC schedule, count < 1), THETIS_ENOMEM, THETIS_EDEVICE. */
+thetis_status thetis_batch_create(int32_t count, thetis_solver *const *solvers, void *stream,
+                                  thetis_batch **out);
+
+/* Runs every active instance for up to max_epochs more epochs; an instance
+ * retires once its certified gap is <= gap_tol at one of its refresh epochs
+ * (gap_tol <= 0: never) or after max_epochs.  epochs_done_host (NULL or
+ * `count` entries) receives the epochs each instance ran.  One epoch of
+ * launches is captured as a HIP graph and replayed. */
+thetis_status thetis_batch_run(thetis_batch *b, int32_t max_epochs, double gap_tol,
+                               int32_t *epochs_done_host);
+
+/* Chooses the launch configuration by timing real epochs of the batch
+ * (epochs_per_candidate each, counted as epochs of the solve): lanes per
+ * column widened 1x or 2x beyond the degree bound, and 1, 2 or 4 times the
+ * resident workgroup count for the work-queue kernels.  Every candidate
+ * computes bit-identical results.  The choice is cached per batch shape
+ * (instance count, entries, largest degree) for the life of the process;
+ * choice_host (NULL or 2 ints) receives (widen, grid multiplier). */
+thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_per_candidate, int32_t *choice_host);
+
+/* Sets the launch configuration directly (widen in {1,2,4}, grid multiplier
+ * in {1,2,4,8}). */
+thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult);
+
+thetis_status thetis_batch_destroy(thetis_batch *b);
+
 /* Message describing the calling thread's last failed call ("" if none). */
 const char *thetis_last_error(void);
 

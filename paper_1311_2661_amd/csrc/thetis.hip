@@ -23,11 +23,13 @@
 //                  the residual norms, row violation, penalty value F and the
 //                  dual bound Phi, reduced in a fixed order (deterministic)
 //   k_round_* / k_check_*          pre-rounding pass, roundings, check
+#include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -45,8 +47,32 @@ using namespace thetis;
 namespace {
 
 // ---------------------------------------------------------------- precision
-struct PF32 { using X = float;  using R = float;  static constexpr int32_t id = THETIS_PREC_FP32; };
-struct PF64 { using X = double; using R = double; static constexpr int32_t id = THETIS_PREC_FP64; };
+// X: storage of the structural x; R: storage of slacks and the residual and
+// the type the updates are computed in
+struct PF32 { using X = float;  using R = float; };
+struct PF64 { using X = double; using R = double; };
+struct PB16 { using X = __hip_bfloat16; using R = float; };
+
+__device__ __forceinline__ float xval(float v) { return v; }
+__device__ __forceinline__ double xval(double v) { return v; }
+__device__ __forceinline__ float xval(__hip_bfloat16 v) { return __bfloat162float(v); }
+// storage encoding (BF16: round to nearest even)
+template <class X, class R> __device__ __forceinline__ X xenc(R v) { return (X)v; }
+template <> __device__ __forceinline__ __hip_bfloat16 xenc<__hip_bfloat16, float>(float v) { return __float2bfloat16(v); }
+template <> __device__ __forceinline__ __hip_bfloat16 xenc<__hip_bfloat16, double>(double v) { return __float2bfloat16((float)v); }
+
+// stores y' into x[j] and returns the value actually stored (the step that
+// reaches the residual is the realised one)
+template <class P>
+__device__ __forceinline__ typename P::R store_x(typename P::X *p, typename P::R v) {
+    const typename P::X e = xenc<typename P::X, typename P::R>(v);
+    *p = e;
+    return (typename P::R)xval(e);
+}
+template <class P>
+__device__ __forceinline__ typename P::R stored_value(typename P::R v) {
+    return (typename P::R)xval(xenc<typename P::X, typename P::R>(v));
+}
 
 // ---------------------------------------------------------------- device arguments
 template <class P>
@@ -151,16 +177,21 @@ struct LaunchPlan {
     int64_t wg_start[kGridKinds + 1];   // by grid position
     int64_t first[kGridKinds];          // offset of the segment in its schedule
     int64_t count[kGridKinds];          // units of the segment
+    int32_t lanes[kGridKinds];          // lanes per column of the lane-group ranges
     int64_t hub_wg;                     // hub workgroups, a multiple of 8
     int64_t nwg;
 };
 
-__device__ __forceinline__ int locate(const LaunchPlan &pl, int64_t b, int64_t *local) {
-    const int64_t L = b < pl.hub_wg ? b : pl.hub_wg + xcd_remap(b - pl.hub_wg, pl.nwg - pl.hub_wg);
+// logical workgroup L of a plan -> grid position and workgroup inside it
+__device__ __forceinline__ int locate_logical(const LaunchPlan &pl, int64_t L, int64_t *local) {
     int p = 0;
     while (p < kGridKinds - 1 && L >= pl.wg_start[p + 1]) ++p;
     *local = L - pl.wg_start[p];
     return p;
+}
+// hardware workgroup b -> logical workgroup (hubs first, the rest XCD-remapped)
+__device__ __forceinline__ int64_t logical_wg(const LaunchPlan &pl, int64_t b) {
+    return b < pl.hub_wg ? b : pl.hub_wg + xcd_remap(b - pl.hub_wg, pl.nwg - pl.hub_wg);
 }
 
 template <class P>
@@ -200,11 +231,11 @@ __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typenam
         acc += VALS ? v * rv : rv;
     }
     acc = group_sum<G>(acc);
-    const R y = (R)a.x[j];
+    const R y = (R)xval(a.x[j]);
     const R g = gradient(a, j, y, acc);
-    const R yn = coord_step(y, g, curvature<P, VALS>(a, j, e1 - e0), a.gamma, col_bound(a, j));
+    const R yn = stored_value<P>(coord_step(y, g, curvature<P, VALS>(a, j, e1 - e0), a.gamma, col_bound(a, j)));
     const R d = yn - y;
-    if (lane == 0) a.x[j] = yn;
+    if (lane == 0) store_x<P>(a.x + j, yn);
     if (d != R(0)) {
         bool first_e = true;
         for (int32_t e = e0 + lane; e < e1; e += G) {
@@ -263,11 +294,12 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
     R tot = red[0];
 #pragma unroll
     for (int w = 1; w < kWG / 64; ++w) tot += red[w];
-    const R y = (R)a.x[j];
+    __syncthreads();   // red is reused by the next column of a batched loop
+    const R y = (R)xval(a.x[j]);
     const R g = gradient(a, j, y, tot);
-    const R yn = coord_step(y, g, curvature<P, VALS>(a, j, e1 - e0), a.gamma, col_bound(a, j));
+    const R yn = stored_value<P>(coord_step(y, g, curvature<P, VALS>(a, j, e1 - e0), a.gamma, col_bound(a, j)));
     const R d = yn - y;
-    if (tid == 0) a.x[j] = yn;
+    if (tid == 0) store_x<P>(a.x + j, yn);
     if (d != R(0)) {
         for (int32_t e = e0 + tid; e < e1; e += kWG) {
             const int32_t o = e - e0;
@@ -305,7 +337,7 @@ __device__ __forceinline__ void sweep_block(const Dev<P> &a, int32_t blk, int lp
     const R L = a.global_lmax ? a.Lmax : a.LB[blk];
     R y = R(0), v = R(0);
     if (own) {
-        y = (R)a.x[j];
+        y = (R)xval(a.x[j]);
         const R g = gradient(a, j, y, acc);
         v = L > R(0) ? y - a.gamma * g / L : y;
     }
@@ -322,8 +354,9 @@ __device__ __forceinline__ void sweep_block(const Dev<P> &a, int32_t blk, int lp
     const R theta = wave_max(cand);
     R w = v - theta;
     if (w < R(0)) w = R(0);
+    w = stored_value<P>(w);
     const R d = own ? w - y : R(0);
-    if (own && sub == 0) a.x[j] = w;
+    if (own && sub == 0) store_x<P>(a.x + j, w);
     if (own && d != R(0)) {
         for (int32_t e = e0 + sub; e < e1; e += lpc) {
             R *p = a.r + a.row_idx[e];
@@ -353,6 +386,29 @@ __device__ __forceinline__ void sweep_slack(const Dev<P> &a, int64_t i) {
 }
 
 // One class (DET) or one whole epoch part (ASYNC) in a single launch.
+// logical workgroup L of a column plan.  A lane-group range may run wider
+// groups than its degree bound (the tuner's choice): the extra lanes hold
+// exact zeros, so the butterfly sums -- and every result -- are unchanged.
+template <class P, bool VALS>
+__device__ __forceinline__ void sweep_item(const Dev<P> &a, const Sched<typename P::R> &sc, const LaunchPlan &pl,
+                                           int64_t L, typename P::R *st_r, int32_t *st_row, typename P::R *red) {
+    int64_t local;
+    const int p = locate_logical(pl, L, &local);
+    const int64_t first = pl.first[p], count = pl.count[p];
+    if (grid_kind(p) == SEG_HUB) {
+        if (local < count) sweep_hub<P, VALS>(a, sc, first + local, st_r, st_row, red);
+        return;
+    }
+    switch (pl.lanes[p]) {
+        case 4: sweep_group<P, VALS, 4>(a, sc, first, count, local); break;
+        case 8: sweep_group<P, VALS, 8>(a, sc, first, count, local); break;
+        case 16: sweep_group<P, VALS, 16>(a, sc, first, count, local); break;
+        case 32: sweep_group<P, VALS, 32>(a, sc, first, count, local); break;
+        case 64: sweep_group<P, VALS, 64>(a, sc, first, count, local); break;
+        default: break;
+    }
+}
+
 // The plain columns of one class (DET) or of a whole epoch (ASYNC) in one
 // launch: hub workgroups first, then the lane-group ranges.
 template <class P, bool VALS>
@@ -361,20 +417,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(Dev<P> a, Sched<typename P::R> sc
     __shared__ R st_r[HubTile<P>::n];
     __shared__ int32_t st_row[HubTile<P>::n];
     __shared__ R red[kWG / 64];
-    int64_t local;
-    const int p = locate(pl, blockIdx.x, &local);
-    const int64_t first = pl.first[p], count = pl.count[p];
-    switch (grid_kind(p)) {
-        case SEG_HUB:
-            if (local < count) sweep_hub<P, VALS>(a, sc, first + local, st_r, st_row, red);
-            break;
-        case SEG_G4: sweep_group<P, VALS, 4>(a, sc, first, count, local); break;
-        case SEG_G8: sweep_group<P, VALS, 8>(a, sc, first, count, local); break;
-        case SEG_G16: sweep_group<P, VALS, 16>(a, sc, first, count, local); break;
-        case SEG_G32: sweep_group<P, VALS, 32>(a, sc, first, count, local); break;
-        case SEG_G64: sweep_group<P, VALS, 64>(a, sc, first, count, local); break;
-        default: break;
-    }
+    sweep_item<P, VALS>(a, sc, pl, logical_wg(pl, blockIdx.x), st_r, st_row, red);
 }
 
 // the simplex blocks of one class: one wavefront per block
@@ -425,6 +468,7 @@ __device__ void block_reduce(const double (&v)[NS], const int (&op)[NS], double 
         for (int ww = 1; ww < kWG / 64; ++ww) t = op[q] ? fmax(t, sh[ww][q]) : t + sh[ww][q];
         out[q] = t;
     }
+    __syncthreads();
 }
 
 // min over [0,U] of red*y + rho/2 (y - yb)^2
@@ -444,15 +488,16 @@ __device__ __forceinline__ double box_min(double red, double U, double rho, doub
 // unbounded slack columns keep a non-negative reduced cost when rho = 0),
 // rounded once to storage precision and used for every term of Phi.
 template <class P>
-__global__ __launch_bounds__(kWG) void k_rows(Dev<P> a, int32_t write_r, int32_t with_dual, double *part) {
+__device__ __forceinline__ void rows_item(const Dev<P> &a, int64_t wg, int32_t write_r, int32_t with_dual,
+                                          double *part) {
     using R = typename P::R;
-    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const int64_t i = wg * kWG + threadIdx.x;
     double v[kRowSlots] = {0, 0, 0, 0, 0, 0};
     const int op[kRowSlots] = {0, 1, 1, 0, 0, 0};
     if (i < a.m) {
         double ax = 0.0;
         for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
-            ax += (a.csr_val ? (double)a.csr_val[e] : 1.0) * (double)a.x[a.csr_col[e]];
+            ax += (a.csr_val ? (double)a.csr_val[e] : 1.0) * (double)xval(a.x[a.csr_col[e]]);
         const int8_t sn = a.sense[i];
         double acc = ax;
         if (sn > 0) acc -= (double)a.s[i];
@@ -476,7 +521,12 @@ __global__ __launch_bounds__(kWG) void k_rows(Dev<P> a, int32_t write_r, int32_t
         v[4] = (ud - ub) * (ud - ub);
         v[5] = -ub * w;
     }
-    block_reduce<kRowSlots>(v, op, part + (int64_t)blockIdx.x * kRowSlots);
+    block_reduce<kRowSlots>(v, op, part + wg * kRowSlots);
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_rows(Dev<P> a, int32_t write_r, int32_t with_dual, double *part) {
+    rows_item<P>(a, blockIdx.x, write_r, with_dual, part);
 }
 
 // Workgroup sum of one double, returned to every thread (fixed order).
@@ -502,11 +552,10 @@ __device__ __forceinline__ double col_ubound(const Dev<P> &a, int64_t j) {
 // function Phi), with the reduced cost gathered lane-group parallel like the
 // sweep.  Every workgroup writes kColSlots partials.
 template <class P, bool VALS>
-__global__ __launch_bounds__(kWG) void k_dual(Dev<P> a, Sched<typename P::R> sc, LaunchPlan pl,
-                                              int32_t slack_identity, double *part) {
-    __shared__ double sh[kWG / 64];
+__device__ __forceinline__ void dual_item(const Dev<P> &a, const Sched<typename P::R> &sc, const LaunchPlan &pl,
+                                          int64_t L, int32_t slack_identity, double *part, double *sh) {
     int64_t local;
-    const int p = locate(pl, blockIdx.x, &local);
+    const int p = locate_logical(pl, L, &local);
     const int64_t first = pl.first[p], count = pl.count[p];
     const int kind = grid_kind(p);
     const double rho = (double)a.rho;
@@ -526,7 +575,7 @@ __global__ __launch_bounds__(kWG) void k_dual(Dev<P> a, Sched<typename P::R> sc,
         if (valid && threadIdx.x == 0)
             v[0] = box_min(a.c[j] - acc, col_ubound(a, j), rho, a.ybar ? (double)a.ybar[j] : 0.0);
     } else if (kind < kGroupKinds) {
-        const int G = 4 << kind;
+        const int G = pl.lanes[p];
         const int lane = threadIdx.x & (G - 1);
         const int64_t u = local * (kWG / G) + threadIdx.x / G;
         const bool valid = u < count;
@@ -595,7 +644,7 @@ __global__ __launch_bounds__(kWG) void k_dual(Dev<P> a, Sched<typename P::R> sc,
         // simplex blocks' contribution to Phi (their first column's thread)
         const int64_t j = local * kWG + threadIdx.x;
         if (j < a.n) {
-            const double xj = (double)a.x[j];
+            const double xj = (double)xval(a.x[j]);
             v[1] = a.c[j] * xj;
             const double yb = a.ybar ? (double)a.ybar[j] : 0.0;
             if (a.prox_on) v[2] = 0.5 * rho * (xj - yb) * (xj - yb);
@@ -616,7 +665,14 @@ __global__ __launch_bounds__(kWG) void k_dual(Dev<P> a, Sched<typename P::R> sc,
             }
         }
     }
-    block_reduce<kColSlots>(v, op, part + (int64_t)blockIdx.x * kColSlots);
+    block_reduce<kColSlots>(v, op, part + L * kColSlots);
+}
+
+template <class P, bool VALS>
+__global__ __launch_bounds__(kWG) void k_dual(Dev<P> a, Sched<typename P::R> sc, LaunchPlan pl,
+                                              int32_t slack_identity, double *part) {
+    __shared__ double sh[kWG / 64];
+    dual_item<P, VALS>(a, sc, pl, logical_wg(pl, blockIdx.x), slack_identity, part, sh);
 }
 
 // metrics slots
@@ -652,10 +708,11 @@ __device__ void fold_records(const double *part, int64_t nb, const int (&op)[NS]
     }
 #pragma unroll
     for (int q = 0; q < NS; ++q) out[q] = sh[0][q];
+    __syncthreads();
 }
 
-__global__ __launch_bounds__(kWG) void k_finalize(const double *rp, int64_t nr, const double *cp,
-                                                  int64_t nc, double beta, int32_t with_dual, double *mt) {
+__device__ __forceinline__ void finalize_item(const double *rp, int64_t nr, const double *cp, int64_t nc,
+                                              double beta, int32_t with_dual, double *mt) {
     const int rop[kRowSlots] = {0, 1, 1, 0, 0, 0};
     const int cop[kColSlots] = {0, 0, 0};
     double rs[kRowSlots], cs[kColSlots];
@@ -676,6 +733,11 @@ __global__ __launch_bounds__(kWG) void k_finalize(const double *rp, int64_t nr, 
     }
 }
 
+__global__ __launch_bounds__(kWG) void k_finalize(const double *rp, int64_t nr, const double *cp,
+                                                  int64_t nc, double beta, int32_t with_dual, double *mt) {
+    finalize_item(rp, nr, cp, nc, beta, with_dual, mt);
+}
+
 // ---------------------------------------------------------------- rounding
 // edge pass for the two-entry rows: op 0 min (x_u+x_v)/2, 1 max (x_u+x_v)/2,
 // 2 max (x_u+x_v-1)
@@ -685,7 +747,7 @@ __global__ __launch_bounds__(kWG) void k_edge_extreme(Dev<P> a, int32_t op, doub
     double v = op == 0 ? INFINITY : -INFINITY;
     if (i < a.m) {
         const int32_t e = a.row_ptr[i];
-        const double xu = (double)a.x[a.csr_col[e]], xv = (double)a.x[a.csr_col[e + 1]];
+        const double xu = (double)xval(a.x[a.csr_col[e]]), xv = (double)xval(a.x[a.csr_col[e + 1]]);
         v = op == 2 ? (xu + xv) - 1.0 : (xu + xv) * 0.5;
     }
     if (op == 0) v = -v;
@@ -733,7 +795,7 @@ __global__ __launch_bounds__(kWG) void k_pick(Dev<P> a, int32_t rule, const doub
     const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
     double v = 0.0;
     if (j < a.n) {
-        const double xj = (double)a.x[j];
+        const double xj = (double)xval(a.x[j]);
         int32_t keep;
         if (rule == THETIS_ROUND_VC_THRESH) keep = xj >= *thr;
         else if (rule == THETIS_ROUND_MIS_THRESH) keep = xj > *thr;
@@ -797,7 +859,7 @@ __global__ __launch_bounds__(kWG) void k_ckr_label(Dev<P> a, double rad, const i
     int32_t l = order[k - 1];
     for (int q = 0; q < k - 1; ++q) {
         const int32_t i = order[q];
-        if ((double)a.x[j0 + i] >= 1.0 - rad) { l = i; break; }
+        if ((double)xval(a.x[j0 + i]) >= 1.0 - rad) { l = i; break; }
     }
     lab[t] = l;
 }
@@ -910,7 +972,7 @@ __global__ __launch_bounds__(kWG) void k_set_start(Dev<P> a) {
     if (t < a.n) {
         const int32_t bl = a.col_block ? a.col_block[t] : -1;
         const bool one = bl >= 0 && a.fixed[bl] >= 0 && t == (int64_t)a.bfirst[bl] + a.fixed[bl];
-        a.x[t] = one ? 1 : 0;
+        a.x[t] = xenc<typename P::X, float>(one ? 1.0f : 0.0f);
     }
     if (t < a.m) a.s[t] = 0;
 }
@@ -924,7 +986,7 @@ __global__ __launch_bounds__(kWG) void k_load_y(Dev<P> a, const double *y) {
         const double U = a.ub ? (double)a.ub[t] : (double)a.ub_value;
         if (v < 0.0) v = 0.0;
         if (v > U) v = U;
-        a.x[t] = (typename P::X)v;
+        a.x[t] = xenc<typename P::X, double>(v);
     }
     if (t < a.m) {
         double v = y[a.n + t];
@@ -936,7 +998,7 @@ __global__ __launch_bounds__(kWG) void k_load_y(Dev<P> a, const double *y) {
 template <class P>
 __global__ __launch_bounds__(kWG) void k_store_y(Dev<P> a, double *x, double *s) {
     const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (t < a.n) x[t] = (double)a.x[t];
+    if (t < a.n) x[t] = (double)xval(a.x[t]);
     if (s && t < a.m) s[t] = (double)a.s[t];
 }
 
@@ -951,6 +1013,7 @@ constexpr int32_t kMaxReps = 64;
 struct ClassLaunch {
     bool has_cols = false;
     LaunchPlan cols{};                      // hub + lane-group ranges (k_sweep)
+    std::vector<Segment> col_segs;          // the segments that plan covers
     int64_t block_first = 0, block_count = 0;
     int64_t slack_first = 0, slack_count = 0;
     double bytes_cols = 0, bytes_block = 0, bytes_slack = 0;   // algorithmic, per launch
@@ -968,7 +1031,7 @@ struct thetis_solver {
     LaunchPlan colterms{};                     // column pass without it (c^T x, prox part of F)
     bool metrics_dual = false;                 // the fresh metrics include the dual bound
     bool edge_shape_cover = false, edge_shape_pack = false;
-    int64_t nunits = 0, updates_per_epoch = 0;
+    int64_t nunits = 0, updates_per_epoch = 0, max_degree = 0;
     int32_t lpc = 1;                           // lanes per column of a simplex block
     // parameters
     thetis_params p{};
@@ -1018,6 +1081,7 @@ struct Carver {
 };
 
 size_t prec_bytes(int32_t prec) { return prec == THETIS_PREC_FP64 ? 8 : 4; }
+size_t x_bytes(int32_t prec) { return prec == THETIS_PREC_FP64 ? 8 : (prec == THETIS_PREC_BF16X ? 2 : 4); }
 
 int64_t units_per_wg(int kind, bool dual) {
     if (kind == SEG_HUB) return 1;
@@ -1028,8 +1092,12 @@ int64_t units_per_wg(int kind, bool dual) {
 
 // Workgroup ranges of one fused launch over the given segments (at most one
 // segment per kind) plus, for the dual pass, ncolterms per-column threads.
-LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolterms) {
+LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolterms, int widen = 1) {
     LaunchPlan pl{};
+    for (int p = 0; p < kGridKinds; ++p) {
+        const int kind = grid_kind(p);
+        pl.lanes[p] = kind < kGroupKinds ? std::min(64, (4 << kind) * widen) : 0;
+    }
     for (const Segment &sg : segs) {
         const int p = grid_pos(sg.kind);
         pl.first[p] = sg.first;
@@ -1040,7 +1108,8 @@ LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolte
     for (int p = 0; p < kGridKinds; ++p) {
         pl.wg_start[p] = wg;
         const int kind = grid_kind(p);
-        int64_t w = pl.count[p] ? cdiv(pl.count[p], kind == SEG_NKIND ? kWG : units_per_wg(kind, dual)) : 0;
+        const int64_t upw = kind < kGroupKinds ? kWG / pl.lanes[p] : (kind == SEG_NKIND ? kWG : units_per_wg(kind, dual));
+        int64_t w = pl.count[p] ? cdiv(pl.count[p], upw) : 0;
         if (kind == SEG_HUB) { w = cdiv(w, 8) * 8; pl.hub_wg = w; }
         wg += w;
     }
@@ -1053,7 +1122,7 @@ LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolte
 void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     Carver cv;
     cv.base = base;
-    const size_t R = prec_bytes(S.p.precision), X = R;
+    const size_t R = prec_bytes(S.p.precision), X = x_bytes(S.p.precision);
     const int64_t n = in.n, m = in.m, nnz = in.nnz, nb = in.nblocks;
     S.col_ptr = cv.take(4 * (n + 1));
     S.row_idx = cv.take(4 * std::max<int64_t>(nnz, 1));
@@ -1456,7 +1525,7 @@ thetis_status check_impl(thetis_solver &S, int32_t rule, const int32_t *sol_host
 }
 
 #define DISPATCH(S, CALL)                                                       \
-    ((S).p.precision == THETIS_PREC_FP64 ? CALL<PF64> : CALL<PF32>)
+    ((S).p.precision == THETIS_PREC_FP64 ? CALL<PF64> : ((S).p.precision == THETIS_PREC_BF16X ? CALL<PB16> : CALL<PF32>))
 
 bool edge_shape(const Inst &in, int8_t want) {
     if (in.m == 0) return false;
@@ -1531,18 +1600,20 @@ thetis_status upload_real(thetis_solver &S, void *dst, const std::vector<double>
     return S.p.precision == THETIS_PREC_FP64 ? upload_conv<double>(S, dst, src) : upload_conv<float>(S, dst, src);
 }
 
-// Algorithmic bytes of one launch of a segment (R = bytes of a stored
-// real).  Plain column j with d entries: list entry 4, column pointers 8,
-// per entry row index 4 + residual read R + write R (+ value R), x read and
-// write 2R, cost R (+ bound R, + ||A_j||^2 R when not implied).  Simplex
+// Algorithmic bytes of one launch of a segment (R = bytes of a stored real,
+// X = bytes of a stored x).  Plain column j with d entries: list entry 4,
+// packed pointers 8, per entry row index 4 + residual read R + write R
+// (+ value R), x read and write 2X, cost 8 (FP64 c; R when shifted by ubar)
+// (+ bound R, + ||A_j||^2 R when not implied, + prox centre R).  Simplex
 // block: the same per column plus the block's first column and curvature.
 // Slack: s and r read and written (+ row list 4 when not every row has one).
 double segment_bytes(const thetis_solver &S, const Inst &in, const std::vector<int32_t> &sched,
                      const Segment &sg) {
     const double R = (double)prec_bytes(S.p.precision);
+    const double X = (double)x_bytes(S.p.precision);
     const double V = in.unit_vals ? 0.0 : R;
-    const double per_col = 8 + 3 * R + (in.uniform_ub ? 0 : R) + (in.unit_vals ? 0 : R) +
-                           (S.has_ubar ? 0 : 0) + (S.has_ybar ? R : 0);
+    const double per_col = 8 + 2 * X + (S.has_ubar ? R : 8.0) + (in.uniform_ub ? 0 : R) +
+                           (in.unit_vals ? 0 : R) + (S.has_ybar ? R : 0);
     double b = 0.0;
     if (sg.kind == SEG_SLACK) return (double)sg.count * (4 * R + (in.all_rows_slack ? 0.0 : 4.0));
     for (int64_t q = 0; q < sg.count; ++q) {
@@ -1576,6 +1647,7 @@ ClassLaunch make_class_launch(const thetis_solver &S, const Inst &in, const std:
     if (!cols.empty()) {
         cl.has_cols = true;
         cl.cols = make_plan(cols, false, 0);
+        cl.col_segs = cols;
     }
     return cl;
 }
@@ -1601,8 +1673,7 @@ thetis_status check_params(const thetis_params *p) {
     if (!(p->step_scale > 0.0 && p->step_scale <= 1.0)) return fail(THETIS_EINVAL, "step_scale must be in (0, 1]");
     if (p->schedule != THETIS_SCHED_DET && p->schedule != THETIS_SCHED_ASYNC)
         return fail(THETIS_EINVAL, "unknown schedule");
-    if (p->precision == THETIS_PREC_BF16X) return fail(THETIS_EUNSUPPORTED, "BF16 x storage is not built in this version");
-    if (p->precision != THETIS_PREC_FP32 && p->precision != THETIS_PREC_FP64)
+    if (p->precision != THETIS_PREC_FP32 && p->precision != THETIS_PREC_FP64 && p->precision != THETIS_PREC_BF16X)
         return fail(THETIS_EINVAL, "unknown precision");
     if (p->refresh_every < 1) return fail(THETIS_EINVAL, "refresh_every must be >= 1");
     return THETIS_OK;
@@ -1649,6 +1720,7 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     S.unit_vals = in.unit_vals; S.uniform_ub = in.uniform_ub; S.ub_value = in.ub_value;
     S.all_rows_slack = in.all_rows_slack;
     while (S.lpc * 2 * std::max(S.k, 1) <= 64) S.lpc *= 2;
+    S.max_degree = in.max_col_degree;
     S.edge_shape_cover = edge_shape(in, 1);
     S.edge_shape_pack = edge_shape(in, -1);
     for (const ClassPlan &cp : in.classes) S.det.push_back(make_class_launch(S, in, in.sched, cp.segs));
@@ -1878,5 +1950,538 @@ extern "C" thetis_status thetis_solver_destroy(thetis_solver *s) {
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     if (s->own_ws && s->ws) (void)hipFree(s->ws);
     delete s;
+    return THETIS_OK;
+}
+
+// ==================================================================== batches
+//
+// A batch advances many solvers with one sequence of launches per epoch.
+// For step q of an epoch, k_bplan picks every active instance's class of
+// that step (its own Philox class order) and its workgroup count, k_bscan
+// turns the counts into offsets, and k_bsweep walks the resulting
+// (instance, workgroup) items: each XCD takes a contiguous share of the
+// items (so an instance's columns stay in one L2) and its workgroups stride
+// through that share.  Kernel boundaries are the class barriers.  After the
+// last step, k_bepoch advances the epoch counters and marks the instances
+// whose refresh is due; k_brows / k_bdual / k_bfinal refresh them and retire
+// those whose certified gap reached the tolerance.  Every per-column and
+// per-row computation is the solo kernels' own device code with the same
+// logical workgroup numbering, so a batched solve equals the solve alone.
+
+namespace {
+
+template <class P>
+struct BInst {
+    Dev<P> a;
+    Sched<typename P::R> sc, asc;       // DET schedule, all-columns schedule
+    LaunchPlan dual;                    // column pass of the refresh
+    double *rpart, *cpart, *metrics;
+    int64_t epoch, rows_wg;
+    uint64_t seed;
+    double gap_tol, beta;
+    int32_t nclasses, class_base, refresh_every, active, due, with_dual, slack_identity, lpc;
+    int32_t epochs_done, max_epochs, diverged;
+};
+
+struct BClass {
+    LaunchPlan cols;
+    int64_t block_first, block_count, slack_first, slack_count;
+    int64_t wg_cols, wg_block, wg_slack;
+};
+
+// class of step q in `epoch`: the q-th smallest (Philox word, class id)
+__device__ int32_t class_of_step(uint64_t seed, int64_t epoch, int32_t nclasses, int32_t q) {
+    for (int32_t c = 0; c < nclasses; ++c) {
+        const uint64_t kc = philox_word_dev(seed, RNG_CLASS_ORDER, (uint64_t)epoch, (uint64_t)c, 0);
+        int32_t rank = 0;
+        for (int32_t c2 = 0; c2 < nclasses; ++c2) {
+            if (c2 == c) continue;
+            const uint64_t k2 = philox_word_dev(seed, RNG_CLASS_ORDER, (uint64_t)epoch, (uint64_t)c2, 0);
+            rank += (k2 < kc || (k2 == kc && c2 < c)) ? 1 : 0;
+        }
+        if (rank == q) return c;
+    }
+    return -1;
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_bplan(BInst<P> *bi, const BClass *bc, int32_t count, int32_t q,
+                                               int32_t *wg, int32_t *cls) {
+    const int32_t i = blockIdx.x * kWG + threadIdx.x;
+    if (i >= count) return;
+    const BInst<P> &I = bi[i];
+    int32_t w = 0, c = -1;
+    if (I.active && q < I.nclasses) {
+        c = class_of_step(I.seed, I.epoch, I.nclasses, q);
+        if (c >= 0) {
+            const BClass &C = bc[I.class_base + c];
+            w = (int32_t)(C.wg_cols + C.wg_block + C.wg_slack);
+        }
+    }
+    wg[i] = w;
+    cls[i] = c;
+}
+
+// exclusive prefix of `count` workgroup counts in one workgroup; start has
+// count + 1 entries, start[count] = total
+__global__ __launch_bounds__(kWG) void k_bscan(const int32_t *in, int32_t count, int64_t *start) {
+    __shared__ int64_t part[kWG + 1];
+    const int t = threadIdx.x;
+    const int32_t chunk = (count + kWG - 1) / kWG;
+    const int32_t lo = t * chunk, hi = min(count, lo + chunk);
+    int64_t sum = 0;
+    for (int32_t i = lo; i < hi; ++i) sum += in[i];
+    part[t + 1] = sum;
+    __syncthreads();
+    if (t == 0) {
+        part[0] = 0;
+        for (int u = 1; u <= kWG; ++u) part[u] += part[u - 1];
+    }
+    __syncthreads();
+    int64_t run = part[t];
+    for (int32_t i = lo; i < hi; ++i) { start[i] = run; run += in[i]; }
+    if (t == 0) start[count] = part[kWG];
+}
+
+// instance owning item `it`: the last i with start[i] <= it
+__device__ __forceinline__ int32_t owner(const int64_t *start, int32_t count, int64_t it) {
+    int32_t lo = 0, hi = count;           // invariant: start[lo] <= it < start[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (start[mid] <= it) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// this workgroup's share of `total` items: XCD x (= block & 7) takes the
+// x-th contiguous eighth, its workgroups stride through it
+struct Share {
+    int64_t lo, hi, step;
+};
+__device__ __forceinline__ Share xcd_share(int64_t total) {
+    const int64_t xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+    const int64_t chunk = (total + 7) >> 3;
+    Share s;
+    s.lo = xcd * chunk + (blockIdx.x >> 3);
+    s.hi = min(total, (xcd + 1) * chunk);
+    s.step = per;
+    return s;
+}
+
+template <class P, bool VALS>
+__global__ __launch_bounds__(kWG) void k_bsweep(const BInst<P> *bi, const BClass *bc, const int32_t *cls,
+                                                const int64_t *start, int32_t count) {
+    using R = typename P::R;
+    __shared__ R st_r[HubTile<P>::n];
+    __shared__ int32_t st_row[HubTile<P>::n];
+    __shared__ R red[kWG / 64];
+    const Share sh = xcd_share(start[count]);
+    for (int64_t it = sh.lo; it < sh.hi; it += sh.step) {
+        const int32_t i = owner(start, count, it);
+        const BInst<P> &I = bi[i];
+        const BClass &C = bc[I.class_base + cls[i]];
+        const int64_t local = it - start[i];
+        if (local < C.wg_cols) {
+            sweep_item<P, VALS>(I.a, I.sc, C.cols, local, st_r, st_row, red);
+        } else if (local < C.wg_cols + C.wg_block) {
+            const int64_t u = (local - C.wg_cols) * (kWG / 64) + (threadIdx.x >> 6);
+            if (u < C.block_count) sweep_block<P, VALS>(I.a, I.sc.ids[C.block_first + u], I.lpc);
+        } else {
+            const int64_t u = (local - C.wg_cols - C.wg_block) * kWG + threadIdx.x;
+            if (u < C.slack_count) sweep_slack<P>(I.a, I.slack_identity ? u : I.sc.ids[C.slack_first + u]);
+        }
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_bepoch(BInst<P> *bi, int32_t count, int32_t *rows_wg, int32_t *dual_wg,
+                                                int32_t *active_count) {
+    const int32_t i = blockIdx.x * kWG + threadIdx.x;
+    if (i >= count) return;
+    BInst<P> &I = bi[i];
+    int32_t rw = 0, dw = 0;
+    if (I.active) {
+        I.epoch += 1;
+        I.epochs_done += 1;
+        I.due = (I.epoch % I.refresh_every) == 0;
+        if (I.due) { rw = (int32_t)I.rows_wg; dw = (int32_t)I.dual.nwg; }
+        else if (I.epochs_done >= I.max_epochs) I.active = 0;
+        if (I.active) atomicAdd(active_count, 1);
+    } else {
+        I.due = 0;
+    }
+    rows_wg[i] = rw;
+    dual_wg[i] = dw;
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_brows(const BInst<P> *bi, const int64_t *start, int32_t count) {
+    const Share sh = xcd_share(start[count]);
+    for (int64_t it = sh.lo; it < sh.hi; it += sh.step) {
+        const int32_t i = owner(start, count, it);
+        const BInst<P> &I = bi[i];
+        rows_item<P>(I.a, it - start[i], 1, I.with_dual, I.rpart);
+    }
+}
+
+template <class P, bool VALS>
+__global__ __launch_bounds__(kWG) void k_bdual(const BInst<P> *bi, const int64_t *start, int32_t count) {
+    __shared__ double sh2[kWG / 64];
+    const Share sh = xcd_share(start[count]);
+    for (int64_t it = sh.lo; it < sh.hi; it += sh.step) {
+        const int32_t i = owner(start, count, it);
+        const BInst<P> &I = bi[i];
+        dual_item<P, VALS>(I.a, I.asc, I.dual, it - start[i], I.slack_identity, I.cpart, sh2);
+    }
+}
+
+// one workgroup per due instance: fold its partials into its metrics, then
+// retire it on a reached gap, the epoch cap or a NaN
+template <class P>
+__global__ __launch_bounds__(kWG) void k_bfinal(BInst<P> *bi, int32_t count) {
+    for (int32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        BInst<P> &I = bi[i];
+        if (!I.due) continue;
+        finalize_item(I.rpart, I.rows_wg, I.cpart, I.dual.nwg, I.beta, I.with_dual, I.metrics);
+        if (threadIdx.x == 0) {
+            const double *mt = I.metrics;
+            if (mt[MT_BAD] != 0.0) { I.diverged = 1; I.active = 0; }
+            if (I.gap_tol > 0.0 && mt[MT_GAP] <= I.gap_tol) I.active = 0;
+            if (I.epochs_done >= I.max_epochs) I.active = 0;
+            I.due = 0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_bclear(int32_t *v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *v = 0;
+}
+
+}  // namespace
+
+struct thetis_batch {
+    int32_t count = 0, precision = 0, max_classes = 0;
+    bool vals = false;
+    std::vector<thetis_solver *> solvers;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int widen = 1, grid_mult = 2;
+    int64_t resident_wg = 2048;
+    // device
+    void *bi = nullptr, *bc = nullptr;
+    int32_t *wg = nullptr, *cls = nullptr, *rows_wg = nullptr, *dual_wg = nullptr, *active = nullptr;
+    int64_t *start = nullptr;
+    size_t bi_bytes = 0;
+    std::vector<char> bi_host;          // host image of the BInst array
+    int64_t nclass_total = 0;
+    // captured epoch
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double captured_gap = -1.0;
+    int captured_widen = 0, captured_grid = 0;
+    uint64_t signature = 0;
+};
+
+namespace {
+
+std::map<uint64_t, std::pair<int, int>> &tuned_choices() {
+    static std::map<uint64_t, std::pair<int, int>> m;
+    return m;
+}
+
+void batch_drop_graph(thetis_batch &B) {
+    if (B.exec) (void)hipGraphExecDestroy(B.exec);
+    if (B.graph) (void)hipGraphDestroy(B.graph);
+    B.exec = nullptr;
+    B.graph = nullptr;
+}
+
+// host image of the per-instance records and the per-class plans for the
+// current launch configuration
+template <class P>
+thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) {
+    std::vector<BInst<P>> bi(B.count);
+    std::vector<BClass> bc;
+    for (int32_t i = 0; i < B.count; ++i) {
+        thetis_solver &S = *B.solvers[i];
+        BInst<P> &I = bi[i];
+        I.a = make_dev<P>(S);
+        I.sc = det_sched<P>(S);
+        I.asc = async_sched<P>(S);
+        I.with_dual = gap_tol > 0.0;
+        I.dual = I.with_dual ? S.dual : S.colterms;
+        I.rpart = (double *)S.rpart;
+        I.cpart = (double *)S.cpart;
+        I.metrics = (double *)S.metrics;
+        I.epoch = S.epoch;
+        I.rows_wg = cdiv(std::max<int64_t>(S.m, 1), kWG);
+        I.seed = S.p.seed;
+        I.gap_tol = gap_tol;
+        I.beta = S.p.beta;
+        I.nclasses = S.nclasses;
+        I.class_base = (int32_t)bc.size();
+        I.refresh_every = S.p.refresh_every;
+        I.active = max_epochs > 0 ? 1 : 0;
+        I.due = 0;
+        I.slack_identity = S.all_rows_slack ? 1 : 0;
+        I.lpc = S.lpc;
+        I.epochs_done = 0;
+        I.max_epochs = max_epochs;
+        I.diverged = 0;
+        for (const ClassLaunch &cl : S.det) {
+            BClass C{};
+            C.cols = cl.has_cols ? make_plan(cl.col_segs, false, 0, B.widen) : LaunchPlan{};
+            C.wg_cols = cl.has_cols ? C.cols.nwg : 0;
+            C.block_first = cl.block_first;
+            C.block_count = cl.block_count;
+            C.wg_block = cdiv(cl.block_count, kWG / 64);
+            C.slack_first = cl.slack_first;
+            C.slack_count = cl.slack_count;
+            C.wg_slack = cdiv(cl.slack_count, kWG);
+            bc.push_back(C);
+        }
+    }
+    if ((int64_t)bc.size() != B.nclass_total) return fail(THETIS_EINVAL, "batch solvers changed shape");
+    HIP_TRY(hipMemcpyAsync(B.bi, bi.data(), sizeof(BInst<P>) * B.count, hipMemcpyHostToDevice, B.stream));
+    HIP_TRY(hipMemcpyAsync(B.bc, bc.data(), sizeof(BClass) * bc.size(), hipMemcpyHostToDevice, B.stream));
+    HIP_TRY(hipStreamSynchronize(B.stream));
+    return THETIS_OK;
+}
+
+// the launches of one epoch (captured once per configuration)
+template <class P>
+void batch_epoch_launches(thetis_batch &B) {
+    const int32_t n = B.count;
+    const int64_t gi = cdiv(n, kWG);
+    const int64_t grid = std::max<int64_t>(8, (B.resident_wg * B.grid_mult) / 8 * 8);
+    BInst<P> *bi = (BInst<P> *)B.bi;
+    const BClass *bc = (const BClass *)B.bc;
+    hipLaunchKernelGGL(k_bclear, dim3(1), dim3(64), 0, B.stream, B.active);
+    for (int32_t q = 0; q < B.max_classes; ++q) {
+        hipLaunchKernelGGL((k_bplan<P>), dim3(gi), dim3(kWG), 0, B.stream, bi, bc, n, q, B.wg, B.cls);
+        hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.wg, n, B.start);
+        if (B.vals) hipLaunchKernelGGL((k_bsweep<P, true>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, (const int32_t *)B.cls, (const int64_t *)B.start, n);
+        else hipLaunchKernelGGL((k_bsweep<P, false>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, (const int32_t *)B.cls, (const int64_t *)B.start, n);
+    }
+    hipLaunchKernelGGL((k_bepoch<P>), dim3(gi), dim3(kWG), 0, B.stream, bi, n, B.rows_wg, B.dual_wg, B.active);
+    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.rows_wg, n, B.start);
+    hipLaunchKernelGGL((k_brows<P>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n);
+    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.dual_wg, n, B.start);
+    if (B.vals) hipLaunchKernelGGL((k_bdual<P, true>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n);
+    else hipLaunchKernelGGL((k_bdual<P, false>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n);
+    hipLaunchKernelGGL((k_bfinal<P>), dim3(std::min<int64_t>(n, 1024)), dim3(kWG), 0, B.stream, bi, n);
+}
+
+template <class P>
+thetis_status batch_capture(thetis_batch &B) {
+    batch_drop_graph(B);
+    HIP_TRY(hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal));
+    batch_epoch_launches<P>(B);
+    hipError_t e = hipStreamEndCapture(B.stream, &B.graph);
+    if (e != hipSuccess) { B.graph = nullptr; return fail(THETIS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e)); }
+    HIP_TRY(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+    B.captured_widen = B.widen;
+    B.captured_grid = B.grid_mult;
+    return THETIS_OK;
+}
+
+template <class P>
+thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol, int32_t *done, double *ms_out) {
+    for (thetis_solver *S : B.solvers) HIP_TRY(hipStreamSynchronize(S->stream));
+    thetis_status st = batch_upload<P>(B, max_epochs, gap_tol);
+    if (st) return st;
+    if (!B.exec || B.captured_widen != B.widen || B.captured_grid != B.grid_mult) {
+        st = batch_capture<P>(B);
+        if (st) return st;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ms_out) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, B.stream));
+    }
+    int32_t refresh_min = 1 << 30;
+    for (thetis_solver *S : B.solvers) refresh_min = std::min(refresh_min, S->p.refresh_every);
+    for (int32_t e = 0; e < max_epochs; ++e) {
+        HIP_TRY(hipGraphLaunch(B.exec, B.stream));
+        if (gap_tol > 0.0 && (e + 1) % refresh_min == 0 && e + 1 < max_epochs) {
+            int32_t act = 0;
+            HIP_TRY(hipMemcpyAsync(&act, B.active, 4, hipMemcpyDeviceToHost, B.stream));
+            HIP_TRY(hipStreamSynchronize(B.stream));
+            if (act == 0) break;
+        }
+    }
+    if (ms_out) {
+        HIP_TRY(hipEventRecord(e1, B.stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        *ms_out = ms;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    std::vector<BInst<P>> bi(B.count);
+    HIP_TRY(hipMemcpyAsync(bi.data(), B.bi, sizeof(BInst<P>) * B.count, hipMemcpyDeviceToHost, B.stream));
+    HIP_TRY(hipStreamSynchronize(B.stream));
+    bool diverged = false;
+    for (int32_t i = 0; i < B.count; ++i) {
+        thetis_solver &S = *B.solvers[i];
+        S.epoch = bi[i].epoch;
+        const bool fresh = bi[i].epochs_done > 0 && (bi[i].epoch % S.p.refresh_every) == 0;
+        if (bi[i].epochs_done > 0) {
+            S.metrics_fresh = fresh;
+            S.metrics_dual = fresh && gap_tol > 0.0;
+            S.have_round = false;
+        }
+        if (done) done[i] = bi[i].epochs_done;
+        diverged = diverged || bi[i].diverged;
+    }
+    if (diverged) return fail(THETIS_EDIVERGED, "NaN or Inf in an instance's refresh");
+    return THETIS_OK;
+}
+
+#define BDISPATCH(B, CALL) \
+    ((B).precision == THETIS_PREC_FP64 ? CALL<PF64> : ((B).precision == THETIS_PREC_BF16X ? CALL<PB16> : CALL<PF32>))
+
+size_t binst_bytes(int32_t precision) {
+    return precision == THETIS_PREC_FP64 ? sizeof(BInst<PF64>)
+                                         : (precision == THETIS_PREC_BF16X ? sizeof(BInst<PB16>) : sizeof(BInst<PF32>));
+}
+
+}  // namespace
+
+extern "C" thetis_status thetis_batch_create(int32_t count, thetis_solver *const *solvers, void *stream,
+                                             thetis_batch **out) {
+    clear_error();
+    if (!out || !solvers || count < 1) return fail(THETIS_EINVAL, "need at least one solver");
+    *out = nullptr;
+    thetis_batch *Bp = new (std::nothrow) thetis_batch;
+    if (!Bp) return fail(THETIS_ENOMEM, "host allocation failed");
+    thetis_batch &B = *Bp;
+    B.count = count;
+    B.stream = (hipStream_t)stream;
+    if (!B.stream) {
+        // stream capture needs a stream other than the null stream
+        if (hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking) != hipSuccess) {
+            delete Bp;
+            return fail(THETIS_EDEVICE, "could not create the batch stream");
+        }
+        B.own_stream = true;
+    }
+    uint64_t sig = 1469598103934665603ULL;
+    int64_t nnz_total = 0, maxdeg = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        thetis_solver *S = solvers[i];
+        if (!S) { delete Bp; return fail(THETIS_EINVAL, "NULL solver"); }
+        if (S->p.schedule != THETIS_SCHED_DET) { delete Bp; return fail(THETIS_EINVAL, "batches run the DET schedule"); }
+        if (i == 0) { B.precision = S->p.precision; B.vals = !S->unit_vals; }
+        if (S->p.precision != B.precision || (!S->unit_vals) != B.vals) {
+            delete Bp;
+            return fail(THETIS_EINVAL, "batch solvers must share precision and matrix value kind");
+        }
+        B.solvers.push_back(S);
+        B.max_classes = std::max(B.max_classes, S->nclasses);
+        B.nclass_total += (int64_t)S->det.size();
+        nnz_total += S->nnz;
+        maxdeg = std::max<int64_t>(maxdeg, S->max_degree);
+    }
+    // shape signature for the tuner cache: count, entries and largest degree
+    // on a log2 scale, precision
+    auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ULL; };
+    mix((uint64_t)count);
+    mix((uint64_t)(nnz_total > 0 ? 64 - __builtin_clzll((uint64_t)nnz_total) : 0));
+    mix((uint64_t)(maxdeg > 0 ? 64 - __builtin_clzll((uint64_t)maxdeg) : 0));
+    mix((uint64_t)B.precision);
+    B.signature = sig;
+    auto it = tuned_choices().find(sig);
+    if (it != tuned_choices().end()) { B.widen = it->second.first; B.grid_mult = it->second.second; }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
+    }
+    B.resident_wg = (int64_t)cus * 8;    // 8 workgroups of 256 threads per CU
+    const size_t nb = binst_bytes(B.precision);
+    hipError_t e = hipMalloc(&B.bi, nb * count);
+    if (e == hipSuccess) e = hipMalloc(&B.bc, sizeof(BClass) * std::max<int64_t>(B.nclass_total, 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&B.wg, 4 * count);
+    if (e == hipSuccess) e = hipMalloc((void **)&B.cls, 4 * count);
+    if (e == hipSuccess) e = hipMalloc((void **)&B.rows_wg, 4 * count);
+    if (e == hipSuccess) e = hipMalloc((void **)&B.dual_wg, 4 * count);
+    if (e == hipSuccess) e = hipMalloc((void **)&B.active, 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&B.start, 8 * (count + 1));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        thetis_batch_destroy(Bp);
+        return fail(THETIS_ENOMEM, "device allocation of the batch tables failed");
+    }
+    *out = Bp;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_batch_run(thetis_batch *b, int32_t max_epochs, double gap_tol, int32_t *done) {
+    clear_error();
+    if (!b) return fail(THETIS_EINVAL, "batch is NULL");
+    if (max_epochs < 0) return fail(THETIS_EINVAL, "max_epochs < 0");
+    if (max_epochs == 0) {
+        if (done) for (int32_t i = 0; i < b->count; ++i) done[i] = 0;
+        return THETIS_OK;
+    }
+    return BDISPATCH(*b, batch_run_impl)(*b, max_epochs, gap_tol, done, nullptr);
+}
+
+extern "C" thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult) {
+    clear_error();
+    if (!b) return fail(THETIS_EINVAL, "batch is NULL");
+    if (widen != 1 && widen != 2 && widen != 4) return fail(THETIS_EINVAL, "widen must be 1, 2 or 4");
+    if (grid_mult != 1 && grid_mult != 2 && grid_mult != 4 && grid_mult != 8)
+        return fail(THETIS_EINVAL, "grid multiplier must be 1, 2, 4 or 8");
+    b->widen = widen;
+    b->grid_mult = grid_mult;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_per_candidate, int32_t *choice) {
+    clear_error();
+    if (!b) return fail(THETIS_EINVAL, "batch is NULL");
+    if (epochs_per_candidate < 1) return fail(THETIS_EINVAL, "epochs_per_candidate < 1");
+    const int widens[2] = {1, 2};
+    const int grids[3] = {1, 2, 4};
+    double best = 1e300;
+    int bw = b->widen, bg = b->grid_mult;
+    for (int w : widens)
+        for (int g : grids) {
+            b->widen = w;
+            b->grid_mult = g;
+            // first replay after a capture includes the capture; time a second run
+            double ms = 0;
+            thetis_status st = BDISPATCH(*b, batch_run_impl)(*b, 1, 0.0, nullptr, nullptr);
+            if (st) return st;
+            st = BDISPATCH(*b, batch_run_impl)(*b, epochs_per_candidate, 0.0, nullptr, &ms);
+            if (st) return st;
+            if (ms < best) { best = ms; bw = w; bg = g; }
+        }
+    b->widen = bw;
+    b->grid_mult = bg;
+    tuned_choices()[b->signature] = {bw, bg};
+    if (choice) { choice[0] = bw; choice[1] = bg; }
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_batch_destroy(thetis_batch *b) {
+    if (!b) return THETIS_OK;
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(*b);
+    (void)hipFree(b->bi);
+    (void)hipFree(b->bc);
+    (void)hipFree(b->wg);
+    (void)hipFree(b->cls);
+    (void)hipFree(b->rows_wg);
+    (void)hipFree(b->dual_wg);
+    (void)hipFree(b->active);
+    (void)hipFree(b->start);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
     return THETIS_OK;
 }

@@ -38,6 +38,8 @@ EXPORTED = [
     "thetis_run_epochs", "thetis_residual", "thetis_objective", "thetis_get_x", "thetis_set_y",
     "thetis_epoch", "thetis_round", "thetis_check_feasible", "thetis_set_timing",
     "thetis_get_timing", "thetis_epoch_traffic", "thetis_solver_destroy", "thetis_last_error",
+    "thetis_batch_create", "thetis_batch_run", "thetis_batch_autotune", "thetis_batch_configure",
+    "thetis_batch_destroy",
 ]
 
 
@@ -89,6 +91,11 @@ def lib():
             "thetis_get_timing": [vp, i32, P(dbl), P(i64), P(dbl)],
             "thetis_epoch_traffic": [vp, P(dbl), P(dbl), P(i64)],
             "thetis_solver_destroy": [vp],
+            "thetis_batch_create": [i32, vp, vp, P(vp)],
+            "thetis_batch_run": [vp, i32, dbl, vp],
+            "thetis_batch_autotune": [vp, i32, vp],
+            "thetis_batch_configure": [vp, i32, i32],
+            "thetis_batch_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -252,6 +259,34 @@ def thetis_solver_destroy(s):
     _check(lib().thetis_solver_destroy(s))
 
 
+def thetis_batch_create(solver_handles, stream_ptr: int = 0):
+    arr = (C.c_void_p * len(solver_handles))(*[h.value if isinstance(h, C.c_void_p) else h for h in solver_handles])
+    b = C.c_void_p()
+    _check(lib().thetis_batch_create(len(solver_handles), C.cast(arr, C.c_void_p), C.c_void_p(stream_ptr or None),
+                                     C.byref(b)))
+    return b
+
+
+def thetis_batch_run(b, count: int, max_epochs: int, gap_tol: float = 0.0) -> np.ndarray:
+    done = np.zeros(count, np.int32)
+    _check(lib().thetis_batch_run(b, max_epochs, gap_tol, _ptr(done)))
+    return done
+
+
+def thetis_batch_autotune(b, epochs_per_candidate: int = 2):
+    ch = np.zeros(2, np.int32)
+    _check(lib().thetis_batch_autotune(b, epochs_per_candidate, _ptr(ch)))
+    return int(ch[0]), int(ch[1])
+
+
+def thetis_batch_configure(b, widen: int, grid_mult: int):
+    _check(lib().thetis_batch_configure(b, widen, grid_mult))
+
+
+def thetis_batch_destroy(b):
+    _check(lib().thetis_batch_destroy(b))
+
+
 # ------------------------------------------------------------ owning wrappers
 
 class Instance:
@@ -367,6 +402,35 @@ class Solver:
     def close(self):
         if getattr(self, "h", None):
             thetis_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several solvers advanced by one launch sequence per epoch."""
+
+    def __init__(self, solvers, stream=None):
+        self.solvers = list(solvers)
+        sp = 0 if stream is None else stream.cuda_stream
+        self.h = thetis_batch_create([s.h for s in self.solvers], sp)
+
+    def run(self, max_epochs: int, gap_tol: float = 0.0) -> np.ndarray:
+        return thetis_batch_run(self.h, len(self.solvers), max_epochs, gap_tol)
+
+    def autotune(self, epochs_per_candidate: int = 2):
+        return thetis_batch_autotune(self.h, epochs_per_candidate)
+
+    def configure(self, widen: int, grid_mult: int):
+        thetis_batch_configure(self.h, widen, grid_mult)
+
+    def close(self):
+        if getattr(self, "h", None):
+            thetis_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

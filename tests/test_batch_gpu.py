@@ -1,0 +1,145 @@
+"""Batched solves through the C ABI: every instance of a batch must compute
+exactly what it computes alone (DET schedule: same classes, same order,
+same kernels), whatever the launch configuration the tuner picks."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1311_2661_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+T = None
+
+
+def setup_module(module):
+    global T
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_2661_amd import thetis as TT
+    T = TT
+    torch.cuda.set_device(0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def mixed_instances():
+    return [I.vc_er(300, 1200, seed=1), I.vc_ba(5000, seed=2), I.mis_regular(800, 7, seed=3),
+            I.vc_er(40, 90, seed=4), I.mis_regular(2000, 16, seed=5), I.vc_ba(20000, seed=6)]
+
+
+def pair(insts, **kw):
+    a = [T.Solver(T.Instance(x), seed=10 + k, **kw) for k, x in enumerate(insts)]
+    b = [T.Solver(T.Instance(x), seed=10 + k, **kw) for k, x in enumerate(insts)]
+    return a, b
+
+
+def assert_same(sa, sb):
+    ya, yb = sa.y, sb.y
+    assert np.array_equal(ya, yb), np.abs(ya - yb).max()
+    ma, mb = sa.metrics(), sb.metrics()
+    for k in ("F", "lp_value", "dual_bound", "linf", "max_viol"):
+        assert ma[k] == mb[k], k
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16"])
+def test_batch_equals_alone_fixed_epochs(prec):
+    say(f"case batch vs alone {prec}")
+    p = dict(fp32=None, fp64=None, bf16=None)
+    precision = {"fp32": T.PREC_FP32, "fp64": T.PREC_FP64, "bf16": T.PREC_BF16X}[prec]
+    alone, batched = pair(mixed_instances(), precision=precision)
+    for s in alone:
+        s.run(23)
+    b = T.Batch(batched)
+    done = b.run(23)
+    assert list(done) == [23] * len(batched)
+    for sa, sb in zip(alone, batched):
+        assert sb.epoch == 23
+        assert_same(sa, sb)
+
+
+def test_batch_gap_stop_per_instance():
+    say("case batch gap stop")
+    insts = [I.vc_er(200, 800, seed=7), I.mis_regular(600, 4, seed=8), I.vc_ba(3000, seed=9)]
+    alone, batched = pair(insts)
+    ref = [s.run(2000, gap_tol=1e-4) for s in alone]
+    done = T.Batch(batched).run(2000, gap_tol=1e-4)
+    say(f"  epochs alone {ref} batched {list(done)}")
+    assert list(done) == ref
+    for sa, sb in zip(alone, batched):
+        assert_same(sa, sb)
+        assert sb.metrics()["gap"] <= 1e-4 + 1e-12
+
+
+def test_batch_multiway_cut_blocks():
+    say("case batch multiway cut")
+    insts = [I.mc_grid(side=12, k=4, seed=1), I.mc_grid(side=20, k=8, seed=2), I.mc_grid(side=7, k=3, seed=3)]
+    alone, batched = pair(insts)
+    for s in alone:
+        s.run(17)
+    T.Batch(batched).run(17)
+    for sa, sb in zip(alone, batched):
+        assert_same(sa, sb)
+
+
+@pytest.mark.parametrize("widen,grid", [(1, 1), (2, 4), (4, 8), (1, 8)])
+def test_batch_launch_configuration_does_not_change_results(widen, grid):
+    insts = mixed_instances()[:4]
+    alone, batched = pair(insts)
+    for s in alone:
+        s.run(12)
+    b = T.Batch(batched)
+    b.configure(widen, grid)
+    b.run(12)
+    for sa, sb in zip(alone, batched):
+        assert_same(sa, sb)
+
+
+def test_batch_autotune_and_continue():
+    say("case batch autotune")
+    insts = mixed_instances()
+    alone, batched = pair(insts)
+    b = T.Batch(batched)
+    w, g = b.autotune(epochs_per_candidate=2)
+    assert w in (1, 2) and g in (1, 2, 4)
+    ran = batched[0].epoch            # the tuner's epochs are real epochs
+    b.run(10)
+    for sa in alone:
+        sa.run(ran + 10)
+    for sa, sb in zip(alone, batched):
+        assert_same(sa, sb)
+
+
+def test_batch_many_uneven_instances():
+    """256 independent-set instances of uneven size and degree, as in the
+    batched workload, against solo runs of a sample."""
+    say("case batch 256 uneven")
+    rng = np.random.default_rng(0)
+    insts = [I.mis_regular(int(rng.integers(200, 3000)), int(rng.integers(3, 17)), seed=100 + k)
+             for k in range(256)]
+    batched = [T.Solver(T.Instance(x), seed=k) for k, x in enumerate(insts)]
+    done = T.Batch(batched).run(40, gap_tol=1e-4)
+    for k in rng.choice(256, 6, replace=False):
+        s = T.Solver(T.Instance(insts[k]), seed=int(k))
+        e = s.run(40, gap_tol=1e-4)
+        assert e == done[k]
+        assert_same(s, batched[k])
+        s.round(T.ROUND_MIS_THRESH)
+        assert s.check(T.ROUND_MIS_THRESH) == (True, 0)
+
+
+def test_batch_rejects_mixed_kinds():
+    a = T.Solver(T.Instance(I.vc_er(50, 100, seed=1)), precision=T.PREC_FP32)
+    b = T.Solver(T.Instance(I.vc_er(50, 100, seed=2)), precision=T.PREC_FP64)
+    with pytest.raises(T.ThetisError):
+        T.Batch([a, b])
+    c = T.Solver(T.Instance(I.vc_er(50, 100, seed=3)), schedule=T.SCHED_ASYNC)
+    with pytest.raises(T.ThetisError):
+        T.Batch([a, c])
+    d = T.Solver(T.Instance(I.mc_grid(side=5, k=3, seed=1)))
+    with pytest.raises(T.ThetisError):
+        T.Batch([a, d])

@@ -400,3 +400,28 @@ def test_full_size_ba_config_parity():
     assert cost == pytest.approx(ocost, rel=1e-4)
     e = inst.meta["edges"]
     assert np.all(sol[e[:, 0]] | sol[e[:, 1]])
+
+
+def test_bf16_x_storage_error_is_stated_and_bounded():
+    """x stored in BF16 (round to nearest even, residual updated with the
+    realised step), s and r in FP32: the iteration is not the FP64 one, so
+    the error against the FP64 oracle is reported; F must stay within 1e-2
+    relative at equal epochs and the roundings must stay valid."""
+    say("case bf16 mis_regular")
+    inst = I.mis_regular(3000, 6, seed=4)
+    g = gpu_solver(inst, beta=10.0, precision=T.PREC_BF16X, seed=4)
+    lp, o = oracle_solver(inst, beta=10.0, seed=4)
+    g.run(60)
+    o.run(60)
+    gm, om = g.metrics(), o.metrics()
+    x, ox = g.x, o.x
+    err = np.abs(x - ox).max()
+    say(f"  F bf16 {gm['F']:.8g} fp64 {om['F']:.8g} rel {rel(gm['F'], om['F']):.2e}; max|x-x64| {err:.3e}")
+    assert rel(gm["F"], om["F"]) < 1e-2
+    assert gm["dual_bound"] <= gm["F"]
+    # every stored x is a bf16 value
+    xb = x.astype(np.float32).view(np.uint32)
+    assert np.all((xb & 0xFFFF) == 0)
+    for rule in (T.ROUND_MIS_THRESH, T.ROUND_MIS_RAND):
+        g.round(rule, seed=3, reps=5)
+        assert g.check(rule) == (True, 0)
