@@ -13,6 +13,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import hashlib
+import numpy as np
 import json
 import os
 import sys
@@ -71,6 +72,229 @@ def cpu_baseline(inst, epochs_cap: int, budget_s: float, seed: int):
                        f"{total:.1f} s, setup excluded")
 
 
+def _mis_spec(k, seed):
+    from paper_1311_2661_amd import instances as I
+    rng = I.rng_for(seed, 1000 + k)
+    n = int(rng.integers(200, 50001))
+    d = int(rng.integers(3, 17))
+    return n, d
+
+
+def _mis_make(args):
+    k, seed = args
+    from paper_1311_2661_amd import instances as I
+    n, d = _mis_spec(k, seed)
+    inst = I.mis_regular(n, d, seed=seed * 100003 + k)
+    return inst.n, inst.meta["edges"].astype(np.int32), -inst.c
+
+
+def mis_batch(args):
+    """Batched workload: independent-set LPs on random d-regular graphs,
+    n uniform in [200, 50000], d uniform in {3..16}, weights uniform[1,5];
+    all instances solved in one batch to a 1e-4 certified gap (cap 200
+    epochs).  Baseline: the same solver run one instance per launch
+    sequence, timed on a stratified sample and extrapolated."""
+    import multiprocessing as mp
+    from paper_1311_2661_amd import instances as I
+    t0 = time.perf_counter()
+    count = args.instances
+    workers = max(1, min(16, (os.cpu_count() or 1)))
+    with mp.get_context("fork").Pool(workers) as pool:      # before the GPU is touched
+        made = pool.map(_mis_make, [(k, args.seed) for k in range(count)], chunksize=8)
+    nv = np.array([m[0] for m in made])
+    ne = np.array([len(m[1]) for m in made])
+    log(f"{count} instances: {nv.sum()} vertices, {ne.sum()} edges, generated in {time.perf_counter() - t0:.1f} s "
+        f"({workers} workers)")
+    import torch
+    from paper_1311_2661_amd import thetis as T
+    T.lib()
+    torch.cuda.set_device(0)
+    prec = {"bf16": T.PREC_BF16X, "fp32": T.PREC_FP32}[args.precision]
+
+    def solver_of(k):
+        n, e, w = made[k]
+        inst = I.mis_lp(n, e.astype(np.int64), w)
+        h = T.Instance(inst)
+        s = T.Solver(h, beta=10.0, precision=prec, refresh_every=5, seed=k)
+        s.instance = None
+        h.close()
+        return s
+
+    t0 = time.perf_counter()
+    solvers = [solver_of(k) for k in range(count)]
+    torch.cuda.synchronize()
+    log(f"layout + upload of {count} solvers: {time.perf_counter() - t0:.1f} s")
+    b = T.Batch(solvers)
+    choice = b.autotune(epochs_per_candidate=2)
+    log(f"autotuned: widen {choice[0]}, grid x{choice[1]}, strided {choice[2]}")
+    upd_total = []
+    for w in range(args.warmup):
+        for s in solvers:
+            s.reset()
+        b.run(args.cap, gap_tol=args.gap)
+    for s in solvers:
+        s.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = b.run(args.cap, gap_tol=args.gap)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    reached = 0
+    for s in solvers[:: max(1, count // 64)]:
+        m = s.metrics()
+        reached += m["gap"] <= args.gap
+    sample_n = len(solvers[:: max(1, count // 64)])
+    log(f"batch: {count} solves in {elapsed:.3f} s; epochs median {int(np.median(done))} max {int(done.max())}; "
+        f"gap reached in {reached}/{sample_n} sampled")
+    # per-instance updates: n + m coordinates per epoch
+    upd = float(np.sum((nv + ne) * done))
+    # one instance per launch sequence: stratified sample by size
+    order = np.argsort(nv)
+    strata = np.array_split(order, args.baseline_sample)
+    pick = [int(st[len(st) // 2]) for st in strata if len(st)]
+    times = []
+    for k in pick:
+        s = solver_of(k)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        s.run(args.cap, gap_tol=args.gap)
+        s.round(T.ROUND_MIS_THRESH)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ta)
+        s.close()
+    per_solve = float(np.mean(times))
+    base = 1.0 / per_solve
+    value = count / elapsed
+    # validity of the batched answers on a sample
+    feas = 0
+    for s in solvers[:: max(1, count // 32)]:
+        s.round(T.ROUND_MIS_THRESH)
+        feas += s.check(T.ROUND_MIS_THRESH)[0]
+    out = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": 1,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"mis_batch_{count}_n200-50000_d3-16_{args.precision}_gap{args.gap:g}_cap{args.cap}",
+                   "instances": count, "vertices": int(nv.sum()), "edges": int(ne.sum()),
+                   "gap_tol": args.gap, "epoch_cap": args.cap, "autotune": list(choice), "seed": args.seed},
+        "coord_updates_per_s": upd / elapsed,
+        "epochs": {"median": float(np.median(done)), "max": int(done.max()), "min": int(done.min())},
+        "gap_reached_sampled": f"{reached}/{sample_n}",
+        "feasible_sampled": f"{feas}/{len(solvers[:: max(1, count // 32)])}",
+        "one_per_launch": {"solves_per_s": base, "sample": f"{len(pick)} instances stratified by size, solved alone, "
+                           f"mean {1e3 * per_solve:.2f} ms per solve (extrapolated to the population)"},
+        "speedup_vs_one_per_launch": value / base,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _serve_compact(req):
+    from paper_1311_2661_amd import instances as I
+    return I.serving_compact(req)
+
+
+def serve(args):
+    """Serving workload: Poisson arrivals of mixed vertex-cover /
+    independent-set / multiway-cut requests (edges log-uniform in [1e3, 1e6])
+    replayed against the continuous-batching server; each request stops at
+    the certified gap or the epoch cap.  Latency = arrival to result on the
+    host, including expanding the request's LP rows and building its layout.
+    Baseline: the same solves one instance at a time (stratified sample)."""
+    import multiprocessing as mp
+    from paper_1311_2661_amd import instances as I
+    n_req = int(args.rate * args.duration)
+    trace = I.serving_trace(n_req, args.rate, args.seed)
+    t0 = time.perf_counter()
+    workers = max(1, min(16, (os.cpu_count() or 1)))
+    with mp.get_context("fork").Pool(workers) as pool:      # before the GPU is touched
+        compact = pool.map(_serve_compact, trace, chunksize=4)
+    edges = np.array([r["edges"] for r in trace])
+    kinds = [r["kind"] for r in trace]
+    log(f"{n_req} requests over {trace[-1]['t_arrival']:.1f} s; edges median {int(np.median(edges))}, "
+        f"kinds vc/mis/mc {kinds.count('vc')}/{kinds.count('mis')}/{kinds.count('mc')}; "
+        f"compact forms in {time.perf_counter() - t0:.1f} s")
+    import threading
+    import torch
+    from paper_1311_2661_amd import serve as SV
+    from paper_1311_2661_amd import thetis as T
+    T.lib()
+    torch.cuda.set_device(0)
+    free, total = torch.cuda.mem_get_info()
+    budget = int(args.budget_gb * (1 << 30)) if args.budget_gb > 0 else int(0.5 * free)
+    srv = SV.Server(hbm_budget=budget, gap_tol=args.gap, epoch_cap=args.cap, slots=args.slots,
+                    precision=T.PREC_FP32, builders=args.builders)
+    # warm-up: one small request of each kind (kernels load, graphs capture)
+    warm = [srv.submit(I.serving_expand(I.serving_compact(dict(kind=k, edges=2000, seed=10**6 + j))), k, seed=j)
+            for j, k in enumerate(["vc", "mis", "mc"])]
+    for f in warm:
+        f.result()
+    futs = [None] * n_req
+    tstart = time.perf_counter()
+
+    def client():
+        for k, r in enumerate(trace):
+            dt = tstart + r["t_arrival"] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            c = compact[k]
+            futs[k] = srv.submit(lambda c=c: I.serving_expand(c), r["kind"], seed=r["seed"] % (1 << 31),
+                                 t_arrival=time.perf_counter())
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    log(f"all {n_req} submitted after {time.perf_counter() - tstart:.1f} s")
+    res, errs = [], 0
+    for k, f in enumerate(futs):
+        try:
+            res.append(f.result())
+        except Exception as e:
+            errs += 1
+            log(f"request {k} failed: {e}")
+        if k % max(1, n_req // 10) == 0:
+            log(f"collected {k + 1}/{n_req}")
+    srv.close()
+    tend = max(r.t_done for r in res)
+    makespan = tend - tstart
+    lat = np.array([r.latency for r in res])
+    per_kind = {}
+    for kd in ("vc", "mis", "mc"):
+        rk = [r for r in res if r.kind == kd]
+        if rk:
+            per_kind[kd] = dict(n=len(rk), p50_s=float(np.median([r.latency for r in rk])),
+                                p99_s=float(np.quantile([r.latency for r in rk], 0.99)),
+                                epochs_median=float(np.median([r.epochs for r in rk])),
+                                gap_reached=f"{sum(r.reached_gap for r in rk)}/{len(rk)}",
+                                feasible=f"{sum(r.feasible for r in rk)}/{len(rk)}")
+    value = len(res) / makespan
+    # one request at a time, same solves: stratified sample by size
+    order = np.argsort(edges)
+    pick = [int(st[len(st) // 2]) for st in np.array_split(order, args.baseline_sample) if len(st)]
+    times = []
+    for k in pick:
+        lp = I.serving_expand(compact[k])
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        SV.solve_alone(lp, trace[k]["kind"], seed=trace[k]["seed"] % (1 << 31), gap_tol=args.gap,
+                       epoch_cap=args.cap)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ta)
+    alone = 1.0 / float(np.mean(times))
+    out = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 3,
+        "ms_per_step": 1e3 * makespan, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serve_poisson{args.rate:g}_{args.duration:g}s_edges1e3-1e6_gap{args.gap:g}_cap{args.cap}",
+                   "requests": n_req, "rate_per_s": args.rate, "budget_bytes": budget, "slots_per_kind": args.slots,
+                   "epochs_per_tick": 5, "seed": args.seed},
+        "latency_s": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99)), "max": float(lat.max())},
+        "per_kind": per_kind, "failed": errs, "peak_budget_used_bytes": srv.peak_used,
+        "one_at_a_time": {"solves_per_s": alone, "sample": f"{len(pick)} requests stratified by size, solved alone "
+                          f"in sequence, mean {1e3 / alone:.1f} ms"},
+        "speedup_vs_one_at_a_time": value / alone,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +308,17 @@ def main():
                     help="time budget of the oracle baseline (0 skips it)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--workload", choices=["vc_ba", "mis_batch", "serve"], default="vc_ba")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
+    ap.add_argument("--budget-gb", type=float, default=0.0, help="serve: device-memory budget (0: half of free)")
+    ap.add_argument("--slots", type=int, default=256, help="serve: slots per batch kind")
+    ap.add_argument("--builders", type=int, default=8, help="serve: host layout threads")
+    ap.add_argument("--instances", type=int, default=4096, help="mis_batch: instance count")
+    ap.add_argument("--precision", choices=["bf16", "fp32"], default="bf16", help="mis_batch: x storage")
+    ap.add_argument("--gap", type=float, default=1e-4, help="mis_batch: certified gap to stop at")
+    ap.add_argument("--cap", type=int, default=200, help="mis_batch: epoch cap")
+    ap.add_argument("--baseline-sample", type=int, default=32, help="mis_batch: instances solved alone")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -91,6 +326,11 @@ def main():
         print("bench.py measures one GPU: the solve is sized for one MI355X and the "
               "multi-GPU path is not part of this build (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "mis_batch":
+        return mis_batch(args)
+    if args.workload == "serve":
+        return serve(args)
 
     import numpy as np
     import torch

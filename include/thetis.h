@@ -244,40 +244,52 @@ thetis_status thetis_solver_destroy(thetis_solver *s);
 
 /* ----------------------------------------------------------------- batches */
 
-/* Groups `count` solvers (DET schedule, same precision, same kind of matrix
- * values -- all ones or not -- created on the current device) so that
- * thetis_batch_run advances all of them in one sequence of launches per
- * epoch: the class of step q of every instance (its own Philox class order)
- * in one launch, instance by instance refresh and stop.  Each solver
+/* A batch is a set of `capacity` slots, each empty or holding a solver (DET
+ * schedule, the batch's precision, matrix values all ones when unit_values
+ * is nonzero and otherwise not, created on the current device).
+ * thetis_batch_run advances every occupied slot in one sequence of launches
+ * per epoch: the class of step q of every instance (its own Philox class
+ * order) in one launch, instance by instance refresh and stop.  Each solver
  * computes exactly what thetis_run_epochs would compute for it alone (same
- * classes, same order, same kernels): results are bit-identical.  The batch
- * borrows the solvers (they must outlive it and must not be run alone while
- * a batch call is in progress).  stream: hipStream_t for the batch's
- * launches, or NULL.  Errors: THETIS_EINVAL (mixed precision or value kind,
- * ASYNC schedule, count < 1), THETIS_ENOMEM, THETIS_EDEVICE. */
-thetis_status thetis_batch_create(int32_t count, thetis_solver *const *solvers, void *stream,
-                                  thetis_batch **out);
+ * classes, same order, same kernels): results are bit-identical, whatever
+ * else occupies the batch.  solvers_host: NULL or `capacity` entries (NULL =
+ * empty slot).  The batch borrows the solvers (they must outlive their slot
+ * and must not be run alone during a batch call).  stream: hipStream_t for
+ * the batch's launches, or NULL (the batch makes its own).  Errors:
+ * THETIS_EINVAL (a solver of another precision or value kind, ASYNC
+ * schedule, capacity < 1), THETIS_EUNSUPPORTED (more than 64 colour
+ * classes), THETIS_ENOMEM, THETIS_EDEVICE. */
+thetis_status thetis_batch_create(int32_t capacity, thetis_solver *const *solvers_host, int32_t precision,
+                                  int32_t unit_values, void *stream, thetis_batch **out);
 
-/* Runs every active instance for up to max_epochs more epochs; an instance
+/* Puts a solver into a slot, or empties it (s = NULL), between runs. */
+thetis_status thetis_batch_set(thetis_batch *b, int32_t slot, thetis_solver *s);
+
+/* Runs every occupied slot for up to max_epochs more epochs; an instance
  * retires once its certified gap is <= gap_tol at one of its refresh epochs
  * (gap_tol <= 0: never) or after max_epochs.  epochs_done_host (NULL or
- * `count` entries) receives the epochs each instance ran.  One epoch of
- * launches is captured as a HIP graph and replayed. */
+ * `capacity` entries) receives the epochs each slot ran; status_host (NULL
+ * or `capacity` entries) 0 still running, 1 gap reached, 2 max_epochs
+ * reached, 3 NaN/Inf, -1 empty slot.  One epoch of launches is captured as a
+ * HIP graph and replayed (re-captured when the slot contents change the
+ * largest class count or the tables move). */
 thetis_status thetis_batch_run(thetis_batch *b, int32_t max_epochs, double gap_tol,
-                               int32_t *epochs_done_host);
+                               int32_t *epochs_done_host, int32_t *status_host);
 
 /* Chooses the launch configuration by timing real epochs of the batch
- * (epochs_per_candidate each, counted as epochs of the solve): lanes per
- * column widened 1x or 2x beyond the degree bound, and 1, 2 or 4 times the
- * resident workgroup count for the work-queue kernels.  Every candidate
- * computes bit-identical results.  The choice is cached per batch shape
- * (instance count, entries, largest degree) for the life of the process;
- * choice_host (NULL or 2 ints) receives (widen, grid multiplier). */
+ * (1 + epochs_per_candidate per candidate, counted as epochs of the solve):
+ * lanes per column widened 1x or 2x beyond the degree bound, 1, 2 or 4
+ * times the resident workgroup count for the work-queue kernels, and
+ * contiguous or strided walks of each XCD's share of the work items.
+ * Every candidate computes bit-identical results.  The choice is cached per
+ * batch shape (instance count, entries, largest degree, precision) for the
+ * life of the process; choice_host (NULL or 3 ints) receives (widen, grid
+ * multiplier, strided). */
 thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_per_candidate, int32_t *choice_host);
 
-/* Sets the launch configuration directly (widen in {1,2,4}, grid multiplier
- * in {1,2,4,8}). */
-thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult);
+/* Sets the launch configuration directly: widen in {1,2,4}, grid multiplier
+ * in {1,2,4,8}, strided in {0,1}. */
+thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult, int32_t strided);
 
 thetis_status thetis_batch_destroy(thetis_batch *b);
 

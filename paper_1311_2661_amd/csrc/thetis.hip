@@ -1956,12 +1956,12 @@ extern "C" thetis_status thetis_solver_destroy(thetis_solver *s) {
 // ==================================================================== batches
 //
 // A batch advances many solvers with one sequence of launches per epoch.
-// For step q of an epoch, k_bplan picks every active instance's class of
-// that step (its own Philox class order) and its workgroup count, k_bscan
-// turns the counts into offsets, and k_bsweep walks the resulting
-// (instance, workgroup) items: each XCD takes a contiguous share of the
-// items (so an instance's columns stay in one L2) and its workgroups stride
-// through that share.  Kernel boundaries are the class barriers.  After the
+// k_border draws every active instance's class order for the epoch (its own
+// Philox order).  For step q, k_bstep looks up each instance's class of that
+// step and its workgroup count and turns the counts into offsets, and
+// k_bsweep walks the resulting (instance, workgroup) items: each XCD takes a
+// contiguous share of the items (so an instance's columns stay in one L2)
+// and each of its workgroups a contiguous run of that share.  Kernel boundaries are the class barriers.  After the
 // last step, k_bepoch advances the epoch counters and marks the instances
 // whose refresh is due; k_brows / k_bdual / k_bfinal refresh them and retire
 // those whose certified gap reached the tolerance.  Every per-column and
@@ -1980,7 +1980,7 @@ struct BInst {
     uint64_t seed;
     double gap_tol, beta;
     int32_t nclasses, class_base, refresh_every, active, due, with_dual, slack_identity, lpc;
-    int32_t epochs_done, max_epochs, diverged;
+    int32_t epochs_done, max_epochs, diverged, reason;   // reason: 0 running, 1 gap, 2 epochs, 3 NaN
 };
 
 struct BClass {
@@ -1989,37 +1989,62 @@ struct BClass {
     int64_t wg_cols, wg_block, wg_slack;
 };
 
-// class of step q in `epoch`: the q-th smallest (Philox word, class id)
-__device__ int32_t class_of_step(uint64_t seed, int64_t epoch, int32_t nclasses, int32_t q) {
-    for (int32_t c = 0; c < nclasses; ++c) {
-        const uint64_t kc = philox_word_dev(seed, RNG_CLASS_ORDER, (uint64_t)epoch, (uint64_t)c, 0);
-        int32_t rank = 0;
-        for (int32_t c2 = 0; c2 < nclasses; ++c2) {
-            if (c2 == c) continue;
-            const uint64_t k2 = philox_word_dev(seed, RNG_CLASS_ORDER, (uint64_t)epoch, (uint64_t)c2, 0);
-            rank += (k2 < kc || (k2 == kc && c2 < c)) ? 1 : 0;
-        }
-        if (rank == q) return c;
-    }
-    return -1;
-}
+constexpr int kMaxBatchClasses = 64;
 
+// class order of every active instance for its current epoch: classes
+// sorted by (Philox word, class id), one thread per instance
 template <class P>
-__global__ __launch_bounds__(kWG) void k_bplan(BInst<P> *bi, const BClass *bc, int32_t count, int32_t q,
-                                               int32_t *wg, int32_t *cls) {
+__global__ __launch_bounds__(kWG) void k_border(const BInst<P> *bi, int32_t count, int8_t *order) {
     const int32_t i = blockIdx.x * kWG + threadIdx.x;
     if (i >= count) return;
     const BInst<P> &I = bi[i];
-    int32_t w = 0, c = -1;
-    if (I.active && q < I.nclasses) {
-        c = class_of_step(I.seed, I.epoch, I.nclasses, q);
-        if (c >= 0) {
-            const BClass &C = bc[I.class_base + c];
-            w = (int32_t)(C.wg_cols + C.wg_block + C.wg_slack);
-        }
+    if (!I.active) return;
+    uint64_t key[kMaxBatchClasses];
+    int8_t id[kMaxBatchClasses];
+    const int32_t C = I.nclasses;
+    for (int32_t c = 0; c < C; ++c) {
+        const uint64_t k = philox_word_dev(I.seed, RNG_CLASS_ORDER, (uint64_t)I.epoch, (uint64_t)c, 0);
+        int32_t p = c;
+        while (p > 0 && key[p - 1] > k) { key[p] = key[p - 1]; id[p] = id[p - 1]; --p; }
+        key[p] = k;
+        id[p] = (int8_t)c;
     }
-    wg[i] = w;
-    cls[i] = c;
+    for (int32_t q = 0; q < C; ++q) order[(int64_t)i * kMaxBatchClasses + q] = id[q];
+}
+
+// step q: every active instance's class and workgroup count, and the
+// exclusive prefix of the counts (start has count + 1 entries); one workgroup
+template <class P>
+__global__ __launch_bounds__(kWG) void k_bstep(const BInst<P> *bi, const BClass *bc, int32_t count, int32_t q,
+                                               const int8_t *order, int32_t *cls, int64_t *start) {
+    __shared__ int64_t part[kWG + 1];
+    const int t = threadIdx.x;
+    const int32_t chunk = (count + kWG - 1) / kWG;
+    const int32_t lo = t * chunk, hi = min(count, lo + chunk);
+    int64_t sum = 0;
+    for (int32_t i = lo; i < hi; ++i) {
+        const BInst<P> &I = bi[i];
+        int32_t c = -1;
+        int64_t w = 0;
+        if (I.active && q < I.nclasses) {
+            c = order[(int64_t)i * kMaxBatchClasses + q];
+            const BClass &C = bc[I.class_base + c];
+            w = C.wg_cols + C.wg_block + C.wg_slack;
+        }
+        cls[i] = c;
+        start[i] = w;          // count for now, prefix below
+        sum += w;
+    }
+    part[t + 1] = sum;
+    __syncthreads();
+    if (t == 0) {
+        part[0] = 0;
+        for (int u = 1; u <= kWG; ++u) part[u] += part[u - 1];
+    }
+    __syncthreads();
+    int64_t run = part[t];
+    for (int32_t i = lo; i < hi; ++i) { const int64_t w = start[i]; start[i] = run; run += w; }
+    if (t == 0) start[count] = part[kWG];
 }
 
 // exclusive prefix of `count` workgroup counts in one workgroup; start has
@@ -2053,31 +2078,44 @@ __device__ __forceinline__ int32_t owner(const int64_t *start, int32_t count, in
     return lo;
 }
 
-// this workgroup's share of `total` items: XCD x (= block & 7) takes the
-// x-th contiguous eighth, its workgroups stride through it
+// this workgroup's share of `total` items.  XCD x (= block & 7) takes the
+// x-th contiguous eighth.  Inside it, either each workgroup of the XCD takes
+// a contiguous run (stride 1), or the XCD's workgroups take neighbouring
+// items and stride by their count, so that at any moment one XCD works on
+// one or two instances whose state fits its L2.  Both walks visit items in
+// increasing order, so the owner is found by stepping forward.
 struct Share {
     int64_t lo, hi, step;
 };
-__device__ __forceinline__ Share xcd_share(int64_t total) {
-    const int64_t xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+__device__ __forceinline__ Share xcd_share(int64_t total, int32_t strided) {
+    const int64_t xcd = blockIdx.x & 7, per = gridDim.x >> 3, lw = blockIdx.x >> 3;
     const int64_t chunk = (total + 7) >> 3;
+    const int64_t xlo = xcd * chunk, xhi = min(total, xlo + chunk);
     Share s;
-    s.lo = xcd * chunk + (blockIdx.x >> 3);
-    s.hi = min(total, (xcd + 1) * chunk);
-    s.step = per;
+    if (strided) {
+        s.lo = xlo + lw;
+        s.hi = xhi;
+        s.step = per;
+    } else {
+        const int64_t sub = (xhi - xlo + per - 1) / per;
+        s.lo = xlo + lw * sub;
+        s.hi = min(xhi, s.lo + sub);
+        s.step = 1;
+    }
     return s;
 }
 
 template <class P, bool VALS>
 __global__ __launch_bounds__(kWG) void k_bsweep(const BInst<P> *bi, const BClass *bc, const int32_t *cls,
-                                                const int64_t *start, int32_t count) {
+                                                const int64_t *start, int32_t count, int32_t strided) {
     using R = typename P::R;
     __shared__ R st_r[HubTile<P>::n];
     __shared__ int32_t st_row[HubTile<P>::n];
     __shared__ R red[kWG / 64];
-    const Share sh = xcd_share(start[count]);
+    const Share sh = xcd_share(start[count], strided);
+    int32_t i = sh.lo < sh.hi ? owner(start, count, sh.lo) : 0;
     for (int64_t it = sh.lo; it < sh.hi; it += sh.step) {
-        const int32_t i = owner(start, count, it);
+        while (start[i + 1] <= it) ++i;
         const BInst<P> &I = bi[i];
         const BClass &C = bc[I.class_base + cls[i]];
         const int64_t local = it - start[i];
@@ -2105,7 +2143,7 @@ __global__ __launch_bounds__(kWG) void k_bepoch(BInst<P> *bi, int32_t count, int
         I.epochs_done += 1;
         I.due = (I.epoch % I.refresh_every) == 0;
         if (I.due) { rw = (int32_t)I.rows_wg; dw = (int32_t)I.dual.nwg; }
-        else if (I.epochs_done >= I.max_epochs) I.active = 0;
+        else if (I.epochs_done >= I.max_epochs) { I.active = 0; I.reason = 2; }
         if (I.active) atomicAdd(active_count, 1);
     } else {
         I.due = 0;
@@ -2115,21 +2153,25 @@ __global__ __launch_bounds__(kWG) void k_bepoch(BInst<P> *bi, int32_t count, int
 }
 
 template <class P>
-__global__ __launch_bounds__(kWG) void k_brows(const BInst<P> *bi, const int64_t *start, int32_t count) {
-    const Share sh = xcd_share(start[count]);
+__global__ __launch_bounds__(kWG) void k_brows(const BInst<P> *bi, const int64_t *start, int32_t count,
+                                               int32_t strided) {
+    const Share sh = xcd_share(start[count], strided);
+    int32_t i = sh.lo < sh.hi ? owner(start, count, sh.lo) : 0;
     for (int64_t it = sh.lo; it < sh.hi; it += sh.step) {
-        const int32_t i = owner(start, count, it);
+        while (start[i + 1] <= it) ++i;
         const BInst<P> &I = bi[i];
         rows_item<P>(I.a, it - start[i], 1, I.with_dual, I.rpart);
     }
 }
 
 template <class P, bool VALS>
-__global__ __launch_bounds__(kWG) void k_bdual(const BInst<P> *bi, const int64_t *start, int32_t count) {
+__global__ __launch_bounds__(kWG) void k_bdual(const BInst<P> *bi, const int64_t *start, int32_t count,
+                                               int32_t strided) {
     __shared__ double sh2[kWG / 64];
-    const Share sh = xcd_share(start[count]);
+    const Share sh = xcd_share(start[count], strided);
+    int32_t i = sh.lo < sh.hi ? owner(start, count, sh.lo) : 0;
     for (int64_t it = sh.lo; it < sh.hi; it += sh.step) {
-        const int32_t i = owner(start, count, it);
+        while (start[i + 1] <= it) ++i;
         const BInst<P> &I = bi[i];
         dual_item<P, VALS>(I.a, I.asc, I.dual, it - start[i], I.slack_identity, I.cpart, sh2);
     }
@@ -2145,9 +2187,9 @@ __global__ __launch_bounds__(kWG) void k_bfinal(BInst<P> *bi, int32_t count) {
         finalize_item(I.rpart, I.rows_wg, I.cpart, I.dual.nwg, I.beta, I.with_dual, I.metrics);
         if (threadIdx.x == 0) {
             const double *mt = I.metrics;
-            if (mt[MT_BAD] != 0.0) { I.diverged = 1; I.active = 0; }
-            if (I.gap_tol > 0.0 && mt[MT_GAP] <= I.gap_tol) I.active = 0;
-            if (I.epochs_done >= I.max_epochs) I.active = 0;
+            if (I.epochs_done >= I.max_epochs) { I.active = 0; I.reason = 2; }
+            if (I.gap_tol > 0.0 && mt[MT_GAP] <= I.gap_tol) { I.active = 0; I.reason = 1; }
+            if (mt[MT_BAD] != 0.0) { I.diverged = 1; I.active = 0; I.reason = 3; }
             I.due = 0;
         }
         __syncthreads();
@@ -2163,14 +2205,16 @@ __global__ void k_bclear(int32_t *v) {
 struct thetis_batch {
     int32_t count = 0, precision = 0, max_classes = 0;
     bool vals = false;
+    int64_t bc_capacity = 0;             // BClass records the device table holds
     std::vector<thetis_solver *> solvers;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    int widen = 1, grid_mult = 2;
+    int widen = 1, grid_mult = 2, strided = 1;
     int64_t resident_wg = 2048;
     // device
     void *bi = nullptr, *bc = nullptr;
     int32_t *wg = nullptr, *cls = nullptr, *rows_wg = nullptr, *dual_wg = nullptr, *active = nullptr;
+    int8_t *order = nullptr;
     int64_t *start = nullptr;
     size_t bi_bytes = 0;
     std::vector<char> bi_host;          // host image of the BInst array
@@ -2178,15 +2222,17 @@ struct thetis_batch {
     // captured epoch
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    double captured_gap = -1.0;
-    int captured_widen = 0, captured_grid = 0;
+    int captured_widen = 0, captured_grid = 0, captured_strided = -1;
     uint64_t signature = 0;
 };
 
 namespace {
 
-std::map<uint64_t, std::pair<int, int>> &tuned_choices() {
-    static std::map<uint64_t, std::pair<int, int>> m;
+struct Choice {
+    int widen, grid_mult, strided;
+};
+std::map<uint64_t, Choice> &tuned_choices() {
+    static std::map<uint64_t, Choice> m;
     return m;
 }
 
@@ -2204,8 +2250,10 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
     std::vector<BInst<P>> bi(B.count);
     std::vector<BClass> bc;
     for (int32_t i = 0; i < B.count; ++i) {
-        thetis_solver &S = *B.solvers[i];
         BInst<P> &I = bi[i];
+        std::memset((void *)&I, 0, sizeof(I));
+        if (!B.solvers[i]) continue;        // empty slot: inactive, no classes
+        thetis_solver &S = *B.solvers[i];
         I.a = make_dev<P>(S);
         I.sc = det_sched<P>(S);
         I.asc = async_sched<P>(S);
@@ -2229,6 +2277,7 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
         I.epochs_done = 0;
         I.max_epochs = max_epochs;
         I.diverged = 0;
+        I.reason = 0;
         for (const ClassLaunch &cl : S.det) {
             BClass C{};
             C.cols = cl.has_cols ? make_plan(cl.col_segs, false, 0, B.widen) : LaunchPlan{};
@@ -2242,9 +2291,21 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
             bc.push_back(C);
         }
     }
-    if ((int64_t)bc.size() != B.nclass_total) return fail(THETIS_EINVAL, "batch solvers changed shape");
+    if ((int64_t)bc.size() > B.bc_capacity) {
+        HIP_TRY(hipStreamSynchronize(B.stream));
+        (void)hipFree(B.bc);
+        B.bc = nullptr;
+        const int64_t cap = std::max<int64_t>((int64_t)bc.size() * 2, 64);
+        HIP_TRY(hipMalloc(&B.bc, sizeof(BClass) * cap));
+        B.bc_capacity = cap;
+        batch_drop_graph(B);                 // the captured launches point at the old table
+    }
+    int32_t mc = 0;
+    for (thetis_solver *S : B.solvers) if (S) mc = std::max(mc, S->nclasses);
+    if (mc != B.max_classes) { B.max_classes = mc; batch_drop_graph(B); }
     HIP_TRY(hipMemcpyAsync(B.bi, bi.data(), sizeof(BInst<P>) * B.count, hipMemcpyHostToDevice, B.stream));
-    HIP_TRY(hipMemcpyAsync(B.bc, bc.data(), sizeof(BClass) * bc.size(), hipMemcpyHostToDevice, B.stream));
+    if (!bc.empty())
+        HIP_TRY(hipMemcpyAsync(B.bc, bc.data(), sizeof(BClass) * bc.size(), hipMemcpyHostToDevice, B.stream));
     HIP_TRY(hipStreamSynchronize(B.stream));
     return THETIS_OK;
 }
@@ -2258,18 +2319,19 @@ void batch_epoch_launches(thetis_batch &B) {
     BInst<P> *bi = (BInst<P> *)B.bi;
     const BClass *bc = (const BClass *)B.bc;
     hipLaunchKernelGGL(k_bclear, dim3(1), dim3(64), 0, B.stream, B.active);
+    hipLaunchKernelGGL((k_border<P>), dim3(gi), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, n, B.order);
     for (int32_t q = 0; q < B.max_classes; ++q) {
-        hipLaunchKernelGGL((k_bplan<P>), dim3(gi), dim3(kWG), 0, B.stream, bi, bc, n, q, B.wg, B.cls);
-        hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.wg, n, B.start);
-        if (B.vals) hipLaunchKernelGGL((k_bsweep<P, true>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, (const int32_t *)B.cls, (const int64_t *)B.start, n);
-        else hipLaunchKernelGGL((k_bsweep<P, false>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, (const int32_t *)B.cls, (const int64_t *)B.start, n);
+        hipLaunchKernelGGL((k_bstep<P>), dim3(1), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, bc, n, q,
+                           (const int8_t *)B.order, B.cls, B.start);
+        if (B.vals) hipLaunchKernelGGL((k_bsweep<P, true>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, (const int32_t *)B.cls, (const int64_t *)B.start, n, B.strided);
+        else hipLaunchKernelGGL((k_bsweep<P, false>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, (const int32_t *)B.cls, (const int64_t *)B.start, n, B.strided);
     }
     hipLaunchKernelGGL((k_bepoch<P>), dim3(gi), dim3(kWG), 0, B.stream, bi, n, B.rows_wg, B.dual_wg, B.active);
     hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.rows_wg, n, B.start);
-    hipLaunchKernelGGL((k_brows<P>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n);
+    hipLaunchKernelGGL((k_brows<P>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n, B.strided);
     hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.dual_wg, n, B.start);
-    if (B.vals) hipLaunchKernelGGL((k_bdual<P, true>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n);
-    else hipLaunchKernelGGL((k_bdual<P, false>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n);
+    if (B.vals) hipLaunchKernelGGL((k_bdual<P, true>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n, B.strided);
+    else hipLaunchKernelGGL((k_bdual<P, false>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n, B.strided);
     hipLaunchKernelGGL((k_bfinal<P>), dim3(std::min<int64_t>(n, 1024)), dim3(kWG), 0, B.stream, bi, n);
 }
 
@@ -2283,15 +2345,17 @@ thetis_status batch_capture(thetis_batch &B) {
     HIP_TRY(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
     B.captured_widen = B.widen;
     B.captured_grid = B.grid_mult;
+    B.captured_strided = B.strided;
     return THETIS_OK;
 }
 
 template <class P>
-thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol, int32_t *done, double *ms_out) {
-    for (thetis_solver *S : B.solvers) HIP_TRY(hipStreamSynchronize(S->stream));
+thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol, int32_t *done, int32_t *status,
+                             double *ms_out) {
+    for (thetis_solver *S : B.solvers) if (S) HIP_TRY(hipStreamSynchronize(S->stream));
     thetis_status st = batch_upload<P>(B, max_epochs, gap_tol);
     if (st) return st;
-    if (!B.exec || B.captured_widen != B.widen || B.captured_grid != B.grid_mult) {
+    if (!B.exec || B.captured_widen != B.widen || B.captured_grid != B.grid_mult || B.captured_strided != B.strided) {
         st = batch_capture<P>(B);
         if (st) return st;
     }
@@ -2302,7 +2366,8 @@ thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol
         HIP_TRY(hipEventRecord(e0, B.stream));
     }
     int32_t refresh_min = 1 << 30;
-    for (thetis_solver *S : B.solvers) refresh_min = std::min(refresh_min, S->p.refresh_every);
+    for (thetis_solver *S : B.solvers) if (S) refresh_min = std::min(refresh_min, S->p.refresh_every);
+    if (refresh_min == (1 << 30)) refresh_min = 1;
     for (int32_t e = 0; e < max_epochs; ++e) {
         HIP_TRY(hipGraphLaunch(B.exec, B.stream));
         if (gap_tol > 0.0 && (e + 1) % refresh_min == 0 && e + 1 < max_epochs) {
@@ -2326,6 +2391,8 @@ thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol
     HIP_TRY(hipStreamSynchronize(B.stream));
     bool diverged = false;
     for (int32_t i = 0; i < B.count; ++i) {
+        if (status) status[i] = B.solvers[i] ? (bi[i].active ? 0 : bi[i].reason) : -1;
+        if (!B.solvers[i]) { if (done) done[i] = 0; continue; }
         thetis_solver &S = *B.solvers[i];
         S.epoch = bi[i].epoch;
         const bool fresh = bi[i].epochs_done > 0 && (bi[i].epoch % S.p.refresh_every) == 0;
@@ -2351,15 +2418,58 @@ size_t binst_bytes(int32_t precision) {
 
 }  // namespace
 
-extern "C" thetis_status thetis_batch_create(int32_t count, thetis_solver *const *solvers, void *stream,
-                                             thetis_batch **out) {
+namespace {
+thetis_status batch_check_solver(const thetis_batch &B, const thetis_solver *S) {
+    if (S->p.schedule != THETIS_SCHED_DET) return fail(THETIS_EINVAL, "batches run the DET schedule");
+    if (S->p.precision != B.precision || (!S->unit_vals) != B.vals)
+        return fail(THETIS_EINVAL, "batch solvers must share precision and matrix value kind");
+    if (S->nclasses > kMaxBatchClasses) return fail(THETIS_EUNSUPPORTED, "batched instances need at most 64 colour classes");
+    return THETIS_OK;
+}
+
+// shape signature for the tuner cache: slot count, entries and largest
+// degree on a log2 scale, precision
+void batch_signature(thetis_batch &B) {
+    uint64_t sig = 1469598103934665603ULL;
+    int64_t nnz_total = 0, maxdeg = 0;
+    for (thetis_solver *S : B.solvers)
+        if (S) { nnz_total += S->nnz; maxdeg = std::max<int64_t>(maxdeg, S->max_degree); }
+    auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ULL; };
+    mix((uint64_t)B.count);
+    mix((uint64_t)(nnz_total > 0 ? 64 - __builtin_clzll((uint64_t)nnz_total) : 0));
+    mix((uint64_t)(maxdeg > 0 ? 64 - __builtin_clzll((uint64_t)maxdeg) : 0));
+    mix((uint64_t)B.precision);
+    B.signature = sig;
+    auto it = tuned_choices().find(sig);
+    if (it != tuned_choices().end()) {
+        B.widen = it->second.widen;
+        B.grid_mult = it->second.grid_mult;
+        B.strided = it->second.strided;
+    }
+}
+}  // namespace
+
+extern "C" thetis_status thetis_batch_create(int32_t capacity, thetis_solver *const *solvers, int32_t precision,
+                                             int32_t unit_values, void *stream, thetis_batch **out) {
     clear_error();
-    if (!out || !solvers || count < 1) return fail(THETIS_EINVAL, "need at least one solver");
+    if (!out || capacity < 1) return fail(THETIS_EINVAL, "need a capacity of at least one slot");
     *out = nullptr;
+    if (precision != THETIS_PREC_FP32 && precision != THETIS_PREC_FP64 && precision != THETIS_PREC_BF16X)
+        return fail(THETIS_EINVAL, "unknown precision");
     thetis_batch *Bp = new (std::nothrow) thetis_batch;
     if (!Bp) return fail(THETIS_ENOMEM, "host allocation failed");
     thetis_batch &B = *Bp;
-    B.count = count;
+    B.count = capacity;
+    B.precision = precision;
+    B.vals = unit_values == 0;
+    B.solvers.assign(capacity, nullptr);
+    for (int32_t i = 0; solvers && i < capacity; ++i) {
+        thetis_solver *S = solvers[i];
+        if (!S) continue;
+        thetis_status st = batch_check_solver(B, S);
+        if (st) { delete Bp; return st; }
+        B.solvers[i] = S;
+    }
     B.stream = (hipStream_t)stream;
     if (!B.stream) {
         // stream capture needs a stream other than the null stream
@@ -2369,48 +2479,23 @@ extern "C" thetis_status thetis_batch_create(int32_t count, thetis_solver *const
         }
         B.own_stream = true;
     }
-    uint64_t sig = 1469598103934665603ULL;
-    int64_t nnz_total = 0, maxdeg = 0;
-    for (int32_t i = 0; i < count; ++i) {
-        thetis_solver *S = solvers[i];
-        if (!S) { delete Bp; return fail(THETIS_EINVAL, "NULL solver"); }
-        if (S->p.schedule != THETIS_SCHED_DET) { delete Bp; return fail(THETIS_EINVAL, "batches run the DET schedule"); }
-        if (i == 0) { B.precision = S->p.precision; B.vals = !S->unit_vals; }
-        if (S->p.precision != B.precision || (!S->unit_vals) != B.vals) {
-            delete Bp;
-            return fail(THETIS_EINVAL, "batch solvers must share precision and matrix value kind");
-        }
-        B.solvers.push_back(S);
-        B.max_classes = std::max(B.max_classes, S->nclasses);
-        B.nclass_total += (int64_t)S->det.size();
-        nnz_total += S->nnz;
-        maxdeg = std::max<int64_t>(maxdeg, S->max_degree);
-    }
-    // shape signature for the tuner cache: count, entries and largest degree
-    // on a log2 scale, precision
-    auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ULL; };
-    mix((uint64_t)count);
-    mix((uint64_t)(nnz_total > 0 ? 64 - __builtin_clzll((uint64_t)nnz_total) : 0));
-    mix((uint64_t)(maxdeg > 0 ? 64 - __builtin_clzll((uint64_t)maxdeg) : 0));
-    mix((uint64_t)B.precision);
-    B.signature = sig;
-    auto it = tuned_choices().find(sig);
-    if (it != tuned_choices().end()) { B.widen = it->second.first; B.grid_mult = it->second.second; }
+    batch_signature(B);
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
     }
     B.resident_wg = (int64_t)cus * 8;    // 8 workgroups of 256 threads per CU
+    const int32_t count = capacity;
     const size_t nb = binst_bytes(B.precision);
     hipError_t e = hipMalloc(&B.bi, nb * count);
-    if (e == hipSuccess) e = hipMalloc(&B.bc, sizeof(BClass) * std::max<int64_t>(B.nclass_total, 1));
     if (e == hipSuccess) e = hipMalloc((void **)&B.wg, 4 * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.cls, 4 * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.rows_wg, 4 * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.dual_wg, 4 * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.active, 4);
     if (e == hipSuccess) e = hipMalloc((void **)&B.start, 8 * (count + 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&B.order, (size_t)kMaxBatchClasses * count);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         thetis_batch_destroy(Bp);
@@ -2420,25 +2505,43 @@ extern "C" thetis_status thetis_batch_create(int32_t count, thetis_solver *const
     return THETIS_OK;
 }
 
-extern "C" thetis_status thetis_batch_run(thetis_batch *b, int32_t max_epochs, double gap_tol, int32_t *done) {
+extern "C" thetis_status thetis_batch_set(thetis_batch *b, int32_t slot, thetis_solver *s) {
+    clear_error();
+    if (!b) return fail(THETIS_EINVAL, "batch is NULL");
+    if (slot < 0 || slot >= b->count) return fail(THETIS_EINVAL, "slot out of range");
+    if (s) {
+        thetis_status st = batch_check_solver(*b, s);
+        if (st) return st;
+    }
+    b->solvers[slot] = s;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_batch_run(thetis_batch *b, int32_t max_epochs, double gap_tol, int32_t *done,
+                                          int32_t *status) {
     clear_error();
     if (!b) return fail(THETIS_EINVAL, "batch is NULL");
     if (max_epochs < 0) return fail(THETIS_EINVAL, "max_epochs < 0");
     if (max_epochs == 0) {
-        if (done) for (int32_t i = 0; i < b->count; ++i) done[i] = 0;
+        for (int32_t i = 0; i < b->count; ++i) {
+            if (done) done[i] = 0;
+            if (status) status[i] = b->solvers[i] ? 0 : -1;
+        }
         return THETIS_OK;
     }
-    return BDISPATCH(*b, batch_run_impl)(*b, max_epochs, gap_tol, done, nullptr);
+    return BDISPATCH(*b, batch_run_impl)(*b, max_epochs, gap_tol, done, status, nullptr);
 }
 
-extern "C" thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult) {
+extern "C" thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult, int32_t strided) {
     clear_error();
     if (!b) return fail(THETIS_EINVAL, "batch is NULL");
     if (widen != 1 && widen != 2 && widen != 4) return fail(THETIS_EINVAL, "widen must be 1, 2 or 4");
     if (grid_mult != 1 && grid_mult != 2 && grid_mult != 4 && grid_mult != 8)
         return fail(THETIS_EINVAL, "grid multiplier must be 1, 2, 4 or 8");
+    if (strided != 0 && strided != 1) return fail(THETIS_EINVAL, "strided must be 0 or 1");
     b->widen = widen;
     b->grid_mult = grid_mult;
+    b->strided = strided;
     return THETIS_OK;
 }
 
@@ -2449,23 +2552,26 @@ extern "C" thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_p
     const int widens[2] = {1, 2};
     const int grids[3] = {1, 2, 4};
     double best = 1e300;
-    int bw = b->widen, bg = b->grid_mult;
-    for (int w : widens)
-        for (int g : grids) {
-            b->widen = w;
-            b->grid_mult = g;
-            // first replay after a capture includes the capture; time a second run
-            double ms = 0;
-            thetis_status st = BDISPATCH(*b, batch_run_impl)(*b, 1, 0.0, nullptr, nullptr);
-            if (st) return st;
-            st = BDISPATCH(*b, batch_run_impl)(*b, epochs_per_candidate, 0.0, nullptr, &ms);
-            if (st) return st;
-            if (ms < best) { best = ms; bw = w; bg = g; }
-        }
-    b->widen = bw;
-    b->grid_mult = bg;
-    tuned_choices()[b->signature] = {bw, bg};
-    if (choice) { choice[0] = bw; choice[1] = bg; }
+    Choice bc{b->widen, b->grid_mult, b->strided};
+    for (int st = 0; st < 2; ++st)
+        for (int w : widens)
+            for (int g : grids) {
+                b->widen = w;
+                b->grid_mult = g;
+                b->strided = st;
+                // the first run after a capture includes the capture; time a second run
+                double ms = 0;
+                thetis_status rc = BDISPATCH(*b, batch_run_impl)(*b, 1, 0.0, nullptr, nullptr, nullptr);
+                if (rc) return rc;
+                rc = BDISPATCH(*b, batch_run_impl)(*b, epochs_per_candidate, 0.0, nullptr, nullptr, &ms);
+                if (rc) return rc;
+                if (ms < best) { best = ms; bc = Choice{w, g, st}; }
+            }
+    b->widen = bc.widen;
+    b->grid_mult = bc.grid_mult;
+    b->strided = bc.strided;
+    tuned_choices()[b->signature] = bc;
+    if (choice) { choice[0] = bc.widen; choice[1] = bc.grid_mult; choice[2] = bc.strided; }
     return THETIS_OK;
 }
 
@@ -2474,13 +2580,14 @@ extern "C" thetis_status thetis_batch_destroy(thetis_batch *b) {
     (void)hipStreamSynchronize(b->stream);
     batch_drop_graph(*b);
     (void)hipFree(b->bi);
-    (void)hipFree(b->bc);
+    if (b->bc) (void)hipFree(b->bc);
     (void)hipFree(b->wg);
     (void)hipFree(b->cls);
     (void)hipFree(b->rows_wg);
     (void)hipFree(b->dual_wg);
     (void)hipFree(b->active);
     (void)hipFree(b->start);
+    (void)hipFree(b->order);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return THETIS_OK;

@@ -156,62 +156,38 @@ def ba_edges(n: int, seed: int, m_per_node: int = 3) -> np.ndarray:
 
 def regular_edges(n: int, d: int, seed: int) -> np.ndarray:
     """Random simple d-regular graph (n*d even): a random pairing of the n*d
-    stubs, then every self-loop or repeated pair is removed by a double-edge
-    swap with a uniformly chosen edge, accepted only if it creates no new
-    defect."""
+    stubs; then, while self-loops or repeated pairs remain, the stubs of the
+    defective edges together with as many uniformly chosen good edges are
+    shuffled and paired again.  Returns int64[n*d/2, 2], u < v, sorted."""
     if (n * d) % 2:
         raise ValueError("n*d must be even")
+    if d >= n:
+        raise ValueError("d must be below n")
     rng = rng_for(seed, 3)
     stubs = np.repeat(np.arange(n, dtype=np.int64), d)
     rng.shuffle(stubs)
     e = stubs.reshape(-1, 2)
-    e.sort(axis=1)
     M = e.shape[0]
-    key = e[:, 0] * n + e[:, 1]
-    from collections import Counter
-    cnt = Counter(key.tolist())
-
-    def is_bad(i):
-        return e[i, 0] == e[i, 1] or cnt[int(e[i, 0] * n + e[i, 1])] > 1
-
-    bad = [i for i in range(M) if is_bad(i)]
-    guard = 0
-    while bad:
-        guard += 1
-        if guard > 200 * M + 10000:
-            raise RuntimeError("regular graph repair did not converge")
-        i = bad.pop()
-        if not is_bad(i):
-            continue
-        j = int(rng.integers(M))
-        if j == i:
-            bad.append(i)
-            continue
-        a, b = int(e[i, 0]), int(e[i, 1])
-        c_, d_ = int(e[j, 0]), int(e[j, 1])
-        if rng.random() < 0.5:
-            c_, d_ = d_, c_
-        n1 = (min(a, c_), max(a, c_))
-        n2 = (min(b, d_), max(b, d_))
-        if n1[0] == n1[1] or n2[0] == n2[1] or n1 == n2:
-            bad.append(i)
-            continue
-        k1 = n1[0] * n + n1[1]
-        k2 = n2[0] * n + n2[1]
-        if cnt.get(k1, 0) > 0 or cnt.get(k2, 0) > 0:
-            bad.append(i)
-            continue
-        for kk in (a * n + b if a <= b else b * n + a, min(c_, d_) * n + max(c_, d_)):
-            cnt[kk] -= 1
-        cnt[k1] = cnt.get(k1, 0) + 1
-        cnt[k2] = cnt.get(k2, 0) + 1
-        e[i] = n1
-        e[j] = n2
-        if is_bad(i):
-            bad.append(i)
-        if is_bad(j):
-            bad.append(j)
-        # the removed pair (a, b) may have been a duplicate of another edge
+    for _ in range(10000):
+        e.sort(axis=1)
+        key = e[:, 0] * n + e[:, 1]
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        bad = e[:, 0] == e[:, 1]
+        rep = np.zeros(M, dtype=bool)
+        rep[order[1:][ks[1:] == ks[:-1]]] = True      # every later copy of a pair
+        bad |= rep
+        nb = int(bad.sum())
+        if nb == 0:
+            break
+        good = np.nonzero(~bad)[0]
+        extra = rng.choice(good, size=min(len(good), max(nb, 8)), replace=False)
+        idx = np.concatenate([np.nonzero(bad)[0], extra])
+        st = e[idx].reshape(-1).copy()
+        rng.shuffle(st)
+        e[idx] = st.reshape(-1, 2)
+    else:
+        raise RuntimeError("regular graph repair did not converge")
     order = np.lexsort((e[:, 1], e[:, 0]))
     return e[order]
 
@@ -354,17 +330,42 @@ def serving_trace(n_requests: int, rate: float, seed: int,
                  seed=int(seed * 1_000_003 + i)) for i in range(n_requests)]
 
 
-def serving_instance(req: dict) -> LPInstance:
-    """Materialise one serving request: VC on G(m/5, m), independent set on a
-    6-regular graph with n = m/3, or multiway cut (k=8) on a grid with about
-    m/2 pixels per side squared."""
+def serving_compact(req: dict) -> dict:
+    """The graph of one serving request, compactly: VC on G(m/5, m),
+    independent set on a 6-regular graph with n = m/3, or multiway cut
+    (k = 8) on a grid of about m edges (side sqrt(m/2)); weights drawn as in
+    the corresponding workloads."""
     m = req["edges"]
-    s = req["seed"]
-    if req["kind"] == "vc":
+    sd = req["seed"]
+    kind = req["kind"]
+    if kind == "vc":
         n = max(10, m // 5)
-        return vc_er(n, min(m, n * (n - 1) // 2), s)
-    if req["kind"] == "mis":
+        mm = min(m, n * (n - 1) // 2)
+        e = er_edges(n, mm, sd).astype(np.int32)
+        return dict(kind=kind, n=n, edges=e, w=rng_for(sd, 10).uniform(1.0, 10.0, n))
+    if kind == "mis":
         n = max(10, m // 3)
-        return mis_regular(n, 6, s)
+        if (n * 6) % 2:
+            n += 1
+        e = regular_edges(n, 6, sd).astype(np.int32)
+        return dict(kind=kind, n=n, edges=e, w=rng_for(sd, 11).uniform(1.0, 5.0, n))
     side = max(4, int(round(np.sqrt(m / 2.0))))
-    return mc_grid(side, 8, s)
+    rng = rng_for(sd, 12)
+    E = 2 * side * (side - 1)
+    d = rng.standard_normal(E)
+    terminals = rng.choice(side * side, size=8, replace=False)
+    return dict(kind="mc", side=side, w=np.exp(-d * d), terminals=terminals)
+
+
+def serving_expand(c: dict) -> LPInstance:
+    """The LP relaxation of a compact serving request."""
+    if c["kind"] == "vc":
+        return vc_lp(c["n"], c["edges"].astype(np.int64), c["w"])
+    if c["kind"] == "mis":
+        return mis_lp(c["n"], c["edges"].astype(np.int64), c["w"])
+    side = c["side"]
+    return mc_grid_lp(side * side, grid_edges(side), c["w"], c["terminals"], meta=dict(side=side))
+
+
+def serving_instance(req: dict) -> LPInstance:
+    return serving_expand(serving_compact(req))

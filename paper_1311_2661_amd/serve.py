@@ -1,0 +1,274 @@
+"""Continuous-batching LP-rounding server on one GPU.
+
+Requests (an LP relaxation of vertex cover, independent set or multiway cut)
+arrive at any time.  A pool of builder threads makes each request's host
+layout (the library call releases the GIL).  Admission is by device-memory
+budget: a built request takes a slot as soon as its workspace fits in the
+budget and its batch has a free slot; otherwise it waits (first fit in
+arrival order, never dropped).  Each batch kind -- all-ones matrices (vertex
+cover, independent set) and +-1 matrices (multiway cut) -- has one worker
+thread and one stream, so their epochs overlap on the device.  A worker
+admits waiting requests into free slots, runs `epochs_per_tick` epochs of
+every slot in one batched launch sequence, and hands back every solve that
+reached the certified gap (or its epoch cap): rounding, feasibility check,
+result, slot and memory released.  Each solve computes exactly what it
+would compute alone (the batch guarantees it), so results do not depend on
+what else is being served.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import thetis as T
+
+RULES = {"vc": T.ROUND_VC_THRESH, "mis": T.ROUND_MIS_RAND, "mc": T.ROUND_MC_CKR}
+GROUP = {"vc": "ones", "mis": "ones", "mc": "signed"}
+
+
+@dataclass
+class Result:
+    kind: str
+    sol: np.ndarray
+    cost: float
+    feasible: bool
+    n_violated: int
+    epochs: int
+    F: float
+    lp_value: float
+    gap: float
+    reached_gap: bool
+    t_arrival: float
+    t_admitted: float
+    t_done: float
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+@dataclass
+class _Req:
+    rid: int
+    kind: str
+    lp: object
+    seed: int
+    t_arrival: float
+    future: cf.Future
+    instance: Optional[T.Instance] = None
+    ws_bytes: int = 0
+    solver: Optional[T.Solver] = None
+    slot: int = -1
+    epochs: int = 0
+    t_admitted: float = 0.0
+    workspace: object = None
+
+
+def admit(waiting, free_bytes: int, free_slots: dict, hold_from: int = -1) -> list:
+    """First fit in arrival order: the indices of `waiting` (objects with
+    ``ws_bytes`` and ``kind``) that can start now.  `free_slots` maps a
+    batch group to its free slot count and is decremented.  With
+    ``hold_from >= 0`` nothing at or after that position is admitted (an
+    older request has waited too long for memory and goes first)."""
+    picked = []
+    for k, r in enumerate(waiting):
+        if 0 <= hold_from <= k:
+            break
+        g = GROUP[r.kind]
+        if r.ws_bytes <= free_bytes and free_slots.get(g, 0) > 0:
+            picked.append(k)
+            free_bytes -= r.ws_bytes
+            free_slots[g] -= 1
+    return picked
+
+
+class Server:
+    AGING_S = 0.5
+
+    def __init__(self, hbm_budget: int, gap_tol: float = 1e-4, epoch_cap: int = 200,
+                 epochs_per_tick: int = 5, slots: int = 256, precision: int = T.PREC_FP32,
+                 builders: int = 4, beta: float = 10.0, reps: int = 10):
+        import torch
+        if epoch_cap % epochs_per_tick:
+            raise ValueError("epoch_cap must be a multiple of epochs_per_tick")
+        self.budget = int(hbm_budget)
+        self.gap_tol, self.cap, self.tick = gap_tol, epoch_cap, epochs_per_tick
+        self.precision, self.beta, self.reps = precision, beta, reps
+        self.lock = threading.Lock()
+        self.cv = threading.Condition(self.lock)
+        self.used = 0
+        self.peak_used = 0
+        self.waiting = []               # built, not admitted
+        self.pending_builds = 0
+        self.closed = False
+        self.next_id = 0
+        self.builders = cf.ThreadPoolExecutor(max_workers=builders)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.groups = {}
+        for g in ("ones", "signed"):
+            stream = torch.cuda.Stream(device=self.device)
+            batch = T.Batch(capacity=slots, precision=precision, unit_values=(g == "ones"), stream=stream)
+            self.groups[g] = dict(stream=stream, batch=batch, slots=[None] * slots, thread=None)
+        for g in self.groups:
+            t = threading.Thread(target=self._worker, args=(g,), daemon=True, name=f"thetis-serve-{g}")
+            self.groups[g]["thread"] = t
+            t.start()
+
+    # -------------------------------------------------------------- client side
+    def submit(self, lp, kind: str, seed: int = 0, t_arrival: Optional[float] = None) -> cf.Future:
+        if kind not in RULES:
+            raise ValueError(f"unknown request kind {kind}")
+        fut = cf.Future()
+        with self.lock:
+            if self.closed:
+                raise RuntimeError("server closed")
+            rid = self.next_id
+            self.next_id += 1
+            self.pending_builds += 1
+        req = _Req(rid, kind, lp, seed, time.perf_counter() if t_arrival is None else t_arrival, fut)
+        self.builders.submit(self._build, req)
+        return fut
+
+    def _build(self, req: _Req):
+        try:
+            lp = req.lp() if callable(req.lp) else req.lp      # a request may carry a builder
+            req.lp = None
+            req.instance = T.Instance(lp)
+            del lp
+            p = T.thetis_params_default()
+            p.beta, p.precision, p.refresh_every, p.seed = self.beta, self.precision, self.tick, req.seed
+            req.ws_bytes = T.thetis_solver_workspace_bytes(req.instance.h, p)
+            if req.ws_bytes > self.budget:
+                raise T.ThetisError(T.EBUDGET, "request larger than the whole device-memory budget")
+        except Exception as e:     # reported to the caller, never silently dropped
+            with self.lock:
+                self.pending_builds -= 1
+                self.cv.notify_all()
+            req.future.set_exception(e)
+            return
+        with self.lock:
+            self.pending_builds -= 1
+            self.waiting.append(req)
+            self.cv.notify_all()
+
+    def close(self, wait: bool = True):
+        with self.lock:
+            self.closed = True
+            self.cv.notify_all()
+        self.builders.shutdown(wait=wait)
+        if wait:
+            for g in self.groups.values():
+                g["thread"].join()
+
+    # -------------------------------------------------------------- device side
+    def _admit_locked(self, g: str):
+        grp = self.groups[g]
+        free = [k for k, s in enumerate(grp["slots"]) if s is None]
+        mine = [r for r in self.waiting if GROUP[r.kind] == g]
+        if not mine or not free:
+            return []
+        # aging: once the oldest waiting request has waited AGING_S for
+        # memory, newer requests (of any kind) wait until it fits
+        hold = -1
+        if self.waiting:
+            old = self.waiting[0]
+            if (old.ws_bytes > self.budget - self.used and
+                    time.perf_counter() - old.t_arrival > self.AGING_S):
+                hold = 0 if GROUP[old.kind] != g else mine.index(old) + 1
+        picked = admit(mine, self.budget - self.used, {g: len(free)}, hold_from=hold)
+        out = []
+        for k in picked:
+            r = mine[k]
+            r.slot = free.pop(0)
+            self.used += r.ws_bytes
+            self.peak_used = max(self.peak_used, self.used)
+            out.append(r)
+        for r in out:
+            self.waiting.remove(r)
+        return out
+
+    def _worker(self, g: str):
+        import torch
+        grp = self.groups[g]
+        batch, stream = grp["batch"], grp["stream"]
+        with torch.cuda.device(self.device), torch.cuda.stream(stream):
+            while True:
+                with self.lock:
+                    while True:
+                        new = self._admit_locked(g)
+                        busy = any(s is not None for s in grp["slots"])
+                        if new or busy:
+                            break
+                        if self.closed and self.pending_builds == 0 and not any(
+                                GROUP[r.kind] == g for r in self.waiting):
+                            return
+                        self.cv.wait(timeout=0.05)
+                for r in new:
+                    try:
+                        r.solver = T.Solver(r.instance, beta=self.beta, precision=self.precision,
+                                            refresh_every=self.tick, seed=r.seed)
+                        r.t_admitted = time.perf_counter()
+                        grp["slots"][r.slot] = r
+                        batch.set(r.slot, r.solver)
+                    except Exception as e:
+                        self._release(g, r)
+                        r.future.set_exception(e)
+                done = batch.run(self.tick, self.gap_tol)
+                status = batch.last_status
+                for slot, r in enumerate(grp["slots"]):
+                    if r is None:
+                        continue
+                    r.epochs += int(done[slot])
+                    st = int(status[slot])
+                    if st in (1, 3) or r.epochs >= self.cap:
+                        self._finish(g, r, reached=(st == 1))
+
+    def _finish(self, g: str, r: _Req, reached: bool):
+        grp = self.groups[g]
+        try:
+            s = r.solver
+            m = s.metrics()
+            sol, cost, _ = s.round(RULES[r.kind], seed=r.seed, reps=self.reps)
+            feas, nv = s.check(RULES[r.kind])
+            res = Result(r.kind, sol, cost, feas, nv, r.epochs, m["F"], m["lp_value"], m["gap"], reached,
+                         r.t_arrival, r.t_admitted, time.perf_counter())
+            err = None
+        except Exception as e:
+            err = e
+        grp["batch"].set(r.slot, None)
+        grp["slots"][r.slot] = None
+        self._release(g, r)
+        if err is None:
+            r.future.set_result(res)
+        else:
+            r.future.set_exception(err)
+
+    def _release(self, g: str, r: _Req):
+        if r.solver is not None:
+            r.solver.close()
+            r.solver = None
+        if r.instance is not None:
+            r.instance.close()
+            r.instance = None
+        with self.lock:
+            if r.slot >= 0:
+                self.used -= r.ws_bytes
+            self.cv.notify_all()
+
+
+def solve_alone(lp, kind: str, seed: int = 0, gap_tol: float = 1e-4, epoch_cap: int = 200,
+                epochs_per_tick: int = 5, precision: int = T.PREC_FP32, beta: float = 10.0, reps: int = 10):
+    """The same solve as the server's, by itself: run to the gap (checked at
+    every refresh) or the cap, round, check."""
+    s = T.Solver(T.Instance(lp), beta=beta, precision=precision, refresh_every=epochs_per_tick, seed=seed)
+    e = s.run(epoch_cap, gap_tol=gap_tol)
+    m = s.metrics()
+    sol, cost, _ = s.round(RULES[kind], seed=seed, reps=reps)
+    feas, nv = s.check(RULES[kind])
+    s.close()
+    return dict(sol=sol, cost=cost, feasible=feas, epochs=e, F=m["F"], gap=m["gap"])

@@ -38,8 +38,8 @@ EXPORTED = [
     "thetis_run_epochs", "thetis_residual", "thetis_objective", "thetis_get_x", "thetis_set_y",
     "thetis_epoch", "thetis_round", "thetis_check_feasible", "thetis_set_timing",
     "thetis_get_timing", "thetis_epoch_traffic", "thetis_solver_destroy", "thetis_last_error",
-    "thetis_batch_create", "thetis_batch_run", "thetis_batch_autotune", "thetis_batch_configure",
-    "thetis_batch_destroy",
+    "thetis_batch_create", "thetis_batch_set", "thetis_batch_run", "thetis_batch_autotune",
+    "thetis_batch_configure", "thetis_batch_destroy",
 ]
 
 
@@ -91,10 +91,11 @@ def lib():
             "thetis_get_timing": [vp, i32, P(dbl), P(i64), P(dbl)],
             "thetis_epoch_traffic": [vp, P(dbl), P(dbl), P(i64)],
             "thetis_solver_destroy": [vp],
-            "thetis_batch_create": [i32, vp, vp, P(vp)],
-            "thetis_batch_run": [vp, i32, dbl, vp],
+            "thetis_batch_create": [i32, vp, i32, i32, vp, P(vp)],
+            "thetis_batch_set": [vp, i32, vp],
+            "thetis_batch_run": [vp, i32, dbl, vp, vp],
             "thetis_batch_autotune": [vp, i32, vp],
-            "thetis_batch_configure": [vp, i32, i32],
+            "thetis_batch_configure": [vp, i32, i32, i32],
             "thetis_batch_destroy": [vp],
         }
         for name, args in sig.items():
@@ -259,28 +260,41 @@ def thetis_solver_destroy(s):
     _check(lib().thetis_solver_destroy(s))
 
 
-def thetis_batch_create(solver_handles, stream_ptr: int = 0):
-    arr = (C.c_void_p * len(solver_handles))(*[h.value if isinstance(h, C.c_void_p) else h for h in solver_handles])
+def _hv(h):
+    if h is None:
+        return None
+    return h.value if isinstance(h, C.c_void_p) else h
+
+
+def thetis_batch_create(capacity: int, solver_handles, precision: int, unit_values: bool, stream_ptr: int = 0):
+    arr = None
+    if solver_handles is not None:
+        arr = (C.c_void_p * capacity)(*[_hv(h) for h in solver_handles])
     b = C.c_void_p()
-    _check(lib().thetis_batch_create(len(solver_handles), C.cast(arr, C.c_void_p), C.c_void_p(stream_ptr or None),
-                                     C.byref(b)))
+    _check(lib().thetis_batch_create(capacity, None if arr is None else C.cast(arr, C.c_void_p), precision,
+                                     int(unit_values), C.c_void_p(stream_ptr or None), C.byref(b)))
     return b
 
 
-def thetis_batch_run(b, count: int, max_epochs: int, gap_tol: float = 0.0) -> np.ndarray:
+def thetis_batch_set(b, slot: int, solver_handle):
+    _check(lib().thetis_batch_set(b, slot, C.c_void_p(_hv(solver_handle))))
+
+
+def thetis_batch_run(b, count: int, max_epochs: int, gap_tol: float = 0.0):
     done = np.zeros(count, np.int32)
-    _check(lib().thetis_batch_run(b, max_epochs, gap_tol, _ptr(done)))
-    return done
+    status = np.zeros(count, np.int32)
+    _check(lib().thetis_batch_run(b, max_epochs, gap_tol, _ptr(done), _ptr(status)))
+    return done, status
 
 
 def thetis_batch_autotune(b, epochs_per_candidate: int = 2):
-    ch = np.zeros(2, np.int32)
+    ch = np.zeros(3, np.int32)
     _check(lib().thetis_batch_autotune(b, epochs_per_candidate, _ptr(ch)))
-    return int(ch[0]), int(ch[1])
+    return int(ch[0]), int(ch[1]), int(ch[2])
 
 
-def thetis_batch_configure(b, widen: int, grid_mult: int):
-    _check(lib().thetis_batch_configure(b, widen, grid_mult))
+def thetis_batch_configure(b, widen: int, grid_mult: int, strided: int = 1):
+    _check(lib().thetis_batch_configure(b, widen, grid_mult, strided))
 
 
 def thetis_batch_destroy(b):
@@ -343,6 +357,10 @@ class Solver:
             self.h = thetis_solver_create(instance.h, p, self.workspace.data_ptr(), nbytes,
                                           self.stream.cuda_stream)
         self.n, self.m = instance.n, instance.m
+        bf = instance.inst.block_first_col
+        self.nblocks = 0 if bf is None else len(bf)
+        v = instance.inst.val
+        self.instance_unit_values = v is None or bool(np.all(v == 1.0))
 
     # thin forwards
     def reset(self):
@@ -383,8 +401,7 @@ class Solver:
         return thetis_epoch(self.h)
 
     def round(self, rule: int, seed: int = 0, reps: int = 1):
-        inst = self.instance.inst
-        nsol = len(inst.block_first_col) if rule == ROUND_MC_CKR else self.n
+        nsol = self.nblocks if rule == ROUND_MC_CKR else self.n
         return thetis_round(self.h, rule, seed, reps, nsol)
 
     def check(self, rule: int, sol=None):
@@ -412,21 +429,40 @@ class Solver:
 
 
 class Batch:
-    """Several solvers advanced by one launch sequence per epoch."""
+    """Slots of solvers advanced by one launch sequence per epoch.
 
-    def __init__(self, solvers, stream=None):
-        self.solvers = list(solvers)
+    Batch(solvers) fills the slots with the given solvers; Batch(capacity=k,
+    precision=..., unit_values=...) starts empty (see ``set``)."""
+
+    def __init__(self, solvers=None, stream=None, capacity=None, precision=None, unit_values=None):
+        self.solvers = list(solvers) if solvers is not None else []
+        cap = capacity if capacity is not None else len(self.solvers)
+        self.solvers += [None] * (cap - len(self.solvers))
+        first = next((s for s in self.solvers if s is not None), None)
+        if precision is None:
+            precision = first.params.precision if first is not None else PREC_FP32
+        if unit_values is None:
+            unit_values = first.instance_unit_values if first is not None else True
         sp = 0 if stream is None else stream.cuda_stream
-        self.h = thetis_batch_create([s.h for s in self.solvers], sp)
+        self.capacity = cap
+        self.h = thetis_batch_create(cap, [None if s is None else s.h for s in self.solvers], precision,
+                                     unit_values, sp)
+        self.last_status = None
+
+    def set(self, slot: int, solver):
+        thetis_batch_set(self.h, slot, None if solver is None else solver.h)
+        self.solvers[slot] = solver
 
     def run(self, max_epochs: int, gap_tol: float = 0.0) -> np.ndarray:
-        return thetis_batch_run(self.h, len(self.solvers), max_epochs, gap_tol)
+        done, status = thetis_batch_run(self.h, self.capacity, max_epochs, gap_tol)
+        self.last_status = status
+        return done
 
     def autotune(self, epochs_per_candidate: int = 2):
         return thetis_batch_autotune(self.h, epochs_per_candidate)
 
-    def configure(self, widen: int, grid_mult: int):
-        thetis_batch_configure(self.h, widen, grid_mult)
+    def configure(self, widen: int, grid_mult: int, strided: int = 1):
+        thetis_batch_configure(self.h, widen, grid_mult, strided)
 
     def close(self):
         if getattr(self, "h", None):

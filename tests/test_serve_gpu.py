@@ -1,0 +1,86 @@
+"""Serving: continuous batching with admission by device-memory budget.
+Every served result must be exactly what the same solve gives alone."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_1311_2661_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+T = S = None
+
+
+def setup_module(module):
+    global T, S
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_2661_amd import serve as SS
+    from paper_1311_2661_amd import thetis as TT
+    T, S = TT, SS
+    torch.cuda.set_device(0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def mix():
+    return [("vc", I.vc_er(400, 2000, seed=1)), ("mis", I.mis_regular(900, 6, seed=2)),
+            ("mc", I.mc_grid(side=10, k=4, seed=3)), ("vc", I.vc_ba(6000, seed=4)),
+            ("mis", I.mis_regular(300, 3, seed=5)), ("mc", I.mc_grid(side=6, k=8, seed=6)),
+            ("vc", I.vc_er(80, 300, seed=7)), ("mis", I.mis_regular(2500, 11, seed=8))]
+
+
+def test_served_results_equal_solve_alone():
+    say("case serve mix vs alone")
+    reqs = mix()
+    srv = S.Server(hbm_budget=8 << 30, epoch_cap=100, slots=16)
+    futs = []
+    for k, (kind, lp) in enumerate(reqs):
+        futs.append(srv.submit(lp, kind, seed=k))
+        time.sleep(0.002 * (k % 3))          # staggered arrivals: later ones join running batches
+    res = [f.result(timeout=120) for f in futs]
+    srv.close()
+    for k, ((kind, lp), r) in enumerate(zip(reqs, res)):
+        a = S.solve_alone(lp, kind, seed=k, epoch_cap=100)
+        say(f"  {kind}: epochs {r.epochs}/{a['epochs']} gap {r.gap:.2e} feasible {r.feasible}")
+        assert r.epochs == a["epochs"]
+        assert r.F == a["F"]
+        assert np.array_equal(r.sol, a["sol"])
+        assert r.cost == a["cost"]
+        assert r.feasible and a["feasible"]
+        assert r.latency > 0
+
+
+def test_budget_forces_waits_but_serves_everything():
+    say("case serve tight budget")
+    reqs = mix()
+    p = T.thetis_params_default()
+    p.refresh_every = 5
+    insts = [T.Instance(lp) for _, lp in reqs]       # keep the handles alive while sizing
+    sizes = [T.thetis_solver_workspace_bytes(h.h, p) for h in insts]
+    del insts
+    budget = int(max(sizes) * 1.2)           # roughly one request at a time
+    srv = S.Server(hbm_budget=budget, epoch_cap=50, slots=16)
+    futs = [srv.submit(lp, kind, seed=k) for k, (kind, lp) in enumerate(reqs)]
+    res = [f.result(timeout=120) for f in futs]
+    srv.close()
+    assert all(r.feasible for r in res)
+    assert srv.peak_used <= budget
+    assert srv.used == 0
+    # some request had to wait for memory
+    assert max(r.t_admitted - r.t_arrival for r in res) > 0
+
+
+def test_oversize_request_fails_loudly():
+    srv = S.Server(hbm_budget=1 << 20, epoch_cap=10, slots=4)
+    f = srv.submit(I.vc_ba(50000, seed=1), "vc")
+    with pytest.raises(T.ThetisError):
+        f.result(timeout=60)
+    ok = srv.submit(I.vc_er(30, 60, seed=2), "vc")
+    assert ok.result(timeout=60).feasible
+    srv.close()
