@@ -222,9 +222,11 @@ enum {
     THETIS_K_NKINDS = 4
 };
 
-/* Turns per-launch HIP-event timing on or off (events are recorded on the
- * solver's stream around every launch of thetis_run_epochs). */
-thetis_status thetis_set_timing(thetis_solver *s, int32_t enable);
+/* Per-launch HIP-event timing: with every > 0, events are recorded on the
+ * solver's stream around every launch of every `every`-th epoch of
+ * thetis_run_epochs (a sample whose average launch duration is unbiased and
+ * whose event overhead stays small); 0 turns it off. */
+thetis_status thetis_set_timing(thetis_solver *s, int32_t every);
 
 /* For kernel group `kind`, over the last thetis_run_epochs with timing on:
  * the summed device time of its launches (ms), the launch count, and the

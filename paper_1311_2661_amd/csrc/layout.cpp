@@ -3,6 +3,7 @@
 // colouring into conflict-free classes, and the per-class work plan that
 // the class-sweep kernels execute.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -184,15 +185,80 @@ static void pack(const Inst &in, const std::vector<int32_t> &sched,
     }
 }
 
+// Renumbers the rows: every row goes to its owner, the structural unit of
+// the row that comes first in the DET schedule (class by class, in plan
+// order); rows are then numbered owner by owner, so the rows a class owns
+// are one contiguous range walked in the order the class sweep visits its
+// columns.  Rows without a free structural column go last.  Returns false
+// when the order is already that one.
+static bool renumber_rows(Inst &in) {
+    const int64_t n = in.n, m = in.m;
+    std::vector<int64_t> pos(n, INT64_MAX);     // schedule position of a column's unit
+    for (const ClassPlan &cp : in.classes)
+        for (const Segment &sg : cp.segs) {
+            if (sg.kind == SEG_SLACK) continue;
+            for (int64_t q = 0; q < sg.count; ++q) {
+                const int32_t id = in.sched[sg.first + q];
+                const int64_t at = sg.first + q;
+                if (sg.kind == SEG_BLOCK)
+                    for (int32_t i = 0; i < in.k; ++i) pos[in.bfirst[id] + i] = at;
+                else
+                    pos[id] = at;
+            }
+        }
+    std::vector<std::pair<int64_t, int32_t>> key(m);
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t best = INT64_MAX;
+        for (int32_t e = in.row_ptr[i]; e < in.row_ptr[i + 1]; ++e) best = std::min(best, pos[in.col_idx[e]]);
+        key[i] = {best, (int32_t)i};
+    }
+    std::stable_sort(key.begin(), key.end());
+    bool same = true;
+    for (int64_t r = 0; r < m; ++r) same = same && key[r].second == r;
+    if (same) return false;
+    std::vector<int32_t> rp(m + 1, 0), ci(in.nnz);
+    std::vector<double> vv(in.unit_vals ? 0 : in.nnz), bb(m);
+    std::vector<int8_t> ss(m);
+    std::vector<int32_t> orig(m);
+    for (int64_t r = 0; r < m; ++r) {
+        const int32_t o = key[r].second;
+        const int32_t len = in.row_ptr[o + 1] - in.row_ptr[o];
+        rp[r + 1] = rp[r] + len;
+        std::copy(in.col_idx.begin() + in.row_ptr[o], in.col_idx.begin() + in.row_ptr[o + 1], ci.begin() + rp[r]);
+        if (!in.unit_vals) std::copy(in.val.begin() + in.row_ptr[o], in.val.begin() + in.row_ptr[o + 1], vv.begin() + rp[r]);
+        bb[r] = in.b[o];
+        ss[r] = in.sense[o];
+        orig[r] = in.row_orig.empty() ? o : in.row_orig[o];
+    }
+    in.row_ptr.swap(rp);
+    in.col_idx.swap(ci);
+    if (!in.unit_vals) in.val.swap(vv);
+    in.b.swap(bb);
+    in.sense.swap(ss);
+    in.row_orig.swap(orig);
+    return true;
+}
+
+static void plan_all(Inst &in) {
+    build_csc(in);
+    colour_units(in);
+    in.sched.clear();
+    in.classes.assign(in.nclasses, ClassPlan());
+    std::vector<std::vector<int64_t>> members(in.nclasses);
+    for (int64_t t = 0; t < in.nunits; ++t) members[in.ucolour[t]].push_back(t);
+    for (int32_t c = 0; c < in.nclasses; ++c) in.classes[c] = plan_units(in, members[c], in.sched);
+}
+
 thetis_status build_layout(Inst &in) {
     try {
-        build_csc(in);
-        colour_units(in);
-        in.sched.clear();
-        in.classes.assign(in.nclasses, ClassPlan());
-        std::vector<std::vector<int64_t>> members(in.nclasses);
-        for (int64_t t = 0; t < in.nunits; ++t) members[in.ucolour[t]].push_back(t);
-        for (int32_t c = 0; c < in.nclasses; ++c) in.classes[c] = plan_units(in, members[c], in.sched);
+        if (in.row_orig.empty()) {
+            in.row_orig.resize(in.m);
+            for (int64_t i = 0; i < in.m; ++i) in.row_orig[i] = (int32_t)i;
+        }
+        plan_all(in);
+        // the colouring does not depend on the row order, so planning again
+        // after the renumbering gives the same classes
+        if (renumber_rows(in)) plan_all(in);
         in.async_sched.clear();
         std::vector<int64_t> st, sl;
         for (int64_t t = 0; t < in.nunits; ++t) (in.ukind[t] == 2 ? sl : st).push_back(t);

@@ -977,8 +977,10 @@ __global__ __launch_bounds__(kWG) void k_set_start(Dev<P> a) {
     if (t < a.m) a.s[t] = 0;
 }
 
+// y arrives and leaves in the caller's row order; row_orig[r] is the
+// caller's index of internal row r
 template <class P>
-__global__ __launch_bounds__(kWG) void k_load_y(Dev<P> a, const double *y) {
+__global__ __launch_bounds__(kWG) void k_load_y(Dev<P> a, const double *y, const int32_t *row_orig) {
     const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
     using R = typename P::R;
     if (t < a.n) {
@@ -989,17 +991,17 @@ __global__ __launch_bounds__(kWG) void k_load_y(Dev<P> a, const double *y) {
         a.x[t] = xenc<typename P::X, double>(v);
     }
     if (t < a.m) {
-        double v = y[a.n + t];
+        double v = y[a.n + row_orig[t]];
         if (v < 0.0 || a.sense[t] == 0) v = 0.0;
         a.s[t] = (R)v;
     }
 }
 
 template <class P>
-__global__ __launch_bounds__(kWG) void k_store_y(Dev<P> a, double *x, double *s) {
+__global__ __launch_bounds__(kWG) void k_store_y(Dev<P> a, double *x, double *s, const int32_t *row_orig) {
     const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (t < a.n) x[t] = (double)xval(a.x[t]);
-    if (s && t < a.m) s[t] = (double)a.s[t];
+    if (s && t < a.m) s[row_orig[t]] = (double)a.s[t];
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -1047,15 +1049,16 @@ struct thetis_solver {
         *norm2, *ybar, *ubar, *bfirst, *fixed, *col_block, *LB, *x, *s, *r, *udual, *sched,
         *async_sched, *pk_det_ptr, *pk_det_row, *pk_det_val, *pk_async_ptr, *pk_async_row,
         *pk_async_val, *rpart, *cpart, *metrics, *sol, *best, *drop, *ckr_order, *thr, *costbuf,
-        *chkbuf, *ystage;
+        *chkbuf, *ystage, *row_orig;
     int64_t nwg_rows = 0, nwg_cols = 0;
     int64_t epoch = 0;
     bool metrics_fresh = false;
     double mt[MT_NSLOT] = {0};
     bool have_round = false;
     int32_t last_rule = 0;
-    // timing
-    bool timing = false;
+    // timing: HIP events around every launch of every `timing`-th epoch
+    int32_t timing = 0;
+    bool timing_now = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     // per kernel group: (start, stop) event indices and the algorithmic
@@ -1172,6 +1175,7 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.costbuf = cv.take(8 * 4);
     S.chkbuf = cv.take(8 * 4);
     S.ystage = cv.take(8 * std::max<int64_t>(n + m, 1));
+    S.row_orig = cv.take(4 * std::max<int64_t>(m, 1));
     *total = cv.off + 256;
 }
 
@@ -1243,13 +1247,13 @@ struct TimedScope {
     double bytes;
     int i0 = -1;
     TimedScope(thetis_solver &s, int k, double b) : S(s), kind(k), bytes(b) {
-        if (S.timing) {
+        if (S.timing && S.timing_now) {
             hipEvent_t e = next_event(S, &i0);
             if (e) (void)hipEventRecord(e, S.stream);
         }
     }
     ~TimedScope() {
-        if (S.timing && i0 >= 0) {
+        if (i0 >= 0) {
             int i1;
             hipEvent_t e = next_event(S, &i1);
             if (e) {
@@ -1335,6 +1339,7 @@ thetis_status run_epochs_impl(thetis_solver &S, int32_t max_epochs, double gap_t
     int32_t e = 0;
     thetis_status st = THETIS_OK;
     for (; e < max_epochs; ++e) {
+        S.timing_now = S.timing > 0 && (S.epoch % S.timing) == 0;
         if (S.p.schedule == THETIS_SCHED_DET) {
             class_order(S.nclasses, S.p.seed, S.epoch, order.data());
             for (int32_t q = 0; q < S.nclasses; ++q) launch_class<P>(S, a, S.det[order[q]], dsc);
@@ -1344,6 +1349,7 @@ thetis_status run_epochs_impl(thetis_solver &S, int32_t max_epochs, double gap_t
         S.epoch++;
         S.metrics_fresh = false;
         if (S.p.refresh_every > 0 && S.epoch % S.p.refresh_every == 0) {
+            S.timing_now = S.timing > 0 && (S.epoch / S.p.refresh_every) % S.timing == 0;
             st = refresh<P>(S, true, gap_tol > 0.0);
             if (st) break;
             if (gap_tol > 0.0) {
@@ -1389,7 +1395,8 @@ thetis_status set_y_impl(thetis_solver &S, const double *y) {
     HIP_TRY(hipMemcpyAsync(S.ystage, y, 8 * (S.n + S.m), hipMemcpyHostToDevice, S.stream));
     Dev<P> a = make_dev<P>(S);
     const int64_t N = std::max<int64_t>(std::max(S.n, S.m), 1);
-    hipLaunchKernelGGL((k_load_y<P>), dim3(cdiv(N, kWG)), dim3(kWG), 0, S.stream, a, (const double *)S.ystage);
+    hipLaunchKernelGGL((k_load_y<P>), dim3(cdiv(N, kWG)), dim3(kWG), 0, S.stream, a, (const double *)S.ystage,
+                       (const int32_t *)S.row_orig);
     HIP_TRY(hipGetLastError());
     thetis_status st = refresh<P>(S, true, false);
     S.have_round = false;
@@ -1403,7 +1410,8 @@ thetis_status get_x_impl(thetis_solver &S, double *x, double *s) {
     Dev<P> a = make_dev<P>(S);
     double *dx = (double *)S.ystage, *ds = dx + S.n;
     const int64_t N = std::max<int64_t>(std::max(S.n, S.m), 1);
-    hipLaunchKernelGGL((k_store_y<P>), dim3(cdiv(N, kWG)), dim3(kWG), 0, S.stream, a, dx, s ? ds : nullptr);
+    hipLaunchKernelGGL((k_store_y<P>), dim3(cdiv(N, kWG)), dim3(kWG), 0, S.stream, a, dx, s ? ds : nullptr,
+                       (const int32_t *)S.row_orig);
     HIP_TRY(hipGetLastError());
     if (x) HIP_TRY(hipMemcpyAsync(x, dx, 8 * S.n, hipMemcpyDeviceToHost, S.stream));
     if (s) HIP_TRY(hipMemcpyAsync(s, ds, 8 * S.m, hipMemcpyDeviceToHost, S.stream));
@@ -1759,6 +1767,7 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     UP(upload(S, S.b, in.b));
     UP(upload(S, S.sense, in.sense));
     UP(upload(S, S.c, in.c));
+    UP(upload(S, S.row_orig, in.row_orig));
     UP(upload(S, S.sched, in.sched));
     UP(upload(S, S.async_sched, in.async_sched));
     UP(upload(S, S.pk_det_ptr, in.pk_det.ptr));
@@ -1780,11 +1789,15 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
         UP(upload_real(S, S.LB, LB));
     }
     if (S.has_ybar) {
-        std::vector<double> yb(p->ybar, p->ybar + in.n + in.m);
+        // the slack part of ybar follows the internal row order
+        std::vector<double> yb(in.n + in.m);
+        for (int64_t j = 0; j < in.n; ++j) yb[j] = p->ybar[j];
+        for (int64_t r = 0; r < in.m; ++r) yb[in.n + r] = p->ybar[in.n + in.row_orig[r]];
         UP(upload_real(S, S.ybar, yb));
     }
     if (S.has_ubar) {
-        std::vector<double> ub(p->ubar, p->ubar + in.m);
+        std::vector<double> ub(in.m);
+        for (int64_t r = 0; r < in.m; ++r) ub[r] = p->ubar[in.row_orig[r]];
         UP(upload(S, S.ubar, ub));
         // ctil = c - A^T ubar over the structural columns, -sign * ubar_i for slacks
         std::vector<double> ct(in.n + in.m, 0.0);
@@ -1913,7 +1926,8 @@ extern "C" thetis_status thetis_check_feasible(thetis_solver *s, int32_t rule, c
 extern "C" thetis_status thetis_set_timing(thetis_solver *s, int32_t enable) {
     clear_error();
     if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    s->timing = enable != 0;
+    if (enable < 0) return fail(THETIS_EINVAL, "timing period must be >= 0");
+    s->timing = enable;
     return THETIS_OK;
 }
 

@@ -86,6 +86,10 @@ struct Inst {
     bool planned = false;
     bool has_solver = false;
     int64_t max_col_degree = 0;
+    // Internal row order: rows are renumbered so that every row's owner (its
+    // first column in DET schedule order) sees its rows contiguously, class
+    // by class.  row_orig[r] = caller's index of internal row r.
+    std::vector<int32_t> row_orig;
 };
 
 thetis_status build_layout(Inst &in);   // CSC, units, colouring, plans

@@ -235,8 +235,8 @@ def thetis_check_feasible(s, rule: int, sol=None):
     return bool(f.value), nv.value
 
 
-def thetis_set_timing(s, enable: bool):
-    _check(lib().thetis_set_timing(s, int(enable)))
+def thetis_set_timing(s, every: int):
+    _check(lib().thetis_set_timing(s, int(every)))
 
 
 K_SWEEP_COLUMNS, K_SWEEP_BLOCK, K_SWEEP_SLACK, K_REFRESH = 0, 1, 2, 3
@@ -407,8 +407,9 @@ class Solver:
     def check(self, rule: int, sol=None):
         return thetis_check_feasible(self.h, rule, sol)
 
-    def set_timing(self, on: bool = True):
-        thetis_set_timing(self.h, on)
+    def set_timing(self, every: int = 1):
+        """HIP-event timing of every launch of every `every`-th epoch (0: off)."""
+        thetis_set_timing(self.h, int(every))
 
     def timing(self) -> dict:
         return {KERNEL_NAMES[k]: thetis_get_timing(self.h, k) for k in KERNEL_NAMES}
