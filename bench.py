@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "coord updates/s + HBM GB/s; batched solves/s and p99 latency at 1e-4 LP gap"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sweep_vc_ba2m.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1311_2661_amd", "csrc", "thetis.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1311_2661_amd", "csrc", f) for f in ("thetis.hip", "layout.cpp")]
 
 
 def log(msg):
@@ -33,8 +33,12 @@ def log(msg):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources that decide the kernel and the layout it walks."""
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def counter_traffic(workload: str):
@@ -48,6 +52,41 @@ def counter_traffic(workload: str):
     if t.get("kernel_source_sha256_16") != kernel_hash() or t.get("workload") != workload:
         return None
     return t.get("hbm_bytes_per_launch")
+
+
+def summarize_counters(fetch_csv: str, write_csv: str, workload: str, copy_mib: int, command: str):
+    """Writes the traffic summary of the dominant kernel from two rocprofv3
+    counter runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch), each scaled by what the same counter reads for the plain
+    device copy of `copy_mib` MiB the runs also perform."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        sweep = [float(r["Counter_Value"]) for r in rows
+                 if "k_sweep<" in r["Kernel_Name"] and "k_sweep_" not in r["Kernel_Name"]]
+        copies = sorted(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
+                        or "elementwise" in r["Kernel_Name"])
+        return sweep, copies
+
+    expect_kib = copy_mib * 1024.0
+    f_sweep, f_copy = per_kernel(fetch_csv, "FETCH_SIZE")
+    w_sweep, w_copy = per_kernel(write_csv, "WRITE_SIZE")
+    # the calibration copies are the dispatches that read (write) about copy_mib
+    f_cal = [v for v in f_copy if 0.5 * expect_kib < v < 2.0 * expect_kib]
+    w_cal = [v for v in w_copy if 0.5 * expect_kib < v < 2.0 * expect_kib]
+    kf = expect_kib / statistics.median(f_cal)
+    kw = expect_kib / statistics.median(w_cal)
+    fetch = statistics.mean(f_sweep) * kf
+    write = statistics.mean(w_sweep) * kw
+    out = dict(kernel="k_sweep", workload=workload, kernel_source_sha256_16=kernel_hash(),
+               fetch_kib_per_launch=statistics.mean(f_sweep), write_kib_per_launch=statistics.mean(w_sweep),
+               launches=len(f_sweep), fetch_scale=kf, write_scale=kw,
+               hbm_bytes_per_launch=1024.0 * (fetch + write), command=command)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def cpu_baseline(inst, epochs_cap: int, budget_s: float, seed: int):
@@ -308,6 +347,8 @@ def main():
                     help="time budget of the oracle baseline (0 skips it)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the k_sweep traffic summary from two rocprofv3 counter runs and exit")
     ap.add_argument("--workload", choices=["vc_ba", "mis_batch", "serve"], default="vc_ba")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
@@ -320,6 +361,13 @@ def main():
     ap.add_argument("--cap", type=int, default=200, help="mis_batch: epoch cap")
     ap.add_argument("--baseline-sample", type=int, default=32, help="mis_batch: instances solved alone")
     args = ap.parse_args()
+
+    if args.summarize_counters:
+        wl = f"vc_ba_n{args.n}_m3_beta10_fp32_refresh5_{args.epochs}ep_{args.schedule}"
+        cmd = ("cd /tmp && rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <out> -o run -- "
+               f"python3 <repo>/bench.py --steps 1 --warmup 0 --epochs {args.epochs} --cpu-baseline-seconds 0 "
+               f"--copy-calibration-mb {args.copy_calibration_mb or 256}")
+        return summarize_counters(*args.summarize_counters, wl, args.copy_calibration_mb or 256, cmd)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
