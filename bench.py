@@ -227,6 +227,99 @@ def mis_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def mc_grid(args):
+    """Multiway cut on the 1024 x 1024 4-connected grid, k = 8 terminals at
+    seeded random pixels, edge weights exp(-d^2), d ~ N(0,1); x blocks on the
+    simplex (block coordinate steps), z and slacks as plain coordinates;
+    FP32, 200 epochs, region-growing rounding (10 repetitions, fixed seed)."""
+    import torch
+    from paper_1311_2661_amd import instances as I
+    from paper_1311_2661_amd import thetis as T
+    T.lib()
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    side = args.side
+    inst = I.mc_grid(side=side, k=8, seed=args.seed)
+    log(f"grid {side}x{side}: {inst.n} columns, {inst.m} rows, {inst.nnz} entries ({time.perf_counter() - t0:.1f} s)")
+    t0 = time.perf_counter()
+    h = T.Instance(inst)
+    s = T.Solver(h, beta=10.0, precision=T.PREC_FP32, refresh_every=5, seed=args.seed)
+    log(f"layout + upload: {time.perf_counter() - t0:.1f} s, {h.classes()[0]} colour classes")
+    tr = s.traffic()
+    ep = args.epochs
+
+    def step():
+        s.reset()
+        s.run(ep)
+        sol, cost, aux = s.round(T.ROUND_MC_CKR, seed=args.seed, reps=10)
+        return sol, cost, s.check(T.ROUND_MC_CKR)
+
+    for _ in range(args.warmup):
+        step()
+    s.set_timing(10)
+    acc = {k: dict(ms=0.0, launches=0, alg_bytes=0.0) for k in T.KERNEL_NAMES.values()}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sol, cost, chk = step()
+        for name, v in s.timing().items():
+            for f in ("ms", "launches", "alg_bytes"):
+                acc[name][f] += v[f]
+        log(f"step {k} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s.set_timing(0)
+    m = s.metrics()
+    # properties at full size: blocks on the simplex, terminals fixed, the
+    # labelling valid, and its cut weight recomputed from the edge list
+    x = s.x
+    nv = side * side
+    X = x[: nv * 8].reshape(nv, 8)
+    e = inst.meta["edges"]
+    cut = float(inst.meta["edge_w"][sol[e[:, 0]] != sol[e[:, 1]]].sum())
+    props = dict(simplex_err=float(np.abs(X.sum(axis=1) - 1).max()), min_x=float(X.min()),
+                 terminals_ok=bool(np.array_equal(np.argmax(X[inst.meta["terminals"]], axis=1), np.arange(8))),
+                 labels_feasible=bool(chk[0]), cut_recomputed=cut, cut_reported=cost,
+                 dual_below_F=bool(m["dual_bound"] <= m["F"]))
+    log(f"properties: {props}")
+    g = acc["k_sweep_block"]
+    avg_ms = g["ms"] / max(g["launches"], 1)
+    avg_bytes = g["alg_bytes"] / max(g["launches"], 1)
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    upd = tr["updates_per_epoch"]
+    out = {
+        "metric": METRIC, "value": args.steps * ep * upd / elapsed, "unit": "coord updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"mc_grid_{side}x{side}_k8_beta10_fp32_refresh5_{ep}ep_det", "columns": inst.n,
+                   "rows": inst.m, "entries": inst.nnz, "coordinates_per_epoch": upd, "seed": args.seed},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep_block", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": avg_bytes, "avg_launch_us": 1e3 * avg_ms},
+        "kernels": {name: dict(ms_total=round(v["ms"], 4), launches=v["launches"],
+                               avg_us=round(1e3 * v["ms"] / max(v["launches"], 1), 3),
+                               alg_gbs=round(v["alg_bytes"] / max(v["ms"], 1e-9) / 1e6, 1))
+                    for name, v in acc.items() if v["launches"]},
+        "solution": {"F": m["F"], "lp_value": m["lp_value"], "gap": m["gap"], "cut": cost, **props},
+    }
+    if args.cpu_baseline_seconds > 0:
+        from oracle import oracle as O
+        lp = O.OracleLP(inst)
+        o = O.OracleSolver(lp, beta=10.0, seed=args.seed)
+        t0 = time.perf_counter()
+        o.run(1)
+        t1 = time.perf_counter() - t0
+        more = int(max(0, min(ep - 1, args.cpu_baseline_seconds / max(t1, 1e-9) - 1)))
+        t0 = time.perf_counter()
+        if more:
+            o.run(more)
+        tt = t1 + time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=(1 + more) * upd / tt, unit="coord updates/s", cores=1, kind="oracle",
+                                   sample=f"{1 + more} of the {ep} epochs of the same instance, DET class order, "
+                                          f"serial FP64 C, {tt:.1f} s, setup excluded")
+    print(json.dumps(out), flush=True)
+
+
 def _serve_compact(req):
     from paper_1311_2661_amd import instances as I
     return I.serving_compact(req)
@@ -349,7 +442,8 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the k_sweep traffic summary from two rocprofv3 counter runs and exit")
-    ap.add_argument("--workload", choices=["vc_ba", "mis_batch", "serve"], default="vc_ba")
+    ap.add_argument("--workload", choices=["vc_ba", "mc_grid", "mis_batch", "serve"], default="vc_ba")
+    ap.add_argument("--side", type=int, default=1024, help="mc_grid: grid side")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serve: device-memory budget (0: half of free)")
@@ -379,6 +473,10 @@ def main():
         return mis_batch(args)
     if args.workload == "serve":
         return serve(args)
+    if args.workload == "mc_grid":
+        if args.epochs == 100:
+            args.epochs = 200
+        return mc_grid(args)
 
     import numpy as np
     import torch
