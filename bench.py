@@ -165,7 +165,7 @@ def mis_batch(args):
     log(f"layout + upload of {count} solvers: {time.perf_counter() - t0:.1f} s")
     b = T.Batch(solvers)
     choice = b.autotune(epochs_per_candidate=2)
-    log(f"autotuned: widen {choice[0]}, grid x{choice[1]}, strided {choice[2]}")
+    log(f"autotuned: widen {choice[0]}, grid x{choice[1]}, strided {choice[2]}, columns per group {choice[3]}")
     upd_total = []
     for w in range(args.warmup):
         for s in solvers:

@@ -178,6 +178,7 @@ struct LaunchPlan {
     int64_t first[kGridKinds];          // offset of the segment in its schedule
     int64_t count[kGridKinds];          // units of the segment
     int32_t lanes[kGridKinds];          // lanes per column of the lane-group ranges
+    int32_t cols[kGridKinds];           // columns per lane group (sweep plans)
     int64_t hub_wg;                     // hub workgroups, a multiple of 8
     int64_t nwg;
 };
@@ -210,43 +211,57 @@ __device__ __forceinline__ typename P::R curvature(const Dev<P> &a, int64_t j, i
     return a.beta * (VALS ? a.norm2[j] : (R)d) + a.rho;
 }
 
-// one plain column per group of G lanes
-template <class P, bool VALS, int G>
+// Plain columns on groups of G lanes.  A column of a lane-group range has
+// at most G entries (its degree bucket), so lane l holds entry l.  Each group
+// takes C columns of the range (workgroup-interleaved) and issues the loads
+// of all C together, so every lane keeps C residual loads in flight and a
+// workgroup covers C times the columns; the sums, steps and stores of each
+// column are exactly those of a lone column, so the results do not depend
+// on C.
+
+template <class P, bool VALS, int G, int C>
 __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typename P::R> &sc,
                                             int64_t first, int64_t count, int64_t lwg) {
     using R = typename P::R;
+    constexpr int NG = kWG / G;
     const int lane = threadIdx.x & (G - 1);
-    const int64_t u = lwg * (kWG / G) + (threadIdx.x / G);
-    if (u >= count) return;           // the whole group leaves together
-    const int64_t q = first + u;
-    const int32_t j = sc.ids[q];
-    const int32_t e0 = sc.ptr[q], e1 = sc.ptr[q + 1];
-    R acc = R(0), r0 = R(0), v0 = R(1);
-    int32_t row0 = -1;
-    for (int32_t e = e0 + lane; e < e1; e += G) {
-        const int32_t row = sc.row[e];
-        const R rv = a.r[row];
-        const R v = VALS ? sc.val[e] : R(1);
-        if (row0 < 0) { row0 = row; r0 = rv; v0 = v; }
-        acc += VALS ? v * rv : rv;
-    }
-    acc = group_sum<G>(acc);
-    const R y = (R)xval(a.x[j]);
-    const R g = gradient(a, j, y, acc);
-    const R yn = stored_value<P>(coord_step(y, g, curvature<P, VALS>(a, j, e1 - e0), a.gamma, col_bound(a, j)));
-    const R d = yn - y;
-    if (lane == 0) store_x<P>(a.x + j, yn);
-    if (d != R(0)) {
-        bool first_e = true;
-        for (int32_t e = e0 + lane; e < e1; e += G) {
-            if (first_e) {
-                r_add(a.r + row0, r0, VALS ? d * v0 : d, a.async_mode);
-                first_e = false;
-            } else {
-                R *p = a.r + sc.row[e];
-                r_add(p, a.async_mode ? R(0) : *p, VALS ? d * sc.val[e] : d, a.async_mode);
+    const int64_t u0 = lwg * (NG * C) + threadIdx.x / G;
+    int32_t j[C], row[C];
+    R v[C], rv[C], y[C], cj[C], L[C], U[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int64_t u = u0 + c * NG;
+        j[c] = -1;
+        row[c] = -1;
+        v[c] = R(1);
+        if (u < count) {
+            const int64_t q = first + u;
+            j[c] = sc.ids[q];
+            const int32_t e0 = sc.ptr[q], d = sc.ptr[q + 1] - e0;
+            if (lane < d) {
+                row[c] = sc.row[e0 + lane];
+                if (VALS) v[c] = sc.val[e0 + lane];
             }
+            y[c] = (R)xval(a.x[j[c]]);
+            cj[c] = a.ctil ? a.ctil[j[c]] : (R)a.c[j[c]];
+            L[c] = curvature<P, VALS>(a, j[c], d);
+            U[c] = col_bound(a, j[c]);
         }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) rv[c] = row[c] >= 0 ? a.r[row[c]] : R(0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        R acc = R(0);
+        if (row[c] >= 0) acc += VALS ? v[c] * rv[c] : rv[c];
+        acc = group_sum<G>(acc);          // every lane of the wave takes part
+        if (j[c] < 0) continue;
+        R g = cj[c] + a.beta * acc;
+        if (a.prox_on) g += a.rho * (y[c] - (a.ybar ? a.ybar[j[c]] : R(0)));
+        const R yn = stored_value<P>(coord_step(y[c], g, L[c], a.gamma, U[c]));
+        const R d = yn - y[c];
+        if (lane == 0) store_x<P>(a.x + j[c], yn);
+        if (d != R(0) && row[c] >= 0) r_add(a.r + row[c], rv[c], VALS ? d * v[c] : d, a.async_mode);
     }
 }
 
@@ -385,6 +400,29 @@ __device__ __forceinline__ void sweep_slack(const Dev<P> &a, int64_t i) {
     }
 }
 
+template <class P, bool VALS, int G>
+__device__ __forceinline__ void sweep_groups_c(const Dev<P> &a, const Sched<typename P::R> &sc, int cols,
+                                               int64_t first, int64_t count, int64_t lwg) {
+    switch (cols) {
+        case 1: sweep_group<P, VALS, G, 1>(a, sc, first, count, lwg); break;
+        case 2: sweep_group<P, VALS, G, 2>(a, sc, first, count, lwg); break;
+        case 4: sweep_group<P, VALS, G, 4>(a, sc, first, count, lwg); break;
+        default: break;
+    }
+}
+template <class P, bool VALS>
+__device__ __forceinline__ void sweep_groups(const Dev<P> &a, const Sched<typename P::R> &sc, int lanes, int cols,
+                                             int64_t first, int64_t count, int64_t lwg) {
+    switch (lanes) {
+        case 4: sweep_groups_c<P, VALS, 4>(a, sc, cols, first, count, lwg); break;
+        case 8: sweep_groups_c<P, VALS, 8>(a, sc, cols, first, count, lwg); break;
+        case 16: sweep_groups_c<P, VALS, 16>(a, sc, cols, first, count, lwg); break;
+        case 32: sweep_groups_c<P, VALS, 32>(a, sc, cols, first, count, lwg); break;
+        case 64: sweep_groups_c<P, VALS, 64>(a, sc, cols, first, count, lwg); break;
+        default: break;
+    }
+}
+
 // One class (DET) or one whole epoch part (ASYNC) in a single launch.
 // logical workgroup L of a column plan.  A lane-group range may run wider
 // groups than its degree bound (the tuner's choice): the extra lanes hold
@@ -399,14 +437,7 @@ __device__ __forceinline__ void sweep_item(const Dev<P> &a, const Sched<typename
         if (local < count) sweep_hub<P, VALS>(a, sc, first + local, st_r, st_row, red);
         return;
     }
-    switch (pl.lanes[p]) {
-        case 4: sweep_group<P, VALS, 4>(a, sc, first, count, local); break;
-        case 8: sweep_group<P, VALS, 8>(a, sc, first, count, local); break;
-        case 16: sweep_group<P, VALS, 16>(a, sc, first, count, local); break;
-        case 32: sweep_group<P, VALS, 32>(a, sc, first, count, local); break;
-        case 64: sweep_group<P, VALS, 64>(a, sc, first, count, local); break;
-        default: break;
-    }
+    sweep_groups<P, VALS>(a, sc, pl.lanes[p], pl.cols[p], first, count, local);
 }
 
 // The plain columns of one class (DET) or of a whole epoch (ASYNC) in one
@@ -1095,11 +1126,15 @@ int64_t units_per_wg(int kind, bool dual) {
 
 // Workgroup ranges of one fused launch over the given segments (at most one
 // segment per kind) plus, for the dual pass, ncolterms per-column threads.
-LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolterms, int widen = 1) {
+// widen multiplies the lanes per column, cols sets the columns per lane
+// group of the lane-group ranges (sweep plans only; at most 2 on 64 lanes).
+LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolterms, int widen = 1,
+                     int cols = 1) {
     LaunchPlan pl{};
     for (int p = 0; p < kGridKinds; ++p) {
         const int kind = grid_kind(p);
         pl.lanes[p] = kind < kGroupKinds ? std::min(64, (4 << kind) * widen) : 0;
+        pl.cols[p] = kind < kGroupKinds && !dual ? (pl.lanes[p] == 64 ? std::min(cols, 2) : cols) : 1;
     }
     for (const Segment &sg : segs) {
         const int p = grid_pos(sg.kind);
@@ -1111,7 +1146,8 @@ LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolte
     for (int p = 0; p < kGridKinds; ++p) {
         pl.wg_start[p] = wg;
         const int kind = grid_kind(p);
-        const int64_t upw = kind < kGroupKinds ? kWG / pl.lanes[p] : (kind == SEG_NKIND ? kWG : units_per_wg(kind, dual));
+        const int64_t upw = kind < kGroupKinds ? kWG / pl.lanes[p] * pl.cols[p]
+                                               : (kind == SEG_NKIND ? kWG : units_per_wg(kind, dual));
         int64_t w = pl.count[p] ? cdiv(pl.count[p], upw) : 0;
         if (kind == SEG_HUB) { w = cdiv(w, 8) * 8; pl.hub_wg = w; }
         wg += w;
@@ -2223,7 +2259,7 @@ struct thetis_batch {
     std::vector<thetis_solver *> solvers;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    int widen = 1, grid_mult = 2, strided = 1;
+    int widen = 1, grid_mult = 2, strided = 1, cols = 1;
     int64_t resident_wg = 2048;
     // device
     void *bi = nullptr, *bc = nullptr;
@@ -2236,14 +2272,14 @@ struct thetis_batch {
     // captured epoch
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int captured_widen = 0, captured_grid = 0, captured_strided = -1;
+    int captured_widen = 0, captured_grid = 0, captured_strided = -1, captured_cols = 0;
     uint64_t signature = 0;
 };
 
 namespace {
 
 struct Choice {
-    int widen, grid_mult, strided;
+    int widen, grid_mult, strided, cols;
 };
 std::map<uint64_t, Choice> &tuned_choices() {
     static std::map<uint64_t, Choice> m;
@@ -2294,7 +2330,7 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
         I.reason = 0;
         for (const ClassLaunch &cl : S.det) {
             BClass C{};
-            C.cols = cl.has_cols ? make_plan(cl.col_segs, false, 0, B.widen) : LaunchPlan{};
+            C.cols = cl.has_cols ? make_plan(cl.col_segs, false, 0, B.widen, B.cols) : LaunchPlan{};
             C.wg_cols = cl.has_cols ? C.cols.nwg : 0;
             C.block_first = cl.block_first;
             C.block_count = cl.block_count;
@@ -2360,6 +2396,7 @@ thetis_status batch_capture(thetis_batch &B) {
     B.captured_widen = B.widen;
     B.captured_grid = B.grid_mult;
     B.captured_strided = B.strided;
+    B.captured_cols = B.cols;
     return THETIS_OK;
 }
 
@@ -2369,7 +2406,8 @@ thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol
     for (thetis_solver *S : B.solvers) if (S) HIP_TRY(hipStreamSynchronize(S->stream));
     thetis_status st = batch_upload<P>(B, max_epochs, gap_tol);
     if (st) return st;
-    if (!B.exec || B.captured_widen != B.widen || B.captured_grid != B.grid_mult || B.captured_strided != B.strided) {
+    if (!B.exec || B.captured_widen != B.widen || B.captured_grid != B.grid_mult || B.captured_strided != B.strided ||
+        B.captured_cols != B.cols) {
         st = batch_capture<P>(B);
         if (st) return st;
     }
@@ -2459,6 +2497,7 @@ void batch_signature(thetis_batch &B) {
         B.widen = it->second.widen;
         B.grid_mult = it->second.grid_mult;
         B.strided = it->second.strided;
+        B.cols = it->second.cols;
     }
 }
 }  // namespace
@@ -2546,46 +2585,68 @@ extern "C" thetis_status thetis_batch_run(thetis_batch *b, int32_t max_epochs, d
     return BDISPATCH(*b, batch_run_impl)(*b, max_epochs, gap_tol, done, status, nullptr);
 }
 
-extern "C" thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult, int32_t strided) {
+extern "C" thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult, int32_t strided,
+                                                int32_t cols) {
     clear_error();
     if (!b) return fail(THETIS_EINVAL, "batch is NULL");
     if (widen != 1 && widen != 2 && widen != 4) return fail(THETIS_EINVAL, "widen must be 1, 2 or 4");
     if (grid_mult != 1 && grid_mult != 2 && grid_mult != 4 && grid_mult != 8)
         return fail(THETIS_EINVAL, "grid multiplier must be 1, 2, 4 or 8");
     if (strided != 0 && strided != 1) return fail(THETIS_EINVAL, "strided must be 0 or 1");
+    if (cols != 1 && cols != 2 && cols != 4) return fail(THETIS_EINVAL, "cols must be 1, 2 or 4");
     b->widen = widen;
     b->grid_mult = grid_mult;
     b->strided = strided;
+    b->cols = cols;
     return THETIS_OK;
 }
+
+namespace {
+// one timed candidate: the first run after a capture includes the capture,
+// so a second run is timed
+thetis_status tune_time(thetis_batch &B, const Choice &c, int32_t epochs, double *ms) {
+    B.widen = c.widen;
+    B.grid_mult = c.grid_mult;
+    B.strided = c.strided;
+    B.cols = c.cols;
+    thetis_status rc = BDISPATCH(B, batch_run_impl)(B, 1, 0.0, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    return BDISPATCH(B, batch_run_impl)(B, epochs, 0.0, nullptr, nullptr, ms);
+}
+}  // namespace
 
 extern "C" thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_per_candidate, int32_t *choice) {
     clear_error();
     if (!b) return fail(THETIS_EINVAL, "batch is NULL");
     if (epochs_per_candidate < 1) return fail(THETIS_EINVAL, "epochs_per_candidate < 1");
-    const int widens[2] = {1, 2};
-    const int grids[3] = {1, 2, 4};
-    double best = 1e300;
-    Choice bc{b->widen, b->grid_mult, b->strided};
+    // two stages: the per-column shape (lanes and columns per group) at the
+    // current grid, then the grid size and walk with the best shape
+    const Choice shapes[4] = {{1, 0, 0, 1}, {2, 0, 0, 1}, {1, 0, 0, 2}, {1, 0, 0, 4}};
+    Choice best{b->widen, b->grid_mult, b->strided, b->cols};
+    double best_ms = 1e300;
+    for (const Choice &sh : shapes) {
+        const Choice c{sh.widen, best.grid_mult, best.strided, sh.cols};
+        double ms = 0;
+        thetis_status rc = tune_time(*b, c, epochs_per_candidate, &ms);
+        if (rc) return rc;
+        if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+    const Choice base = best;
     for (int st = 0; st < 2; ++st)
-        for (int w : widens)
-            for (int g : grids) {
-                b->widen = w;
-                b->grid_mult = g;
-                b->strided = st;
-                // the first run after a capture includes the capture; time a second run
-                double ms = 0;
-                thetis_status rc = BDISPATCH(*b, batch_run_impl)(*b, 1, 0.0, nullptr, nullptr, nullptr);
-                if (rc) return rc;
-                rc = BDISPATCH(*b, batch_run_impl)(*b, epochs_per_candidate, 0.0, nullptr, nullptr, &ms);
-                if (rc) return rc;
-                if (ms < best) { best = ms; bc = Choice{w, g, st}; }
-            }
-    b->widen = bc.widen;
-    b->grid_mult = bc.grid_mult;
-    b->strided = bc.strided;
-    tuned_choices()[b->signature] = bc;
-    if (choice) { choice[0] = bc.widen; choice[1] = bc.grid_mult; choice[2] = bc.strided; }
+        for (int g : {1, 2, 4}) {
+            const Choice c{base.widen, g, st, base.cols};
+            if (g == base.grid_mult && st == base.strided) continue;
+            double ms = 0;
+            thetis_status rc = tune_time(*b, c, epochs_per_candidate, &ms);
+            if (rc) return rc;
+            if (ms < best_ms) { best_ms = ms; best = c; }
+        }
+    b->widen = best.widen;
+    b->grid_mult = best.grid_mult;
+    b->strided = best.strided;
+    b->cols = best.cols;
+    tuned_choices()[b->signature] = best;
+    if (choice) { choice[0] = best.widen; choice[1] = best.grid_mult; choice[2] = best.strided; choice[3] = best.cols; }
     return THETIS_OK;
 }
 

@@ -95,7 +95,7 @@ def lib():
             "thetis_batch_set": [vp, i32, vp],
             "thetis_batch_run": [vp, i32, dbl, vp, vp],
             "thetis_batch_autotune": [vp, i32, vp],
-            "thetis_batch_configure": [vp, i32, i32, i32],
+            "thetis_batch_configure": [vp, i32, i32, i32, i32],
             "thetis_batch_destroy": [vp],
         }
         for name, args in sig.items():
@@ -288,13 +288,13 @@ def thetis_batch_run(b, count: int, max_epochs: int, gap_tol: float = 0.0):
 
 
 def thetis_batch_autotune(b, epochs_per_candidate: int = 2):
-    ch = np.zeros(3, np.int32)
+    ch = np.zeros(4, np.int32)
     _check(lib().thetis_batch_autotune(b, epochs_per_candidate, _ptr(ch)))
-    return int(ch[0]), int(ch[1]), int(ch[2])
+    return tuple(int(v) for v in ch)
 
 
-def thetis_batch_configure(b, widen: int, grid_mult: int, strided: int = 1):
-    _check(lib().thetis_batch_configure(b, widen, grid_mult, strided))
+def thetis_batch_configure(b, widen: int, grid_mult: int, strided: int = 1, cols: int = 1):
+    _check(lib().thetis_batch_configure(b, widen, grid_mult, strided, cols))
 
 
 def thetis_batch_destroy(b):
@@ -462,8 +462,8 @@ class Batch:
     def autotune(self, epochs_per_candidate: int = 2):
         return thetis_batch_autotune(self.h, epochs_per_candidate)
 
-    def configure(self, widen: int, grid_mult: int, strided: int = 1):
-        thetis_batch_configure(self.h, widen, grid_mult, strided)
+    def configure(self, widen: int, grid_mult: int, strided: int = 1, cols: int = 1):
+        thetis_batch_configure(self.h, widen, grid_mult, strided, cols)
 
     def close(self):
         if getattr(self, "h", None):
