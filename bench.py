@@ -89,6 +89,47 @@ def summarize_counters(fetch_csv: str, write_csv: str, workload: str, copy_mib: 
     print(json.dumps(out, indent=1))
 
 
+def access_split(inst, unit_class):
+    """Entries of the structural columns per colour class, split into those
+    whose row the class owns (the row's first-scheduled column is in it: its
+    residual sits in the column's own contiguous run) and the rest (the row
+    belongs to an earlier class: a random residual access)."""
+    import numpy as np
+    rp = inst.row_ptr
+    cls = unit_class[: inst.n]
+    ent_cls = cls[inst.col_idx]
+    lens = np.diff(rp)
+    nz = lens > 0
+    row_min = np.full(inst.m, np.iinfo(np.int32).max, np.int64)
+    row_min[nz] = np.minimum.reduceat(ent_cls, rp[:-1][nz])
+    owned = ent_cls == np.repeat(row_min, lens)
+    nc = int(cls.max()) + 1
+    return (np.bincount(ent_cls[owned], minlength=nc).astype(np.int64),
+            np.bincount(ent_cls[~owned], minlength=nc).astype(np.int64),
+            np.bincount(cls, minlength=nc).astype(np.int64))
+
+
+def random_access_model(T, words: int, owned, foreign, ncols, sweep_ms_per_epoch: float):
+    """Times random 4-byte gathers / read-modify-writes and a copy over a
+    buffer the size of the residual (live, on this GPU) and prices one
+    epoch of plain-column sweeps with them: every foreign entry one random
+    read-modify-write, plus the sequential bytes (row index 4 B per entry,
+    residual read + write 8 B per owned entry, 20 B per column) at the copy
+    rate."""
+    import math
+    k = max(10, min(28, int(round(math.log2(max(words, 1024))))))
+    g_ms, rmw_ms, cp_ms = T.thetis_calibrate_random(k, 10)
+    w = float(1 << k)
+    rmw_rate, gather_rate, copy_gbs = w / (rmw_ms * 1e-3), w / (g_ms * 1e-3), 8 * w / (cp_ms * 1e-3) / 1e9
+    F, O, N = float(sum(foreign)), float(sum(owned)), float(sum(ncols))
+    seq_bytes = 4 * (F + O) + 8 * O + 20 * N
+    model_us = 1e6 * (F / rmw_rate) + 1e6 * seq_bytes / (copy_gbs * 1e9)
+    return {"buffer_words": int(w), "random_rmw_per_s": rmw_rate, "random_gather_per_s": gather_rate,
+            "copy_gbs": copy_gbs, "owned_entries_per_epoch": int(O), "foreign_entries_per_epoch": int(F),
+            "model_us_per_epoch": model_us, "measured_us_per_epoch": 1e3 * sweep_ms_per_epoch,
+            "frac_of_model": model_us / (1e3 * sweep_ms_per_epoch) if sweep_ms_per_epoch > 0 else None}
+
+
 def cpu_baseline(inst, epochs_cap: int, budget_s: float, seed: int):
     """The FP64 oracle (serial C, one thread) in the same DET order on the
     same instance; a bounded number of epochs, timed without its setup."""
@@ -577,6 +618,11 @@ def main():
                      "max_row_violation": m["max_viol"], "cover_cost": results[-1][0],
                      "feasible": bool(results[-1][1])},
     }
+    if sched == T.SCHED_DET:
+        owned, foreign, ncols = access_split(inst, h.classes()[2])
+        sweep_ms_epoch = g["ms"] / max(g["launches"], 1) * (nclasses - 1)
+        out["random_access"] = random_access_model(T, inst.m, owned, foreign, ncols, sweep_ms_epoch)
+        log(f"random access: {out['random_access']}")
     if args.cpu_baseline_seconds > 0:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(inst, args.epochs, args.cpu_baseline_seconds, args.seed)

@@ -130,8 +130,9 @@ thetis_status thetis_inst_set_simplex_blocks(thetis_inst *inst, int64_t nblocks,
  * update units in index order, all slack units in one last class) and the
  * class of every unit: units are the free simplex blocks and the columns
  * outside blocks in increasing column order, then the slack of every
- * inequality row in row order.  class_host may be NULL; otherwise it needs
- * room for thetis_inst_num_units() entries. */
+ * inequality row in row order.  class_host may be NULL (a first call then
+ * returns the unit count in nunits); otherwise it needs room for nunits
+ * entries. */
 thetis_status thetis_inst_classes(const thetis_inst *inst, int32_t *nclasses, int64_t *nunits,
                                   int32_t *class_host);
 
@@ -243,6 +244,15 @@ thetis_status thetis_epoch_traffic(const thetis_solver *s, double *sweep_bytes,
                                    double *refresh_bytes, int64_t *updates_per_epoch);
 
 thetis_status thetis_solver_destroy(thetis_solver *s);
+
+/* Measurement aid (no part of the method): on `stream` (NULL: the null
+ * stream) of the current device, times passes over a buffer of
+ * 2^words_log2 4-byte words (words_log2 in [10, 28]) that touch every word
+ * once: ms_host[0] a gather at random distinct addresses, ms_host[1] a
+ * read-modify-write at random distinct addresses, ms_host[2] a plain copy
+ * into a second buffer; each the mean of `iters` passes after one warm-up.
+ * Allocates and frees its two buffers; synchronises the stream. */
+thetis_status thetis_calibrate_random(int32_t words_log2, int32_t iters, void *stream, double *ms_host);
 
 /* ----------------------------------------------------------------- batches */
 

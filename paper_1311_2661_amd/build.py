@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libthetis.so")
-SOURCES = [os.path.join(CSRC, "thetis.hip"), os.path.join(CSRC, "layout.cpp")]
+SOURCES = [os.path.join(CSRC, "thetis.hip"), os.path.join(CSRC, "layout.cpp"), os.path.join(CSRC, "calibrate.hip")]
 HEADERS = [os.path.join(CSRC, "thetis_internal.h"),
            os.path.join(os.path.dirname(HERE), "include", "thetis.h")]
 

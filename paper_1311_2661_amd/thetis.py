@@ -37,7 +37,8 @@ EXPORTED = [
     "thetis_solver_create", "thetis_solver_reset", "thetis_set_beta", "thetis_set_step_rule",
     "thetis_run_epochs", "thetis_residual", "thetis_objective", "thetis_get_x", "thetis_set_y",
     "thetis_epoch", "thetis_round", "thetis_check_feasible", "thetis_set_timing",
-    "thetis_get_timing", "thetis_epoch_traffic", "thetis_solver_destroy", "thetis_last_error",
+    "thetis_get_timing", "thetis_epoch_traffic", "thetis_solver_destroy", "thetis_calibrate_random",
+    "thetis_last_error",
     "thetis_batch_create", "thetis_batch_set", "thetis_batch_run", "thetis_batch_autotune",
     "thetis_batch_configure", "thetis_batch_destroy",
 ]
@@ -91,6 +92,7 @@ def lib():
             "thetis_get_timing": [vp, i32, P(dbl), P(i64), P(dbl)],
             "thetis_epoch_traffic": [vp, P(dbl), P(dbl), P(i64)],
             "thetis_solver_destroy": [vp],
+            "thetis_calibrate_random": [i32, i32, vp, vp],
             "thetis_batch_create": [i32, vp, i32, i32, vp, P(vp)],
             "thetis_batch_set": [vp, i32, vp],
             "thetis_batch_run": [vp, i32, dbl, vp, vp],
@@ -285,6 +287,17 @@ def thetis_batch_run(b, count: int, max_epochs: int, gap_tol: float = 0.0):
     status = np.zeros(count, np.int32)
     _check(lib().thetis_batch_run(b, max_epochs, gap_tol, _ptr(done), _ptr(status)))
     return done, status
+
+
+def thetis_calibrate_random(words_log2: int, iters: int = 10):
+    """Random-access calibration on the current torch stream: mean ms per pass
+    of (random gather, random read-modify-write, copy) over 2^words_log2
+    4-byte words."""
+    import torch
+    out = np.zeros(3, np.float64)
+    st = torch.cuda.current_stream().cuda_stream
+    _check(lib().thetis_calibrate_random(words_log2, iters, C.c_void_p(st), _ptr(out)))
+    return float(out[0]), float(out[1]), float(out[2])
 
 
 def thetis_batch_autotune(b, epochs_per_candidate: int = 2):

@@ -425,3 +425,13 @@ def test_bf16_x_storage_error_is_stated_and_bounded():
     for rule in (T.ROUND_MIS_THRESH, T.ROUND_MIS_RAND):
         g.round(rule, seed=3, reps=5)
         assert g.check(rule) == (True, 0)
+
+
+def test_calibrate_random_rates_are_positive():
+    """The random-access calibration runs in bounds and returns finite
+    positive times for the gather, read-modify-write and copy passes."""
+    import math
+    g, rmw, cp = T.thetis_calibrate_random(16, 3)
+    assert all(math.isfinite(v) and v > 0 for v in (g, rmw, cp))
+    with pytest.raises(T.ThetisError):
+        T.thetis_calibrate_random(40, 1)
