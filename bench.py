@@ -205,6 +205,8 @@ def mis_batch(args):
     torch.cuda.synchronize()
     log(f"layout + upload of {count} solvers: {time.perf_counter() - t0:.1f} s")
     b = T.Batch(solvers)
+    if args.window:
+        b.set_window(args.window)
     choice = b.autotune(epochs_per_candidate=2)
     log(f"autotuned: widen {choice[0]}, grid x{choice[1]}, strided {choice[2]}, columns per group {choice[3]}")
     upd_total = []
@@ -256,7 +258,8 @@ def mis_batch(args):
         "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
         "config": {"workload": f"mis_batch_{count}_n200-50000_d3-16_{args.precision}_gap{args.gap:g}_cap{args.cap}",
                    "instances": count, "vertices": int(nv.sum()), "edges": int(ne.sum()),
-                   "gap_tol": args.gap, "epoch_cap": args.cap, "autotune": list(choice), "seed": args.seed},
+                   "gap_tol": args.gap, "epoch_cap": args.cap, "autotune": list(choice),
+                   "window": args.window, "seed": args.seed},
         "coord_updates_per_s": upd / elapsed,
         "epochs": {"median": float(np.median(done)), "max": int(done.max()), "min": int(done.min())},
         "gap_reached_sampled": f"{reached}/{sample_n}",
@@ -495,6 +498,8 @@ def main():
     ap.add_argument("--gap", type=float, default=1e-4, help="mis_batch: certified gap to stop at")
     ap.add_argument("--cap", type=int, default=200, help="mis_batch: epoch cap")
     ap.add_argument("--baseline-sample", type=int, default=32, help="mis_batch: instances solved alone")
+    ap.add_argument("--window", type=int, default=64,
+                    help="mis_batch: most instances running at once (0: all); the rest start as they retire")
     args = ap.parse_args()
 
     if args.summarize_counters:

@@ -306,6 +306,16 @@ thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_per_candidat
 thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult, int32_t strided,
                                      int32_t cols);
 
+/* At most `window` occupied slots run at once (0, the default: all).  The
+ * first `window` occupied slots start; when one retires, the waiting slot
+ * with the lowest index takes its place at the end of that epoch, on the
+ * device.  thetis_batch_run then counts max_epochs per instance, from the
+ * epoch it starts, and replays epochs until every slot has retired (at most
+ * max_epochs * (ceil(occupied / window) + 1) epochs of launches).  A smaller
+ * active set keeps the residuals of the running instances in the device's
+ * caches.  Results do not depend on it. */
+thetis_status thetis_batch_set_window(thetis_batch *b, int32_t window);
+
 thetis_status thetis_batch_destroy(thetis_batch *b);
 
 /* Message describing the calling thread's last failed call ("" if none). */

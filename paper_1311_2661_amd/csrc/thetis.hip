@@ -719,7 +719,23 @@ __device__ void fold_records(const double *part, int64_t nb, const int (&op)[NS]
     double acc[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) acc[q] = op[q] == 0 ? 0.0 : (op[q] == 1 ? -INFINITY : INFINITY);
-    for (int64_t b = t; b < nb; b += kWG)
+    // eight records' loads are issued together, then combined in record
+    // order: the same sequence of operations as one record at a time
+    constexpr int U = 8;
+    int64_t b = t;
+    for (; b + (U - 1) * kWG < nb; b += U * kWG) {
+        double x[U][NS];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < NS; ++q) x[u][q] = part[(b + u * kWG) * NS + q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                acc[q] = op[q] == 0 ? acc[q] + x[u][q] : (op[q] == 1 ? fmax(acc[q], x[u][q]) : fmin(acc[q], x[u][q]));
+    }
+    for (; b < nb; b += kWG)
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
             const double x = part[b * NS + q];
@@ -2007,9 +2023,10 @@ extern "C" thetis_status thetis_solver_destroy(thetis_solver *s) {
 //
 // A batch advances many solvers with one sequence of launches per epoch.
 // k_border draws every active instance's class order for the epoch (its own
-// Philox order).  For step q, k_bstep looks up each instance's class of that
-// step and its workgroup count and turns the counts into offsets, and
-// k_bsweep walks the resulting (instance, workgroup) items: each XCD takes a
+// Philox order).  k_bplan then, for every step q at once, looks up each
+// instance's class of that step and its workgroup count and turns the counts
+// into offsets, and k_bsweep of step q walks the resulting (instance,
+// workgroup) items: each XCD takes a
 // contiguous share of the items (so an instance's columns stay in one L2)
 // and each of its workgroups a contiguous run of that share.  Kernel boundaries are the class barriers.  After the
 // last step, k_bepoch advances the epoch counters and marks the instances
@@ -2031,6 +2048,7 @@ struct BInst {
     double gap_tol, beta;
     int32_t nclasses, class_base, refresh_every, active, due, with_dual, slack_identity, lpc;
     int32_t epochs_done, max_epochs, diverged, reason;   // reason: 0 running, 1 gap, 2 epochs, 3 NaN
+    int32_t pending;                    // waits for a place in the window
 };
 
 struct BClass {
@@ -2042,32 +2060,36 @@ struct BClass {
 constexpr int kMaxBatchClasses = 64;
 
 // class order of every active instance for its current epoch: classes
-// sorted by (Philox word, class id), one thread per instance
+// sorted by (Philox word, class id).  One wavefront per instance, lane c
+// draws the word of class c and counts the classes ahead of it.
 template <class P>
 __global__ __launch_bounds__(kWG) void k_border(const BInst<P> *bi, int32_t count, int8_t *order) {
-    const int32_t i = blockIdx.x * kWG + threadIdx.x;
-    if (i >= count) return;
+    const int32_t i = blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= count) return;               // the whole wavefront leaves together
     const BInst<P> &I = bi[i];
     if (!I.active) return;
-    uint64_t key[kMaxBatchClasses];
-    int8_t id[kMaxBatchClasses];
     const int32_t C = I.nclasses;
+    const uint64_t key = lane < C ? philox_word_dev(I.seed, RNG_CLASS_ORDER, (uint64_t)I.epoch, (uint64_t)lane, 0) : 0;
+    const uint32_t klo = (uint32_t)key, khi = (uint32_t)(key >> 32);
+    int32_t rank = 0;
     for (int32_t c = 0; c < C; ++c) {
-        const uint64_t k = philox_word_dev(I.seed, RNG_CLASS_ORDER, (uint64_t)I.epoch, (uint64_t)c, 0);
-        int32_t p = c;
-        while (p > 0 && key[p - 1] > k) { key[p] = key[p - 1]; id[p] = id[p - 1]; --p; }
-        key[p] = k;
-        id[p] = (int8_t)c;
+        const uint64_t kc = ((uint64_t)(uint32_t)__shfl((int)khi, c, 64) << 32) | (uint32_t)__shfl((int)klo, c, 64);
+        rank += (kc < key || (kc == key && c < lane)) ? 1 : 0;
     }
-    for (int32_t q = 0; q < C; ++q) order[(int64_t)i * kMaxBatchClasses + q] = id[q];
+    if (lane < C) order[(int64_t)i * kMaxBatchClasses + rank] = (int8_t)lane;
 }
 
-// step q: every active instance's class and workgroup count, and the
-// exclusive prefix of the counts (start has count + 1 entries); one workgroup
+// every step q of the epoch (workgroup q): each active instance's class at
+// that step and its workgroup count, and the exclusive prefix of the counts
+// (start_q has count + 1 entries)
 template <class P>
-__global__ __launch_bounds__(kWG) void k_bstep(const BInst<P> *bi, const BClass *bc, int32_t count, int32_t q,
+__global__ __launch_bounds__(kWG) void k_bplan(const BInst<P> *bi, const BClass *bc, int32_t count,
                                                const int8_t *order, int32_t *cls, int64_t *start) {
     __shared__ int64_t part[kWG + 1];
+    const int32_t q = blockIdx.x;
+    int32_t *cls_q = cls + (int64_t)q * count;
+    int64_t *start_q = start + (int64_t)q * (count + 1);
     const int t = threadIdx.x;
     const int32_t chunk = (count + kWG - 1) / kWG;
     const int32_t lo = t * chunk, hi = min(count, lo + chunk);
@@ -2081,8 +2103,8 @@ __global__ __launch_bounds__(kWG) void k_bstep(const BInst<P> *bi, const BClass 
             const BClass &C = bc[I.class_base + c];
             w = C.wg_cols + C.wg_block + C.wg_slack;
         }
-        cls[i] = c;
-        start[i] = w;          // count for now, prefix below
+        cls_q[i] = c;
+        start_q[i] = w;          // count for now, prefix below
         sum += w;
     }
     part[t + 1] = sum;
@@ -2093,8 +2115,8 @@ __global__ __launch_bounds__(kWG) void k_bstep(const BInst<P> *bi, const BClass 
     }
     __syncthreads();
     int64_t run = part[t];
-    for (int32_t i = lo; i < hi; ++i) { const int64_t w = start[i]; start[i] = run; run += w; }
-    if (t == 0) start[count] = part[kWG];
+    for (int32_t i = lo; i < hi; ++i) { const int64_t w = start_q[i]; start_q[i] = run; run += w; }
+    if (t == 0) start_q[count] = part[kWG];
 }
 
 // exclusive prefix of `count` workgroup counts in one workgroup; start has
@@ -2182,8 +2204,7 @@ __global__ __launch_bounds__(kWG) void k_bsweep(const BInst<P> *bi, const BClass
 }
 
 template <class P>
-__global__ __launch_bounds__(kWG) void k_bepoch(BInst<P> *bi, int32_t count, int32_t *rows_wg, int32_t *dual_wg,
-                                                int32_t *active_count) {
+__global__ __launch_bounds__(kWG) void k_bepoch(BInst<P> *bi, int32_t count, int32_t *rows_wg, int32_t *dual_wg) {
     const int32_t i = blockIdx.x * kWG + threadIdx.x;
     if (i >= count) return;
     BInst<P> &I = bi[i];
@@ -2194,7 +2215,6 @@ __global__ __launch_bounds__(kWG) void k_bepoch(BInst<P> *bi, int32_t count, int
         I.due = (I.epoch % I.refresh_every) == 0;
         if (I.due) { rw = (int32_t)I.rows_wg; dw = (int32_t)I.dual.nwg; }
         else if (I.epochs_done >= I.max_epochs) { I.active = 0; I.reason = 2; }
-        if (I.active) atomicAdd(active_count, 1);
     } else {
         I.due = 0;
     }
@@ -2246,8 +2266,35 @@ __global__ __launch_bounds__(kWG) void k_bfinal(BInst<P> *bi, int32_t count) {
     }
 }
 
-__global__ void k_bclear(int32_t *v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *v = 0;
+// end of an epoch, one workgroup: waiting instances take the places of
+// retired ones in slot order until `window` run at once; left[0] receives
+// the number of instances running or waiting
+template <class P>
+__global__ __launch_bounds__(kWG) void k_bwindow(BInst<P> *bi, int32_t count, int32_t window, int32_t *left) {
+    __shared__ int32_t pend[kWG + 1];
+    __shared__ int32_t n_active;
+    const int t = threadIdx.x;
+    const int32_t chunk = (count + kWG - 1) / kWG;
+    const int32_t lo = t * chunk, hi = min(count, lo + chunk);
+    int32_t act = 0, np = 0;
+    for (int32_t i = lo; i < hi; ++i) { act += bi[i].active; np += bi[i].pending; }
+    if (t == 0) n_active = 0;
+    pend[t + 1] = np;
+    __syncthreads();
+    atomicAdd(&n_active, act);           // integer sum: exact in any order
+    if (t == 0) {
+        pend[0] = 0;
+        for (int u = 1; u <= kWG; ++u) pend[u] += pend[u - 1];
+    }
+    __syncthreads();
+    const int32_t room = max(0, window - n_active);
+    int32_t rank = pend[t];              // waiting instances in earlier slots
+    for (int32_t i = lo; i < hi; ++i) {
+        if (!bi[i].pending) continue;
+        if (rank < room) { bi[i].pending = 0; bi[i].active = 1; }
+        ++rank;
+    }
+    if (t == 0) left[0] = n_active + pend[kWG];
 }
 
 }  // namespace
@@ -2260,10 +2307,11 @@ struct thetis_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int widen = 1, grid_mult = 2, strided = 1, cols = 1;
+    int32_t window = 0;                 // most instances running at once (0: all)
     int64_t resident_wg = 2048;
     // device
     void *bi = nullptr, *bc = nullptr;
-    int32_t *wg = nullptr, *cls = nullptr, *rows_wg = nullptr, *dual_wg = nullptr, *active = nullptr;
+    int32_t *cls = nullptr, *rows_wg = nullptr, *dual_wg = nullptr, *active = nullptr;
     int8_t *order = nullptr;
     int64_t *start = nullptr;
     size_t bi_bytes = 0;
@@ -2272,7 +2320,7 @@ struct thetis_batch {
     // captured epoch
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int captured_widen = 0, captured_grid = 0, captured_strided = -1, captured_cols = 0;
+    int captured_widen = 0, captured_grid = 0, captured_strided = -1, captured_cols = 0, captured_window = -1;
     uint64_t signature = 0;
 };
 
@@ -2299,6 +2347,7 @@ template <class P>
 thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) {
     std::vector<BInst<P>> bi(B.count);
     std::vector<BClass> bc;
+    int32_t occupied = 0;
     for (int32_t i = 0; i < B.count; ++i) {
         BInst<P> &I = bi[i];
         std::memset((void *)&I, 0, sizeof(I));
@@ -2320,7 +2369,11 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
         I.nclasses = S.nclasses;
         I.class_base = (int32_t)bc.size();
         I.refresh_every = S.p.refresh_every;
-        I.active = max_epochs > 0 ? 1 : 0;
+        // with a window, the first `window` occupied slots start and the
+        // rest wait
+        I.pending = (max_epochs > 0 && B.window > 0 && occupied >= B.window) ? 1 : 0;
+        I.active = (max_epochs > 0 && !I.pending) ? 1 : 0;
+        ++occupied;
         I.due = 0;
         I.slack_identity = S.all_rows_slack ? 1 : 0;
         I.lpc = S.lpc;
@@ -2368,21 +2421,24 @@ void batch_epoch_launches(thetis_batch &B) {
     const int64_t grid = std::max<int64_t>(8, (B.resident_wg * B.grid_mult) / 8 * 8);
     BInst<P> *bi = (BInst<P> *)B.bi;
     const BClass *bc = (const BClass *)B.bc;
-    hipLaunchKernelGGL(k_bclear, dim3(1), dim3(64), 0, B.stream, B.active);
-    hipLaunchKernelGGL((k_border<P>), dim3(gi), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, n, B.order);
+    hipLaunchKernelGGL((k_border<P>), dim3(cdiv(n, kWG / 64)), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, n, B.order);
+    hipLaunchKernelGGL((k_bplan<P>), dim3(std::max(B.max_classes, 1)), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, bc, n,
+                       (const int8_t *)B.order, B.cls, B.start);
     for (int32_t q = 0; q < B.max_classes; ++q) {
-        hipLaunchKernelGGL((k_bstep<P>), dim3(1), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, bc, n, q,
-                           (const int8_t *)B.order, B.cls, B.start);
-        if (B.vals) hipLaunchKernelGGL((k_bsweep<P, true>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, (const int32_t *)B.cls, (const int64_t *)B.start, n, B.strided);
-        else hipLaunchKernelGGL((k_bsweep<P, false>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, (const int32_t *)B.cls, (const int64_t *)B.start, n, B.strided);
+        const int32_t *cls_q = B.cls + (int64_t)q * n;
+        const int64_t *start_q = B.start + (int64_t)q * (n + 1);
+        if (B.vals) hipLaunchKernelGGL((k_bsweep<P, true>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, cls_q, start_q, n, B.strided);
+        else hipLaunchKernelGGL((k_bsweep<P, false>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, cls_q, start_q, n, B.strided);
     }
-    hipLaunchKernelGGL((k_bepoch<P>), dim3(gi), dim3(kWG), 0, B.stream, bi, n, B.rows_wg, B.dual_wg, B.active);
-    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.rows_wg, n, B.start);
-    hipLaunchKernelGGL((k_brows<P>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n, B.strided);
-    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.dual_wg, n, B.start);
-    if (B.vals) hipLaunchKernelGGL((k_bdual<P, true>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n, B.strided);
-    else hipLaunchKernelGGL((k_bdual<P, false>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)B.start, n, B.strided);
+    int64_t *start_r = B.start + (int64_t)kMaxBatchClasses * (n + 1);   // refresh offsets
+    hipLaunchKernelGGL((k_bepoch<P>), dim3(gi), dim3(kWG), 0, B.stream, bi, n, B.rows_wg, B.dual_wg);
+    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.rows_wg, n, start_r);
+    hipLaunchKernelGGL((k_brows<P>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)start_r, n, B.strided);
+    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.dual_wg, n, start_r);
+    if (B.vals) hipLaunchKernelGGL((k_bdual<P, true>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)start_r, n, B.strided);
+    else hipLaunchKernelGGL((k_bdual<P, false>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)start_r, n, B.strided);
     hipLaunchKernelGGL((k_bfinal<P>), dim3(std::min<int64_t>(n, 1024)), dim3(kWG), 0, B.stream, bi, n);
+    hipLaunchKernelGGL((k_bwindow<P>), dim3(1), dim3(kWG), 0, B.stream, bi, n, B.window > 0 ? B.window : n, B.active);
 }
 
 template <class P>
@@ -2397,6 +2453,7 @@ thetis_status batch_capture(thetis_batch &B) {
     B.captured_grid = B.grid_mult;
     B.captured_strided = B.strided;
     B.captured_cols = B.cols;
+    B.captured_window = B.window;
     return THETIS_OK;
 }
 
@@ -2407,7 +2464,7 @@ thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol
     thetis_status st = batch_upload<P>(B, max_epochs, gap_tol);
     if (st) return st;
     if (!B.exec || B.captured_widen != B.widen || B.captured_grid != B.grid_mult || B.captured_strided != B.strided ||
-        B.captured_cols != B.cols) {
+        B.captured_cols != B.cols || B.captured_window != B.window) {
         st = batch_capture<P>(B);
         if (st) return st;
     }
@@ -2417,12 +2474,16 @@ thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol
         HIP_TRY(hipEventCreate(&e1));
         HIP_TRY(hipEventRecord(e0, B.stream));
     }
-    int32_t refresh_min = 1 << 30;
-    for (thetis_solver *S : B.solvers) if (S) refresh_min = std::min(refresh_min, S->p.refresh_every);
+    int32_t refresh_min = 1 << 30, occupied = 0;
+    for (thetis_solver *S : B.solvers)
+        if (S) { refresh_min = std::min(refresh_min, S->p.refresh_every); ++occupied; }
     if (refresh_min == (1 << 30)) refresh_min = 1;
-    for (int32_t e = 0; e < max_epochs; ++e) {
+    // with a window, instances run in turns: enough epochs for every turn
+    const bool windowed = B.window > 0 && B.window < occupied;
+    const int64_t replays = windowed ? (int64_t)max_epochs * (cdiv(occupied, B.window) + 1) : max_epochs;
+    for (int64_t e = 0; e < replays; ++e) {
         HIP_TRY(hipGraphLaunch(B.exec, B.stream));
-        if (gap_tol > 0.0 && (e + 1) % refresh_min == 0 && e + 1 < max_epochs) {
+        if ((gap_tol > 0.0 || windowed) && (e + 1) % refresh_min == 0 && e + 1 < replays) {
             int32_t act = 0;
             HIP_TRY(hipMemcpyAsync(&act, B.active, 4, hipMemcpyDeviceToHost, B.stream));
             HIP_TRY(hipStreamSynchronize(B.stream));
@@ -2542,12 +2603,13 @@ extern "C" thetis_status thetis_batch_create(int32_t capacity, thetis_solver *co
     const int32_t count = capacity;
     const size_t nb = binst_bytes(B.precision);
     hipError_t e = hipMalloc(&B.bi, nb * count);
-    if (e == hipSuccess) e = hipMalloc((void **)&B.wg, 4 * count);
-    if (e == hipSuccess) e = hipMalloc((void **)&B.cls, 4 * count);
+    // per-step classes and offsets of every step of an epoch; the offsets
+    // have one more block for the refresh passes
+    if (e == hipSuccess) e = hipMalloc((void **)&B.cls, (size_t)4 * kMaxBatchClasses * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.rows_wg, 4 * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.dual_wg, 4 * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.active, 4);
-    if (e == hipSuccess) e = hipMalloc((void **)&B.start, 8 * (count + 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&B.start, (size_t)8 * (kMaxBatchClasses + 1) * (count + 1));
     if (e == hipSuccess) e = hipMalloc((void **)&B.order, (size_t)kMaxBatchClasses * count);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -2650,13 +2712,20 @@ extern "C" thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_p
     return THETIS_OK;
 }
 
+extern "C" thetis_status thetis_batch_set_window(thetis_batch *b, int32_t window) {
+    clear_error();
+    if (!b) return fail(THETIS_EINVAL, "batch is NULL");
+    if (window < 0) return fail(THETIS_EINVAL, "window must be >= 0");
+    b->window = window;
+    return THETIS_OK;
+}
+
 extern "C" thetis_status thetis_batch_destroy(thetis_batch *b) {
     if (!b) return THETIS_OK;
     (void)hipStreamSynchronize(b->stream);
     batch_drop_graph(*b);
     (void)hipFree(b->bi);
     if (b->bc) (void)hipFree(b->bc);
-    (void)hipFree(b->wg);
     (void)hipFree(b->cls);
     (void)hipFree(b->rows_wg);
     (void)hipFree(b->dual_wg);

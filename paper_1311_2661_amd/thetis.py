@@ -40,7 +40,7 @@ EXPORTED = [
     "thetis_get_timing", "thetis_epoch_traffic", "thetis_solver_destroy", "thetis_calibrate_random",
     "thetis_last_error",
     "thetis_batch_create", "thetis_batch_set", "thetis_batch_run", "thetis_batch_autotune",
-    "thetis_batch_configure", "thetis_batch_destroy",
+    "thetis_batch_configure", "thetis_batch_set_window", "thetis_batch_destroy",
 ]
 
 
@@ -98,6 +98,7 @@ def lib():
             "thetis_batch_run": [vp, i32, dbl, vp, vp],
             "thetis_batch_autotune": [vp, i32, vp],
             "thetis_batch_configure": [vp, i32, i32, i32, i32],
+            "thetis_batch_set_window": [vp, i32],
             "thetis_batch_destroy": [vp],
         }
         for name, args in sig.items():
@@ -477,6 +478,11 @@ class Batch:
 
     def configure(self, widen: int, grid_mult: int, strided: int = 1, cols: int = 1):
         thetis_batch_configure(self.h, widen, grid_mult, strided, cols)
+
+    def set_window(self, window: int):
+        """At most `window` instances run at once (0: all); the others wait
+        in slot order and start on the device as running ones retire."""
+        _check(lib().thetis_batch_set_window(self.h, window))
 
     def close(self):
         if getattr(self, "h", None):

@@ -115,6 +115,40 @@ def test_batch_autotune_and_continue():
         assert_same(sa, sb)
 
 
+@pytest.mark.parametrize("window", [1, 2, 5])
+def test_batch_window_equals_alone(window):
+    """With a window, waiting instances start on the device as others
+    retire; each still computes exactly its solo trajectory, and the batch
+    runs until every instance has retired."""
+    say(f"case batch window {window}")
+    insts = [I.vc_er(200, 800, seed=7), I.mis_regular(600, 4, seed=8), I.vc_ba(3000, seed=9),
+             I.vc_er(40, 90, seed=4), I.mis_regular(900, 9, seed=5), I.vc_er(300, 1200, seed=1)]
+    alone, batched = pair(insts)
+    ref = [s.run(300, gap_tol=1e-4) for s in alone]
+    b = T.Batch(batched)
+    b.set_window(window)
+    done = b.run(300, gap_tol=1e-4)
+    say(f"  epochs alone {ref} batched {list(done)}")
+    assert list(done) == ref
+    assert all(int(v) in (1, 2) for v in b.last_status)
+    for sa, sb in zip(alone, batched):
+        assert_same(sa, sb)
+
+
+def test_batch_window_fixed_epochs():
+    """Without a gap every instance runs exactly max_epochs, in turns."""
+    insts = mixed_instances()[:5]
+    alone, batched = pair(insts)
+    for s in alone:
+        s.run(11)
+    b = T.Batch(batched)
+    b.set_window(2)
+    done = b.run(11)
+    assert list(done) == [11] * 5
+    for sa, sb in zip(alone, batched):
+        assert_same(sa, sb)
+
+
 def test_batch_many_uneven_instances():
     """256 independent-set instances of uneven size and degree, as in the
     batched workload, against solo runs of a sample."""
