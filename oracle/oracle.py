@@ -71,6 +71,7 @@ def lib():
         L.orc_set_y.argtypes = [P, dp]
         L.orc_epoch.restype = C.c_int64
         L.orc_epoch.argtypes = [P]
+        L.orc_set_epoch.argtypes = [P, C.c_int64]
         L.orc_lmax.restype = C.c_double
         L.orc_lmax.argtypes = [P]
         L.orc_penalty.restype = C.c_double
@@ -222,6 +223,11 @@ class OracleSolver:
     @property
     def epoch(self) -> int:
         return lib().orc_epoch(self.h)
+
+    @epoch.setter
+    def epoch(self, e: int):
+        """Epoch counter (selects the class order of the next epoch)."""
+        lib().orc_set_epoch(self.h, int(e))
 
     @property
     def lmax(self) -> float:
