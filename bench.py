@@ -492,7 +492,7 @@ def main():
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serve: device-memory budget (0: half of free)")
     ap.add_argument("--slots", type=int, default=256, help="serve: slots per batch kind")
-    ap.add_argument("--builders", type=int, default=8, help="serve: host layout threads")
+    ap.add_argument("--builders", type=int, default=12, help="serve: host layout threads")
     ap.add_argument("--instances", type=int, default=4096, help="mis_batch: instance count")
     ap.add_argument("--precision", choices=["bf16", "fp32"], default="bf16", help="mis_batch: x storage")
     ap.add_argument("--gap", type=float, default=1e-4, help="mis_batch: certified gap to stop at")

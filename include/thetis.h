@@ -109,7 +109,10 @@ thetis_status thetis_params_default(thetis_params *p);
  * is appended per inequality row (-1 for '>=', +1 for '<='), bounded below
  * by 0.  All inputs are copied.  Limits: nnz < 2^31, n + m < 2^31.
  * Errors: THETIS_EINVAL for non-finite data, indices out of range or a bad
- * row_ptr; THETIS_ENOMEM. */
+ * row_ptr; THETIS_ENOMEM.  The layout (column copy, colouring, plans) is
+ * built once, by the first call that needs it (thetis_inst_classes,
+ * thetis_solver_workspace_bytes, thetis_solver_create; those calls may be
+ * made from several threads). */
 thetis_status thetis_inst_create_csr(int64_t m, int64_t n, int64_t nnz,
                                      const int64_t *row_ptr_host, const int32_t *col_idx_host,
                                      const double *val_host, const double *b_host,
@@ -302,7 +305,8 @@ thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_per_candidat
 
 /* Sets the launch configuration directly: widen in {1,2,4}, grid multiplier
  * in {1,2,4,8}, strided in {0,1}, columns per lane group in {1,2,4} (at most
- * 2 where a column takes 64 lanes).  Results do not depend on it. */
+ * 2 where a column takes 64 lanes).  Defaults: 1, 2, 1, 4.  Results do not
+ * depend on it. */
 thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult, int32_t strided,
                                      int32_t cols);
 

@@ -71,12 +71,32 @@ static void build_csc(Inst &in) {
         in.max_col_degree = std::max<int64_t>(in.max_col_degree, in.col_ptr[j + 1] - in.col_ptr[j]);
 }
 
+// The slack units, one per inequality row in row order, after the
+// structural units: all in one class after the structural classes.
+static void list_slack_units(Inst &in) {
+    in.ukind.resize(in.nstruct_units);
+    in.uid.resize(in.nstruct_units);
+    in.ucolour.resize(in.nstruct_units);
+    bool any_slack = false;
+    in.all_rows_slack = true;
+    for (int64_t i = 0; i < in.m; ++i) {
+        if (in.sense[i] != 0) {
+            in.ukind.push_back(2); in.uid.push_back((int32_t)i); in.ucolour.push_back(in.nstruct_classes);
+            any_slack = true;
+        } else {
+            in.all_rows_slack = false;
+        }
+    }
+    in.nunits = (int64_t)in.ukind.size();
+    in.nclasses = in.nstruct_classes + (any_slack ? 1 : 0);
+}
+
 // Units in unit order and a greedy colouring: unit t takes the smallest
 // colour not held by an earlier unit that shares a row with it.  Slack
 // units (one per inequality row) all go to one extra, last class: they
 // touch one row each, all different.
 static void colour_units(Inst &in) {
-    const int64_t n = in.n, m = in.m;
+    const int64_t n = in.n;
     in.ukind.clear(); in.uid.clear(); in.ucolour.clear();
     std::vector<int32_t> unit_of_col(n, -1);
     for (int64_t j = 0; j < n; ++j) {
@@ -112,18 +132,8 @@ static void colour_units(Inst &in) {
         in.ucolour[t] = cc;
         ncol = std::max(ncol, cc + 1);
     }
-    bool any_slack = false;
-    in.all_rows_slack = true;
-    for (int64_t i = 0; i < m; ++i) {
-        if (in.sense[i] != 0) {
-            in.ukind.push_back(2); in.uid.push_back((int32_t)i); in.ucolour.push_back(ncol);
-            any_slack = true;
-        } else {
-            in.all_rows_slack = false;
-        }
-    }
-    in.nunits = (int64_t)in.ukind.size();
-    in.nclasses = ncol + (any_slack ? 1 : 0);
+    in.nstruct_classes = ncol;
+    list_slack_units(in);
 }
 
 static int32_t column_kind(int64_t d) {
@@ -193,7 +203,8 @@ static void pack(const Inst &in, const std::vector<int32_t> &sched,
 // when the order is already that one.
 static bool renumber_rows(Inst &in) {
     const int64_t n = in.n, m = in.m;
-    std::vector<int64_t> pos(n, INT64_MAX);     // schedule position of a column's unit
+    const int32_t none = (int32_t)in.sched.size();  // positions are below n + m < 2^31
+    std::vector<int32_t> pos(n, none);          // schedule position of a column's unit
     for (const ClassPlan &cp : in.classes)
         for (const Segment &sg : cp.segs) {
             if (sg.kind == SEG_SLACK) continue;
@@ -201,27 +212,30 @@ static bool renumber_rows(Inst &in) {
                 const int32_t id = in.sched[sg.first + q];
                 const int64_t at = sg.first + q;
                 if (sg.kind == SEG_BLOCK)
-                    for (int32_t i = 0; i < in.k; ++i) pos[in.bfirst[id] + i] = at;
+                    for (int32_t i = 0; i < in.k; ++i) pos[in.bfirst[id] + i] = (int32_t)at;
                 else
-                    pos[id] = at;
+                    pos[id] = (int32_t)at;
             }
         }
-    std::vector<std::pair<int64_t, int32_t>> key(m);
+    // owner position of every row, then a stable counting sort by it
+    std::vector<int32_t> key(m), at((size_t)none + 2, 0), order(m);
     for (int64_t i = 0; i < m; ++i) {
-        int64_t best = INT64_MAX;
+        int32_t best = none;
         for (int32_t e = in.row_ptr[i]; e < in.row_ptr[i + 1]; ++e) best = std::min(best, pos[in.col_idx[e]]);
-        key[i] = {best, (int32_t)i};
+        key[i] = best;
+        at[(size_t)best + 1]++;
     }
-    std::stable_sort(key.begin(), key.end());
+    for (size_t q = 1; q < at.size(); ++q) at[q] += at[q - 1];
+    for (int64_t i = 0; i < m; ++i) order[at[key[i]]++] = (int32_t)i;
     bool same = true;
-    for (int64_t r = 0; r < m; ++r) same = same && key[r].second == r;
+    for (int64_t r = 0; r < m && same; ++r) same = order[r] == r;
     if (same) return false;
     std::vector<int32_t> rp(m + 1, 0), ci(in.nnz);
     std::vector<double> vv(in.unit_vals ? 0 : in.nnz), bb(m);
     std::vector<int8_t> ss(m);
     std::vector<int32_t> orig(m);
     for (int64_t r = 0; r < m; ++r) {
-        const int32_t o = key[r].second;
+        const int32_t o = order[r];
         const int32_t len = in.row_ptr[o + 1] - in.row_ptr[o];
         rp[r + 1] = rp[r] + len;
         std::copy(in.col_idx.begin() + in.row_ptr[o], in.col_idx.begin() + in.row_ptr[o + 1], ci.begin() + rp[r]);
@@ -239,9 +253,8 @@ static bool renumber_rows(Inst &in) {
     return true;
 }
 
-static void plan_all(Inst &in) {
-    build_csc(in);
-    colour_units(in);
+// the DET plan: the units of every class split into segment kinds
+static void plan_classes(Inst &in) {
     in.sched.clear();
     in.classes.assign(in.nclasses, ClassPlan());
     std::vector<std::vector<int64_t>> members(in.nclasses);
@@ -255,10 +268,17 @@ thetis_status build_layout(Inst &in) {
             in.row_orig.resize(in.m);
             for (int64_t i = 0; i < in.m; ++i) in.row_orig[i] = (int32_t)i;
         }
-        plan_all(in);
-        // the colouring does not depend on the row order, so planning again
-        // after the renumbering gives the same classes
-        if (renumber_rows(in)) plan_all(in);
+        build_csc(in);
+        colour_units(in);
+        plan_classes(in);
+        // the colouring does not depend on the row order: after the
+        // renumbering only the column copy, the slack units (listed in row
+        // order) and the plans are redone
+        if (renumber_rows(in)) {
+            build_csc(in);
+            list_slack_units(in);
+            plan_classes(in);
+        }
         in.async_sched.clear();
         std::vector<int64_t> st, sl;
         for (int64_t t = 0; t < in.nunits; ++t) (in.ukind[t] == 2 ? sl : st).push_back(t);
@@ -278,6 +298,12 @@ thetis_status build_layout(Inst &in) {
 }  // namespace thetis
 
 using namespace thetis;
+
+thetis_status thetis::ensure_layout(const thetis_inst *hc) {
+    thetis_inst *h = const_cast<thetis_inst *>(hc);
+    std::lock_guard<std::mutex> lock(h->layout_mu);
+    return h->in.planned ? THETIS_OK : build_layout(h->in);
+}
 
 // ------------------------------------------------------------------ C ABI
 
@@ -364,8 +390,7 @@ extern "C" thetis_status thetis_inst_create_csr(int64_t m, int64_t n, int64_t nn
         delete h;
         return fail(THETIS_ENOMEM, "host allocation failed");
     }
-    thetis_status st = build_layout(in);
-    if (st != THETIS_OK) { delete h; return st; }
+    in.planned = false;          // built on first use (blocks may still be set)
     *out = h;
     return THETIS_OK;
 }
@@ -396,15 +421,19 @@ extern "C" thetis_status thetis_inst_set_simplex_blocks(thetis_inst *h, int64_t 
         for (int32_t i = 0; i < k; ++i)
             if (in.u[bf[t] + i] < 1.0)
                 return fail(THETIS_EINVAL, "simplex block columns need an upper bound of at least 1");
+    std::lock_guard<std::mutex> lock(h->layout_mu);
     in.nblocks = nblocks; in.k = k;
     in.bfirst.swap(bf); in.fixed.swap(fx); in.col_block.swap(cb);
-    return build_layout(in);
+    in.planned = false;
+    return THETIS_OK;
 }
 
 extern "C" thetis_status thetis_inst_classes(const thetis_inst *h, int32_t *nclasses, int64_t *nunits,
                                              int32_t *class_host) {
     clear_error();
     if (!h) return fail(THETIS_EINVAL, "instance is NULL");
+    thetis_status st = ensure_layout(h);
+    if (st) return st;
     if (nclasses) *nclasses = h->in.nclasses;
     if (nunits) *nunits = h->in.nunits;
     if (class_host) std::copy(h->in.ucolour.begin(), h->in.ucolour.end(), class_host);

@@ -1749,6 +1749,8 @@ extern "C" thetis_status thetis_solver_workspace_bytes(const thetis_inst *h, con
     if (!h || !bytes) return fail(THETIS_EINVAL, "NULL argument");
     thetis_status st = check_params(p);
     if (st) return st;
+    st = ensure_layout(h);
+    if (st) return st;
     thetis_solver S;
     S.p = *p;
     S.has_ybar = p->prox && p->ybar;
@@ -1764,6 +1766,8 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     if (!h || !out) return fail(THETIS_EINVAL, "NULL argument");
     *out = nullptr;
     thetis_status st = check_params(p);
+    if (st) return st;
+    st = ensure_layout(h);
     if (st) return st;
     const Inst &in = h->in;
     thetis_solver *Sp = new (std::nothrow) thetis_solver;
@@ -2058,6 +2062,11 @@ struct BClass {
 };
 
 constexpr int kMaxBatchClasses = 64;
+// a batch work item covers one logical workgroup of plain columns, or this
+// many simplex blocks per wavefront, or this many slacks per thread (larger
+// items amortise the walk to the item's instance and plan)
+constexpr int kBatchBlocks = 4;
+constexpr int kBatchSlacks = 4;
 
 // class order of every active instance for its current epoch: classes
 // sorted by (Philox word, class id).  One wavefront per instance, lane c
@@ -2194,11 +2203,19 @@ __global__ __launch_bounds__(kWG) void k_bsweep(const BInst<P> *bi, const BClass
         if (local < C.wg_cols) {
             sweep_item<P, VALS>(I.a, I.sc, C.cols, local, st_r, st_row, red);
         } else if (local < C.wg_cols + C.wg_block) {
-            const int64_t u = (local - C.wg_cols) * (kWG / 64) + (threadIdx.x >> 6);
-            if (u < C.block_count) sweep_block<P, VALS>(I.a, I.sc.ids[C.block_first + u], I.lpc);
+            // kBatchBlocks blocks per wavefront
+            const int64_t base = (local - C.wg_cols) * (kWG / 64) * kBatchBlocks + (threadIdx.x >> 6);
+            for (int b = 0; b < kBatchBlocks; ++b) {
+                const int64_t u = base + b * (kWG / 64);
+                if (u < C.block_count) sweep_block<P, VALS>(I.a, I.sc.ids[C.block_first + u], I.lpc);
+            }
         } else {
-            const int64_t u = (local - C.wg_cols - C.wg_block) * kWG + threadIdx.x;
-            if (u < C.slack_count) sweep_slack<P>(I.a, I.slack_identity ? u : I.sc.ids[C.slack_first + u]);
+            // kBatchSlacks slacks per thread
+            const int64_t base = (local - C.wg_cols - C.wg_block) * kWG * kBatchSlacks + threadIdx.x;
+            for (int b = 0; b < kBatchSlacks; ++b) {
+                const int64_t u = base + b * kWG;
+                if (u < C.slack_count) sweep_slack<P>(I.a, I.slack_identity ? u : I.sc.ids[C.slack_first + u]);
+            }
         }
     }
 }
@@ -2306,7 +2323,7 @@ struct thetis_batch {
     std::vector<thetis_solver *> solvers;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    int widen = 1, grid_mult = 2, strided = 1, cols = 1;
+    int widen = 1, grid_mult = 2, strided = 1, cols = 4;
     int32_t window = 0;                 // most instances running at once (0: all)
     int64_t resident_wg = 2048;
     // device
@@ -2387,10 +2404,10 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
             C.wg_cols = cl.has_cols ? C.cols.nwg : 0;
             C.block_first = cl.block_first;
             C.block_count = cl.block_count;
-            C.wg_block = cdiv(cl.block_count, kWG / 64);
+            C.wg_block = cdiv(cl.block_count, (kWG / 64) * kBatchBlocks);
             C.slack_first = cl.slack_first;
             C.slack_count = cl.slack_count;
-            C.wg_slack = cdiv(cl.slack_count, kWG);
+            C.wg_slack = cdiv(cl.slack_count, kWG * kBatchSlacks);
             bc.push_back(C);
         }
     }

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -75,7 +76,7 @@ struct Inst {
     std::vector<int8_t> ukind;          // 0 column, 1 block, 2 slack
     std::vector<int32_t> uid;           // column / block / row
     std::vector<int32_t> ucolour;
-    int32_t nclasses = 0;
+    int32_t nclasses = 0, nstruct_classes = 0;
     // DET schedule: units of each class, grouped by segment kind
     std::vector<int32_t> sched;
     std::vector<ClassPlan> classes;
@@ -111,4 +112,10 @@ void class_order(int32_t nclasses, uint64_t seed, int64_t epoch, int32_t *order)
 
 struct thetis_inst {
     thetis::Inst in;
+    std::mutex layout_mu;    // the layout is built once, on first use
 };
+
+namespace thetis {
+// builds the instance's layout if it is not built yet (thread-safe)
+thetis_status ensure_layout(const thetis_inst *h);
+}

@@ -5,7 +5,9 @@ arrive at any time.  A pool of builder threads makes each request's host
 layout (the library call releases the GIL).  Admission is by device-memory
 budget: a built request takes a slot as soon as its workspace fits in the
 budget and its batch has a free slot; otherwise it waits (first fit in
-arrival order, never dropped).  Each batch kind -- all-ones matrices (vertex
+arrival order, never dropped).  An admitted request's device state is
+allocated and uploaded by an uploader thread on its own stream, so the
+batch keeps running meanwhile; it joins the batch at the next tick.  Each batch kind -- all-ones matrices (vertex
 cover, independent set) and +-1 matrices (multiway cut) -- has one worker
 thread and one stream, so their epochs overlap on the device.  A worker
 admits waiting requests into free slots, runs `epochs_per_tick` epochs of
@@ -67,6 +69,7 @@ class _Req:
     epochs: int = 0
     t_admitted: float = 0.0
     workspace: object = None
+    upload: Optional[cf.Future] = None
 
 
 def admit(waiting, free_bytes: int, free_slots: dict, hold_from: int = -1) -> list:
@@ -108,12 +111,14 @@ class Server:
         self.closed = False
         self.next_id = 0
         self.builders = cf.ThreadPoolExecutor(max_workers=builders)
+        self.uploaders = cf.ThreadPoolExecutor(max_workers=2)
+        self._local = threading.local()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.groups = {}
         for g in ("ones", "signed"):
             stream = torch.cuda.Stream(device=self.device)
             batch = T.Batch(capacity=slots, precision=precision, unit_values=(g == "ones"), stream=stream)
-            self.groups[g] = dict(stream=stream, batch=batch, slots=[None] * slots, thread=None)
+            self.groups[g] = dict(stream=stream, batch=batch, slots=[None] * slots, thread=None, uploading=[])
         for g in self.groups:
             t = threading.Thread(target=self._worker, args=(g,), daemon=True, name=f"thetis-serve-{g}")
             self.groups[g]["thread"] = t
@@ -164,11 +169,13 @@ class Server:
         if wait:
             for g in self.groups.values():
                 g["thread"].join()
+        self.uploaders.shutdown(wait=wait)
 
     # -------------------------------------------------------------- device side
     def _admit_locked(self, g: str):
         grp = self.groups[g]
-        free = [k for k, s in enumerate(grp["slots"]) if s is None]
+        reserved = {r.slot for r in grp["uploading"]}
+        free = [k for k, s in enumerate(grp["slots"]) if s is None and k not in reserved]
         mine = [r for r in self.waiting if GROUP[r.kind] == g]
         if not mine or not free:
             return []
@@ -192,6 +199,17 @@ class Server:
             self.waiting.remove(r)
         return out
 
+    def _make_solver(self, r: _Req):
+        """Uploader thread: the request's device state, on this thread's own
+        stream (the batch waits for that stream before its first epoch)."""
+        import torch
+        loc = self._local
+        if getattr(loc, "stream", None) is None:
+            loc.stream = torch.cuda.Stream(device=self.device)
+        with torch.cuda.device(self.device), torch.cuda.stream(loc.stream):
+            return T.Solver(r.instance, beta=self.beta, precision=self.precision,
+                            refresh_every=self.tick, seed=r.seed)
+
     def _worker(self, g: str):
         import torch
         grp = self.groups[g]
@@ -200,24 +218,33 @@ class Server:
             while True:
                 with self.lock:
                     while True:
-                        new = self._admit_locked(g)
+                        for r in self._admit_locked(g):
+                            r.upload = self.uploaders.submit(self._make_solver, r)
+                            grp["uploading"].append(r)
                         busy = any(s is not None for s in grp["slots"])
-                        if new or busy:
+                        if busy or grp["uploading"]:
                             break
                         if self.closed and self.pending_builds == 0 and not any(
                                 GROUP[r.kind] == g for r in self.waiting):
                             return
                         self.cv.wait(timeout=0.05)
-                for r in new:
+                # uploaded requests join the batch
+                if grp["uploading"] and not busy:
+                    cf.wait([r.upload for r in grp["uploading"]], timeout=0.05,
+                            return_when=cf.FIRST_COMPLETED)
+                for r in [r for r in grp["uploading"] if r.upload.done()]:
+                    grp["uploading"].remove(r)
                     try:
-                        r.solver = T.Solver(r.instance, beta=self.beta, precision=self.precision,
-                                            refresh_every=self.tick, seed=r.seed)
+                        r.solver = r.upload.result()
                         r.t_admitted = time.perf_counter()
                         grp["slots"][r.slot] = r
                         batch.set(r.slot, r.solver)
                     except Exception as e:
+                        grp["slots"][r.slot] = None
                         self._release(g, r)
                         r.future.set_exception(e)
+                if not any(s is not None for s in grp["slots"]):
+                    continue
                 done = batch.run(self.tick, self.gap_tol)
                 status = batch.last_status
                 for slot, r in enumerate(grp["slots"]):
