@@ -622,43 +622,43 @@ __device__ __forceinline__ void dual_item(const Dev<P> &a, const Sched<typename 
         if (valid && lane == 0)
             v[0] = box_min(a.c[j] - acc, col_ubound(a, j), rho, a.ybar ? (double)a.ybar[j] : 0.0);
     } else if (kind == SEG_BLOCK) {
-        const int64_t u = local * kWG + threadIdx.x;
-        if (u < count) {
+        // one wavefront per block, lpc lanes per column as in the sweep; the
+        // minimum over the simplex without prox is the smallest reduced
+        // cost, with prox the value at the projection of yb - red/rho
+        const int64_t u = local * (kWG / 64) + (threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        if (u < count) {                      // the whole wavefront together
             const int32_t bl = sc.ids[first + u];
-            const int32_t j0 = a.bfirst[bl], k = a.k;
-            double red[64], yb[64];
-            for (int i = 0; i < k; ++i) {
-                const int32_t j = j0 + i;
-                double rr = a.c[j];
-                for (int32_t e = a.col_ptr[j]; e < a.col_ptr[j + 1]; ++e)
-                    rr -= (VALS ? (double)a.cval[e] : 1.0) * (double)a.udual[a.row_idx[e]];
-                red[i] = rr;
-                yb[i] = a.ybar ? (double)a.ybar[j] : 0.0;
-            }
+            const int32_t k = a.k;
+            int lpc = 64;
+            while (lpc * k > 64) lpc >>= 1;
+            const int ci = lane / lpc, sub = lane % lpc;
+            const bool own = ci < k;
+            const int32_t j = a.bfirst[bl] + (own ? ci : 0);
+            double acc = 0.0;
+            if (own)
+                for (int32_t e = a.col_ptr[j] + sub; e < a.col_ptr[j + 1]; e += lpc)
+                    acc += (VALS ? (double)a.cval[e] : 1.0) * (double)a.udual[a.row_idx[e]];
+            for (int o = lpc / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            const double red = own ? a.c[j] - acc : INFINITY;
+            double term;
             if (a.prox_on) {
-                // minimiser of red^T y + rho/2||y - yb||^2 over the simplex:
-                // projection of yb - red/rho
-                double w[64];
-                for (int i = 0; i < k; ++i) w[i] = yb[i] - red[i] / rho;
-                double theta = -INFINITY;
-                for (int q = 0; q < k; ++q) {
-                    double ps = 0.0;
-                    int cnt = 0;
-                    for (int l = 0; l < k; ++l)
-                        if (w[l] > w[q] || (w[l] == w[q] && l <= q)) { ps += w[l]; ++cnt; }
-                    theta = fmax(theta, (ps - 1.0) / cnt);
+                const double yb = own && a.ybar ? (double)a.ybar[j] : 0.0;
+                const double w = own ? yb - red / rho : 0.0;
+                const double wq = __shfl(w, (lane < k ? lane : 0) * lpc, 64);
+                double ps = 0.0;
+                int cnt = 0;
+                for (int l = 0; l < k; ++l) {
+                    const double wl = __shfl(w, l * lpc, 64);
+                    if (wl > wq || (wl == wq && l <= lane)) { ps += wl; ++cnt; }
                 }
-                double val = 0.0;
-                for (int i = 0; i < k; ++i) {
-                    const double yi = fmax(w[i] - theta, 0.0);
-                    val += red[i] * yi + 0.5 * rho * (yi - yb[i]) * (yi - yb[i]);
-                }
-                v[0] = val;
+                const double theta = wmax(lane < k ? (ps - 1.0) / cnt : -INFINITY);
+                const double yi = fmax(w - theta, 0.0);
+                term = wsum(own && sub == 0 ? red * yi + 0.5 * rho * (yi - yb) * (yi - yb) : 0.0);
             } else {
-                double mn = red[0];
-                for (int i = 1; i < k; ++i) mn = fmin(mn, red[i]);
-                v[0] = mn;
+                term = -wmax(-red);
             }
+            if (lane == 0) v[0] = term;
         }
     } else if (kind == SEG_SLACK) {
         const int64_t u = local * kWG + threadIdx.x;
@@ -1136,7 +1136,7 @@ size_t x_bytes(int32_t prec) { return prec == THETIS_PREC_FP64 ? 8 : (prec == TH
 int64_t units_per_wg(int kind, bool dual) {
     if (kind == SEG_HUB) return 1;
     if (kind < kGroupKinds) return kWG / (4 << kind);
-    if (kind == SEG_BLOCK) return dual ? kWG : kWG / 64;
+    if (kind == SEG_BLOCK) return kWG / 64;
     return kWG;
 }
 
@@ -2186,8 +2186,15 @@ __device__ __forceinline__ Share xcd_share(int64_t total, int32_t strided) {
     return s;
 }
 
+// waves per SIMD the batch sweep is compiled for: the FP32 forms fit 64
+// registers (full occupancy); the FP64 validation form keeps its registers
+template <class P>
+struct BsweepWaves {
+    static constexpr int value = sizeof(typename P::R) == 4 ? 8 : 4;
+};
+
 template <class P, bool VALS>
-__global__ __launch_bounds__(kWG) void k_bsweep(const BInst<P> *bi, const BClass *bc, const int32_t *cls,
+__global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BInst<P> *bi, const BClass *bc, const int32_t *cls,
                                                 const int64_t *start, int32_t count, int32_t strided) {
     using R = typename P::R;
     __shared__ R st_r[HubTile<P>::n];
