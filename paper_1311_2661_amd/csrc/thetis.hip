@@ -2089,74 +2089,110 @@ __global__ __launch_bounds__(kWG) void k_border(const BInst<P> *bi, int32_t coun
     if (lane < C) order[(int64_t)i * kMaxBatchClasses + rank] = (int8_t)lane;
 }
 
-// every step q of the epoch (workgroup q): each active instance's class at
-// that step and its workgroup count, and the exclusive prefix of the counts
-// (start_q has count + 1 entries)
+// A directory of the work items of one launch: the instances with work, in
+// slot order, with their class, the offset of their first item and, for
+// every kDirChunk-th item, the directory entry that owns it.  A walk finds
+// an item's instance with one table load and a short forward step, however
+// many slots are empty.
+constexpr int kDirChunk = 16;
+struct Dir {
+    int64_t *total, *start;                   // start: nact + 1 entries
+    int32_t *inst, *cls, *wtmp, *ctmp, *chunk;
+    int64_t chunk_cap;
+};
+__host__ __device__ inline int64_t dir_bytes(int32_t count, int64_t chunk_cap) {
+    const int64_t b = 8 + 8 * ((int64_t)count + 1) + 16 * (int64_t)count + 4 * chunk_cap;
+    return (b + 255) / 256 * 256;
+}
+__host__ __device__ inline Dir dir_at(char *base, int32_t count, int64_t chunk_cap, int d) {
+    char *p = base + (int64_t)d * dir_bytes(count, chunk_cap);
+    Dir r;
+    r.total = (int64_t *)p;
+    r.start = r.total + 1;
+    r.inst = (int32_t *)(r.start + count + 1);
+    r.cls = r.inst + count;
+    r.wtmp = r.cls + count;
+    r.ctmp = r.wtmp + count;
+    r.chunk = r.ctmp + count;
+    r.chunk_cap = chunk_cap;
+    return r;
+}
+
+// one workgroup: builds the directory from per-slot item counts (the
+// weight functor gives slot i's count and class)
+template <class Wf>
+__device__ void build_dir(const Dir &d, int32_t count, Wf weight) {
+    __shared__ int64_t psum[kWG + 1];
+    __shared__ int32_t pnz[kWG + 1];
+    const int t = threadIdx.x;
+    const int32_t per = (count + kWG - 1) / kWG;
+    const int32_t lo = min(count, t * per), hi = min(count, lo + per);
+    int64_t sum = 0;
+    int32_t nz = 0;
+    for (int32_t i = lo; i < hi; ++i) {
+        int32_t c = 0;
+        const int32_t w = weight(i, &c);
+        d.wtmp[i] = w;
+        d.ctmp[i] = c;
+        sum += w;
+        nz += w > 0;
+    }
+    psum[t + 1] = sum;
+    pnz[t + 1] = nz;
+    __syncthreads();
+    if (t == 0) {
+        psum[0] = 0;
+        pnz[0] = 0;
+        for (int u = 1; u <= kWG; ++u) { psum[u] += psum[u - 1]; pnz[u] += pnz[u - 1]; }
+    }
+    __syncthreads();
+    int64_t s = psum[t];
+    int32_t q = pnz[t];
+    for (int32_t i = lo; i < hi; ++i) {
+        const int32_t w = d.wtmp[i];
+        if (w == 0) continue;
+        d.inst[q] = i;
+        d.cls[q] = d.ctmp[i];
+        d.start[q] = s;
+        for (int64_t c = (s + kDirChunk - 1) / kDirChunk; c * kDirChunk < s + w && c < d.chunk_cap; ++c)
+            d.chunk[c] = q;
+        s += w;
+        ++q;
+    }
+    if (t == 0) {
+        d.start[pnz[kWG]] = psum[kWG];
+        *d.total = psum[kWG];
+    }
+}
+
+// every step q of the epoch (workgroup q): the directory of the step's items,
+// each active instance contributing its class of step q
 template <class P>
 __global__ __launch_bounds__(kWG) void k_bplan(const BInst<P> *bi, const BClass *bc, int32_t count,
-                                               const int8_t *order, int32_t *cls, int64_t *start) {
-    __shared__ int64_t part[kWG + 1];
+                                               const int8_t *order, char *dirs, int64_t chunk_cap) {
     const int32_t q = blockIdx.x;
-    int32_t *cls_q = cls + (int64_t)q * count;
-    int64_t *start_q = start + (int64_t)q * (count + 1);
-    const int t = threadIdx.x;
-    const int32_t chunk = (count + kWG - 1) / kWG;
-    const int32_t lo = t * chunk, hi = min(count, lo + chunk);
-    int64_t sum = 0;
-    for (int32_t i = lo; i < hi; ++i) {
+    const Dir d = dir_at(dirs, count, chunk_cap, q);
+    build_dir(d, count, [&](int32_t i, int32_t *c) -> int32_t {
         const BInst<P> &I = bi[i];
-        int32_t c = -1;
-        int64_t w = 0;
-        if (I.active && q < I.nclasses) {
-            c = order[(int64_t)i * kMaxBatchClasses + q];
-            const BClass &C = bc[I.class_base + c];
-            w = C.wg_cols + C.wg_block + C.wg_slack;
-        }
-        cls_q[i] = c;
-        start_q[i] = w;          // count for now, prefix below
-        sum += w;
-    }
-    part[t + 1] = sum;
-    __syncthreads();
-    if (t == 0) {
-        part[0] = 0;
-        for (int u = 1; u <= kWG; ++u) part[u] += part[u - 1];
-    }
-    __syncthreads();
-    int64_t run = part[t];
-    for (int32_t i = lo; i < hi; ++i) { const int64_t w = start_q[i]; start_q[i] = run; run += w; }
-    if (t == 0) start_q[count] = part[kWG];
+        if (!I.active || q >= I.nclasses) return 0;
+        *c = order[(int64_t)i * kMaxBatchClasses + q];
+        const BClass &C = bc[I.class_base + *c];
+        return (int32_t)(C.wg_cols + C.wg_block + C.wg_slack);
+    });
 }
 
-// exclusive prefix of `count` workgroup counts in one workgroup; start has
-// count + 1 entries, start[count] = total
-__global__ __launch_bounds__(kWG) void k_bscan(const int32_t *in, int32_t count, int64_t *start) {
-    __shared__ int64_t part[kWG + 1];
-    const int t = threadIdx.x;
-    const int32_t chunk = (count + kWG - 1) / kWG;
-    const int32_t lo = t * chunk, hi = min(count, lo + chunk);
-    int64_t sum = 0;
-    for (int32_t i = lo; i < hi; ++i) sum += in[i];
-    part[t + 1] = sum;
-    __syncthreads();
-    if (t == 0) {
-        part[0] = 0;
-        for (int u = 1; u <= kWG; ++u) part[u] += part[u - 1];
-    }
-    __syncthreads();
-    int64_t run = part[t];
-    for (int32_t i = lo; i < hi; ++i) { start[i] = run; run += in[i]; }
-    if (t == 0) start[count] = part[kWG];
+// the directory of per-slot workgroup counts (refresh passes)
+__global__ __launch_bounds__(kWG) void k_bdir(const int32_t *counts, int32_t count, char *dirs, int64_t chunk_cap,
+                                              int32_t which) {
+    const Dir d = dir_at(dirs, count, chunk_cap, which);
+    build_dir(d, count, [&](int32_t i, int32_t *c) -> int32_t { *c = 0; return counts[i]; });
 }
 
-// instance owning item `it`: the last i with start[i] <= it
-__device__ __forceinline__ int32_t owner(const int64_t *start, int32_t count, int64_t it) {
-    int32_t lo = 0, hi = count;           // invariant: start[lo] <= it < start[hi]
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (start[mid] <= it) lo = mid; else hi = mid;
-    }
-    return lo;
+// the directory entry of item `it`, from a hint at or before it
+__device__ __forceinline__ int32_t dir_find(const Dir &d, int64_t it, int32_t p, bool jump) {
+    if (jump) p = d.chunk[it / kDirChunk];
+    while (d.start[p + 1] <= it) ++p;
+    return p;
 }
 
 // this workgroup's share of `total` items.  XCD x (= block & 7) takes the
@@ -2194,19 +2230,21 @@ struct BsweepWaves {
 };
 
 template <class P, bool VALS>
-__global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BInst<P> *bi, const BClass *bc, const int32_t *cls,
-                                                const int64_t *start, int32_t count, int32_t strided) {
+__global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BInst<P> *bi, const BClass *bc,
+                                                                        char *dirs, int32_t count, int64_t chunk_cap,
+                                                                        int32_t q, int32_t strided) {
     using R = typename P::R;
     __shared__ R st_r[HubTile<P>::n];
     __shared__ int32_t st_row[HubTile<P>::n];
     __shared__ R red[kWG / 64];
-    const Share sh = xcd_share(start[count], strided);
-    int32_t i = sh.lo < sh.hi ? owner(start, count, sh.lo) : 0;
+    const Dir d = dir_at(dirs, count, chunk_cap, q);
+    const Share sh = xcd_share(*d.total, strided);
+    int32_t p = 0;
     for (int64_t it = sh.lo; it < sh.hi; it += sh.step) {
-        while (start[i + 1] <= it) ++i;
-        const BInst<P> &I = bi[i];
-        const BClass &C = bc[I.class_base + cls[i]];
-        const int64_t local = it - start[i];
+        p = dir_find(d, it, p, it == sh.lo || sh.step > 1);
+        const BInst<P> &I = bi[d.inst[p]];
+        const BClass &C = bc[I.class_base + d.cls[p]];
+        const int64_t local = it - d.start[p];
         if (local < C.wg_cols) {
             sweep_item<P, VALS>(I.a, I.sc, C.cols, local, st_r, st_row, red);
         } else if (local < C.wg_cols + C.wg_block) {
@@ -2247,27 +2285,29 @@ __global__ __launch_bounds__(kWG) void k_bepoch(BInst<P> *bi, int32_t count, int
 }
 
 template <class P>
-__global__ __launch_bounds__(kWG) void k_brows(const BInst<P> *bi, const int64_t *start, int32_t count,
-                                               int32_t strided) {
-    const Share sh = xcd_share(start[count], strided);
-    int32_t i = sh.lo < sh.hi ? owner(start, count, sh.lo) : 0;
+__global__ __launch_bounds__(kWG) void k_brows(const BInst<P> *bi, char *dirs, int32_t count, int64_t chunk_cap,
+                                               int32_t which, int32_t strided) {
+    const Dir d = dir_at(dirs, count, chunk_cap, which);
+    const Share sh = xcd_share(*d.total, strided);
+    int32_t p = 0;
     for (int64_t it = sh.lo; it < sh.hi; it += sh.step) {
-        while (start[i + 1] <= it) ++i;
-        const BInst<P> &I = bi[i];
-        rows_item<P>(I.a, it - start[i], 1, I.with_dual, I.rpart);
+        p = dir_find(d, it, p, it == sh.lo || sh.step > 1);
+        const BInst<P> &I = bi[d.inst[p]];
+        rows_item<P>(I.a, it - d.start[p], 1, I.with_dual, I.rpart);
     }
 }
 
 template <class P, bool VALS>
-__global__ __launch_bounds__(kWG) void k_bdual(const BInst<P> *bi, const int64_t *start, int32_t count,
-                                               int32_t strided) {
+__global__ __launch_bounds__(kWG) void k_bdual(const BInst<P> *bi, char *dirs, int32_t count, int64_t chunk_cap,
+                                               int32_t which, int32_t strided) {
     __shared__ double sh2[kWG / 64];
-    const Share sh = xcd_share(start[count], strided);
-    int32_t i = sh.lo < sh.hi ? owner(start, count, sh.lo) : 0;
+    const Dir d = dir_at(dirs, count, chunk_cap, which);
+    const Share sh = xcd_share(*d.total, strided);
+    int32_t p = 0;
     for (int64_t it = sh.lo; it < sh.hi; it += sh.step) {
-        while (start[i + 1] <= it) ++i;
-        const BInst<P> &I = bi[i];
-        dual_item<P, VALS>(I.a, I.asc, I.dual, it - start[i], I.slack_identity, I.cpart, sh2);
+        p = dir_find(d, it, p, it == sh.lo || sh.step > 1);
+        const BInst<P> &I = bi[d.inst[p]];
+        dual_item<P, VALS>(I.a, I.asc, I.dual, it - d.start[p], I.slack_identity, I.cpart, sh2);
     }
 }
 
@@ -2335,9 +2375,11 @@ struct thetis_batch {
     int64_t resident_wg = 2048;
     // device
     void *bi = nullptr, *bc = nullptr;
-    int32_t *cls = nullptr, *rows_wg = nullptr, *dual_wg = nullptr, *active = nullptr;
+    int32_t *rows_wg = nullptr, *dual_wg = nullptr, *active = nullptr;
     int8_t *order = nullptr;
-    int64_t *start = nullptr;
+    // item directories: one per step of an epoch, then rows and dual refresh
+    char *dirs = nullptr;
+    int64_t chunk_cap = 0;
     size_t bi_bytes = 0;
     std::vector<char> bi_host;          // host image of the BInst array
     int64_t nclass_total = 0;
@@ -2430,6 +2472,33 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
     int32_t mc = 0;
     for (thetis_solver *S : B.solvers) if (S) mc = std::max(mc, S->nclasses);
     if (mc != B.max_classes) { B.max_classes = mc; batch_drop_graph(B); }
+    // directory chunk tables: enough for the most items any launch can have
+    int64_t most = 1;
+    {
+        int64_t steps = 0, rows = 0, dual = 0;
+        for (int32_t i = 0; i < B.count; ++i) {
+            if (!B.solvers[i]) continue;
+            int64_t w = 0;
+            for (int32_t c = 0; c < bi[i].nclasses; ++c) {
+                const BClass &C = bc[bi[i].class_base + c];
+                w = std::max<int64_t>(w, C.wg_cols + C.wg_block + C.wg_slack);
+            }
+            steps += w;
+            rows += bi[i].rows_wg;
+            dual += bi[i].dual.nwg;
+        }
+        most = std::max<int64_t>({most, steps, rows, dual});
+    }
+    const int64_t cap_needed = most / kDirChunk + 2;
+    if (!B.dirs || cap_needed > B.chunk_cap) {
+        HIP_TRY(hipStreamSynchronize(B.stream));
+        if (B.dirs) (void)hipFree(B.dirs);
+        B.dirs = nullptr;
+        const int64_t cap = cap_needed * 2;
+        HIP_TRY(hipMalloc((void **)&B.dirs, dir_bytes(B.count, cap) * (kMaxBatchClasses + 2)));
+        B.chunk_cap = cap;
+        batch_drop_graph(B);                 // the captured launches point at the old tables
+    }
     HIP_TRY(hipMemcpyAsync(B.bi, bi.data(), sizeof(BInst<P>) * B.count, hipMemcpyHostToDevice, B.stream));
     if (!bc.empty())
         HIP_TRY(hipMemcpyAsync(B.bc, bc.data(), sizeof(BClass) * bc.size(), hipMemcpyHostToDevice, B.stream));
@@ -2447,20 +2516,18 @@ void batch_epoch_launches(thetis_batch &B) {
     const BClass *bc = (const BClass *)B.bc;
     hipLaunchKernelGGL((k_border<P>), dim3(cdiv(n, kWG / 64)), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, n, B.order);
     hipLaunchKernelGGL((k_bplan<P>), dim3(std::max(B.max_classes, 1)), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, bc, n,
-                       (const int8_t *)B.order, B.cls, B.start);
+                       (const int8_t *)B.order, B.dirs, B.chunk_cap);
     for (int32_t q = 0; q < B.max_classes; ++q) {
-        const int32_t *cls_q = B.cls + (int64_t)q * n;
-        const int64_t *start_q = B.start + (int64_t)q * (n + 1);
-        if (B.vals) hipLaunchKernelGGL((k_bsweep<P, true>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, cls_q, start_q, n, B.strided);
-        else hipLaunchKernelGGL((k_bsweep<P, false>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, cls_q, start_q, n, B.strided);
+        if (B.vals) hipLaunchKernelGGL((k_bsweep<P, true>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, B.dirs, n, B.chunk_cap, q, B.strided);
+        else hipLaunchKernelGGL((k_bsweep<P, false>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, B.dirs, n, B.chunk_cap, q, B.strided);
     }
-    int64_t *start_r = B.start + (int64_t)kMaxBatchClasses * (n + 1);   // refresh offsets
+    const int32_t d_rows = kMaxBatchClasses, d_dual = kMaxBatchClasses + 1;
     hipLaunchKernelGGL((k_bepoch<P>), dim3(gi), dim3(kWG), 0, B.stream, bi, n, B.rows_wg, B.dual_wg);
-    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.rows_wg, n, start_r);
-    hipLaunchKernelGGL((k_brows<P>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)start_r, n, B.strided);
-    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.dual_wg, n, start_r);
-    if (B.vals) hipLaunchKernelGGL((k_bdual<P, true>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)start_r, n, B.strided);
-    else hipLaunchKernelGGL((k_bdual<P, false>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, (const int64_t *)start_r, n, B.strided);
+    hipLaunchKernelGGL(k_bdir, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.rows_wg, n, B.dirs, B.chunk_cap, d_rows);
+    hipLaunchKernelGGL(k_bdir, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.dual_wg, n, B.dirs, B.chunk_cap, d_dual);
+    hipLaunchKernelGGL((k_brows<P>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, B.dirs, n, B.chunk_cap, d_rows, B.strided);
+    if (B.vals) hipLaunchKernelGGL((k_bdual<P, true>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, B.dirs, n, B.chunk_cap, d_dual, B.strided);
+    else hipLaunchKernelGGL((k_bdual<P, false>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, B.dirs, n, B.chunk_cap, d_dual, B.strided);
     hipLaunchKernelGGL((k_bfinal<P>), dim3(std::min<int64_t>(n, 1024)), dim3(kWG), 0, B.stream, bi, n);
     hipLaunchKernelGGL((k_bwindow<P>), dim3(1), dim3(kWG), 0, B.stream, bi, n, B.window > 0 ? B.window : n, B.active);
 }
@@ -2627,13 +2694,9 @@ extern "C" thetis_status thetis_batch_create(int32_t capacity, thetis_solver *co
     const int32_t count = capacity;
     const size_t nb = binst_bytes(B.precision);
     hipError_t e = hipMalloc(&B.bi, nb * count);
-    // per-step classes and offsets of every step of an epoch; the offsets
-    // have one more block for the refresh passes
-    if (e == hipSuccess) e = hipMalloc((void **)&B.cls, (size_t)4 * kMaxBatchClasses * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.rows_wg, 4 * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.dual_wg, 4 * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.active, 4);
-    if (e == hipSuccess) e = hipMalloc((void **)&B.start, (size_t)8 * (kMaxBatchClasses + 1) * (count + 1));
     if (e == hipSuccess) e = hipMalloc((void **)&B.order, (size_t)kMaxBatchClasses * count);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -2750,11 +2813,10 @@ extern "C" thetis_status thetis_batch_destroy(thetis_batch *b) {
     batch_drop_graph(*b);
     (void)hipFree(b->bi);
     if (b->bc) (void)hipFree(b->bc);
-    (void)hipFree(b->cls);
     (void)hipFree(b->rows_wg);
     (void)hipFree(b->dual_wg);
     (void)hipFree(b->active);
-    (void)hipFree(b->start);
+    if (b->dirs) (void)hipFree(b->dirs);
     (void)hipFree(b->order);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
