@@ -295,8 +295,9 @@ thetis_status thetis_batch_run(thetis_batch *b, int32_t max_epochs, double gap_t
  * (1 + epochs_per_candidate per candidate, counted as epochs of the solve).
  * First the per-column shape: lanes per column widened 1x or 2x beyond the
  * degree bound, or 1, 2 or 4 columns per lane group; then, with that shape,
- * 1, 2 or 4 times the resident workgroup count for the work-queue kernels
- * and contiguous or strided walks of each XCD's share of the work items.
+ * one workgroup per work item or 1, 2 or 4 times the resident workgroup
+ * count walking the items, and contiguous or strided walks of each XCD's
+ * share of the work items.
  * Every candidate computes bit-identical results.  The choice is cached per
  * batch shape (instance count, entries, largest degree, precision) for the
  * life of the process; choice_host (NULL or 4 ints) receives (widen, grid
@@ -304,7 +305,8 @@ thetis_status thetis_batch_run(thetis_batch *b, int32_t max_epochs, double gap_t
 thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_per_candidate, int32_t *choice_host);
 
 /* Sets the launch configuration directly: widen in {1,2,4}, grid multiplier
- * in {1,2,4,8}, strided in {0,1}, columns per lane group in {1,2,4} (at most
+ * in {0,1,2,4,8} (0: one workgroup per work item), strided in {0,1},
+ * columns per lane group in {1,2,4} (at most
  * 2 where a column takes 64 lanes).  Defaults: 1, 2, 1, 4.  Results do not
  * depend on it. */
 thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult, int32_t strided,

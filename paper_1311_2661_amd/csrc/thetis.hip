@@ -2229,8 +2229,11 @@ struct BsweepWaves {
     static constexpr int value = sizeof(typename P::R) == 4 ? 8 : 4;
 };
 
+// bi and bc are only read while the sweep runs (restrict: the sweep's stores
+// cannot change them, so their fields are loaded once, as scalars)
 template <class P, bool VALS>
-__global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BInst<P> *bi, const BClass *bc,
+__global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BInst<P> *__restrict__ bi,
+                                                                        const BClass *__restrict__ bc,
                                                                         char *dirs, int32_t count, int64_t chunk_cap,
                                                                         int32_t q, int32_t strided) {
     using R = typename P::R;
@@ -2245,21 +2248,28 @@ __global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BIn
         const BInst<P> &I = bi[d.inst[p]];
         const BClass &C = bc[I.class_base + d.cls[p]];
         const int64_t local = it - d.start[p];
-        if (local < C.wg_cols) {
-            sweep_item<P, VALS>(I.a, I.sc, C.cols, local, st_r, st_row, red);
-        } else if (local < C.wg_cols + C.wg_block) {
+        const Dev<P> &a = I.a;
+        const Sched<R> &sc = I.sc;
+        const int64_t wg_cols = C.wg_cols, wg_block = C.wg_block;
+        if (local < wg_cols) {
+            sweep_item<P, VALS>(a, sc, C.cols, local, st_r, st_row, red);
+        } else if (local < wg_cols + wg_block) {
             // kBatchBlocks blocks per wavefront
-            const int64_t base = (local - C.wg_cols) * (kWG / 64) * kBatchBlocks + (threadIdx.x >> 6);
+            const int64_t first = C.block_first, count = C.block_count;
+            const int32_t lpc = I.lpc;
+            const int64_t base = (local - wg_cols) * (kWG / 64) * kBatchBlocks + (threadIdx.x >> 6);
             for (int b = 0; b < kBatchBlocks; ++b) {
                 const int64_t u = base + b * (kWG / 64);
-                if (u < C.block_count) sweep_block<P, VALS>(I.a, I.sc.ids[C.block_first + u], I.lpc);
+                if (u < count) sweep_block<P, VALS>(a, sc.ids[first + u], lpc);
             }
         } else {
             // kBatchSlacks slacks per thread
-            const int64_t base = (local - C.wg_cols - C.wg_block) * kWG * kBatchSlacks + threadIdx.x;
+            const int64_t first = C.slack_first, count = C.slack_count;
+            const bool ident = I.slack_identity;
+            const int64_t base = (local - wg_cols - wg_block) * kWG * kBatchSlacks + threadIdx.x;
             for (int b = 0; b < kBatchSlacks; ++b) {
                 const int64_t u = base + b * kWG;
-                if (u < C.slack_count) sweep_slack<P>(I.a, I.slack_identity ? u : I.sc.ids[C.slack_first + u]);
+                if (u < count) sweep_slack<P>(a, ident ? u : sc.ids[first + u]);
             }
         }
     }
@@ -2285,7 +2295,7 @@ __global__ __launch_bounds__(kWG) void k_bepoch(BInst<P> *bi, int32_t count, int
 }
 
 template <class P>
-__global__ __launch_bounds__(kWG) void k_brows(const BInst<P> *bi, char *dirs, int32_t count, int64_t chunk_cap,
+__global__ __launch_bounds__(kWG) void k_brows(const BInst<P> *__restrict__ bi, char *dirs, int32_t count, int64_t chunk_cap,
                                                int32_t which, int32_t strided) {
     const Dir d = dir_at(dirs, count, chunk_cap, which);
     const Share sh = xcd_share(*d.total, strided);
@@ -2298,7 +2308,7 @@ __global__ __launch_bounds__(kWG) void k_brows(const BInst<P> *bi, char *dirs, i
 }
 
 template <class P, bool VALS>
-__global__ __launch_bounds__(kWG) void k_bdual(const BInst<P> *bi, char *dirs, int32_t count, int64_t chunk_cap,
+__global__ __launch_bounds__(kWG) void k_bdual(const BInst<P> *__restrict__ bi, char *dirs, int32_t count, int64_t chunk_cap,
                                                int32_t which, int32_t strided) {
     __shared__ double sh2[kWG / 64];
     const Dir d = dir_at(dirs, count, chunk_cap, which);
@@ -2371,6 +2381,7 @@ struct thetis_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int widen = 1, grid_mult = 2, strided = 1, cols = 4;
+    int64_t most_items = 1;             // the largest item count of any launch
     int32_t window = 0;                 // most instances running at once (0: all)
     int64_t resident_wg = 2048;
     // device
@@ -2386,7 +2397,8 @@ struct thetis_batch {
     // captured epoch
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int captured_widen = 0, captured_grid = 0, captured_strided = -1, captured_cols = 0, captured_window = -1;
+    int captured_widen = 0, captured_grid = -1, captured_strided = -1, captured_cols = 0, captured_window = -1;
+    int64_t captured_most = 0;
     uint64_t signature = 0;
 };
 
@@ -2489,6 +2501,7 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
         }
         most = std::max<int64_t>({most, steps, rows, dual});
     }
+    B.most_items = most;
     const int64_t cap_needed = most / kDirChunk + 2;
     if (!B.dirs || cap_needed > B.chunk_cap) {
         HIP_TRY(hipStreamSynchronize(B.stream));
@@ -2511,7 +2524,11 @@ template <class P>
 void batch_epoch_launches(thetis_batch &B) {
     const int32_t n = B.count;
     const int64_t gi = cdiv(n, kWG);
-    const int64_t grid = std::max<int64_t>(8, (B.resident_wg * B.grid_mult) / 8 * 8);
+    // grid_mult 0: one workgroup per work item of the largest launch (the
+    // hardware dispatcher balances the items); else a multiple of the
+    // resident workgroups walking the items
+    const int64_t grid = B.grid_mult > 0 ? std::max<int64_t>(8, (B.resident_wg * B.grid_mult) / 8 * 8)
+                                         : std::max<int64_t>(8, (B.most_items + 7) / 8 * 8);
     BInst<P> *bi = (BInst<P> *)B.bi;
     const BClass *bc = (const BClass *)B.bc;
     hipLaunchKernelGGL((k_border<P>), dim3(cdiv(n, kWG / 64)), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, n, B.order);
@@ -2542,6 +2559,7 @@ thetis_status batch_capture(thetis_batch &B) {
     HIP_TRY(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
     B.captured_widen = B.widen;
     B.captured_grid = B.grid_mult;
+    B.captured_most = B.most_items;
     B.captured_strided = B.strided;
     B.captured_cols = B.cols;
     B.captured_window = B.window;
@@ -2555,6 +2573,7 @@ thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol
     thetis_status st = batch_upload<P>(B, max_epochs, gap_tol);
     if (st) return st;
     if (!B.exec || B.captured_widen != B.widen || B.captured_grid != B.grid_mult || B.captured_strided != B.strided ||
+        (B.grid_mult == 0 && B.captured_most != B.most_items) ||
         B.captured_cols != B.cols || B.captured_window != B.window) {
         st = batch_capture<P>(B);
         if (st) return st;
@@ -2739,8 +2758,8 @@ extern "C" thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, 
     clear_error();
     if (!b) return fail(THETIS_EINVAL, "batch is NULL");
     if (widen != 1 && widen != 2 && widen != 4) return fail(THETIS_EINVAL, "widen must be 1, 2 or 4");
-    if (grid_mult != 1 && grid_mult != 2 && grid_mult != 4 && grid_mult != 8)
-        return fail(THETIS_EINVAL, "grid multiplier must be 1, 2, 4 or 8");
+    if (grid_mult != 0 && grid_mult != 1 && grid_mult != 2 && grid_mult != 4 && grid_mult != 8)
+        return fail(THETIS_EINVAL, "grid multiplier must be 0 (one workgroup per item), 1, 2, 4 or 8");
     if (strided != 0 && strided != 1) return fail(THETIS_EINVAL, "strided must be 0 or 1");
     if (cols != 1 && cols != 2 && cols != 4) return fail(THETIS_EINVAL, "cols must be 1, 2 or 4");
     b->widen = widen;
@@ -2782,7 +2801,7 @@ extern "C" thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_p
     }
     const Choice base = best;
     for (int st = 0; st < 2; ++st)
-        for (int g : {1, 2, 4}) {
+        for (int g : {0, 1, 2, 4}) {
             const Choice c{base.widen, g, st, base.cols};
             if (g == base.grid_mult && st == base.strided) continue;
             double ms = 0;

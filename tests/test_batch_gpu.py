@@ -87,7 +87,8 @@ def test_batch_multiway_cut_blocks():
 
 
 @pytest.mark.parametrize("widen,grid,strided,cols", [(1, 1, 1, 1), (2, 4, 0, 1), (4, 8, 1, 1), (1, 8, 0, 1),
-                                                     (1, 2, 1, 2), (1, 1, 0, 4), (2, 2, 1, 4), (4, 1, 1, 4)])
+                                                     (1, 2, 1, 2), (1, 1, 0, 4), (2, 2, 1, 4), (4, 1, 1, 4),
+                                                     (1, 0, 1, 4), (1, 0, 0, 1)])
 def test_batch_launch_configuration_does_not_change_results(widen, grid, strided, cols):
     insts = mixed_instances()[:4]
     alone, batched = pair(insts)
@@ -106,7 +107,7 @@ def test_batch_autotune_and_continue():
     alone, batched = pair(insts)
     b = T.Batch(batched)
     w, g, st, c = b.autotune(epochs_per_candidate=2)
-    assert w in (1, 2) and g in (1, 2, 4) and st in (0, 1) and c in (1, 2, 4)
+    assert w in (1, 2) and g in (0, 1, 2, 4) and st in (0, 1) and c in (1, 2, 4)
     ran = batched[0].epoch            # the tuner's epochs are real epochs
     b.run(10)
     for sa in alone:
