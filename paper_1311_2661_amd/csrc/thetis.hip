@@ -2068,14 +2068,22 @@ constexpr int kMaxBatchClasses = 64;
 constexpr int kBatchBlocks = 4;
 constexpr int kBatchSlacks = 4;
 
+// The running instances: alist[0 .. ctl[CTL_NACT]) holds their slots in
+// slot order, and the per-epoch kernels visit only those.  ctl[CTL_CURSOR]
+// is the first slot not yet considered for a start, ctl[CTL_PENDING] the
+// number of waiting slots, ctl[CTL_LEFT] running + waiting (read by the host).
+enum { CTL_NACT = 0, CTL_CURSOR, CTL_PENDING, CTL_LEFT, CTL_N };
+
 // class order of every active instance for its current epoch: classes
 // sorted by (Philox word, class id).  One wavefront per instance, lane c
 // draws the word of class c and counts the classes ahead of it.
 template <class P>
-__global__ __launch_bounds__(kWG) void k_border(const BInst<P> *bi, int32_t count, int8_t *order) {
-    const int32_t i = blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
+__global__ __launch_bounds__(kWG) void k_border(const BInst<P> *bi, const int32_t *alist, const int32_t *ctl,
+                                                int8_t *order) {
+    const int32_t w = blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (i >= count) return;               // the whole wavefront leaves together
+    if (w >= ctl[CTL_NACT]) return;       // the whole wavefront leaves together
+    const int32_t i = alist[w];
     const BInst<P> &I = bi[i];
     if (!I.active) return;
     const int32_t C = I.nclasses;
@@ -2097,11 +2105,11 @@ __global__ __launch_bounds__(kWG) void k_border(const BInst<P> *bi, int32_t coun
 constexpr int kDirChunk = 16;
 struct Dir {
     int64_t *total, *start;                   // start: nact + 1 entries
-    int32_t *inst, *cls, *wtmp, *ctmp, *chunk;
+    int32_t *inst, *cls, *wtmp, *ctmp, *itmp, *chunk;
     int64_t chunk_cap;
 };
 __host__ __device__ inline int64_t dir_bytes(int32_t count, int64_t chunk_cap) {
-    const int64_t b = 8 + 8 * ((int64_t)count + 1) + 16 * (int64_t)count + 4 * chunk_cap;
+    const int64_t b = 8 + 8 * ((int64_t)count + 1) + 20 * (int64_t)count + 4 * chunk_cap;
     return (b + 255) / 256 * 256;
 }
 __host__ __device__ inline Dir dir_at(char *base, int32_t count, int64_t chunk_cap, int d) {
@@ -2113,13 +2121,14 @@ __host__ __device__ inline Dir dir_at(char *base, int32_t count, int64_t chunk_c
     r.cls = r.inst + count;
     r.wtmp = r.cls + count;
     r.ctmp = r.wtmp + count;
-    r.chunk = r.ctmp + count;
+    r.itmp = r.ctmp + count;
+    r.chunk = r.itmp + count;
     r.chunk_cap = chunk_cap;
     return r;
 }
 
-// one workgroup: builds the directory from per-slot item counts (the
-// weight functor gives slot i's count and class)
+// one workgroup: builds the directory from n entries (the weight functor
+// gives entry k's item count, class and slot)
 template <class Wf>
 __device__ void build_dir(const Dir &d, int32_t count, Wf weight) {
     __shared__ int64_t psum[kWG + 1];
@@ -2130,10 +2139,11 @@ __device__ void build_dir(const Dir &d, int32_t count, Wf weight) {
     int64_t sum = 0;
     int32_t nz = 0;
     for (int32_t i = lo; i < hi; ++i) {
-        int32_t c = 0;
-        const int32_t w = weight(i, &c);
+        int32_t c = 0, id = i;
+        const int32_t w = weight(i, &c, &id);
         d.wtmp[i] = w;
         d.ctmp[i] = c;
+        d.itmp[i] = id;
         sum += w;
         nz += w > 0;
     }
@@ -2151,7 +2161,7 @@ __device__ void build_dir(const Dir &d, int32_t count, Wf weight) {
     for (int32_t i = lo; i < hi; ++i) {
         const int32_t w = d.wtmp[i];
         if (w == 0) continue;
-        d.inst[q] = i;
+        d.inst[q] = d.itmp[i];
         d.cls[q] = d.ctmp[i];
         d.start[q] = s;
         for (int64_t c = (s + kDirChunk - 1) / kDirChunk; c * kDirChunk < s + w && c < d.chunk_cap; ++c)
@@ -2169,10 +2179,13 @@ __device__ void build_dir(const Dir &d, int32_t count, Wf weight) {
 // each active instance contributing its class of step q
 template <class P>
 __global__ __launch_bounds__(kWG) void k_bplan(const BInst<P> *bi, const BClass *bc, int32_t count,
-                                               const int8_t *order, char *dirs, int64_t chunk_cap) {
+                                               const int32_t *alist, const int32_t *ctl, const int8_t *order,
+                                               char *dirs, int64_t chunk_cap) {
     const int32_t q = blockIdx.x;
     const Dir d = dir_at(dirs, count, chunk_cap, q);
-    build_dir(d, count, [&](int32_t i, int32_t *c) -> int32_t {
+    build_dir(d, ctl[CTL_NACT], [&](int32_t k, int32_t *c, int32_t *id) -> int32_t {
+        const int32_t i = alist[k];
+        *id = i;
         const BInst<P> &I = bi[i];
         if (!I.active || q >= I.nclasses) return 0;
         *c = order[(int64_t)i * kMaxBatchClasses + q];
@@ -2181,11 +2194,16 @@ __global__ __launch_bounds__(kWG) void k_bplan(const BInst<P> *bi, const BClass 
     });
 }
 
-// the directory of per-slot workgroup counts (refresh passes)
-__global__ __launch_bounds__(kWG) void k_bdir(const int32_t *counts, int32_t count, char *dirs, int64_t chunk_cap,
-                                              int32_t which) {
+// the directory of the running instances' workgroup counts (refresh
+// passes; counts[k] belongs to alist[k])
+__global__ __launch_bounds__(kWG) void k_bdir(const int32_t *counts, const int32_t *alist, const int32_t *ctl,
+                                              int32_t count, char *dirs, int64_t chunk_cap, int32_t which) {
     const Dir d = dir_at(dirs, count, chunk_cap, which);
-    build_dir(d, count, [&](int32_t i, int32_t *c) -> int32_t { *c = 0; return counts[i]; });
+    build_dir(d, ctl[CTL_NACT], [&](int32_t k, int32_t *c, int32_t *id) -> int32_t {
+        *c = 0;
+        *id = alist[k];
+        return counts[k];
+    });
 }
 
 // the directory entry of item `it`, from a hint at or before it
@@ -2276,10 +2294,11 @@ __global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BIn
 }
 
 template <class P>
-__global__ __launch_bounds__(kWG) void k_bepoch(BInst<P> *bi, int32_t count, int32_t *rows_wg, int32_t *dual_wg) {
-    const int32_t i = blockIdx.x * kWG + threadIdx.x;
-    if (i >= count) return;
-    BInst<P> &I = bi[i];
+__global__ __launch_bounds__(kWG) void k_bepoch(BInst<P> *bi, const int32_t *alist, const int32_t *ctl,
+                                                int32_t *rows_wg, int32_t *dual_wg) {
+    const int32_t k = blockIdx.x * kWG + threadIdx.x;
+    if (k >= ctl[CTL_NACT]) return;
+    BInst<P> &I = bi[alist[k]];
     int32_t rw = 0, dw = 0;
     if (I.active) {
         I.epoch += 1;
@@ -2290,8 +2309,8 @@ __global__ __launch_bounds__(kWG) void k_bepoch(BInst<P> *bi, int32_t count, int
     } else {
         I.due = 0;
     }
-    rows_wg[i] = rw;
-    dual_wg[i] = dw;
+    rows_wg[k] = rw;
+    dual_wg[k] = dw;
 }
 
 template <class P>
@@ -2324,9 +2343,10 @@ __global__ __launch_bounds__(kWG) void k_bdual(const BInst<P> *__restrict__ bi, 
 // one workgroup per due instance: fold its partials into its metrics, then
 // retire it on a reached gap, the epoch cap or a NaN
 template <class P>
-__global__ __launch_bounds__(kWG) void k_bfinal(BInst<P> *bi, int32_t count) {
-    for (int32_t i = blockIdx.x; i < count; i += gridDim.x) {
-        BInst<P> &I = bi[i];
+__global__ __launch_bounds__(kWG) void k_bfinal(BInst<P> *bi, const int32_t *alist, const int32_t *ctl) {
+    const int32_t n = ctl[CTL_NACT];
+    for (int32_t k = blockIdx.x; k < n; k += gridDim.x) {
+        BInst<P> &I = bi[alist[k]];
         if (!I.due) continue;
         finalize_item(I.rpart, I.rows_wg, I.cpart, I.dual.nwg, I.beta, I.with_dual, I.metrics);
         if (threadIdx.x == 0) {
@@ -2340,35 +2360,79 @@ __global__ __launch_bounds__(kWG) void k_bfinal(BInst<P> *bi, int32_t count) {
     }
 }
 
-// end of an epoch, one workgroup: waiting instances take the places of
-// retired ones in slot order until `window` run at once; left[0] receives
-// the number of instances running or waiting
+// end of an epoch, one workgroup: the running list drops the instances that
+// retired, then waiting slots (in slot order, from the cursor) start until
+// `window` run at once
 template <class P>
-__global__ __launch_bounds__(kWG) void k_bwindow(BInst<P> *bi, int32_t count, int32_t window, int32_t *left) {
-    __shared__ int32_t pend[kWG + 1];
-    __shared__ int32_t n_active;
+__global__ __launch_bounds__(kWG) void k_bwindow(BInst<P> *bi, int32_t count, int32_t window, int32_t *alist,
+                                                 int32_t *ctl) {
+    __shared__ int32_t part[kWG + 1];
+    __shared__ int32_t keep[kWG];
+    __shared__ int32_t n_run, cursor, pending;
     const int t = threadIdx.x;
-    const int32_t chunk = (count + kWG - 1) / kWG;
-    const int32_t lo = t * chunk, hi = min(count, lo + chunk);
-    int32_t act = 0, np = 0;
-    for (int32_t i = lo; i < hi; ++i) { act += bi[i].active; np += bi[i].pending; }
-    if (t == 0) n_active = 0;
-    pend[t + 1] = np;
+    const int32_t n = ctl[CTL_NACT];
+    if (t == 0) { n_run = 0; cursor = ctl[CTL_CURSOR]; pending = ctl[CTL_PENDING]; }
     __syncthreads();
-    atomicAdd(&n_active, act);           // integer sum: exact in any order
+    // compaction in kWG-wide rounds: entries only move to lower positions,
+    // and a round reads all of its entries before any is written
+    for (int32_t base = 0; base < n; base += kWG) {
+        const int32_t k = base + t;
+        const int32_t slot = k < n ? alist[k] : -1;
+        const int32_t alive = slot >= 0 && bi[slot].active ? 1 : 0;
+        keep[t] = alive;
+        __syncthreads();
+        if (t == 0) {
+            part[0] = 0;
+            for (int u = 0; u < kWG; ++u) part[u + 1] = part[u] + keep[u];
+        }
+        __syncthreads();
+        if (alive) alist[n_run + part[t]] = slot;
+        __syncthreads();
+        if (t == 0) n_run += part[kWG];
+        __syncthreads();
+    }
+    // starts: scan the slots after the cursor, kWG at a time
+    while (n_run < window && pending > 0 && cursor < count) {
+        const int32_t s = cursor + t;
+        const int32_t waiting = s < count && bi[s].pending ? 1 : 0;
+        keep[t] = waiting;
+        __syncthreads();
+        if (t == 0) {
+            part[0] = 0;
+            for (int u = 0; u < kWG; ++u) part[u + 1] = part[u] + keep[u];
+        }
+        __syncthreads();
+        const int32_t room = window - n_run;
+        const int32_t rank = part[t];
+        if (waiting && rank < room) {
+            bi[s].pending = 0;
+            bi[s].active = 1;
+            alist[n_run + rank] = s;
+        }
+        __syncthreads();
+        if (t == 0) {
+            const int32_t started = min(room, part[kWG]);
+            // the cursor stops after the last slot started when the room ran out
+            int32_t adv = kWG;
+            if (part[kWG] > room) {
+                // the last slot started is the first u with room waiting
+                // slots in [0, u]; the slots after it are looked at again
+                int u = 0;
+                while (part[u + 1] < room) ++u;
+                adv = u + 1;
+            }
+            cursor += adv;
+            n_run += started;
+            pending -= started;
+        }
+        __syncthreads();
+    }
     if (t == 0) {
-        pend[0] = 0;
-        for (int u = 1; u <= kWG; ++u) pend[u] += pend[u - 1];
+        ctl[CTL_NACT] = n_run;
+        ctl[CTL_CURSOR] = cursor;
+        ctl[CTL_PENDING] = pending;
+        ctl[CTL_LEFT] = n_run + pending;
     }
-    __syncthreads();
-    const int32_t room = max(0, window - n_active);
-    int32_t rank = pend[t];              // waiting instances in earlier slots
-    for (int32_t i = lo; i < hi; ++i) {
-        if (!bi[i].pending) continue;
-        if (rank < room) { bi[i].pending = 0; bi[i].active = 1; }
-        ++rank;
-    }
-    if (t == 0) left[0] = n_active + pend[kWG];
 }
 
 }  // namespace
@@ -2386,7 +2450,8 @@ struct thetis_batch {
     int64_t resident_wg = 2048;
     // device
     void *bi = nullptr, *bc = nullptr;
-    int32_t *rows_wg = nullptr, *dual_wg = nullptr, *active = nullptr;
+    int32_t *rows_wg = nullptr, *dual_wg = nullptr;
+    int32_t *alist = nullptr, *ctl = nullptr;      // running slots, window control (CTL_*)
     int8_t *order = nullptr;
     // item directories: one per step of an epoch, then rows and dual refresh
     char *dirs = nullptr;
@@ -2512,6 +2577,20 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
         B.chunk_cap = cap;
         batch_drop_graph(B);                 // the captured launches point at the old tables
     }
+    // the running list and window control: the first `window` occupied
+    // slots run, the rest wait from the first waiting slot on
+    std::vector<int32_t> alist;
+    int32_t ctl[CTL_N] = {0, B.count, 0, 0};
+    for (int32_t i = 0; i < B.count; ++i) {
+        if (!B.solvers[i]) continue;
+        if (bi[i].active) alist.push_back(i);
+        else if (bi[i].pending) { ctl[CTL_PENDING]++; ctl[CTL_CURSOR] = std::min(ctl[CTL_CURSOR], i); }
+    }
+    ctl[CTL_NACT] = (int32_t)alist.size();
+    ctl[CTL_LEFT] = ctl[CTL_NACT] + ctl[CTL_PENDING];
+    if (!alist.empty())
+        HIP_TRY(hipMemcpyAsync(B.alist, alist.data(), 4 * alist.size(), hipMemcpyHostToDevice, B.stream));
+    HIP_TRY(hipMemcpyAsync(B.ctl, ctl, sizeof(ctl), hipMemcpyHostToDevice, B.stream));
     HIP_TRY(hipMemcpyAsync(B.bi, bi.data(), sizeof(BInst<P>) * B.count, hipMemcpyHostToDevice, B.stream));
     if (!bc.empty())
         HIP_TRY(hipMemcpyAsync(B.bc, bc.data(), sizeof(BClass) * bc.size(), hipMemcpyHostToDevice, B.stream));
@@ -2523,7 +2602,6 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
 template <class P>
 void batch_epoch_launches(thetis_batch &B) {
     const int32_t n = B.count;
-    const int64_t gi = cdiv(n, kWG);
     // grid_mult 0: one workgroup per work item of the largest launch (the
     // hardware dispatcher balances the items); else a multiple of the
     // resident workgroups walking the items
@@ -2531,22 +2609,28 @@ void batch_epoch_launches(thetis_batch &B) {
                                          : std::max<int64_t>(8, (B.most_items + 7) / 8 * 8);
     BInst<P> *bi = (BInst<P> *)B.bi;
     const BClass *bc = (const BClass *)B.bc;
-    hipLaunchKernelGGL((k_border<P>), dim3(cdiv(n, kWG / 64)), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, n, B.order);
+    const int32_t win = B.window > 0 ? std::min(B.window, n) : n;
+    hipLaunchKernelGGL((k_border<P>), dim3(cdiv(win, kWG / 64)), dim3(kWG), 0, B.stream, (const BInst<P> *)bi,
+                       (const int32_t *)B.alist, (const int32_t *)B.ctl, B.order);
     hipLaunchKernelGGL((k_bplan<P>), dim3(std::max(B.max_classes, 1)), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, bc, n,
-                       (const int8_t *)B.order, B.dirs, B.chunk_cap);
+                       (const int32_t *)B.alist, (const int32_t *)B.ctl, (const int8_t *)B.order, B.dirs, B.chunk_cap);
     for (int32_t q = 0; q < B.max_classes; ++q) {
         if (B.vals) hipLaunchKernelGGL((k_bsweep<P, true>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, B.dirs, n, B.chunk_cap, q, B.strided);
         else hipLaunchKernelGGL((k_bsweep<P, false>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, B.dirs, n, B.chunk_cap, q, B.strided);
     }
     const int32_t d_rows = kMaxBatchClasses, d_dual = kMaxBatchClasses + 1;
-    hipLaunchKernelGGL((k_bepoch<P>), dim3(gi), dim3(kWG), 0, B.stream, bi, n, B.rows_wg, B.dual_wg);
-    hipLaunchKernelGGL(k_bdir, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.rows_wg, n, B.dirs, B.chunk_cap, d_rows);
-    hipLaunchKernelGGL(k_bdir, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.dual_wg, n, B.dirs, B.chunk_cap, d_dual);
+    hipLaunchKernelGGL((k_bepoch<P>), dim3(cdiv(win, kWG)), dim3(kWG), 0, B.stream, bi, (const int32_t *)B.alist,
+                       (const int32_t *)B.ctl, B.rows_wg, B.dual_wg);
+    hipLaunchKernelGGL(k_bdir, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.rows_wg, (const int32_t *)B.alist,
+                       (const int32_t *)B.ctl, n, B.dirs, B.chunk_cap, d_rows);
+    hipLaunchKernelGGL(k_bdir, dim3(1), dim3(kWG), 0, B.stream, (const int32_t *)B.dual_wg, (const int32_t *)B.alist,
+                       (const int32_t *)B.ctl, n, B.dirs, B.chunk_cap, d_dual);
     hipLaunchKernelGGL((k_brows<P>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, B.dirs, n, B.chunk_cap, d_rows, B.strided);
     if (B.vals) hipLaunchKernelGGL((k_bdual<P, true>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, B.dirs, n, B.chunk_cap, d_dual, B.strided);
     else hipLaunchKernelGGL((k_bdual<P, false>), dim3(grid), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, B.dirs, n, B.chunk_cap, d_dual, B.strided);
-    hipLaunchKernelGGL((k_bfinal<P>), dim3(std::min<int64_t>(n, 1024)), dim3(kWG), 0, B.stream, bi, n);
-    hipLaunchKernelGGL((k_bwindow<P>), dim3(1), dim3(kWG), 0, B.stream, bi, n, B.window > 0 ? B.window : n, B.active);
+    hipLaunchKernelGGL((k_bfinal<P>), dim3(std::min<int64_t>(win, 1024)), dim3(kWG), 0, B.stream, bi,
+                       (const int32_t *)B.alist, (const int32_t *)B.ctl);
+    hipLaunchKernelGGL((k_bwindow<P>), dim3(1), dim3(kWG), 0, B.stream, bi, n, win, B.alist, B.ctl);
 }
 
 template <class P>
@@ -2595,7 +2679,7 @@ thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol
         HIP_TRY(hipGraphLaunch(B.exec, B.stream));
         if ((gap_tol > 0.0 || windowed) && (e + 1) % refresh_min == 0 && e + 1 < replays) {
             int32_t act = 0;
-            HIP_TRY(hipMemcpyAsync(&act, B.active, 4, hipMemcpyDeviceToHost, B.stream));
+            HIP_TRY(hipMemcpyAsync(&act, B.ctl + CTL_LEFT, 4, hipMemcpyDeviceToHost, B.stream));
             HIP_TRY(hipStreamSynchronize(B.stream));
             if (act == 0) break;
         }
@@ -2715,7 +2799,8 @@ extern "C" thetis_status thetis_batch_create(int32_t capacity, thetis_solver *co
     hipError_t e = hipMalloc(&B.bi, nb * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.rows_wg, 4 * count);
     if (e == hipSuccess) e = hipMalloc((void **)&B.dual_wg, 4 * count);
-    if (e == hipSuccess) e = hipMalloc((void **)&B.active, 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&B.alist, 4 * (size_t)count);
+    if (e == hipSuccess) e = hipMalloc((void **)&B.ctl, 4 * CTL_N);
     if (e == hipSuccess) e = hipMalloc((void **)&B.order, (size_t)kMaxBatchClasses * count);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -2834,7 +2919,8 @@ extern "C" thetis_status thetis_batch_destroy(thetis_batch *b) {
     if (b->bc) (void)hipFree(b->bc);
     (void)hipFree(b->rows_wg);
     (void)hipFree(b->dual_wg);
-    (void)hipFree(b->active);
+    (void)hipFree(b->alist);
+    (void)hipFree(b->ctl);
     if (b->dirs) (void)hipFree(b->dirs);
     (void)hipFree(b->order);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
