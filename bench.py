@@ -557,7 +557,7 @@ def main():
     ap.add_argument("--gap", type=float, default=1e-4, help="mis_batch: certified gap to stop at")
     ap.add_argument("--cap", type=int, default=200, help="mis_batch: epoch cap")
     ap.add_argument("--baseline-sample", type=int, default=32, help="mis_batch: instances solved alone")
-    ap.add_argument("--window", type=int, default=64,
+    ap.add_argument("--window", type=int, default=256,
                     help="mis_batch: most instances running at once (0: all); the rest start as they retire")
     args = ap.parse_args()
 
