@@ -553,7 +553,7 @@ def main():
     ap.add_argument("--slots", type=int, default=256, help="serve: slots per batch kind")
     ap.add_argument("--builders", type=int, default=12, help="serve: host layout threads")
     ap.add_argument("--instances", type=int, default=4096, help="mis_batch: instance count")
-    ap.add_argument("--precision", choices=["bf16", "fp32"], default="bf16", help="mis_batch: x storage")
+    ap.add_argument("--precision", choices=["bf16", "fp32"], default="fp32", help="mis_batch: x storage")
     ap.add_argument("--gap", type=float, default=1e-4, help="mis_batch: certified gap to stop at")
     ap.add_argument("--cap", type=int, default=200, help="mis_batch: epoch cap")
     ap.add_argument("--baseline-sample", type=int, default=32, help="mis_batch: instances solved alone")
