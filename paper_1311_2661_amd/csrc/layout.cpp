@@ -170,6 +170,31 @@ static ClassPlan plan_units(const Inst &in, const std::vector<int64_t> &units,
     return cp;
 }
 
+static void pack_blocks(Inst &in) {
+    PackedBlocks &pb = in.pb_det;
+    pb = PackedBlocks();
+    if (!in.nblocks) return;
+    pb.ptr.push_back(0);
+    for (ClassPlan &cp : in.classes)
+        for (Segment &sg : cp.segs) {
+            if (sg.kind != SEG_BLOCK) continue;
+            sg.pb_first = (int64_t)pb.id.size();
+            for (int64_t q = 0; q < sg.count; ++q) {
+                const int32_t bl = in.sched[sg.first + q];
+                pb.id.push_back(bl);
+                pb.j0.push_back(in.bfirst[bl]);
+                for (int32_t i = 0; i < in.k; ++i) {
+                    const int32_t j = in.bfirst[bl] + i;
+                    for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e) {
+                        pb.row.push_back(in.row_idx[e]);
+                        if (!in.unit_vals) pb.val.push_back(in.cval[e]);
+                    }
+                    pb.ptr.push_back((int32_t)pb.row.size());
+                }
+            }
+        }
+}
+
 static void pack(const Inst &in, const std::vector<int32_t> &sched,
                  const std::vector<const ClassPlan *> &plans, Packed &pk) {
     std::vector<int8_t> plain(sched.size(), 0);
@@ -284,6 +309,7 @@ thetis_status build_layout(Inst &in) {
         for (int64_t t = 0; t < in.nunits; ++t) (in.ukind[t] == 2 ? sl : st).push_back(t);
         in.async_struct = plan_units(in, st, in.async_sched);
         in.async_slack = plan_units(in, sl, in.async_sched);
+        pack_blocks(in);
         std::vector<const ClassPlan *> det;
         for (const ClassPlan &cp : in.classes) det.push_back(&cp);
         pack(in, in.sched, det, in.pk_det);

@@ -334,19 +334,22 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
 // theta = max_j (P_j - 1)/c_j over the prefixes of the values sorted
 // downwards (Held, Wolfe & Crowder; Duchi et al.), every lane evaluating
 // one candidate j without sorting.
+// The block's columns are j0 .. j0+k-1; the entries of column i are
+// [cptr[i], cptr[i+1]) of rows / vals (the CSC, or the packed block copy).
 template <class P, bool VALS>
-__device__ __forceinline__ void sweep_block(const Dev<P> &a, int32_t blk, int lpc) {
+__device__ __forceinline__ void sweep_block(const Dev<P> &a, int32_t blk, int32_t j0, const int32_t *cptr,
+                                            const int32_t *rows, const typename P::R *vals, int lpc) {
     using R = typename P::R;
     const int lane = threadIdx.x & 63;
     const int32_t k = a.k;
     const int ci = lane / lpc, sub = lane % lpc;
     const bool own = ci < k;
-    const int32_t j = a.bfirst[blk] + (own ? ci : 0);
-    const int32_t e0 = own ? a.col_ptr[j] : 0, e1 = own ? a.col_ptr[j + 1] : 0;
+    const int32_t j = j0 + (own ? ci : 0);
+    const int32_t e0 = own ? cptr[ci] : 0, e1 = own ? cptr[ci + 1] : 0;
     R acc = R(0);
     for (int32_t e = e0 + sub; e < e1; e += lpc) {
-        const R rv = a.r[a.row_idx[e]];
-        acc += VALS ? a.cval[e] * rv : rv;
+        const R rv = a.r[rows[e]];
+        acc += VALS ? vals[e] * rv : rv;
     }
     for (int o = lpc / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     const R L = a.global_lmax ? a.Lmax : a.LB[blk];
@@ -374,11 +377,28 @@ __device__ __forceinline__ void sweep_block(const Dev<P> &a, int32_t blk, int lp
     if (own && sub == 0) store_x<P>(a.x + j, w);
     if (own && d != R(0)) {
         for (int32_t e = e0 + sub; e < e1; e += lpc) {
-            R *p = a.r + a.row_idx[e];
-            const R dv = VALS ? d * a.cval[e] : d;
+            R *p = a.r + rows[e];
+            const R dv = VALS ? d * vals[e] : d;
             r_add(p, a.async_mode ? R(0) : *p, dv, a.async_mode);
         }
     }
+}
+
+// the packed DET blocks
+template <class R>
+struct BlockPack {
+    const int32_t *id, *j0, *ptr, *row;
+    const R *val;
+};
+template <class P, bool VALS>
+__device__ __forceinline__ void sweep_block_packed(const Dev<P> &a, const BlockPack<typename P::R> &bp, int64_t t,
+                                                   int lpc) {
+    sweep_block<P, VALS>(a, bp.id[t], bp.j0[t], bp.ptr + t * a.k, bp.row, bp.val, lpc);
+}
+template <class P, bool VALS>
+__device__ __forceinline__ void sweep_block_csc(const Dev<P> &a, int32_t blk, int lpc) {
+    const int32_t j0 = a.bfirst[blk];
+    sweep_block<P, VALS>(a, blk, j0, a.col_ptr + j0, a.row_idx, a.cval, lpc);
 }
 
 // slack s_i of an inequality row: column -e_i ('>=') or +e_i ('<='), s >= 0
@@ -451,12 +471,16 @@ __global__ __launch_bounds__(kWG) void k_sweep(Dev<P> a, Sched<typename P::R> sc
     sweep_item<P, VALS>(a, sc, pl, logical_wg(pl, blockIdx.x), st_r, st_row, red);
 }
 
-// the simplex blocks of one class: one wavefront per block
+// the simplex blocks of one class: one wavefront per block, from the packed
+// DET copy (list == null: blocks pb_first ..) or by id through the CSC
 template <class P, bool VALS>
 __global__ __launch_bounds__(kWG) void k_sweep_block(Dev<P> a, const int32_t *__restrict__ list,
+                                                     BlockPack<typename P::R> bp, int64_t pb_first,
                                                      int64_t count, int32_t lpc) {
     const int64_t u = xcd_remap(blockIdx.x, gridDim.x) * (kWG / 64) + (threadIdx.x >> 6);
-    if (u < count) sweep_block<P, VALS>(a, list[u], lpc);
+    if (u >= count) return;
+    if (list) sweep_block_csc<P, VALS>(a, list[u], lpc);
+    else sweep_block_packed<P, VALS>(a, bp, pb_first + u, lpc);
 }
 
 // the slack class: one lane per inequality row
@@ -1063,7 +1087,7 @@ struct ClassLaunch {
     bool has_cols = false;
     LaunchPlan cols{};                      // hub + lane-group ranges (k_sweep)
     std::vector<Segment> col_segs;          // the segments that plan covers
-    int64_t block_first = 0, block_count = 0;
+    int64_t block_first = 0, block_count = 0, block_pb = -1;   // block_pb: first packed block (DET)
     int64_t slack_first = 0, slack_count = 0;
     double bytes_cols = 0, bytes_block = 0, bytes_slack = 0;   // algorithmic, per launch
 };
@@ -1095,7 +1119,8 @@ struct thetis_solver {
     void *col_ptr, *row_idx, *cval, *row_ptr, *csr_col, *csr_val, *b, *sense, *c, *ctil, *ub,
         *norm2, *ybar, *ubar, *bfirst, *fixed, *col_block, *LB, *x, *s, *r, *udual, *sched,
         *async_sched, *pk_det_ptr, *pk_det_row, *pk_det_val, *pk_async_ptr, *pk_async_row,
-        *pk_async_val, *rpart, *cpart, *metrics, *sol, *best, *drop, *ckr_order, *thr, *costbuf,
+        *pk_async_val, *pb_id, *pb_j0, *pb_ptr, *pb_row, *pb_val, *rpart, *cpart, *metrics, *sol, *best, *drop,
+        *ckr_order, *thr, *costbuf,
         *chkbuf, *ystage, *row_orig;
     int64_t nwg_rows = 0, nwg_cols = 0;
     int64_t epoch = 0;
@@ -1209,6 +1234,11 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.pk_async_ptr = cv.take(4 * in.pk_async.ptr.size());
     S.pk_async_row = cv.take(4 * std::max<size_t>(in.pk_async.row.size(), 1));
     S.pk_async_val = in.unit_vals ? nullptr : cv.take(R * std::max<size_t>(in.pk_async.val.size(), 1));
+    S.pb_id = nb ? cv.take(4 * in.pb_det.id.size()) : nullptr;
+    S.pb_j0 = nb ? cv.take(4 * in.pb_det.j0.size()) : nullptr;
+    S.pb_ptr = nb ? cv.take(4 * in.pb_det.ptr.size()) : nullptr;
+    S.pb_row = nb ? cv.take(4 * std::max<size_t>(in.pb_det.row.size(), 1)) : nullptr;
+    S.pb_val = nb && !in.unit_vals ? cv.take(R * std::max<size_t>(in.pb_det.val.size(), 1)) : nullptr;
     S.nwg_rows = std::max<int64_t>(cdiv(std::max(m, n), kWG), 1);
     std::vector<Segment> dsegs = in.async_struct.segs;
     dsegs.insert(dsegs.end(), in.async_slack.segs.begin(), in.async_slack.segs.end());
@@ -1278,6 +1308,11 @@ Sched<typename P::R> det_sched(const thetis_solver &S) {
             (const typename P::R *)S.pk_det_val};
 }
 template <class P>
+BlockPack<typename P::R> block_pack(const thetis_solver &S) {
+    return {(const int32_t *)S.pb_id, (const int32_t *)S.pb_j0, (const int32_t *)S.pb_ptr, (const int32_t *)S.pb_row,
+            (const typename P::R *)S.pb_val};
+}
+template <class P>
 Sched<typename P::R> async_sched(const thetis_solver &S) {
     return {(const int32_t *)S.async_sched, (const int32_t *)S.pk_async_ptr, (const int32_t *)S.pk_async_row,
             (const typename P::R *)S.pk_async_val};
@@ -1330,9 +1365,10 @@ void launch_class(thetis_solver &S, const Dev<P> &a, const ClassLaunch &cl, cons
     if (cl.block_count) {
         TimedScope ts(S, THETIS_K_SWEEP_BLOCK, cl.bytes_block);
         const int64_t grid = cdiv(cl.block_count, kWG / 64);
-        const int32_t *list = sc.ids + cl.block_first;
-        if (vals) hipLaunchKernelGGL((k_sweep_block<P, true>), dim3(grid), dim3(kWG), 0, S.stream, a, list, cl.block_count, S.lpc);
-        else hipLaunchKernelGGL((k_sweep_block<P, false>), dim3(grid), dim3(kWG), 0, S.stream, a, list, cl.block_count, S.lpc);
+        const int32_t *list = cl.block_pb >= 0 ? nullptr : sc.ids + cl.block_first;
+        const BlockPack<typename P::R> bp = block_pack<P>(S);
+        if (vals) hipLaunchKernelGGL((k_sweep_block<P, true>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
+        else hipLaunchKernelGGL((k_sweep_block<P, false>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
     }
     if (cl.slack_count) {
         TimedScope ts(S, THETIS_K_SWEEP_SLACK, cl.bytes_slack);
@@ -1700,7 +1736,9 @@ ClassLaunch make_class_launch(const thetis_solver &S, const Inst &in, const std:
     std::vector<Segment> cols;
     for (const Segment &sg : segs) {
         const double b = segment_bytes(S, in, sched, sg);
-        if (sg.kind == SEG_BLOCK) { cl.block_first = sg.first; cl.block_count = sg.count; cl.bytes_block = b; }
+        if (sg.kind == SEG_BLOCK) {
+            cl.block_first = sg.first; cl.block_count = sg.count; cl.block_pb = sg.pb_first; cl.bytes_block = b;
+        }
         else if (sg.kind == SEG_SLACK) { cl.slack_first = sg.first; cl.slack_count = sg.count; cl.bytes_slack = b; }
         else { cols.push_back(sg); cl.bytes_cols += b; }
     }
@@ -1840,6 +1878,11 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     if (!in.uniform_ub) UP(upload_real(S, S.ub, in.u));
     if (in.nblocks) {
         UP(upload(S, S.bfirst, in.bfirst));
+        UP(upload(S, S.pb_id, in.pb_det.id));
+        UP(upload(S, S.pb_j0, in.pb_det.j0));
+        UP(upload(S, S.pb_ptr, in.pb_det.ptr));
+        UP(upload(S, S.pb_row, in.pb_det.row));
+        if (!in.unit_vals) UP(upload_real(S, S.pb_val, in.pb_det.val));
         UP(upload(S, S.fixed, in.fixed));
         UP(upload(S, S.col_block, in.col_block));
         UP(upload_real(S, S.LB, LB));
@@ -2045,6 +2088,7 @@ template <class P>
 struct BInst {
     Dev<P> a;
     Sched<typename P::R> sc, asc;       // DET schedule, all-columns schedule
+    BlockPack<typename P::R> pb;        // packed DET blocks
     LaunchPlan dual;                    // column pass of the refresh
     double *rpart, *cpart, *metrics;
     int64_t epoch, rows_wg;
@@ -2057,7 +2101,7 @@ struct BInst {
 
 struct BClass {
     LaunchPlan cols;
-    int64_t block_first, block_count, slack_first, slack_count;
+    int64_t block_first, block_count, block_pb, slack_first, slack_count;
     int64_t wg_cols, wg_block, wg_slack;
 };
 
@@ -2273,12 +2317,12 @@ __global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BIn
             sweep_item<P, VALS>(a, sc, C.cols, local, st_r, st_row, red);
         } else if (local < wg_cols + wg_block) {
             // kBatchBlocks blocks per wavefront
-            const int64_t first = C.block_first, count = C.block_count;
+            const int64_t first = C.block_pb, count = C.block_count;
             const int32_t lpc = I.lpc;
             const int64_t base = (local - wg_cols) * (kWG / 64) * kBatchBlocks + (threadIdx.x >> 6);
             for (int b = 0; b < kBatchBlocks; ++b) {
                 const int64_t u = base + b * (kWG / 64);
-                if (u < count) sweep_block<P, VALS>(a, sc.ids[first + u], lpc);
+                if (u < count) sweep_block_packed<P, VALS>(a, I.pb, first + u, lpc);
             }
         } else {
             // kBatchSlacks slacks per thread
@@ -2498,6 +2542,7 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
         thetis_solver &S = *B.solvers[i];
         I.a = make_dev<P>(S);
         I.sc = det_sched<P>(S);
+        I.pb = block_pack<P>(S);
         I.asc = async_sched<P>(S);
         I.with_dual = gap_tol > 0.0;
         I.dual = I.with_dual ? S.dual : S.colterms;
@@ -2530,6 +2575,7 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
             C.wg_cols = cl.has_cols ? C.cols.nwg : 0;
             C.block_first = cl.block_first;
             C.block_count = cl.block_count;
+            C.block_pb = cl.block_pb;
             C.wg_block = cdiv(cl.block_count, (kWG / 64) * kBatchBlocks);
             C.slack_first = cl.slack_first;
             C.slack_count = cl.slack_count;

@@ -36,6 +36,7 @@ struct Segment {
     int32_t kind;
     int64_t first;   // offset into Inst::sched
     int64_t count;   // units in this segment
+    int64_t pb_first = -1;   // SEG_BLOCK of the DET plan: first block in Inst::pb_det
 };
 
 struct ClassPlan {
@@ -48,6 +49,14 @@ struct ClassPlan {
 // contiguous in memory and a lane group reads its indices coalesced.
 struct Packed {
     std::vector<int32_t> ptr, row;
+    std::vector<double> val;   // empty when every entry is 1
+};
+
+// The simplex blocks of the DET plan packed in plan order: block t is block
+// id[t] with first column j0[t]; the entries of its column i are
+// [ptr[t k + i], ptr[t k + i + 1]) of row / val, in column order.
+struct PackedBlocks {
+    std::vector<int32_t> id, j0, ptr, row;
     std::vector<double> val;   // empty when every entry is 1
 };
 
@@ -84,6 +93,7 @@ struct Inst {
     std::vector<int32_t> async_sched;
     ClassPlan async_struct, async_slack;
     Packed pk_det, pk_async;
+    PackedBlocks pb_det;
     bool planned = false;
     bool has_solver = false;
     int64_t max_col_degree = 0;
