@@ -328,22 +328,25 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
     }
 }
 
-// Simplex block (k columns of one pixel): one wavefront.  Lanes are split
-// into k groups of LPC lanes (LPC = largest power of two <= 64/k); group i
-// forms the gradient of column i.  The projection onto the simplex uses
-// theta = max_j (P_j - 1)/c_j over the prefixes of the values sorted
-// downwards (Held, Wolfe & Crowder; Duchi et al.), every lane evaluating
-// one candidate j without sorting.
-// The block's columns are j0 .. j0+k-1; the entries of column i are
-// [cptr[i], cptr[i+1]) of rows / vals (the CSC, or the packed block copy).
-template <class P, bool VALS>
-__device__ __forceinline__ void sweep_block(const Dev<P> &a, int32_t blk, int32_t j0, const int32_t *cptr,
+// Simplex blocks (k columns of one pixel): BPW blocks per wavefront, each on
+// 64/BPW lanes split into k groups of LPC lanes (LPC = largest power of two
+// <= 64/(BPW k)); group i forms the gradient of column i.  The projection
+// onto the simplex uses theta = max_j (P_j - 1)/c_j over the prefixes of the
+// values sorted downwards (Held, Wolfe & Crowder; Duchi et al.), every lane
+// evaluating one candidate j without sorting.  A lane's block has columns
+// j0 .. j0+k-1; the entries of column i are [cptr[i], cptr[i+1]) of rows /
+// vals (the CSC, or the packed block copy); `valid` is false for the lanes
+// of a block position past the end (they still take part in the shuffles).
+template <class P, bool VALS, int BPW>
+__device__ __forceinline__ void sweep_block(const Dev<P> &a, bool valid, int32_t blk, int32_t j0, const int32_t *cptr,
                                             const int32_t *rows, const typename P::R *vals, int lpc) {
     using R = typename P::R;
+    constexpr int LB = 64 / BPW;
     const int lane = threadIdx.x & 63;
+    const int lb = lane % LB, base = lane - lb;
     const int32_t k = a.k;
-    const int ci = lane / lpc, sub = lane % lpc;
-    const bool own = ci < k;
+    const int ci = lb / lpc, sub = lb % lpc;
+    const bool own = valid && ci < k;
     const int32_t j = j0 + (own ? ci : 0);
     const int32_t e0 = own ? cptr[ci] : 0, e1 = own ? cptr[ci + 1] : 0;
     R acc = R(0);
@@ -352,24 +355,28 @@ __device__ __forceinline__ void sweep_block(const Dev<P> &a, int32_t blk, int32_
         acc += VALS ? vals[e] * rv : rv;
     }
     for (int o = lpc / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    const R L = a.global_lmax ? a.Lmax : a.LB[blk];
+    const R L = a.global_lmax ? a.Lmax : (valid ? a.LB[blk] : R(0));
     R y = R(0), v = R(0);
     if (own) {
         y = (R)xval(a.x[j]);
         const R g = gradient(a, j, y, acc);
         v = L > R(0) ? y - a.gamma * g / L : y;
     }
-    // lane q < k takes the value of column q; every shuffle runs with the
-    // whole wavefront active
-    const R vq = __shfl(v, (lane < k ? lane : 0) * lpc, 64);
+    // lane q < k of a block takes the value of column q; every shuffle runs
+    // with the whole wavefront active
+    const R vq = __shfl(v, base + (lb < k ? lb : 0) * lpc, 64);
     R psum = R(0);
     int cnt = 0;
     for (int l = 0; l < k; ++l) {
-        const R vl = __shfl(v, l * lpc, 64);
-        if (vl > vq || (vl == vq && l <= lane)) { psum += vl; ++cnt; }
+        const R vl = __shfl(v, base + l * lpc, 64);
+        if (vl > vq || (vl == vq && l <= lb)) { psum += vl; ++cnt; }
     }
-    const R cand = lane < k ? (psum - R(1)) / (R)cnt : R(-INFINITY);
-    const R theta = wave_max(cand);
+    R theta = valid && lb < k ? (psum - R(1)) / (R)cnt : R(-INFINITY);
+#pragma unroll
+    for (int o = LB / 2; o > 0; o >>= 1) {
+        const R t2 = __shfl_xor(theta, o, 64);
+        theta = t2 > theta ? t2 : theta;
+    }
     R w = v - theta;
     if (w < R(0)) w = R(0);
     w = stored_value<P>(w);
@@ -390,16 +397,20 @@ struct BlockPack {
     const int32_t *id, *j0, *ptr, *row;
     const R *val;
 };
-template <class P, bool VALS>
-__device__ __forceinline__ void sweep_block_packed(const Dev<P> &a, const BlockPack<typename P::R> &bp, int64_t t,
-                                                   int lpc) {
-    sweep_block<P, VALS>(a, bp.id[t], bp.j0[t], bp.ptr + t * a.k, bp.row, bp.val, lpc);
+template <class P, bool VALS, int BPW>
+__device__ __forceinline__ void sweep_block_packed(const Dev<P> &a, const BlockPack<typename P::R> &bp, bool valid,
+                                                   int64_t t, int lpc) {
+    const int32_t blk = valid ? bp.id[t] : 0, j0 = valid ? bp.j0[t] : 0;
+    sweep_block<P, VALS, BPW>(a, valid, blk, j0, bp.ptr + (valid ? t * a.k : 0), bp.row, bp.val, lpc);
 }
-template <class P, bool VALS>
-__device__ __forceinline__ void sweep_block_csc(const Dev<P> &a, int32_t blk, int lpc) {
-    const int32_t j0 = a.bfirst[blk];
-    sweep_block<P, VALS>(a, blk, j0, a.col_ptr + j0, a.row_idx, a.cval, lpc);
+template <class P, bool VALS, int BPW>
+__device__ __forceinline__ void sweep_block_csc(const Dev<P> &a, bool valid, int32_t blk, int lpc) {
+    const int32_t j0 = valid ? a.bfirst[blk] : 0;
+    sweep_block<P, VALS, BPW>(a, valid, blk, j0, a.col_ptr + j0, a.row_idx, a.cval, lpc);
 }
+// blocks per wavefront for block size k (the layout of the sums depends on
+// it, so the solo and batched sweeps take the same)
+__host__ __device__ constexpr int block_bpw(int k) { return k <= 16 ? 2 : 1; }
 
 // slack s_i of an inequality row: column -e_i ('>=') or +e_i ('<='), s >= 0
 template <class P>
@@ -473,14 +484,16 @@ __global__ __launch_bounds__(kWG) void k_sweep(Dev<P> a, Sched<typename P::R> sc
 
 // the simplex blocks of one class: one wavefront per block, from the packed
 // DET copy (list == null: blocks pb_first ..) or by id through the CSC
-template <class P, bool VALS>
+template <class P, bool VALS, int BPW>
 __global__ __launch_bounds__(kWG) void k_sweep_block(Dev<P> a, const int32_t *__restrict__ list,
                                                      BlockPack<typename P::R> bp, int64_t pb_first,
                                                      int64_t count, int32_t lpc) {
-    const int64_t u = xcd_remap(blockIdx.x, gridDim.x) * (kWG / 64) + (threadIdx.x >> 6);
-    if (u >= count) return;
-    if (list) sweep_block_csc<P, VALS>(a, list[u], lpc);
-    else sweep_block_packed<P, VALS>(a, bp, pb_first + u, lpc);
+    const int64_t w = xcd_remap(blockIdx.x, gridDim.x) * (kWG / 64) + (threadIdx.x >> 6);
+    if (w * BPW >= count) return;        // the whole wavefront leaves together
+    const int64_t u = w * BPW + (threadIdx.x & 63) / (64 / BPW);
+    const bool valid = u < count;
+    if (list) sweep_block_csc<P, VALS, BPW>(a, valid, valid ? list[u] : 0, lpc);
+    else sweep_block_packed<P, VALS, BPW>(a, bp, valid, pb_first + u, lpc);
 }
 
 // the slack class: one lane per inequality row
@@ -1364,11 +1377,17 @@ void launch_class(thetis_solver &S, const Dev<P> &a, const ClassLaunch &cl, cons
     }
     if (cl.block_count) {
         TimedScope ts(S, THETIS_K_SWEEP_BLOCK, cl.bytes_block);
-        const int64_t grid = cdiv(cl.block_count, kWG / 64);
         const int32_t *list = cl.block_pb >= 0 ? nullptr : sc.ids + cl.block_first;
         const BlockPack<typename P::R> bp = block_pack<P>(S);
-        if (vals) hipLaunchKernelGGL((k_sweep_block<P, true>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
-        else hipLaunchKernelGGL((k_sweep_block<P, false>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
+        if (block_bpw(S.k) == 2) {
+            const int64_t grid = cdiv(cl.block_count, 2 * (kWG / 64));
+            if (vals) hipLaunchKernelGGL((k_sweep_block<P, true, 2>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
+            else hipLaunchKernelGGL((k_sweep_block<P, false, 2>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
+        } else {
+            const int64_t grid = cdiv(cl.block_count, kWG / 64);
+            if (vals) hipLaunchKernelGGL((k_sweep_block<P, true, 1>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
+            else hipLaunchKernelGGL((k_sweep_block<P, false, 1>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
+        }
     }
     if (cl.slack_count) {
         TimedScope ts(S, THETIS_K_SWEEP_SLACK, cl.bytes_slack);
@@ -1821,7 +1840,7 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     S.nclasses = in.nclasses; S.nunits = in.nunits;
     S.unit_vals = in.unit_vals; S.uniform_ub = in.uniform_ub; S.ub_value = in.ub_value;
     S.all_rows_slack = in.all_rows_slack;
-    while (S.lpc * 2 * std::max(S.k, 1) <= 64) S.lpc *= 2;
+    while (S.lpc * 2 * std::max(S.k, 1) * block_bpw(S.k) <= 64) S.lpc *= 2;
     S.max_degree = in.max_col_degree;
     S.edge_shape_cover = edge_shape(in, 1);
     S.edge_shape_pack = edge_shape(in, -1);
@@ -2317,12 +2336,23 @@ __global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BIn
             sweep_item<P, VALS>(a, sc, C.cols, local, st_r, st_row, red);
         } else if (local < wg_cols + wg_block) {
             // kBatchBlocks blocks per wavefront
+            // kBatchBlocks wavefront positions, each with BPW blocks
             const int64_t first = C.block_pb, count = C.block_count;
             const int32_t lpc = I.lpc;
             const int64_t base = (local - wg_cols) * (kWG / 64) * kBatchBlocks + (threadIdx.x >> 6);
-            for (int b = 0; b < kBatchBlocks; ++b) {
-                const int64_t u = base + b * (kWG / 64);
-                if (u < count) sweep_block_packed<P, VALS>(a, I.pb, first + u, lpc);
+            if (block_bpw(a.k) == 2) {
+                for (int b = 0; b < kBatchBlocks; ++b) {
+                    const int64_t w = base + b * (kWG / 64);
+                    if (w * 2 >= count) break;
+                    const int64_t u = w * 2 + (threadIdx.x & 63) / 32;
+                    sweep_block_packed<P, VALS, 2>(a, I.pb, u < count, first + u, lpc);
+                }
+            } else {
+                for (int b = 0; b < kBatchBlocks; ++b) {
+                    const int64_t w = base + b * (kWG / 64);
+                    if (w >= count) break;
+                    sweep_block_packed<P, VALS, 1>(a, I.pb, true, first + w, lpc);
+                }
             }
         } else {
             // kBatchSlacks slacks per thread
@@ -2576,7 +2606,7 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
             C.block_first = cl.block_first;
             C.block_count = cl.block_count;
             C.block_pb = cl.block_pb;
-            C.wg_block = cdiv(cl.block_count, (kWG / 64) * kBatchBlocks);
+            C.wg_block = cdiv(cl.block_count, (kWG / 64) * kBatchBlocks * block_bpw(S.k));
             C.slack_first = cl.slack_first;
             C.slack_count = cl.slack_count;
             C.wg_slack = cdiv(cl.slack_count, kWG * kBatchSlacks);
