@@ -410,7 +410,7 @@ __device__ __forceinline__ void sweep_block_csc(const Dev<P> &a, bool valid, int
 }
 // blocks per wavefront for block size k (the layout of the sums depends on
 // it, so the solo and batched sweeps take the same)
-__host__ __device__ constexpr int block_bpw(int k) { return k <= 16 ? 2 : 1; }
+__host__ __device__ constexpr int block_bpw(int k) { return k <= 8 ? 4 : (k <= 16 ? 2 : 1); }
 
 // slack s_i of an inequality row: column -e_i ('>=') or +e_i ('<='), s >= 0
 template <class P>
@@ -1379,7 +1379,11 @@ void launch_class(thetis_solver &S, const Dev<P> &a, const ClassLaunch &cl, cons
         TimedScope ts(S, THETIS_K_SWEEP_BLOCK, cl.bytes_block);
         const int32_t *list = cl.block_pb >= 0 ? nullptr : sc.ids + cl.block_first;
         const BlockPack<typename P::R> bp = block_pack<P>(S);
-        if (block_bpw(S.k) == 2) {
+        if (block_bpw(S.k) == 4) {
+            const int64_t grid = cdiv(cl.block_count, 4 * (kWG / 64));
+            if (vals) hipLaunchKernelGGL((k_sweep_block<P, true, 4>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
+            else hipLaunchKernelGGL((k_sweep_block<P, false, 4>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
+        } else if (block_bpw(S.k) == 2) {
             const int64_t grid = cdiv(cl.block_count, 2 * (kWG / 64));
             if (vals) hipLaunchKernelGGL((k_sweep_block<P, true, 2>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
             else hipLaunchKernelGGL((k_sweep_block<P, false, 2>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
@@ -2340,7 +2344,14 @@ __global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BIn
             const int64_t first = C.block_pb, count = C.block_count;
             const int32_t lpc = I.lpc;
             const int64_t base = (local - wg_cols) * (kWG / 64) * kBatchBlocks + (threadIdx.x >> 6);
-            if (block_bpw(a.k) == 2) {
+            if (block_bpw(a.k) == 4) {
+                for (int b = 0; b < kBatchBlocks; ++b) {
+                    const int64_t w = base + b * (kWG / 64);
+                    if (w * 4 >= count) break;
+                    const int64_t u = w * 4 + (threadIdx.x & 63) / 16;
+                    sweep_block_packed<P, VALS, 4>(a, I.pb, u < count, first + u, lpc);
+                }
+            } else if (block_bpw(a.k) == 2) {
                 for (int b = 0; b < kBatchBlocks; ++b) {
                     const int64_t w = base + b * (kWG / 64);
                     if (w * 2 >= count) break;
