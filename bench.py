@@ -342,6 +342,8 @@ def mc_grid(args):
     h = T.Instance(inst)
     s = T.Solver(h, beta=10.0, precision=T.PREC_FP32, refresh_every=5, seed=args.seed)
     log(f"layout + upload: {time.perf_counter() - t0:.1f} s, {h.classes()[0]} colour classes")
+    tuned = s.autotune(4)                  # real epochs; every step resets
+    log(f"columns per lane group by class: {tuned}")
     tr = s.traffic()
     ep = args.epochs
 
@@ -389,7 +391,8 @@ def mc_grid(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"mc_grid_{side}x{side}_k8_beta10_fp32_refresh5_{ep}ep_det", "columns": inst.n,
-                   "rows": inst.m, "entries": inst.nnz, "coordinates_per_epoch": upd, "seed": args.seed},
+                   "rows": inst.m, "entries": inst.nnz, "coordinates_per_epoch": upd,
+                   "group_cols_by_class": tuned, "seed": args.seed},
         "roofline": {"bound": "hbm", "kernel": "k_sweep_block", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_launch": avg_bytes, "avg_launch_us": 1e3 * avg_ms},
@@ -601,6 +604,8 @@ def main():
                  step_scale=1.0 if sched == T.SCHED_DET else 0.5, seed=args.seed)
     nclasses = h.classes()[0]
     log(f"layout + upload: {time.perf_counter() - t0:.1f} s, {nclasses} colour classes")
+    tuned = s.autotune(4) if sched == T.SCHED_DET else []      # real epochs; every step resets
+    log(f"columns per lane group by class: {tuned}")
     traffic = s.traffic()
     upd_per_epoch = traffic["updates_per_epoch"]
 
@@ -672,7 +677,7 @@ def main():
         "config": {"workload": workload, "graph": "barabasi_albert", "n_vertices": inst.n,
                    "edges": inst.m, "coordinates_per_epoch": upd_per_epoch, "epochs": args.epochs,
                    "beta": 10.0, "refresh_every": 5, "schedule": args.schedule,
-                   "colour_classes": nclasses, "seed": args.seed},
+                   "colour_classes": nclasses, "group_cols_by_class": tuned, "seed": args.seed},
         "hbm_gbs_algorithmic_step": step_bytes / (elapsed / args.steps) / 1e9,
         "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -173,6 +173,16 @@ thetis_status thetis_set_step_rule(thetis_solver *s, int32_t rule, double step_s
 thetis_status thetis_run_epochs(thetis_solver *s, int32_t max_epochs, double gap_tol,
                                 int32_t *epochs_done);
 
+/* Chooses, for every colour class of the DET schedule, how many columns a
+ * lane group updates at once (1, 2 or 4: more loads in flight against more
+ * serial work per wavefront) by timing real epochs: 1 + 3 x
+ * epochs_per_candidate epochs of the solve are run (counted in
+ * thetis_epoch; no gap test); a shape other than one column per group is
+ * taken only when it is at least 3% faster.
+ * choice_host (NULL or one int per class) receives the choices.  Results do
+ * not depend on them.  ASYNC solvers are left as they are. */
+thetis_status thetis_solver_autotune(thetis_solver *s, int32_t epochs_per_candidate, int32_t *choice_host);
+
 /* Residual norms of the slack form, ||A y - b||_inf and ||.||_2, and the
  * largest violation of an original row by x (Definition of an
  * (eps,delta)-approximate solution, Section 3.1).  Computed in FP64 from

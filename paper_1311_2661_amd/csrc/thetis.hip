@@ -1098,6 +1098,7 @@ constexpr int32_t kMaxReps = 64;
 // launches of one class (DET) or one epoch part (ASYNC)
 struct ClassLaunch {
     bool has_cols = false;
+    int32_t group_cols = 1;                 // columns per lane group (the tuner's choice)
     LaunchPlan cols{};                      // hub + lane-group ranges (k_sweep)
     std::vector<Segment> col_segs;          // the segments that plan covers
     int64_t block_first = 0, block_count = 0, block_pb = -1;   // block_pb: first packed block (DET)
@@ -1105,7 +1106,14 @@ struct ClassLaunch {
     double bytes_cols = 0, bytes_block = 0, bytes_slack = 0;   // algorithmic, per launch
 };
 
+struct ClassEvent {
+    int32_t cls;
+    hipEvent_t e0, e1;
+};
+
 struct thetis_solver {
+    // tuner: events around every class launch while set
+    std::vector<ClassEvent> *class_events = nullptr;
     // host copy of what the launches need
     int64_t m = 0, n = 0, nnz = 0, nblocks = 0;
     int32_t k = 0, nclasses = 0;
@@ -1453,7 +1461,19 @@ thetis_status run_epochs_impl(thetis_solver &S, int32_t max_epochs, double gap_t
         S.timing_now = S.timing > 0 && (S.epoch % S.timing) == 0;
         if (S.p.schedule == THETIS_SCHED_DET) {
             class_order(S.nclasses, S.p.seed, S.epoch, order.data());
-            for (int32_t q = 0; q < S.nclasses; ++q) launch_class<P>(S, a, S.det[order[q]], dsc);
+            for (int32_t q = 0; q < S.nclasses; ++q) {
+                if (S.class_events) {
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    HIP_TRY(hipEventCreate(&e0));
+                    HIP_TRY(hipEventCreate(&e1));
+                    HIP_TRY(hipEventRecord(e0, S.stream));
+                    launch_class<P>(S, a, S.det[order[q]], dsc);
+                    HIP_TRY(hipEventRecord(e1, S.stream));
+                    S.class_events->push_back({order[q], e0, e1});
+                } else {
+                    launch_class<P>(S, a, S.det[order[q]], dsc);
+                }
+            }
         } else {
             launch_class<P>(S, a, S.async_launch, asc);
         }
@@ -1985,6 +2005,48 @@ extern "C" thetis_status thetis_run_epochs(thetis_solver *s, int32_t max_epochs,
     if (max_epochs < 0) return fail(THETIS_EINVAL, "max_epochs < 0");
     s->have_round = false;
     return DISPATCH(*s, run_epochs_impl)(*s, max_epochs, gap_tol, epochs_done);
+}
+
+extern "C" thetis_status thetis_solver_autotune(thetis_solver *s, int32_t epochs_per_candidate, int32_t *choice_host) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    if (epochs_per_candidate < 1) return fail(THETIS_EINVAL, "epochs_per_candidate < 1");
+    thetis_solver &S = *s;
+    const int32_t nc = (int32_t)S.det.size();
+    if (S.p.schedule != THETIS_SCHED_DET) {
+        if (choice_host) for (int32_t c = 0; c < nc; ++c) choice_host[c] = S.det[c].group_cols;
+        return THETIS_OK;
+    }
+    const int cands[3] = {1, 2, 4};
+    std::vector<double> ms(3 * (size_t)std::max(nc, 1), 0.0);
+    std::vector<ClassEvent> evs;
+    // one untimed epoch first, so that no candidate runs on cold caches
+    thetis_status st = DISPATCH(S, run_epochs_impl)(S, 1, 0.0, nullptr);
+    for (int ci = 0; ci < 3 && st == THETIS_OK; ++ci) {
+        for (ClassLaunch &cl : S.det)
+            if (cl.has_cols) { cl.group_cols = cands[ci]; cl.cols = make_plan(cl.col_segs, false, 0, 1, cands[ci]); }
+        evs.clear();
+        S.class_events = &evs;
+        st = DISPATCH(S, run_epochs_impl)(S, epochs_per_candidate, 0.0, nullptr);
+        S.class_events = nullptr;
+        if (st == THETIS_OK && hipStreamSynchronize(S.stream) != hipSuccess) st = fail(THETIS_EDEVICE, "tuner sync failed");
+        for (const ClassEvent &ev : evs) {
+            float t = 0.f;
+            if (st == THETIS_OK && hipEventElapsedTime(&t, ev.e0, ev.e1) == hipSuccess) ms[3 * ev.cls + ci] += t;
+            (void)hipEventDestroy(ev.e0);
+            (void)hipEventDestroy(ev.e1);
+        }
+    }
+    for (int32_t c = 0; c < nc; ++c) {
+        ClassLaunch &cl = S.det[c];
+        // one column per group unless another shape is clearly faster
+        int best = 0;
+        for (int ci = 1; ci < 3; ++ci) if (ms[3 * c + ci] < 0.97 * ms[3 * c + best]) best = ci;
+        if (cl.has_cols) { cl.group_cols = cands[best]; cl.cols = make_plan(cl.col_segs, false, 0, 1, cands[best]); }
+        if (choice_host) choice_host[c] = cl.group_cols;
+    }
+    s->have_round = false;
+    return st;
 }
 
 extern "C" thetis_status thetis_residual(thetis_solver *s, double *linf, double *l2, double *viol) {

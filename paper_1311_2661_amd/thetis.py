@@ -35,7 +35,8 @@ EXPORTED = [
     "thetis_params_default", "thetis_inst_create_csr", "thetis_inst_set_simplex_blocks",
     "thetis_inst_classes", "thetis_inst_destroy", "thetis_solver_workspace_bytes",
     "thetis_solver_create", "thetis_solver_reset", "thetis_set_beta", "thetis_set_step_rule",
-    "thetis_run_epochs", "thetis_residual", "thetis_objective", "thetis_get_x", "thetis_set_y",
+    "thetis_run_epochs", "thetis_solver_autotune", "thetis_residual", "thetis_objective", "thetis_get_x",
+    "thetis_set_y",
     "thetis_epoch", "thetis_round", "thetis_check_feasible", "thetis_set_timing",
     "thetis_get_timing", "thetis_epoch_traffic", "thetis_solver_destroy", "thetis_calibrate_random",
     "thetis_last_error",
@@ -81,6 +82,7 @@ def lib():
             "thetis_set_beta": [vp, dbl],
             "thetis_set_step_rule": [vp, i32, dbl],
             "thetis_run_epochs": [vp, i32, dbl, P(i32)],
+            "thetis_solver_autotune": [vp, i32, vp],
             "thetis_residual": [vp, P(dbl), P(dbl), P(dbl)],
             "thetis_objective": [vp, P(dbl), P(dbl), P(dbl)],
             "thetis_get_x": [vp, vp, vp],
@@ -371,6 +373,7 @@ class Solver:
             self.h = thetis_solver_create(instance.h, p, self.workspace.data_ptr(), nbytes,
                                           self.stream.cuda_stream)
         self.n, self.m = instance.n, instance.m
+        self.nclasses = thetis_inst_classes(instance.h)[0]
         bf = instance.inst.block_first_col
         self.nblocks = 0 if bf is None else len(bf)
         v = instance.inst.val
@@ -382,6 +385,14 @@ class Solver:
 
     def run(self, epochs: int, gap_tol: float = 0.0) -> int:
         return thetis_run_epochs(self.h, epochs, gap_tol)
+
+    def autotune(self, epochs_per_candidate: int = 2) -> list:
+        """Per-class columns per lane group, chosen by timing real epochs
+        (1 + 3 x epochs_per_candidate epochs of the solve)."""
+        nc = self.nclasses
+        out = np.zeros(max(nc, 1), np.int32)
+        _check(lib().thetis_solver_autotune(self.h, epochs_per_candidate, _ptr(out)))
+        return [int(v) for v in out[:nc]]
 
     def residual(self):
         linf, l2, viol = thetis_residual(self.h)

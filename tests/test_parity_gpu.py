@@ -474,6 +474,22 @@ def test_bf16_x_storage_error_is_stated_and_bounded():
         assert g.check(rule) == (True, 0)
 
 
+@pytest.mark.parametrize("maker", [lambda: I.vc_ba(20000, seed=3), lambda: I.mc_grid(side=24, k=8, seed=4)])
+def test_solo_autotune_does_not_change_results(maker):
+    """The per-class tuner runs real epochs and changes only how many columns
+    a lane group updates at once: the trajectory is the untuned one."""
+    inst = maker()
+    a = gpu_solver(inst, seed=5)
+    b = gpu_solver(inst, seed=5)
+    ch = a.autotune(2)
+    assert len(ch) == a.nclasses and all(c in (1, 2, 4) for c in ch)
+    assert a.epoch == 7
+    a.run(10)
+    b.run(17)
+    assert np.array_equal(a.y, b.y)
+    assert a.metrics()["F"] == b.metrics()["F"]
+
+
 def test_calibrate_random_rates_are_positive():
     """The random-access calibration runs in bounds and returns finite
     positive times for the gather, read-modify-write and copy passes."""
