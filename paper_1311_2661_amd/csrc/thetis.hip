@@ -555,14 +555,18 @@ __device__ __forceinline__ double box_min(double red, double U, double rho, doub
 // running residual; the dual estimate u = ubar - beta w (clipped so the
 // unbounded slack columns keep a non-negative reduced cost when rho = 0),
 // rounded once to storage precision and used for every term of Phi.
+// rows a thread of the row pass takes (fewer partial records to fold)
+constexpr int kRowsPerThread = 4;
+
 template <class P>
 __device__ __forceinline__ void rows_item(const Dev<P> &a, int64_t wg, int32_t write_r, int32_t with_dual,
                                           double *part) {
     using R = typename P::R;
-    const int64_t i = wg * kWG + threadIdx.x;
     double v[kRowSlots] = {0, 0, 0, 0, 0, 0};
     const int op[kRowSlots] = {0, 1, 1, 0, 0, 0};
-    if (i < a.m) {
+    for (int q = 0; q < kRowsPerThread; ++q) {
+        const int64_t i = (wg * kRowsPerThread + q) * kWG + threadIdx.x;
+        if (i >= a.m) break;
         double ax = 0.0;
         for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
             ax += (a.csr_val ? (double)a.csr_val[e] : 1.0) * (double)xval(a.x[a.csr_col[e]]);
@@ -581,13 +585,14 @@ __device__ __forceinline__ void rows_item(const Dev<P> &a, int64_t wg, int32_t w
         const R ur = (R)ui;
         if (with_dual) a.udual[i] = ur;
         const double ud = (double)ur;
-        v[0] = w * w;
-        v[1] = fabs(w);
-        v[2] = sn > 0 ? a.b[i] - ax : (sn < 0 ? ax - a.b[i] : fabs(ax - a.b[i]));
-        if (v[2] < 0.0) v[2] = 0.0;
-        v[3] = a.b[i] * ud;
-        v[4] = (ud - ub) * (ud - ub);
-        v[5] = -ub * w;
+        double viol = sn > 0 ? a.b[i] - ax : (sn < 0 ? ax - a.b[i] : fabs(ax - a.b[i]));
+        if (viol < 0.0) viol = 0.0;
+        v[0] += w * w;
+        v[1] = fmax(v[1], fabs(w));
+        v[2] = fmax(v[2], viol);
+        v[3] += a.b[i] * ud;
+        v[4] += (ud - ub) * (ud - ub);
+        v[5] += -ub * w;
     }
     block_reduce<kRowSlots>(v, op, part + wg * kRowSlots);
 }
@@ -708,14 +713,16 @@ __device__ __forceinline__ void dual_item(const Dev<P> &a, const Sched<typename 
             v[0] = box_min((sn > 0 ? 1.0 : -1.0) * (double)a.udual[i], INFINITY, rho, yb);
         }
     } else {
-        // every structural column: c^T x, the prox part of F, and the fixed
-        // simplex blocks' contribution to Phi (their first column's thread)
-        const int64_t j = local * kWG + threadIdx.x;
-        if (j < a.n) {
+        // every structural column (kRowsPerThread per thread): c^T x, the
+        // prox part of F, and the fixed simplex blocks' contribution to Phi
+        // (their first column's thread)
+        for (int q = 0; q < kRowsPerThread; ++q) {
+            const int64_t j = (local * kRowsPerThread + q) * kWG + threadIdx.x;
+            if (j >= a.n) break;
             const double xj = (double)xval(a.x[j]);
-            v[1] = a.c[j] * xj;
+            v[1] += a.c[j] * xj;
             const double yb = a.ybar ? (double)a.ybar[j] : 0.0;
-            if (a.prox_on) v[2] = 0.5 * rho * (xj - yb) * (xj - yb);
+            if (a.prox_on) v[2] += 0.5 * rho * (xj - yb) * (xj - yb);
             const int32_t bl = a.col_block ? a.col_block[j] : -1;
             if (bl >= 0 && a.fixed[bl] >= 0 && j == a.bfirst[bl]) {
                 const int f = a.fixed[bl], k = a.k;
@@ -729,7 +736,7 @@ __device__ __forceinline__ void dual_item(const Dev<P> &a, const Sched<typename 
                         const double d = (i == f ? 1.0 : 0.0) - ybi;
                         val += 0.5 * rho * d * d;
                     }
-                v[0] = val;
+                v[0] += val;
             }
         }
     }
@@ -1209,7 +1216,7 @@ LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolte
         pl.wg_start[p] = wg;
         const int kind = grid_kind(p);
         const int64_t upw = kind < kGroupKinds ? kWG / pl.lanes[p] * pl.cols[p]
-                                               : (kind == SEG_NKIND ? kWG : units_per_wg(kind, dual));
+                                               : (kind == SEG_NKIND ? kWG * kRowsPerThread : units_per_wg(kind, dual));
         int64_t w = pl.count[p] ? cdiv(pl.count[p], upw) : 0;
         if (kind == SEG_HUB) { w = cdiv(w, 8) * 8; pl.hub_wg = w; }
         wg += w;
@@ -1260,7 +1267,7 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.pb_ptr = nb ? cv.take(4 * in.pb_det.ptr.size()) : nullptr;
     S.pb_row = nb ? cv.take(4 * std::max<size_t>(in.pb_det.row.size(), 1)) : nullptr;
     S.pb_val = nb && !in.unit_vals ? cv.take(R * std::max<size_t>(in.pb_det.val.size(), 1)) : nullptr;
-    S.nwg_rows = std::max<int64_t>(cdiv(std::max(m, n), kWG), 1);
+    S.nwg_rows = std::max<int64_t>(cdiv(std::max(m, n), kWG), 1);   // also the rounding's partials
     std::vector<Segment> dsegs = in.async_struct.segs;
     dsegs.insert(dsegs.end(), in.async_slack.segs.begin(), in.async_slack.segs.end());
     S.dual = make_plan(dsegs, true, n);
@@ -1415,7 +1422,7 @@ void launch_class(thetis_solver &S, const Dev<P> &a, const ClassLaunch &cl, cons
 template <class P>
 thetis_status refresh(thetis_solver &S, bool write_r, bool with_dual) {
     Dev<P> a = make_dev<P>(S);
-    const int64_t gr = cdiv(std::max<int64_t>(S.m, 1), kWG);
+    const int64_t gr = cdiv(std::max<int64_t>(S.m, 1), (int64_t)kWG * kRowsPerThread);
     const LaunchPlan &pl = with_dual ? S.dual : S.colterms;
     {
         TimedScope ts(S, THETIS_K_REFRESH, with_dual ? S.refresh_bytes : S.refresh_bytes_nodual);
@@ -2653,7 +2660,7 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
         I.cpart = (double *)S.cpart;
         I.metrics = (double *)S.metrics;
         I.epoch = S.epoch;
-        I.rows_wg = cdiv(std::max<int64_t>(S.m, 1), kWG);
+        I.rows_wg = cdiv(std::max<int64_t>(S.m, 1), (int64_t)kWG * kRowsPerThread);
         I.seed = S.p.seed;
         I.gap_tol = gap_tol;
         I.beta = S.p.beta;
