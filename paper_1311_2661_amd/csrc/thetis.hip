@@ -648,28 +648,33 @@ __device__ __forceinline__ void dual_item(const Dev<P> &a, const Sched<typename 
         if (valid && threadIdx.x == 0)
             v[0] = box_min(a.c[j] - acc, col_ubound(a, j), rho, a.ybar ? (double)a.ybar[j] : 0.0);
     } else if (kind < kGroupKinds) {
+        // kRowsPerThread columns per lane group
         const int G = pl.lanes[p];
         const int lane = threadIdx.x & (G - 1);
-        const int64_t u = local * (kWG / G) + threadIdx.x / G;
-        const bool valid = u < count;
-        double acc = 0.0;
-        int32_t j = 0;
-        if (valid) {
-            const int64_t q = first + u;
-            j = sc.ids[q];
-            for (int32_t e = sc.ptr[q] + lane; e < sc.ptr[q + 1]; e += G)
-                acc += (VALS ? (double)sc.val[e] : 1.0) * (double)a.udual[sc.row[e]];
+        for (int rq = 0; rq < kRowsPerThread; ++rq) {
+            const int64_t u = (local * kRowsPerThread + rq) * (kWG / G) + threadIdx.x / G;
+            const bool valid = u < count;
+            double acc = 0.0;
+            int32_t j = 0;
+            if (valid) {
+                const int64_t q = first + u;
+                j = sc.ids[q];
+                for (int32_t e = sc.ptr[q] + lane; e < sc.ptr[q + 1]; e += G)
+                    acc += (VALS ? (double)sc.val[e] : 1.0) * (double)a.udual[sc.row[e]];
+            }
+            for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            if (valid && lane == 0)
+                v[0] += box_min(a.c[j] - acc, col_ubound(a, j), rho, a.ybar ? (double)a.ybar[j] : 0.0);
         }
-        for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (valid && lane == 0)
-            v[0] = box_min(a.c[j] - acc, col_ubound(a, j), rho, a.ybar ? (double)a.ybar[j] : 0.0);
     } else if (kind == SEG_BLOCK) {
         // one wavefront per block, lpc lanes per column as in the sweep; the
         // minimum over the simplex without prox is the smallest reduced
-        // cost, with prox the value at the projection of yb - red/rho
-        const int64_t u = local * (kWG / 64) + (threadIdx.x >> 6);
+        // cost, with prox the value at the projection of yb - red/rho;
+        // kRowsPerThread blocks per wavefront
         const int lane = threadIdx.x & 63;
-        if (u < count) {                      // the whole wavefront together
+        for (int rq = 0; rq < kRowsPerThread; ++rq) {
+            const int64_t u = (local * kRowsPerThread + rq) * (kWG / 64) + (threadIdx.x >> 6);
+            if (u >= count) break;                // the whole wavefront together
             const int32_t bl = sc.ids[first + u];
             const int32_t k = a.k;
             int lpc = 64;
@@ -700,17 +705,18 @@ __device__ __forceinline__ void dual_item(const Dev<P> &a, const Sched<typename 
             } else {
                 term = -wmax(-red);
             }
-            if (lane == 0) v[0] = term;
+            if (lane == 0) v[0] += term;
         }
     } else if (kind == SEG_SLACK) {
-        const int64_t u = local * kWG + threadIdx.x;
-        if (u < count) {
+        for (int rq = 0; rq < kRowsPerThread; ++rq) {
+            const int64_t u = (local * kRowsPerThread + rq) * kWG + threadIdx.x;
+            if (u >= count) break;
             const int64_t i = slack_identity ? u : sc.ids[first + u];
             const int8_t sn = a.sense[i];
             const double sv = (double)a.s[i];
             const double yb = a.ybar ? (double)a.ybar[a.n + i] : 0.0;
-            if (a.prox_on) v[2] = 0.5 * rho * (sv - yb) * (sv - yb);
-            v[0] = box_min((sn > 0 ? 1.0 : -1.0) * (double)a.udual[i], INFINITY, rho, yb);
+            if (a.prox_on) v[2] += 0.5 * rho * (sv - yb) * (sv - yb);
+            v[0] += box_min((sn > 0 ? 1.0 : -1.0) * (double)a.udual[i], INFINITY, rho, yb);
         }
     } else {
         // every structural column (kRowsPerThread per thread): c^T x, the
@@ -1215,8 +1221,10 @@ LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolte
     for (int p = 0; p < kGridKinds; ++p) {
         pl.wg_start[p] = wg;
         const int kind = grid_kind(p);
-        const int64_t upw = kind < kGroupKinds ? kWG / pl.lanes[p] * pl.cols[p]
-                                               : (kind == SEG_NKIND ? kWG * kRowsPerThread : units_per_wg(kind, dual));
+        // dual plans: kRowsPerThread units per group / wavefront / thread
+        const int64_t upw = kind < kGroupKinds ? kWG / pl.lanes[p] * pl.cols[p] * (dual ? kRowsPerThread : 1)
+                          : (kind == SEG_NKIND ? kWG * kRowsPerThread
+                                               : units_per_wg(kind, dual) * (dual && kind != SEG_HUB ? kRowsPerThread : 1));
         int64_t w = pl.count[p] ? cdiv(pl.count[p], upw) : 0;
         if (kind == SEG_HUB) { w = cdiv(w, 8) * 8; pl.hub_wg = w; }
         wg += w;
