@@ -166,12 +166,17 @@ struct Sched {
 // Grid layout of one fused launch: the workgroup ranges of the segment
 // kinds in this order (hubs first so their long gathers start early).
 constexpr int kGridKinds = SEG_NKIND + 1;   // + the per-column terms of the dual pass
-// grid position -> segment kind: HUB, G4..G64, BLOCK, SLACK, column terms
+// grid position -> segment kind: HUB, G2..G64, BLOCK, SLACK, column terms
 __host__ __device__ constexpr int grid_kind(int p) {
-    return p == 0 ? SEG_HUB : (p <= kGroupKinds ? p - 1 : (p == 6 ? SEG_BLOCK : (p == 7 ? SEG_SLACK : SEG_NKIND)));
+    return p == 0 ? SEG_HUB
+                  : (p <= kGroupKinds ? p - 1
+                                      : (p == kGroupKinds + 1 ? SEG_BLOCK : (p == kGroupKinds + 2 ? SEG_SLACK : SEG_NKIND)));
 }
 __host__ __device__ constexpr int grid_pos(int kind) {
-    return kind == SEG_HUB ? 0 : (kind < kGroupKinds ? kind + 1 : (kind == SEG_BLOCK ? 6 : (kind == SEG_SLACK ? 7 : 8)));
+    return kind == SEG_HUB ? 0
+                           : (kind < kGroupKinds ? kind + 1
+                                                 : (kind == SEG_BLOCK ? kGroupKinds + 1
+                                                                      : (kind == SEG_SLACK ? kGroupKinds + 2 : kGroupKinds + 3)));
 }
 struct LaunchPlan {
     int64_t wg_start[kGridKinds + 1];   // by grid position
@@ -445,6 +450,7 @@ template <class P, bool VALS>
 __device__ __forceinline__ void sweep_groups(const Dev<P> &a, const Sched<typename P::R> &sc, int lanes, int cols,
                                              int64_t first, int64_t count, int64_t lwg) {
     switch (lanes) {
+        case 2: sweep_groups_c<P, VALS, 2>(a, sc, cols, first, count, lwg); break;
         case 4: sweep_groups_c<P, VALS, 4>(a, sc, cols, first, count, lwg); break;
         case 8: sweep_groups_c<P, VALS, 8>(a, sc, cols, first, count, lwg); break;
         case 16: sweep_groups_c<P, VALS, 16>(a, sc, cols, first, count, lwg); break;
@@ -1194,7 +1200,7 @@ size_t x_bytes(int32_t prec) { return prec == THETIS_PREC_FP64 ? 8 : (prec == TH
 
 int64_t units_per_wg(int kind, bool dual) {
     if (kind == SEG_HUB) return 1;
-    if (kind < kGroupKinds) return kWG / (4 << kind);
+    if (kind < kGroupKinds) return kWG / kGroupLanes[kind];
     if (kind == SEG_BLOCK) return kWG / 64;
     return kWG;
 }
@@ -1208,7 +1214,7 @@ LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolte
     LaunchPlan pl{};
     for (int p = 0; p < kGridKinds; ++p) {
         const int kind = grid_kind(p);
-        pl.lanes[p] = kind < kGroupKinds ? std::min(64, (4 << kind) * widen) : 0;
+        pl.lanes[p] = kind < kGroupKinds ? std::min(64, kGroupLanes[kind] * widen) : 0;
         pl.cols[p] = kind < kGroupKinds && !dual ? (pl.lanes[p] == 64 ? std::min(cols, 2) : cols) : 1;
     }
     for (const Segment &sg : segs) {

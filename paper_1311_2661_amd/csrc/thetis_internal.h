@@ -21,14 +21,14 @@ void clear_error();
 // residual entries staged in LDS; simplex blocks get one wavefront each;
 // slacks one lane each.
 enum SegKind : int32_t {
-    SEG_G4 = 0, SEG_G8, SEG_G16, SEG_G32, SEG_G64,   // lane groups
+    SEG_G2 = 0, SEG_G4, SEG_G8, SEG_G16, SEG_G32, SEG_G64,   // lane groups
     SEG_HUB,                                        // workgroup per column
     SEG_BLOCK,                                      // wavefront per simplex block
     SEG_SLACK,                                      // lane per slack row
     SEG_NKIND
 };
-constexpr int kGroupKinds = 5;
-constexpr int kGroupLanes[kGroupKinds] = {4, 8, 16, 32, 64};
+constexpr int kGroupKinds = 6;
+constexpr int kGroupLanes[kGroupKinds] = {2, 4, 8, 16, 32, 64};
 constexpr int kWG = 256;              // threads per workgroup, every kernel
 constexpr int kHubMinDegree = 65;     // columns with more entries go to SEG_HUB
 
