@@ -77,6 +77,11 @@ def lib():
         L.orc_penalty.restype = C.c_double
         L.orc_penalty.argtypes = [P]
         L.orc_metrics.argtypes = [P, dp]
+        L.orc_multiplier_step.argtypes = [P, C.c_int32, C.c_double, dp]
+        L.orc_get_ubar.argtypes = [P, dp]
+        L.orc_get_ybar.argtypes = [P, dp]
+        L.orc_beta.restype = C.c_double
+        L.orc_beta.argtypes = [P]
         L.orc_round.restype = C.c_int32
         L.orc_round.argtypes = [P, dp, C.c_int32, C.c_uint64, C.c_int32, i32p, C.POINTER(C.c_double), dp]
         L.orc_check.restype = C.c_int32
@@ -241,3 +246,28 @@ class OracleSolver:
         lib().orc_metrics(self.h, out)
         return dict(F=out[0], lp_value=out[1], linf=out[2], l2=out[3], max_viol=out[4],
                     dual_bound=out[5], gap=out[6])
+
+    def multiplier_step(self, move_centre: bool = False, beta: float = 0.0) -> dict:
+        """One augmented-Lagrangian update (Section 3.2): ubar -= beta (A y - b),
+        ybar <- y with move_centre (prox on), then beta <- beta when > 0.
+        Returns c^T x, ||A y - b||_inf, the LP dual bound D at the clipped new
+        multiplier and the relative LP gap, all at the current y."""
+        out = np.zeros(4)
+        lib().orc_multiplier_step(self.h, int(move_centre), float(beta), out)
+        return dict(lp_value=out[0], linf=out[1], lp_dual=out[2], lp_gap=out[3])
+
+    @property
+    def ubar(self) -> np.ndarray:
+        out = np.zeros(self.lp.m)
+        lib().orc_get_ubar(self.h, out)
+        return out
+
+    @property
+    def ybar(self) -> np.ndarray:
+        out = np.zeros(self.lp.N)
+        lib().orc_get_ybar(self.h, out)
+        return out
+
+    @property
+    def beta(self) -> float:
+        return lib().orc_beta(self.h)

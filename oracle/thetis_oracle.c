@@ -601,6 +601,85 @@ void orc_metrics(const orc_solver *s, double *out) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* One multiplier update between two penalty solves: the augmented
+ * Lagrangian framework of Section 3.2 (a proximal method of multipliers when
+ * prox is on).  With w = A y - b recomputed from y:
+ *     ubar <- ubar - beta w;   ybar <- y (move_centre, prox on only);
+ *     beta <- new_beta when new_beta > 0 (rho = 1/beta follows with prox);
+ *     ctil = c - A^T ubar and every unit's curvature recomputed.
+ * The statistics describe the iterate y at which the step is taken:
+ *   out[0] = c^T x, out[1] = ||w||_inf,
+ *   out[2] = D(u), the Lagrangian dual function of the LP of Section 3.1,
+ *            D(u) = b^T u + sum over variables of min over its feasible set
+ *            (box, or simplex for a free block, the unit vector for a fixed
+ *            block) of its reduced cost term, at u = the new ubar with each
+ *            inequality row's entry clipped to the sign its slack allows
+ *            (covering >= 0, packing <= 0), so that D(u) <= LP*,
+ *   out[3] = (out[0] - out[2]) / max(1, |out[0]|). */
+void orc_multiplier_step(orc_solver *s, int32_t move_centre, double new_beta, double *out) {
+    const orc_lp *p = s->lp;
+    int64_t m = p->m, n = p->n, N = p->N;
+    recompute_residual(s);
+    double *u = (double *)malloc((m + 1) * 8);
+    double linf = 0.0, bu = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double w = s->r[i];
+        if (fabs(w) > linf) linf = fabs(w);
+        s->ubar[i] = s->ubar[i] - s->beta * w;
+        double ui = s->ubar[i];
+        if (p->sense[i] > 0 && ui < 0.0) ui = 0.0;
+        if (p->sense[i] < 0 && ui > 0.0) ui = 0.0;
+        u[i] = ui;
+        bu += p->b[i] * ui;
+    }
+    double d = bu;
+    for (int64_t j = 0; j < N; ++j) {
+        if (j < n && p->col_block[j] >= 0) continue;
+        if (j >= n && p->sense[j - n] == 0) continue;
+        double red = p->c[j];
+        for (int64_t e = p->cptr[j]; e < p->cptr[j + 1]; ++e) red -= p->cval[e] * u[p->ridx[e]];
+        d += box_min(red, p->ub[j], 0.0, 0.0);
+    }
+    for (int64_t t = 0; t < p->nblocks; ++t) {
+        double best = INFINITY;
+        for (int32_t i = 0; i < p->k; ++i) {
+            if (p->fixed[t] >= 0 && i != p->fixed[t]) continue;
+            int64_t j = p->bfirst[t] + i;
+            double red = p->c[j];
+            for (int64_t e = p->cptr[j]; e < p->cptr[j + 1]; ++e) red -= p->cval[e] * u[p->ridx[e]];
+            if (red < best) best = red;
+        }
+        d += best;
+    }
+    free(u);
+    double cx = 0.0;
+    for (int64_t j = 0; j < n; ++j) cx += p->c[j] * s->y[j];
+    out[0] = cx; out[1] = linf; out[2] = d;
+    out[3] = (cx - d) / (fabs(cx) > 1.0 ? fabs(cx) : 1.0);
+    if (move_centre && s->rho > 0.0)
+        for (int64_t j = 0; j < N; ++j) s->ybar[j] = s->y[j];
+    if (new_beta > 0.0) {
+        int prox = s->rho > 0.0;
+        s->beta = new_beta;
+        s->rho = prox ? 1.0 / new_beta : 0.0;
+    }
+    for (int64_t j = 0; j < N; ++j) {
+        double acc = 0.0;
+        for (int64_t e = p->cptr[j]; e < p->cptr[j + 1]; ++e) acc += p->cval[e] * s->ubar[p->ridx[e]];
+        s->ctil[j] = p->c[j] - acc;
+    }
+    s->Lmax = 0.0;
+    for (int64_t t = 0; t < p->nunits; ++t) {
+        s->L[t] = unit_curvature(s, t);
+        if (s->L[t] > s->Lmax) s->Lmax = s->L[t];
+    }
+}
+
+void orc_get_ubar(const orc_solver *s, double *ubar) { memcpy(ubar, s->ubar, s->lp->m * 8); }
+void orc_get_ybar(const orc_solver *s, double *ybar) { memcpy(ybar, s->ybar, s->lp->N * 8); }
+double orc_beta(const orc_solver *s) { return s->beta; }
+
+/* ------------------------------------------------------------------------ */
 /* rounding (Section 2; Appendix B; Appendix C scalings).  x is the
  * structural part of y; sol is 0/1 per column (VC, MIS) or a label per
  * block (MC).  Returns 0, or -1 when the instance does not have the shape
