@@ -160,7 +160,8 @@ thetis_status thetis_solver_create(const thetis_inst *inst, const thetis_params 
 /* Back to the starting point (y = 0, epoch 0) without re-uploading. */
 thetis_status thetis_solver_reset(thetis_solver *s);
 
-/* Changes beta (recomputes every L_j) or the step rule between epochs. */
+/* Changes beta between epochs (with prox, rho = 1/beta follows); every
+ * curvature L_j and the simplex blocks' bounds are recomputed. */
 thetis_status thetis_set_beta(thetis_solver *s, double beta);
 thetis_status thetis_set_step_rule(thetis_solver *s, int32_t rule, double step_scale);
 
@@ -182,6 +183,56 @@ thetis_status thetis_run_epochs(thetis_solver *s, int32_t max_epochs, double gap
  * choice_host (NULL or one int per class) receives the choices.  Results do
  * not depend on them.  ASYNC solvers are left as they are. */
 thetis_status thetis_solver_autotune(thetis_solver *s, int32_t epochs_per_candidate, int32_t *choice_host);
+
+/* ------------------------------------------------ augmented Lagrangian */
+
+/* Figures of one multiplier step, all FP64, at the iterate y the step is
+ * taken at. */
+typedef struct {
+    double lp_value;   /* c^T x                                                   */
+    double linf;       /* ||A y - b||_inf                                         */
+    double lp_dual;    /* D(u) = b^T u + sum over variables of the minimum of its
+                          reduced-cost term over its feasible set (box; simplex
+                          for a free block; the unit vector for a fixed one), at
+                          u = the new ubar with each inequality row's entry
+                          clipped to the sign its slack allows (covering >= 0,
+                          packing <= 0): a lower bound on the LP optimum       */
+    double lp_gap;     /* (lp_value - lp_dual) / max(1, |lp_value|)               */
+    double device_ms;  /* device time of the step's three launches (HIP events) */
+    double alg_bytes;  /* their algorithmic bytes: CSR and CSC read once, x, s,
+                          ubar, ctil (and the prox centre when it moves)         */
+} thetis_mul_stats;
+
+/* One update of the augmented-Lagrangian framework of Section 3.2 between
+ * two penalty solves (with prox on, a proximal method of multipliers):
+ *     ubar <- ubar - beta (A y - b)   (w recomputed from y in FP64),
+ *     ybar <- y                        when move_centre != 0,
+ *     beta <- new_beta                 when new_beta > 0 (as thetis_set_beta),
+ * and the shifted costs c - A^T ubar recomputed in FP64 (stored in the
+ * storage precision).  y and the epoch count are unchanged.  The solver
+ * must have been created with a ubar (zeros are fine) and, for
+ * move_centre, with prox on and a ybar: THETIS_EUNSUPPORTED otherwise.
+ * stats_host may be NULL.  Synchronises the solver's stream. */
+thetis_status thetis_multiplier_step(thetis_solver *s, int32_t move_centre, double new_beta,
+                                     thetis_mul_stats *stats_host);
+
+/* Copies the current multiplier ubar (m entries, the caller's row order) and,
+ * if ybar_host is not NULL, the prox centre (n + m entries, x then one slack
+ * per row, as stored: in the storage precision) to the host.  Either may be
+ * NULL; asking for one the solver does not hold is THETIS_EUNSUPPORTED. */
+thetis_status thetis_get_multipliers(thetis_solver *s, double *ubar_host, double *ybar_host);
+
+/* The outer loop of that framework: up to max_outer times, run up to
+ * inner_epochs epochs (stopping early at the penalty gap inner_gap_tol as
+ * thetis_run_epochs does), then take a multiplier step with
+ * new_beta = min(beta * beta_growth, beta_max) when beta_growth > 1 (else
+ * beta is kept).  Stops after the first step whose linf and lp_gap are both
+ * <= tol.  outer_done, epochs_done and last_host (the last step's figures)
+ * may be NULL.  Errors as thetis_run_epochs and thetis_multiplier_step. */
+thetis_status thetis_run_multipliers(thetis_solver *s, int32_t max_outer, int32_t inner_epochs,
+                                     double inner_gap_tol, double beta_growth, double beta_max,
+                                     double tol, int32_t move_centre, int32_t *outer_done,
+                                     int64_t *epochs_done, thetis_mul_stats *last_host);
 
 /* Residual norms of the slack form, ||A y - b||_inf and ||.||_2, and the
  * largest violation of an original row by x (Definition of an

@@ -841,6 +841,184 @@ __global__ __launch_bounds__(kWG) void k_finalize(const double *rp, int64_t nr, 
     finalize_item(rp, nr, cp, nc, beta, with_dual, mt);
 }
 
+// ---------------------------------------------------------------- multiplier step
+// Augmented-Lagrangian update between two penalty solves (Section 3.2):
+// ubar <- ubar - beta (A y - b), optionally ybar <- y, and ctil = c - A^T ubar
+// recomputed in FP64, together with the LP dual function D at the new
+// multiplier clipped to the sign each inequality row's slack allows
+// (covering >= 0, packing <= 0): D(u) = b^T u + sum over variables of the
+// minimum of its reduced-cost term over its feasible set, a lower bound on
+// the LP optimum.  After the clip every slack's reduced cost is
+// non-negative, so the slacks add nothing to D.
+constexpr int kMulRowSlots = 2;   // sum b u, max |w|
+constexpr int kMulColSlots = 2;   // sum of minima, c^T x
+
+__device__ __forceinline__ double clip_dual(double u, int8_t sn) {
+    return sn > 0 ? fmax(u, 0.0) : (sn < 0 ? fmin(u, 0.0) : u);
+}
+
+// Row pass: w from x and s in FP64 (kRowsPerThread rows per thread), the new
+// multiplier, the slack entries of ctil (covering +ubar, packing -ubar) and,
+// when ybar_w is set, the slack part of the new prox centre.
+template <class P>
+__global__ __launch_bounds__(kWG) void k_mul_rows(Dev<P> a, double *ubar_w, typename P::R *ctil_w,
+                                                  typename P::R *ybar_w, double beta, double *part) {
+    using R = typename P::R;
+    double v[kMulRowSlots] = {0, 0};
+    const int op[kMulRowSlots] = {0, 1};
+    for (int q = 0; q < kRowsPerThread; ++q) {
+        const int64_t i = ((int64_t)blockIdx.x * kRowsPerThread + q) * kWG + threadIdx.x;
+        if (i >= a.m) break;
+        double acc = 0.0;
+        for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
+            acc += (a.csr_val ? (double)a.csr_val[e] : 1.0) * (double)xval(a.x[a.csr_col[e]]);
+        const int8_t sn = a.sense[i];
+        if (sn > 0) acc -= (double)a.s[i];
+        else if (sn < 0) acc += (double)a.s[i];
+        const double w = acc - a.b[i];
+        const double un = ubar_w[i] - beta * w;
+        ubar_w[i] = un;
+        ctil_w[a.n + i] = (R)(sn > 0 ? un : (sn < 0 ? -un : 0.0));
+        if (ybar_w) ybar_w[a.n + i] = a.s[i];
+        v[0] += a.b[i] * clip_dual(un, sn);
+        v[1] = fmax(v[1], fabs(w));
+    }
+    block_reduce<kMulRowSlots>(v, op, part + (int64_t)blockIdx.x * kMulRowSlots);
+}
+
+// Column pass on the refresh's column plan (every free unit in degree
+// buckets, then one range over all columns): per column the two gathers
+// A_j^T ubar (new ctil_j) and A_j^T clip(ubar) (reduced cost of D); plain
+// columns add their box minimum, free blocks the smallest reduced cost of
+// the block, fixed blocks the reduced cost of their fixed label; the range
+// over all columns adds c^T x, writes ctil of fixed-block columns and moves
+// the structural part of ybar.
+template <class P, bool VALS>
+__device__ __forceinline__ void mul_item(const Dev<P> &a, const Sched<typename P::R> &sc, const LaunchPlan &pl,
+                                         int64_t L, const double *ubar, typename P::R *ctil_w,
+                                         typename P::R *ybar_w, double *part, double *sh) {
+    using R = typename P::R;
+    int64_t local;
+    const int p = locate_logical(pl, L, &local);
+    const int64_t first = pl.first[p], count = pl.count[p];
+    const int kind = grid_kind(p);
+    double v[kMulColSlots] = {0, 0};
+    const int op[kMulColSlots] = {0, 0};
+    auto gather = [&](int32_t e0, int32_t e1, int32_t step, const R *val, const int32_t *row,
+                      double &t_u, double &t_c) {
+        for (int32_t e = e0; e < e1; e += step) {
+            const double av = VALS ? (double)val[e] : 1.0;
+            const int32_t i = row[e];
+            const double ub = ubar[i];
+            t_u += av * ub;
+            t_c += av * clip_dual(ub, a.sense[i]);
+        }
+    };
+    if (kind == SEG_HUB) {
+        const bool valid = local < count;
+        double tu = 0.0, tc = 0.0;
+        int32_t j = 0;
+        if (valid) {
+            const int64_t q = first + local;
+            j = sc.ids[q];
+            gather(sc.ptr[q] + threadIdx.x, sc.ptr[q + 1], kWG, sc.val, sc.row, tu, tc);
+        }
+        tu = block_sum_all(tu, sh);
+        tc = block_sum_all(tc, sh);
+        if (valid && threadIdx.x == 0) {
+            ctil_w[j] = (R)(a.c[j] - tu);
+            v[0] = box_min(a.c[j] - tc, col_ubound(a, j), 0.0, 0.0);
+        }
+    } else if (kind < kGroupKinds) {
+        const int G = pl.lanes[p];
+        const int lane = threadIdx.x & (G - 1);
+        for (int rq = 0; rq < kRowsPerThread; ++rq) {
+            const int64_t u = (local * kRowsPerThread + rq) * (kWG / G) + threadIdx.x / G;
+            const bool valid = u < count;
+            double tu = 0.0, tc = 0.0;
+            int32_t j = 0;
+            if (valid) {
+                const int64_t q = first + u;
+                j = sc.ids[q];
+                gather(sc.ptr[q] + lane, sc.ptr[q + 1], G, sc.val, sc.row, tu, tc);
+            }
+            for (int o = G / 2; o > 0; o >>= 1) {
+                tu += __shfl_xor(tu, o, 64);
+                tc += __shfl_xor(tc, o, 64);
+            }
+            if (valid && lane == 0) {
+                ctil_w[j] = (R)(a.c[j] - tu);
+                v[0] += box_min(a.c[j] - tc, col_ubound(a, j), 0.0, 0.0);
+            }
+        }
+    } else if (kind == SEG_BLOCK) {
+        const int lane = threadIdx.x & 63;
+        for (int rq = 0; rq < kRowsPerThread; ++rq) {
+            const int64_t u = (local * kRowsPerThread + rq) * (kWG / 64) + (threadIdx.x >> 6);
+            if (u >= count) break;                // the whole wavefront together
+            const int32_t bl = sc.ids[first + u];
+            const int32_t k = a.k;
+            int lpc = 64;
+            while (lpc * k > 64) lpc >>= 1;
+            const int ci = lane / lpc, sub = lane % lpc;
+            const bool own = ci < k;
+            const int32_t j = a.bfirst[bl] + (own ? ci : 0);
+            double tu = 0.0, tc = 0.0;
+            if (own) gather(a.col_ptr[j] + sub, a.col_ptr[j + 1], lpc, a.cval, a.row_idx, tu, tc);
+            for (int o = lpc / 2; o > 0; o >>= 1) {
+                tu += __shfl_xor(tu, o, 64);
+                tc += __shfl_xor(tc, o, 64);
+            }
+            if (own && sub == 0) ctil_w[j] = (R)(a.c[j] - tu);
+            const double red = own ? a.c[j] - tc : INFINITY;
+            const double term = -wmax(-red);
+            if (lane == 0) v[0] += term;
+        }
+    } else if (kind == SEG_NKIND) {
+        for (int q = 0; q < kRowsPerThread; ++q) {
+            const int64_t j = (local * kRowsPerThread + q) * kWG + threadIdx.x;
+            if (j >= a.n) break;
+            const auto xs = a.x[j];
+            v[1] += a.c[j] * (double)xval(xs);
+            if (ybar_w) ybar_w[j] = (R)xval(xs);
+            const int32_t bl = a.col_block ? a.col_block[j] : -1;
+            if (bl >= 0 && a.fixed[bl] >= 0) {
+                double tu = 0.0, tc = 0.0;
+                gather(a.col_ptr[j], a.col_ptr[j + 1], 1, a.cval, a.row_idx, tu, tc);
+                ctil_w[j] = (R)(a.c[j] - tu);
+                if (j == a.bfirst[bl] + a.fixed[bl]) v[0] += a.c[j] - tc;
+            }
+        }
+    }
+    // slack units add nothing (clipped multiplier: reduced cost >= 0)
+    block_reduce<kMulColSlots>(v, op, part + L * kMulColSlots);
+}
+
+template <class P, bool VALS>
+__global__ __launch_bounds__(kWG) void k_mul_cols(Dev<P> a, Sched<typename P::R> sc, LaunchPlan pl,
+                                                  const double *ubar, typename P::R *ctil_w,
+                                                  typename P::R *ybar_w, double *part) {
+    __shared__ double sh[kWG / 64];
+    mul_item<P, VALS>(a, sc, pl, logical_wg(pl, blockIdx.x), ubar, ctil_w, ybar_w, part, sh);
+}
+
+// out: c^T x, max |w|, D, (c^T x - D) / max(1, |c^T x|)
+__global__ __launch_bounds__(kWG) void k_mul_final(const double *rp, int64_t nr, const double *cp, int64_t nc,
+                                                   double *out) {
+    const int rop[kMulRowSlots] = {0, 1};
+    const int cop[kMulColSlots] = {0, 0};
+    double rs[kMulRowSlots], cs[kMulColSlots];
+    fold_records<kMulRowSlots>(rp, nr, rop, rs);
+    fold_records<kMulColSlots>(cp, nc, cop, cs);
+    if (threadIdx.x == 0) {
+        const double d = rs[0] + cs[0];
+        out[0] = cs[1];
+        out[1] = rs[1];
+        out[2] = d;
+        out[3] = (cs[1] - d) / (fabs(cs[1]) > 1.0 ? fabs(cs[1]) : 1.0);
+    }
+}
+
 // ---------------------------------------------------------------- rounding
 // edge pass for the two-entry rows: op 0 min (x_u+x_v)/2, 1 max (x_u+x_v)/2,
 // 2 max (x_u+x_v-1)
@@ -1149,6 +1327,10 @@ struct thetis_solver {
     // parameters
     thetis_params p{};
     double rho = 0.0, Lmax = 0.0;
+    // curvature factors without beta: every unit's curvature is beta * a + rho
+    // (a = ||A_j||^2, the block's Gershgorin bound, or 1 for a slack)
+    double amax = 0.0;
+    std::vector<double> lb_factor;             // a per simplex block (-1 for fixed ones)
     bool has_ybar = false, has_ubar = false;
     // device
     hipStream_t stream = nullptr;
@@ -1161,7 +1343,7 @@ struct thetis_solver {
         *async_sched, *pk_det_ptr, *pk_det_row, *pk_det_val, *pk_async_ptr, *pk_async_row,
         *pk_async_val, *pb_id, *pb_j0, *pb_ptr, *pb_row, *pb_val, *rpart, *cpart, *metrics, *sol, *best, *drop,
         *ckr_order, *thr, *costbuf,
-        *chkbuf, *ystage, *row_orig;
+        *chkbuf, *mulstats, *ystage, *row_orig;
     int64_t nwg_rows = 0, nwg_cols = 0;
     int64_t epoch = 0;
     bool metrics_fresh = false;
@@ -1298,6 +1480,7 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.thr = cv.take(8 * 4);
     S.costbuf = cv.take(8 * 4);
     S.chkbuf = cv.take(8 * 4);
+    S.mulstats = cv.take(8 * 4);
     S.ystage = cv.take(8 * std::max<int64_t>(n + m, 1));
     S.row_orig = cv.take(4 * std::max<int64_t>(m, 1));
     *total = cv.off + 256;
@@ -1542,6 +1725,61 @@ thetis_status reset_impl(thetis_solver &S) {
     return refresh<P>(S, true, false);
 }
 
+// Multiplier step: row pass, column pass on the refresh's column plan, fold;
+// out[0..3] as k_mul_final writes them, out[4] the device time (ms) of the
+// three launches.
+template <class P>
+thetis_status multiplier_impl(thetis_solver &S, bool move_centre, double *out) {
+    using R = typename P::R;
+    Dev<P> a = make_dev<P>(S);
+    R *ybar_w = move_centre ? (R *)S.ybar : nullptr;
+    const int64_t gr = cdiv(std::max<int64_t>(S.m, 1), (int64_t)kWG * kRowsPerThread);
+    const LaunchPlan &pl = S.dual;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(THETIS_EDEVICE, "hipEventCreate failed");
+    }
+    (void)hipEventRecord(e0, S.stream);
+    hipLaunchKernelGGL((k_mul_rows<P>), dim3(gr), dim3(kWG), 0, S.stream, a, (double *)S.ubar, (R *)S.ctil,
+                       ybar_w, S.p.beta, (double *)S.rpart);
+    if (pl.nwg > 0) {
+        if (S.unit_vals) hipLaunchKernelGGL((k_mul_cols<P, false>), dim3(pl.nwg), dim3(kWG), 0, S.stream, a, async_sched<P>(S), pl, (const double *)S.ubar, (R *)S.ctil, ybar_w, (double *)S.cpart);
+        else hipLaunchKernelGGL((k_mul_cols<P, true>), dim3(pl.nwg), dim3(kWG), 0, S.stream, a, async_sched<P>(S), pl, (const double *)S.ubar, (R *)S.ctil, ybar_w, (double *)S.cpart);
+    }
+    hipLaunchKernelGGL(k_mul_final, dim3(1), dim3(kWG), 0, S.stream, (const double *)S.rpart, gr,
+                       (const double *)S.cpart, pl.nwg, (double *)S.mulstats);
+    (void)hipEventRecord(e1, S.stream);
+    hipError_t err = hipGetLastError();
+    if (err == hipSuccess) err = hipMemcpyAsync(out, S.mulstats, 4 * sizeof(double), hipMemcpyDeviceToHost, S.stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(S.stream);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(err);
+    out[4] = ms;
+    S.metrics_fresh = false;
+    return THETIS_OK;
+}
+
+// Algorithmic bytes of one multiplier step (R real, X stored x, V a matrix
+// value when stored): row pass per row: pointer 4, b 8, sense 1, s R, ubar
+// read and written 16, slack ctil R (+ ybar R), per entry column index 4 +
+// V + x X; column pass per structural column: list entry 4, pointer 4, c 8,
+// bound R when stored, ctil R, per entry row index 4 + V + ubar 8 + sense 1;
+// the range over all columns: c 8, x X (+ block id 4, + ybar R).
+double multiplier_traffic(const thetis_solver &S, bool move_centre) {
+    const double R = (double)prec_bytes(S.p.precision), X = (double)x_bytes(S.p.precision);
+    const double V = S.unit_vals ? 0.0 : R;
+    const double m = (double)S.m, n = (double)S.n, nnz = (double)S.nnz;
+    const double rows = m * (4 + 8 + 1 + R + 16 + R + (move_centre ? R : 0)) + nnz * (4 + V + X);
+    const double cols = n * (4 + 4 + 8 + (S.uniform_ub ? 0 : R) + R) + nnz * (4 + V + 8 + 1);
+    const double all = n * (8 + X + (S.nblocks ? 4 : 0) + (move_centre ? R : 0));
+    return rows + cols + all;
+}
+
 template <class P>
 thetis_status set_y_impl(thetis_solver &S, const double *y) {
     HIP_TRY(hipMemcpyAsync(S.ystage, y, 8 * (S.n + S.m), hipMemcpyHostToDevice, S.stream));
@@ -1712,7 +1950,8 @@ void compute_curvatures(thetis_solver &S, const Inst &in, std::vector<double> &n
         norm2[j] = a2;
     }
     LB.assign(in.nblocks, 0.0);
-    double Lmax = 0.0;
+    S.lb_factor.assign(in.nblocks, -1.0);
+    double amax = 0.0;
     for (int64_t t = 0; t < in.nblocks; ++t) {
         if (in.fixed[t] >= 0) continue;
         double best = 0.0;
@@ -1728,16 +1967,20 @@ void compute_curvatures(thetis_solver &S, const Inst &in, std::vector<double> &n
             }
             best = std::max(best, acc);
         }
+        S.lb_factor[t] = best;
         LB[t] = S.p.beta * best + S.rho;
-        Lmax = std::max(Lmax, LB[t]);
+        amax = std::max(amax, best);
     }
     for (int64_t j = 0; j < in.n; ++j) {
         if (in.nblocks && in.col_block[j] >= 0) continue;
-        Lmax = std::max(Lmax, S.p.beta * norm2[j] + S.rho);
+        amax = std::max(amax, norm2[j]);
     }
     for (int64_t i = 0; i < in.m; ++i)
-        if (in.sense[i] != 0) Lmax = std::max(Lmax, S.p.beta + S.rho);
-    S.Lmax = Lmax;
+        if (in.sense[i] != 0) amax = std::max(amax, 1.0);
+    S.amax = amax;
+    // beta * a + rho is monotone in a (also after rounding): the largest
+    // curvature is the one of the largest factor
+    S.Lmax = in.nunits ? S.p.beta * amax + S.rho : 0.0;
 }
 
 template <class T>
@@ -1994,19 +2237,120 @@ extern "C" thetis_status thetis_solver_reset(thetis_solver *s) {
     return DISPATCH(*s, reset_impl)(*s);
 }
 
+namespace {
+
+// new beta: rho follows with prox; the plain columns' curvatures are formed
+// from beta in the kernels, the blocks' bounds are stored and re-uploaded
+thetis_status apply_beta(thetis_solver &S, double beta) {
+    S.p.beta = beta;
+    S.rho = S.p.prox ? 1.0 / beta : 0.0;
+    S.Lmax = S.nunits ? beta * S.amax + S.rho : 0.0;
+    S.metrics_fresh = false;
+    if (S.nblocks) {
+        std::vector<double> LB(S.nblocks, 0.0);
+        for (int64_t t = 0; t < S.nblocks; ++t)
+            if (S.lb_factor[t] >= 0.0) LB[t] = beta * S.lb_factor[t] + S.rho;
+        thetis_status st = upload_real(S, S.LB, LB);
+        if (st) return st;
+    }
+    return THETIS_OK;
+}
+
+}  // namespace
+
 extern "C" thetis_status thetis_set_beta(thetis_solver *s, double beta) {
     clear_error();
     if (!s) return fail(THETIS_EINVAL, "solver is NULL");
     if (!(beta > 0.0) || !std::isfinite(beta)) return fail(THETIS_EINVAL, "beta must be positive");
-    if (s->nblocks) return fail(THETIS_EUNSUPPORTED, "changing beta with simplex blocks needs a new solver");
-    const double old = s->p.beta;
-    s->p.beta = beta;
-    s->rho = s->p.prox ? 1.0 / beta : 0.0;
-    // every curvature is beta * ||A_j||^2 + rho; Lmax scales the same way
-    const double oldrho = s->p.prox ? 1.0 / old : 0.0;
-    s->Lmax = (s->Lmax - oldrho) / old * beta + s->rho;
-    s->metrics_fresh = false;
+    return apply_beta(*s, beta);
+}
+
+extern "C" thetis_status thetis_multiplier_step(thetis_solver *s, int32_t move_centre, double new_beta,
+                                                thetis_mul_stats *stats_host) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    thetis_solver &S = *s;
+    if (!S.has_ubar) return fail(THETIS_EUNSUPPORTED, "the solver was created without ubar");
+    if (move_centre && !S.has_ybar) return fail(THETIS_EUNSUPPORTED, "moving the prox centre needs prox on and a ybar");
+    if (!(new_beta == 0.0 || (new_beta > 0.0 && std::isfinite(new_beta))))
+        return fail(THETIS_EINVAL, "new_beta must be 0 (keep) or positive");
+    double out[5] = {0, 0, 0, 0, 0};
+    thetis_status st = DISPATCH(S, multiplier_impl)(S, move_centre != 0, out);
+    if (st) return st;
+    if (new_beta > 0.0) {
+        st = apply_beta(S, new_beta);
+        if (st) return st;
+    }
+    if (stats_host) {
+        stats_host->lp_value = out[0];
+        stats_host->linf = out[1];
+        stats_host->lp_dual = out[2];
+        stats_host->lp_gap = out[3];
+        stats_host->device_ms = out[4];
+        stats_host->alg_bytes = multiplier_traffic(S, move_centre != 0);
+    }
+    if (!std::isfinite(out[0]) || std::isnan(out[2])) return fail(THETIS_EDIVERGED, "NaN or Inf in the multiplier step");
     return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_get_multipliers(thetis_solver *s, double *ubar_host, double *ybar_host) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    thetis_solver &S = *s;
+    if (ubar_host && !S.has_ubar) return fail(THETIS_EUNSUPPORTED, "the solver was created without ubar");
+    if (ybar_host && !S.has_ybar) return fail(THETIS_EUNSUPPORTED, "the solver has no prox centre");
+    const int64_t n = S.n, m = S.m;
+    std::vector<int32_t> ro(m);
+    std::vector<double> u(ubar_host ? m : 0);
+    const size_t R = prec_bytes(S.p.precision);
+    std::vector<char> yb(ybar_host ? R * (n + m) : 0);
+    if (m) HIP_TRY(hipMemcpyAsync(ro.data(), S.row_orig, 4 * m, hipMemcpyDeviceToHost, S.stream));
+    if (ubar_host && m) HIP_TRY(hipMemcpyAsync(u.data(), S.ubar, 8 * m, hipMemcpyDeviceToHost, S.stream));
+    if (ybar_host && n + m) HIP_TRY(hipMemcpyAsync(yb.data(), S.ybar, yb.size(), hipMemcpyDeviceToHost, S.stream));
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    // rows are stored in the layout's order; hand them back in the caller's
+    if (ubar_host)
+        for (int64_t r = 0; r < m; ++r) ubar_host[ro[r]] = u[r];
+    if (ybar_host) {
+        auto get = [&](int64_t j) {
+            if (R == 8) { double v; std::memcpy(&v, yb.data() + 8 * j, 8); return v; }
+            float v; std::memcpy(&v, yb.data() + 4 * j, 4); return (double)v;
+        };
+        for (int64_t j = 0; j < n; ++j) ybar_host[j] = get(j);
+        for (int64_t r = 0; r < m; ++r) ybar_host[n + ro[r]] = get(n + r);
+    }
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_run_multipliers(thetis_solver *s, int32_t max_outer, int32_t inner_epochs,
+                                                double inner_gap_tol, double beta_growth, double beta_max,
+                                                double tol, int32_t move_centre, int32_t *outer_done,
+                                                int64_t *epochs_done, thetis_mul_stats *last_host) {
+    clear_error();
+    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+    if (max_outer < 0 || inner_epochs < 0) return fail(THETIS_EINVAL, "max_outer and inner_epochs must be >= 0");
+    if (beta_growth > 1.0 && !(beta_max > 0.0 && std::isfinite(beta_max)))
+        return fail(THETIS_EINVAL, "beta_max must be positive and finite when beta grows");
+    if (!(beta_growth >= 0.0) || !std::isfinite(beta_growth)) return fail(THETIS_EINVAL, "beta_growth must be finite and >= 0");
+    int32_t outer = 0;
+    int64_t epochs = 0;
+    thetis_mul_stats st_last{};
+    thetis_status st = THETIS_OK;
+    for (; outer < max_outer; ) {
+        int32_t done = 0;
+        st = thetis_run_epochs(s, inner_epochs, inner_gap_tol, &done);
+        epochs += done;
+        if (st) break;
+        const double nb = beta_growth > 1.0 ? std::min(s->p.beta * beta_growth, std::max(beta_max, s->p.beta)) : 0.0;
+        st = thetis_multiplier_step(s, move_centre, nb, &st_last);
+        ++outer;
+        if (st) break;
+        if (st_last.linf <= tol && st_last.lp_gap <= tol) break;
+    }
+    if (outer_done) *outer_done = outer;
+    if (epochs_done) *epochs_done = epochs;
+    if (last_host) *last_host = st_last;
+    return st;
 }
 
 extern "C" thetis_status thetis_set_step_rule(thetis_solver *s, int32_t rule, double scale) {

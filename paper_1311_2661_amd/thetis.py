@@ -35,7 +35,8 @@ EXPORTED = [
     "thetis_params_default", "thetis_inst_create_csr", "thetis_inst_set_simplex_blocks",
     "thetis_inst_classes", "thetis_inst_destroy", "thetis_solver_workspace_bytes",
     "thetis_solver_create", "thetis_solver_reset", "thetis_set_beta", "thetis_set_step_rule",
-    "thetis_run_epochs", "thetis_solver_autotune", "thetis_residual", "thetis_objective", "thetis_get_x",
+    "thetis_run_epochs", "thetis_solver_autotune", "thetis_multiplier_step", "thetis_run_multipliers",
+    "thetis_get_multipliers", "thetis_residual", "thetis_objective", "thetis_get_x",
     "thetis_set_y",
     "thetis_epoch", "thetis_round", "thetis_check_feasible", "thetis_set_timing",
     "thetis_get_timing", "thetis_epoch_traffic", "thetis_solver_destroy", "thetis_calibrate_random",
@@ -49,6 +50,14 @@ class ThetisError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"thetis error {code}: {msg}")
         self.code = code
+
+
+class thetis_mul_stats(C.Structure):
+    _fields_ = [("lp_value", C.c_double), ("linf", C.c_double), ("lp_dual", C.c_double),
+                ("lp_gap", C.c_double), ("device_ms", C.c_double), ("alg_bytes", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class thetis_params(C.Structure):
@@ -83,6 +92,10 @@ def lib():
             "thetis_set_step_rule": [vp, i32, dbl],
             "thetis_run_epochs": [vp, i32, dbl, P(i32)],
             "thetis_solver_autotune": [vp, i32, vp],
+            "thetis_multiplier_step": [vp, i32, dbl, P(thetis_mul_stats)],
+            "thetis_run_multipliers": [vp, i32, i32, dbl, dbl, dbl, dbl, i32, P(i32), P(i64),
+                                       P(thetis_mul_stats)],
+            "thetis_get_multipliers": [vp, vp, vp],
             "thetis_residual": [vp, P(dbl), P(dbl), P(dbl)],
             "thetis_objective": [vp, P(dbl), P(dbl), P(dbl)],
             "thetis_get_x": [vp, vp, vp],
@@ -193,6 +206,29 @@ def thetis_run_epochs(s, max_epochs: int, gap_tol: float = 0.0) -> int:
     done = C.c_int32()
     _check(lib().thetis_run_epochs(s, max_epochs, gap_tol, C.byref(done)))
     return done.value
+
+
+def thetis_multiplier_step(s, move_centre: bool = False, new_beta: float = 0.0) -> dict:
+    st = thetis_mul_stats()
+    _check(lib().thetis_multiplier_step(s, int(move_centre), float(new_beta), C.byref(st)))
+    return st.as_dict()
+
+
+def thetis_run_multipliers(s, max_outer: int, inner_epochs: int, inner_gap_tol: float = 0.0,
+                           beta_growth: float = 1.0, beta_max: float = 0.0, tol: float = 0.0,
+                           move_centre: bool = False):
+    outer, epochs, st = C.c_int32(), C.c_int64(), thetis_mul_stats()
+    _check(lib().thetis_run_multipliers(s, max_outer, inner_epochs, inner_gap_tol, beta_growth,
+                                        beta_max, tol, int(move_centre), C.byref(outer),
+                                        C.byref(epochs), C.byref(st)))
+    return outer.value, epochs.value, st.as_dict()
+
+
+def thetis_get_multipliers(s, m: int, n: int, multiplier: bool = True, centre: bool = False):
+    u = np.zeros(m) if multiplier else None
+    yb = np.zeros(n + m) if centre else None
+    _check(lib().thetis_get_multipliers(s, _ptr(u), _ptr(yb)))
+    return u, yb
 
 
 def thetis_residual(s):
@@ -393,6 +429,26 @@ class Solver:
         out = np.zeros(max(nc, 1), np.int32)
         _check(lib().thetis_solver_autotune(self.h, epochs_per_candidate, _ptr(out)))
         return [int(v) for v in out[:nc]]
+
+    def multiplier_step(self, move_centre: bool = False, beta: float = 0.0) -> dict:
+        """ubar -= beta (A y - b); ybar <- y with move_centre; then beta <- beta
+        when > 0.  Returns the step's figures at the current y."""
+        return thetis_multiplier_step(self.h, move_centre, beta)
+
+    def run_multipliers(self, max_outer: int, inner_epochs: int, inner_gap_tol: float = 0.0,
+                        beta_growth: float = 1.0, beta_max: float = 0.0, tol: float = 0.0,
+                        move_centre: bool = False):
+        """Outer loop: (outer steps done, epochs done, last step's figures)."""
+        return thetis_run_multipliers(self.h, max_outer, inner_epochs, inner_gap_tol, beta_growth,
+                                      beta_max, tol, move_centre)
+
+    @property
+    def ubar(self) -> np.ndarray:
+        return thetis_get_multipliers(self.h, self.m, self.n)[0]
+
+    @property
+    def ybar(self) -> np.ndarray:
+        return thetis_get_multipliers(self.h, self.m, self.n, multiplier=False, centre=True)[1]
 
     def residual(self):
         linf, l2, viol = thetis_residual(self.h)

@@ -1,0 +1,226 @@
+"""GPU parity of the augmented-Lagrangian multiplier step (Section 3.2)
+through the C ABI against the FP64 oracle's step on the same state.
+
+Bars (from the arithmetic):
+  * FP64 storage, DET schedule, same epochs and steps on both sides: the
+    multiplier, the prox centre and y agree to 1e-10 (only the order of the
+    FP64 sums differs); c^T x, ||w||_inf and the LP dual function D agree to
+    1e-12 relative.
+  * Full size (BA n = 2,000,000, FP32, the benchmark's configuration): the
+    step taken from the same y on both sides (the GPU's FP32 y is exact in
+    FP64) agrees to 1e-12 relative in every figure and 1e-9 absolute in
+    ubar; D never exceeds the cost of a feasible rounded cover.
+  * FP32 outer loop on a medium instance: reaches the LP optimum of HiGHS
+    to 1e-4 relative with ||w||_inf <= 1e-4, and D <= LP* at every step.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1311_2661_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+T = None
+
+
+def setup_module(module):
+    global T
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_2661_amd import thetis as TT
+    T = TT
+    torch.cuda.set_device(0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    if np.isinf(a) or np.isinf(b):
+        return 0.0 if a == b else np.inf
+    return abs(a - b) / max(1.0, abs(b))
+
+
+def pair(inst, beta=10.0, prox=False, seed=0, precision=None, **kw):
+    n, m = inst.n, inst.m
+    yb = np.zeros(n + m) if prox else None
+    ub = np.zeros(m)
+    g = T.Solver(T.Instance(inst), beta=beta, prox=prox, ybar=yb, ubar=ub,
+                 precision=T.PREC_FP64 if precision is None else precision, seed=seed, **kw)
+    lp = O.OracleLP(inst)
+    o = O.OracleSolver(lp, beta=beta, prox=prox, ybar=yb, ubar=ub, seed=seed)
+    return g, lp, o
+
+
+def compare_step(gs, os_, tol=1e-12):
+    for k in ("lp_value", "lp_dual"):
+        assert rel(gs[k], os_[k]) < tol, (k, gs[k], os_[k])
+    assert abs(gs["linf"] - os_["linf"]) < tol, (gs["linf"], os_["linf"])
+    assert gs["device_ms"] > 0 and gs["alg_bytes"] > 0
+
+
+def rounds(g, o, plan, prox, ytol=1e-10):
+    """plan: list of (epochs, new beta or 0)."""
+    for epochs, nb in plan:
+        g.run(epochs)
+        o.run(epochs)
+        assert np.abs(g.y - o.y).max() < ytol
+        gs = g.multiplier_step(move_centre=prox, beta=nb)
+        os_ = o.multiplier_step(move_centre=prox, beta=nb)
+        compare_step(gs, os_)
+        assert np.abs(g.ubar - o.ubar).max() < ytol
+        if prox:
+            assert np.abs(g.ybar - o.ybar).max() < ytol
+    g.run(10)
+    o.run(10)
+    assert np.abs(g.y - o.y).max() < ytol
+
+
+# ------------------------------------------------------------------ FP64 parity
+
+@pytest.mark.parametrize("prox", [False, True])
+def test_fp64_steps_with_beta_continuation_vertex_cover(prox):
+    say(f"case fp64 multiplier steps vc_er(1000, 5000) prox={prox}")
+    inst = I.vc_er(1000, 5000, seed=3)
+    g, lp, o = pair(inst, prox=prox, seed=3, refresh_every=1000000)
+    rounds(g, o, [(15, 0.0), (15, 20.0), (15, 40.0)], prox)
+
+
+def test_fp64_steps_multiway_cut_blocks():
+    """Free and fixed simplex blocks in D; a beta change re-forms the
+    blocks' curvature bounds."""
+    say("case fp64 multiplier steps multiway cut 16x16 k=4")
+    inst = I.mc_grid(side=16, k=4, seed=5)
+    g, lp, o = pair(inst, seed=5)
+    rounds(g, o, [(10, 0.0), (10, 30.0)], False, ytol=1e-9)
+
+
+def test_fp64_steps_independent_set_prox():
+    say("case fp64 multiplier steps mis_regular(600, 4) prox")
+    inst = I.mis_regular(600, 4, seed=2)
+    g, lp, o = pair(inst, prox=True, seed=2)
+    rounds(g, o, [(12, 0.0), (12, 0.0)], True)
+
+
+def test_fp64_steps_general_lp_values_equality_rows_and_bounds():
+    """Non-unit entries, all three senses, infinite bounds (D may be -inf),
+    an empty column and a long row."""
+    say("case fp64 multiplier steps general LP")
+    rng = np.random.default_rng(5)
+    m, n = 300, 200
+    rows = []
+    for i in range(m):
+        k = int(rng.integers(1, 6)) if i < m - 1 else 60
+        rows.append(np.sort(rng.choice(n - 1, size=k, replace=False)))
+    row_ptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    col = np.concatenate(rows).astype(np.int32)
+    val = rng.uniform(-2, 3, len(col))
+    sense = rng.choice([-1, 0, 1], size=m).astype(np.int8)
+    u = rng.uniform(0.5, 3, n)
+    u[rng.choice(n, 20, replace=False)] = np.inf
+    inst = I.LPInstance(m=m, n=n, row_ptr=row_ptr, col_idx=col, val=val, b=rng.uniform(-1, 2, m),
+                        c=rng.uniform(0.1, 2, n), u=u, sense=sense)
+    for prox in (False, True):
+        g, lp, o = pair(inst, beta=3.0, prox=prox, seed=9)
+        rounds(g, o, [(8, 0.0), (8, 6.0)], prox, ytol=1e-9)
+
+
+def test_fp64_step_on_hubs_and_every_lane_group():
+    say("case fp64 multiplier step hubs + lane groups")
+    edges = [(0, i) for i in range(1, 5001)]
+    base = 5001
+    edges += [(base, base + i) for i in range(1, 301)]
+    base += 301
+    for d in (1, 3, 5, 8, 12, 16, 20, 32, 40, 64):
+        edges += [(base, base + i) for i in range(1, d + 1)]
+        base += d + 1
+    edges = np.array(edges, dtype=np.int64)
+    inst = I.vc_lp(base, edges, np.random.default_rng(3).uniform(1, 10, base))
+    g, lp, o = pair(inst, seed=1)
+    rounds(g, o, [(6, 0.0), (6, 0.0)], False)
+
+
+def test_step_argument_errors():
+    inst = I.vc_er(200, 600, seed=1)
+    plain = T.Solver(T.Instance(inst))
+    with pytest.raises(T.ThetisError) as e:
+        plain.multiplier_step()
+    assert e.value.code == T.EUNSUPPORTED
+    g = T.Solver(T.Instance(inst), ubar=np.zeros(inst.m))
+    with pytest.raises(T.ThetisError) as e:
+        g.multiplier_step(move_centre=True)
+    assert e.value.code == T.EUNSUPPORTED
+    with pytest.raises(T.ThetisError) as e:
+        g.multiplier_step(beta=-1.0)
+    assert e.value.code == T.EINVAL
+    st = g.multiplier_step()
+    assert st["linf"] == pytest.approx(1.0)        # y = 0: every edge row has w = -1
+
+
+# ------------------------------------------------------------------ FP32
+
+def highs_vc(inst):
+    from scipy.optimize import linprog
+    from scipy.sparse import csr_matrix
+    A = csr_matrix((np.ones(inst.nnz), inst.col_idx, inst.row_ptr), shape=(inst.m, inst.n))
+    res = linprog(inst.c, A_ub=-A, b_ub=-inst.b, bounds=(0, 1), method="highs")
+    assert res.status == 0
+    return res.fun
+
+
+def test_fp32_outer_loop_reaches_the_lp_optimum():
+    say("case fp32 outer loop vc_er(2000, 8000)")
+    inst = I.vc_er(2000, 8000, seed=7)
+    lpstar = highs_vc(inst)
+    g = T.Solver(T.Instance(inst), beta=10.0, ubar=np.zeros(inst.m), precision=T.PREC_FP32, seed=7)
+    seen = []
+    for _ in range(12):
+        g.run(100, gap_tol=1e-7)
+        seen.append(g.multiplier_step())
+    for st in seen:
+        assert st["lp_dual"] <= lpstar * (1 + 1e-12) + 1e-12
+    last = seen[-1]
+    say(f"  LP* {lpstar:.10g}; last c^T x {last['lp_value']:.10g} linf {last['linf']:.2e} "
+        f"D {last['lp_dual']:.10g}")
+    assert last["linf"] <= 1e-4
+    assert rel(last["lp_value"], lpstar) <= 1e-4
+    assert rel(last["lp_dual"], lpstar) <= 1e-4
+    # the C loop reproduces the same sequence of states
+    h = T.Solver(T.Instance(inst), beta=10.0, ubar=np.zeros(inst.m), precision=T.PREC_FP32, seed=7)
+    outer, epochs, st = h.run_multipliers(12, 100, inner_gap_tol=1e-7)
+    assert outer == 12
+    assert st["lp_value"] == last["lp_value"] and st["lp_dual"] == last["lp_dual"]
+    assert np.array_equal(h.y, g.y)
+
+
+# ------------------------------------------------------------------ full size
+
+@pytest.mark.timeout(600)
+def test_full_size_ba_step_from_the_same_state():
+    import time
+    say("case full-size vc_ba n=2000000: multiplier step from the same y")
+    t0 = time.time()
+    inst = I.vc_ba(2_000_000, seed=0)
+    g = T.Solver(T.Instance(inst), beta=10.0, ubar=np.zeros(inst.m), precision=T.PREC_FP32,
+                 refresh_every=5, seed=0)
+    g.run(100)
+    y = g.y
+    gs = g.multiplier_step()
+    gu = g.ubar
+    say(f"  gpu done {time.time() - t0:.1f} s; step {gs['device_ms']:.3f} ms")
+    lp = O.OracleLP(inst)
+    o = O.OracleSolver(lp, beta=10.0, ubar=np.zeros(inst.m), seed=0)
+    o.y = y
+    os_ = o.multiplier_step()
+    say(f"  oracle done {time.time() - t0:.1f} s; D {gs['lp_dual']:.12g} vs {os_['lp_dual']:.12g}")
+    compare_step(gs, os_)
+    assert np.abs(gu - o.ubar).max() <= 1e-9
+    sol, cost, _ = g.round(T.ROUND_VC_THRESH)
+    assert g.check(T.ROUND_VC_THRESH) == (True, 0)
+    assert gs["lp_dual"] <= cost
