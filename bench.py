@@ -420,6 +420,107 @@ def mc_grid(args):
     print(json.dumps(out), flush=True)
 
 
+def al_ba(args):
+    """Augmented-Lagrangian outer loop on the vertex-cover LP of the BA graph
+    (n = 2,000,000, FP32 storage): starting from ubar = 0, blocks of
+    `inner` epochs alternate with multiplier steps until ||A y - b||_inf <=
+    feas_tol and the LP gap certified by the dual function <= lp_gap_tol
+    (at most `outer` steps); then threshold rounding and the check."""
+    import torch
+    from paper_1311_2661_amd import instances as I
+    from paper_1311_2661_amd import thetis as T
+    T.lib()
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    inst = I.vc_ba(args.n, seed=args.seed)
+    log(f"instance: BA n={inst.n} edges={inst.m} ({time.perf_counter() - t0:.1f} s)")
+    h = T.Instance(inst)
+    s = T.Solver(h, beta=10.0, ubar=np.zeros(inst.m), precision=T.PREC_FP32, refresh_every=5, seed=args.seed)
+    tuned = s.autotune(4)
+    log(f"columns per lane group by class: {tuned}")
+    upd = s.traffic()["updates_per_epoch"]
+
+    def step():
+        s.reset()
+        outer, epochs, st = s.run_multipliers(args.outer, args.inner, feas_tol=args.feas_tol,
+                                              lp_gap_tol=args.lp_gap_tol)
+        sol, cost, aux = s.round(T.ROUND_VC_THRESH)
+        feas, nviol = s.check(T.ROUND_VC_THRESH)
+        return outer, epochs, st, cost, feas
+
+    for w in range(args.warmup):
+        r = step()
+        log(f"warmup {w}: outer {r[0]} epochs {r[1]} linf {r[2]['linf']:.3e} gap {r[2]['lp_gap']:.3e}")
+    s.set_timing(10)
+    acc = {k: dict(ms=0.0, launches=0, alg_bytes=0.0) for k in T.KERNEL_NAMES.values()}
+    mul_ms, mul_bytes, results = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = step()
+        results.append(r)
+        mul_ms.append(r[2]["device_ms"])
+        mul_bytes.append(r[2]["alg_bytes"])
+        for name, v in s.timing().items():
+            for f in ("ms", "launches", "alg_bytes"):
+                acc[name][f] += v[f]
+        log(f"step {k} done: outer {r[0]} epochs {r[1]}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s.set_timing(0)
+    assert all(r[4] for r in results), "rounded cover infeasible"
+    outer, epochs, st, cost, feas = results[-1]
+    g = acc["k_sweep"]
+    avg_ms = g["ms"] / max(g["launches"], 1)
+    avg_bytes = g["alg_bytes"] / max(g["launches"], 1)
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    mms = float(np.mean(mul_ms))
+    mgbs = float(np.mean(mul_bytes)) / (mms * 1e-3) / 1e9
+    workload = (f"vc_ba_n{args.n}_m3_augmented_lagrangian_beta10_fp32_refresh5_{args.inner}ep_per_step_"
+                f"to_linf{args.feas_tol:g}_gap{args.lp_gap_tol:g}_det")
+    out = {
+        "metric": METRIC, "value": sum(r[1] for r in results) * upd / elapsed, "unit": "coord updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": workload, "graph": "barabasi_albert", "n_vertices": inst.n, "edges": inst.m,
+                   "coordinates_per_epoch": upd, "beta": 10.0, "epochs_per_outer_step": args.inner,
+                   "max_outer_steps": args.outer, "feas_tol": args.feas_tol, "lp_gap_tol": args.lp_gap_tol,
+                   "group_cols_by_class": tuned, "seed": args.seed},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": avg_bytes, "avg_launch_us": 1e3 * avg_ms},
+        "multiplier_step": {"device_ms": mms, "alg_bytes": float(np.mean(mul_bytes)), "alg_gbs": mgbs,
+                            "frac_of_hbm_peak": mgbs / HBM_PEAK_GBS, "kernels": "k_mul_rows + k_mul_cols + k_mul_final"},
+        "solution": {"outer_steps": outer, "epochs": epochs, "lp_value": st["lp_value"], "lp_dual": st["lp_dual"],
+                     "lp_gap": st["lp_gap"], "linf": st["linf"], "cover_cost": cost, "feasible": bool(feas)},
+    }
+    log(f"solve: {outer} outer steps, {epochs} epochs, c^T x {st['lp_value']:.10g} D {st['lp_dual']:.10g} "
+        f"linf {st['linf']:.3e}; multiplier step {mms:.3f} ms ({mgbs:.0f} GB/s)")
+    if args.cpu_baseline_seconds > 0:
+        from oracle import oracle as O
+        lp = O.OracleLP(inst)
+        o = O.OracleSolver(lp, beta=10.0, ubar=np.zeros(inst.m), seed=args.seed)
+        t0 = time.perf_counter()
+        o.run(1)
+        t_ep = time.perf_counter() - t0
+        more = int(max(0, min(args.inner - 1, args.cpu_baseline_seconds / max(t_ep, 1e-9) - 2)))
+        t0 = time.perf_counter()
+        if more:
+            o.run(more)
+        t_more = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        o.multiplier_step()
+        t_mul = time.perf_counter() - t0
+        ne = 1 + more
+        # one multiplier step per `inner` epochs, as in the GPU solve
+        tt = t_ep + t_more + t_mul * ne / args.inner
+        out["cpu_baseline"] = dict(value=ne * upd / tt, unit="coord updates/s", cores=1, kind="oracle",
+                                   sample=f"{ne} epochs of the same instance from ubar = 0 (DET class order) and "
+                                          f"one multiplier step ({t_mul:.2f} s) charged at one per {args.inner} "
+                                          f"epochs; serial FP64 C, setup excluded")
+    print(json.dumps(out), flush=True)
+
+
 def _serve_compact(req):
     from paper_1311_2661_amd import instances as I
     return I.serving_compact(req)
@@ -548,7 +649,11 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the k_sweep traffic summary from two rocprofv3 counter runs and exit")
-    ap.add_argument("--workload", choices=["vc_ba", "mc_grid", "mis_batch", "serve"], default="vc_ba")
+    ap.add_argument("--workload", choices=["vc_ba", "mc_grid", "mis_batch", "serve", "al_ba"], default="vc_ba")
+    ap.add_argument("--outer", type=int, default=40, help="al_ba: most multiplier steps")
+    ap.add_argument("--inner", type=int, default=50, help="al_ba: epochs between multiplier steps")
+    ap.add_argument("--feas-tol", type=float, default=5e-2, help="al_ba: ||A y - b||_inf to stop at")
+    ap.add_argument("--lp-gap-tol", type=float, default=1e-4, help="al_ba: certified LP gap to stop at")
     ap.add_argument("--side", type=int, default=1024, help="mc_grid: grid side")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
@@ -581,6 +686,8 @@ def main():
         return mis_batch(args)
     if args.workload == "serve":
         return serve(args)
+    if args.workload == "al_ba":
+        return al_ba(args)
     if args.workload == "mc_grid":
         if args.epochs == 100:
             args.epochs = 200

@@ -157,7 +157,10 @@ thetis_status thetis_solver_create(const thetis_inst *inst, const thetis_params 
                                    void *dev_workspace, size_t ws_bytes, void *stream,
                                    thetis_solver **out);
 
-/* Back to the starting point (y = 0, epoch 0) without re-uploading. */
+/* Back to the starting point (y = 0, epoch 0) without re-uploading.  After
+ * multiplier steps, ubar, ybar and the shifted costs return to the values
+ * given at creation and beta to the one of creation or of the last
+ * thetis_set_beta. */
 thetis_status thetis_solver_reset(thetis_solver *s);
 
 /* Changes beta between epochs (with prox, rho = 1/beta follows); every
@@ -226,13 +229,16 @@ thetis_status thetis_get_multipliers(thetis_solver *s, double *ubar_host, double
  * inner_epochs epochs (stopping early at the penalty gap inner_gap_tol as
  * thetis_run_epochs does), then take a multiplier step with
  * new_beta = min(beta * beta_growth, beta_max) when beta_growth > 1 (else
- * beta is kept).  Stops after the first step whose linf and lp_gap are both
- * <= tol.  outer_done, epochs_done and last_host (the last step's figures)
- * may be NULL.  Errors as thetis_run_epochs and thetis_multiplier_step. */
+ * beta is kept).  Stops after the first step with linf <= feas_tol and
+ * lp_gap <= lp_gap_tol (an (eps, delta)-approximate point of Section 3.1,
+ * certified by the dual bound).  outer_done, epochs_done and last_host (the
+ * last step's figures) may be NULL.  Errors as thetis_run_epochs and
+ * thetis_multiplier_step. */
 thetis_status thetis_run_multipliers(thetis_solver *s, int32_t max_outer, int32_t inner_epochs,
                                      double inner_gap_tol, double beta_growth, double beta_max,
-                                     double tol, int32_t move_centre, int32_t *outer_done,
-                                     int64_t *epochs_done, thetis_mul_stats *last_host);
+                                     double feas_tol, double lp_gap_tol, int32_t move_centre,
+                                     int32_t *outer_done, int64_t *epochs_done,
+                                     thetis_mul_stats *last_host);
 
 /* Residual norms of the slack form, ||A y - b||_inf and ||.||_2, and the
  * largest violation of an original row by x (Definition of an

@@ -1332,6 +1332,8 @@ struct thetis_solver {
     double amax = 0.0;
     std::vector<double> lb_factor;             // a per simplex block (-1 for fixed ones)
     bool has_ybar = false, has_ubar = false;
+    double beta0 = 0.0;                        // beta at creation
+    bool mul_dirty = false;                    // ubar / ctil / ybar / beta moved since creation
     // device
     hipStream_t stream = nullptr;
     bool own_ws = false;
@@ -1343,7 +1345,7 @@ struct thetis_solver {
         *async_sched, *pk_det_ptr, *pk_det_row, *pk_det_val, *pk_async_ptr, *pk_async_row,
         *pk_async_val, *pb_id, *pb_j0, *pb_ptr, *pb_row, *pb_val, *rpart, *cpart, *metrics, *sol, *best, *drop,
         *ckr_order, *thr, *costbuf,
-        *chkbuf, *mulstats, *ystage, *row_orig;
+        *chkbuf, *mulstats, *ystage, *row_orig, *ctil0, *ybar0, *ubar0;
     int64_t nwg_rows = 0, nwg_cols = 0;
     int64_t epoch = 0;
     bool metrics_fresh = false;
@@ -1442,6 +1444,10 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.ub = in.uniform_ub ? nullptr : cv.take(R * n);
     S.ybar = S.has_ybar ? cv.take(R * (n + m)) : nullptr;
     S.ubar = S.has_ubar ? cv.take(8 * m) : nullptr;
+    // the values given at creation, restored by a reset after multiplier steps
+    S.ctil0 = S.has_ubar ? cv.take(R * (n + m)) : nullptr;
+    S.ybar0 = S.has_ybar ? cv.take(R * (n + m)) : nullptr;
+    S.ubar0 = S.has_ubar ? cv.take(8 * m) : nullptr;
     S.bfirst = nb ? cv.take(4 * nb) : nullptr;
     S.fixed = nb ? cv.take(4 * nb) : nullptr;
     S.col_block = nb ? cv.take(4 * n) : nullptr;
@@ -1714,8 +1720,23 @@ thetis_status run_epochs_impl(thetis_solver &S, int32_t max_epochs, double gap_t
     return st;
 }
 
+thetis_status apply_beta(thetis_solver &S, double beta);
+
 template <class P>
 thetis_status reset_impl(thetis_solver &S) {
+    if (S.mul_dirty) {
+        const size_t R = prec_bytes(S.p.precision);
+        if (S.has_ubar) {
+            HIP_TRY(hipMemcpyAsync(S.ubar, S.ubar0, 8 * S.m, hipMemcpyDeviceToDevice, S.stream));
+            HIP_TRY(hipMemcpyAsync(S.ctil, S.ctil0, R * (S.n + S.m), hipMemcpyDeviceToDevice, S.stream));
+        }
+        if (S.has_ybar) HIP_TRY(hipMemcpyAsync(S.ybar, S.ybar0, R * (S.n + S.m), hipMemcpyDeviceToDevice, S.stream));
+        if (S.p.beta != S.beta0) {
+            thetis_status st = apply_beta(S, S.beta0);
+            if (st) return st;
+        }
+        S.mul_dirty = false;
+    }
     Dev<P> a = make_dev<P>(S);
     const int64_t N = std::max<int64_t>(std::max(S.n, S.m), 1);
     hipLaunchKernelGGL((k_set_start<P>), dim3(cdiv(N, kWG)), dim3(kWG), 0, S.stream, a);
@@ -1761,6 +1782,7 @@ thetis_status multiplier_impl(thetis_solver &S, bool move_centre, double *out) {
     HIP_TRY(err);
     out[4] = ms;
     S.metrics_fresh = false;
+    S.mul_dirty = true;
     return THETIS_OK;
 }
 
@@ -1999,6 +2021,11 @@ thetis_status upload_conv(thetis_solver &S, void *dst, const std::vector<double>
     return THETIS_OK;
 }
 
+thetis_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return THETIS_OK;
+    return fail(THETIS_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+}
+
 thetis_status upload_real(thetis_solver &S, void *dst, const std::vector<double> &src) {
     return S.p.precision == THETIS_PREC_FP64 ? upload_conv<double>(S, dst, src) : upload_conv<float>(S, dst, src);
 }
@@ -2121,6 +2148,7 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     S.p = *p;
     S.p.ybar = nullptr;
     S.p.ubar = nullptr;
+    S.beta0 = p->beta;
     S.rho = p->prox ? 1.0 / p->beta : 0.0;
     S.has_ybar = p->prox && p->ybar;
     S.has_ubar = p->ubar != nullptr;
@@ -2200,6 +2228,8 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
         for (int64_t j = 0; j < in.n; ++j) yb[j] = p->ybar[j];
         for (int64_t r = 0; r < in.m; ++r) yb[in.n + r] = p->ybar[in.n + in.row_orig[r]];
         UP(upload_real(S, S.ybar, yb));
+        UP(hip_status(hipMemcpyAsync(S.ybar0, S.ybar, prec_bytes(S.p.precision) * (in.n + in.m),
+                                     hipMemcpyDeviceToDevice, S.stream)));
     }
     if (S.has_ubar) {
         std::vector<double> ub(in.m);
@@ -2218,6 +2248,9 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
             ct[in.n + i] = -sg * ub[i];
         }
         UP(upload_real(S, S.ctil, ct));
+        UP(hip_status(hipMemcpyAsync(S.ctil0, S.ctil, prec_bytes(S.p.precision) * (in.n + in.m),
+                                     hipMemcpyDeviceToDevice, S.stream)));
+        UP(hip_status(hipMemcpyAsync(S.ubar0, S.ubar, 8 * in.m, hipMemcpyDeviceToDevice, S.stream)));
     }
     const_cast<thetis_inst *>(h)->in.has_solver = true;
     st = DISPATCH(S, reset_impl)(S);
@@ -2262,6 +2295,7 @@ extern "C" thetis_status thetis_set_beta(thetis_solver *s, double beta) {
     clear_error();
     if (!s) return fail(THETIS_EINVAL, "solver is NULL");
     if (!(beta > 0.0) || !std::isfinite(beta)) return fail(THETIS_EINVAL, "beta must be positive");
+    s->beta0 = beta;          // the beta a reset returns to
     return apply_beta(*s, beta);
 }
 
@@ -2324,8 +2358,9 @@ extern "C" thetis_status thetis_get_multipliers(thetis_solver *s, double *ubar_h
 
 extern "C" thetis_status thetis_run_multipliers(thetis_solver *s, int32_t max_outer, int32_t inner_epochs,
                                                 double inner_gap_tol, double beta_growth, double beta_max,
-                                                double tol, int32_t move_centre, int32_t *outer_done,
-                                                int64_t *epochs_done, thetis_mul_stats *last_host) {
+                                                double feas_tol, double lp_gap_tol, int32_t move_centre,
+                                                int32_t *outer_done, int64_t *epochs_done,
+                                                thetis_mul_stats *last_host) {
     clear_error();
     if (!s) return fail(THETIS_EINVAL, "solver is NULL");
     if (max_outer < 0 || inner_epochs < 0) return fail(THETIS_EINVAL, "max_outer and inner_epochs must be >= 0");
@@ -2345,7 +2380,7 @@ extern "C" thetis_status thetis_run_multipliers(thetis_solver *s, int32_t max_ou
         st = thetis_multiplier_step(s, move_centre, nb, &st_last);
         ++outer;
         if (st) break;
-        if (st_last.linf <= tol && st_last.lp_gap <= tol) break;
+        if (st_last.linf <= feas_tol && st_last.lp_gap <= lp_gap_tol) break;
     }
     if (outer_done) *outer_done = outer;
     if (epochs_done) *epochs_done = epochs;

@@ -93,7 +93,7 @@ def lib():
             "thetis_run_epochs": [vp, i32, dbl, P(i32)],
             "thetis_solver_autotune": [vp, i32, vp],
             "thetis_multiplier_step": [vp, i32, dbl, P(thetis_mul_stats)],
-            "thetis_run_multipliers": [vp, i32, i32, dbl, dbl, dbl, dbl, i32, P(i32), P(i64),
+            "thetis_run_multipliers": [vp, i32, i32, dbl, dbl, dbl, dbl, dbl, i32, P(i32), P(i64),
                                        P(thetis_mul_stats)],
             "thetis_get_multipliers": [vp, vp, vp],
             "thetis_residual": [vp, P(dbl), P(dbl), P(dbl)],
@@ -215,12 +215,12 @@ def thetis_multiplier_step(s, move_centre: bool = False, new_beta: float = 0.0) 
 
 
 def thetis_run_multipliers(s, max_outer: int, inner_epochs: int, inner_gap_tol: float = 0.0,
-                           beta_growth: float = 1.0, beta_max: float = 0.0, tol: float = 0.0,
-                           move_centre: bool = False):
+                           beta_growth: float = 1.0, beta_max: float = 0.0, feas_tol: float = 0.0,
+                           lp_gap_tol: float = 0.0, move_centre: bool = False):
     outer, epochs, st = C.c_int32(), C.c_int64(), thetis_mul_stats()
     _check(lib().thetis_run_multipliers(s, max_outer, inner_epochs, inner_gap_tol, beta_growth,
-                                        beta_max, tol, int(move_centre), C.byref(outer),
-                                        C.byref(epochs), C.byref(st)))
+                                        beta_max, feas_tol, lp_gap_tol, int(move_centre),
+                                        C.byref(outer), C.byref(epochs), C.byref(st)))
     return outer.value, epochs.value, st.as_dict()
 
 
@@ -436,11 +436,11 @@ class Solver:
         return thetis_multiplier_step(self.h, move_centre, beta)
 
     def run_multipliers(self, max_outer: int, inner_epochs: int, inner_gap_tol: float = 0.0,
-                        beta_growth: float = 1.0, beta_max: float = 0.0, tol: float = 0.0,
-                        move_centre: bool = False):
+                        beta_growth: float = 1.0, beta_max: float = 0.0, feas_tol: float = 0.0,
+                        lp_gap_tol: float = 0.0, move_centre: bool = False):
         """Outer loop: (outer steps done, epochs done, last step's figures)."""
         return thetis_run_multipliers(self.h, max_outer, inner_epochs, inner_gap_tol, beta_growth,
-                                      beta_max, tol, move_centre)
+                                      beta_max, feas_tol, lp_gap_tol, move_centre)
 
     @property
     def ubar(self) -> np.ndarray:

@@ -197,6 +197,35 @@ def test_fp32_outer_loop_reaches_the_lp_optimum():
     assert outer == 12
     assert st["lp_value"] == last["lp_value"] and st["lp_dual"] == last["lp_dual"]
     assert np.array_equal(h.y, g.y)
+    # a reset restores the multiplier, the shifted costs and beta of creation
+    y1 = h.y
+    h.reset()
+    assert np.all(h.ubar == 0.0)
+    outer2, epochs2, st2 = h.run_multipliers(12, 100, inner_gap_tol=1e-7)
+    assert (outer2, epochs2) == (outer, epochs)
+    assert st2["lp_value"] == st["lp_value"] and np.array_equal(h.y, y1)
+    # the stopping rule: the first step inside both tolerances ends the loop
+    h.reset()
+    outer3, _, st3 = h.run_multipliers(50, 100, inner_gap_tol=1e-7, feas_tol=1e-3, lp_gap_tol=1e-4)
+    assert outer3 <= 12 and st3["linf"] <= 1e-3 and st3["lp_gap"] <= 1e-4
+    hist = [s_["linf"] <= 1e-3 and s_["lp_gap"] <= 1e-4 for s_ in seen[: outer3]]
+    assert hist[-1] and not any(hist[:-1])
+
+
+def test_reset_restores_beta_and_prox_centre_after_continuation():
+    inst = I.vc_er(500, 2000, seed=4)
+    yb = np.random.default_rng(4).uniform(0, 1, inst.n + inst.m)
+    g = T.Solver(T.Instance(inst), beta=5.0, prox=True, ybar=yb, ubar=np.zeros(inst.m),
+                 precision=T.PREC_FP64, seed=4)
+    g.run(10)
+    first = g.multiplier_step(move_centre=True, beta=20.0)
+    g.run(10)
+    g.multiplier_step(move_centre=True, beta=80.0)
+    g.reset()
+    assert np.abs(g.ybar - yb).max() == 0.0
+    g.run(10)
+    again = g.multiplier_step(move_centre=True, beta=20.0)
+    assert again["lp_value"] == first["lp_value"] and again["lp_dual"] == first["lp_dual"]
 
 
 # ------------------------------------------------------------------ full size
