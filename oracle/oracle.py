@@ -19,6 +19,7 @@ LIB = os.path.join(HERE, "liborc.so")
 SCHED_DET, SCHED_PERM, SCHED_UNIFORM = 0, 1, 2
 STEP_PER_COORD, STEP_GLOBAL_LMAX = 0, 1
 RULE_VC_THRESH, RULE_MIS_THRESH, RULE_MIS_RAND, RULE_MC_CKR = 1, 2, 3, 4
+RULE_COVER_THRESH, RULE_COVER_RAND, RULE_PACK_RAND = 5, 6, 7
 
 
 def build(force: bool = False) -> str:
@@ -84,6 +85,8 @@ def lib():
         L.orc_beta.argtypes = [P]
         L.orc_round.restype = C.c_int32
         L.orc_round.argtypes = [P, dp, C.c_int32, C.c_uint64, C.c_int32, i32p, C.POINTER(C.c_double), dp]
+        L.orc_cover_q.restype = C.c_double
+        L.orc_cover_q.argtypes = [P]
         L.orc_check.restype = C.c_int32
         L.orc_check.argtypes = [P, C.c_int32, i32p, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         _lib = L
@@ -154,6 +157,10 @@ class OracleLP:
         out = np.zeros(self.nclasses, np.int32)
         lib().orc_class_order(self.h, seed, epoch, out)
         return out
+
+    def cover_q(self) -> float:
+        """q(P) of the covering lemma (-1: not an integer covering program)."""
+        return lib().orc_cover_q(self.h)
 
     def round(self, x, rule: int, seed: int = 0, reps: int = 1):
         x = np.ascontiguousarray(x, dtype=np.float64)

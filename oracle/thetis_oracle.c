@@ -21,8 +21,12 @@
  *   - the block variant with projection onto the k-simplex used for
  *     multiway cut (Appendix E);
  *   - the pre-rounding scalings of Lemma (infeasible:rounded:vc) and the
- *     packing lemma of Appendix C, the threshold and randomized roundings of
- *     Section 2 and Appendix B, and the feasibility check.
+ *     covering (with q(P)) and packing lemmas of Appendix C, the threshold
+ *     and randomized roundings of Section 2 and Appendix B (vertex cover,
+ *     independent set, set cover, integer covering, weighted packing,
+ *     multiway cut), and the feasibility check;
+ *   - the multiplier step of the augmented-Lagrangian framework (Section
+ *     3.2) with the LP's Lagrangian dual bound.
  *
  * Everything is FP64 with no fused multiply-add (built -ffp-contract=off),
  * plain loops in the order the algorithm states them.
@@ -93,7 +97,8 @@ typedef struct {
 
 enum { STEP_PER_COORD = 0, STEP_GLOBAL_LMAX = 1 };
 enum { SCHED_DET = 0, SCHED_PERM = 1, SCHED_UNIFORM = 2 };
-enum { RULE_VC_THRESH = 1, RULE_MIS_THRESH = 2, RULE_MIS_RAND = 3, RULE_MC_CKR = 4 };
+enum { RULE_VC_THRESH = 1, RULE_MIS_THRESH = 2, RULE_MIS_RAND = 3, RULE_MC_CKR = 4,
+       RULE_COVER_THRESH = 5, RULE_COVER_RAND = 6, RULE_PACK_RAND = 7 };
 
 void orc_lp_free(orc_lp *p) {
     if (!p) return;
@@ -694,9 +699,201 @@ static int edge_rows_ok(const orc_lp *p, int want_sense) {
     return 1;
 }
 
+/* binary columns and rows of one sense with non-negative entries (and,
+ * for covering, integer entries and right-hand sides) */
+static int general_rows_ok(const orc_lp *p, int want_sense, int integral) {
+    if (p->nblocks > 0) return 0;
+    for (int64_t j = 0; j < p->n; ++j) if (p->ub[j] != 1.0) return 0;
+    for (int64_t i = 0; i < p->m; ++i) {
+        if (p->sense[i] != want_sense) return 0;
+        if (integral && p->b[i] != floor(p->b[i])) return 0;
+        if (!integral && !(p->b[i] > 0.0)) return 0;
+        for (int64_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) {
+            if (p->val[e] < 0.0) return 0;
+            if (integral && p->val[e] != floor(p->val[e])) return 0;
+        }
+    }
+    return 1;
+}
+
+static int set_cover_rows_ok(const orc_lp *p) {
+    if (!general_rows_ok(p, 1, 1)) return 0;
+    for (int64_t i = 0; i < p->m; ++i) {
+        if (p->b[i] != 1.0) return 0;
+        for (int64_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) if (p->val[e] != 1.0) return 0;
+    }
+    return 1;
+}
+
+/* q(P) of the covering lemma (Appendix C): over the rows, the smallest
+ * b_j - A_j x among binary x with A_j x < b_j.  The sums A_j x reachable
+ * below b_j come from the textbook subset-sum table over 0..b_j-1.  Rows
+ * with b_j <= 0 have no such x.  Rows with b_j above 2^24 take the lower
+ * bound 1 (valid for integer data).  Returns INFINITY without rows that
+ * count, -1 when the instance is not an integer covering program. */
+double orc_cover_q(const orc_lp *p) {
+    if (!general_rows_ok(p, 1, 1)) return -1.0;
+    double q = INFINITY;
+    for (int64_t i = 0; i < p->m; ++i) {
+        double bj = p->b[i];
+        if (bj <= 0.0) continue;
+        if (bj > 16777216.0) { if (1.0 < q) q = 1.0; continue; }
+        int64_t B = (int64_t)bj;
+        char *reach = (char *)calloc(B, 1);
+        reach[0] = 1;
+        for (int64_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) {
+            int64_t a = (int64_t)p->val[e];
+            if (a <= 0) continue;
+            for (int64_t t = B - 1; t >= a; --t) if (reach[t - a]) reach[t] = 1;
+        }
+        int64_t top = B - 1;
+        while (!reach[top]) --top;
+        free(reach);
+        if (bj - (double)top < q) q = bj - (double)top;
+    }
+    return q;
+}
+
 int32_t orc_round(const orc_lp *p, const double *x, int32_t rule, uint64_t seed, int32_t reps,
                   int32_t *sol, double *cost, double *aux) {
     int64_t n = p->n, m = p->m;
+    if (rule == RULE_COVER_THRESH) {
+        if (!set_cover_rows_ok(p)) return -1;
+        /* Hochbaum's f-threshold (Appendix B, set cover) after the covering
+           scaling with q = 1: keep s iff x_s/(1-eps) >= 1/f, i.e.
+           x_s >= min(1, min_j S_j)/f with S_j the row sums, f the largest row
+           length; each row's largest entry caps the threshold so that every
+           row keeps a set in floating point as it does in exact arithmetic */
+        int64_t f = 1;
+        for (int64_t i = 0; i < m; ++i) if (p->row_ptr[i + 1] - p->row_ptr[i] > f) f = p->row_ptr[i + 1] - p->row_ptr[i];
+        double T = 1.0 / (double)f;
+        for (int64_t i = 0; i < m; ++i) {
+            double sm = 0.0, mx = -INFINITY;
+            for (int64_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) {
+                double xv = x[p->col_idx[e]];
+                sm += xv;
+                if (xv > mx) mx = xv;
+            }
+            if (sm / (double)f < T) T = sm / (double)f;
+            if (mx < T) T = mx;
+        }
+        double cst = 0.0;
+        for (int64_t j = 0; j < n; ++j) { sol[j] = x[j] >= T ? 1 : 0; cst += sol[j] ? p->c[j] : 0.0; }
+        *cost = cst;
+        if (aux) { aux[0] = T; aux[1] = 0.0; }
+        return 0;
+    }
+    if (rule == RULE_COVER_RAND) {
+        double q = orc_cover_q(p);
+        if (q < 0.0) return -1;
+        /* covering lemma (Appendix C): eps = max_j (b_j - A_j x)_+,
+           alpha = eps/q(P), xt = min(1, x/(1-alpha)) (all ones when alpha >= 1);
+           randomized rounding (Appendix B, set cover): t = ceil(ln(2m))
+           independent rounds each keep s with probability xt_s, their union
+           is kept; a row still short is completed, from the union alone, by
+           its unkept sets in decreasing xt (ties: entry order) */
+        double eps = 0.0;
+        for (int64_t i = 0; i < m; ++i) {
+            double ax = 0.0;
+            for (int64_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) ax += p->val[e] * x[p->col_idx[e]];
+            if (p->b[i] - ax > eps) eps = p->b[i] - ax;
+        }
+        double alpha = isinf(q) ? 0.0 : eps / q;
+        int32_t t = m > 0 ? (int32_t)ceil(log(2.0 * (double)m)) : 1;
+        if (t < 1) t = 1;
+        double *xt = (double *)malloc((n + 1) * 8);
+        for (int64_t j = 0; j < n; ++j) {
+            double v = alpha < 1.0 ? x[j] / (1.0 - alpha) : 1.0;
+            xt[j] = v > 1.0 ? 1.0 : v;
+        }
+        int32_t *pick = (int32_t *)malloc((n + 1) * 4);
+        int32_t *add = (int32_t *)malloc((n + 1) * 4);
+        char *used = (char *)malloc(n + 1);
+        double best = INFINITY;
+        for (int32_t rep = 0; rep < (reps > 0 ? reps : 1); ++rep) {
+            for (int64_t j = 0; j < n; ++j) {
+                pick[j] = 0; add[j] = 0;
+                for (int32_t r = 0; r < t; ++r)
+                    if (u53(ph_word(seed, ST_ROUND, (uint64_t)rep, (uint64_t)j, 16 + (uint64_t)r)) < xt[j]) pick[j] = 1;
+            }
+            for (int64_t i = 0; i < m; ++i) {
+                double cov = 0.0;
+                for (int64_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) cov += p->val[e] * (double)pick[p->col_idx[e]];
+                for (int64_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) used[p->col_idx[e]] = 0;
+                while (cov < p->b[i]) {
+                    int64_t pickc = -1; double bx = -1.0, ba = 0.0;
+                    for (int64_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) {
+                        int64_t j = p->col_idx[e];
+                        if (pick[j] || used[j] || p->val[e] <= 0.0) continue;
+                        if (xt[j] > bx) { bx = xt[j]; pickc = j; ba = p->val[e]; }
+                    }
+                    if (pickc < 0) break;
+                    used[pickc] = 1;
+                    add[pickc] = 1;
+                    cov += ba;
+                }
+            }
+            double cst = 0.0;
+            for (int64_t j = 0; j < n; ++j) if (pick[j] || add[j]) cst += p->c[j];
+            if (cst < best) {
+                best = cst;
+                for (int64_t j = 0; j < n; ++j) sol[j] = pick[j] || add[j];
+                if (aux) aux[1] = rep;
+            }
+        }
+        free(xt); free(pick); free(add); free(used);
+        *cost = best;
+        if (aux) aux[0] = alpha;
+        return 0;
+    }
+    if (rule == RULE_PACK_RAND) {
+        if (!general_rows_ok(p, -1, 0)) return -1;
+        /* packing lemma (Appendix C): alpha = max_j ((A_j x - b_j)/b_j)_+,
+           xt = x/(1+alpha); Bansal et al.'s alteration with theta = 1/k:
+           choose s with probability xt_s; with weights w = A_js/b_j, drop a
+           chosen s when, in some row where it has weight, the chosen sets of
+           weight >= its own (itself included) weigh more than 1 */
+        double alpha = 0.0;
+        for (int64_t i = 0; i < m; ++i) {
+            double ax = 0.0;
+            for (int64_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) ax += p->val[e] * x[p->col_idx[e]];
+            double v = (ax - p->b[i]) / p->b[i];
+            if (v > alpha) alpha = v;
+        }
+        int32_t *pick = (int32_t *)malloc((n + 1) * 4);
+        int32_t *drop = (int32_t *)malloc((n + 1) * 4);
+        double best = INFINITY;
+        for (int32_t rep = 0; rep < (reps > 0 ? reps : 1); ++rep) {
+            for (int64_t j = 0; j < n; ++j) {
+                double xt = x[j] / (1.0 + alpha);
+                pick[j] = u53(ph_word(seed, ST_ROUND, (uint64_t)rep, (uint64_t)j, 0)) < xt ? 1 : 0;
+                drop[j] = 0;
+            }
+            for (int64_t i = 0; i < m; ++i)
+                for (int64_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) {
+                    int64_t j = p->col_idx[e];
+                    if (!pick[j] || p->val[e] <= 0.0) continue;
+                    double w = p->val[e] / p->b[i], tot = 0.0;
+                    for (int64_t e2 = p->row_ptr[i]; e2 < p->row_ptr[i + 1]; ++e2) {
+                        if (!pick[p->col_idx[e2]]) continue;
+                        double w2 = p->val[e2] / p->b[i];
+                        if (w2 >= w) tot += w2;
+                    }
+                    if (tot > 1.0) drop[j] = 1;
+                }
+            double cst = 0.0;
+            for (int64_t j = 0; j < n; ++j) if (pick[j] && !drop[j]) cst += p->c[j];
+            if (cst < best) {
+                best = cst;
+                for (int64_t j = 0; j < n; ++j) sol[j] = pick[j] && !drop[j];
+                if (aux) aux[1] = rep;
+            }
+        }
+        free(pick); free(drop);
+        *cost = best;
+        if (aux) aux[0] = alpha;
+        return 0;
+    }
     if (rule == RULE_VC_THRESH) {
         if (!edge_rows_ok(p, 1)) return -1;
         /* Lemma (infeasible:rounded:vc): with eps = max_e (1 - x_u - x_v)_+,
@@ -830,7 +1027,8 @@ int32_t orc_check(const orc_lp *p, int32_t rule, const int32_t *sol, int32_t *fe
             if (sol[t] < 0 || sol[t] >= p->k) { ++bad; continue; }
             if (p->fixed[t] >= 0 && sol[t] != p->fixed[t]) ++bad;
         }
-    } else if (rule >= RULE_VC_THRESH && rule <= RULE_MIS_RAND) {
+    } else if ((rule >= RULE_VC_THRESH && rule <= RULE_MIS_RAND) ||
+               (rule >= RULE_COVER_THRESH && rule <= RULE_PACK_RAND)) {
         for (int64_t j = 0; j < p->n; ++j) if (sol[j] != 0 && sol[j] != 1) ++bad;
         for (int64_t i = 0; i < p->m; ++i) {
             double ax = 0.0;

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "LPInstance", "rng_for", "er_edges", "ba_edges", "regular_edges",
     "grid_edges", "vc_lp", "mis_lp", "mc_grid_lp", "vc_er", "vc_ba",
-    "mis_regular", "mc_grid", "serving_trace",
+    "mis_regular", "mc_grid", "serving_trace", "set_cover", "multicover", "kcs_packing",
 ]
 
 
@@ -312,6 +312,85 @@ def mc_grid(side: int = 1024, k: int = 8, seed: int = 0) -> LPInstance:
     w = np.exp(-d * d)
     terminals = rng.choice(side * side, size=k, replace=False)
     return mc_grid_lp(side * side, edges, w, terminals, meta=dict(graph="grid", side=side, seed=seed))
+
+
+def _rows_from_pairs(n_rows: int, row_of: np.ndarray, col_of: np.ndarray, val=None):
+    """CSR from distinct (row, column) pairs, columns ascending inside a row."""
+    order = np.lexsort((col_of, row_of))
+    counts = np.bincount(row_of, minlength=n_rows)
+    row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return row_ptr, col_of[order].astype(np.int32), (None if val is None else val[order])
+
+
+def _set_members(n_elements: int, n_sets: int, rng, mean_size: float):
+    """Set sizes 1 + Poisson(mean_size - 1) (at most n_elements), members
+    uniform (duplicates inside a set merged); every element that no set
+    drew joins one set chosen uniformly.  Returns (set, element) pairs."""
+    sizes = np.minimum(1 + rng.poisson(mean_size - 1.0, n_sets), n_elements)
+    set_id = np.repeat(np.arange(n_sets, dtype=np.int64), sizes)
+    elem = rng.integers(0, n_elements, set_id.size)
+    key = np.unique(set_id * n_elements + elem)
+    set_id, elem = key // n_elements, key % n_elements
+    covered = np.zeros(n_elements, bool)
+    covered[elem] = True
+    miss = np.nonzero(~covered)[0]
+    set_id = np.concatenate([set_id, rng.integers(0, n_sets, miss.size)])
+    elem = np.concatenate([elem, miss])
+    return set_id, elem
+
+
+def set_cover(n_elements: int, n_sets: int, seed: int, mean_size: float = 8.0) -> LPInstance:
+    """Weighted set cover (Appendix B): one row per element, sum over the
+    sets containing it >= 1; costs U[1, 10]; x in [0, 1]."""
+    rng = rng_for(seed, 20)
+    set_id, elem = _set_members(n_elements, n_sets, rng, mean_size)
+    row_ptr, col_idx, _ = _rows_from_pairs(n_elements, elem, set_id)
+    c = rng_for(seed, 21).uniform(1.0, 10.0, n_sets)
+    return LPInstance(m=n_elements, n=n_sets, row_ptr=row_ptr, col_idx=col_idx, val=None,
+                      b=np.ones(n_elements), c=c, u=np.ones(n_sets), sense=np.ones(n_elements, np.int8),
+                      meta=dict(kind="set_cover", seed=seed, mean_size=mean_size))
+
+
+def multicover(n_elements: int, n_sets: int, seed: int, mean_size: float = 8.0,
+               max_weight: int = 3, max_demand: int = 4) -> LPInstance:
+    """Integer covering program (Appendix C) on a set-cover pattern: entries
+    U{1..max_weight}, demands U{1..max_demand} capped at the row's total
+    weight (so taking every set is feasible); costs U[1, 10]."""
+    rng = rng_for(seed, 22)
+    set_id, elem = _set_members(n_elements, n_sets, rng, mean_size)
+    w = rng.integers(1, max_weight + 1, set_id.size).astype(np.float64)
+    row_ptr, col_idx, val = _rows_from_pairs(n_elements, elem, set_id, w)
+    tot = np.add.reduceat(val, row_ptr[:-1]) if val.size else np.zeros(n_elements)
+    b = np.minimum(rng.integers(1, max_demand + 1, n_elements).astype(np.float64), tot)
+    c = rng_for(seed, 23).uniform(1.0, 10.0, n_sets)
+    return LPInstance(m=n_elements, n=n_sets, row_ptr=row_ptr, col_idx=col_idx, val=val, b=b, c=c,
+                      u=np.ones(n_sets), sense=np.ones(n_elements, np.int8),
+                      meta=dict(kind="multicover", seed=seed))
+
+
+def kcs_packing(n_sets: int, n_elements: int, k: int, seed: int, max_weight: int = 4,
+                capacity=(4, 12)) -> LPInstance:
+    """k-column-sparse packing (Appendix B, Bansal et al.'s setting): every
+    set holds k distinct elements with integer weights U{1..max_weight};
+    element capacities U{capacity}; profits U[1, 10], written as
+    min -profit^T x, A x <= b, x in [0, 1]."""
+    rng = rng_for(seed, 24)
+    members = rng.integers(0, n_elements, (n_sets, k))
+    while True:
+        srt = np.sort(members, axis=1)
+        dup = np.any(srt[:, 1:] == srt[:, :-1], axis=1) if k > 1 else np.zeros(n_sets, bool)
+        if not dup.any():
+            break
+        members[dup] = rng.integers(0, n_elements, (int(dup.sum()), k))
+    set_id = np.repeat(np.arange(n_sets, dtype=np.int64), k)
+    elem = members.reshape(-1).astype(np.int64)
+    w = rng.integers(1, max_weight + 1, set_id.size).astype(np.float64)
+    row_ptr, col_idx, val = _rows_from_pairs(n_elements, elem, set_id, w)
+    b = rng.integers(capacity[0], capacity[1] + 1, n_elements).astype(np.float64)
+    profit = rng_for(seed, 25).uniform(1.0, 10.0, n_sets)
+    return LPInstance(m=n_elements, n=n_sets, row_ptr=row_ptr, col_idx=col_idx, val=val, b=b, c=-profit,
+                      u=np.ones(n_sets), sense=-np.ones(n_elements, np.int8),
+                      meta=dict(kind="kcs_packing", k=k, seed=seed))
 
 
 def serving_trace(n_requests: int, rate: float, seed: int,
