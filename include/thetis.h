@@ -72,7 +72,27 @@ enum {
                                      T' = max(1/2, max_e (x_u+x_v)/2)          */
     THETIS_ROUND_MIS_RAND = 3,    /* independent set: scale by 1/(1+alpha), keep
                                      v with probability x~_v, drop conflicts    */
-    THETIS_ROUND_MC_CKR = 4       /* multiway cut: region growing from terminals */
+    THETIS_ROUND_MC_CKR = 4,      /* multiway cut: region growing from terminals */
+    THETIS_ROUND_COVER_THRESH = 5,/* set cover (Appendix B, Hochbaum): keep s iff
+                                     x_s >= T, T = min(1, min_j A_j x)/f with f the
+                                     longest row (the covering scaling of Appendix
+                                     C with q = 1), capped by every row's largest
+                                     x so each row keeps a set                   */
+    THETIS_ROUND_COVER_RAND = 6,  /* integer covering (Appendix B randomized set
+                                     cover, Appendix C scaling): alpha =
+                                     max_j (b_j - A_j x)_+ / q(P), xt = min(1,
+                                     x/(1-alpha)) (1 once alpha >= 1); the union of
+                                     ceil(ln 2m) rounds keeping s with probability
+                                     xt_s; a row still short takes, from that
+                                     union alone, its unkept sets by decreasing xt
+                                     (ties: entry order) until covered           */
+    THETIS_ROUND_PACK_RAND = 7    /* packing (Appendix C scaling, Bansal et al.'s
+                                     alteration with theta = 1/k): alpha =
+                                     max_j ((A_j x - b_j)/b_j)_+, keep s with
+                                     probability x_s/(1+alpha); with w = A_js/b_j,
+                                     drop a kept s when, in a row where it has
+                                     weight, the kept sets of weight >= its own
+                                     (itself included) weigh more than 1         */
 };
 
 /* Solver parameters.  The penalty function is eq. (QP) of Section 3.2 with
@@ -138,6 +158,18 @@ thetis_status thetis_inst_set_simplex_blocks(thetis_inst *inst, int64_t nblocks,
  * entries. */
 thetis_status thetis_inst_classes(const thetis_inst *inst, int32_t *nclasses, int64_t *nunits,
                                   int32_t *class_host);
+
+/* Shapes the general rounding rules accept, as bits of *flags:
+ * THETIS_SHAPE_COVER (every row '>=' with non-negative integer entries and
+ * right-hand side, binary columns, no blocks), THETIS_SHAPE_SET_COVER (also
+ * every entry and right-hand side 1), THETIS_SHAPE_PACK (every row '<=' with
+ * non-negative entries and b > 0, binary columns, no blocks); and q(P) of
+ * the covering lemma (Appendix C): over the rows with b_j > 0, the least
+ * b_j - A_j x among binary x with A_j x < b_j (exact for b_j <= 2^24, else
+ * the lower bound 1; +inf without such rows; 0 when not covering).  Either
+ * pointer may be NULL.  Builds the layout if needed. */
+enum { THETIS_SHAPE_COVER = 1, THETIS_SHAPE_SET_COVER = 2, THETIS_SHAPE_PACK = 4 };
+thetis_status thetis_inst_rounding_shape(const thetis_inst *inst, int32_t *flags, double *cover_q);
 
 thetis_status thetis_inst_destroy(thetis_inst *inst);
 
@@ -264,13 +296,16 @@ thetis_status thetis_epoch(const thetis_solver *s, int64_t *epoch);
 
 /* Pre-rounding pass and rounding of the current x (Section 2, Lemma
  * infeasible:rounded:vc, Appendix B and C) into sol_host: 0/1 per column
- * for the VC and MIS rules (n entries), a label per simplex block for
- * MC_CKR (nblocks entries); sol_host may be NULL.  reps >= 1 draws for the
- * randomised rules, keeping the cheapest (ties: first).  cost = c^T sol
- * (for MC: the cut weight).  aux_host (NULL or 2 doubles) gets the
- * threshold T (or alpha, or the region radius) and the winning repetition.
- * THETIS_EINVAL when the instance does not have the rule's shape (VC/MIS:
- * every row x_u + x_v with b = 1 and the rule's sense; MC: blocks). */
+ * for the VC, MIS, COVER and PACK rules (n entries), a label per simplex
+ * block for MC_CKR (nblocks entries); sol_host may be NULL.  reps >= 1
+ * draws for the randomised rules, keeping the cheapest (ties: first).
+ * cost = c^T sol (for MC: the cut weight).  aux_host (NULL or 2 doubles)
+ * gets the threshold T (or alpha, or the region radius) and the winning
+ * repetition.  THETIS_EINVAL when the instance does not have the rule's
+ * shape (VC/MIS: every row x_u + x_v with b = 1 and the rule's sense; MC:
+ * blocks; COVER/PACK: see thetis_inst_rounding_shape).  Draws: Philox
+ * stream 4, counter (repetition, column, 0) for the keep draws of MIS_RAND
+ * and PACK_RAND, (repetition, column, 16 + round) for COVER_RAND. */
 thetis_status thetis_round(thetis_solver *s, int32_t rule, uint64_t seed, int32_t reps,
                            int32_t *sol_host, double *cost, double *aux_host);
 

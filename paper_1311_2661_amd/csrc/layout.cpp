@@ -287,8 +287,66 @@ static void plan_classes(Inst &in) {
     for (int32_t c = 0; c < in.nclasses; ++c) in.classes[c] = plan_units(in, members[c], in.sched);
 }
 
+// Shapes for the general roundings and q(P) of the covering lemma
+// (Appendix C): over the rows with b_j > 0, the least b_j - A_j x among
+// binary x with A_j x < b_j, i.e. b_j minus the largest subset sum of the
+// row's entries below b_j, found with a bitset of the reachable sums.  Rows
+// with b_j above 2^24 take the lower bound 1 (valid for integer data).
+static void rounding_facts(Inst &in) {
+    in.max_row_len = 0;
+    for (int64_t i = 0; i < in.m; ++i)
+        in.max_row_len = std::max<int64_t>(in.max_row_len, in.row_ptr[i + 1] - in.row_ptr[i]);
+    bool binary = in.nblocks == 0;
+    for (int64_t j = 0; j < in.n && binary; ++j) binary = in.u[j] == 1.0;
+    auto entry = [&](int64_t e) { return in.unit_vals ? 1.0 : in.val[e]; };
+    bool cover = binary, setc = binary, pack = binary;
+    for (int64_t i = 0; i < in.m; ++i) {
+        const double bi = in.b[i];
+        if (in.sense[i] != 1 || bi != std::floor(bi)) cover = false;
+        if (in.sense[i] != 1 || bi != 1.0) setc = false;
+        if (in.sense[i] != -1 || !(bi > 0.0)) pack = false;
+        for (int32_t e = in.row_ptr[i]; e < in.row_ptr[i + 1]; ++e) {
+            const double v = entry(e);
+            if (v < 0.0) { cover = false; setc = false; pack = false; }
+            if (v != std::floor(v)) cover = false;
+            if (v != 1.0) setc = false;
+        }
+    }
+    in.cover_int = cover;
+    in.set_cover = cover && setc;
+    in.packing = pack;
+    in.cover_q = INFINITY;
+    if (!cover) return;
+    std::vector<uint64_t> bits;
+    for (int64_t i = 0; i < in.m; ++i) {
+        const double bi = in.b[i];
+        if (bi <= 0.0) continue;
+        if (bi > 16777216.0) { in.cover_q = std::min(in.cover_q, 1.0); continue; }
+        const int64_t B = (int64_t)bi, W = (B + 63) / 64;
+        bits.assign(W, 0);
+        bits[0] = 1;
+        for (int32_t e = in.row_ptr[i]; e < in.row_ptr[i + 1]; ++e) {
+            const int64_t a = (int64_t)entry(e);
+            if (a <= 0 || a >= B) continue;
+            // bits |= bits << a, high words first so every source word is old
+            const int64_t ws = a / 64, bs = a % 64;
+            for (int64_t w = W - 1; w >= ws; --w) {
+                uint64_t v = bits[w - ws] << bs;
+                if (bs && w - ws - 1 >= 0) v |= bits[w - ws - 1] >> (64 - bs);
+                bits[w] |= v;
+            }
+            if (B % 64) bits[W - 1] &= (uint64_t(1) << (B % 64)) - 1;
+        }
+        int64_t top = 0;
+        for (int64_t w = W - 1; w >= 0; --w)
+            if (bits[w]) { top = 64 * w + 63 - __builtin_clzll(bits[w]); break; }
+        in.cover_q = std::min(in.cover_q, bi - (double)top);
+    }
+}
+
 thetis_status build_layout(Inst &in) {
     try {
+        rounding_facts(in);
         if (in.row_orig.empty()) {
             in.row_orig.resize(in.m);
             for (int64_t i = 0; i < in.m; ++i) in.row_orig[i] = (int32_t)i;
@@ -463,6 +521,19 @@ extern "C" thetis_status thetis_inst_classes(const thetis_inst *h, int32_t *ncla
     if (nclasses) *nclasses = h->in.nclasses;
     if (nunits) *nunits = h->in.nunits;
     if (class_host) std::copy(h->in.ucolour.begin(), h->in.ucolour.end(), class_host);
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_inst_rounding_shape(const thetis_inst *h, int32_t *flags, double *cover_q) {
+    clear_error();
+    if (!h) return fail(THETIS_EINVAL, "instance is NULL");
+    thetis_status st = ensure_layout(h);
+    if (st) return st;
+    const Inst &in = h->in;
+    if (flags)
+        *flags = (in.cover_int ? THETIS_SHAPE_COVER : 0) | (in.set_cover ? THETIS_SHAPE_SET_COVER : 0) |
+                 (in.packing ? THETIS_SHAPE_PACK : 0);
+    if (cover_q) *cover_q = in.cover_int ? in.cover_q : 0.0;
     return THETIS_OK;
 }
 

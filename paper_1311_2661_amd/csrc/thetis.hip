@@ -1068,19 +1068,34 @@ __device__ uint64_t philox_word_dev(uint64_t seed, uint64_t stream, uint64_t c0,
     return x0;
 }
 
-// rule 1: x >= T, rule 2: x > T, rule 3: U_v < x/(1+alpha); writes 0/1 and
-// the cost partial
+// the covering rounding's scaled point: x/(1-alpha) capped at 1, all ones
+// once alpha reaches 1
+__device__ __forceinline__ double cover_scaled(double x, double alpha) {
+    const double v = alpha < 1.0 ? x / (1.0 - alpha) : 1.0;
+    return v > 1.0 ? 1.0 : v;
+}
+
+// rule VC / COVER threshold: x >= T; MIS threshold: x > T; COVER_RAND: any
+// of `rounds` draws below the scaled x; MIS_RAND / PACK_RAND: U_v <
+// x/(1+alpha); writes 0/1 and the cost partial
 template <class P>
 __global__ __launch_bounds__(kWG) void k_pick(Dev<P> a, int32_t rule, const double *thr,
-                                              uint64_t seed, int32_t rep, int32_t *sol, double *part) {
+                                              uint64_t seed, int32_t rep, int32_t rounds, int32_t *sol,
+                                              double *part) {
     const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
     double v = 0.0;
     if (j < a.n) {
         const double xj = (double)xval(a.x[j]);
         int32_t keep;
-        if (rule == THETIS_ROUND_VC_THRESH) keep = xj >= *thr;
+        if (rule == THETIS_ROUND_VC_THRESH || rule == THETIS_ROUND_COVER_THRESH) keep = xj >= *thr;
         else if (rule == THETIS_ROUND_MIS_THRESH) keep = xj > *thr;
-        else {
+        else if (rule == THETIS_ROUND_COVER_RAND) {
+            const double xt = cover_scaled(xj, *thr);
+            keep = 0;
+            for (int32_t r = 0; r < rounds; ++r)
+                if (unit53_dev(philox_word_dev(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)j, 16 + (uint64_t)r)) < xt)
+                    keep = 1;
+        } else {
             const double xt = xj / (1.0 + *thr);
             keep = unit53_dev(philox_word_dev(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)j, 0)) < xt;
         }
@@ -1126,6 +1141,136 @@ __global__ __launch_bounds__(kWG) void k_apply_drop(Dev<P> a, int32_t *sol, cons
         double t = sh[0];
         for (int w = 1; w < kWG / 64; ++w) t += sh[w];
         part[blockIdx.x] = t;
+    }
+}
+
+// Row pass of the general roundings (one thread per row, sums in entry
+// order without contraction, as the scalings define them): COVER_THRESH
+// min(S/f, max x) (f passed in `fx`), COVER_RAND b - S, PACK_RAND (S - b)/b,
+// with S = A_j x; one partial per workgroup (min for the threshold, max
+// otherwise)
+template <class P>
+__global__ __launch_bounds__(kWG) void k_row_scale(Dev<P> a, int32_t rule, double fx, double *part) {
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const bool is_min = rule == THETIS_ROUND_COVER_THRESH;
+    double v = is_min ? INFINITY : -INFINITY;
+    if (i < a.m) {
+        double sm = 0.0, mx = -INFINITY;
+        for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e) {
+            const double xv = (double)xval(a.x[a.csr_col[e]]);
+            sm = __dadd_rn(sm, __dmul_rn(a.csr_val ? (double)a.csr_val[e] : 1.0, xv));
+            mx = fmax(mx, xv);
+        }
+        if (rule == THETIS_ROUND_COVER_THRESH) v = fmin(sm / fx, mx);
+        else if (rule == THETIS_ROUND_COVER_RAND) v = a.b[i] - sm;
+        else v = (sm - a.b[i]) / a.b[i];
+    }
+    if (is_min) v = -v;
+    v = wmax(v);
+    __shared__ double sh[kWG / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int w = 1; w < kWG / 64; ++w) t = fmax(t, sh[w]);
+        part[blockIdx.x] = is_min ? -t : t;
+    }
+}
+
+// fold into the rule's scalar: COVER_THRESH T = min(1/f, min); COVER_RAND
+// alpha = max(0, max)/q (0 without rows); PACK_RAND alpha = max(0, max)
+__global__ __launch_bounds__(kWG) void k_row_scale_fold(const double *part, int64_t nb, int32_t rule, double fx,
+                                                        double q, double *out) {
+    const bool is_min = rule == THETIS_ROUND_COVER_THRESH;
+    const int o[1] = {is_min ? 2 : 1};
+    double r[1];
+    fold_records<1>(part, nb, o, r);
+    if (threadIdx.x == 0) {
+        if (is_min) *out = fmin(1.0 / fx, r[0]);
+        else if (rule == THETIS_ROUND_COVER_RAND) *out = isinf(q) ? 0.0 : fmax(0.0, r[0]) / q;
+        else *out = fmax(0.0, r[0]);
+    }
+}
+
+// Covering completion: a row whose picked sets fall short of b takes, from
+// the picked set alone, its unpicked sets of positive weight in decreasing
+// scaled x (ties: entry order) until it is covered; marks them in `add`.
+// Every row decides from the same picked set, so the result does not depend
+// on the order rows run in.
+template <class P>
+__global__ __launch_bounds__(kWG) void k_cover_repair(Dev<P> a, const int32_t *pick, const double *alpha,
+                                                      int32_t *add) {
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= a.m) return;
+    const int32_t e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+    double cov = 0.0;
+    for (int32_t e = e0; e < e1; ++e)
+        cov = __dadd_rn(cov, __dmul_rn(a.csr_val ? (double)a.csr_val[e] : 1.0, (double)pick[a.csr_col[e]]));
+    const double al = *alpha;
+    double prev_x = INFINITY;
+    int32_t prev_e = -1;
+    while (cov < a.b[i]) {
+        // next in the order (scaled x descending, entry position ascending)
+        double bx = -1.0;
+        int32_t be = -1;
+        for (int32_t e = e0; e < e1; ++e) {
+            const double av = a.csr_val ? (double)a.csr_val[e] : 1.0;
+            const int32_t j = a.csr_col[e];
+            if (pick[j] || av <= 0.0) continue;
+            const double xt = cover_scaled((double)xval(a.x[j]), al);
+            const bool after = xt < prev_x || (xt == prev_x && e > prev_e);
+            if (after && xt > bx) { bx = xt; be = e; }
+        }
+        if (be < 0) break;
+        add[a.csr_col[be]] = 1;
+        cov = __dadd_rn(cov, a.csr_val ? (double)a.csr_val[be] : 1.0);
+        prev_x = bx;
+        prev_e = be;
+    }
+}
+
+// sol |= add; cost partial
+template <class P>
+__global__ __launch_bounds__(kWG) void k_apply_add(Dev<P> a, int32_t *sol, const int32_t *add, double *part) {
+    const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v = 0.0;
+    if (j < a.n) {
+        const int32_t keep = sol[j] || add[j];
+        sol[j] = keep;
+        v = keep ? a.c[j] : 0.0;
+    }
+    v = wsum(v);
+    __shared__ double sh[kWG / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int w = 1; w < kWG / 64; ++w) t += sh[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+// Packing alteration (Bansal et al., Appendix B) with weights w = A_js/b_j:
+// a picked set is marked for deletion when, in a row where it has weight,
+// the picked sets of weight >= its own (itself included) weigh more than 1
+template <class P>
+__global__ __launch_bounds__(kWG) void k_pack_conflicts(Dev<P> a, const int32_t *pick, int32_t *drop) {
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= a.m) return;
+    const int32_t e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+    const double bi = a.b[i];
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t j = a.csr_col[e];
+        const double av = a.csr_val ? (double)a.csr_val[e] : 1.0;
+        if (!pick[j] || av <= 0.0) continue;
+        const double w = av / bi;
+        double tot = 0.0;
+        for (int32_t e2 = e0; e2 < e1; ++e2) {
+            if (!pick[a.csr_col[e2]]) continue;
+            const double w2 = (a.csr_val ? (double)a.csr_val[e2] : 1.0) / bi;
+            if (w2 >= w) tot = __dadd_rn(tot, w2);
+        }
+        if (tot > 1.0) drop[j] = 1;
     }
 }
 
@@ -1322,6 +1467,9 @@ struct thetis_solver {
     LaunchPlan colterms{};                     // column pass without it (c^T x, prox part of F)
     bool metrics_dual = false;                 // the fresh metrics include the dual bound
     bool edge_shape_cover = false, edge_shape_pack = false;
+    bool cover_int = false, set_cover = false, packing = false;   // shapes of the general roundings
+    double cover_q = 0.0;
+    int64_t max_row_len = 0;
     int64_t nunits = 0, updates_per_epoch = 0, max_degree = 0;
     int32_t lpc = 1;                           // lanes per column of a simplex block
     // parameters
@@ -1849,7 +1997,7 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
         const int32_t op = rule == THETIS_ROUND_VC_THRESH ? 0 : 1;
         hipLaunchKernelGGL((k_edge_extreme<P>), dim3(gm), dim3(kWG), 0, S.stream, a, op, part);
         hipLaunchKernelGGL(k_edge_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gm, op, thr);
-        hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, 0, best, part);
+        hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, 0, 0, best, part);
         hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gn, 1.0, 0, cb);
         HIP_TRY(hipMemcpyAsync(auxv, thr, 8, hipMemcpyDeviceToHost, S.stream));
     } else if (rule == THETIS_ROUND_MIS_RAND) {
@@ -1859,9 +2007,47 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
         hipLaunchKernelGGL(k_edge_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gm, 2, thr);
         for (int32_t rep = 0; rep < reps; ++rep) {
             HIP_TRY(hipMemsetAsync(drop, 0, 4 * S.n, S.stream));
-            hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, rep, sol, part);
+            hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, rep, 0, sol, part);
             hipLaunchKernelGGL((k_conflicts<P>), dim3(gm), dim3(kWG), 0, S.stream, a, (const int32_t *)sol, drop);
             hipLaunchKernelGGL((k_apply_drop<P>), dim3(gn), dim3(kWG), 0, S.stream, a, sol, (const int32_t *)drop, part);
+            hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gn, 1.0, rep, cb);
+            hipLaunchKernelGGL(k_copy_if, dim3(gn), dim3(kWG), 0, S.stream, (const double *)cb, (const int32_t *)sol, best, S.n);
+        }
+        HIP_TRY(hipMemcpyAsync(auxv, thr, 8, hipMemcpyDeviceToHost, S.stream));
+    } else if (rule == THETIS_ROUND_COVER_THRESH) {
+        if (!S.set_cover) return fail(THETIS_EINVAL, "COVER_THRESH needs set-cover rows (0/1 entries, >= 1) and binary columns");
+        const double f = (double)std::max<int64_t>(S.max_row_len, 1);
+        hipLaunchKernelGGL((k_row_scale<P>), dim3(gm), dim3(kWG), 0, S.stream, a, rule, f, part);
+        hipLaunchKernelGGL(k_row_scale_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gm, rule, f, 1.0, thr);
+        hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, 0, 0, best, part);
+        hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gn, 1.0, 0, cb);
+        HIP_TRY(hipMemcpyAsync(auxv, thr, 8, hipMemcpyDeviceToHost, S.stream));
+    } else if (rule == THETIS_ROUND_COVER_RAND || rule == THETIS_ROUND_PACK_RAND) {
+        const bool cover = rule == THETIS_ROUND_COVER_RAND;
+        if (cover && !S.cover_int)
+            return fail(THETIS_EINVAL, "COVER_RAND needs rows >= with non-negative integer entries and b, and binary columns");
+        if (!cover && !S.packing)
+            return fail(THETIS_EINVAL, "PACK_RAND needs rows <= with non-negative entries and b > 0, and binary columns");
+        if (reps < 1) return fail(THETIS_EINVAL, "reps must be >= 1");
+        // independent rounds whose union is kept: ceil(ln(2m)), so that a
+        // row stays uncovered with probability at most 1/(2m)
+        int32_t rounds = 0;
+        if (cover) rounds = std::max<int32_t>(1, S.m > 0 ? (int32_t)std::ceil(std::log(2.0 * (double)S.m)) : 1);
+        hipLaunchKernelGGL((k_row_scale<P>), dim3(gm), dim3(kWG), 0, S.stream, a, rule, 1.0, part);
+        hipLaunchKernelGGL(k_row_scale_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gm, rule, 1.0,
+                           S.cover_q, thr);
+        for (int32_t rep = 0; rep < reps; ++rep) {
+            HIP_TRY(hipMemsetAsync(drop, 0, 4 * S.n, S.stream));
+            hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, rep,
+                               rounds, sol, part);
+            if (cover) {
+                hipLaunchKernelGGL((k_cover_repair<P>), dim3(gm), dim3(kWG), 0, S.stream, a, (const int32_t *)sol,
+                                   (const double *)thr, drop);
+                hipLaunchKernelGGL((k_apply_add<P>), dim3(gn), dim3(kWG), 0, S.stream, a, sol, (const int32_t *)drop, part);
+            } else {
+                hipLaunchKernelGGL((k_pack_conflicts<P>), dim3(gm), dim3(kWG), 0, S.stream, a, (const int32_t *)sol, drop);
+                hipLaunchKernelGGL((k_apply_drop<P>), dim3(gn), dim3(kWG), 0, S.stream, a, sol, (const int32_t *)drop, part);
+            }
             hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gn, 1.0, rep, cb);
             hipLaunchKernelGGL(k_copy_if, dim3(gn), dim3(kWG), 0, S.stream, (const double *)cb, (const int32_t *)sol, best, S.n);
         }
@@ -1914,7 +2100,7 @@ thetis_status check_impl(thetis_solver &S, int32_t rule, const int32_t *sol_host
     const int32_t *sol = (const int32_t *)S.best;
     const bool labels = rule == THETIS_ROUND_MC_CKR;
     if (labels && S.nblocks <= 0) return fail(THETIS_EINVAL, "MC check needs simplex blocks");
-    if (!labels && (rule < THETIS_ROUND_VC_THRESH || rule > THETIS_ROUND_MIS_RAND))
+    if (!labels && (rule < THETIS_ROUND_VC_THRESH || rule > THETIS_ROUND_PACK_RAND))
         return fail(THETIS_EINVAL, "unknown rule");
     const int64_t nsol = labels ? S.nblocks : S.n;
     if (sol_host) {
@@ -2160,6 +2346,11 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     S.max_degree = in.max_col_degree;
     S.edge_shape_cover = edge_shape(in, 1);
     S.edge_shape_pack = edge_shape(in, -1);
+    S.cover_int = in.cover_int;
+    S.set_cover = in.set_cover;
+    S.packing = in.packing;
+    S.cover_q = in.cover_q;
+    S.max_row_len = in.max_row_len;
     for (const ClassPlan &cp : in.classes) S.det.push_back(make_class_launch(S, in, in.sched, cp.segs));
     {
         std::vector<Segment> all = in.async_struct.segs;

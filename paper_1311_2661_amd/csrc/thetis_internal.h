@@ -97,6 +97,14 @@ struct Inst {
     bool planned = false;
     bool has_solver = false;
     int64_t max_col_degree = 0;
+    // shapes the general roundings need (binary columns, no blocks): every
+    // row '>=' with non-negative integer entries and right-hand side
+    // (covering), additionally all entries and right-hand sides 1 (set
+    // cover), or every row '<=' with non-negative entries and b > 0
+    // (packing); q(P) of the covering lemma; the longest row
+    bool cover_int = false, set_cover = false, packing = false;
+    double cover_q = 0.0;
+    int64_t max_row_len = 0;
     // Internal row order: rows are renumbered so that every row's owner (its
     // first column in DET schedule order) sees its rows contiguously, class
     // by class.  row_orig[r] = caller's index of internal row r.

@@ -30,10 +30,12 @@ STEP_PER_COORD, STEP_GLOBAL_LMAX = 0, 1
 SCHED_DET, SCHED_ASYNC = 0, 1
 PREC_FP32, PREC_FP64, PREC_BF16X = 0, 1, 2
 ROUND_VC_THRESH, ROUND_MIS_THRESH, ROUND_MIS_RAND, ROUND_MC_CKR = 1, 2, 3, 4
+ROUND_COVER_THRESH, ROUND_COVER_RAND, ROUND_PACK_RAND = 5, 6, 7
+SHAPE_COVER, SHAPE_SET_COVER, SHAPE_PACK = 1, 2, 4
 
 EXPORTED = [
     "thetis_params_default", "thetis_inst_create_csr", "thetis_inst_set_simplex_blocks",
-    "thetis_inst_classes", "thetis_inst_destroy", "thetis_solver_workspace_bytes",
+    "thetis_inst_classes", "thetis_inst_rounding_shape", "thetis_inst_destroy", "thetis_solver_workspace_bytes",
     "thetis_solver_create", "thetis_solver_reset", "thetis_set_beta", "thetis_set_step_rule",
     "thetis_run_epochs", "thetis_solver_autotune", "thetis_multiplier_step", "thetis_run_multipliers",
     "thetis_get_multipliers", "thetis_residual", "thetis_objective", "thetis_get_x",
@@ -84,6 +86,7 @@ def lib():
             "thetis_inst_create_csr": [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, P(vp)],
             "thetis_inst_set_simplex_blocks": [vp, i64, i32, vp, vp],
             "thetis_inst_classes": [vp, P(i32), P(i64), vp],
+            "thetis_inst_rounding_shape": [vp, P(i32), P(dbl)],
             "thetis_inst_destroy": [vp],
             "thetis_solver_workspace_bytes": [vp, P(thetis_params), P(C.c_size_t)],
             "thetis_solver_create": [vp, P(thetis_params), vp, C.c_size_t, vp, P(vp)],
@@ -163,6 +166,12 @@ def thetis_inst_set_simplex_blocks(h, nblocks, k, first_col, fixed_label=None):
     f = _c(first_col, np.int64)
     fx = _c(fixed_label, np.int32)
     _check(lib().thetis_inst_set_simplex_blocks(h, nblocks, k, _ptr(f), _ptr(fx)))
+
+
+def thetis_inst_rounding_shape(h):
+    fl, q = C.c_int32(), C.c_double()
+    _check(lib().thetis_inst_rounding_shape(h, C.byref(fl), C.byref(q)))
+    return fl.value, q.value
 
 
 def thetis_inst_classes(h):
@@ -369,6 +378,11 @@ class Instance:
 
     def classes(self):
         return thetis_inst_classes(self.h)
+
+    def rounding_shape(self):
+        """(flags, q(P)): SHAPE_* bits the general roundings accept, and the
+        covering lemma's q."""
+        return thetis_inst_rounding_shape(self.h)
 
     def close(self):
         if getattr(self, "h", None):

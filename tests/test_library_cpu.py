@@ -118,3 +118,51 @@ def test_workspace_bytes_scale_with_precision():
     bad.refresh_every = 0
     with pytest.raises(T.ThetisError):
         T.thetis_solver_workspace_bytes(h.h, bad)
+
+
+# ------------------------------------------------------------ general rounding shapes
+
+def _rows_lp(rows, b, sense, n):
+    row_ptr = [0]
+    col, val = [], []
+    for r in rows:
+        for j in sorted(r):
+            col.append(j)
+            val.append(float(r[j]))
+        row_ptr.append(len(col))
+    m = len(rows)
+    return I.LPInstance(m=m, n=n, row_ptr=np.array(row_ptr, np.int64), col_idx=np.array(col, np.int32),
+                        val=np.array(val), b=np.array(b, float), c=np.ones(n), u=np.ones(n),
+                        sense=np.full(m, sense, np.int8))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_cover_q_and_shapes_match_the_oracle(seed):
+    """q(P) from the library's bitset subset sums equals the oracle's
+    subset-sum table, on random integer rows (right-hand sides up to 200)."""
+    rng = np.random.default_rng(seed)
+    n = 30
+    rows = []
+    for _ in range(25):
+        cols = rng.choice(n, size=int(rng.integers(1, 9)), replace=False)
+        rows.append({int(j): int(rng.integers(1, 70)) for j in cols})
+    inst = _rows_lp(rows, [int(rng.integers(1, 200)) for _ in rows], 1, n)
+    flags, q = T.Instance(inst).rounding_shape()
+    assert flags == T.SHAPE_COVER
+    assert q == O.OracleLP(inst).cover_q()
+
+
+def test_rounding_shapes_of_the_workloads():
+    sc = T.Instance(I.set_cover(200, 80, seed=1)).rounding_shape()
+    assert sc == (T.SHAPE_COVER | T.SHAPE_SET_COVER, 1.0)
+    vc = T.Instance(I.vc_er(50, 100, seed=1)).rounding_shape()
+    assert vc == (T.SHAPE_COVER | T.SHAPE_SET_COVER, 1.0)
+    mis = T.Instance(I.mis_regular(50, 3, seed=1)).rounding_shape()
+    assert mis == (T.SHAPE_PACK, 0.0)
+    pk = T.Instance(I.kcs_packing(60, 40, 3, seed=1)).rounding_shape()
+    assert pk == (T.SHAPE_PACK, 0.0)
+    mc = T.Instance(I.mc_grid(side=6, k=3, seed=1))
+    assert mc.rounding_shape()[0] == 0
+    mcov = I.multicover(80, 40, seed=2)
+    fl, q = T.Instance(mcov).rounding_shape()
+    assert fl == T.SHAPE_COVER and q == O.OracleLP(mcov).cover_q()
