@@ -420,33 +420,64 @@ def mc_grid(args):
     print(json.dumps(out), flush=True)
 
 
-def al_ba(args):
-    """Augmented-Lagrangian outer loop on the vertex-cover LP of the BA graph
-    (n = 2,000,000, FP32 storage): starting from ubar = 0, blocks of
-    `inner` epochs alternate with multiplier steps until ||A y - b||_inf <=
-    feas_tol and the LP gap certified by the dual function <= lp_gap_tol
-    (at most `outer` steps); then threshold rounding and the check."""
-    import torch
+# augmented-Lagrangian workloads: rounding rules with their repetitions, and
+# the workload name's prefix
+AL_WORKLOADS = {
+    "al_ba": ([(1, 1)], "vc_ba_n{n}_m3", 1e-4),
+    "setcover": ([(5, 1), (6, 10)], "set_cover_4000000x1000000_mean8", 1e-4),
+    # the packing LP's gap closes slowly under the outer loop (5.6e-4 after
+    # 30 steps of 50 epochs): its default stop is a 1e-3 gap
+    "packing": ([(7, 10)], "kcs_packing_2000000x1000000_k4", 1e-3),
+}
+
+
+def _al_instance(args):
     from paper_1311_2661_amd import instances as I
+    if args.workload == "al_ba":
+        return I.vc_ba(args.n, seed=args.seed)
+    if args.workload == "setcover":
+        return I.set_cover(4_000_000, 1_000_000, seed=args.seed)
+    return I.kcs_packing(2_000_000, 1_000_000, 4, seed=args.seed)
+
+
+def al_workload(args):
+    """Augmented-Lagrangian outer loop on one LP, then its roundings.
+    al_ba: vertex cover on the BA graph (n = 2,000,000); setcover: weighted
+    set cover, 4,000,000 elements, 1,000,000 sets of mean size 8; packing:
+    k-column-sparse packing, 2,000,000 sets of 4 elements over 1,000,000
+    elements, integer weights and capacities.  FP32 storage, beta 10, refresh
+    every 5 epochs, DET: from ubar = 0, blocks of `inner` epochs alternate
+    with multiplier steps until ||A y - b||_inf <= feas_tol and the LP gap
+    certified by the dual function <= lp_gap_tol (at most `outer` steps);
+    then the workload's roundings and the check.  Every step re-solves from
+    the start."""
+    import torch
     from paper_1311_2661_amd import thetis as T
     T.lib()
     torch.cuda.set_device(0)
+    rules, wname, gap_default = AL_WORKLOADS[args.workload]
+    if args.lp_gap_tol is None:
+        args.lp_gap_tol = gap_default
     t0 = time.perf_counter()
-    inst = I.vc_ba(args.n, seed=args.seed)
-    log(f"instance: BA n={inst.n} edges={inst.m} ({time.perf_counter() - t0:.1f} s)")
+    inst = _al_instance(args)
+    log(f"instance: {inst.m} rows, {inst.n} columns, {inst.nnz} entries ({time.perf_counter() - t0:.1f} s)")
     h = T.Instance(inst)
     s = T.Solver(h, beta=10.0, ubar=np.zeros(inst.m), precision=T.PREC_FP32, refresh_every=5, seed=args.seed)
     tuned = s.autotune(4)
     log(f"columns per lane group by class: {tuned}")
     upd = s.traffic()["updates_per_epoch"]
+    maximise = args.workload == "packing"
 
     def step():
         s.reset()
         outer, epochs, st = s.run_multipliers(args.outer, args.inner, feas_tol=args.feas_tol,
                                               lp_gap_tol=args.lp_gap_tol)
-        sol, cost, aux = s.round(T.ROUND_VC_THRESH)
-        feas, nviol = s.check(T.ROUND_VC_THRESH)
-        return outer, epochs, st, cost, feas
+        rounded = []
+        for rule, reps in rules:
+            sol, cost, aux = s.round(rule, seed=args.seed, reps=reps)
+            feas, nviol = s.check(rule)
+            rounded.append((rule, reps, cost, aux, feas))
+        return outer, epochs, st, rounded
 
     for w in range(args.warmup):
         r = step()
@@ -468,34 +499,55 @@ def al_ba(args):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     s.set_timing(0)
-    assert all(r[4] for r in results), "rounded cover infeasible"
-    outer, epochs, st, cost, feas = results[-1]
+    assert all(all(x[4] for x in r[3]) for r in results), "a rounded solution is infeasible"
+    outer, epochs, st, rounded = results[-1]
+    # time of the roundings alone (outside the timed steps, same state)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for rule, reps in rules:
+        s.round(rule, seed=args.seed, reps=reps)
+    torch.cuda.synchronize()
+    round_ms = 1e3 * (time.perf_counter() - t1)
     g = acc["k_sweep"]
     avg_ms = g["ms"] / max(g["launches"], 1)
     avg_bytes = g["alg_bytes"] / max(g["launches"], 1)
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     mms = float(np.mean(mul_ms))
     mgbs = float(np.mean(mul_bytes)) / (mms * 1e-3) / 1e9
-    workload = (f"vc_ba_n{args.n}_m3_augmented_lagrangian_beta10_fp32_refresh5_{args.inner}ep_per_step_"
+    names = {1: "vc_threshold", 5: "set_cover_threshold", 6: "cover_randomized", 7: "packing_alteration"}
+    lp_bound = st["lp_dual"]
+    sol_out = {"outer_steps": outer, "epochs": epochs, "lp_value": st["lp_value"], "lp_dual": lp_bound,
+               "lp_gap": st["lp_gap"], "linf": st["linf"]}
+    for rule, reps, cost, aux, feas in rounded:
+        key = names[rule]
+        if maximise:
+            sol_out[key] = {"profit": -cost, "reps": reps, "alpha": aux[0], "feasible": bool(feas),
+                            "ratio_to_lp_upper_bound": (-cost) / (-lp_bound)}
+        else:
+            sol_out[key] = {"cost": cost, "reps": reps, "aux": aux[0], "feasible": bool(feas),
+                            "ratio_to_lp_lower_bound": cost / lp_bound}
+    workload = (f"{wname.format(n=args.n)}_augmented_lagrangian_beta10_fp32_refresh5_{args.inner}ep_per_step_"
                 f"to_linf{args.feas_tol:g}_gap{args.lp_gap_tol:g}_det")
     out = {
         "metric": METRIC, "value": sum(r[1] for r in results) * upd / elapsed, "unit": "coord updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": workload, "graph": "barabasi_albert", "n_vertices": inst.n, "edges": inst.m,
+        "config": {"workload": workload, "rows": inst.m, "columns": inst.n, "entries": inst.nnz,
                    "coordinates_per_epoch": upd, "beta": 10.0, "epochs_per_outer_step": args.inner,
                    "max_outer_steps": args.outer, "feas_tol": args.feas_tol, "lp_gap_tol": args.lp_gap_tol,
-                   "group_cols_by_class": tuned, "seed": args.seed},
+                   "roundings": [[names[r], reps] for r, reps in rules], "group_cols_by_class": tuned,
+                   "seed": args.seed},
         "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_launch": avg_bytes, "avg_launch_us": 1e3 * avg_ms},
         "multiplier_step": {"device_ms": mms, "alg_bytes": float(np.mean(mul_bytes)), "alg_gbs": mgbs,
-                            "frac_of_hbm_peak": mgbs / HBM_PEAK_GBS, "kernels": "k_mul_rows + k_mul_cols + k_mul_final"},
-        "solution": {"outer_steps": outer, "epochs": epochs, "lp_value": st["lp_value"], "lp_dual": st["lp_dual"],
-                     "lp_gap": st["lp_gap"], "linf": st["linf"], "cover_cost": cost, "feasible": bool(feas)},
+                            "frac_of_hbm_peak": mgbs / HBM_PEAK_GBS,
+                            "kernels": "k_mul_rows + k_mul_cols + k_mul_final"},
+        "roundings_ms": round_ms,
+        "solution": sol_out,
     }
-    log(f"solve: {outer} outer steps, {epochs} epochs, c^T x {st['lp_value']:.10g} D {st['lp_dual']:.10g} "
-        f"linf {st['linf']:.3e}; multiplier step {mms:.3f} ms ({mgbs:.0f} GB/s)")
+    log(f"solve: {outer} outer steps, {epochs} epochs, c^T x {st['lp_value']:.10g} D {lp_bound:.10g} "
+        f"linf {st['linf']:.3e}; roundings {json.dumps({k: v for k, v in sol_out.items() if isinstance(v, dict)})}")
     if args.cpu_baseline_seconds > 0:
         from oracle import oracle as O
         lp = O.OracleLP(inst)
@@ -649,11 +701,12 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the k_sweep traffic summary from two rocprofv3 counter runs and exit")
-    ap.add_argument("--workload", choices=["vc_ba", "mc_grid", "mis_batch", "serve", "al_ba"], default="vc_ba")
-    ap.add_argument("--outer", type=int, default=40, help="al_ba: most multiplier steps")
-    ap.add_argument("--inner", type=int, default=50, help="al_ba: epochs between multiplier steps")
-    ap.add_argument("--feas-tol", type=float, default=5e-2, help="al_ba: ||A y - b||_inf to stop at")
-    ap.add_argument("--lp-gap-tol", type=float, default=1e-4, help="al_ba: certified LP gap to stop at")
+    ap.add_argument("--workload", choices=["vc_ba", "mc_grid", "mis_batch", "serve", "al_ba", "setcover", "packing"],
+                    default="vc_ba")
+    ap.add_argument("--outer", type=int, default=40, help="al_ba / setcover / packing: most multiplier steps")
+    ap.add_argument("--inner", type=int, default=50, help="al_ba / setcover / packing: epochs between multiplier steps")
+    ap.add_argument("--feas-tol", type=float, default=5e-2, help="al_ba / setcover / packing: ||A y - b||_inf to stop at")
+    ap.add_argument("--lp-gap-tol", type=float, default=None, help="al_ba / setcover / packing: certified LP gap to stop at")
     ap.add_argument("--side", type=int, default=1024, help="mc_grid: grid side")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
@@ -686,8 +739,8 @@ def main():
         return mis_batch(args)
     if args.workload == "serve":
         return serve(args)
-    if args.workload == "al_ba":
-        return al_ba(args)
+    if args.workload in AL_WORKLOADS:
+        return al_workload(args)
     if args.workload == "mc_grid":
         if args.epochs == 100:
             args.epochs = 200

@@ -1090,11 +1090,12 @@ __global__ __launch_bounds__(kWG) void k_pick(Dev<P> a, int32_t rule, const doub
         if (rule == THETIS_ROUND_VC_THRESH || rule == THETIS_ROUND_COVER_THRESH) keep = xj >= *thr;
         else if (rule == THETIS_ROUND_MIS_THRESH) keep = xj > *thr;
         else if (rule == THETIS_ROUND_COVER_RAND) {
+            // the union needs one draw below xt: stop at the first, and draw
+            // nothing when xt <= 0 (no draw in [0, 1) is below it)
             const double xt = cover_scaled(xj, *thr);
             keep = 0;
-            for (int32_t r = 0; r < rounds; ++r)
-                if (unit53_dev(philox_word_dev(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)j, 16 + (uint64_t)r)) < xt)
-                    keep = 1;
+            for (int32_t r = 0; r < rounds && xt > 0.0 && !keep; ++r)
+                keep = unit53_dev(philox_word_dev(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)j, 16 + (uint64_t)r)) < xt;
         } else {
             const double xt = xj / (1.0 + *thr);
             keep = unit53_dev(philox_word_dev(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)j, 0)) < xt;
@@ -1259,6 +1260,32 @@ __global__ __launch_bounds__(kWG) void k_pack_conflicts(Dev<P> a, const int32_t 
     if (i >= a.m) return;
     const int32_t e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
     const double bi = a.b[i];
+    // rows of up to 16 entries: the picked entries' weights gathered once
+    constexpr int kShort = 16;
+    if (e1 - e0 <= kShort) {
+        double w[kShort];
+        int32_t col[kShort];
+        bool has[kShort];
+        int np = 0;
+        for (int32_t e = e0; e < e1; ++e) {
+            const int32_t j = a.csr_col[e];
+            if (!pick[j]) continue;
+            const double av = a.csr_val ? (double)a.csr_val[e] : 1.0;
+            w[np] = av / bi;
+            has[np] = av > 0.0;
+            col[np] = j;
+            ++np;
+        }
+        // the same sums in the same (entry) order as the general loop below
+        for (int q = 0; q < np; ++q) {
+            if (!has[q]) continue;
+            double tot = 0.0;
+            for (int q2 = 0; q2 < np; ++q2)
+                if (w[q2] >= w[q]) tot = __dadd_rn(tot, w[q2]);
+            if (tot > 1.0) drop[col[q]] = 1;
+        }
+        return;
+    }
     for (int32_t e = e0; e < e1; ++e) {
         const int32_t j = a.csr_col[e];
         const double av = a.csr_val ? (double)a.csr_val[e] : 1.0;
