@@ -20,6 +20,7 @@ SCHED_DET, SCHED_PERM, SCHED_UNIFORM = 0, 1, 2
 STEP_PER_COORD, STEP_GLOBAL_LMAX = 0, 1
 RULE_VC_THRESH, RULE_MIS_THRESH, RULE_MIS_RAND, RULE_MC_CKR = 1, 2, 3, 4
 RULE_COVER_THRESH, RULE_COVER_RAND, RULE_PACK_RAND = 5, 6, 7
+RULE_MAP_ARGMAX, RULE_MAP_SAMPLE = 8, 9
 
 
 def build(force: bool = False) -> str:
@@ -85,6 +86,7 @@ def lib():
         L.orc_beta.argtypes = [P]
         L.orc_round.restype = C.c_int32
         L.orc_round.argtypes = [P, dp, C.c_int32, C.c_uint64, C.c_int32, i32p, C.POINTER(C.c_double), dp]
+        L.orc_lp_set_pairwise.argtypes = [P, C.c_int64, i32p, i64p]
         L.orc_cover_q.restype = C.c_double
         L.orc_cover_q.argtypes = [P]
         L.orc_check.restype = C.c_int32
@@ -133,6 +135,12 @@ class OracleLP:
             if L.orc_lp_set_blocks(self.h, first.size, inst.block_k, first, _ptr(fx)) != 0:
                 raise ValueError("oracle rejected the blocks")
             self._keep += [first, fx]
+        if getattr(inst, "pair_ends", None) is not None:
+            pe = np.ascontiguousarray(inst.pair_ends, dtype=np.int32).reshape(-1)
+            pf = np.ascontiguousarray(inst.pair_first, dtype=np.int64)
+            if L.orc_lp_set_pairwise(self.h, pf.size, pe, pf) != 0:
+                raise ValueError("oracle rejected the pairwise factors")
+            self._keep += [pe, pf]
         self.m, self.n, self.N = inst.m, inst.n, inst.n + inst.m
 
     def __del__(self):
@@ -164,7 +172,8 @@ class OracleLP:
 
     def round(self, x, rule: int, seed: int = 0, reps: int = 1):
         x = np.ascontiguousarray(x, dtype=np.float64)
-        nsol = self.inst.fixed_label.size if rule == RULE_MC_CKR else self.n
+        labels = rule in (RULE_MC_CKR, RULE_MAP_ARGMAX, RULE_MAP_SAMPLE)
+        nsol = self.inst.fixed_label.size if labels else self.n
         sol = np.zeros(nsol, np.int32)
         cost = C.c_double()
         aux = np.zeros(4)

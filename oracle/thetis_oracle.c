@@ -81,6 +81,10 @@ typedef struct {
     /* update units: unit u is a free block (kind 1, id = block) or a single
        free column (kind 0, id = column) */
     int64_t nunits; int8_t *ukind; int64_t *uid; int32_t *ucolour; int32_t nclasses;
+    /* pairwise factors of a MAP-inference LP: factor e joins blocks
+       pw_ends[2e], pw_ends[2e+1]; its k*k columns start at pw_first[e],
+       row-major in (label of the first block, label of the second) */
+    int64_t npw; int64_t *pw_ends; int64_t *pw_first;
 } orc_lp;
 
 typedef struct {
@@ -98,13 +102,15 @@ typedef struct {
 enum { STEP_PER_COORD = 0, STEP_GLOBAL_LMAX = 1 };
 enum { SCHED_DET = 0, SCHED_PERM = 1, SCHED_UNIFORM = 2 };
 enum { RULE_VC_THRESH = 1, RULE_MIS_THRESH = 2, RULE_MIS_RAND = 3, RULE_MC_CKR = 4,
-       RULE_COVER_THRESH = 5, RULE_COVER_RAND = 6, RULE_PACK_RAND = 7 };
+       RULE_COVER_THRESH = 5, RULE_COVER_RAND = 6, RULE_PACK_RAND = 7,
+       RULE_MAP_ARGMAX = 8, RULE_MAP_SAMPLE = 9 };
 
 void orc_lp_free(orc_lp *p) {
     if (!p) return;
     free(p->row_ptr); free(p->col_idx); free(p->val); free(p->b); free(p->c); free(p->ub);
     free(p->sense); free(p->cptr); free(p->ridx); free(p->cval); free(p->bfirst);
     free(p->fixed); free(p->col_block); free(p->ukind); free(p->uid); free(p->ucolour);
+    free(p->pw_ends); free(p->pw_first);
     free(p);
 }
 
@@ -243,6 +249,37 @@ int orc_lp_set_blocks(orc_lp *p, int64_t nblocks, int32_t k, const int64_t *firs
         }
     }
     return build_units(p);
+}
+
+/* pairwise factors for the MAP roundings' energy; -1 on bad input */
+int orc_lp_set_pairwise(orc_lp *p, int64_t nf, const int32_t *ends, const int64_t *first) {
+    if (p->nblocks <= 0 || nf < 0) return -1;
+    int64_t kk = (int64_t)p->k * p->k;
+    free(p->pw_ends); free(p->pw_first);
+    p->pw_ends = (int64_t *)malloc((2 * nf + 1) * 8);
+    p->pw_first = (int64_t *)malloc((nf + 1) * 8);
+    p->npw = -1;
+    for (int64_t e = 0; e < nf; ++e) {
+        for (int q = 0; q < 2; ++q) {
+            if (ends[2 * e + q] < 0 || ends[2 * e + q] >= p->nblocks) return -1;
+            p->pw_ends[2 * e + q] = ends[2 * e + q];
+        }
+        if (first[e] < 0 || first[e] + kk > p->n) return -1;
+        for (int64_t j = first[e]; j < first[e] + kk; ++j) if (p->col_block[j] >= 0) return -1;
+        p->pw_first[e] = first[e];
+    }
+    p->npw = nf;
+    return 0;
+}
+
+/* energy of a labelling: node terms of every block, then the factor terms,
+ * read off the objective */
+static double map_energy(const orc_lp *p, const int32_t *lab) {
+    double en = 0.0;
+    for (int64_t t = 0; t < p->nblocks; ++t) en += p->c[p->bfirst[t] + lab[t]];
+    for (int64_t e = 0; e < p->npw; ++e)
+        en += p->c[p->pw_first[e] + (int64_t)lab[p->pw_ends[2 * e]] * p->k + lab[p->pw_ends[2 * e + 1]]];
+    return en;
 }
 
 int64_t orc_num_units(const orc_lp *p) { return p->nunits; }
@@ -958,6 +995,52 @@ int32_t orc_round(const orc_lp *p, const double *x, int32_t rule, uint64_t seed,
         if (aux) aux[0] = alpha;
         return 0;
     }
+    if (rule == RULE_MAP_ARGMAX || rule == RULE_MAP_SAMPLE) {
+        if (p->nblocks <= 0 || p->npw < 0 || !p->pw_ends) return -1;
+        /* node-based roundings of the local-polytope LP (Ravikumar et al.,
+           cited for the MAP experiments): a fixed block keeps its label;
+           otherwise the label of the largest marginal (ties: the lower
+           label), or a label drawn from the marginal by inverse CDF in label
+           order (u below the running sum; past the end, the last label with
+           positive mass); best of reps by energy */
+        int32_t k = p->k;
+        int64_t nb = p->nblocks;
+        int32_t *lab = (int32_t *)malloc((nb + 1) * 4);
+        int32_t nrep = rule == RULE_MAP_ARGMAX ? 1 : (reps > 0 ? reps : 1);
+        double best = INFINITY;
+        for (int32_t rep = 0; rep < nrep; ++rep) {
+            for (int64_t t = 0; t < nb; ++t) {
+                const double *mu = x + p->bfirst[t];
+                int32_t l = 0;
+                if (p->fixed[t] >= 0) {
+                    l = p->fixed[t];
+                } else if (rule == RULE_MAP_ARGMAX) {
+                    for (int32_t a = 1; a < k; ++a) if (mu[a] > mu[l]) l = a;
+                } else {
+                    double u = u53(ph_word(seed, ST_ROUND, (uint64_t)rep, (uint64_t)t, 3)), cum = 0.0;
+                    l = -1;
+                    int32_t lastpos = 0;
+                    for (int32_t a = 0; a < k; ++a) {
+                        if (mu[a] > 0.0) lastpos = a;
+                        cum += mu[a];
+                        if (l < 0 && u < cum) l = a;
+                    }
+                    if (l < 0) l = lastpos;
+                }
+                lab[t] = l;
+            }
+            double en = map_energy(p, lab);
+            if (en < best) {
+                best = en;
+                for (int64_t t = 0; t < nb; ++t) sol[t] = lab[t];
+                if (aux) aux[1] = rep;
+            }
+        }
+        free(lab);
+        *cost = best;
+        if (aux) aux[0] = 0.0;
+        return 0;
+    }
     if (rule == RULE_MC_CKR) {
         if (p->nblocks <= 0) return -1;
         /* region growing: radius rho ~ U[0,1), terminal order sigma random;
@@ -1022,7 +1105,7 @@ int32_t orc_round(const orc_lp *p, const double *x, int32_t rule, uint64_t seed,
 int32_t orc_check(const orc_lp *p, int32_t rule, const int32_t *sol, int32_t *feasible,
                   int64_t *nviol) {
     int64_t bad = 0;
-    if (rule == RULE_MC_CKR) {
+    if (rule == RULE_MC_CKR || rule == RULE_MAP_ARGMAX || rule == RULE_MAP_SAMPLE) {
         for (int64_t t = 0; t < p->nblocks; ++t) {
             if (sol[t] < 0 || sol[t] >= p->k) { ++bad; continue; }
             if (p->fixed[t] >= 0 && sol[t] != p->fixed[t]) ++bad;

@@ -27,6 +27,7 @@ __all__ = [
     "LPInstance", "rng_for", "er_edges", "ba_edges", "regular_edges",
     "grid_edges", "vc_lp", "mis_lp", "mc_grid_lp", "vc_er", "vc_ba",
     "mis_regular", "mc_grid", "serving_trace", "set_cover", "multicover", "kcs_packing",
+    "map_lp", "map_chain_window",
 ]
 
 
@@ -46,6 +47,11 @@ class LPInstance:
     block_first_col: Optional[np.ndarray] = None   # int64[nblocks]
     block_k: int = 0
     fixed_label: Optional[np.ndarray] = None       # int32[nblocks], -1 = free
+    # pairwise factors of a MAP-inference LP: factor e joins blocks
+    # pair_ends[e, 0], pair_ends[e, 1]; its k*k columns start at
+    # pair_first[e], row-major in (label of the first, label of the second)
+    pair_ends: Optional[np.ndarray] = None         # int32[nfactors, 2]
+    pair_first: Optional[np.ndarray] = None        # int64[nfactors]
     meta: dict = field(default_factory=dict)
 
     @property
@@ -391,6 +397,73 @@ def kcs_packing(n_sets: int, n_elements: int, k: int, seed: int, max_weight: int
     return LPInstance(m=n_elements, n=n_sets, row_ptr=row_ptr, col_idx=col_idx, val=val, b=b, c=-profit,
                       u=np.ones(n_sets), sense=-np.ones(n_elements, np.int8),
                       meta=dict(kind="kcs_packing", k=k, seed=seed))
+
+
+def map_lp(n_vars: int, k: int, ends: np.ndarray, unary: np.ndarray, pair: np.ndarray,
+           evidence=None, meta=None) -> LPInstance:
+    """Local-polytope LP of MAP inference on a pairwise factor graph (the
+    formulation the MAP experiments solve): node marginals mu_i in the
+    k-simplex (block i, columns i*k + a), factor marginals mu_e(a, b) >= 0
+    (columns n_vars*k + e*k*k + a*k + b), and per factor e = (i, j) the
+    equalities sum_b mu_e(a, b) = mu_i(a) and sum_a mu_e(a, b) = mu_j(b);
+    minimise sum_i unary[i] . mu_i + sum_e pair[e] . mu_e.  `pair` is
+    [n_factors, k, k]; `evidence` (optional, int per variable, -1 free)
+    fixes observed variables."""
+    nf = ends.shape[0]
+    kk = k * k
+    nx = n_vars * k
+    n = nx + nf * kk
+    m = 2 * nf * k
+    first = nx + np.arange(nf, dtype=np.int64) * kk
+    lab = np.arange(k, dtype=np.int64)
+    # left rows (e, a): mu_i(a) then mu_e(a, 0..k-1); right rows (e, b):
+    # mu_j(b) then mu_e(0..k-1, b); node columns precede factor columns
+    node_l = ends[:, 0:1].astype(np.int64) * k + lab                     # [nf, k]
+    node_r = ends[:, 1:2].astype(np.int64) * k + lab
+    fac_l = first[:, None, None] + lab[None, :, None] * k + lab[None, None, :]   # [nf, a, b]
+    fac_r = first[:, None, None] + lab[None, None, :] * k + lab[None, :, None]   # [nf, b, a]
+    cols_l = np.concatenate([node_l[:, :, None], fac_l], axis=2)          # [nf, k, k+1]
+    cols_r = np.concatenate([node_r[:, :, None], fac_r], axis=2)
+    cols = np.stack([cols_l, cols_r], axis=1).reshape(-1, k + 1)         # rows (e, side, label)
+    vals = np.ones((cols.shape[0], k + 1))
+    vals[:, 0] = -1.0
+    row_ptr = np.arange(0, m * (k + 1) + 1, k + 1, dtype=np.int64)
+    c = np.concatenate([np.asarray(unary, np.float64).reshape(-1), np.asarray(pair, np.float64).reshape(-1)])
+    fixed = np.full(n_vars, -1, np.int32) if evidence is None else np.asarray(evidence, np.int32)
+    return LPInstance(m=m, n=n, row_ptr=row_ptr, col_idx=cols.reshape(-1).astype(np.int32),
+                      val=vals.reshape(-1), b=np.zeros(m), c=c, u=np.ones(n), sense=np.zeros(m, np.int8),
+                      block_first_col=np.arange(n_vars, dtype=np.int64) * k, block_k=k, fixed_label=fixed,
+                      pair_ends=ends.astype(np.int32), pair_first=first,
+                      meta=dict(meta or {}, kind="map", n_vars=n_vars))
+
+
+def map_chain_window(n_vars: int, k: int, n_factors: int, seed: int, window: int = 6) -> LPInstance:
+    """A factor graph shaped like a sequence-labelling task (text chunking):
+    a chain over the tokens with one transition table shared by every chain
+    factor (entries N(0, 1/2)), plus n_factors - (n_vars - 1) agreement
+    factors between tokens 2..window apart (-w on equal labels, w ~ U[0, 1));
+    unary terms N(0, 1).  n_factors = n_vars - 1 gives a plain chain."""
+    rng = rng_for(seed, 26)
+    chain = np.stack([np.arange(n_vars - 1), np.arange(1, n_vars)], axis=1)
+    extra = max(0, n_factors - (n_vars - 1))
+    if extra:
+        i = rng.integers(0, n_vars, extra * 2)
+        d = rng.integers(2, window + 1, extra * 2)
+        ok = i + d < n_vars
+        pairs = np.unique(np.stack([i[ok], i[ok] + d[ok]], axis=1), axis=0)
+        pairs = pairs[rng.permutation(len(pairs))[:extra]]
+        pairs = pairs[np.lexsort((pairs[:, 1], pairs[:, 0]))]
+        ends = np.concatenate([chain, pairs])
+    else:
+        ends = chain
+    unary = rng.standard_normal((n_vars, k))
+    trans = 0.5 * rng.standard_normal((k, k))
+    pair = np.empty((ends.shape[0], k, k))
+    pair[: n_vars - 1] = trans
+    if ends.shape[0] > n_vars - 1:
+        w = rng.uniform(0.0, 1.0, ends.shape[0] - (n_vars - 1))
+        pair[n_vars - 1:] = -w[:, None, None] * np.eye(k)[None]
+    return map_lp(n_vars, k, ends, unary, pair, meta=dict(graph="chain_window", seed=seed, window=window))
 
 
 def serving_trace(n_requests: int, rate: float, seed: int,
