@@ -423,11 +423,17 @@ def mc_grid(args):
 # augmented-Lagrangian workloads: rounding rules with their repetitions, and
 # the workload name's prefix
 AL_WORKLOADS = {
-    "al_ba": ([(1, 1)], "vc_ba_n{n}_m3", 1e-4),
-    "setcover": ([(5, 1), (6, 10)], "set_cover_4000000x1000000_mean8", 1e-4),
+    "al_ba": dict(rules=[(1, 1)], name="vc_ba_n{n}_m3", gap=1e-4, feas=5e-2, beta=10.0),
+    "setcover": dict(rules=[(5, 1), (6, 10)], name="set_cover_4000000x1000000_mean8", gap=1e-4, feas=5e-2,
+                     beta=10.0),
     # the packing LP's gap closes slowly under the outer loop (5.6e-4 after
     # 30 steps of 50 epochs): its default stop is a 1e-3 gap
-    "packing": ([(7, 10)], "kcs_packing_2000000x1000000_k4", 1e-3),
+    "packing": dict(rules=[(7, 10)], name="kcs_packing_2000000x1000000_k4", gap=1e-3, feas=5e-2, beta=10.0),
+    # the text-chunking shape of the MAP experiments (47,000 variables of
+    # domain 23, 100,000 factors); the coupled marginals converge best at a
+    # smaller beta (1, 3 and 10 tried: 3 reaches the tolerances first)
+    "map": dict(rules=[(8, 1), (9, 10)], name="map_chain_window_47000x23_100000factors", gap=3e-4, feas=1e-2,
+                beta=3.0),
 }
 
 
@@ -437,6 +443,8 @@ def _al_instance(args):
         return I.vc_ba(args.n, seed=args.seed)
     if args.workload == "setcover":
         return I.set_cover(4_000_000, 1_000_000, seed=args.seed)
+    if args.workload == "map":
+        return I.map_chain_window(47_000, 23, 100_000, seed=args.seed)
     return I.kcs_packing(2_000_000, 1_000_000, 4, seed=args.seed)
 
 
@@ -445,8 +453,11 @@ def al_workload(args):
     al_ba: vertex cover on the BA graph (n = 2,000,000); setcover: weighted
     set cover, 4,000,000 elements, 1,000,000 sets of mean size 8; packing:
     k-column-sparse packing, 2,000,000 sets of 4 elements over 1,000,000
-    elements, integer weights and capacities.  FP32 storage, beta 10, refresh
-    every 5 epochs, DET: from ubar = 0, blocks of `inner` epochs alternate
+    elements, integer weights and capacities; map: the local-polytope LP of
+    a pairwise factor graph shaped like text chunking (47,000 variables of
+    domain 23, a chain plus agreement factors, 100,000 factors).  FP32
+    storage, the workload's beta, refresh every 5 epochs, DET: from
+    ubar = 0, blocks of `inner` epochs alternate
     with multiplier steps until ||A y - b||_inf <= feas_tol and the LP gap
     certified by the dual function <= lp_gap_tol (at most `outer` steps);
     then the workload's roundings and the check.  Every step re-solves from
@@ -455,14 +466,17 @@ def al_workload(args):
     from paper_1311_2661_amd import thetis as T
     T.lib()
     torch.cuda.set_device(0)
-    rules, wname, gap_default = AL_WORKLOADS[args.workload]
+    wl = AL_WORKLOADS[args.workload]
+    rules, wname, beta = wl["rules"], wl["name"], wl["beta"]
     if args.lp_gap_tol is None:
-        args.lp_gap_tol = gap_default
+        args.lp_gap_tol = wl["gap"]
+    if args.feas_tol is None:
+        args.feas_tol = wl["feas"]
     t0 = time.perf_counter()
     inst = _al_instance(args)
     log(f"instance: {inst.m} rows, {inst.n} columns, {inst.nnz} entries ({time.perf_counter() - t0:.1f} s)")
     h = T.Instance(inst)
-    s = T.Solver(h, beta=10.0, ubar=np.zeros(inst.m), precision=T.PREC_FP32, refresh_every=5, seed=args.seed)
+    s = T.Solver(h, beta=beta, ubar=np.zeros(inst.m), precision=T.PREC_FP32, refresh_every=5, seed=args.seed)
     tuned = s.autotune(4)
     log(f"columns per lane group by class: {tuned}")
     upd = s.traffic()["updates_per_epoch"]
@@ -476,7 +490,7 @@ def al_workload(args):
         for rule, reps in rules:
             sol, cost, aux = s.round(rule, seed=args.seed, reps=reps)
             feas, nviol = s.check(rule)
-            rounded.append((rule, reps, cost, aux, feas))
+            rounded.append((rule, reps, cost, aux, feas, sol))
         return outer, epochs, st, rounded
 
     for w in range(args.warmup):
@@ -500,6 +514,17 @@ def al_workload(args):
     elapsed = time.perf_counter() - t0
     s.set_timing(0)
     assert all(all(x[4] for x in r[3]) for r in results), "a rounded solution is infeasible"
+    # a property at any size: the reported cost recomputed on the host from
+    # the instance and the returned solution
+    for rule, reps, cost, aux, feas, sol in results[-1][3]:
+        if rule in (8, 9):
+            k = inst.block_k
+            e = inst.pair_ends
+            host = float(inst.c[inst.block_first_col + sol].sum() +
+                         inst.c[inst.pair_first + sol[e[:, 0]].astype(np.int64) * k + sol[e[:, 1]]].sum())
+        else:
+            host = float(inst.c @ sol)
+        assert abs(host - cost) <= 1e-9 * max(1.0, abs(cost)), (rule, host, cost)
     outer, epochs, st, rounded = results[-1]
     # time of the roundings alone (outside the timed steps, same state)
     torch.cuda.synchronize()
@@ -514,26 +539,28 @@ def al_workload(args):
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     mms = float(np.mean(mul_ms))
     mgbs = float(np.mean(mul_bytes)) / (mms * 1e-3) / 1e9
-    names = {1: "vc_threshold", 5: "set_cover_threshold", 6: "cover_randomized", 7: "packing_alteration"}
+    names = {1: "vc_threshold", 5: "set_cover_threshold", 6: "cover_randomized", 7: "packing_alteration",
+             8: "map_argmax", 9: "map_sampling"}
     lp_bound = st["lp_dual"]
     sol_out = {"outer_steps": outer, "epochs": epochs, "lp_value": st["lp_value"], "lp_dual": lp_bound,
                "lp_gap": st["lp_gap"], "linf": st["linf"]}
-    for rule, reps, cost, aux, feas in rounded:
+    for rule, reps, cost, aux, feas, _ in rounded:
         key = names[rule]
         if maximise:
             sol_out[key] = {"profit": -cost, "reps": reps, "alpha": aux[0], "feasible": bool(feas),
                             "ratio_to_lp_upper_bound": (-cost) / (-lp_bound)}
         else:
             sol_out[key] = {"cost": cost, "reps": reps, "aux": aux[0], "feasible": bool(feas),
-                            "ratio_to_lp_lower_bound": cost / lp_bound}
-    workload = (f"{wname.format(n=args.n)}_augmented_lagrangian_beta10_fp32_refresh5_{args.inner}ep_per_step_"
+                            "rel_gap_to_lp_bound": (cost - lp_bound) / abs(lp_bound),
+                            "host_recomputed": True}
+    workload = (f"{wname.format(n=args.n)}_augmented_lagrangian_beta{beta:g}_fp32_refresh5_{args.inner}ep_per_step_"
                 f"to_linf{args.feas_tol:g}_gap{args.lp_gap_tol:g}_det")
     out = {
         "metric": METRIC, "value": sum(r[1] for r in results) * upd / elapsed, "unit": "coord updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": workload, "rows": inst.m, "columns": inst.n, "entries": inst.nnz,
-                   "coordinates_per_epoch": upd, "beta": 10.0, "epochs_per_outer_step": args.inner,
+                   "coordinates_per_epoch": upd, "beta": beta, "epochs_per_outer_step": args.inner,
                    "max_outer_steps": args.outer, "feas_tol": args.feas_tol, "lp_gap_tol": args.lp_gap_tol,
                    "roundings": [[names[r], reps] for r, reps in rules], "group_cols_by_class": tuned,
                    "seed": args.seed},
@@ -551,7 +578,7 @@ def al_workload(args):
     if args.cpu_baseline_seconds > 0:
         from oracle import oracle as O
         lp = O.OracleLP(inst)
-        o = O.OracleSolver(lp, beta=10.0, ubar=np.zeros(inst.m), seed=args.seed)
+        o = O.OracleSolver(lp, beta=beta, ubar=np.zeros(inst.m), seed=args.seed)
         t0 = time.perf_counter()
         o.run(1)
         t_ep = time.perf_counter() - t0
@@ -701,11 +728,12 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the k_sweep traffic summary from two rocprofv3 counter runs and exit")
-    ap.add_argument("--workload", choices=["vc_ba", "mc_grid", "mis_batch", "serve", "al_ba", "setcover", "packing"],
+    ap.add_argument("--workload", choices=["vc_ba", "mc_grid", "mis_batch", "serve", "al_ba", "setcover", "packing",
+                                           "map"],
                     default="vc_ba")
     ap.add_argument("--outer", type=int, default=40, help="al_ba / setcover / packing: most multiplier steps")
     ap.add_argument("--inner", type=int, default=50, help="al_ba / setcover / packing: epochs between multiplier steps")
-    ap.add_argument("--feas-tol", type=float, default=5e-2, help="al_ba / setcover / packing: ||A y - b||_inf to stop at")
+    ap.add_argument("--feas-tol", type=float, default=None, help="al_ba / setcover / packing: ||A y - b||_inf to stop at")
     ap.add_argument("--lp-gap-tol", type=float, default=None, help="al_ba / setcover / packing: certified LP gap to stop at")
     ap.add_argument("--side", type=int, default=1024, help="mc_grid: grid side")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")

@@ -86,13 +86,22 @@ enum {
                                      xt_s; a row still short takes, from that
                                      union alone, its unkept sets by decreasing xt
                                      (ties: entry order) until covered           */
-    THETIS_ROUND_PACK_RAND = 7    /* packing (Appendix C scaling, Bansal et al.'s
+    THETIS_ROUND_PACK_RAND = 7,   /* packing (Appendix C scaling, Bansal et al.'s
                                      alteration with theta = 1/k): alpha =
                                      max_j ((A_j x - b_j)/b_j)_+, keep s with
                                      probability x_s/(1+alpha); with w = A_js/b_j,
                                      drop a kept s when, in a row where it has
                                      weight, the kept sets of weight >= its own
                                      (itself included) weigh more than 1         */
+    THETIS_ROUND_MAP_ARGMAX = 8,  /* MAP LP (pairwise factors declared): every free
+                                     block takes the label of its largest
+                                     marginal (ties: the lower label); cost = the
+                                     energy of the labelling                   */
+    THETIS_ROUND_MAP_SAMPLE = 9   /* MAP LP: every free block draws its label from
+                                     its marginal (inverse CDF in label order,
+                                     Philox counter (repetition, block, 3); past
+                                     the end, the last label with positive mass);
+                                     best of reps by energy                    */
 };
 
 /* Solver parameters.  The penalty function is eq. (QP) of Section 3.2 with
@@ -148,6 +157,20 @@ thetis_status thetis_inst_create_csr(int64_t m, int64_t n, int64_t nnz,
 thetis_status thetis_inst_set_simplex_blocks(thetis_inst *inst, int64_t nblocks, int32_t k,
                                              const int64_t *first_col_host,
                                              const int32_t *fixed_label_host);
+
+/* Declares the pairwise factors of a MAP-inference LP (the local polytope
+ * of a pairwise factor graph; the MAP experiments' formulation): factor e
+ * joins simplex blocks ends_host[2e] and ends_host[2e+1] (the node
+ * marginals), and its k*k factor-marginal columns start at
+ * first_col_host[e], row-major in (label of the first block, label of the
+ * second).  Used only by the MAP roundings' energy: sum over blocks of the
+ * objective at the block's label plus, per factor, the objective at its
+ * label pair.  Call after thetis_inst_set_simplex_blocks and before any
+ * solver is created.  Copies the arrays.  THETIS_EINVAL for ends or columns
+ * out of range or factor columns inside a block; THETIS_EBUSY after a
+ * solver exists. */
+thetis_status thetis_inst_set_pairwise(thetis_inst *inst, int64_t nfactors, const int32_t *ends_host,
+                                       const int64_t *first_col_host);
 
 /* Number of colour classes of the DET schedule (greedy colouring of the
  * update units in index order, all slack units in one last class) and the
@@ -297,7 +320,8 @@ thetis_status thetis_epoch(const thetis_solver *s, int64_t *epoch);
 /* Pre-rounding pass and rounding of the current x (Section 2, Lemma
  * infeasible:rounded:vc, Appendix B and C) into sol_host: 0/1 per column
  * for the VC, MIS, COVER and PACK rules (n entries), a label per simplex
- * block for MC_CKR (nblocks entries); sol_host may be NULL.  reps >= 1
+ * block for MC_CKR and the MAP rules (nblocks entries); sol_host may be
+ * NULL.  reps >= 1
  * draws for the randomised rules, keeping the cheapest (ties: first).
  * cost = c^T sol (for MC: the cut weight).  aux_host (NULL or 2 doubles)
  * gets the threshold T (or alpha, or the region radius) and the winning

@@ -512,6 +512,33 @@ extern "C" thetis_status thetis_inst_set_simplex_blocks(thetis_inst *h, int64_t 
     return THETIS_OK;
 }
 
+extern "C" thetis_status thetis_inst_set_pairwise(thetis_inst *h, int64_t nfactors, const int32_t *ends,
+                                                  const int64_t *first_col) {
+    clear_error();
+    if (!h) return fail(THETIS_EINVAL, "instance is NULL");
+    Inst &in = h->in;
+    if (in.has_solver) return fail(THETIS_EBUSY, "pairwise factors must be set before any solver is created");
+    if (in.nblocks <= 0) return fail(THETIS_EINVAL, "pairwise factors need simplex blocks");
+    if (nfactors < 0 || (nfactors && (!ends || !first_col))) return fail(THETIS_EINVAL, "bad factor list");
+    const int64_t kk = (int64_t)in.k * in.k;
+    std::vector<int32_t> pe(2 * nfactors), pf(nfactors);
+    for (int64_t e = 0; e < nfactors; ++e) {
+        for (int q = 0; q < 2; ++q) {
+            if (ends[2 * e + q] < 0 || ends[2 * e + q] >= in.nblocks) return fail(THETIS_EINVAL, "factor end out of range");
+            pe[2 * e + q] = ends[2 * e + q];
+        }
+        if (first_col[e] < 0 || first_col[e] + kk > in.n) return fail(THETIS_EINVAL, "factor columns out of range");
+        for (int64_t j = first_col[e]; j < first_col[e] + kk; ++j)
+            if (in.col_block[j] >= 0) return fail(THETIS_EINVAL, "factor columns inside a simplex block");
+        pf[e] = (int32_t)first_col[e];
+    }
+    std::lock_guard<std::mutex> lock(h->layout_mu);
+    in.npw = nfactors;
+    in.pw_ends.swap(pe);
+    in.pw_first.swap(pf);
+    return THETIS_OK;
+}
+
 extern "C" thetis_status thetis_inst_classes(const thetis_inst *h, int32_t *nclasses, int64_t *nunits,
                                              int32_t *class_host) {
     clear_error();

@@ -1301,6 +1301,61 @@ __global__ __launch_bounds__(kWG) void k_pack_conflicts(Dev<P> a, const int32_t 
     }
 }
 
+// MAP LP, node-based roundings: a fixed block keeps its label; ARGMAX takes
+// the largest marginal (first maximum), SAMPLE the first label whose running
+// sum of marginals (label order, FP64) exceeds a Philox uniform, else the
+// last label with positive mass
+template <class P>
+__global__ __launch_bounds__(kWG) void k_map_label(Dev<P> a, int32_t rule, uint64_t seed, int32_t rep,
+                                                   int32_t *lab) {
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (t >= a.nblocks) return;
+    const int32_t j0 = a.bfirst[t], k = a.k;
+    int32_t l = 0;
+    if (a.fixed[t] >= 0) {
+        l = a.fixed[t];
+    } else if (rule == THETIS_ROUND_MAP_ARGMAX) {
+        double best = (double)xval(a.x[j0]);
+        for (int32_t i = 1; i < k; ++i) {
+            const double v = (double)xval(a.x[j0 + i]);
+            if (v > best) { best = v; l = i; }
+        }
+    } else {
+        const double u = unit53_dev(philox_word_dev(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)t, 3));
+        double cum = 0.0;
+        int32_t got = -1, lastpos = 0;
+        for (int32_t i = 0; i < k; ++i) {
+            const double v = (double)xval(a.x[j0 + i]);
+            if (v > 0.0) lastpos = i;
+            cum = __dadd_rn(cum, v);
+            if (got < 0 && u < cum) got = i;
+        }
+        l = got < 0 ? lastpos : got;
+    }
+    lab[t] = l;
+}
+
+// energy partials: block t's objective at its label, factor t's at its
+// label pair (one index serves both)
+template <class P>
+__global__ __launch_bounds__(kWG) void k_map_energy(Dev<P> a, const int32_t *lab, const int32_t *pw_ends,
+                                                    const int32_t *pw_first, int64_t npw, double *part) {
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    double v = 0.0;
+    if (t < a.nblocks) v += a.c[a.bfirst[t] + lab[t]];
+    if (t < npw)
+        v += a.c[(int64_t)pw_first[t] + (int64_t)lab[pw_ends[2 * t]] * a.k + lab[pw_ends[2 * t + 1]]];
+    v = wsum(v);
+    __shared__ double sh[kWG / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tt = sh[0];
+        for (int w = 1; w < kWG / 64; ++w) tt += sh[w];
+        part[blockIdx.x] = tt;
+    }
+}
+
 // region growing: block t takes the first label of the order whose entry
 // reaches 1 - rad, else the last label of the order
 template <class P>
@@ -1495,6 +1550,7 @@ struct thetis_solver {
     bool metrics_dual = false;                 // the fresh metrics include the dual bound
     bool edge_shape_cover = false, edge_shape_pack = false;
     bool cover_int = false, set_cover = false, packing = false;   // shapes of the general roundings
+    int64_t npw = -1;                                              // pairwise factors (MAP LP)
     double cover_q = 0.0;
     int64_t max_row_len = 0;
     int64_t nunits = 0, updates_per_epoch = 0, max_degree = 0;
@@ -1520,7 +1576,7 @@ struct thetis_solver {
         *async_sched, *pk_det_ptr, *pk_det_row, *pk_det_val, *pk_async_ptr, *pk_async_row,
         *pk_async_val, *pb_id, *pb_j0, *pb_ptr, *pb_row, *pb_val, *rpart, *cpart, *metrics, *sol, *best, *drop,
         *ckr_order, *thr, *costbuf,
-        *chkbuf, *mulstats, *ystage, *row_orig, *ctil0, *ybar0, *ubar0;
+        *chkbuf, *mulstats, *ystage, *row_orig, *ctil0, *ybar0, *ubar0, *pw_ends, *pw_first;
     int64_t nwg_rows = 0, nwg_cols = 0;
     int64_t epoch = 0;
     bool metrics_fresh = false;
@@ -1662,6 +1718,8 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.costbuf = cv.take(8 * 4);
     S.chkbuf = cv.take(8 * 4);
     S.mulstats = cv.take(8 * 4);
+    S.pw_ends = in.npw > 0 ? cv.take(8 * in.npw) : nullptr;
+    S.pw_first = in.npw > 0 ? cv.take(4 * in.npw) : nullptr;
     S.ystage = cv.take(8 * std::max<int64_t>(n + m, 1));
     S.row_orig = cv.take(4 * std::max<int64_t>(m, 1));
     *total = cv.off + 256;
@@ -2079,6 +2137,20 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
             hipLaunchKernelGGL(k_copy_if, dim3(gn), dim3(kWG), 0, S.stream, (const double *)cb, (const int32_t *)sol, best, S.n);
         }
         HIP_TRY(hipMemcpyAsync(auxv, thr, 8, hipMemcpyDeviceToHost, S.stream));
+    } else if (rule == THETIS_ROUND_MAP_ARGMAX || rule == THETIS_ROUND_MAP_SAMPLE) {
+        if (S.nblocks <= 0 || S.npw < 0) return fail(THETIS_EINVAL, "MAP rounding needs simplex blocks and pairwise factors");
+        const int32_t nrep = rule == THETIS_ROUND_MAP_ARGMAX ? 1 : reps;
+        if (nrep < 1) return fail(THETIS_EINVAL, "reps must be >= 1");
+        nsol = S.nblocks;
+        const int64_t gb = std::max<int64_t>(cdiv(S.nblocks, kWG), 1);
+        const int64_t ge = std::max<int64_t>(cdiv(std::max(S.nblocks, S.npw), kWG), 1);
+        for (int32_t rep = 0; rep < nrep; ++rep) {
+            hipLaunchKernelGGL((k_map_label<P>), dim3(gb), dim3(kWG), 0, S.stream, a, rule, seed, rep, sol);
+            hipLaunchKernelGGL((k_map_energy<P>), dim3(ge), dim3(kWG), 0, S.stream, a, (const int32_t *)sol,
+                               (const int32_t *)S.pw_ends, (const int32_t *)S.pw_first, S.npw, part);
+            hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, ge, 1.0, rep, cb);
+            hipLaunchKernelGGL(k_copy_if, dim3(gb), dim3(kWG), 0, S.stream, (const double *)cb, (const int32_t *)sol, best, S.nblocks);
+        }
     } else if (rule == THETIS_ROUND_MC_CKR) {
         if (S.nblocks <= 0) return fail(THETIS_EINVAL, "MC rounding needs simplex blocks");
         if (reps < 1 || reps > kMaxReps) return fail(THETIS_EINVAL, "reps must be in [1, 64]");
@@ -2125,8 +2197,8 @@ thetis_status check_impl(thetis_solver &S, int32_t rule, const int32_t *sol_host
                          int64_t *nviol) {
     Dev<P> a = make_dev<P>(S);
     const int32_t *sol = (const int32_t *)S.best;
-    const bool labels = rule == THETIS_ROUND_MC_CKR;
-    if (labels && S.nblocks <= 0) return fail(THETIS_EINVAL, "MC check needs simplex blocks");
+    const bool labels = rule == THETIS_ROUND_MC_CKR || rule == THETIS_ROUND_MAP_ARGMAX || rule == THETIS_ROUND_MAP_SAMPLE;
+    if (labels && S.nblocks <= 0) return fail(THETIS_EINVAL, "label check needs simplex blocks");
     if (!labels && (rule < THETIS_ROUND_VC_THRESH || rule > THETIS_ROUND_PACK_RAND))
         return fail(THETIS_EINVAL, "unknown rule");
     const int64_t nsol = labels ? S.nblocks : S.n;
@@ -2378,6 +2450,7 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     S.packing = in.packing;
     S.cover_q = in.cover_q;
     S.max_row_len = in.max_row_len;
+    S.npw = in.npw;
     for (const ClassPlan &cp : in.classes) S.det.push_back(make_class_launch(S, in, in.sched, cp.segs));
     {
         std::vector<Segment> all = in.async_struct.segs;
@@ -2415,6 +2488,10 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     UP(upload(S, S.sense, in.sense));
     UP(upload(S, S.c, in.c));
     UP(upload(S, S.row_orig, in.row_orig));
+    if (in.npw > 0) {
+        UP(upload(S, S.pw_ends, in.pw_ends));
+        UP(upload(S, S.pw_first, in.pw_first));
+    }
     UP(upload(S, S.sched, in.sched));
     UP(upload(S, S.async_sched, in.async_sched));
     UP(upload(S, S.pk_det_ptr, in.pk_det.ptr));

@@ -102,6 +102,11 @@ struct Inst {
     // (covering), additionally all entries and right-hand sides 1 (set
     // cover), or every row '<=' with non-negative entries and b > 0
     // (packing); q(P) of the covering lemma; the longest row
+    // pairwise factors of a MAP-inference LP (npw = -1: none declared):
+    // factor e joins blocks pw_ends[2e], pw_ends[2e+1], its k*k columns
+    // start at pw_first[e] (row-major in the two labels)
+    int64_t npw = -1;
+    std::vector<int32_t> pw_ends, pw_first;
     bool cover_int = false, set_cover = false, packing = false;
     double cover_q = 0.0;
     int64_t max_row_len = 0;

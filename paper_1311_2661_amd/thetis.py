@@ -31,11 +31,13 @@ SCHED_DET, SCHED_ASYNC = 0, 1
 PREC_FP32, PREC_FP64, PREC_BF16X = 0, 1, 2
 ROUND_VC_THRESH, ROUND_MIS_THRESH, ROUND_MIS_RAND, ROUND_MC_CKR = 1, 2, 3, 4
 ROUND_COVER_THRESH, ROUND_COVER_RAND, ROUND_PACK_RAND = 5, 6, 7
+ROUND_MAP_ARGMAX, ROUND_MAP_SAMPLE = 8, 9
+LABEL_RULES = (ROUND_MC_CKR, ROUND_MAP_ARGMAX, ROUND_MAP_SAMPLE)
 SHAPE_COVER, SHAPE_SET_COVER, SHAPE_PACK = 1, 2, 4
 
 EXPORTED = [
     "thetis_params_default", "thetis_inst_create_csr", "thetis_inst_set_simplex_blocks",
-    "thetis_inst_classes", "thetis_inst_rounding_shape", "thetis_inst_destroy", "thetis_solver_workspace_bytes",
+    "thetis_inst_classes", "thetis_inst_rounding_shape", "thetis_inst_set_pairwise", "thetis_inst_destroy", "thetis_solver_workspace_bytes",
     "thetis_solver_create", "thetis_solver_reset", "thetis_set_beta", "thetis_set_step_rule",
     "thetis_run_epochs", "thetis_solver_autotune", "thetis_multiplier_step", "thetis_run_multipliers",
     "thetis_get_multipliers", "thetis_residual", "thetis_objective", "thetis_get_x",
@@ -87,6 +89,7 @@ def lib():
             "thetis_inst_set_simplex_blocks": [vp, i64, i32, vp, vp],
             "thetis_inst_classes": [vp, P(i32), P(i64), vp],
             "thetis_inst_rounding_shape": [vp, P(i32), P(dbl)],
+            "thetis_inst_set_pairwise": [vp, i64, vp, vp],
             "thetis_inst_destroy": [vp],
             "thetis_solver_workspace_bytes": [vp, P(thetis_params), P(C.c_size_t)],
             "thetis_solver_create": [vp, P(thetis_params), vp, C.c_size_t, vp, P(vp)],
@@ -166,6 +169,12 @@ def thetis_inst_set_simplex_blocks(h, nblocks, k, first_col, fixed_label=None):
     f = _c(first_col, np.int64)
     fx = _c(fixed_label, np.int32)
     _check(lib().thetis_inst_set_simplex_blocks(h, nblocks, k, _ptr(f), _ptr(fx)))
+
+
+def thetis_inst_set_pairwise(h, ends, first_col):
+    e = np.ascontiguousarray(ends, dtype=np.int32).reshape(-1)
+    f = np.ascontiguousarray(first_col, dtype=np.int64)
+    _check(lib().thetis_inst_set_pairwise(h, f.size, _ptr(e), _ptr(f)))
 
 
 def thetis_inst_rounding_shape(h):
@@ -374,6 +383,8 @@ class Instance:
         if inst.block_first_col is not None:
             thetis_inst_set_simplex_blocks(self.h, len(inst.block_first_col), inst.block_k,
                                            inst.block_first_col, inst.fixed_label)
+        if getattr(inst, "pair_ends", None) is not None:
+            thetis_inst_set_pairwise(self.h, inst.pair_ends, inst.pair_first)
         self.m, self.n = inst.m, inst.n
 
     def classes(self):
@@ -496,7 +507,7 @@ class Solver:
         return thetis_epoch(self.h)
 
     def round(self, rule: int, seed: int = 0, reps: int = 1):
-        nsol = self.nblocks if rule == ROUND_MC_CKR else self.n
+        nsol = self.nblocks if rule in LABEL_RULES else self.n
         return thetis_round(self.h, rule, seed, reps, nsol)
 
     def check(self, rule: int, sol=None):
