@@ -100,6 +100,7 @@ struct Dev {
     // scalars
     R beta, rho, gamma, Lmax, ub_value;
     int32_t global_lmax, async_mode, prox_on;
+    int32_t row_lanes;        // lanes per row in the row passes (1: a thread per row)
     int64_t n, m, nblocks;
     int32_t k;
 };
@@ -570,12 +571,17 @@ __device__ __forceinline__ void rows_item(const Dev<P> &a, int64_t wg, int32_t w
     using R = typename P::R;
     double v[kRowSlots] = {0, 0, 0, 0, 0, 0};
     const int op[kRowSlots] = {0, 1, 1, 0, 0, 0};
+    // rows_lanes lanes per row (a power of two; long rows): the group's lanes
+    // stride the row and reduce with a butterfly, its first lane finishes
+    const int G = a.row_lanes, lane = threadIdx.x & (G - 1);
     for (int q = 0; q < kRowsPerThread; ++q) {
-        const int64_t i = (wg * kRowsPerThread + q) * kWG + threadIdx.x;
-        if (i >= a.m) break;
+        const int64_t i = (wg * kRowsPerThread + q) * (kWG / G) + threadIdx.x / G;
+        if (i >= a.m) break;                  // the whole group together
         double ax = 0.0;
-        for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
+        for (int32_t e = a.row_ptr[i] + lane; e < a.row_ptr[i + 1]; e += G)
             ax += (a.csr_val ? (double)a.csr_val[e] : 1.0) * (double)xval(a.x[a.csr_col[e]]);
+        for (int o = G / 2; o > 0; o >>= 1) ax += __shfl_xor(ax, o, 64);
+        if (lane) continue;
         const int8_t sn = a.sense[i];
         double acc = ax;
         if (sn > 0) acc -= (double)a.s[i];
@@ -866,12 +872,15 @@ __global__ __launch_bounds__(kWG) void k_mul_rows(Dev<P> a, double *ubar_w, type
     using R = typename P::R;
     double v[kMulRowSlots] = {0, 0};
     const int op[kMulRowSlots] = {0, 1};
+    const int G = a.row_lanes, lane = threadIdx.x & (G - 1);
     for (int q = 0; q < kRowsPerThread; ++q) {
-        const int64_t i = ((int64_t)blockIdx.x * kRowsPerThread + q) * kWG + threadIdx.x;
-        if (i >= a.m) break;
+        const int64_t i = ((int64_t)blockIdx.x * kRowsPerThread + q) * (kWG / G) + threadIdx.x / G;
+        if (i >= a.m) break;                  // the whole group together
         double acc = 0.0;
-        for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
+        for (int32_t e = a.row_ptr[i] + lane; e < a.row_ptr[i + 1]; e += G)
             acc += (a.csr_val ? (double)a.csr_val[e] : 1.0) * (double)xval(a.x[a.csr_col[e]]);
+        for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane) continue;
         const int8_t sn = a.sense[i];
         if (sn > 0) acc -= (double)a.s[i];
         else if (sn < 0) acc += (double)a.s[i];
@@ -1554,6 +1563,7 @@ struct thetis_solver {
     double cover_q = 0.0;
     int64_t max_row_len = 0;
     int64_t nunits = 0, updates_per_epoch = 0, max_degree = 0;
+    int32_t row_lanes = 1;                     // lanes per row of the row passes
     int32_t lpc = 1;                           // lanes per column of a simplex block
     // parameters
     thetis_params p{};
@@ -1618,6 +1628,22 @@ int64_t units_per_wg(int kind, bool dual) {
     if (kind < kGroupKinds) return kWG / kGroupLanes[kind];
     if (kind == SEG_BLOCK) return kWG / 64;
     return kWG;
+}
+
+// workgroups of a row pass: kRowsPerThread rows per group of row_lanes lanes
+int64_t row_wgs(int64_t m, int32_t lanes) {
+    return cdiv(std::max<int64_t>(m, 1), (int64_t)(kWG / lanes) * kRowsPerThread);
+}
+int64_t row_wgs(const thetis_solver &S) { return row_wgs(S.m, S.row_lanes); }
+
+// lanes per row for the row passes: 1 for short rows (edges), else the
+// largest power of two up to half the mean row length, at most 16
+int32_t choose_row_lanes(int64_t nnz, int64_t m) {
+    const double len = m ? (double)nnz / (double)m : 0.0;
+    if (len < 4.0) return 1;
+    int32_t g = 2;
+    while (g < 16 && 2.0 * g <= len / 2.0) g *= 2;
+    return g;
 }
 
 // Workgroup ranges of one fused launch over the given segments (at most one
@@ -1700,7 +1726,9 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.pb_ptr = nb ? cv.take(4 * in.pb_det.ptr.size()) : nullptr;
     S.pb_row = nb ? cv.take(4 * std::max<size_t>(in.pb_det.row.size(), 1)) : nullptr;
     S.pb_val = nb && !in.unit_vals ? cv.take(R * std::max<size_t>(in.pb_det.val.size(), 1)) : nullptr;
-    S.nwg_rows = std::max<int64_t>(cdiv(std::max(m, n), kWG), 1);   // also the rounding's partials
+    S.row_lanes = choose_row_lanes(nnz, m);
+    // row-pass records (row_wgs) and the rounding's per-thread partials
+    S.nwg_rows = std::max<int64_t>(std::max<int64_t>(cdiv(std::max(m, n), kWG), row_wgs(m, S.row_lanes)), 1);
     std::vector<Segment> dsegs = in.async_struct.segs;
     dsegs.insert(dsegs.end(), in.async_slack.segs.begin(), in.async_slack.segs.end());
     S.dual = make_plan(dsegs, true, n);
@@ -1759,6 +1787,7 @@ Dev<P> make_dev(const thetis_solver &S) {
     a.global_lmax = S.p.step_rule == THETIS_STEP_GLOBAL_LMAX;
     a.async_mode = S.p.schedule == THETIS_SCHED_ASYNC;
     a.prox_on = S.p.prox != 0;
+    a.row_lanes = S.row_lanes;
     a.n = S.n;
     a.m = S.m;
     a.nblocks = S.nblocks;
@@ -1858,7 +1887,7 @@ void launch_class(thetis_solver &S, const Dev<P> &a, const ClassLaunch &cl, cons
 template <class P>
 thetis_status refresh(thetis_solver &S, bool write_r, bool with_dual) {
     Dev<P> a = make_dev<P>(S);
-    const int64_t gr = cdiv(std::max<int64_t>(S.m, 1), (int64_t)kWG * kRowsPerThread);
+    const int64_t gr = row_wgs(S);
     const LaunchPlan &pl = with_dual ? S.dual : S.colterms;
     {
         TimedScope ts(S, THETIS_K_REFRESH, with_dual ? S.refresh_bytes : S.refresh_bytes_nodual);
@@ -1987,7 +2016,7 @@ thetis_status multiplier_impl(thetis_solver &S, bool move_centre, double *out) {
     using R = typename P::R;
     Dev<P> a = make_dev<P>(S);
     R *ybar_w = move_centre ? (R *)S.ybar : nullptr;
-    const int64_t gr = cdiv(std::max<int64_t>(S.m, 1), (int64_t)kWG * kRowsPerThread);
+    const int64_t gr = row_wgs(S);
     const LaunchPlan &pl = S.dual;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
@@ -3348,7 +3377,7 @@ thetis_status batch_upload(thetis_batch &B, int32_t max_epochs, double gap_tol) 
         I.cpart = (double *)S.cpart;
         I.metrics = (double *)S.metrics;
         I.epoch = S.epoch;
-        I.rows_wg = cdiv(std::max<int64_t>(S.m, 1), (int64_t)kWG * kRowsPerThread);
+        I.rows_wg = row_wgs(S);
         I.seed = S.p.seed;
         I.gap_tol = gap_tol;
         I.beta = S.p.beta;
