@@ -1623,7 +1623,7 @@ struct Carver {
 size_t prec_bytes(int32_t prec) { return prec == THETIS_PREC_FP64 ? 8 : 4; }
 size_t x_bytes(int32_t prec) { return prec == THETIS_PREC_FP64 ? 8 : (prec == THETIS_PREC_BF16X ? 2 : 4); }
 
-int64_t units_per_wg(int kind, bool dual) {
+int64_t units_per_wg(int kind) {
     if (kind == SEG_HUB) return 1;
     if (kind < kGroupKinds) return kWG / kGroupLanes[kind];
     if (kind == SEG_BLOCK) return kWG / 64;
@@ -1671,7 +1671,7 @@ LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolte
         // dual plans: kRowsPerThread units per group / wavefront / thread
         const int64_t upw = kind < kGroupKinds ? kWG / pl.lanes[p] * pl.cols[p] * (dual ? kRowsPerThread : 1)
                           : (kind == SEG_NKIND ? kWG * kRowsPerThread
-                                               : units_per_wg(kind, dual) * (dual && kind != SEG_HUB ? kRowsPerThread : 1));
+                                               : units_per_wg(kind) * (dual && kind != SEG_HUB ? kRowsPerThread : 1));
         int64_t w = pl.count[p] ? cdiv(pl.count[p], upw) : 0;
         if (kind == SEG_HUB) { w = cdiv(w, 8) * 8; pl.hub_wg = w; }
         wg += w;
