@@ -372,6 +372,21 @@ thetis_status thetis_get_timing(const thetis_solver *s, int32_t kind, double *ms
 thetis_status thetis_epoch_traffic(const thetis_solver *s, double *sweep_bytes,
                                    double *refresh_bytes, int64_t *updates_per_epoch);
 
+/* Checkpoint of a solver's state (not part of the method): x, s, the running
+ * residual r, the epoch (which selects the next class orders), beta and,
+ * when the solver holds them, ubar, the shifted costs and the prox centre,
+ * all as stored on the device.  thetis_solver_save with host_buf NULL puts
+ * the size in *bytes; otherwise *bytes gives the buffer's size (too small:
+ * THETIS_EINVAL with the size in *bytes) and receives the bytes written.
+ * thetis_solver_load restores such a checkpoint into a solver of the same
+ * instance, precision and ubar/prox setting (THETIS_EINVAL otherwise); the
+ * solve then continues bit for bit as it would have from the save (DET).
+ * A reset afterwards still returns to the creation values.  Both
+ * synchronise the solver's stream; not while a batch holding the solver
+ * runs. */
+thetis_status thetis_solver_save(thetis_solver *s, void *host_buf, size_t *bytes);
+thetis_status thetis_solver_load(thetis_solver *s, const void *host_buf, size_t bytes);
+
 thetis_status thetis_solver_destroy(thetis_solver *s);
 
 /* Measurement aid (no part of the method): on `stream` (NULL: the null

@@ -2866,6 +2866,102 @@ extern "C" thetis_status thetis_epoch_traffic(const thetis_solver *s, double *sw
     return THETIS_OK;
 }
 
+namespace {
+
+// Checkpoint layout: a header, then x, s, r, and, when the solver holds
+// them, ubar (FP64), the shifted costs and the prox centre, each as stored.
+struct CheckpointHeader {
+    char magic[8];
+    int32_t version, precision, has_ubar, has_ybar;
+    int64_t n, m, epoch;
+    double beta;
+};
+constexpr char kCheckpointMagic[8] = {'T', 'H', 'E', 'T', 'I', 'S', 'C', 'K'};
+
+struct CheckpointPart {
+    void *dev;
+    size_t bytes;
+};
+
+std::vector<CheckpointPart> checkpoint_parts(const thetis_solver &S) {
+    const size_t R = prec_bytes(S.p.precision), X = x_bytes(S.p.precision);
+    std::vector<CheckpointPart> parts = {{S.x, X * (size_t)S.n}, {S.s, R * (size_t)S.m}, {S.r, R * (size_t)S.m}};
+    if (S.has_ubar) {
+        parts.push_back({S.ubar, 8 * (size_t)S.m});
+        parts.push_back({S.ctil, R * (size_t)(S.n + S.m)});
+    }
+    if (S.has_ybar) parts.push_back({S.ybar, R * (size_t)(S.n + S.m)});
+    return parts;
+}
+
+}  // namespace
+
+extern "C" thetis_status thetis_solver_save(thetis_solver *s, void *host_buf, size_t *bytes) {
+    clear_error();
+    if (!s || !bytes) return fail(THETIS_EINVAL, "NULL argument");
+    thetis_solver &S = *s;
+    const std::vector<CheckpointPart> parts = checkpoint_parts(S);
+    size_t need = sizeof(CheckpointHeader);
+    for (const CheckpointPart &q : parts) need += q.bytes;
+    if (!host_buf) { *bytes = need; return THETIS_OK; }
+    if (*bytes < need) { *bytes = need; return fail(THETIS_EINVAL, "checkpoint buffer too small"); }
+    CheckpointHeader h{};
+    std::memcpy(h.magic, kCheckpointMagic, 8);
+    h.version = 1;
+    h.precision = S.p.precision;
+    h.has_ubar = S.has_ubar;
+    h.has_ybar = S.has_ybar;
+    h.n = S.n;
+    h.m = S.m;
+    h.epoch = S.epoch;
+    h.beta = S.p.beta;
+    char *out = (char *)host_buf;
+    std::memcpy(out, &h, sizeof(h));
+    size_t off = sizeof(h);
+    for (const CheckpointPart &q : parts) {
+        if (q.bytes) HIP_TRY(hipMemcpyAsync(out + off, q.dev, q.bytes, hipMemcpyDeviceToHost, S.stream));
+        off += q.bytes;
+    }
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    *bytes = need;
+    return THETIS_OK;
+}
+
+extern "C" thetis_status thetis_solver_load(thetis_solver *s, const void *host_buf, size_t bytes) {
+    clear_error();
+    if (!s || !host_buf) return fail(THETIS_EINVAL, "NULL argument");
+    thetis_solver &S = *s;
+    if (bytes < sizeof(CheckpointHeader)) return fail(THETIS_EINVAL, "checkpoint too short");
+    CheckpointHeader h;
+    std::memcpy(&h, host_buf, sizeof(h));
+    if (std::memcmp(h.magic, kCheckpointMagic, 8) != 0 || h.version != 1)
+        return fail(THETIS_EINVAL, "not a checkpoint of this library");
+    if (h.precision != S.p.precision || h.n != S.n || h.m != S.m || h.has_ubar != (int32_t)S.has_ubar ||
+        h.has_ybar != (int32_t)S.has_ybar)
+        return fail(THETIS_EINVAL, "checkpoint of a different instance, precision or parameter set");
+    if (!(h.beta > 0.0) || !std::isfinite(h.beta) || h.epoch < 0) return fail(THETIS_EINVAL, "corrupt checkpoint header");
+    const std::vector<CheckpointPart> parts = checkpoint_parts(S);
+    size_t need = sizeof(h);
+    for (const CheckpointPart &q : parts) need += q.bytes;
+    if (bytes != need) return fail(THETIS_EINVAL, "checkpoint size does not match the solver");
+    const char *in = (const char *)host_buf;
+    size_t off = sizeof(h);
+    for (const CheckpointPart &q : parts) {
+        if (q.bytes) HIP_TRY(hipMemcpyAsync(q.dev, in + off, q.bytes, hipMemcpyHostToDevice, S.stream));
+        off += q.bytes;
+    }
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    if (h.beta != S.p.beta) {
+        thetis_status st = apply_beta(S, h.beta);
+        if (st) return st;
+    }
+    S.epoch = h.epoch;
+    S.metrics_fresh = false;
+    S.have_round = false;
+    if (S.has_ubar || S.has_ybar || h.beta != S.beta0) S.mul_dirty = true;   // a reset returns to creation
+    return THETIS_OK;
+}
+
 extern "C" thetis_status thetis_solver_destroy(thetis_solver *s) {
     if (!s) return THETIS_OK;
     (void)hipStreamSynchronize(s->stream);

@@ -40,7 +40,7 @@ EXPORTED = [
     "thetis_inst_classes", "thetis_inst_rounding_shape", "thetis_inst_set_pairwise", "thetis_inst_destroy", "thetis_solver_workspace_bytes",
     "thetis_solver_create", "thetis_solver_reset", "thetis_set_beta", "thetis_set_step_rule",
     "thetis_run_epochs", "thetis_solver_autotune", "thetis_multiplier_step", "thetis_run_multipliers",
-    "thetis_get_multipliers", "thetis_residual", "thetis_objective", "thetis_get_x",
+    "thetis_get_multipliers", "thetis_solver_save", "thetis_solver_load", "thetis_residual", "thetis_objective", "thetis_get_x",
     "thetis_set_y",
     "thetis_epoch", "thetis_round", "thetis_check_feasible", "thetis_set_timing",
     "thetis_get_timing", "thetis_epoch_traffic", "thetis_solver_destroy", "thetis_calibrate_random",
@@ -102,6 +102,8 @@ def lib():
             "thetis_run_multipliers": [vp, i32, i32, dbl, dbl, dbl, dbl, dbl, i32, P(i32), P(i64),
                                        P(thetis_mul_stats)],
             "thetis_get_multipliers": [vp, vp, vp],
+            "thetis_solver_save": [vp, vp, P(C.c_size_t)],
+            "thetis_solver_load": [vp, vp, C.c_size_t],
             "thetis_residual": [vp, P(dbl), P(dbl), P(dbl)],
             "thetis_objective": [vp, P(dbl), P(dbl), P(dbl)],
             "thetis_get_x": [vp, vp, vp],
@@ -247,6 +249,19 @@ def thetis_get_multipliers(s, m: int, n: int, multiplier: bool = True, centre: b
     yb = np.zeros(n + m) if centre else None
     _check(lib().thetis_get_multipliers(s, _ptr(u), _ptr(yb)))
     return u, yb
+
+
+def thetis_solver_save(s) -> bytes:
+    n = C.c_size_t()
+    _check(lib().thetis_solver_save(s, None, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _check(lib().thetis_solver_save(s, buf, C.byref(n)))
+    return buf.raw[: n.value]
+
+
+def thetis_solver_load(s, blob: bytes):
+    buf = C.create_string_buffer(blob, len(blob))
+    _check(lib().thetis_solver_load(s, buf, len(blob)))
 
 
 def thetis_residual(s):
@@ -474,6 +489,13 @@ class Solver:
     @property
     def ybar(self) -> np.ndarray:
         return thetis_get_multipliers(self.h, self.m, self.n, multiplier=False, centre=True)[1]
+
+    def save(self) -> bytes:
+        """Checkpoint of the device state (bit-exact resume)."""
+        return thetis_solver_save(self.h)
+
+    def load(self, blob: bytes):
+        thetis_solver_load(self.h, blob)
 
     def residual(self):
         linf, l2, viol = thetis_residual(self.h)
