@@ -422,18 +422,21 @@ def mc_grid(args):
 
 # augmented-Lagrangian workloads: rounding rules with their repetitions, and
 # the workload name's prefix
+# beta and epochs between multiplier steps are the fastest to the tolerances
+# among beta in {3, 10} (also 1 and 30 for packing, 1 for the MAP LP) and
+# 10, 20, 30 or 50 epochs, measured on these instances
 AL_WORKLOADS = {
-    "al_ba": dict(rules=[(1, 1)], name="vc_ba_n{n}_m3", gap=1e-4, feas=5e-2, beta=10.0),
+    "al_ba": dict(rules=[(1, 1)], name="vc_ba_n{n}_m3", gap=1e-4, feas=5e-2, beta=3.0, inner=10),
     "setcover": dict(rules=[(5, 1), (6, 10)], name="set_cover_4000000x1000000_mean8", gap=1e-4, feas=5e-2,
-                     beta=10.0),
-    # the packing LP's gap closes slowly under the outer loop (5.6e-4 after
-    # 30 steps of 50 epochs): its default stop is a 1e-3 gap
-    "packing": dict(rules=[(7, 10)], name="kcs_packing_2000000x1000000_k4", gap=1e-3, feas=5e-2, beta=10.0),
+                     beta=10.0, inner=10),
+    # the packing LP's gap closes slowly under the outer loop: its stop is a
+    # 1e-3 gap
+    "packing": dict(rules=[(7, 10)], name="kcs_packing_2000000x1000000_k4", gap=1e-3, feas=5e-2, beta=3.0,
+                    inner=10),
     # the text-chunking shape of the MAP experiments (47,000 variables of
-    # domain 23, 100,000 factors); the coupled marginals converge best at a
-    # smaller beta (1, 3 and 10 tried: 3 reaches the tolerances first)
+    # domain 23, 100,000 factors)
     "map": dict(rules=[(8, 1), (9, 10)], name="map_chain_window_47000x23_100000factors", gap=3e-4, feas=1e-2,
-                beta=3.0),
+                beta=3.0, inner=10),
 }
 
 
@@ -472,6 +475,8 @@ def al_workload(args):
         args.lp_gap_tol = wl["gap"]
     if args.feas_tol is None:
         args.feas_tol = wl["feas"]
+    if args.inner is None:
+        args.inner = wl["inner"]
     t0 = time.perf_counter()
     inst = _al_instance(args)
     log(f"instance: {inst.m} rows, {inst.n} columns, {inst.nnz} entries ({time.perf_counter() - t0:.1f} s)")
@@ -731,8 +736,8 @@ def main():
     ap.add_argument("--workload", choices=["vc_ba", "mc_grid", "mis_batch", "serve", "al_ba", "setcover", "packing",
                                            "map"],
                     default="vc_ba")
-    ap.add_argument("--outer", type=int, default=40, help="al_ba / setcover / packing: most multiplier steps")
-    ap.add_argument("--inner", type=int, default=50, help="al_ba / setcover / packing: epochs between multiplier steps")
+    ap.add_argument("--outer", type=int, default=200, help="al_ba / setcover / packing: most multiplier steps")
+    ap.add_argument("--inner", type=int, default=None, help="al_ba / setcover / packing: epochs between multiplier steps")
     ap.add_argument("--feas-tol", type=float, default=None, help="al_ba / setcover / packing: ||A y - b||_inf to stop at")
     ap.add_argument("--lp-gap-tol", type=float, default=None, help="al_ba / setcover / packing: certified LP gap to stop at")
     ap.add_argument("--side", type=int, default=1024, help="mc_grid: grid side")

@@ -867,7 +867,7 @@ __device__ __forceinline__ double clip_dual(double u, int8_t sn) {
 // multiplier, the slack entries of ctil (covering +ubar, packing -ubar) and,
 // when ybar_w is set, the slack part of the new prox centre.
 template <class P>
-__global__ __launch_bounds__(kWG) void k_mul_rows(Dev<P> a, double *ubar_w, typename P::R *ctil_w,
+__global__ __launch_bounds__(kWG) void k_mul_rows(Dev<P> a, double *ubar_w, double2 *upair, typename P::R *ctil_w,
                                                   typename P::R *ybar_w, double beta, double *part) {
     using R = typename P::R;
     double v[kMulRowSlots] = {0, 0};
@@ -886,10 +886,13 @@ __global__ __launch_bounds__(kWG) void k_mul_rows(Dev<P> a, double *ubar_w, type
         else if (sn < 0) acc += (double)a.s[i];
         const double w = acc - a.b[i];
         const double un = ubar_w[i] - beta * w;
+        const double uc = clip_dual(un, sn);
         ubar_w[i] = un;
+        // the column pass reads both values of a row with one 16-byte load
+        upair[i] = make_double2(un, uc);
         ctil_w[a.n + i] = (R)(sn > 0 ? un : (sn < 0 ? -un : 0.0));
         if (ybar_w) ybar_w[a.n + i] = a.s[i];
-        v[0] += a.b[i] * clip_dual(un, sn);
+        v[0] += a.b[i] * uc;
         v[1] = fmax(v[1], fabs(w));
     }
     block_reduce<kMulRowSlots>(v, op, part + (int64_t)blockIdx.x * kMulRowSlots);
@@ -904,7 +907,7 @@ __global__ __launch_bounds__(kWG) void k_mul_rows(Dev<P> a, double *ubar_w, type
 // the structural part of ybar.
 template <class P, bool VALS>
 __device__ __forceinline__ void mul_item(const Dev<P> &a, const Sched<typename P::R> &sc, const LaunchPlan &pl,
-                                         int64_t L, const double *ubar, typename P::R *ctil_w,
+                                         int64_t L, const double2 *upair, typename P::R *ctil_w,
                                          typename P::R *ybar_w, double *part, double *sh) {
     using R = typename P::R;
     int64_t local;
@@ -917,10 +920,9 @@ __device__ __forceinline__ void mul_item(const Dev<P> &a, const Sched<typename P
                       double &t_u, double &t_c) {
         for (int32_t e = e0; e < e1; e += step) {
             const double av = VALS ? (double)val[e] : 1.0;
-            const int32_t i = row[e];
-            const double ub = ubar[i];
-            t_u += av * ub;
-            t_c += av * clip_dual(ub, a.sense[i]);
+            const double2 up = upair[row[e]];
+            t_u += av * up.x;
+            t_c += av * up.y;
         }
     };
     if (kind == SEG_HUB) {
@@ -1005,10 +1007,10 @@ __device__ __forceinline__ void mul_item(const Dev<P> &a, const Sched<typename P
 
 template <class P, bool VALS>
 __global__ __launch_bounds__(kWG) void k_mul_cols(Dev<P> a, Sched<typename P::R> sc, LaunchPlan pl,
-                                                  const double *ubar, typename P::R *ctil_w,
+                                                  const double2 *upair, typename P::R *ctil_w,
                                                   typename P::R *ybar_w, double *part) {
     __shared__ double sh[kWG / 64];
-    mul_item<P, VALS>(a, sc, pl, logical_wg(pl, blockIdx.x), ubar, ctil_w, ybar_w, part, sh);
+    mul_item<P, VALS>(a, sc, pl, logical_wg(pl, blockIdx.x), upair, ctil_w, ybar_w, part, sh);
 }
 
 // out: c^T x, max |w|, D, (c^T x - D) / max(1, |c^T x|)
@@ -1586,7 +1588,7 @@ struct thetis_solver {
         *async_sched, *pk_det_ptr, *pk_det_row, *pk_det_val, *pk_async_ptr, *pk_async_row,
         *pk_async_val, *pb_id, *pb_j0, *pb_ptr, *pb_row, *pb_val, *rpart, *cpart, *metrics, *sol, *best, *drop,
         *ckr_order, *thr, *costbuf,
-        *chkbuf, *mulstats, *ystage, *row_orig, *ctil0, *ybar0, *ubar0, *pw_ends, *pw_first;
+        *chkbuf, *mulstats, *ystage, *row_orig, *ctil0, *ybar0, *ubar0, *upair, *pw_ends, *pw_first;
     int64_t nwg_rows = 0, nwg_cols = 0;
     int64_t epoch = 0;
     bool metrics_fresh = false;
@@ -1705,6 +1707,7 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.ctil0 = S.has_ubar ? cv.take(R * (n + m)) : nullptr;
     S.ybar0 = S.has_ybar ? cv.take(R * (n + m)) : nullptr;
     S.ubar0 = S.has_ubar ? cv.take(8 * m) : nullptr;
+    S.upair = S.has_ubar ? cv.take(16 * std::max<int64_t>(m, 1)) : nullptr;   // multiplier step's row records
     S.bfirst = nb ? cv.take(4 * nb) : nullptr;
     S.fixed = nb ? cv.take(4 * nb) : nullptr;
     S.col_block = nb ? cv.take(4 * n) : nullptr;
@@ -2025,11 +2028,11 @@ thetis_status multiplier_impl(thetis_solver &S, bool move_centre, double *out) {
         return fail(THETIS_EDEVICE, "hipEventCreate failed");
     }
     (void)hipEventRecord(e0, S.stream);
-    hipLaunchKernelGGL((k_mul_rows<P>), dim3(gr), dim3(kWG), 0, S.stream, a, (double *)S.ubar, (R *)S.ctil,
-                       ybar_w, S.p.beta, (double *)S.rpart);
+    hipLaunchKernelGGL((k_mul_rows<P>), dim3(gr), dim3(kWG), 0, S.stream, a, (double *)S.ubar, (double2 *)S.upair,
+                       (R *)S.ctil, ybar_w, S.p.beta, (double *)S.rpart);
     if (pl.nwg > 0) {
-        if (S.unit_vals) hipLaunchKernelGGL((k_mul_cols<P, false>), dim3(pl.nwg), dim3(kWG), 0, S.stream, a, async_sched<P>(S), pl, (const double *)S.ubar, (R *)S.ctil, ybar_w, (double *)S.cpart);
-        else hipLaunchKernelGGL((k_mul_cols<P, true>), dim3(pl.nwg), dim3(kWG), 0, S.stream, a, async_sched<P>(S), pl, (const double *)S.ubar, (R *)S.ctil, ybar_w, (double *)S.cpart);
+        if (S.unit_vals) hipLaunchKernelGGL((k_mul_cols<P, false>), dim3(pl.nwg), dim3(kWG), 0, S.stream, a, async_sched<P>(S), pl, (const double2 *)S.upair, (R *)S.ctil, ybar_w, (double *)S.cpart);
+        else hipLaunchKernelGGL((k_mul_cols<P, true>), dim3(pl.nwg), dim3(kWG), 0, S.stream, a, async_sched<P>(S), pl, (const double2 *)S.upair, (R *)S.ctil, ybar_w, (double *)S.cpart);
     }
     hipLaunchKernelGGL(k_mul_final, dim3(1), dim3(kWG), 0, S.stream, (const double *)S.rpart, gr,
                        (const double *)S.cpart, pl.nwg, (double *)S.mulstats);
@@ -2050,16 +2053,17 @@ thetis_status multiplier_impl(thetis_solver &S, bool move_centre, double *out) {
 
 // Algorithmic bytes of one multiplier step (R real, X stored x, V a matrix
 // value when stored): row pass per row: pointer 4, b 8, sense 1, s R, ubar
-// read and written 16, slack ctil R (+ ybar R), per entry column index 4 +
-// V + x X; column pass per structural column: list entry 4, pointer 4, c 8,
-// bound R when stored, ctil R, per entry row index 4 + V + ubar 8 + sense 1;
-// the range over all columns: c 8, x X (+ block id 4, + ybar R).
+// read and written 16, the row record {ubar, clipped ubar} 16, slack ctil R
+// (+ ybar R), per entry column index 4 + V + x X; column pass per structural
+// column: list entry 4, pointer 4, c 8, bound R when stored, ctil R, per
+// entry row index 4 + V + the row record 16; the range over all columns:
+// c 8, x X (+ block id 4, + ybar R).
 double multiplier_traffic(const thetis_solver &S, bool move_centre) {
     const double R = (double)prec_bytes(S.p.precision), X = (double)x_bytes(S.p.precision);
     const double V = S.unit_vals ? 0.0 : R;
     const double m = (double)S.m, n = (double)S.n, nnz = (double)S.nnz;
-    const double rows = m * (4 + 8 + 1 + R + 16 + R + (move_centre ? R : 0)) + nnz * (4 + V + X);
-    const double cols = n * (4 + 4 + 8 + (S.uniform_ub ? 0 : R) + R) + nnz * (4 + V + 8 + 1);
+    const double rows = m * (4 + 8 + 1 + R + 16 + 16 + R + (move_centre ? R : 0)) + nnz * (4 + V + X);
+    const double cols = n * (4 + 4 + 8 + (S.uniform_ub ? 0 : R) + R) + nnz * (4 + V + 16);
     const double all = n * (8 + X + (S.nblocks ? 4 : 0) + (move_centre ? R : 0));
     return rows + cols + all;
 }
