@@ -334,9 +334,10 @@ thetis_status thetis_round(thetis_solver *s, int32_t rule, uint64_t seed, int32_
                            int32_t *sol_host, double *cost, double *aux_host);
 
 /* Feasibility of an integer solution for the original problem: every row
- * of A (VC, MIS: A sol vs b by sense) or every label valid and every
- * terminal on its own label (MC).  sol_host = NULL checks the solution of
- * the last thetis_round on the device. */
+ * of A against b by its sense, every entry 0 or 1 (VC, MIS, COVER and PACK
+ * rules: n entries), or every label in range and every fixed block on its
+ * own label (MC_CKR and the MAP rules: nblocks entries).  sol_host = NULL
+ * checks the solution of the last thetis_round on the device. */
 thetis_status thetis_check_feasible(thetis_solver *s, int32_t rule, const int32_t *sol_host,
                                     int32_t *feasible, int64_t *n_violated);
 
