@@ -170,6 +170,9 @@ static ClassPlan plan_units(const Inst &in, const std::vector<int64_t> &units,
     return cp;
 }
 
+// the sign bit of a packed row index (values +-1, rows below 2^31)
+static int32_t signed_row(int32_t row, double val) { return val < 0 ? (int32_t)((uint32_t)row | 0x80000000u) : row; }
+
 static void pack_blocks(Inst &in) {
     PackedBlocks &pb = in.pb_det;
     pb = PackedBlocks();
@@ -186,8 +189,11 @@ static void pack_blocks(Inst &in) {
                 for (int32_t i = 0; i < in.k; ++i) {
                     const int32_t j = in.bfirst[bl] + i;
                     for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e) {
-                        pb.row.push_back(in.row_idx[e]);
-                        if (!in.unit_vals) pb.val.push_back(in.cval[e]);
+                        if (in.sign_vals) pb.row.push_back(signed_row(in.row_idx[e], in.cval[e]));
+                        else {
+                            pb.row.push_back(in.row_idx[e]);
+                            if (!in.unit_vals) pb.val.push_back(in.cval[e]);
+                        }
                     }
                     pb.ptr.push_back((int32_t)pb.row.size());
                 }
@@ -196,7 +202,7 @@ static void pack_blocks(Inst &in) {
 }
 
 static void pack(const Inst &in, const std::vector<int32_t> &sched,
-                 const std::vector<const ClassPlan *> &plans, Packed &pk) {
+                 const std::vector<const ClassPlan *> &plans, Packed &pk, bool signs) {
     std::vector<int8_t> plain(sched.size(), 0);
     for (const ClassPlan *cp : plans)
         for (const Segment &sg : cp->segs)
@@ -208,14 +214,16 @@ static void pack(const Inst &in, const std::vector<int32_t> &sched,
         pk.ptr[q + 1] = pk.ptr[q] + (plain[q] ? in.col_ptr[j + 1] - in.col_ptr[j] : 0);
     }
     pk.row.resize(pk.ptr.back());
-    if (!in.unit_vals) pk.val.resize(pk.ptr.back());
+    pk.val.clear();
+    const bool vals = !in.unit_vals && !signs;
+    if (vals) pk.val.resize(pk.ptr.back());
     for (size_t q = 0; q < sched.size(); ++q) {
         if (!plain[q]) continue;
         const int32_t j = sched[q];
         int32_t w = pk.ptr[q];
         for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e, ++w) {
-            pk.row[w] = in.row_idx[e];
-            if (!in.unit_vals) pk.val[w] = in.cval[e];
+            pk.row[w] = signs ? signed_row(in.row_idx[e], in.cval[e]) : in.row_idx[e];
+            if (vals) pk.val[w] = in.cval[e];
         }
     }
 }
@@ -347,6 +355,8 @@ static void rounding_facts(Inst &in) {
 thetis_status build_layout(Inst &in) {
     try {
         rounding_facts(in);
+        in.sign_vals = !in.unit_vals;
+        for (size_t e = 0; e < in.val.size() && in.sign_vals; ++e) in.sign_vals = in.val[e] == 1.0 || in.val[e] == -1.0;
         if (in.row_orig.empty()) {
             in.row_orig.resize(in.m);
             for (int64_t i = 0; i < in.m; ++i) in.row_orig[i] = (int32_t)i;
@@ -370,8 +380,8 @@ thetis_status build_layout(Inst &in) {
         pack_blocks(in);
         std::vector<const ClassPlan *> det;
         for (const ClassPlan &cp : in.classes) det.push_back(&cp);
-        pack(in, in.sched, det, in.pk_det);
-        pack(in, in.async_sched, {&in.async_struct, &in.async_slack}, in.pk_async);
+        pack(in, in.sched, det, in.pk_det, in.sign_vals);
+        pack(in, in.async_sched, {&in.async_struct, &in.async_slack}, in.pk_async, false);
         in.planned = true;
     } catch (const std::bad_alloc &) {
         return fail(THETIS_ENOMEM, "host allocation failed while building the layout");

@@ -161,8 +161,23 @@ struct Sched {
     const int32_t *ids;
     const int32_t *ptr;
     const int32_t *row;
-    const R *val;          // null when every entry is 1
+    const R *val;          // null when every entry is 1 or the signs are packed
+    int32_t vmode;         // how entries are stored: see entry_at
 };
+
+// One entry of a packed column.  VM 0: every value 1; 1: values stored
+// beside the row indices; 2: every value +-1, the sign in the row index's
+// top bit (rows stay below 2^31), so the sweep reads no value array.
+template <int VM, class R>
+__device__ __forceinline__ int32_t entry_at(const int32_t *row, const R *val, int64_t e, R &v) {
+    const int32_t raw = row[e];
+    if (VM == 2) {
+        v = raw < 0 ? R(-1) : R(1);
+        return raw & 0x7fffffff;
+    }
+    v = VM == 1 ? val[e] : R(1);
+    return raw;
+}
 
 // Grid layout of one fused launch: the workgroup ranges of the segment
 // kinds in this order (hubs first so their long gathers start early).
@@ -210,11 +225,12 @@ __device__ __forceinline__ typename P::R gradient(const Dev<P> &a, int64_t j, ty
     return g;
 }
 
-template <class P, bool VALS>
+// ||A_j||^2 is the degree when every value is +-1
+template <class P, int VM>
 __device__ __forceinline__ typename P::R curvature(const Dev<P> &a, int64_t j, int32_t d) {
     using R = typename P::R;
     if (a.global_lmax) return a.Lmax;
-    return a.beta * (VALS ? a.norm2[j] : (R)d) + a.rho;
+    return a.beta * (VM == 1 ? a.norm2[j] : (R)d) + a.rho;
 }
 
 // Plain columns on groups of G lanes.  A column of a lane-group range has
@@ -225,7 +241,7 @@ __device__ __forceinline__ typename P::R curvature(const Dev<P> &a, int64_t j, i
 // column are exactly those of a lone column, so the results do not depend
 // on C.
 
-template <class P, bool VALS, int G, int C>
+template <class P, int VM, int G, int C>
 __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typename P::R> &sc,
                                             int64_t first, int64_t count, int64_t lwg) {
     using R = typename P::R;
@@ -244,13 +260,10 @@ __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typenam
             const int64_t q = first + u;
             j[c] = sc.ids[q];
             const int32_t e0 = sc.ptr[q], d = sc.ptr[q + 1] - e0;
-            if (lane < d) {
-                row[c] = sc.row[e0 + lane];
-                if (VALS) v[c] = sc.val[e0 + lane];
-            }
+            if (lane < d) row[c] = entry_at<VM>(sc.row, sc.val, e0 + lane, v[c]);
             y[c] = (R)xval(a.x[j[c]]);
             cj[c] = a.ctil ? a.ctil[j[c]] : (R)a.c[j[c]];
-            L[c] = curvature<P, VALS>(a, j[c], d);
+            L[c] = curvature<P, VM>(a, j[c], d);
             U[c] = col_bound(a, j[c]);
         }
     }
@@ -259,7 +272,7 @@ __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typenam
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         R acc = R(0);
-        if (row[c] >= 0) acc += VALS ? v[c] * rv[c] : rv[c];
+        if (row[c] >= 0) acc += VM ? v[c] * rv[c] : rv[c];
         acc = group_sum<G>(acc);          // every lane of the wave takes part
         if (j[c] < 0) continue;
         R g = cj[c] + a.beta * acc;
@@ -267,7 +280,7 @@ __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typenam
         const R yn = stored_value<P>(coord_step(y[c], g, L[c], a.gamma, U[c]));
         const R d = yn - y[c];
         if (lane == 0) store_x<P>(a.x + j[c], yn);
-        if (d != R(0) && row[c] >= 0) r_add(a.r + row[c], rv[c], VALS ? d * v[c] : d, a.async_mode);
+        if (d != R(0) && row[c] >= 0) r_add(a.r + row[c], rv[c], VM ? d * v[c] : d, a.async_mode);
     }
 }
 
@@ -279,7 +292,7 @@ struct HubTile {
     static constexpr int n = sizeof(typename P::R) == 4 ? 2048 : 1024;
 };
 
-template <class P, bool VALS>
+template <class P, int VM>
 __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename P::R> &sc,
                                           int64_t q, typename P::R *st_r, int32_t *st_row,
                                           typename P::R *red) {
@@ -291,11 +304,11 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
     R acc = R(0);
     for (int32_t base = e0; base < e1; base += 4 * kWG) {
         int32_t rw[4];
-        R rv[4];
+        R rv[4], vv[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int32_t e = base + t * kWG + tid;
-            rw[t] = e < e1 ? sc.row[e] : -1;
+            rw[t] = e < e1 ? entry_at<VM>(sc.row, sc.val, e, vv[t]) : -1;
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) rv[t] = rw[t] >= 0 ? a.r[rw[t]] : R(0);
@@ -305,7 +318,7 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
             if (rw[t] >= 0) {
                 const int32_t o = e - e0;
                 if (o < TILE) { st_r[o] = rv[t]; st_row[o] = rw[t]; }
-                acc += VALS ? sc.val[e] * rv[t] : rv[t];
+                acc += VM ? vv[t] * rv[t] : rv[t];
             }
         }
     }
@@ -318,16 +331,19 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
     __syncthreads();   // red is reused by the next column of a batched loop
     const R y = (R)xval(a.x[j]);
     const R g = gradient(a, j, y, tot);
-    const R yn = stored_value<P>(coord_step(y, g, curvature<P, VALS>(a, j, e1 - e0), a.gamma, col_bound(a, j)));
+    const R yn = stored_value<P>(coord_step(y, g, curvature<P, VM>(a, j, e1 - e0), a.gamma, col_bound(a, j)));
     const R d = yn - y;
     if (tid == 0) store_x<P>(a.x + j, yn);
     if (d != R(0)) {
         for (int32_t e = e0 + tid; e < e1; e += kWG) {
             const int32_t o = e - e0;
-            const R dv = VALS ? d * sc.val[e] : d;
+            R ve = R(1);
+            int32_t re = 0;
+            if (VM || o >= TILE) re = entry_at<VM>(sc.row, sc.val, e, ve);
+            const R dv = VM ? d * ve : d;
             if (o < TILE) r_add(a.r + st_row[o], st_r[o], dv, a.async_mode);
             else {
-                R *p = a.r + sc.row[e];
+                R *p = a.r + re;
                 r_add(p, a.async_mode ? R(0) : *p, dv, a.async_mode);
             }
         }
@@ -343,7 +359,7 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
 // j0 .. j0+k-1; the entries of column i are [cptr[i], cptr[i+1]) of rows /
 // vals (the CSC, or the packed block copy); `valid` is false for the lanes
 // of a block position past the end (they still take part in the shuffles).
-template <class P, bool VALS, int BPW>
+template <class P, int VM, int BPW>
 __device__ __forceinline__ void sweep_block(const Dev<P> &a, bool valid, int32_t blk, int32_t j0, const int32_t *cptr,
                                             const int32_t *rows, const typename P::R *vals, int lpc) {
     using R = typename P::R;
@@ -357,8 +373,9 @@ __device__ __forceinline__ void sweep_block(const Dev<P> &a, bool valid, int32_t
     const int32_t e0 = own ? cptr[ci] : 0, e1 = own ? cptr[ci + 1] : 0;
     R acc = R(0);
     for (int32_t e = e0 + sub; e < e1; e += lpc) {
-        const R rv = a.r[rows[e]];
-        acc += VALS ? vals[e] * rv : rv;
+        R ve;
+        const R rv = a.r[entry_at<VM>(rows, vals, e, ve)];
+        acc += VM ? ve * rv : rv;
     }
     for (int o = lpc / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     const R L = a.global_lmax ? a.Lmax : (valid ? a.LB[blk] : R(0));
@@ -390,8 +407,9 @@ __device__ __forceinline__ void sweep_block(const Dev<P> &a, bool valid, int32_t
     if (own && sub == 0) store_x<P>(a.x + j, w);
     if (own && d != R(0)) {
         for (int32_t e = e0 + sub; e < e1; e += lpc) {
-            R *p = a.r + rows[e];
-            const R dv = VALS ? d * vals[e] : d;
+            R ve;
+            R *p = a.r + entry_at<VM>(rows, vals, e, ve);
+            const R dv = VM ? d * ve : d;
             r_add(p, a.async_mode ? R(0) : *p, dv, a.async_mode);
         }
     }
@@ -402,17 +420,19 @@ template <class R>
 struct BlockPack {
     const int32_t *id, *j0, *ptr, *row;
     const R *val;
+    int32_t vmode;         // entries as in Sched
 };
-template <class P, bool VALS, int BPW>
+template <class P, int VM, int BPW>
 __device__ __forceinline__ void sweep_block_packed(const Dev<P> &a, const BlockPack<typename P::R> &bp, bool valid,
                                                    int64_t t, int lpc) {
     const int32_t blk = valid ? bp.id[t] : 0, j0 = valid ? bp.j0[t] : 0;
-    sweep_block<P, VALS, BPW>(a, valid, blk, j0, bp.ptr + (valid ? t * a.k : 0), bp.row, bp.val, lpc);
+    sweep_block<P, VM, BPW>(a, valid, blk, j0, bp.ptr + (valid ? t * a.k : 0), bp.row, bp.val, lpc);
 }
-template <class P, bool VALS, int BPW>
+// the column copy always stores its values (or none when all are 1)
+template <class P, int VM, int BPW>
 __device__ __forceinline__ void sweep_block_csc(const Dev<P> &a, bool valid, int32_t blk, int lpc) {
     const int32_t j0 = valid ? a.bfirst[blk] : 0;
-    sweep_block<P, VALS, BPW>(a, valid, blk, j0, a.col_ptr + j0, a.row_idx, a.cval, lpc);
+    sweep_block<P, (VM == 0 ? 0 : 1), BPW>(a, valid, blk, j0, a.col_ptr + j0, a.row_idx, a.cval, lpc);
 }
 // blocks per wavefront for block size k (the layout of the sums depends on
 // it, so the solo and batched sweeps take the same)
@@ -437,26 +457,26 @@ __device__ __forceinline__ void sweep_slack(const Dev<P> &a, int64_t i) {
     }
 }
 
-template <class P, bool VALS, int G>
+template <class P, int VM, int G>
 __device__ __forceinline__ void sweep_groups_c(const Dev<P> &a, const Sched<typename P::R> &sc, int cols,
                                                int64_t first, int64_t count, int64_t lwg) {
     switch (cols) {
-        case 1: sweep_group<P, VALS, G, 1>(a, sc, first, count, lwg); break;
-        case 2: sweep_group<P, VALS, G, 2>(a, sc, first, count, lwg); break;
-        case 4: sweep_group<P, VALS, G, 4>(a, sc, first, count, lwg); break;
+        case 1: sweep_group<P, VM, G, 1>(a, sc, first, count, lwg); break;
+        case 2: sweep_group<P, VM, G, 2>(a, sc, first, count, lwg); break;
+        case 4: sweep_group<P, VM, G, 4>(a, sc, first, count, lwg); break;
         default: break;
     }
 }
-template <class P, bool VALS>
+template <class P, int VM>
 __device__ __forceinline__ void sweep_groups(const Dev<P> &a, const Sched<typename P::R> &sc, int lanes, int cols,
                                              int64_t first, int64_t count, int64_t lwg) {
     switch (lanes) {
-        case 2: sweep_groups_c<P, VALS, 2>(a, sc, cols, first, count, lwg); break;
-        case 4: sweep_groups_c<P, VALS, 4>(a, sc, cols, first, count, lwg); break;
-        case 8: sweep_groups_c<P, VALS, 8>(a, sc, cols, first, count, lwg); break;
-        case 16: sweep_groups_c<P, VALS, 16>(a, sc, cols, first, count, lwg); break;
-        case 32: sweep_groups_c<P, VALS, 32>(a, sc, cols, first, count, lwg); break;
-        case 64: sweep_groups_c<P, VALS, 64>(a, sc, cols, first, count, lwg); break;
+        case 2: sweep_groups_c<P, VM, 2>(a, sc, cols, first, count, lwg); break;
+        case 4: sweep_groups_c<P, VM, 4>(a, sc, cols, first, count, lwg); break;
+        case 8: sweep_groups_c<P, VM, 8>(a, sc, cols, first, count, lwg); break;
+        case 16: sweep_groups_c<P, VM, 16>(a, sc, cols, first, count, lwg); break;
+        case 32: sweep_groups_c<P, VM, 32>(a, sc, cols, first, count, lwg); break;
+        case 64: sweep_groups_c<P, VM, 64>(a, sc, cols, first, count, lwg); break;
         default: break;
     }
 }
@@ -465,33 +485,33 @@ __device__ __forceinline__ void sweep_groups(const Dev<P> &a, const Sched<typena
 // logical workgroup L of a column plan.  A lane-group range may run wider
 // groups than its degree bound (the tuner's choice): the extra lanes hold
 // exact zeros, so the butterfly sums -- and every result -- are unchanged.
-template <class P, bool VALS>
+template <class P, int VM>
 __device__ __forceinline__ void sweep_item(const Dev<P> &a, const Sched<typename P::R> &sc, const LaunchPlan &pl,
                                            int64_t L, typename P::R *st_r, int32_t *st_row, typename P::R *red) {
     int64_t local;
     const int p = locate_logical(pl, L, &local);
     const int64_t first = pl.first[p], count = pl.count[p];
     if (grid_kind(p) == SEG_HUB) {
-        if (local < count) sweep_hub<P, VALS>(a, sc, first + local, st_r, st_row, red);
+        if (local < count) sweep_hub<P, VM>(a, sc, first + local, st_r, st_row, red);
         return;
     }
-    sweep_groups<P, VALS>(a, sc, pl.lanes[p], pl.cols[p], first, count, local);
+    sweep_groups<P, VM>(a, sc, pl.lanes[p], pl.cols[p], first, count, local);
 }
 
 // The plain columns of one class (DET) or of a whole epoch (ASYNC) in one
 // launch: hub workgroups first, then the lane-group ranges.
-template <class P, bool VALS>
+template <class P, int VM>
 __global__ __launch_bounds__(kWG) void k_sweep(Dev<P> a, Sched<typename P::R> sc, LaunchPlan pl) {
     using R = typename P::R;
     __shared__ R st_r[HubTile<P>::n];
     __shared__ int32_t st_row[HubTile<P>::n];
     __shared__ R red[kWG / 64];
-    sweep_item<P, VALS>(a, sc, pl, logical_wg(pl, blockIdx.x), st_r, st_row, red);
+    sweep_item<P, VM>(a, sc, pl, logical_wg(pl, blockIdx.x), st_r, st_row, red);
 }
 
 // the simplex blocks of one class: one wavefront per block, from the packed
 // DET copy (list == null: blocks pb_first ..) or by id through the CSC
-template <class P, bool VALS, int BPW>
+template <class P, int VM, int BPW>
 __global__ __launch_bounds__(kWG) void k_sweep_block(Dev<P> a, const int32_t *__restrict__ list,
                                                      BlockPack<typename P::R> bp, int64_t pb_first,
                                                      int64_t count, int32_t lpc) {
@@ -499,8 +519,8 @@ __global__ __launch_bounds__(kWG) void k_sweep_block(Dev<P> a, const int32_t *__
     if (w * BPW >= count) return;        // the whole wavefront leaves together
     const int64_t u = w * BPW + (threadIdx.x & 63) / (64 / BPW);
     const bool valid = u < count;
-    if (list) sweep_block_csc<P, VALS, BPW>(a, valid, valid ? list[u] : 0, lpc);
-    else sweep_block_packed<P, VALS, BPW>(a, bp, valid, pb_first + u, lpc);
+    if (list) sweep_block_csc<P, VM, BPW>(a, valid, valid ? list[u] : 0, lpc);
+    else sweep_block_packed<P, VM, BPW>(a, bp, valid, pb_first + u, lpc);
 }
 
 // the slack class: one lane per inequality row
@@ -1560,6 +1580,7 @@ struct thetis_solver {
     LaunchPlan colterms{};                     // column pass without it (c^T x, prox part of F)
     bool metrics_dual = false;                 // the fresh metrics include the dual bound
     bool edge_shape_cover = false, edge_shape_pack = false;
+    bool sign_vals = false;                    // every matrix value +-1, not all 1 (signs packed)
     bool cover_int = false, set_cover = false, packing = false;   // shapes of the general roundings
     int64_t npw = -1;                                              // pairwise factors (MAP LP)
     double cover_q = 0.0;
@@ -1720,7 +1741,7 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.async_sched = cv.take(4 * std::max<size_t>(in.async_sched.size(), 1));
     S.pk_det_ptr = cv.take(4 * in.pk_det.ptr.size());
     S.pk_det_row = cv.take(4 * std::max<size_t>(in.pk_det.row.size(), 1));
-    S.pk_det_val = in.unit_vals ? nullptr : cv.take(R * std::max<size_t>(in.pk_det.val.size(), 1));
+    S.pk_det_val = in.unit_vals || in.sign_vals ? nullptr : cv.take(R * std::max<size_t>(in.pk_det.val.size(), 1));
     S.pk_async_ptr = cv.take(4 * in.pk_async.ptr.size());
     S.pk_async_row = cv.take(4 * std::max<size_t>(in.pk_async.row.size(), 1));
     S.pk_async_val = in.unit_vals ? nullptr : cv.take(R * std::max<size_t>(in.pk_async.val.size(), 1));
@@ -1728,7 +1749,7 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.pb_j0 = nb ? cv.take(4 * in.pb_det.j0.size()) : nullptr;
     S.pb_ptr = nb ? cv.take(4 * in.pb_det.ptr.size()) : nullptr;
     S.pb_row = nb ? cv.take(4 * std::max<size_t>(in.pb_det.row.size(), 1)) : nullptr;
-    S.pb_val = nb && !in.unit_vals ? cv.take(R * std::max<size_t>(in.pb_det.val.size(), 1)) : nullptr;
+    S.pb_val = nb && !in.unit_vals && !in.sign_vals ? cv.take(R * std::max<size_t>(in.pb_det.val.size(), 1)) : nullptr;
     S.row_lanes = choose_row_lanes(nnz, m);
     // row-pass records (row_wgs) and the rounding's per-thread partials
     S.nwg_rows = std::max<int64_t>(std::max<int64_t>(cdiv(std::max(m, n), kWG), row_wgs(m, S.row_lanes)), 1);
@@ -1798,20 +1819,24 @@ Dev<P> make_dev(const thetis_solver &S) {
     return a;
 }
 
+// how the DET copies store their entries (the ASYNC copy and the column copy
+// keep their values): see entry_at
+int32_t det_vmode(const thetis_solver &S) { return S.unit_vals ? 0 : (S.sign_vals ? 2 : 1); }
+
 template <class P>
 Sched<typename P::R> det_sched(const thetis_solver &S) {
     return {(const int32_t *)S.sched, (const int32_t *)S.pk_det_ptr, (const int32_t *)S.pk_det_row,
-            (const typename P::R *)S.pk_det_val};
+            (const typename P::R *)S.pk_det_val, det_vmode(S)};
 }
 template <class P>
 BlockPack<typename P::R> block_pack(const thetis_solver &S) {
     return {(const int32_t *)S.pb_id, (const int32_t *)S.pb_j0, (const int32_t *)S.pb_ptr, (const int32_t *)S.pb_row,
-            (const typename P::R *)S.pb_val};
+            (const typename P::R *)S.pb_val, det_vmode(S)};
 }
 template <class P>
 Sched<typename P::R> async_sched(const thetis_solver &S) {
     return {(const int32_t *)S.async_sched, (const int32_t *)S.pk_async_ptr, (const int32_t *)S.pk_async_row,
-            (const typename P::R *)S.pk_async_val};
+            (const typename P::R *)S.pk_async_val, S.unit_vals ? 0 : 1};
 }
 
 hipEvent_t next_event(thetis_solver &S, int *idx) {
@@ -1848,33 +1873,40 @@ struct TimedScope {
     }
 };
 
+template <class P, int VM>
+void launch_cols(thetis_solver &S, const Dev<P> &a, const Sched<typename P::R> &sc, const LaunchPlan &pl) {
+    hipLaunchKernelGGL((k_sweep<P, VM>), dim3(pl.nwg), dim3(kWG), 0, S.stream, a, sc, pl);
+}
+
+template <class P, int VM>
+void launch_blocks(thetis_solver &S, const Dev<P> &a, const int32_t *list, const BlockPack<typename P::R> &bp,
+                   int64_t pb_first, int64_t count) {
+    const int bpw = block_bpw(S.k);
+    const int64_t grid = cdiv(count, (int64_t)bpw * (kWG / 64));
+    if (bpw == 4) hipLaunchKernelGGL((k_sweep_block<P, VM, 4>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, pb_first, count, S.lpc);
+    else if (bpw == 2) hipLaunchKernelGGL((k_sweep_block<P, VM, 2>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, pb_first, count, S.lpc);
+    else hipLaunchKernelGGL((k_sweep_block<P, VM, 1>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, pb_first, count, S.lpc);
+}
+
 // the launches of one class: plain columns (hubs + lane groups) in one
 // fused launch, simplex blocks, slacks; all conflict-free among themselves
 template <class P>
 void launch_class(thetis_solver &S, const Dev<P> &a, const ClassLaunch &cl, const Sched<typename P::R> &sc) {
-    const bool vals = !S.unit_vals;
     if (cl.has_cols) {
         TimedScope ts(S, THETIS_K_SWEEP_COLUMNS, cl.bytes_cols);
-        if (vals) hipLaunchKernelGGL((k_sweep<P, true>), dim3(cl.cols.nwg), dim3(kWG), 0, S.stream, a, sc, cl.cols);
-        else hipLaunchKernelGGL((k_sweep<P, false>), dim3(cl.cols.nwg), dim3(kWG), 0, S.stream, a, sc, cl.cols);
+        if (sc.vmode == 2) launch_cols<P, 2>(S, a, sc, cl.cols);
+        else if (sc.vmode == 1) launch_cols<P, 1>(S, a, sc, cl.cols);
+        else launch_cols<P, 0>(S, a, sc, cl.cols);
     }
     if (cl.block_count) {
         TimedScope ts(S, THETIS_K_SWEEP_BLOCK, cl.bytes_block);
+        // the packed DET copy, else by id through the column copy
         const int32_t *list = cl.block_pb >= 0 ? nullptr : sc.ids + cl.block_first;
         const BlockPack<typename P::R> bp = block_pack<P>(S);
-        if (block_bpw(S.k) == 4) {
-            const int64_t grid = cdiv(cl.block_count, 4 * (kWG / 64));
-            if (vals) hipLaunchKernelGGL((k_sweep_block<P, true, 4>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
-            else hipLaunchKernelGGL((k_sweep_block<P, false, 4>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
-        } else if (block_bpw(S.k) == 2) {
-            const int64_t grid = cdiv(cl.block_count, 2 * (kWG / 64));
-            if (vals) hipLaunchKernelGGL((k_sweep_block<P, true, 2>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
-            else hipLaunchKernelGGL((k_sweep_block<P, false, 2>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
-        } else {
-            const int64_t grid = cdiv(cl.block_count, kWG / 64);
-            if (vals) hipLaunchKernelGGL((k_sweep_block<P, true, 1>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
-            else hipLaunchKernelGGL((k_sweep_block<P, false, 1>), dim3(grid), dim3(kWG), 0, S.stream, a, list, bp, cl.block_pb, cl.block_count, S.lpc);
-        }
+        const int vm = list ? (S.unit_vals ? 0 : 1) : bp.vmode;
+        if (vm == 2) launch_blocks<P, 2>(S, a, list, bp, cl.block_pb, cl.block_count);
+        else if (vm == 1) launch_blocks<P, 1>(S, a, list, bp, cl.block_pb, cl.block_count);
+        else launch_blocks<P, 0>(S, a, list, bp, cl.block_pb, cl.block_count);
     }
     if (cl.slack_count) {
         TimedScope ts(S, THETIS_K_SWEEP_SLACK, cl.bytes_slack);
@@ -2359,9 +2391,12 @@ double segment_bytes(const thetis_solver &S, const Inst &in, const std::vector<i
                      const Segment &sg) {
     const double R = (double)prec_bytes(S.p.precision);
     const double X = (double)x_bytes(S.p.precision);
-    const double V = in.unit_vals ? 0.0 : R;
+    // the DET copies of a +-1 matrix carry the signs in the row indices
+    // (no value, no stored ||A_j||^2)
+    const bool noval = in.unit_vals || (in.sign_vals && &sched == &in.sched);
+    const double V = noval ? 0.0 : R;
     const double per_col = 8 + 2 * X + (S.has_ubar ? R : 8.0) + (in.uniform_ub ? 0 : R) +
-                           (in.unit_vals ? 0 : R) + (S.has_ybar ? R : 0);
+                           (noval ? 0 : R) + (S.has_ybar ? R : 0);
     double b = 0.0;
     if (sg.kind == SEG_SLACK) return (double)sg.count * (4 * R + (in.all_rows_slack ? 0.0 : 4.0));
     for (int64_t q = 0; q < sg.count; ++q) {
@@ -2478,6 +2513,7 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     S.max_degree = in.max_col_degree;
     S.edge_shape_cover = edge_shape(in, 1);
     S.edge_shape_pack = edge_shape(in, -1);
+    S.sign_vals = in.sign_vals;
     S.cover_int = in.cover_int;
     S.set_cover = in.set_cover;
     S.packing = in.packing;
@@ -3202,7 +3238,7 @@ struct BsweepWaves {
 
 // bi and bc are only read while the sweep runs (restrict: the sweep's stores
 // cannot change them, so their fields are loaded once, as scalars)
-template <class P, bool VALS>
+template <class P, int VM>
 __global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BInst<P> *__restrict__ bi,
                                                                         const BClass *__restrict__ bc,
                                                                         char *dirs, int32_t count, int64_t chunk_cap,
@@ -3223,7 +3259,7 @@ __global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BIn
         const Sched<R> &sc = I.sc;
         const int64_t wg_cols = C.wg_cols, wg_block = C.wg_block;
         if (local < wg_cols) {
-            sweep_item<P, VALS>(a, sc, C.cols, local, st_r, st_row, red);
+            sweep_item<P, VM>(a, sc, C.cols, local, st_r, st_row, red);
         } else if (local < wg_cols + wg_block) {
             // kBatchBlocks blocks per wavefront
             // kBatchBlocks wavefront positions, each with BPW blocks
@@ -3235,20 +3271,20 @@ __global__ __launch_bounds__(kWG, BsweepWaves<P>::value) void k_bsweep(const BIn
                     const int64_t w = base + b * (kWG / 64);
                     if (w * 4 >= count) break;
                     const int64_t u = w * 4 + (threadIdx.x & 63) / 16;
-                    sweep_block_packed<P, VALS, 4>(a, I.pb, u < count, first + u, lpc);
+                    sweep_block_packed<P, VM, 4>(a, I.pb, u < count, first + u, lpc);
                 }
             } else if (block_bpw(a.k) == 2) {
                 for (int b = 0; b < kBatchBlocks; ++b) {
                     const int64_t w = base + b * (kWG / 64);
                     if (w * 2 >= count) break;
                     const int64_t u = w * 2 + (threadIdx.x & 63) / 32;
-                    sweep_block_packed<P, VALS, 2>(a, I.pb, u < count, first + u, lpc);
+                    sweep_block_packed<P, VM, 2>(a, I.pb, u < count, first + u, lpc);
                 }
             } else {
                 for (int b = 0; b < kBatchBlocks; ++b) {
                     const int64_t w = base + b * (kWG / 64);
                     if (w >= count) break;
-                    sweep_block_packed<P, VALS, 1>(a, I.pb, true, first + w, lpc);
+                    sweep_block_packed<P, VM, 1>(a, I.pb, true, first + w, lpc);
                 }
             }
         } else {
@@ -3411,6 +3447,7 @@ __global__ __launch_bounds__(kWG) void k_bwindow(BInst<P> *bi, int32_t count, in
 struct thetis_batch {
     int32_t count = 0, precision = 0, max_classes = 0;
     bool vals = false;
+    int32_t vmode = -1;                  // how the solvers' DET copies store values (entry_at); -1: none yet
     int64_t bc_capacity = 0;             // BClass records the device table holds
     std::vector<thetis_solver *> solvers;
     hipStream_t stream = nullptr;
@@ -3588,8 +3625,9 @@ void batch_epoch_launches(thetis_batch &B) {
     hipLaunchKernelGGL((k_bplan<P>), dim3(std::max(B.max_classes, 1)), dim3(kWG), 0, B.stream, (const BInst<P> *)bi, bc, n,
                        (const int32_t *)B.alist, (const int32_t *)B.ctl, (const int8_t *)B.order, B.dirs, B.chunk_cap);
     for (int32_t q = 0; q < B.max_classes; ++q) {
-        if (B.vals) hipLaunchKernelGGL((k_bsweep<P, true>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, B.dirs, n, B.chunk_cap, q, B.strided);
-        else hipLaunchKernelGGL((k_bsweep<P, false>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, B.dirs, n, B.chunk_cap, q, B.strided);
+        if (B.vmode == 2) hipLaunchKernelGGL((k_bsweep<P, 2>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, B.dirs, n, B.chunk_cap, q, B.strided);
+        else if (B.vmode == 1) hipLaunchKernelGGL((k_bsweep<P, 1>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, B.dirs, n, B.chunk_cap, q, B.strided);
+        else hipLaunchKernelGGL((k_bsweep<P, 0>), dim3(grid), dim3(kWG), 0, B.stream, bi, bc, B.dirs, n, B.chunk_cap, q, B.strided);
     }
     const int32_t d_rows = kMaxBatchClasses, d_dual = kMaxBatchClasses + 1;
     hipLaunchKernelGGL((k_bepoch<P>), dim3(cdiv(win, kWG)), dim3(kWG), 0, B.stream, bi, (const int32_t *)B.alist,
@@ -3699,10 +3737,13 @@ size_t binst_bytes(int32_t precision) {
 }  // namespace
 
 namespace {
-thetis_status batch_check_solver(const thetis_batch &B, const thetis_solver *S) {
+thetis_status batch_check_solver(thetis_batch &B, const thetis_solver *S) {
     if (S->p.schedule != THETIS_SCHED_DET) return fail(THETIS_EINVAL, "batches run the DET schedule");
     if (S->p.precision != B.precision || (!S->unit_vals) != B.vals)
         return fail(THETIS_EINVAL, "batch solvers must share precision and matrix value kind");
+    const int32_t vm = det_vmode(*S);
+    if (B.vmode >= 0 && B.vmode != vm)
+        return fail(THETIS_EINVAL, "batch solvers must share how their values are stored (all +-1 or general)");
     if (S->nclasses > kMaxBatchClasses) return fail(THETIS_EUNSUPPORTED, "batched instances need at most 64 colour classes");
     return THETIS_OK;
 }
@@ -3750,7 +3791,9 @@ extern "C" thetis_status thetis_batch_create(int32_t capacity, thetis_solver *co
         thetis_status st = batch_check_solver(B, S);
         if (st) { delete Bp; return st; }
         B.solvers[i] = S;
+        B.vmode = det_vmode(*S);
     }
+    if (!B.vals) B.vmode = 0;
     B.stream = (hipStream_t)stream;
     if (!B.stream) {
         // stream capture needs a stream other than the null stream
@@ -3793,6 +3836,10 @@ extern "C" thetis_status thetis_batch_set(thetis_batch *b, int32_t slot, thetis_
         if (st) return st;
     }
     b->solvers[slot] = s;
+    // the value storage the batch's sweeps read: that of its solvers
+    b->vmode = b->vals ? -1 : 0;
+    for (const thetis_solver *o : b->solvers)
+        if (o) { b->vmode = det_vmode(*o); break; }
     return THETIS_OK;
 }
 

@@ -109,6 +109,9 @@ struct Inst {
     std::vector<int32_t> pw_ends, pw_first;
     bool cover_int = false, set_cover = false, packing = false;
     double cover_q = 0.0;
+    // every matrix value is +1 or -1 (and not all +1): the DET copies keep
+    // the sign in the row index's top bit instead of a value array
+    bool sign_vals = false;
     int64_t max_row_len = 0;
     // Internal row order: rows are renumbered so that every row's owner (its
     // first column in DET schedule order) sees its rows contiguously, class
