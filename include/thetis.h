@@ -380,7 +380,8 @@ thetis_status thetis_epoch_traffic(const thetis_solver *s, double *sweep_bytes,
  * the size in *bytes; otherwise *bytes gives the buffer's size (too small:
  * THETIS_EINVAL with the size in *bytes) and receives the bytes written.
  * thetis_solver_load restores such a checkpoint into a solver of the same
- * instance, precision and ubar/prox setting (THETIS_EINVAL otherwise); the
+ * instance (the checkpoint carries a 64-bit digest of the LP and its simplex
+ * blocks), precision and ubar/prox setting (THETIS_EINVAL otherwise); the
  * solve then continues bit for bit as it would have from the save (DET).
  * A reset afterwards still returns to the creation values.  Both
  * synchronise the solver's stream; not while a batch holding the solver

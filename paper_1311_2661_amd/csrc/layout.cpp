@@ -401,6 +401,46 @@ thetis_status thetis::ensure_layout(const thetis_inst *hc) {
 
 // ------------------------------------------------------------------ C ABI
 
+namespace {
+
+// Word-wise multiply-xorshift digest (not cryptographic): it tells one
+// instance from another, so a checkpoint cannot be loaded into a solver of a
+// different LP with the same sizes.
+uint64_t digest_bytes(uint64_t h, const void *p, size_t bytes) {
+    const unsigned char *q = (const unsigned char *)p;
+    auto step = [&h](uint64_t w) {
+        h ^= w;
+        h *= 0x9E3779B97F4A7C15ULL;
+        h ^= h >> 29;
+    };
+    size_t i = 0;
+    for (; i + 8 <= bytes; i += 8) {
+        uint64_t w;
+        std::memcpy(&w, q + i, 8);
+        step(w);
+    }
+    uint64_t tail = 0;
+    std::memcpy(&tail, q + i, bytes - i);
+    step(tail ^ ((uint64_t)bytes << 56));
+    return h;
+}
+
+template <class T>
+uint64_t digest_vec(uint64_t h, const std::vector<T> &v) {
+    const uint64_t len = v.size();
+    h = digest_bytes(h, &len, sizeof(len));
+    return v.empty() ? h : digest_bytes(h, v.data(), v.size() * sizeof(T));
+}
+
+uint64_t block_digest(const Inst &in) {
+    uint64_t h = digest_bytes(in.lp_digest, &in.nblocks, sizeof(in.nblocks));
+    h = digest_bytes(h, &in.k, sizeof(in.k));
+    h = digest_vec(h, in.bfirst);
+    return digest_vec(h, in.fixed);
+}
+
+}  // namespace
+
 extern "C" const char *thetis_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" thetis_status thetis_params_default(thetis_params *p) {
@@ -484,6 +524,14 @@ extern "C" thetis_status thetis_inst_create_csr(int64_t m, int64_t n, int64_t nn
         delete h;
         return fail(THETIS_ENOMEM, "host allocation failed");
     }
+    {
+        const int64_t sizes[3] = {m, n, nnz};
+        uint64_t d = digest_bytes(0x5448455449534C50ULL, sizes, sizeof(sizes));
+        for (const auto *v : {&in.row_ptr, &in.col_idx}) d = digest_vec(d, *v);
+        for (const auto *v : {&in.val, &in.b, &in.c, &in.u}) d = digest_vec(d, *v);
+        in.lp_digest = digest_vec(d, in.sense);
+        in.digest = block_digest(in);
+    }
     in.planned = false;          // built on first use (blocks may still be set)
     *out = h;
     return THETIS_OK;
@@ -518,6 +566,7 @@ extern "C" thetis_status thetis_inst_set_simplex_blocks(thetis_inst *h, int64_t 
     std::lock_guard<std::mutex> lock(h->layout_mu);
     in.nblocks = nblocks; in.k = k;
     in.bfirst.swap(bf); in.fixed.swap(fx); in.col_block.swap(cb);
+    in.digest = block_digest(in);
     in.planned = false;
     return THETIS_OK;
 }

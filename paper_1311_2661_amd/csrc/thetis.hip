@@ -163,6 +163,7 @@ struct Sched {
     const int32_t *row;
     const R *val;          // null when every entry is 1 or the signs are packed
     int32_t vmode;         // how entries are stored: see entry_at
+    int64_t row_off = 0;   // VM 3 (one class's launch): row of entry e = e + row_off
 };
 
 // One entry of a packed column.  VM 0: every value 1; 1: values stored
@@ -177,6 +178,19 @@ __device__ __forceinline__ int32_t entry_at(const int32_t *row, const R *val, in
     }
     v = VM == 1 ? val[e] : R(1);
     return raw;
+}
+
+// VM 3: every value 1 and the rows of a class's entries are consecutive in
+// entry order (a class whose columns own every row they touch, such as the
+// first class in colouring order), so the row is computed, not loaded.
+template <int VM> __host__ __device__ constexpr bool has_vals() { return VM == 1 || VM == 2; }
+template <int VM, class R>
+__device__ __forceinline__ int32_t sched_entry(const Sched<R> &sc, int64_t e, R &v) {
+    if (VM == 3) {
+        v = R(1);
+        return (int32_t)(e + sc.row_off);
+    }
+    return entry_at<VM>(sc.row, sc.val, e, v);
 }
 
 // Grid layout of one fused launch: the workgroup ranges of the segment
@@ -260,7 +274,7 @@ __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typenam
             const int64_t q = first + u;
             j[c] = sc.ids[q];
             const int32_t e0 = sc.ptr[q], d = sc.ptr[q + 1] - e0;
-            if (lane < d) row[c] = entry_at<VM>(sc.row, sc.val, e0 + lane, v[c]);
+            if (lane < d) row[c] = sched_entry<VM>(sc, e0 + lane, v[c]);
             y[c] = (R)xval(a.x[j[c]]);
             cj[c] = a.ctil ? a.ctil[j[c]] : (R)a.c[j[c]];
             L[c] = curvature<P, VM>(a, j[c], d);
@@ -272,7 +286,7 @@ __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typenam
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         R acc = R(0);
-        if (row[c] >= 0) acc += VM ? v[c] * rv[c] : rv[c];
+        if (row[c] >= 0) acc += has_vals<VM>() ? v[c] * rv[c] : rv[c];
         acc = group_sum<G>(acc);          // every lane of the wave takes part
         if (j[c] < 0) continue;
         R g = cj[c] + a.beta * acc;
@@ -280,7 +294,7 @@ __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typenam
         const R yn = stored_value<P>(coord_step(y[c], g, L[c], a.gamma, U[c]));
         const R d = yn - y[c];
         if (lane == 0) store_x<P>(a.x + j[c], yn);
-        if (d != R(0) && row[c] >= 0) r_add(a.r + row[c], rv[c], VM ? d * v[c] : d, a.async_mode);
+        if (d != R(0) && row[c] >= 0) r_add(a.r + row[c], rv[c], has_vals<VM>() ? d * v[c] : d, a.async_mode);
     }
 }
 
@@ -308,7 +322,7 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int32_t e = base + t * kWG + tid;
-            rw[t] = e < e1 ? entry_at<VM>(sc.row, sc.val, e, vv[t]) : -1;
+            rw[t] = e < e1 ? sched_entry<VM>(sc, e, vv[t]) : -1;
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) rv[t] = rw[t] >= 0 ? a.r[rw[t]] : R(0);
@@ -318,7 +332,7 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
             if (rw[t] >= 0) {
                 const int32_t o = e - e0;
                 if (o < TILE) { st_r[o] = rv[t]; st_row[o] = rw[t]; }
-                acc += VM ? vv[t] * rv[t] : rv[t];
+                acc += has_vals<VM>() ? vv[t] * rv[t] : rv[t];
             }
         }
     }
@@ -339,8 +353,8 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
             const int32_t o = e - e0;
             R ve = R(1);
             int32_t re = 0;
-            if (VM || o >= TILE) re = entry_at<VM>(sc.row, sc.val, e, ve);
-            const R dv = VM ? d * ve : d;
+            if (has_vals<VM>() || o >= TILE) re = sched_entry<VM>(sc, e, ve);
+            const R dv = has_vals<VM>() ? d * ve : d;
             if (o < TILE) r_add(a.r + st_row[o], st_r[o], dv, a.async_mode);
             else {
                 R *p = a.r + re;
@@ -1559,6 +1573,8 @@ struct ClassLaunch {
     int64_t block_first = 0, block_count = 0, block_pb = -1;   // block_pb: first packed block (DET)
     int64_t slack_first = 0, slack_count = 0;
     double bytes_cols = 0, bytes_block = 0, bytes_slack = 0;   // algorithmic, per launch
+    bool ident_rows = false;                // DET, unit values: row of entry e is e + row_off
+    int64_t row_off = 0;
 };
 
 struct ClassEvent {
@@ -1597,6 +1613,7 @@ struct thetis_solver {
     std::vector<double> lb_factor;             // a per simplex block (-1 for fixed ones)
     bool has_ybar = false, has_ubar = false;
     double beta0 = 0.0;                        // beta at creation
+    uint64_t inst_digest = 0;                  // the instance's digest (checkpoints)
     bool mul_dirty = false;                    // ubar / ctil / ybar / beta moved since creation
     // device
     hipStream_t stream = nullptr;
@@ -1896,7 +1913,11 @@ void launch_class(thetis_solver &S, const Dev<P> &a, const ClassLaunch &cl, cons
         TimedScope ts(S, THETIS_K_SWEEP_COLUMNS, cl.bytes_cols);
         if (sc.vmode == 2) launch_cols<P, 2>(S, a, sc, cl.cols);
         else if (sc.vmode == 1) launch_cols<P, 1>(S, a, sc, cl.cols);
-        else launch_cols<P, 0>(S, a, sc, cl.cols);
+        else if (cl.ident_rows) {
+            Sched<typename P::R> si = sc;
+            si.row_off = cl.row_off;
+            launch_cols<P, 3>(S, a, si, cl.cols);
+        } else launch_cols<P, 0>(S, a, sc, cl.cols);
     }
     if (cl.block_count) {
         TimedScope ts(S, THETIS_K_SWEEP_BLOCK, cl.bytes_block);
@@ -2417,8 +2438,10 @@ double segment_bytes(const thetis_solver &S, const Inst &in, const std::vector<i
     return b;
 }
 
+// pk: the packed DET copy when the class is one of the DET schedule's (its
+// entries are then checked for consecutive rows), else null
 ClassLaunch make_class_launch(const thetis_solver &S, const Inst &in, const std::vector<int32_t> &sched,
-                              const std::vector<Segment> &segs) {
+                              const std::vector<Segment> &segs, const Packed *pk) {
     ClassLaunch cl;
     std::vector<Segment> cols;
     for (const Segment &sg : segs) {
@@ -2433,6 +2456,18 @@ ClassLaunch make_class_launch(const thetis_solver &S, const Inst &in, const std:
         cl.has_cols = true;
         cl.cols = make_plan(cols, false, 0);
         cl.col_segs = cols;
+    }
+    if (pk && cl.has_cols && det_vmode(S) == 0) {
+        bool ident = true, any = false;
+        int64_t off = 0;
+        for (const Segment &sg : cols)
+            for (int64_t q = sg.first; q < sg.first + sg.count && ident; ++q)
+                for (int64_t e = pk->ptr[q]; e < pk->ptr[q + 1] && ident; ++e) {
+                    if (!any) { off = (int64_t)pk->row[e] - e; any = true; }
+                    ident = (int64_t)pk->row[e] == e + off;
+                }
+        cl.ident_rows = ident && any;
+        cl.row_off = cl.ident_rows ? off : 0;
     }
     return cl;
 }
@@ -2518,13 +2553,14 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
     S.set_cover = in.set_cover;
     S.packing = in.packing;
     S.cover_q = in.cover_q;
+    S.inst_digest = in.digest;
     S.max_row_len = in.max_row_len;
     S.npw = in.npw;
-    for (const ClassPlan &cp : in.classes) S.det.push_back(make_class_launch(S, in, in.sched, cp.segs));
+    for (const ClassPlan &cp : in.classes) S.det.push_back(make_class_launch(S, in, in.sched, cp.segs, &in.pk_det));
     {
         std::vector<Segment> all = in.async_struct.segs;
         all.insert(all.end(), in.async_slack.segs.begin(), in.async_slack.segs.end());
-        S.async_launch = make_class_launch(S, in, in.async_sched, all);
+        S.async_launch = make_class_launch(S, in, in.async_sched, all, nullptr);
     }
     S.updates_per_epoch = 0;
     for (const ClassPlan &cp : in.classes)
@@ -2915,6 +2951,7 @@ struct CheckpointHeader {
     int32_t version, precision, has_ubar, has_ybar;
     int64_t n, m, epoch;
     double beta;
+    uint64_t inst_digest;
 };
 constexpr char kCheckpointMagic[8] = {'T', 'H', 'E', 'T', 'I', 'S', 'C', 'K'};
 
@@ -2955,6 +2992,7 @@ extern "C" thetis_status thetis_solver_save(thetis_solver *s, void *host_buf, si
     h.m = S.m;
     h.epoch = S.epoch;
     h.beta = S.p.beta;
+    h.inst_digest = S.inst_digest;
     char *out = (char *)host_buf;
     std::memcpy(out, &h, sizeof(h));
     size_t off = sizeof(h);
@@ -2976,8 +3014,8 @@ extern "C" thetis_status thetis_solver_load(thetis_solver *s, const void *host_b
     std::memcpy(&h, host_buf, sizeof(h));
     if (std::memcmp(h.magic, kCheckpointMagic, 8) != 0 || h.version != 1)
         return fail(THETIS_EINVAL, "not a checkpoint of this library");
-    if (h.precision != S.p.precision || h.n != S.n || h.m != S.m || h.has_ubar != (int32_t)S.has_ubar ||
-        h.has_ybar != (int32_t)S.has_ybar)
+    if (h.precision != S.p.precision || h.n != S.n || h.m != S.m || h.inst_digest != S.inst_digest ||
+        h.has_ubar != (int32_t)S.has_ubar || h.has_ybar != (int32_t)S.has_ybar)
         return fail(THETIS_EINVAL, "checkpoint of a different instance, precision or parameter set");
     if (!(h.beta > 0.0) || !std::isfinite(h.beta) || h.epoch < 0) return fail(THETIS_EINVAL, "corrupt checkpoint header");
     const std::vector<CheckpointPart> parts = checkpoint_parts(S);

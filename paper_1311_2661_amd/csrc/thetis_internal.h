@@ -117,6 +117,9 @@ struct Inst {
     // first column in DET schedule order) sees its rows contiguously, class
     // by class.  row_orig[r] = caller's index of internal row r.
     std::vector<int32_t> row_orig;
+    // 64-bit digest of the LP as given (sizes, matrix, b, c, u, senses) and
+    // of the simplex blocks; a checkpoint records it and a load compares it
+    uint64_t lp_digest = 0, digest = 0;
 };
 
 thetis_status build_layout(Inst &in);   // CSC, units, colouring, plans

@@ -77,10 +77,12 @@ def test_resume_across_multiplier_steps(prox):
 def test_mismatched_checkpoints_are_refused():
     h1 = T.Instance(I.vc_er(500, 1500, seed=1))
     h2 = T.Instance(I.vc_er(600, 1500, seed=1))
+    h3 = T.Instance(I.vc_er(500, 1500, seed=2))       # same sizes, other edges and costs
     a = T.Solver(h1)
     a.run(3)
     blob = a.save()
-    for other in (T.Solver(h2), T.Solver(h1, precision=T.PREC_FP64), T.Solver(h1, ubar=np.zeros(1500))):
+    for other in (T.Solver(h2), T.Solver(h3), T.Solver(h1, precision=T.PREC_FP64),
+                  T.Solver(h1, ubar=np.zeros(1500))):
         with pytest.raises(T.ThetisError) as e:
             other.load(blob)
         assert e.value.code == T.EINVAL

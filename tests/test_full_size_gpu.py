@@ -9,8 +9,10 @@ process), checked on sampled outputs:
     solve alone, and the FP64 oracle run for the same epochs on a stratified
     sample agrees (F, c^T x within 1e-4 relative, violation within 1e-4).
   * Poisson arrivals at 200/s of mixed requests (1e3..1e6 edges) for one
-    second: nothing fails, every result is feasible, and every sampled
-    served result equals the same request solved alone.
+    second: nothing fails, every result is feasible, every sampled served
+    result equals the same request solved alone, and the FP64 oracle run for
+    the served epochs on a stratified sample agrees (F, c^T x within 1e-4
+    relative).
 """
 import json
 import os
@@ -66,3 +68,6 @@ def test_serving_at_full_rate():
         assert n == m, kind
     n, m = d["served_equals_alone_sampled"].split("/")
     assert n == m and int(m) == 16
+    # the FP64 oracle, run for the served epochs on a size-stratified sample
+    n, m = d["cpu_baseline"]["agrees_with_gpu"].split(" ")[0].split("/")
+    assert n == m and int(m) >= 2
