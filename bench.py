@@ -807,8 +807,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the solve is sized for one MI355X and the "
-              "multi-GPU path is not part of this build (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the solve is sized for one MI355X and the library "
+              "has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "mis_batch":

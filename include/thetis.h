@@ -37,7 +37,7 @@ enum {
     THETIS_EDIVERGED = -4,    /* NaN or Inf in a residual/objective reduction  */
     THETIS_EBUSY = -5,        /* a handle is in use by a batch                 */
     THETIS_EBUDGET = -6,      /* device-memory budget exceeded (serving)       */
-    THETIS_EUNSUPPORTED = -7  /* valid request outside what this build does    */
+    THETIS_EUNSUPPORTED = -7  /* valid request outside what the library does   */
 };
 
 typedef struct thetis_inst thetis_inst;       /* host-side instance, library owned */
