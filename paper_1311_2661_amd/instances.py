@@ -399,6 +399,42 @@ def kcs_packing(n_sets: int, n_elements: int, k: int, seed: int, max_weight: int
                       meta=dict(kind="kcs_packing", k=k, seed=seed))
 
 
+def mixed_lp(seed: int) -> LPInstance:
+    """A seeded sparse LP of mixed shape: ragged rows (a few long ones), a
+    column in more than 64 rows (workgroup path), an empty column, all
+    three senses, finite, zero and infinite upper bounds, and matrix values
+    by seed: all 1, all +-1, or general (the three ways the sweep copies
+    store entries).  Costs are non-negative where the bound is infinite, so
+    the penalty problem is bounded."""
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(80, 400))
+    m = int(rng.integers(200, 400))
+    rows = []
+    for i in range(m):
+        k = int(rng.integers(1, 7)) if rng.random() > 0.03 else int(rng.integers(20, 48))
+        r = set(rng.choice(np.arange(1, n - 1), size=min(k, n - 2), replace=False).tolist())
+        if i % 2 == 0:
+            r.add(0)                     # column 0: m/2 >= 100 entries
+        rows.append(np.array(sorted(r)))  # column n-1 stays empty
+    row_ptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    col = np.concatenate(rows).astype(np.int32)
+    kind = seed % 3
+    if kind == 0:
+        val = None
+    elif kind == 1:
+        val = rng.choice([-1.0, 1.0], size=len(col))
+    else:
+        val = rng.uniform(-2, 3, len(col))
+    sense = rng.choice([-1, 0, 1], size=m).astype(np.int8)
+    u = rng.uniform(0.5, 3, n)
+    u[rng.choice(n, n // 8, replace=False)] = np.inf
+    u[rng.choice(n, 3, replace=False)] = 0.0
+    c = rng.uniform(-1, 2, n)
+    c[np.isinf(u)] = np.abs(c[np.isinf(u)])
+    return LPInstance(m=m, n=n, row_ptr=row_ptr, col_idx=col, val=val, b=rng.uniform(-1, 2, m),
+                      c=c, u=u, sense=sense)
+
+
 def map_lp(n_vars: int, k: int, ends: np.ndarray, unary: np.ndarray, pair: np.ndarray,
            evidence=None, meta=None) -> LPInstance:
     """Local-polytope LP of MAP inference on a pairwise factor graph (the

@@ -62,6 +62,23 @@ def test_batch_equals_alone_fixed_epochs(prec):
         assert_same(sa, sb)
 
 
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_equals_alone_on_mixed_lps(kind, prec):
+    """General LPs of mixed shape (instances.mixed_lp: all three senses,
+    zero / finite / infinite bounds, a column of more than 64 entries), one
+    batch per way of storing the values (all 1, +-1, general)."""
+    say(f"case batch vs alone, mixed LPs kind {kind} {prec}")
+    precision = {"fp32": T.PREC_FP32, "fp64": T.PREC_FP64}[prec]
+    alone, batched = pair([I.mixed_lp(kind + 3 * t) for t in range(4)], beta=4.0, precision=precision)
+    for s in alone:
+        s.run(17)
+    done = T.Batch(batched).run(17)
+    assert list(done) == [17] * len(batched)
+    for sa, sb in zip(alone, batched):
+        assert_same(sa, sb)
+
+
 def test_batch_gap_stop_per_instance():
     say("case batch gap stop")
     insts = [I.vc_er(200, 800, seed=7), I.mis_regular(600, 4, seed=8), I.vc_ba(3000, seed=9)]

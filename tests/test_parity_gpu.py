@@ -168,6 +168,30 @@ def test_fp64_hubs_beyond_the_lds_tile_and_every_lane_group():
     assert np.abs(g.y - o.y).max() < 1e-10
 
 
+@pytest.mark.parametrize("seed", range(9))
+def test_fp64_random_lp_sweep(seed):
+    """Seeded LPs of mixed shape (instances.mixed_lp), with the step rule and the
+    prox term varied by seed: FP64 DET iterates and every reduction against
+    the oracle's replay."""
+    inst = I.mixed_lp(seed)
+    rule = T.STEP_GLOBAL_LMAX if seed % 4 == 3 else T.STEP_PER_COORD
+    prox = seed % 2 == 1
+    yb = np.random.default_rng(seed).uniform(0, 1, inst.n + inst.m) if prox else None
+    say(f"case random LP seed {seed}: m={inst.m} n={inst.n} nnz={len(inst.col_idx)} rule={rule} prox={prox}")
+    g = gpu_solver(inst, beta=4.0, step_rule=rule, prox=prox, ybar=yb, precision=T.PREC_FP64, seed=seed)
+    lp, o = oracle_solver(inst, beta=4.0, step_rule=rule, prox=prox, ybar=yb, seed=seed)
+    for _ in range(2):
+        g.run(6)
+        o.run(6)
+        assert np.abs(g.y - o.y).max() < 1e-9
+    gm, om = g.metrics(), o.metrics()
+    for k in ("F", "lp_value", "linf", "max_viol", "dual_bound"):
+        if np.isfinite(om[k]):
+            assert rel(gm[k], om[k]) < 1e-10, k
+        else:                            # an unbounded column minimum: Phi = -inf on both sides
+            assert gm[k] == om[k], k
+
+
 def test_fp64_multiway_cut_blocks():
     say("case fp64 multiway cut 24x24 k=5")
     inst = I.mc_grid(side=24, k=5, seed=2)
