@@ -8,7 +8,8 @@
  * Conventions for every call:
  *   - Every call returns a thetis_status: THETIS_OK (0) or a negative code.
  *     thetis_last_error() gives a message for the calling thread's last
- *     failure.  No C++ exception crosses this boundary.
+ *     failure.  No C++ exception crosses this boundary: a host allocation
+ *     that fails inside a call returns THETIS_ENOMEM.
  *   - Pointers named *_host are host memory owned by the caller; the library
  *     copies what it needs before the call returns and keeps no reference.
  *   - Device work is enqueued on the solver's stream (a hipStream_t passed

@@ -46,48 +46,53 @@ __global__ __launch_bounds__(256) void k_cal_copy(const float *__restrict__ a, f
 
 }  // namespace
 
+using thetis::exception_status;
 using thetis::fail;
 
 extern "C" thetis_status thetis_calibrate_random(int32_t words_log2, int32_t iters, void *stream,
                                                  double *ms_host) {
-    thetis::clear_error();
-    if (words_log2 < 10 || words_log2 > 28) return fail(THETIS_EINVAL, "words_log2 must be in [10, 28]");
-    if (iters < 1) return fail(THETIS_EINVAL, "iters must be positive");
-    if (!ms_host) return fail(THETIS_EINVAL, "ms_host is NULL");
-    const uint32_t words = 1u << words_log2, mask = words - 1;
-    const hipStream_t st = (hipStream_t)stream;
-    float *buf = nullptr, *dst = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    thetis_status rc = THETIS_OK;
-    auto check = [&](hipError_t e, const char *what) {
-        if (e != hipSuccess && rc == THETIS_OK) rc = fail(THETIS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
-        return rc == THETIS_OK;
-    };
-    if (check(hipMalloc(&buf, sizeof(float) * words), "hipMalloc") &&
-        check(hipMalloc(&dst, sizeof(float) * words), "hipMalloc") &&
-        check(hipMemsetAsync(buf, 0, sizeof(float) * words, st), "hipMemsetAsync") &&
-        check(hipEventCreate(&e0), "hipEventCreate") && check(hipEventCreate(&e1), "hipEventCreate")) {
-        const dim3 grid(words / 256u), block(256);
-        for (int kind = 0; kind < 3 && rc == THETIS_OK; ++kind) {
-            auto launch = [&]() {
-                if (kind == 0) hipLaunchKernelGGL(k_cal_gather, grid, block, 0, st, buf, mask, words_log2, dst);
-                else if (kind == 1) hipLaunchKernelGGL(k_cal_rmw, grid, block, 0, st, buf, mask, words_log2);
-                else hipLaunchKernelGGL(k_cal_copy, grid, block, 0, st, buf, dst, mask);
-            };
-            launch();                                          // warm-up
-            if (!check(hipEventRecord(e0, st), "hipEventRecord")) break;
-            for (int it = 0; it < iters; ++it) launch();
-            if (!check(hipGetLastError(), "kernel launch") || !check(hipEventRecord(e1, st), "hipEventRecord") ||
-                !check(hipEventSynchronize(e1), "hipEventSynchronize"))
-                break;
-            float ms = 0.f;
-            if (!check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) break;
-            ms_host[kind] = (double)ms / iters;
+    try {
+        thetis::clear_error();
+        if (words_log2 < 10 || words_log2 > 28) return fail(THETIS_EINVAL, "words_log2 must be in [10, 28]");
+        if (iters < 1) return fail(THETIS_EINVAL, "iters must be positive");
+        if (!ms_host) return fail(THETIS_EINVAL, "ms_host is NULL");
+        const uint32_t words = 1u << words_log2, mask = words - 1;
+        const hipStream_t st = (hipStream_t)stream;
+        float *buf = nullptr, *dst = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        thetis_status rc = THETIS_OK;
+        auto check = [&](hipError_t e, const char *what) {
+            if (e != hipSuccess && rc == THETIS_OK) rc = fail(THETIS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+            return rc == THETIS_OK;
+        };
+        if (check(hipMalloc(&buf, sizeof(float) * words), "hipMalloc") &&
+            check(hipMalloc(&dst, sizeof(float) * words), "hipMalloc") &&
+            check(hipMemsetAsync(buf, 0, sizeof(float) * words, st), "hipMemsetAsync") &&
+            check(hipEventCreate(&e0), "hipEventCreate") && check(hipEventCreate(&e1), "hipEventCreate")) {
+            const dim3 grid(words / 256u), block(256);
+            for (int kind = 0; kind < 3 && rc == THETIS_OK; ++kind) {
+                auto launch = [&]() {
+                    if (kind == 0) hipLaunchKernelGGL(k_cal_gather, grid, block, 0, st, buf, mask, words_log2, dst);
+                    else if (kind == 1) hipLaunchKernelGGL(k_cal_rmw, grid, block, 0, st, buf, mask, words_log2);
+                    else hipLaunchKernelGGL(k_cal_copy, grid, block, 0, st, buf, dst, mask);
+                };
+                launch();                                          // warm-up
+                if (!check(hipEventRecord(e0, st), "hipEventRecord")) break;
+                for (int it = 0; it < iters; ++it) launch();
+                if (!check(hipGetLastError(), "kernel launch") || !check(hipEventRecord(e1, st), "hipEventRecord") ||
+                    !check(hipEventSynchronize(e1), "hipEventSynchronize"))
+                    break;
+                float ms = 0.f;
+                if (!check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) break;
+                ms_host[kind] = (double)ms / iters;
+            }
         }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (buf) { (void)hipStreamSynchronize(st); (void)hipFree(buf); }
+        if (dst) (void)hipFree(dst);
+        return rc;
+    } catch (...) {
+        return exception_status();
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (buf) { (void)hipStreamSynchronize(st); (void)hipFree(buf); }
-    if (dst) (void)hipFree(dst);
-    return rc;
 }

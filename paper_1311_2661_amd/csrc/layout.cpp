@@ -14,11 +14,33 @@ namespace thetis {
 
 static thread_local std::string g_last_error;
 
-thetis_status fail(thetis_status code, const std::string &msg) {
-    g_last_error = msg;
+// recording the message never throws: if it cannot be stored it is dropped
+thetis_status fail(thetis_status code, const char *msg) noexcept {
+    try {
+        g_last_error.assign(msg);
+    } catch (...) {
+        g_last_error.clear();
+    }
     return code;
 }
+thetis_status fail(thetis_status code, const std::string &msg) noexcept { return fail(code, msg.c_str()); }
 void clear_error() { g_last_error.clear(); }
+
+thetis_status exception_status() {
+    try {
+        throw;
+    } catch (const std::bad_alloc &) {
+        return fail(THETIS_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        try {
+            return fail(THETIS_EINVAL, std::string("host error: ") + e.what());
+        } catch (...) {
+            return fail(THETIS_EINVAL, "host error");
+        }
+    } catch (...) {
+        return fail(THETIS_EINVAL, "unknown host error");
+    }
+}
 
 // ------------------------------------------------------------------ Philox
 void philox_host(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
@@ -444,17 +466,21 @@ uint64_t block_digest(const Inst &in) {
 extern "C" const char *thetis_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" thetis_status thetis_params_default(thetis_params *p) {
-    if (!p) return fail(THETIS_EINVAL, "params is NULL");
-    std::memset(p, 0, sizeof(*p));
-    p->beta = 10.0;
-    p->step_rule = THETIS_STEP_PER_COORD;
-    p->step_scale = 1.0;
-    p->prox = 0;
-    p->schedule = THETIS_SCHED_DET;
-    p->precision = THETIS_PREC_FP32;
-    p->refresh_every = 5;
-    p->seed = 0;
-    return THETIS_OK;
+    try {
+        if (!p) return fail(THETIS_EINVAL, "params is NULL");
+        std::memset(p, 0, sizeof(*p));
+        p->beta = 10.0;
+        p->step_rule = THETIS_STEP_PER_COORD;
+        p->step_scale = 1.0;
+        p->prox = 0;
+        p->schedule = THETIS_SCHED_DET;
+        p->precision = THETIS_PREC_FP32;
+        p->refresh_every = 5;
+        p->seed = 0;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_inst_create_csr(int64_t m, int64_t n, int64_t nnz,
@@ -462,168 +488,192 @@ extern "C" thetis_status thetis_inst_create_csr(int64_t m, int64_t n, int64_t nn
                                                 const double *val, const double *b,
                                                 const double *c, const double *u,
                                                 const int8_t *sense, thetis_inst **out) {
-    clear_error();
-    if (!out) return fail(THETIS_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (m < 0 || n < 0 || nnz < 0) return fail(THETIS_EINVAL, "negative size");
-    if (nnz >= (int64_t(1) << 31) || n + m >= (int64_t(1) << 31))
-        return fail(THETIS_EUNSUPPORTED, "nnz and n+m must stay below 2^31");
-    if (!row_ptr || (nnz && !col_idx) || (m && !b) || (n && !c))
-        return fail(THETIS_EINVAL, "missing array");
-    if (row_ptr[0] != 0 || row_ptr[m] != nnz) return fail(THETIS_EINVAL, "row_ptr must run from 0 to nnz");
-    thetis_inst *h = new (std::nothrow) thetis_inst;
-    if (!h) return fail(THETIS_ENOMEM, "host allocation failed");
-    Inst &in = h->in;
     try {
-        in.m = m; in.n = n; in.nnz = nnz;
-        in.row_ptr.resize(m + 1);
-        for (int64_t i = 0; i <= m; ++i) {
-            if (i && row_ptr[i] < row_ptr[i - 1]) { delete h; return fail(THETIS_EINVAL, "row_ptr decreases"); }
-            in.row_ptr[i] = (int32_t)row_ptr[i];
+        clear_error();
+        if (!out) return fail(THETIS_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (m < 0 || n < 0 || nnz < 0) return fail(THETIS_EINVAL, "negative size");
+        if (nnz >= (int64_t(1) << 31) || n + m >= (int64_t(1) << 31))
+            return fail(THETIS_EUNSUPPORTED, "nnz and n+m must stay below 2^31");
+        if (!row_ptr || (nnz && !col_idx) || (m && !b) || (n && !c))
+            return fail(THETIS_EINVAL, "missing array");
+        if (row_ptr[0] != 0 || row_ptr[m] != nnz) return fail(THETIS_EINVAL, "row_ptr must run from 0 to nnz");
+        thetis_inst *h = new (std::nothrow) thetis_inst;
+        if (!h) return fail(THETIS_ENOMEM, "host allocation failed");
+        Inst &in = h->in;
+        try {
+            in.m = m; in.n = n; in.nnz = nnz;
+            in.row_ptr.resize(m + 1);
+            for (int64_t i = 0; i <= m; ++i) {
+                if (i && row_ptr[i] < row_ptr[i - 1]) { delete h; return fail(THETIS_EINVAL, "row_ptr decreases"); }
+                in.row_ptr[i] = (int32_t)row_ptr[i];
+            }
+            in.col_idx.assign(col_idx, col_idx + nnz);
+            std::vector<int64_t> seen(n, -1);
+            for (int64_t i = 0; i < m; ++i)
+                for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                    const int32_t j = col_idx[e];
+                    if (j < 0 || j >= n) { delete h; return fail(THETIS_EINVAL, "column index out of range"); }
+                    if (seen[j] == i) { delete h; return fail(THETIS_EINVAL, "column repeated inside a row"); }
+                    seen[j] = i;
+                }
+            in.unit_vals = true;
+            if (val) {
+                for (int64_t e = 0; e < nnz; ++e) {
+                    if (!std::isfinite(val[e])) { delete h; return fail(THETIS_EINVAL, "non-finite matrix entry"); }
+                    if (val[e] != 1.0) in.unit_vals = false;
+                }
+                if (!in.unit_vals) in.val.assign(val, val + nnz);
+            }
+            in.b.assign(b, b + m);
+            in.c.assign(c, c + n);
+            for (int64_t i = 0; i < m; ++i)
+                if (!std::isfinite(b[i])) { delete h; return fail(THETIS_EINVAL, "non-finite b"); }
+            for (int64_t j = 0; j < n; ++j)
+                if (!std::isfinite(c[j])) { delete h; return fail(THETIS_EINVAL, "non-finite c"); }
+            in.u.assign(n, INFINITY);
+            if (u) {
+                for (int64_t j = 0; j < n; ++j) {
+                    if (std::isnan(u[j]) || u[j] < 0) { delete h; return fail(THETIS_EINVAL, "upper bounds must be >= 0 or +inf"); }
+                    in.u[j] = u[j];
+                }
+            }
+            in.uniform_ub = true;
+            in.ub_value = n ? in.u[0] : 1.0;
+            for (int64_t j = 1; j < n; ++j) if (in.u[j] != in.ub_value) in.uniform_ub = false;
+            in.sense.assign(m, 0);
+            if (sense)
+                for (int64_t i = 0; i < m; ++i) {
+                    if (sense[i] < -1 || sense[i] > 1) { delete h; return fail(THETIS_EINVAL, "sense must be -1, 0 or +1"); }
+                    in.sense[i] = sense[i];
+                }
+        } catch (const std::bad_alloc &) {
+            delete h;
+            return fail(THETIS_ENOMEM, "host allocation failed");
         }
-        in.col_idx.assign(col_idx, col_idx + nnz);
-        std::vector<int64_t> seen(n, -1);
-        for (int64_t i = 0; i < m; ++i)
-            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-                const int32_t j = col_idx[e];
-                if (j < 0 || j >= n) { delete h; return fail(THETIS_EINVAL, "column index out of range"); }
-                if (seen[j] == i) { delete h; return fail(THETIS_EINVAL, "column repeated inside a row"); }
-                seen[j] = i;
-            }
-        in.unit_vals = true;
-        if (val) {
-            for (int64_t e = 0; e < nnz; ++e) {
-                if (!std::isfinite(val[e])) { delete h; return fail(THETIS_EINVAL, "non-finite matrix entry"); }
-                if (val[e] != 1.0) in.unit_vals = false;
-            }
-            if (!in.unit_vals) in.val.assign(val, val + nnz);
+        {
+            const int64_t sizes[3] = {m, n, nnz};
+            uint64_t d = digest_bytes(0x5448455449534C50ULL, sizes, sizeof(sizes));
+            for (const auto *v : {&in.row_ptr, &in.col_idx}) d = digest_vec(d, *v);
+            for (const auto *v : {&in.val, &in.b, &in.c, &in.u}) d = digest_vec(d, *v);
+            in.lp_digest = digest_vec(d, in.sense);
+            in.digest = block_digest(in);
         }
-        in.b.assign(b, b + m);
-        in.c.assign(c, c + n);
-        for (int64_t i = 0; i < m; ++i)
-            if (!std::isfinite(b[i])) { delete h; return fail(THETIS_EINVAL, "non-finite b"); }
-        for (int64_t j = 0; j < n; ++j)
-            if (!std::isfinite(c[j])) { delete h; return fail(THETIS_EINVAL, "non-finite c"); }
-        in.u.assign(n, INFINITY);
-        if (u) {
-            for (int64_t j = 0; j < n; ++j) {
-                if (std::isnan(u[j]) || u[j] < 0) { delete h; return fail(THETIS_EINVAL, "upper bounds must be >= 0 or +inf"); }
-                in.u[j] = u[j];
-            }
-        }
-        in.uniform_ub = true;
-        in.ub_value = n ? in.u[0] : 1.0;
-        for (int64_t j = 1; j < n; ++j) if (in.u[j] != in.ub_value) in.uniform_ub = false;
-        in.sense.assign(m, 0);
-        if (sense)
-            for (int64_t i = 0; i < m; ++i) {
-                if (sense[i] < -1 || sense[i] > 1) { delete h; return fail(THETIS_EINVAL, "sense must be -1, 0 or +1"); }
-                in.sense[i] = sense[i];
-            }
-    } catch (const std::bad_alloc &) {
-        delete h;
-        return fail(THETIS_ENOMEM, "host allocation failed");
+        in.planned = false;          // built on first use (blocks may still be set)
+        *out = h;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
     }
-    {
-        const int64_t sizes[3] = {m, n, nnz};
-        uint64_t d = digest_bytes(0x5448455449534C50ULL, sizes, sizeof(sizes));
-        for (const auto *v : {&in.row_ptr, &in.col_idx}) d = digest_vec(d, *v);
-        for (const auto *v : {&in.val, &in.b, &in.c, &in.u}) d = digest_vec(d, *v);
-        in.lp_digest = digest_vec(d, in.sense);
-        in.digest = block_digest(in);
-    }
-    in.planned = false;          // built on first use (blocks may still be set)
-    *out = h;
-    return THETIS_OK;
 }
 
 extern "C" thetis_status thetis_inst_set_simplex_blocks(thetis_inst *h, int64_t nblocks, int32_t k,
                                                         const int64_t *first,
                                                         const int32_t *fixed_label) {
-    clear_error();
-    if (!h) return fail(THETIS_EINVAL, "instance is NULL");
-    Inst &in = h->in;
-    if (in.has_solver) return fail(THETIS_EBUSY, "blocks must be set before any solver is created");
-    if (k < 1 || k > 64) return fail(THETIS_EUNSUPPORTED, "block size k must be in [1, 64]");
-    if (nblocks < 0 || (nblocks && !first)) return fail(THETIS_EINVAL, "bad block list");
-    std::vector<int32_t> cb(in.n, -1), bf(nblocks), fx(nblocks, -1);
-    for (int64_t t = 0; t < nblocks; ++t) {
-        if (first[t] < 0 || first[t] + k > in.n) return fail(THETIS_EINVAL, "block out of range");
-        bf[t] = (int32_t)first[t];
-        if (fixed_label) {
-            if (fixed_label[t] < -1 || fixed_label[t] >= k) return fail(THETIS_EINVAL, "fixed label out of range");
-            fx[t] = fixed_label[t];
+    try {
+        clear_error();
+        if (!h) return fail(THETIS_EINVAL, "instance is NULL");
+        Inst &in = h->in;
+        if (in.has_solver) return fail(THETIS_EBUSY, "blocks must be set before any solver is created");
+        if (k < 1 || k > 64) return fail(THETIS_EUNSUPPORTED, "block size k must be in [1, 64]");
+        if (nblocks < 0 || (nblocks && !first)) return fail(THETIS_EINVAL, "bad block list");
+        std::vector<int32_t> cb(in.n, -1), bf(nblocks), fx(nblocks, -1);
+        for (int64_t t = 0; t < nblocks; ++t) {
+            if (first[t] < 0 || first[t] + k > in.n) return fail(THETIS_EINVAL, "block out of range");
+            bf[t] = (int32_t)first[t];
+            if (fixed_label) {
+                if (fixed_label[t] < -1 || fixed_label[t] >= k) return fail(THETIS_EINVAL, "fixed label out of range");
+                fx[t] = fixed_label[t];
+            }
+            for (int32_t i = 0; i < k; ++i) {
+                if (cb[first[t] + i] != -1) return fail(THETIS_EINVAL, "blocks overlap");
+                cb[first[t] + i] = (int32_t)t;
+            }
         }
-        for (int32_t i = 0; i < k; ++i) {
-            if (cb[first[t] + i] != -1) return fail(THETIS_EINVAL, "blocks overlap");
-            cb[first[t] + i] = (int32_t)t;
-        }
+        for (int64_t t = 0; t < nblocks; ++t)
+            for (int32_t i = 0; i < k; ++i)
+                if (in.u[bf[t] + i] < 1.0)
+                    return fail(THETIS_EINVAL, "simplex block columns need an upper bound of at least 1");
+        std::lock_guard<std::mutex> lock(h->layout_mu);
+        in.nblocks = nblocks; in.k = k;
+        in.bfirst.swap(bf); in.fixed.swap(fx); in.col_block.swap(cb);
+        in.digest = block_digest(in);
+        in.planned = false;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
     }
-    for (int64_t t = 0; t < nblocks; ++t)
-        for (int32_t i = 0; i < k; ++i)
-            if (in.u[bf[t] + i] < 1.0)
-                return fail(THETIS_EINVAL, "simplex block columns need an upper bound of at least 1");
-    std::lock_guard<std::mutex> lock(h->layout_mu);
-    in.nblocks = nblocks; in.k = k;
-    in.bfirst.swap(bf); in.fixed.swap(fx); in.col_block.swap(cb);
-    in.digest = block_digest(in);
-    in.planned = false;
-    return THETIS_OK;
 }
 
 extern "C" thetis_status thetis_inst_set_pairwise(thetis_inst *h, int64_t nfactors, const int32_t *ends,
                                                   const int64_t *first_col) {
-    clear_error();
-    if (!h) return fail(THETIS_EINVAL, "instance is NULL");
-    Inst &in = h->in;
-    if (in.has_solver) return fail(THETIS_EBUSY, "pairwise factors must be set before any solver is created");
-    if (in.nblocks <= 0) return fail(THETIS_EINVAL, "pairwise factors need simplex blocks");
-    if (nfactors < 0 || (nfactors && (!ends || !first_col))) return fail(THETIS_EINVAL, "bad factor list");
-    const int64_t kk = (int64_t)in.k * in.k;
-    std::vector<int32_t> pe(2 * nfactors), pf(nfactors);
-    for (int64_t e = 0; e < nfactors; ++e) {
-        for (int q = 0; q < 2; ++q) {
-            if (ends[2 * e + q] < 0 || ends[2 * e + q] >= in.nblocks) return fail(THETIS_EINVAL, "factor end out of range");
-            pe[2 * e + q] = ends[2 * e + q];
+    try {
+        clear_error();
+        if (!h) return fail(THETIS_EINVAL, "instance is NULL");
+        Inst &in = h->in;
+        if (in.has_solver) return fail(THETIS_EBUSY, "pairwise factors must be set before any solver is created");
+        if (in.nblocks <= 0) return fail(THETIS_EINVAL, "pairwise factors need simplex blocks");
+        if (nfactors < 0 || (nfactors && (!ends || !first_col))) return fail(THETIS_EINVAL, "bad factor list");
+        const int64_t kk = (int64_t)in.k * in.k;
+        std::vector<int32_t> pe(2 * nfactors), pf(nfactors);
+        for (int64_t e = 0; e < nfactors; ++e) {
+            for (int q = 0; q < 2; ++q) {
+                if (ends[2 * e + q] < 0 || ends[2 * e + q] >= in.nblocks) return fail(THETIS_EINVAL, "factor end out of range");
+                pe[2 * e + q] = ends[2 * e + q];
+            }
+            if (first_col[e] < 0 || first_col[e] + kk > in.n) return fail(THETIS_EINVAL, "factor columns out of range");
+            for (int64_t j = first_col[e]; j < first_col[e] + kk; ++j)
+                if (in.col_block[j] >= 0) return fail(THETIS_EINVAL, "factor columns inside a simplex block");
+            pf[e] = (int32_t)first_col[e];
         }
-        if (first_col[e] < 0 || first_col[e] + kk > in.n) return fail(THETIS_EINVAL, "factor columns out of range");
-        for (int64_t j = first_col[e]; j < first_col[e] + kk; ++j)
-            if (in.col_block[j] >= 0) return fail(THETIS_EINVAL, "factor columns inside a simplex block");
-        pf[e] = (int32_t)first_col[e];
+        std::lock_guard<std::mutex> lock(h->layout_mu);
+        in.npw = nfactors;
+        in.pw_ends.swap(pe);
+        in.pw_first.swap(pf);
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
     }
-    std::lock_guard<std::mutex> lock(h->layout_mu);
-    in.npw = nfactors;
-    in.pw_ends.swap(pe);
-    in.pw_first.swap(pf);
-    return THETIS_OK;
 }
 
 extern "C" thetis_status thetis_inst_classes(const thetis_inst *h, int32_t *nclasses, int64_t *nunits,
                                              int32_t *class_host) {
-    clear_error();
-    if (!h) return fail(THETIS_EINVAL, "instance is NULL");
-    thetis_status st = ensure_layout(h);
-    if (st) return st;
-    if (nclasses) *nclasses = h->in.nclasses;
-    if (nunits) *nunits = h->in.nunits;
-    if (class_host) std::copy(h->in.ucolour.begin(), h->in.ucolour.end(), class_host);
-    return THETIS_OK;
+    try {
+        clear_error();
+        if (!h) return fail(THETIS_EINVAL, "instance is NULL");
+        thetis_status st = ensure_layout(h);
+        if (st) return st;
+        if (nclasses) *nclasses = h->in.nclasses;
+        if (nunits) *nunits = h->in.nunits;
+        if (class_host) std::copy(h->in.ucolour.begin(), h->in.ucolour.end(), class_host);
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_inst_rounding_shape(const thetis_inst *h, int32_t *flags, double *cover_q) {
-    clear_error();
-    if (!h) return fail(THETIS_EINVAL, "instance is NULL");
-    thetis_status st = ensure_layout(h);
-    if (st) return st;
-    const Inst &in = h->in;
-    if (flags)
-        *flags = (in.cover_int ? THETIS_SHAPE_COVER : 0) | (in.set_cover ? THETIS_SHAPE_SET_COVER : 0) |
-                 (in.packing ? THETIS_SHAPE_PACK : 0);
-    if (cover_q) *cover_q = in.cover_int ? in.cover_q : 0.0;
-    return THETIS_OK;
+    try {
+        clear_error();
+        if (!h) return fail(THETIS_EINVAL, "instance is NULL");
+        thetis_status st = ensure_layout(h);
+        if (st) return st;
+        const Inst &in = h->in;
+        if (flags)
+            *flags = (in.cover_int ? THETIS_SHAPE_COVER : 0) | (in.set_cover ? THETIS_SHAPE_SET_COVER : 0) |
+                     (in.packing ? THETIS_SHAPE_PACK : 0);
+        if (cover_q) *cover_q = in.cover_int ? in.cover_q : 0.0;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_inst_destroy(thetis_inst *h) {
-    delete h;
-    return THETIS_OK;
+    try {
+        delete h;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }

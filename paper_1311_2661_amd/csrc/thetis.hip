@@ -2505,169 +2505,184 @@ thetis_status check_params(const thetis_params *p) {
 
 extern "C" thetis_status thetis_solver_workspace_bytes(const thetis_inst *h, const thetis_params *p,
                                                        size_t *bytes) {
-    clear_error();
-    if (!h || !bytes) return fail(THETIS_EINVAL, "NULL argument");
-    thetis_status st = check_params(p);
-    if (st) return st;
-    st = ensure_layout(h);
-    if (st) return st;
-    thetis_solver S;
-    S.p = *p;
-    S.has_ybar = p->prox && p->ybar;
-    S.has_ubar = p->ubar != nullptr;
-    carve(S, h->in, nullptr, bytes);
-    return THETIS_OK;
+    try {
+        clear_error();
+        if (!h || !bytes) return fail(THETIS_EINVAL, "NULL argument");
+        thetis_status st = check_params(p);
+        if (st) return st;
+        st = ensure_layout(h);
+        if (st) return st;
+        thetis_solver S;
+        S.p = *p;
+        S.has_ybar = p->prox && p->ybar;
+        S.has_ubar = p->ubar != nullptr;
+        carve(S, h->in, nullptr, bytes);
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis_params *p,
                                               void *dev_workspace, size_t ws_bytes, void *stream,
                                               thetis_solver **out) {
-    clear_error();
-    if (!h || !out) return fail(THETIS_EINVAL, "NULL argument");
-    *out = nullptr;
-    thetis_status st = check_params(p);
-    if (st) return st;
-    st = ensure_layout(h);
-    if (st) return st;
-    const Inst &in = h->in;
-    thetis_solver *Sp = new (std::nothrow) thetis_solver;
-    if (!Sp) return fail(THETIS_ENOMEM, "host allocation failed");
-    thetis_solver &S = *Sp;
-    S.p = *p;
-    S.p.ybar = nullptr;
-    S.p.ubar = nullptr;
-    S.beta0 = p->beta;
-    S.rho = p->prox ? 1.0 / p->beta : 0.0;
-    S.has_ybar = p->prox && p->ybar;
-    S.has_ubar = p->ubar != nullptr;
-    S.m = in.m; S.n = in.n; S.nnz = in.nnz; S.nblocks = in.nblocks; S.k = in.k;
-    S.nclasses = in.nclasses; S.nunits = in.nunits;
-    S.unit_vals = in.unit_vals; S.uniform_ub = in.uniform_ub; S.ub_value = in.ub_value;
-    S.all_rows_slack = in.all_rows_slack;
-    while (S.lpc * 2 * std::max(S.k, 1) * block_bpw(S.k) <= 64) S.lpc *= 2;
-    S.max_degree = in.max_col_degree;
-    S.edge_shape_cover = edge_shape(in, 1);
-    S.edge_shape_pack = edge_shape(in, -1);
-    S.sign_vals = in.sign_vals;
-    S.cover_int = in.cover_int;
-    S.set_cover = in.set_cover;
-    S.packing = in.packing;
-    S.cover_q = in.cover_q;
-    S.inst_digest = in.digest;
-    S.max_row_len = in.max_row_len;
-    S.npw = in.npw;
-    for (const ClassPlan &cp : in.classes) S.det.push_back(make_class_launch(S, in, in.sched, cp.segs, &in.pk_det));
-    {
-        std::vector<Segment> all = in.async_struct.segs;
-        all.insert(all.end(), in.async_slack.segs.begin(), in.async_slack.segs.end());
-        S.async_launch = make_class_launch(S, in, in.async_sched, all, nullptr);
-    }
-    S.updates_per_epoch = 0;
-    for (const ClassPlan &cp : in.classes)
-        for (const Segment &sg : cp.segs) S.updates_per_epoch += sg.kind == SEG_BLOCK ? sg.count * in.k : sg.count;
-    S.refresh_bytes = refresh_traffic(S, true);
-    S.refresh_bytes_nodual = refresh_traffic(S, false);
-    S.stream = (hipStream_t)stream;
-    size_t need = 0;
-    carve(S, in, nullptr, &need);
-    if (dev_workspace) {
-        if (ws_bytes < need) { delete Sp; return fail(THETIS_ENOMEM, "workspace smaller than thetis_solver_workspace_bytes"); }
-        S.ws = (char *)dev_workspace;
-        S.ws_bytes = ws_bytes;
-    } else {
-        if (hipMalloc(&S.ws, need) != hipSuccess) { delete Sp; (void)hipGetLastError(); return fail(THETIS_ENOMEM, "hipMalloc of the workspace failed"); }
-        S.own_ws = true;
-        S.ws_bytes = need;
-    }
-    char *base = (char *)(((uintptr_t)S.ws + 255) & ~uintptr_t(255));
-    size_t dummy;
-    carve(S, in, base, &dummy);
-    std::vector<double> norm2, LB;
-    compute_curvatures(S, in, norm2, LB);
+    thetis_solver *Sp = nullptr;   // released by the handler below if the host side throws
+    try {
+        clear_error();
+        if (!h || !out) return fail(THETIS_EINVAL, "NULL argument");
+        *out = nullptr;
+        thetis_status st = check_params(p);
+        if (st) return st;
+        st = ensure_layout(h);
+        if (st) return st;
+        const Inst &in = h->in;
+        Sp = new (std::nothrow) thetis_solver;
+        if (!Sp) return fail(THETIS_ENOMEM, "host allocation failed");
+        thetis_solver &S = *Sp;
+        S.p = *p;
+        S.p.ybar = nullptr;
+        S.p.ubar = nullptr;
+        S.beta0 = p->beta;
+        S.rho = p->prox ? 1.0 / p->beta : 0.0;
+        S.has_ybar = p->prox && p->ybar;
+        S.has_ubar = p->ubar != nullptr;
+        S.m = in.m; S.n = in.n; S.nnz = in.nnz; S.nblocks = in.nblocks; S.k = in.k;
+        S.nclasses = in.nclasses; S.nunits = in.nunits;
+        S.unit_vals = in.unit_vals; S.uniform_ub = in.uniform_ub; S.ub_value = in.ub_value;
+        S.all_rows_slack = in.all_rows_slack;
+        while (S.lpc * 2 * std::max(S.k, 1) * block_bpw(S.k) <= 64) S.lpc *= 2;
+        S.max_degree = in.max_col_degree;
+        S.edge_shape_cover = edge_shape(in, 1);
+        S.edge_shape_pack = edge_shape(in, -1);
+        S.sign_vals = in.sign_vals;
+        S.cover_int = in.cover_int;
+        S.set_cover = in.set_cover;
+        S.packing = in.packing;
+        S.cover_q = in.cover_q;
+        S.inst_digest = in.digest;
+        S.max_row_len = in.max_row_len;
+        S.npw = in.npw;
+        for (const ClassPlan &cp : in.classes) S.det.push_back(make_class_launch(S, in, in.sched, cp.segs, &in.pk_det));
+        {
+            std::vector<Segment> all = in.async_struct.segs;
+            all.insert(all.end(), in.async_slack.segs.begin(), in.async_slack.segs.end());
+            S.async_launch = make_class_launch(S, in, in.async_sched, all, nullptr);
+        }
+        S.updates_per_epoch = 0;
+        for (const ClassPlan &cp : in.classes)
+            for (const Segment &sg : cp.segs) S.updates_per_epoch += sg.kind == SEG_BLOCK ? sg.count * in.k : sg.count;
+        S.refresh_bytes = refresh_traffic(S, true);
+        S.refresh_bytes_nodual = refresh_traffic(S, false);
+        S.stream = (hipStream_t)stream;
+        size_t need = 0;
+        carve(S, in, nullptr, &need);
+        if (dev_workspace) {
+            if (ws_bytes < need) { delete Sp; return fail(THETIS_ENOMEM, "workspace smaller than thetis_solver_workspace_bytes"); }
+            S.ws = (char *)dev_workspace;
+            S.ws_bytes = ws_bytes;
+        } else {
+            if (hipMalloc(&S.ws, need) != hipSuccess) { delete Sp; (void)hipGetLastError(); return fail(THETIS_ENOMEM, "hipMalloc of the workspace failed"); }
+            S.own_ws = true;
+            S.ws_bytes = need;
+        }
+        char *base = (char *)(((uintptr_t)S.ws + 255) & ~uintptr_t(255));
+        size_t dummy;
+        carve(S, in, base, &dummy);
+        std::vector<double> norm2, LB;
+        compute_curvatures(S, in, norm2, LB);
 #define UP(expr) do { thetis_status s_ = (expr); if (s_) { thetis_solver_destroy(Sp); return s_; } } while (0)
-    UP(upload(S, S.col_ptr, in.col_ptr));
-    UP(upload(S, S.row_idx, in.row_idx));
-    UP(upload(S, S.row_ptr, in.row_ptr));
-    UP(upload(S, S.csr_col, in.col_idx));
-    UP(upload(S, S.b, in.b));
-    UP(upload(S, S.sense, in.sense));
-    UP(upload(S, S.c, in.c));
-    UP(upload(S, S.row_orig, in.row_orig));
-    if (in.npw > 0) {
-        UP(upload(S, S.pw_ends, in.pw_ends));
-        UP(upload(S, S.pw_first, in.pw_first));
-    }
-    UP(upload(S, S.sched, in.sched));
-    UP(upload(S, S.async_sched, in.async_sched));
-    UP(upload(S, S.pk_det_ptr, in.pk_det.ptr));
-    UP(upload(S, S.pk_det_row, in.pk_det.row));
-    UP(upload(S, S.pk_async_ptr, in.pk_async.ptr));
-    UP(upload(S, S.pk_async_row, in.pk_async.row));
-    if (!in.unit_vals) {
-        UP(upload_real(S, S.cval, in.cval));
-        UP(upload_real(S, S.csr_val, in.val));
-        UP(upload_real(S, S.norm2, norm2));
-        UP(upload_real(S, S.pk_det_val, in.pk_det.val));
-        UP(upload_real(S, S.pk_async_val, in.pk_async.val));
-    }
-    if (!in.uniform_ub) UP(upload_real(S, S.ub, in.u));
-    if (in.nblocks) {
-        UP(upload(S, S.bfirst, in.bfirst));
-        UP(upload(S, S.pb_id, in.pb_det.id));
-        UP(upload(S, S.pb_j0, in.pb_det.j0));
-        UP(upload(S, S.pb_ptr, in.pb_det.ptr));
-        UP(upload(S, S.pb_row, in.pb_det.row));
-        if (!in.unit_vals) UP(upload_real(S, S.pb_val, in.pb_det.val));
-        UP(upload(S, S.fixed, in.fixed));
-        UP(upload(S, S.col_block, in.col_block));
-        UP(upload_real(S, S.LB, LB));
-    }
-    if (S.has_ybar) {
-        // the slack part of ybar follows the internal row order
-        std::vector<double> yb(in.n + in.m);
-        for (int64_t j = 0; j < in.n; ++j) yb[j] = p->ybar[j];
-        for (int64_t r = 0; r < in.m; ++r) yb[in.n + r] = p->ybar[in.n + in.row_orig[r]];
-        UP(upload_real(S, S.ybar, yb));
-        UP(hip_status(hipMemcpyAsync(S.ybar0, S.ybar, prec_bytes(S.p.precision) * (in.n + in.m),
-                                     hipMemcpyDeviceToDevice, S.stream)));
-    }
-    if (S.has_ubar) {
-        std::vector<double> ub(in.m);
-        for (int64_t r = 0; r < in.m; ++r) ub[r] = p->ubar[in.row_orig[r]];
-        UP(upload(S, S.ubar, ub));
-        // ctil = c - A^T ubar over the structural columns, -sign * ubar_i for slacks
-        std::vector<double> ct(in.n + in.m, 0.0);
-        for (int64_t j = 0; j < in.n; ++j) {
-            double acc = 0.0;
-            for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e)
-                acc += (in.unit_vals ? 1.0 : in.cval[e]) * ub[in.row_idx[e]];
-            ct[j] = in.c[j] - acc;
+        UP(upload(S, S.col_ptr, in.col_ptr));
+        UP(upload(S, S.row_idx, in.row_idx));
+        UP(upload(S, S.row_ptr, in.row_ptr));
+        UP(upload(S, S.csr_col, in.col_idx));
+        UP(upload(S, S.b, in.b));
+        UP(upload(S, S.sense, in.sense));
+        UP(upload(S, S.c, in.c));
+        UP(upload(S, S.row_orig, in.row_orig));
+        if (in.npw > 0) {
+            UP(upload(S, S.pw_ends, in.pw_ends));
+            UP(upload(S, S.pw_first, in.pw_first));
         }
-        for (int64_t i = 0; i < in.m; ++i) {
-            const double sg = in.sense[i] > 0 ? -1.0 : (in.sense[i] < 0 ? 1.0 : 0.0);
-            ct[in.n + i] = -sg * ub[i];
+        UP(upload(S, S.sched, in.sched));
+        UP(upload(S, S.async_sched, in.async_sched));
+        UP(upload(S, S.pk_det_ptr, in.pk_det.ptr));
+        UP(upload(S, S.pk_det_row, in.pk_det.row));
+        UP(upload(S, S.pk_async_ptr, in.pk_async.ptr));
+        UP(upload(S, S.pk_async_row, in.pk_async.row));
+        if (!in.unit_vals) {
+            UP(upload_real(S, S.cval, in.cval));
+            UP(upload_real(S, S.csr_val, in.val));
+            UP(upload_real(S, S.norm2, norm2));
+            UP(upload_real(S, S.pk_det_val, in.pk_det.val));
+            UP(upload_real(S, S.pk_async_val, in.pk_async.val));
         }
-        UP(upload_real(S, S.ctil, ct));
-        UP(hip_status(hipMemcpyAsync(S.ctil0, S.ctil, prec_bytes(S.p.precision) * (in.n + in.m),
-                                     hipMemcpyDeviceToDevice, S.stream)));
-        UP(hip_status(hipMemcpyAsync(S.ubar0, S.ubar, 8 * in.m, hipMemcpyDeviceToDevice, S.stream)));
-    }
-    const_cast<thetis_inst *>(h)->in.has_solver = true;
-    st = DISPATCH(S, reset_impl)(S);
-    if (st) { thetis_solver_destroy(Sp); return st; }
-    if (hipStreamSynchronize(S.stream) != hipSuccess) {
-        thetis_solver_destroy(Sp);
-        return fail(THETIS_EDEVICE, "device error while creating the solver");
-    }
+        if (!in.uniform_ub) UP(upload_real(S, S.ub, in.u));
+        if (in.nblocks) {
+            UP(upload(S, S.bfirst, in.bfirst));
+            UP(upload(S, S.pb_id, in.pb_det.id));
+            UP(upload(S, S.pb_j0, in.pb_det.j0));
+            UP(upload(S, S.pb_ptr, in.pb_det.ptr));
+            UP(upload(S, S.pb_row, in.pb_det.row));
+            if (!in.unit_vals) UP(upload_real(S, S.pb_val, in.pb_det.val));
+            UP(upload(S, S.fixed, in.fixed));
+            UP(upload(S, S.col_block, in.col_block));
+            UP(upload_real(S, S.LB, LB));
+        }
+        if (S.has_ybar) {
+            // the slack part of ybar follows the internal row order
+            std::vector<double> yb(in.n + in.m);
+            for (int64_t j = 0; j < in.n; ++j) yb[j] = p->ybar[j];
+            for (int64_t r = 0; r < in.m; ++r) yb[in.n + r] = p->ybar[in.n + in.row_orig[r]];
+            UP(upload_real(S, S.ybar, yb));
+            UP(hip_status(hipMemcpyAsync(S.ybar0, S.ybar, prec_bytes(S.p.precision) * (in.n + in.m),
+                                         hipMemcpyDeviceToDevice, S.stream)));
+        }
+        if (S.has_ubar) {
+            std::vector<double> ub(in.m);
+            for (int64_t r = 0; r < in.m; ++r) ub[r] = p->ubar[in.row_orig[r]];
+            UP(upload(S, S.ubar, ub));
+            // ctil = c - A^T ubar over the structural columns, -sign * ubar_i for slacks
+            std::vector<double> ct(in.n + in.m, 0.0);
+            for (int64_t j = 0; j < in.n; ++j) {
+                double acc = 0.0;
+                for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e)
+                    acc += (in.unit_vals ? 1.0 : in.cval[e]) * ub[in.row_idx[e]];
+                ct[j] = in.c[j] - acc;
+            }
+            for (int64_t i = 0; i < in.m; ++i) {
+                const double sg = in.sense[i] > 0 ? -1.0 : (in.sense[i] < 0 ? 1.0 : 0.0);
+                ct[in.n + i] = -sg * ub[i];
+            }
+            UP(upload_real(S, S.ctil, ct));
+            UP(hip_status(hipMemcpyAsync(S.ctil0, S.ctil, prec_bytes(S.p.precision) * (in.n + in.m),
+                                         hipMemcpyDeviceToDevice, S.stream)));
+            UP(hip_status(hipMemcpyAsync(S.ubar0, S.ubar, 8 * in.m, hipMemcpyDeviceToDevice, S.stream)));
+        }
+        const_cast<thetis_inst *>(h)->in.has_solver = true;
+        st = DISPATCH(S, reset_impl)(S);
+        if (st) { thetis_solver_destroy(Sp); return st; }
+        if (hipStreamSynchronize(S.stream) != hipSuccess) {
+            thetis_solver_destroy(Sp);
+            return fail(THETIS_EDEVICE, "device error while creating the solver");
+        }
 #undef UP
-    *out = Sp;
-    return THETIS_OK;
+        *out = Sp;
+        return THETIS_OK;
+    } catch (...) {
+        const thetis_status st = exception_status();
+        if (Sp) thetis_solver_destroy(Sp);
+        return st;
+    }
 }
 
 extern "C" thetis_status thetis_solver_reset(thetis_solver *s) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    return DISPATCH(*s, reset_impl)(*s);
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        return DISPATCH(*s, reset_impl)(*s);
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 namespace {
@@ -2692,68 +2707,80 @@ thetis_status apply_beta(thetis_solver &S, double beta) {
 }  // namespace
 
 extern "C" thetis_status thetis_set_beta(thetis_solver *s, double beta) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    if (!(beta > 0.0) || !std::isfinite(beta)) return fail(THETIS_EINVAL, "beta must be positive");
-    s->beta0 = beta;          // the beta a reset returns to
-    return apply_beta(*s, beta);
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        if (!(beta > 0.0) || !std::isfinite(beta)) return fail(THETIS_EINVAL, "beta must be positive");
+        s->beta0 = beta;          // the beta a reset returns to
+        return apply_beta(*s, beta);
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_multiplier_step(thetis_solver *s, int32_t move_centre, double new_beta,
                                                 thetis_mul_stats *stats_host) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    thetis_solver &S = *s;
-    if (!S.has_ubar) return fail(THETIS_EUNSUPPORTED, "the solver was created without ubar");
-    if (move_centre && !S.has_ybar) return fail(THETIS_EUNSUPPORTED, "moving the prox centre needs prox on and a ybar");
-    if (!(new_beta == 0.0 || (new_beta > 0.0 && std::isfinite(new_beta))))
-        return fail(THETIS_EINVAL, "new_beta must be 0 (keep) or positive");
-    double out[5] = {0, 0, 0, 0, 0};
-    thetis_status st = DISPATCH(S, multiplier_impl)(S, move_centre != 0, out);
-    if (st) return st;
-    if (new_beta > 0.0) {
-        st = apply_beta(S, new_beta);
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        thetis_solver &S = *s;
+        if (!S.has_ubar) return fail(THETIS_EUNSUPPORTED, "the solver was created without ubar");
+        if (move_centre && !S.has_ybar) return fail(THETIS_EUNSUPPORTED, "moving the prox centre needs prox on and a ybar");
+        if (!(new_beta == 0.0 || (new_beta > 0.0 && std::isfinite(new_beta))))
+            return fail(THETIS_EINVAL, "new_beta must be 0 (keep) or positive");
+        double out[5] = {0, 0, 0, 0, 0};
+        thetis_status st = DISPATCH(S, multiplier_impl)(S, move_centre != 0, out);
         if (st) return st;
+        if (new_beta > 0.0) {
+            st = apply_beta(S, new_beta);
+            if (st) return st;
+        }
+        if (stats_host) {
+            stats_host->lp_value = out[0];
+            stats_host->linf = out[1];
+            stats_host->lp_dual = out[2];
+            stats_host->lp_gap = out[3];
+            stats_host->device_ms = out[4];
+            stats_host->alg_bytes = multiplier_traffic(S, move_centre != 0);
+        }
+        if (!std::isfinite(out[0]) || std::isnan(out[2])) return fail(THETIS_EDIVERGED, "NaN or Inf in the multiplier step");
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
     }
-    if (stats_host) {
-        stats_host->lp_value = out[0];
-        stats_host->linf = out[1];
-        stats_host->lp_dual = out[2];
-        stats_host->lp_gap = out[3];
-        stats_host->device_ms = out[4];
-        stats_host->alg_bytes = multiplier_traffic(S, move_centre != 0);
-    }
-    if (!std::isfinite(out[0]) || std::isnan(out[2])) return fail(THETIS_EDIVERGED, "NaN or Inf in the multiplier step");
-    return THETIS_OK;
 }
 
 extern "C" thetis_status thetis_get_multipliers(thetis_solver *s, double *ubar_host, double *ybar_host) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    thetis_solver &S = *s;
-    if (ubar_host && !S.has_ubar) return fail(THETIS_EUNSUPPORTED, "the solver was created without ubar");
-    if (ybar_host && !S.has_ybar) return fail(THETIS_EUNSUPPORTED, "the solver has no prox centre");
-    const int64_t n = S.n, m = S.m;
-    std::vector<int32_t> ro(m);
-    std::vector<double> u(ubar_host ? m : 0);
-    const size_t R = prec_bytes(S.p.precision);
-    std::vector<char> yb(ybar_host ? R * (n + m) : 0);
-    if (m) HIP_TRY(hipMemcpyAsync(ro.data(), S.row_orig, 4 * m, hipMemcpyDeviceToHost, S.stream));
-    if (ubar_host && m) HIP_TRY(hipMemcpyAsync(u.data(), S.ubar, 8 * m, hipMemcpyDeviceToHost, S.stream));
-    if (ybar_host && n + m) HIP_TRY(hipMemcpyAsync(yb.data(), S.ybar, yb.size(), hipMemcpyDeviceToHost, S.stream));
-    HIP_TRY(hipStreamSynchronize(S.stream));
-    // rows are stored in the layout's order; hand them back in the caller's
-    if (ubar_host)
-        for (int64_t r = 0; r < m; ++r) ubar_host[ro[r]] = u[r];
-    if (ybar_host) {
-        auto get = [&](int64_t j) {
-            if (R == 8) { double v; std::memcpy(&v, yb.data() + 8 * j, 8); return v; }
-            float v; std::memcpy(&v, yb.data() + 4 * j, 4); return (double)v;
-        };
-        for (int64_t j = 0; j < n; ++j) ybar_host[j] = get(j);
-        for (int64_t r = 0; r < m; ++r) ybar_host[n + ro[r]] = get(n + r);
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        thetis_solver &S = *s;
+        if (ubar_host && !S.has_ubar) return fail(THETIS_EUNSUPPORTED, "the solver was created without ubar");
+        if (ybar_host && !S.has_ybar) return fail(THETIS_EUNSUPPORTED, "the solver has no prox centre");
+        const int64_t n = S.n, m = S.m;
+        std::vector<int32_t> ro(m);
+        std::vector<double> u(ubar_host ? m : 0);
+        const size_t R = prec_bytes(S.p.precision);
+        std::vector<char> yb(ybar_host ? R * (n + m) : 0);
+        if (m) HIP_TRY(hipMemcpyAsync(ro.data(), S.row_orig, 4 * m, hipMemcpyDeviceToHost, S.stream));
+        if (ubar_host && m) HIP_TRY(hipMemcpyAsync(u.data(), S.ubar, 8 * m, hipMemcpyDeviceToHost, S.stream));
+        if (ybar_host && n + m) HIP_TRY(hipMemcpyAsync(yb.data(), S.ybar, yb.size(), hipMemcpyDeviceToHost, S.stream));
+        HIP_TRY(hipStreamSynchronize(S.stream));
+        // rows are stored in the layout's order; hand them back in the caller's
+        if (ubar_host)
+            for (int64_t r = 0; r < m; ++r) ubar_host[ro[r]] = u[r];
+        if (ybar_host) {
+            auto get = [&](int64_t j) {
+                if (R == 8) { double v; std::memcpy(&v, yb.data() + 8 * j, 8); return v; }
+                float v; std::memcpy(&v, yb.data() + 4 * j, 4); return (double)v;
+            };
+            for (int64_t j = 0; j < n; ++j) ybar_host[j] = get(j);
+            for (int64_t r = 0; r < m; ++r) ybar_host[n + ro[r]] = get(n + r);
+        }
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
     }
-    return THETIS_OK;
 }
 
 extern "C" thetis_status thetis_run_multipliers(thetis_solver *s, int32_t max_outer, int32_t inner_epochs,
@@ -2761,185 +2788,241 @@ extern "C" thetis_status thetis_run_multipliers(thetis_solver *s, int32_t max_ou
                                                 double feas_tol, double lp_gap_tol, int32_t move_centre,
                                                 int32_t *outer_done, int64_t *epochs_done,
                                                 thetis_mul_stats *last_host) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    if (max_outer < 0 || inner_epochs < 0) return fail(THETIS_EINVAL, "max_outer and inner_epochs must be >= 0");
-    if (beta_growth > 1.0 && !(beta_max > 0.0 && std::isfinite(beta_max)))
-        return fail(THETIS_EINVAL, "beta_max must be positive and finite when beta grows");
-    if (!(beta_growth >= 0.0) || !std::isfinite(beta_growth)) return fail(THETIS_EINVAL, "beta_growth must be finite and >= 0");
-    int32_t outer = 0;
-    int64_t epochs = 0;
-    thetis_mul_stats st_last{};
-    thetis_status st = THETIS_OK;
-    for (; outer < max_outer; ) {
-        int32_t done = 0;
-        st = thetis_run_epochs(s, inner_epochs, inner_gap_tol, &done);
-        epochs += done;
-        if (st) break;
-        const double nb = beta_growth > 1.0 ? std::min(s->p.beta * beta_growth, std::max(beta_max, s->p.beta)) : 0.0;
-        st = thetis_multiplier_step(s, move_centre, nb, &st_last);
-        ++outer;
-        if (st) break;
-        if (st_last.linf <= feas_tol && st_last.lp_gap <= lp_gap_tol) break;
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        if (max_outer < 0 || inner_epochs < 0) return fail(THETIS_EINVAL, "max_outer and inner_epochs must be >= 0");
+        if (beta_growth > 1.0 && !(beta_max > 0.0 && std::isfinite(beta_max)))
+            return fail(THETIS_EINVAL, "beta_max must be positive and finite when beta grows");
+        if (!(beta_growth >= 0.0) || !std::isfinite(beta_growth)) return fail(THETIS_EINVAL, "beta_growth must be finite and >= 0");
+        int32_t outer = 0;
+        int64_t epochs = 0;
+        thetis_mul_stats st_last{};
+        thetis_status st = THETIS_OK;
+        for (; outer < max_outer; ) {
+            int32_t done = 0;
+            st = thetis_run_epochs(s, inner_epochs, inner_gap_tol, &done);
+            epochs += done;
+            if (st) break;
+            const double nb = beta_growth > 1.0 ? std::min(s->p.beta * beta_growth, std::max(beta_max, s->p.beta)) : 0.0;
+            st = thetis_multiplier_step(s, move_centre, nb, &st_last);
+            ++outer;
+            if (st) break;
+            if (st_last.linf <= feas_tol && st_last.lp_gap <= lp_gap_tol) break;
+        }
+        if (outer_done) *outer_done = outer;
+        if (epochs_done) *epochs_done = epochs;
+        if (last_host) *last_host = st_last;
+        return st;
+    } catch (...) {
+        return exception_status();
     }
-    if (outer_done) *outer_done = outer;
-    if (epochs_done) *epochs_done = epochs;
-    if (last_host) *last_host = st_last;
-    return st;
 }
 
 extern "C" thetis_status thetis_set_step_rule(thetis_solver *s, int32_t rule, double scale) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    if (rule != THETIS_STEP_PER_COORD && rule != THETIS_STEP_GLOBAL_LMAX) return fail(THETIS_EINVAL, "unknown step rule");
-    if (!(scale > 0.0 && scale <= 1.0)) return fail(THETIS_EINVAL, "step_scale must be in (0, 1]");
-    s->p.step_rule = rule;
-    s->p.step_scale = scale;
-    return THETIS_OK;
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        if (rule != THETIS_STEP_PER_COORD && rule != THETIS_STEP_GLOBAL_LMAX) return fail(THETIS_EINVAL, "unknown step rule");
+        if (!(scale > 0.0 && scale <= 1.0)) return fail(THETIS_EINVAL, "step_scale must be in (0, 1]");
+        s->p.step_rule = rule;
+        s->p.step_scale = scale;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_run_epochs(thetis_solver *s, int32_t max_epochs, double gap_tol,
                                            int32_t *epochs_done) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    if (max_epochs < 0) return fail(THETIS_EINVAL, "max_epochs < 0");
-    s->have_round = false;
-    return DISPATCH(*s, run_epochs_impl)(*s, max_epochs, gap_tol, epochs_done);
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        if (max_epochs < 0) return fail(THETIS_EINVAL, "max_epochs < 0");
+        s->have_round = false;
+        return DISPATCH(*s, run_epochs_impl)(*s, max_epochs, gap_tol, epochs_done);
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_solver_autotune(thetis_solver *s, int32_t epochs_per_candidate, int32_t *choice_host) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    if (epochs_per_candidate < 1) return fail(THETIS_EINVAL, "epochs_per_candidate < 1");
-    thetis_solver &S = *s;
-    const int32_t nc = (int32_t)S.det.size();
-    if (S.p.schedule != THETIS_SCHED_DET) {
-        if (choice_host) for (int32_t c = 0; c < nc; ++c) choice_host[c] = S.det[c].group_cols;
-        return THETIS_OK;
-    }
-    const int cands[3] = {1, 2, 4};
-    std::vector<double> ms(3 * (size_t)std::max(nc, 1), 0.0);
-    std::vector<ClassEvent> evs;
-    // one untimed epoch first, so that no candidate runs on cold caches
-    thetis_status st = DISPATCH(S, run_epochs_impl)(S, 1, 0.0, nullptr);
-    for (int ci = 0; ci < 3 && st == THETIS_OK; ++ci) {
-        for (ClassLaunch &cl : S.det)
-            if (cl.has_cols) { cl.group_cols = cands[ci]; cl.cols = make_plan(cl.col_segs, false, 0, 1, cands[ci]); }
-        evs.clear();
-        S.class_events = &evs;
-        st = DISPATCH(S, run_epochs_impl)(S, epochs_per_candidate, 0.0, nullptr);
-        S.class_events = nullptr;
-        if (st == THETIS_OK && hipStreamSynchronize(S.stream) != hipSuccess) st = fail(THETIS_EDEVICE, "tuner sync failed");
-        for (const ClassEvent &ev : evs) {
-            float t = 0.f;
-            if (st == THETIS_OK && hipEventElapsedTime(&t, ev.e0, ev.e1) == hipSuccess) ms[3 * ev.cls + ci] += t;
-            (void)hipEventDestroy(ev.e0);
-            (void)hipEventDestroy(ev.e1);
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        if (epochs_per_candidate < 1) return fail(THETIS_EINVAL, "epochs_per_candidate < 1");
+        thetis_solver &S = *s;
+        const int32_t nc = (int32_t)S.det.size();
+        if (S.p.schedule != THETIS_SCHED_DET) {
+            if (choice_host) for (int32_t c = 0; c < nc; ++c) choice_host[c] = S.det[c].group_cols;
+            return THETIS_OK;
         }
+        const int cands[3] = {1, 2, 4};
+        std::vector<double> ms(3 * (size_t)std::max(nc, 1), 0.0);
+        std::vector<ClassEvent> evs;
+        // one untimed epoch first, so that no candidate runs on cold caches
+        thetis_status st = DISPATCH(S, run_epochs_impl)(S, 1, 0.0, nullptr);
+        for (int ci = 0; ci < 3 && st == THETIS_OK; ++ci) {
+            for (ClassLaunch &cl : S.det)
+                if (cl.has_cols) { cl.group_cols = cands[ci]; cl.cols = make_plan(cl.col_segs, false, 0, 1, cands[ci]); }
+            evs.clear();
+            S.class_events = &evs;
+            st = DISPATCH(S, run_epochs_impl)(S, epochs_per_candidate, 0.0, nullptr);
+            S.class_events = nullptr;
+            if (st == THETIS_OK && hipStreamSynchronize(S.stream) != hipSuccess) st = fail(THETIS_EDEVICE, "tuner sync failed");
+            for (const ClassEvent &ev : evs) {
+                float t = 0.f;
+                if (st == THETIS_OK && hipEventElapsedTime(&t, ev.e0, ev.e1) == hipSuccess) ms[3 * ev.cls + ci] += t;
+                (void)hipEventDestroy(ev.e0);
+                (void)hipEventDestroy(ev.e1);
+            }
+        }
+        for (int32_t c = 0; c < nc; ++c) {
+            ClassLaunch &cl = S.det[c];
+            // one column per group unless another shape is clearly faster
+            int best = 0;
+            for (int ci = 1; ci < 3; ++ci) if (ms[3 * c + ci] < 0.97 * ms[3 * c + best]) best = ci;
+            if (cl.has_cols) { cl.group_cols = cands[best]; cl.cols = make_plan(cl.col_segs, false, 0, 1, cands[best]); }
+            if (choice_host) choice_host[c] = cl.group_cols;
+        }
+        s->have_round = false;
+        return st;
+    } catch (...) {
+        return exception_status();
     }
-    for (int32_t c = 0; c < nc; ++c) {
-        ClassLaunch &cl = S.det[c];
-        // one column per group unless another shape is clearly faster
-        int best = 0;
-        for (int ci = 1; ci < 3; ++ci) if (ms[3 * c + ci] < 0.97 * ms[3 * c + best]) best = ci;
-        if (cl.has_cols) { cl.group_cols = cands[best]; cl.cols = make_plan(cl.col_segs, false, 0, 1, cands[best]); }
-        if (choice_host) choice_host[c] = cl.group_cols;
-    }
-    s->have_round = false;
-    return st;
 }
 
 extern "C" thetis_status thetis_residual(thetis_solver *s, double *linf, double *l2, double *viol) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    thetis_status st = DISPATCH(*s, read_metrics)(*s);
-    if (st) return st;
-    if (linf) *linf = s->mt[MT_LINF];
-    if (l2) *l2 = s->mt[MT_L2];
-    if (viol) *viol = s->mt[MT_VIOL];
-    return THETIS_OK;
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        thetis_status st = DISPATCH(*s, read_metrics)(*s);
+        if (st) return st;
+        if (linf) *linf = s->mt[MT_LINF];
+        if (l2) *l2 = s->mt[MT_L2];
+        if (viol) *viol = s->mt[MT_VIOL];
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_objective(thetis_solver *s, double *lp_value, double *penalty,
                                           double *dual_bound) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    thetis_status st = DISPATCH(*s, read_metrics)(*s);
-    if (st) return st;
-    if (lp_value) *lp_value = s->mt[MT_CX];
-    if (penalty) *penalty = s->mt[MT_F];
-    if (dual_bound) *dual_bound = s->mt[MT_PHI];
-    return THETIS_OK;
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        thetis_status st = DISPATCH(*s, read_metrics)(*s);
+        if (st) return st;
+        if (lp_value) *lp_value = s->mt[MT_CX];
+        if (penalty) *penalty = s->mt[MT_F];
+        if (dual_bound) *dual_bound = s->mt[MT_PHI];
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_get_x(thetis_solver *s, double *x, double *sl) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    return DISPATCH(*s, get_x_impl)(*s, x, sl);
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        return DISPATCH(*s, get_x_impl)(*s, x, sl);
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_set_y(thetis_solver *s, const double *y) {
-    clear_error();
-    if (!s || !y) return fail(THETIS_EINVAL, "NULL argument");
-    for (int64_t j = 0; j < s->n + s->m; ++j)
-        if (!std::isfinite(y[j])) return fail(THETIS_EINVAL, "non-finite y");
-    return DISPATCH(*s, set_y_impl)(*s, y);
+    try {
+        clear_error();
+        if (!s || !y) return fail(THETIS_EINVAL, "NULL argument");
+        for (int64_t j = 0; j < s->n + s->m; ++j)
+            if (!std::isfinite(y[j])) return fail(THETIS_EINVAL, "non-finite y");
+        return DISPATCH(*s, set_y_impl)(*s, y);
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_epoch(const thetis_solver *s, int64_t *epoch) {
-    clear_error();
-    if (!s || !epoch) return fail(THETIS_EINVAL, "NULL argument");
-    *epoch = s->epoch;
-    return THETIS_OK;
+    try {
+        clear_error();
+        if (!s || !epoch) return fail(THETIS_EINVAL, "NULL argument");
+        *epoch = s->epoch;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_round(thetis_solver *s, int32_t rule, uint64_t seed, int32_t reps,
                                       int32_t *sol_host, double *cost, double *aux) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    return DISPATCH(*s, round_impl)(*s, rule, seed, reps, sol_host, cost, aux);
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        return DISPATCH(*s, round_impl)(*s, rule, seed, reps, sol_host, cost, aux);
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_check_feasible(thetis_solver *s, int32_t rule, const int32_t *sol_host,
                                                int32_t *feasible, int64_t *n_violated) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    return DISPATCH(*s, check_impl)(*s, rule, sol_host, feasible, n_violated);
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        return DISPATCH(*s, check_impl)(*s, rule, sol_host, feasible, n_violated);
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_set_timing(thetis_solver *s, int32_t enable) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    if (enable < 0) return fail(THETIS_EINVAL, "timing period must be >= 0");
-    s->timing = enable;
-    return THETIS_OK;
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        if (enable < 0) return fail(THETIS_EINVAL, "timing period must be >= 0");
+        s->timing = enable;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_get_timing(const thetis_solver *s, int32_t kind, double *ms,
                                            int64_t *launches, double *alg_bytes) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    if (kind < 0 || kind >= THETIS_K_NKINDS) return fail(THETIS_EINVAL, "unknown kernel group");
-    if (ms) *ms = s->ms[kind];
-    if (launches) *launches = s->launches[kind];
-    if (alg_bytes) *alg_bytes = s->bytes[kind];
-    return THETIS_OK;
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        if (kind < 0 || kind >= THETIS_K_NKINDS) return fail(THETIS_EINVAL, "unknown kernel group");
+        if (ms) *ms = s->ms[kind];
+        if (launches) *launches = s->launches[kind];
+        if (alg_bytes) *alg_bytes = s->bytes[kind];
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_epoch_traffic(const thetis_solver *s, double *sweep_bytes,
                                               double *refresh_bytes, int64_t *updates) {
-    clear_error();
-    if (!s) return fail(THETIS_EINVAL, "solver is NULL");
-    double sw = 0.0;
-    if (s->p.schedule == THETIS_SCHED_ASYNC) {
-        sw = s->async_launch.bytes_cols + s->async_launch.bytes_block + s->async_launch.bytes_slack;
-    } else {
-        for (const ClassLaunch &cl : s->det) sw += cl.bytes_cols + cl.bytes_block + cl.bytes_slack;
+    try {
+        clear_error();
+        if (!s) return fail(THETIS_EINVAL, "solver is NULL");
+        double sw = 0.0;
+        if (s->p.schedule == THETIS_SCHED_ASYNC) {
+            sw = s->async_launch.bytes_cols + s->async_launch.bytes_block + s->async_launch.bytes_slack;
+        } else {
+            for (const ClassLaunch &cl : s->det) sw += cl.bytes_cols + cl.bytes_block + cl.bytes_slack;
+        }
+        if (sweep_bytes) *sweep_bytes = sw;
+        if (refresh_bytes) *refresh_bytes = s->refresh_bytes;
+        if (updates) *updates = s->updates_per_epoch;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
     }
-    if (sweep_bytes) *sweep_bytes = sw;
-    if (refresh_bytes) *refresh_bytes = s->refresh_bytes;
-    if (updates) *updates = s->updates_per_epoch;
-    return THETIS_OK;
 }
 
 namespace {
@@ -2974,79 +3057,91 @@ std::vector<CheckpointPart> checkpoint_parts(const thetis_solver &S) {
 }  // namespace
 
 extern "C" thetis_status thetis_solver_save(thetis_solver *s, void *host_buf, size_t *bytes) {
-    clear_error();
-    if (!s || !bytes) return fail(THETIS_EINVAL, "NULL argument");
-    thetis_solver &S = *s;
-    const std::vector<CheckpointPart> parts = checkpoint_parts(S);
-    size_t need = sizeof(CheckpointHeader);
-    for (const CheckpointPart &q : parts) need += q.bytes;
-    if (!host_buf) { *bytes = need; return THETIS_OK; }
-    if (*bytes < need) { *bytes = need; return fail(THETIS_EINVAL, "checkpoint buffer too small"); }
-    CheckpointHeader h{};
-    std::memcpy(h.magic, kCheckpointMagic, 8);
-    h.version = 1;
-    h.precision = S.p.precision;
-    h.has_ubar = S.has_ubar;
-    h.has_ybar = S.has_ybar;
-    h.n = S.n;
-    h.m = S.m;
-    h.epoch = S.epoch;
-    h.beta = S.p.beta;
-    h.inst_digest = S.inst_digest;
-    char *out = (char *)host_buf;
-    std::memcpy(out, &h, sizeof(h));
-    size_t off = sizeof(h);
-    for (const CheckpointPart &q : parts) {
-        if (q.bytes) HIP_TRY(hipMemcpyAsync(out + off, q.dev, q.bytes, hipMemcpyDeviceToHost, S.stream));
-        off += q.bytes;
+    try {
+        clear_error();
+        if (!s || !bytes) return fail(THETIS_EINVAL, "NULL argument");
+        thetis_solver &S = *s;
+        const std::vector<CheckpointPart> parts = checkpoint_parts(S);
+        size_t need = sizeof(CheckpointHeader);
+        for (const CheckpointPart &q : parts) need += q.bytes;
+        if (!host_buf) { *bytes = need; return THETIS_OK; }
+        if (*bytes < need) { *bytes = need; return fail(THETIS_EINVAL, "checkpoint buffer too small"); }
+        CheckpointHeader h{};
+        std::memcpy(h.magic, kCheckpointMagic, 8);
+        h.version = 1;
+        h.precision = S.p.precision;
+        h.has_ubar = S.has_ubar;
+        h.has_ybar = S.has_ybar;
+        h.n = S.n;
+        h.m = S.m;
+        h.epoch = S.epoch;
+        h.beta = S.p.beta;
+        h.inst_digest = S.inst_digest;
+        char *out = (char *)host_buf;
+        std::memcpy(out, &h, sizeof(h));
+        size_t off = sizeof(h);
+        for (const CheckpointPart &q : parts) {
+            if (q.bytes) HIP_TRY(hipMemcpyAsync(out + off, q.dev, q.bytes, hipMemcpyDeviceToHost, S.stream));
+            off += q.bytes;
+        }
+        HIP_TRY(hipStreamSynchronize(S.stream));
+        *bytes = need;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
     }
-    HIP_TRY(hipStreamSynchronize(S.stream));
-    *bytes = need;
-    return THETIS_OK;
 }
 
 extern "C" thetis_status thetis_solver_load(thetis_solver *s, const void *host_buf, size_t bytes) {
-    clear_error();
-    if (!s || !host_buf) return fail(THETIS_EINVAL, "NULL argument");
-    thetis_solver &S = *s;
-    if (bytes < sizeof(CheckpointHeader)) return fail(THETIS_EINVAL, "checkpoint too short");
-    CheckpointHeader h;
-    std::memcpy(&h, host_buf, sizeof(h));
-    if (std::memcmp(h.magic, kCheckpointMagic, 8) != 0 || h.version != 1)
-        return fail(THETIS_EINVAL, "not a checkpoint of this library");
-    if (h.precision != S.p.precision || h.n != S.n || h.m != S.m || h.inst_digest != S.inst_digest ||
-        h.has_ubar != (int32_t)S.has_ubar || h.has_ybar != (int32_t)S.has_ybar)
-        return fail(THETIS_EINVAL, "checkpoint of a different instance, precision or parameter set");
-    if (!(h.beta > 0.0) || !std::isfinite(h.beta) || h.epoch < 0) return fail(THETIS_EINVAL, "corrupt checkpoint header");
-    const std::vector<CheckpointPart> parts = checkpoint_parts(S);
-    size_t need = sizeof(h);
-    for (const CheckpointPart &q : parts) need += q.bytes;
-    if (bytes != need) return fail(THETIS_EINVAL, "checkpoint size does not match the solver");
-    const char *in = (const char *)host_buf;
-    size_t off = sizeof(h);
-    for (const CheckpointPart &q : parts) {
-        if (q.bytes) HIP_TRY(hipMemcpyAsync(q.dev, in + off, q.bytes, hipMemcpyHostToDevice, S.stream));
-        off += q.bytes;
+    try {
+        clear_error();
+        if (!s || !host_buf) return fail(THETIS_EINVAL, "NULL argument");
+        thetis_solver &S = *s;
+        if (bytes < sizeof(CheckpointHeader)) return fail(THETIS_EINVAL, "checkpoint too short");
+        CheckpointHeader h;
+        std::memcpy(&h, host_buf, sizeof(h));
+        if (std::memcmp(h.magic, kCheckpointMagic, 8) != 0 || h.version != 1)
+            return fail(THETIS_EINVAL, "not a checkpoint of this library");
+        if (h.precision != S.p.precision || h.n != S.n || h.m != S.m || h.inst_digest != S.inst_digest ||
+            h.has_ubar != (int32_t)S.has_ubar || h.has_ybar != (int32_t)S.has_ybar)
+            return fail(THETIS_EINVAL, "checkpoint of a different instance, precision or parameter set");
+        if (!(h.beta > 0.0) || !std::isfinite(h.beta) || h.epoch < 0) return fail(THETIS_EINVAL, "corrupt checkpoint header");
+        const std::vector<CheckpointPart> parts = checkpoint_parts(S);
+        size_t need = sizeof(h);
+        for (const CheckpointPart &q : parts) need += q.bytes;
+        if (bytes != need) return fail(THETIS_EINVAL, "checkpoint size does not match the solver");
+        const char *in = (const char *)host_buf;
+        size_t off = sizeof(h);
+        for (const CheckpointPart &q : parts) {
+            if (q.bytes) HIP_TRY(hipMemcpyAsync(q.dev, in + off, q.bytes, hipMemcpyHostToDevice, S.stream));
+            off += q.bytes;
+        }
+        HIP_TRY(hipStreamSynchronize(S.stream));
+        if (h.beta != S.p.beta) {
+            thetis_status st = apply_beta(S, h.beta);
+            if (st) return st;
+        }
+        S.epoch = h.epoch;
+        S.metrics_fresh = false;
+        S.have_round = false;
+        if (S.has_ubar || S.has_ybar || h.beta != S.beta0) S.mul_dirty = true;   // a reset returns to creation
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
     }
-    HIP_TRY(hipStreamSynchronize(S.stream));
-    if (h.beta != S.p.beta) {
-        thetis_status st = apply_beta(S, h.beta);
-        if (st) return st;
-    }
-    S.epoch = h.epoch;
-    S.metrics_fresh = false;
-    S.have_round = false;
-    if (S.has_ubar || S.has_ybar || h.beta != S.beta0) S.mul_dirty = true;   // a reset returns to creation
-    return THETIS_OK;
 }
 
 extern "C" thetis_status thetis_solver_destroy(thetis_solver *s) {
-    if (!s) return THETIS_OK;
-    (void)hipStreamSynchronize(s->stream);
-    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
-    if (s->own_ws && s->ws) (void)hipFree(s->ws);
-    delete s;
-    return THETIS_OK;
+    try {
+        if (!s) return THETIS_OK;
+        (void)hipStreamSynchronize(s->stream);
+        for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+        if (s->own_ws && s->ws) (void)hipFree(s->ws);
+        delete s;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 // ==================================================================== batches
@@ -3811,105 +3906,124 @@ void batch_signature(thetis_batch &B) {
 
 extern "C" thetis_status thetis_batch_create(int32_t capacity, thetis_solver *const *solvers, int32_t precision,
                                              int32_t unit_values, void *stream, thetis_batch **out) {
-    clear_error();
-    if (!out || capacity < 1) return fail(THETIS_EINVAL, "need a capacity of at least one slot");
-    *out = nullptr;
-    if (precision != THETIS_PREC_FP32 && precision != THETIS_PREC_FP64 && precision != THETIS_PREC_BF16X)
-        return fail(THETIS_EINVAL, "unknown precision");
-    thetis_batch *Bp = new (std::nothrow) thetis_batch;
-    if (!Bp) return fail(THETIS_ENOMEM, "host allocation failed");
-    thetis_batch &B = *Bp;
-    B.count = capacity;
-    B.precision = precision;
-    B.vals = unit_values == 0;
-    B.solvers.assign(capacity, nullptr);
-    for (int32_t i = 0; solvers && i < capacity; ++i) {
-        thetis_solver *S = solvers[i];
-        if (!S) continue;
-        thetis_status st = batch_check_solver(B, S);
-        if (st) { delete Bp; return st; }
-        B.solvers[i] = S;
-        B.vmode = det_vmode(*S);
-    }
-    if (!B.vals) B.vmode = 0;
-    B.stream = (hipStream_t)stream;
-    if (!B.stream) {
-        // stream capture needs a stream other than the null stream
-        if (hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking) != hipSuccess) {
-            delete Bp;
-            return fail(THETIS_EDEVICE, "could not create the batch stream");
+    thetis_batch *Bp = nullptr;   // released by the handler below if the host side throws
+    try {
+        clear_error();
+        if (!out || capacity < 1) return fail(THETIS_EINVAL, "need a capacity of at least one slot");
+        *out = nullptr;
+        if (precision != THETIS_PREC_FP32 && precision != THETIS_PREC_FP64 && precision != THETIS_PREC_BF16X)
+            return fail(THETIS_EINVAL, "unknown precision");
+        Bp = new (std::nothrow) thetis_batch;
+        if (!Bp) return fail(THETIS_ENOMEM, "host allocation failed");
+        thetis_batch &B = *Bp;
+        B.count = capacity;
+        B.precision = precision;
+        B.vals = unit_values == 0;
+        B.solvers.assign(capacity, nullptr);
+        for (int32_t i = 0; solvers && i < capacity; ++i) {
+            thetis_solver *S = solvers[i];
+            if (!S) continue;
+            thetis_status st = batch_check_solver(B, S);
+            if (st) { delete Bp; return st; }
+            B.solvers[i] = S;
+            B.vmode = det_vmode(*S);
         }
-        B.own_stream = true;
+        if (!B.vals) B.vmode = 0;
+        B.stream = (hipStream_t)stream;
+        if (!B.stream) {
+            // stream capture needs a stream other than the null stream
+            if (hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking) != hipSuccess) {
+                delete Bp;
+                return fail(THETIS_EDEVICE, "could not create the batch stream");
+            }
+            B.own_stream = true;
+        }
+        batch_signature(B);
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
+        }
+        B.resident_wg = (int64_t)cus * 8;    // 8 workgroups of 256 threads per CU
+        const int32_t count = capacity;
+        const size_t nb = binst_bytes(B.precision);
+        hipError_t e = hipMalloc(&B.bi, nb * count);
+        if (e == hipSuccess) e = hipMalloc((void **)&B.rows_wg, 4 * count);
+        if (e == hipSuccess) e = hipMalloc((void **)&B.dual_wg, 4 * count);
+        if (e == hipSuccess) e = hipMalloc((void **)&B.alist, 4 * (size_t)count);
+        if (e == hipSuccess) e = hipMalloc((void **)&B.ctl, 4 * CTL_N);
+        if (e == hipSuccess) e = hipMalloc((void **)&B.order, (size_t)kMaxBatchClasses * count);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            thetis_batch_destroy(Bp);
+            return fail(THETIS_ENOMEM, "device allocation of the batch tables failed");
+        }
+        *out = Bp;
+        return THETIS_OK;
+    } catch (...) {
+        const thetis_status st = exception_status();
+        if (Bp) thetis_batch_destroy(Bp);
+        return st;
     }
-    batch_signature(B);
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
-    }
-    B.resident_wg = (int64_t)cus * 8;    // 8 workgroups of 256 threads per CU
-    const int32_t count = capacity;
-    const size_t nb = binst_bytes(B.precision);
-    hipError_t e = hipMalloc(&B.bi, nb * count);
-    if (e == hipSuccess) e = hipMalloc((void **)&B.rows_wg, 4 * count);
-    if (e == hipSuccess) e = hipMalloc((void **)&B.dual_wg, 4 * count);
-    if (e == hipSuccess) e = hipMalloc((void **)&B.alist, 4 * (size_t)count);
-    if (e == hipSuccess) e = hipMalloc((void **)&B.ctl, 4 * CTL_N);
-    if (e == hipSuccess) e = hipMalloc((void **)&B.order, (size_t)kMaxBatchClasses * count);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        thetis_batch_destroy(Bp);
-        return fail(THETIS_ENOMEM, "device allocation of the batch tables failed");
-    }
-    *out = Bp;
-    return THETIS_OK;
 }
 
 extern "C" thetis_status thetis_batch_set(thetis_batch *b, int32_t slot, thetis_solver *s) {
-    clear_error();
-    if (!b) return fail(THETIS_EINVAL, "batch is NULL");
-    if (slot < 0 || slot >= b->count) return fail(THETIS_EINVAL, "slot out of range");
-    if (s) {
-        thetis_status st = batch_check_solver(*b, s);
-        if (st) return st;
+    try {
+        clear_error();
+        if (!b) return fail(THETIS_EINVAL, "batch is NULL");
+        if (slot < 0 || slot >= b->count) return fail(THETIS_EINVAL, "slot out of range");
+        if (s) {
+            thetis_status st = batch_check_solver(*b, s);
+            if (st) return st;
+        }
+        b->solvers[slot] = s;
+        // the value storage the batch's sweeps read: that of its solvers
+        b->vmode = b->vals ? -1 : 0;
+        for (const thetis_solver *o : b->solvers)
+            if (o) { b->vmode = det_vmode(*o); break; }
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
     }
-    b->solvers[slot] = s;
-    // the value storage the batch's sweeps read: that of its solvers
-    b->vmode = b->vals ? -1 : 0;
-    for (const thetis_solver *o : b->solvers)
-        if (o) { b->vmode = det_vmode(*o); break; }
-    return THETIS_OK;
 }
 
 extern "C" thetis_status thetis_batch_run(thetis_batch *b, int32_t max_epochs, double gap_tol, int32_t *done,
                                           int32_t *status) {
-    clear_error();
-    if (!b) return fail(THETIS_EINVAL, "batch is NULL");
-    if (max_epochs < 0) return fail(THETIS_EINVAL, "max_epochs < 0");
-    if (max_epochs == 0) {
-        for (int32_t i = 0; i < b->count; ++i) {
-            if (done) done[i] = 0;
-            if (status) status[i] = b->solvers[i] ? 0 : -1;
+    try {
+        clear_error();
+        if (!b) return fail(THETIS_EINVAL, "batch is NULL");
+        if (max_epochs < 0) return fail(THETIS_EINVAL, "max_epochs < 0");
+        if (max_epochs == 0) {
+            for (int32_t i = 0; i < b->count; ++i) {
+                if (done) done[i] = 0;
+                if (status) status[i] = b->solvers[i] ? 0 : -1;
+            }
+            return THETIS_OK;
         }
-        return THETIS_OK;
+        return BDISPATCH(*b, batch_run_impl)(*b, max_epochs, gap_tol, done, status, nullptr);
+    } catch (...) {
+        return exception_status();
     }
-    return BDISPATCH(*b, batch_run_impl)(*b, max_epochs, gap_tol, done, status, nullptr);
 }
 
 extern "C" thetis_status thetis_batch_configure(thetis_batch *b, int32_t widen, int32_t grid_mult, int32_t strided,
                                                 int32_t cols) {
-    clear_error();
-    if (!b) return fail(THETIS_EINVAL, "batch is NULL");
-    if (widen != 1 && widen != 2 && widen != 4) return fail(THETIS_EINVAL, "widen must be 1, 2 or 4");
-    if (grid_mult != 0 && grid_mult != 1 && grid_mult != 2 && grid_mult != 4 && grid_mult != 8)
-        return fail(THETIS_EINVAL, "grid multiplier must be 0 (one workgroup per item), 1, 2, 4 or 8");
-    if (strided != 0 && strided != 1) return fail(THETIS_EINVAL, "strided must be 0 or 1");
-    if (cols != 1 && cols != 2 && cols != 4) return fail(THETIS_EINVAL, "cols must be 1, 2 or 4");
-    b->widen = widen;
-    b->grid_mult = grid_mult;
-    b->strided = strided;
-    b->cols = cols;
-    return THETIS_OK;
+    try {
+        clear_error();
+        if (!b) return fail(THETIS_EINVAL, "batch is NULL");
+        if (widen != 1 && widen != 2 && widen != 4) return fail(THETIS_EINVAL, "widen must be 1, 2 or 4");
+        if (grid_mult != 0 && grid_mult != 1 && grid_mult != 2 && grid_mult != 4 && grid_mult != 8)
+            return fail(THETIS_EINVAL, "grid multiplier must be 0 (one workgroup per item), 1, 2, 4 or 8");
+        if (strided != 0 && strided != 1) return fail(THETIS_EINVAL, "strided must be 0 or 1");
+        if (cols != 1 && cols != 2 && cols != 4) return fail(THETIS_EINVAL, "cols must be 1, 2 or 4");
+        b->widen = widen;
+        b->grid_mult = grid_mult;
+        b->strided = strided;
+        b->cols = cols;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 namespace {
@@ -3927,61 +4041,73 @@ thetis_status tune_time(thetis_batch &B, const Choice &c, int32_t epochs, double
 }  // namespace
 
 extern "C" thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_per_candidate, int32_t *choice) {
-    clear_error();
-    if (!b) return fail(THETIS_EINVAL, "batch is NULL");
-    if (epochs_per_candidate < 1) return fail(THETIS_EINVAL, "epochs_per_candidate < 1");
-    // two stages: the per-column shape (lanes and columns per group) at the
-    // current grid, then the grid size and walk with the best shape
-    const Choice shapes[4] = {{1, 0, 0, 1}, {2, 0, 0, 1}, {1, 0, 0, 2}, {1, 0, 0, 4}};
-    Choice best{b->widen, b->grid_mult, b->strided, b->cols};
-    double best_ms = 1e300;
-    for (const Choice &sh : shapes) {
-        const Choice c{sh.widen, best.grid_mult, best.strided, sh.cols};
-        double ms = 0;
-        thetis_status rc = tune_time(*b, c, epochs_per_candidate, &ms);
-        if (rc) return rc;
-        if (ms < best_ms) { best_ms = ms; best = c; }
-    }
-    const Choice base = best;
-    for (int st = 0; st < 2; ++st)
-        for (int g : {0, 1, 2, 4}) {
-            const Choice c{base.widen, g, st, base.cols};
-            if (g == base.grid_mult && st == base.strided) continue;
+    try {
+        clear_error();
+        if (!b) return fail(THETIS_EINVAL, "batch is NULL");
+        if (epochs_per_candidate < 1) return fail(THETIS_EINVAL, "epochs_per_candidate < 1");
+        // two stages: the per-column shape (lanes and columns per group) at the
+        // current grid, then the grid size and walk with the best shape
+        const Choice shapes[4] = {{1, 0, 0, 1}, {2, 0, 0, 1}, {1, 0, 0, 2}, {1, 0, 0, 4}};
+        Choice best{b->widen, b->grid_mult, b->strided, b->cols};
+        double best_ms = 1e300;
+        for (const Choice &sh : shapes) {
+            const Choice c{sh.widen, best.grid_mult, best.strided, sh.cols};
             double ms = 0;
             thetis_status rc = tune_time(*b, c, epochs_per_candidate, &ms);
             if (rc) return rc;
             if (ms < best_ms) { best_ms = ms; best = c; }
         }
-    b->widen = best.widen;
-    b->grid_mult = best.grid_mult;
-    b->strided = best.strided;
-    b->cols = best.cols;
-    tuned_choices()[b->signature] = best;
-    if (choice) { choice[0] = best.widen; choice[1] = best.grid_mult; choice[2] = best.strided; choice[3] = best.cols; }
-    return THETIS_OK;
+        const Choice base = best;
+        for (int st = 0; st < 2; ++st)
+            for (int g : {0, 1, 2, 4}) {
+                const Choice c{base.widen, g, st, base.cols};
+                if (g == base.grid_mult && st == base.strided) continue;
+                double ms = 0;
+                thetis_status rc = tune_time(*b, c, epochs_per_candidate, &ms);
+                if (rc) return rc;
+                if (ms < best_ms) { best_ms = ms; best = c; }
+            }
+        b->widen = best.widen;
+        b->grid_mult = best.grid_mult;
+        b->strided = best.strided;
+        b->cols = best.cols;
+        tuned_choices()[b->signature] = best;
+        if (choice) { choice[0] = best.widen; choice[1] = best.grid_mult; choice[2] = best.strided; choice[3] = best.cols; }
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_batch_set_window(thetis_batch *b, int32_t window) {
-    clear_error();
-    if (!b) return fail(THETIS_EINVAL, "batch is NULL");
-    if (window < 0) return fail(THETIS_EINVAL, "window must be >= 0");
-    b->window = window;
-    return THETIS_OK;
+    try {
+        clear_error();
+        if (!b) return fail(THETIS_EINVAL, "batch is NULL");
+        if (window < 0) return fail(THETIS_EINVAL, "window must be >= 0");
+        b->window = window;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }
 
 extern "C" thetis_status thetis_batch_destroy(thetis_batch *b) {
-    if (!b) return THETIS_OK;
-    (void)hipStreamSynchronize(b->stream);
-    batch_drop_graph(*b);
-    (void)hipFree(b->bi);
-    if (b->bc) (void)hipFree(b->bc);
-    (void)hipFree(b->rows_wg);
-    (void)hipFree(b->dual_wg);
-    (void)hipFree(b->alist);
-    (void)hipFree(b->ctl);
-    if (b->dirs) (void)hipFree(b->dirs);
-    (void)hipFree(b->order);
-    if (b->own_stream) (void)hipStreamDestroy(b->stream);
-    delete b;
-    return THETIS_OK;
+    try {
+        if (!b) return THETIS_OK;
+        (void)hipStreamSynchronize(b->stream);
+        batch_drop_graph(*b);
+        (void)hipFree(b->bi);
+        if (b->bc) (void)hipFree(b->bc);
+        (void)hipFree(b->rows_wg);
+        (void)hipFree(b->dual_wg);
+        (void)hipFree(b->alist);
+        (void)hipFree(b->ctl);
+        if (b->dirs) (void)hipFree(b->dirs);
+        (void)hipFree(b->order);
+        if (b->own_stream) (void)hipStreamDestroy(b->stream);
+        delete b;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
+    }
 }

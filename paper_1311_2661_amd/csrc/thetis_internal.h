@@ -12,8 +12,13 @@
 namespace thetis {
 
 // error plumbing: every C entry point funnels failures through fail()
-thetis_status fail(thetis_status code, const std::string &msg);
+thetis_status fail(thetis_status code, const char *msg) noexcept;
+thetis_status fail(thetis_status code, const std::string &msg) noexcept;
 void clear_error();
+// C++ exceptions never cross the C ABI: every entry point catches them and
+// returns this (called inside a handler): THETIS_ENOMEM for a failed host
+// allocation, THETIS_EINVAL with the message for anything else
+thetis_status exception_status();
 
 // Work kinds of the class sweep.  Plain columns are grouped by degree into
 // lane groups of G lanes per column (G divides the 64-lane wavefront);
