@@ -599,40 +599,6 @@ __device__ __forceinline__ double box_min(double red, double U, double rho, doub
 // rows a thread of the row pass takes (fewer partial records to fold)
 constexpr int kRowsPerThread = 4;
 
-// The lane's part of A_i x (FP64) for the kRowsPerThread rows ri[] of a
-// row-pass thread in workgroup wg (rows at or past m give 0).  The rows
-// advance together, one entry slot at a time, so the index and x loads of
-// all of them are in flight at once; each lane still sums its entries in
-// entry order.
-template <class P>
-__device__ __forceinline__ void row_dots(const Dev<P> &a, int64_t wg, int G, int lane,
-                                         int64_t (&ri)[kRowsPerThread], double (&ax)[kRowsPerThread]) {
-    int32_t e0[kRowsPerThread], e1[kRowsPerThread];
-#pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q) {
-        ri[q] = (wg * kRowsPerThread + q) * (kWG / G) + threadIdx.x / G;
-        const bool in = ri[q] < a.m;
-        e0[q] = in ? a.row_ptr[ri[q]] + lane : 0;
-        e1[q] = in ? a.row_ptr[ri[q] + 1] : 0;
-        ax[q] = 0.0;
-    }
-    for (int32_t t = 0;; t += G) {
-        int32_t col[kRowsPerThread];
-        bool any = false;
-#pragma unroll
-        for (int q = 0; q < kRowsPerThread; ++q) {
-            const int32_t e = e0[q] + t;
-            col[q] = e < e1[q] ? a.csr_col[e] : -1;
-            any |= col[q] >= 0;
-        }
-        if (!any) break;
-#pragma unroll
-        for (int q = 0; q < kRowsPerThread; ++q)
-            if (col[q] >= 0)
-                ax[q] += (a.csr_val ? (double)a.csr_val[e0[q] + t] : 1.0) * (double)xval(a.x[col[q]]);
-    }
-}
-
 template <class P>
 __device__ __forceinline__ void rows_item(const Dev<P> &a, int64_t wg, int32_t write_r, int32_t with_dual,
                                           double *part) {
@@ -642,13 +608,12 @@ __device__ __forceinline__ void rows_item(const Dev<P> &a, int64_t wg, int32_t w
     // rows_lanes lanes per row (a power of two; long rows): the group's lanes
     // stride the row and reduce with a butterfly, its first lane finishes
     const int G = a.row_lanes, lane = threadIdx.x & (G - 1);
-    int64_t ri[kRowsPerThread];
-    double axs[kRowsPerThread];
-    row_dots(a, wg, G, lane, ri, axs);
     for (int q = 0; q < kRowsPerThread; ++q) {
-        const int64_t i = ri[q];
+        const int64_t i = (wg * kRowsPerThread + q) * (kWG / G) + threadIdx.x / G;
         if (i >= a.m) break;                  // the whole group together
-        double ax = axs[q];
+        double ax = 0.0;
+        for (int32_t e = a.row_ptr[i] + lane; e < a.row_ptr[i + 1]; e += G)
+            ax += (a.csr_val ? (double)a.csr_val[e] : 1.0) * (double)xval(a.x[a.csr_col[e]]);
         for (int o = G / 2; o > 0; o >>= 1) ax += __shfl_xor(ax, o, 64);
         if (lane) continue;
         const int8_t sn = a.sense[i];
@@ -942,13 +907,12 @@ __global__ __launch_bounds__(kWG) void k_mul_rows(Dev<P> a, double *ubar_w, doub
     double v[kMulRowSlots] = {0, 0};
     const int op[kMulRowSlots] = {0, 1};
     const int G = a.row_lanes, lane = threadIdx.x & (G - 1);
-    int64_t ri[kRowsPerThread];
-    double axs[kRowsPerThread];
-    row_dots(a, (int64_t)blockIdx.x, G, lane, ri, axs);
     for (int q = 0; q < kRowsPerThread; ++q) {
-        const int64_t i = ri[q];
+        const int64_t i = ((int64_t)blockIdx.x * kRowsPerThread + q) * (kWG / G) + threadIdx.x / G;
         if (i >= a.m) break;                  // the whole group together
-        double acc = axs[q];
+        double acc = 0.0;
+        for (int32_t e = a.row_ptr[i] + lane; e < a.row_ptr[i + 1]; e += G)
+            acc += (a.csr_val ? (double)a.csr_val[e] : 1.0) * (double)xval(a.x[a.csr_col[e]]);
         for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
         if (lane) continue;
         const int8_t sn = a.sense[i];
