@@ -390,7 +390,7 @@ orc_solver *orc_solver_create(orc_lp *p, double beta, int32_t step_rule, double 
     return s;
 }
 
-/* one SCD step on unit t (Algorithm 1, step 4; block form of Appendix E) */
+/* one SCD step on unit t (the coordinate update of Algorithm 1; block form of Appendix E) */
 static void update_unit(orc_solver *s, int64_t t) {
     const orc_lp *p = s->lp;
     double L = s->step_rule == STEP_GLOBAL_LMAX ? s->Lmax : s->L[t];
@@ -480,7 +480,7 @@ static int64_t epoch_sequence(orc_solver *s, int32_t within_reverse) {
         free(ks);
         return U;
     }
-    /* uniform with replacement (Algorithm 1, step 3) */
+    /* uniform with replacement (the coordinate choice of Algorithm 1) */
     for (int64_t t = 0; t < U; ++t) {
         int64_t pick = (int64_t)(u53(ph_word(s->seed, ST_UNIFORM, (uint64_t)s->epoch, (uint64_t)t, 0)) * (double)U);
         if (pick >= U) pick = U - 1;

@@ -135,7 +135,7 @@ __device__ __forceinline__ typename P::R col_bound(const Dev<P> &a, int64_t j) {
     return a.ub ? a.ub[j] : a.ub_value;
 }
 
-// projected coordinate step, same operation order as Algorithm 1 step 4:
+// projected coordinate step, same operation order as the update of Algorithm 1:
 // y' = clip(y - gamma g / L, 0, U); an empty column without prox moves to
 // its cheaper bound
 template <class R>
