@@ -312,7 +312,9 @@ thetis_status thetis_objective(thetis_solver *s, double *lp_value, double *penal
 thetis_status thetis_get_x(thetis_solver *s, double *x_host, double *s_host);
 
 /* Replaces y by y_host[n+m] (rounded to the storage precision) and
- * recomputes r.  Entries are clipped to their bounds. */
+ * recomputes r.  Entries are clipped to their bounds; the columns of a fixed
+ * simplex block keep its unit vector, and a free block is taken as given
+ * (its next update projects it onto the simplex). */
 thetis_status thetis_set_y(thetis_solver *s, const double *y_host);
 
 /* Epochs run since creation or reset. */

@@ -1541,6 +1541,9 @@ __global__ __launch_bounds__(kWG) void k_load_y(Dev<P> a, const double *y, const
         const double U = a.ub ? (double)a.ub[t] : (double)a.ub_value;
         if (v < 0.0) v = 0.0;
         if (v > U) v = U;
+        // a fixed block (a terminal, an observed variable) keeps its unit vector
+        const int32_t blk = a.col_block ? a.col_block[t] : -1;
+        if (blk >= 0 && a.fixed[blk] >= 0) v = (t - a.bfirst[blk] == a.fixed[blk]) ? 1.0 : 0.0;
         a.x[t] = xenc<typename P::X, double>(v);
     }
     if (t < a.m) {

@@ -264,6 +264,23 @@ def test_rounding_and_check_kernels_bit_exact_on_oracle_point(seed):
         assert aux[0] == oaux[0]
 
 
+def test_set_y_keeps_fixed_blocks():
+    """thetis_set_y clips to the bounds, keeps every fixed block (terminal)
+    at its unit vector and takes free blocks as given."""
+    inst = I.mc_grid(side=12, k=4, seed=3)
+    nv, k = inst.meta["n_vertices"], inst.block_k
+    g = gpu_solver(inst, precision=T.PREC_FP64)
+    y = np.full(inst.n + inst.m, 0.25)
+    y[nv * k] = 7.0                           # an edge variable above its bound 1
+    g.y = y
+    got = g.y[: nv * k].reshape(nv, k)
+    term = np.asarray(inst.meta["terminals"])
+    assert np.array_equal(got[term], np.eye(k)[inst.fixed_label[term]])
+    free = np.setdiff1d(np.arange(nv), term)
+    assert np.all(got[free] == 0.25)
+    assert g.y[nv * k] == 1.0
+
+
 def test_multiway_cut_rounding_on_random_simplex_point():
     inst = I.mc_grid(side=40, k=8, seed=9)
     rng = np.random.default_rng(2)
