@@ -392,6 +392,8 @@ thetis_status thetis_epoch_traffic(const thetis_solver *s, double *sweep_bytes,
 thetis_status thetis_solver_save(thetis_solver *s, void *host_buf, size_t *bytes);
 thetis_status thetis_solver_load(thetis_solver *s, const void *host_buf, size_t bytes);
 
+/* Frees the solver (NULL is a no-op).  THETIS_EBUSY, and nothing freed,
+ * while a batch slot holds it: empty the slot or destroy the batch first. */
 thetis_status thetis_solver_destroy(thetis_solver *s);
 
 /* Measurement aid (no part of the method): on `stream` (NULL: the null
@@ -414,8 +416,9 @@ thetis_status thetis_calibrate_random(int32_t words_log2, int32_t iters, void *s
  * computes exactly what thetis_run_epochs would compute for it alone (same
  * classes, same order, same kernels): results are bit-identical, whatever
  * else occupies the batch.  solvers_host: NULL or `capacity` entries (NULL =
- * empty slot).  The batch borrows the solvers (they must outlive their slot
- * and must not be run alone during a batch call).  stream: hipStream_t for
+ * empty slot).  The batch borrows the solvers (they must outlive their slot,
+ * which thetis_solver_destroy enforces, and must not be run alone during a
+ * batch call).  stream: hipStream_t for
  * the batch's launches, or NULL (the batch makes its own).  Errors:
  * THETIS_EINVAL (a solver of another precision or value kind, ASYNC
  * schedule, capacity < 1), THETIS_EUNSUPPORTED (more than 64 colour

@@ -23,6 +23,7 @@
 //                  the residual norms, row violation, penalty value F and the
 //                  dual bound Phi, reduced in a fixed order (deterministic)
 //   k_round_* / k_check_*          pre-rounding pass, roundings, check
+#include <atomic>
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
@@ -1632,6 +1633,7 @@ struct thetis_solver {
         *chkbuf, *mulstats, *ystage, *row_orig, *ctil0, *ybar0, *ubar0, *upair, *pw_ends, *pw_first;
     int64_t nwg_rows = 0, nwg_cols = 0;
     int64_t epoch = 0;
+    std::atomic<int32_t> batch_slots{0};       // batch slots holding this solver (destroy refuses while > 0)
     bool metrics_fresh = false;
     double mt[MT_NSLOT] = {0};
     bool have_round = false;
@@ -3136,7 +3138,10 @@ extern "C" thetis_status thetis_solver_load(thetis_solver *s, const void *host_b
 
 extern "C" thetis_status thetis_solver_destroy(thetis_solver *s) {
     try {
+        clear_error();
         if (!s) return THETIS_OK;
+        if (s->batch_slots.load() > 0)
+            return fail(THETIS_EBUSY, "the solver occupies a batch slot: empty the slot or destroy the batch first");
         (void)hipStreamSynchronize(s->stream);
         for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
         if (s->own_ws && s->ws) (void)hipFree(s->ws);
@@ -3586,6 +3591,7 @@ struct thetis_batch {
     int32_t vmode = -1;                  // how the solvers' DET copies store values (entry_at); -1: none yet
     int64_t bc_capacity = 0;             // BClass records the device table holds
     std::vector<thetis_solver *> solvers;
+    bool slots_counted = false;          // the solvers' batch_slots count this batch's slots
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int widen = 1, grid_mult = 2, strided = 1, cols = 4;
@@ -3961,6 +3967,9 @@ extern "C" thetis_status thetis_batch_create(int32_t capacity, thetis_solver *co
             thetis_batch_destroy(Bp);
             return fail(THETIS_ENOMEM, "device allocation of the batch tables failed");
         }
+        for (thetis_solver *S : B.solvers)
+            if (S) S->batch_slots++;
+        B.slots_counted = true;
         *out = Bp;
         return THETIS_OK;
     } catch (...) {
@@ -3979,6 +3988,8 @@ extern "C" thetis_status thetis_batch_set(thetis_batch *b, int32_t slot, thetis_
             thetis_status st = batch_check_solver(*b, s);
             if (st) return st;
         }
+        if (b->solvers[slot]) b->solvers[slot]->batch_slots--;
+        if (s) s->batch_slots++;
         b->solvers[slot] = s;
         // the value storage the batch's sweeps read: that of its solvers
         b->vmode = b->vals ? -1 : 0;
@@ -4098,6 +4109,9 @@ extern "C" thetis_status thetis_batch_destroy(thetis_batch *b) {
     try {
         if (!b) return THETIS_OK;
         (void)hipStreamSynchronize(b->stream);
+        if (b->slots_counted)
+            for (thetis_solver *S : b->solvers)
+                if (S) S->batch_slots--;
         batch_drop_graph(*b);
         (void)hipFree(b->bi);
         if (b->bc) (void)hipFree(b->bc);

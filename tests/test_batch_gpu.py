@@ -185,6 +185,24 @@ def test_batch_many_uneven_instances():
         assert s.check(T.ROUND_MIS_THRESH) == (True, 0)
 
 
+def test_solver_in_a_batch_cannot_be_destroyed():
+    sa = T.Solver(T.Instance(I.vc_er(300, 1200, seed=1)))
+    sb = T.Solver(T.Instance(I.vc_er(200, 700, seed=2)))
+    b = T.Batch([sa, sb])
+    with pytest.raises(T.ThetisError) as e:
+        sa.close()
+    assert e.value.code == T.EBUSY
+    b.set(0, None)
+    sa.close()                                # the slot is empty now
+    assert list(b.run(3)) == [0, 3]
+    b.set(0, sb)                              # one solver in two slots
+    b.set(1, None)
+    with pytest.raises(T.ThetisError):
+        sb.close()
+    b.close()
+    sb.close()
+
+
 def test_batch_rejects_mixed_kinds():
     a = T.Solver(T.Instance(I.vc_er(50, 100, seed=1)), precision=T.PREC_FP32)
     b = T.Solver(T.Instance(I.vc_er(50, 100, seed=2)), precision=T.PREC_FP64)
