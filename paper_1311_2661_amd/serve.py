@@ -245,7 +245,12 @@ class Server:
                         r.future.set_exception(e)
                 if not any(s is not None for s in grp["slots"]):
                     continue
-                done = batch.run(self.tick, self.gap_tol)
+                try:
+                    done = batch.run(self.tick, self.gap_tol)
+                except Exception as e:
+                    # a failed batch call ends every request the batch held
+                    self._fail_all(g, e)
+                    continue
                 status = batch.last_status
                 for slot, r in enumerate(grp["slots"]):
                     if r is None:
@@ -273,6 +278,16 @@ class Server:
         if err is None:
             r.future.set_result(res)
         else:
+            r.future.set_exception(err)
+
+    def _fail_all(self, g: str, err: Exception):
+        grp = self.groups[g]
+        for slot, r in enumerate(grp["slots"]):
+            if r is None:
+                continue
+            grp["batch"].set(slot, None)
+            grp["slots"][slot] = None
+            self._release(g, r)
             r.future.set_exception(err)
 
     def _release(self, g: str, r: _Req):

@@ -84,3 +84,28 @@ def test_oversize_request_fails_loudly():
     ok = srv.submit(I.vc_er(30, 60, seed=2), "vc")
     assert ok.result(timeout=60).feasible
     srv.close()
+
+
+def test_failed_batch_call_fails_its_requests_and_serving_continues():
+    """A batch call that raises (forced from the host: the Python call is
+    replaced once) ends the requests it held with that error; the server
+    keeps serving."""
+    srv = S.Server(hbm_budget=8 << 30, epoch_cap=20, slots=4)
+    b = srv.groups["ones"]["batch"]
+    real = b.run
+    state = {"armed": True}
+
+    def run_once_failing(*args, **kw):
+        if state["armed"]:
+            state["armed"] = False
+            raise T.ThetisError(T.EDEVICE, "batch call failed (forced from the host)")
+        return real(*args, **kw)
+
+    b.run = run_once_failing
+    f = srv.submit(I.vc_er(200, 600, seed=1), "vc", seed=1)
+    with pytest.raises(T.ThetisError) as e:
+        f.result(timeout=60)
+    assert e.value.code == T.EDEVICE
+    ok = srv.submit(I.vc_er(150, 400, seed=2), "vc", seed=2)
+    assert ok.result(timeout=60).feasible
+    srv.close()
