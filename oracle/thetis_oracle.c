@@ -24,7 +24,8 @@
  *     covering (with q(P)) and packing lemmas of Appendix C, the threshold
  *     and randomized roundings of Section 2 and Appendix B (vertex cover,
  *     independent set, set cover, integer covering, weighted packing,
- *     multiway cut), and the feasibility check;
+ *     multiway cut), the node-based roundings (argmax, sampling) of the
+ *     MAP-inference LP of the experiments, and the feasibility check;
  *   - the multiplier step of the augmented-Lagrangian framework (Section
  *     3.2) with the LP's Lagrangian dual bound.
  *
