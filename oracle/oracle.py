@@ -14,7 +14,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "thetis_oracle.c")
-LIB = os.path.join(HERE, "liborc.so")
+# THETIS_ORACLE_LIB names another build of the oracle to load instead: the
+# mutation check of the pins points it at builds with a planted mistake
+LIB = os.environ.get("THETIS_ORACLE_LIB") or os.path.join(HERE, "liborc.so")
 
 SCHED_DET, SCHED_PERM, SCHED_UNIFORM = 0, 1, 2
 STEP_PER_COORD, STEP_GLOBAL_LMAX = 0, 1

@@ -1,0 +1,84 @@
+"""Mutation check of the oracle's pins.  Each mutant plants one plausible
+mistake in a copy of the oracle's C source -- a dropped factor, a flipped
+sign, a wrong index or divisor, a missing bound, a strict comparison, a
+wrong round count -- builds it with the oracle's own flags, and runs the
+oracle's pins (CPU) against that build in a child process.  Every mutant
+must make at least one pin fail: a pin set that let one through would not
+pin the oracle."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "thetis_oracle.c")
+PINS = ["tests/test_oracle_pins.py", "tests/test_multipliers_cpu.py", "tests/test_rounding_general_cpu.py",
+        "tests/test_map_cpu.py"]
+
+MUTANTS = [
+    ("gradient_drops_beta",
+     "double g = s->ctil[j] + s->beta * dot + s->rho * (s->y[j] - s->ybar[j]);",
+     "double g = s->ctil[j] + dot + s->rho * (s->y[j] - s->ybar[j]);"),
+    ("prox_term_sign",
+     "double g = s->ctil[j] + s->beta * dot + s->rho * (s->y[j] - s->ybar[j]);",
+     "double g = s->ctil[j] + s->beta * dot - s->rho * (s->y[j] - s->ybar[j]);"),
+    ("upper_bound_not_clipped",
+     "        if (yn > p->ub[j]) yn = p->ub[j];\n        double d = yn - s->y[j];",
+     "        double d = yn - s->y[j];"),
+    ("residual_update_drops_value",
+     "s->r[p->ridx[e]] += d * p->cval[e];\n        return;",
+     "s->r[p->ridx[e]] += d;\n        return;"),
+    ("slack_sign_swapped",
+     "p->sense[i] > 0 ? -1.0 : (p->sense[i] < 0 ? 1.0 : 0.0)",
+     "p->sense[i] > 0 ? 1.0 : (p->sense[i] < 0 ? -1.0 : 0.0)"),
+    ("curvature_drops_beta",
+     "        return s->beta * a2 + s->rho;",
+     "        return a2 + s->rho;"),
+    ("penalty_drops_half",
+     "f += -s->ubar[i] * w + 0.5 * s->beta * w * w;",
+     "f += -s->ubar[i] * w + s->beta * w * w;"),
+    ("dual_clip_wrong_side",
+     "if (s->rho == 0.0) {\n            if (p->sense[i] > 0 && ui < 0.0) ui = 0.0;",
+     "if (s->rho == 0.0) {\n            if (p->sense[i] > 0 && ui > 0.0) ui = 0.0;"),
+    ("dual_quadratic_term",
+     "double phi = bu - uu / (2.0 * s->beta);",
+     "double phi = bu - uu / s->beta;"),
+    ("simplex_projection_divisor",
+     "double t = (csum - 1.0) / (double)(j + 1);",
+     "double t = (csum - 1.0) / (double)(j + 2);"),
+    ("multiplier_step_sign",
+     "s->ubar[i] = s->ubar[i] - s->beta * w;",
+     "s->ubar[i] = s->ubar[i] + s->beta * w;"),
+    ("vc_threshold_unscaled",
+     "            if (s2 < T) T = s2;\n        }\n        double cst = 0.0;\n"
+     "        for (int64_t j = 0; j < n; ++j) { sol[j] = x[j] >= T ? 1 : 0;",
+     "        }\n        double cst = 0.0;\n"
+     "        for (int64_t j = 0; j < n; ++j) { sol[j] = x[j] >= T ? 1 : 0;"),
+    ("philox_nine_rounds", "for (int round = 0; round < 10; ++round)", "for (int round = 0; round < 9; ++round)"),
+    ("cover_rounds_too_few",
+     "(int32_t)ceil(log(2.0 * (double)m))",
+     "(int32_t)ceil(log((double)m))"),
+    ("packing_alteration_strict",
+     "if (w2 >= w) tot += w2;",
+     "if (w2 > w) tot += w2;"),
+    ("map_argmax_ties_to_higher_label",
+     "for (int32_t a = 1; a < k; ++a) if (mu[a] > mu[l]) l = a;",
+     "for (int32_t a = 1; a < k; ++a) if (mu[a] >= mu[l]) l = a;"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_a_planted_mistake(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site of {name} not unique"
+    mutated = tmp_path / "thetis_oracle_mutant.c"
+    mutated.write_text(src.replace(old, new))
+    lib = tmp_path / "liborc_mutant.so"
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-o",
+                           str(lib), str(mutated), "-lm"])
+    env = dict(os.environ, THETIS_ORACLE_LIB=str(lib))
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+                          *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    # 0: every pin passed (the mistake survived); 2-5: the run itself broke
+    assert res.returncode not in (0, 2, 3, 4, 5), f"{name}: rc {res.returncode}\n{res.stdout[-2000:]}"

@@ -194,6 +194,35 @@ def test_cover_random_completes_short_rows_by_decreasing_x():
     assert 1 in seen and 2 in seen
 
 
+def test_cover_random_takes_the_union_of_ceil_ln_2m_rounds():
+    """Four rows of two sets each (b = 1, x = 0.3 everywhere): the union is
+    over t = ceil(ln 8) = 3 rounds of draws (reading R23: each row then stays
+    short with probability at most 1/(2m)); a row the draws leave uncovered
+    takes its larger scaled x, ties to the first entry.  Reproduced from
+    explicit Philox draws for 30 seeds."""
+    m = 4
+    inst = lp_from_rows([{2 * i: 1, 2 * i + 1: 1} for i in range(m)], [1] * m, [1] * (2 * m), 1)
+    lp = O.OracleLP(inst)
+    x = np.full(2 * m, 0.3)
+    t = int(np.ceil(np.log(2.0 * m)))
+    assert t == 3
+    for seed in range(30):
+        sol, cost, aux = lp.round(x, O.RULE_COVER_RAND, seed=seed, reps=1)
+        assert aux[0] == pytest.approx(0.4, abs=1e-15)
+        xt = np.minimum(1.0, x / (1.0 - aux[0]))
+        drawn = set()
+        for j in range(2 * m):
+            for r in range(t):
+                w = O.philox(np.array([0, j, 16 + r, 0], np.uint64), np.array([seed, 4], np.uint64))[0]
+                if (int(w) >> 11) * 2.0 ** -53 < xt[j]:
+                    drawn.add(j)
+        want = set(drawn)
+        for i in range(m):
+            if 2 * i not in drawn and 2 * i + 1 not in drawn:
+                want.add(2 * i)
+        assert set(np.nonzero(sol)[0]) == want, seed
+
+
 # ---------------------------------------------------------------- packing alteration
 
 @pytest.mark.parametrize("seed", range(4))
