@@ -62,6 +62,18 @@ MUTANTS = [
     ("packing_alteration_strict",
      "if (w2 >= w) tot += w2;",
      "if (w2 > w) tot += w2;"),
+    ("block_curvature_drops_beta",
+     "    return s->beta * best + s->rho;",
+     "    return best + s->rho;"),
+    ("class_order_descending",
+     "if (x->key != y->key) return x->key < y->key ? -1 : 1;",
+     "if (x->key != y->key) return x->key < y->key ? 1 : -1;"),
+    ("mis_threshold_not_strict",
+     "sol[j] = x[j] > T ? 1 : 0;",
+     "sol[j] = x[j] >= T ? 1 : 0;"),
+    ("region_growing_last_label_first",
+     "                lab[t] = (int32_t)ks[k - 1].idx;",
+     "                lab[t] = (int32_t)ks[0].idx;"),
     ("map_argmax_ties_to_higher_label",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] > mu[l]) l = a;",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] >= mu[l]) l = a;"),

@@ -371,6 +371,60 @@ def test_class_order_is_a_permutation():
         assert sorted(o.tolist()) == list(range(lp.nclasses))
 
 
+def numpy_philox_word(key, ctr):
+    """First word of Philox4x64-10 block `ctr` under `key`, from numpy's
+    generator (which advances its counter before each block)."""
+    c = np.array(ctr, dtype=np.uint64)
+    prev = c.copy()
+    for w in range(4):
+        if prev[w] != 0:
+            prev[w] -= np.uint64(1)
+            break
+        prev[w] = np.uint64(2**64 - 1)
+    return int(np.random.Philox(key=np.array(key, dtype=np.uint64), counter=prev).random_raw(1)[0])
+
+
+def test_class_order_follows_the_philox_words():
+    """Reading R13: in epoch e the classes run in increasing order of the
+    Philox word of counter (e, class, 0, 0) under key (seed, 1), ties by
+    class id; and a DET epoch is the serial steps of the units class by
+    class in that order."""
+    inst = I.vc_er(60, 150, seed=4)
+    lp = O.OracleLP(inst)
+    kind, uid, col = lp.units()
+    nc = lp.nclasses
+    for seed, epoch in [(3, 0), (3, 1), (11, 7)]:
+        words = [numpy_philox_word((seed, 1), (epoch, c, 0, 0)) for c in range(nc)]
+        want = sorted(range(nc), key=lambda c: (words[c], c))
+        assert lp.class_order(seed, epoch).tolist() == want
+    a = O.OracleSolver(lp, beta=5.0, seed=3)
+    a.run(1)
+    b = O.OracleSolver(lp, beta=5.0, seed=3)
+    words = [numpy_philox_word((3, 1), (0, c, 0, 0)) for c in range(nc)]
+    for c in sorted(range(nc), key=lambda c: (words[c], c)):
+        for t in np.nonzero(col == c)[0]:
+            b.step_unit(int(t))
+    assert np.array_equal(a.y, b.y)
+
+
+def test_mis_threshold_is_strict():
+    """Reading R9: MIS_THRESH keeps v iff x_v > max(1/2, max_e fl(x_u+x_v)/2).
+    At the all-1/2 point nothing is kept (keeping ties would take both ends
+    of every edge); a vertex at 0.6 whose neighbours sit at 0.4 is the only
+    one kept."""
+    inst = I.mis_regular(40, 3, seed=1)
+    lp = O.OracleLP(inst)
+    sol, cost, aux = lp.round(np.full(inst.n, 0.5), O.RULE_MIS_THRESH)
+    assert not sol.any() and cost == 0.0 and aux[0] == 0.5
+    x = np.full(inst.n, 0.5)
+    nbrs = [inst.col_idx[inst.row_ptr[i] + 1 - k] for i in range(inst.m) for k in (0, 1)
+            if inst.col_idx[inst.row_ptr[i] + k] == 0]
+    x[0], x[nbrs] = 0.6, 0.4
+    sol, cost, aux = lp.round(x, O.RULE_MIS_THRESH)
+    assert aux[0] == 0.5
+    assert np.nonzero(sol)[0].tolist() == [0]
+
+
 def test_kkt_projected_gradient_vanishes():
     """At convergence the projected-gradient residual of the box QP is ~0
     (the monotone LCP of Appendix A)."""
