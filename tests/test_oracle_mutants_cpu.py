@@ -74,6 +74,12 @@ MUTANTS = [
     ("region_growing_last_label_first",
      "                lab[t] = (int32_t)ks[k - 1].idx;",
      "                lab[t] = (int32_t)ks[0].idx;"),
+    ("step_scale_dropped",
+     "            yn = s->y[j] - s->gamma * g / L;",
+     "            yn = s->y[j] - g / L;"),
+    ("map_sampling_shifted_draw",
+     "                        if (l < 0 && u < cum) l = a;",
+     "                        if (l < 0 && u < cum - mu[a] * 0.5) l = a;"),
     ("map_argmax_ties_to_higher_label",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] > mu[l]) l = a;",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] >= mu[l]) l = a;"),

@@ -425,6 +425,20 @@ def test_mis_threshold_is_strict():
     assert np.nonzero(sol)[0].tolist() == [0]
 
 
+@pytest.mark.parametrize("gamma", [1.0, 0.5, 0.25])
+def test_step_scale_scales_the_coordinate_step(gamma):
+    """The scaled step y - gamma g / L (Algorithm 1 with a step factor):
+    single edge, c = (1, 1), beta 10, from y = 0 the residual is -1, so the
+    first vertex has g = 1 - 10 = -9 and L = 10: it moves to 0.9 gamma."""
+    inst = I.vc_lp(2, np.array([[0, 1]]), np.array([1.0, 1.0]))
+    lp = O.OracleLP(inst)
+    s = O.OracleSolver(lp, beta=10.0, step_scale=gamma)
+    kind, uid, col = lp.units()
+    t = int(np.nonzero((kind == 0) & (uid == 0))[0][0])
+    s.step_unit(t)
+    assert s.y[0] == pytest.approx(0.9 * gamma, abs=1e-15)
+
+
 def test_kkt_projected_gradient_vanishes():
     """At convergence the projected-gradient residual of the box QP is ~0
     (the monotone LCP of Appendix A)."""
