@@ -80,6 +80,18 @@ MUTANTS = [
     ("map_sampling_shifted_draw",
      "                        if (l < 0 && u < cum) l = a;",
      "                        if (l < 0 && u < cum - mu[a] * 0.5) l = a;"),
+    ("equality_violation_signed",
+     "(p->sense[i] < 0 ? ax - p->b[i] : fabs(ax - p->b[i]));",
+     "(p->sense[i] < 0 ? ax - p->b[i] : ax - p->b[i]);"),
+    ("prox_box_minimiser_sign",
+     "        double y = yb - red / rho;",
+     "        double y = yb + red / rho;"),
+    ("cover_threshold_divisor",
+     "            if (sm / (double)f < T) T = sm / (double)f;",
+     "            if (sm < T) T = sm;"),
+    ("subset_sum_skips_largest",
+     "            for (int64_t t = B - 1; t >= a; --t) if (reach[t - a]) reach[t] = 1;",
+     "            for (int64_t t = B - 2; t >= a; --t) if (reach[t - a]) reach[t] = 1;"),
     ("map_argmax_ties_to_higher_label",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] > mu[l]) l = a;",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] >= mu[l]) l = a;"),

@@ -146,21 +146,37 @@ def test_converged_penalty_matches_lbfgsb(seed):
     assert s.metrics()["F"] <= res.fun + 1e-10
 
 
-@pytest.mark.parametrize("seed", [3, 4])
-def test_dual_bound_weak_and_strong_duality(seed):
-    """Phi(u) <= F(y) along the whole run and meets it at convergence."""
+@pytest.mark.parametrize("seed,prox", [(3, False), (4, False), (5, True), (6, True)])
+def test_dual_bound_weak_and_strong_duality(seed, prox):
+    """Phi(u) <= F(y) along the whole run and meets it at convergence, with
+    the prox term too (then each column's minimum is the clipped minimiser
+    of red y + rho/2 (y - ybar)^2)."""
     rng = np.random.default_rng(seed)
     n = 15
     inst = I.vc_lp(n, random_graph(n, 0.3, rng), rng.uniform(1, 10, n))
+    yb = rng.uniform(0, 1, inst.n + inst.m) if prox else None
     lp = O.OracleLP(inst)
-    s = O.OracleSolver(lp, beta=10.0, schedule=O.SCHED_PERM, seed=seed)
+    s = O.OracleSolver(lp, beta=10.0, schedule=O.SCHED_PERM, seed=seed, prox=prox, ybar=yb)
     for _ in range(50):
         m = s.metrics()
         assert m["dual_bound"] <= m["F"] + 1e-12
         s.run(3)
-    _, s2 = converge(inst, 10.0)
+    _, s2 = converge(inst, 10.0, prox=prox, ybar=yb)
     m = s2.metrics()
     assert m["F"] - m["dual_bound"] < 1e-9
+
+
+def test_violation_of_equality_rows_is_absolute():
+    """The original-row violation: b - A x on '>=' rows, A x - b on '<='
+    rows, |A x - b| on equality rows (either side)."""
+    inst = I.LPInstance(m=2, n=3, row_ptr=np.array([0, 2, 4], np.int64), col_idx=np.array([0, 1, 1, 2], np.int32),
+                        val=None, b=np.array([1.0, 1.0]), c=np.ones(3), u=np.ones(3),
+                        sense=np.array([0, 1], np.int8))
+    lp = O.OracleLP(inst)
+    s = O.OracleSolver(lp)
+    for x, viol in (((0.8, 0.5, 0.9), 0.3), ((0.2, 0.6, 0.6), 0.2), ((0.5, 0.5, 0.2), 0.3)):
+        s.y = np.array(list(x) + [0.0, 0.0])
+        assert s.metrics()["max_viol"] == pytest.approx(viol, abs=1e-15)
 
 
 @pytest.mark.parametrize("seed", [5, 6, 7])
