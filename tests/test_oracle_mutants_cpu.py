@@ -92,6 +92,18 @@ MUTANTS = [
     ("subset_sum_skips_largest",
      "            for (int64_t t = B - 1; t >= a; --t) if (reach[t - a]) reach[t] = 1;",
      "            for (int64_t t = B - 2; t >= a; --t) if (reach[t - a]) reach[t] = 1;"),
+    ("block_gradient_drops_beta",
+     "        s->g[i] = s->ctil[j] + s->beta * dot + s->rho * (s->y[j] - s->ybar[j]);",
+     "        s->g[i] = s->ctil[j] + dot + s->rho * (s->y[j] - s->ybar[j]);"),
+    ("cover_completion_smallest_x",
+     "if (xt[j] > bx) { bx = xt[j]; pickc = j; ba = p->val[e]; }",
+     "if (bx < 0.0 || xt[j] < bx) { bx = xt[j]; pickc = j; ba = p->val[e]; }"),
+    ("mis_alteration_keeps_one_end",
+     "if (pick[a] && pick[b]) { drop[a] = 1; drop[b] = 1; }",
+     "if (pick[a] && pick[b]) { drop[a] = 1; }"),
+    ("cut_cost_not_halved",
+     "            cst *= 0.5;     /* each (edge,label) pair owns two rows */",
+     ""),
     ("map_argmax_ties_to_higher_label",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] > mu[l]) l = a;",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] >= mu[l]) l = a;"),
