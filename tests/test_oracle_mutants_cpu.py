@@ -104,6 +104,15 @@ MUTANTS = [
     ("cut_cost_not_halved",
      "            cst *= 0.5;     /* each (edge,label) pair owns two rows */",
      ""),
+    ("penalty_prox_term_doubled",
+     "            double d = s->y[j] - s->ybar[j];\n            f += 0.5 * s->rho * d * d;",
+     "            double d = s->y[j] - s->ybar[j];\n            f += s->rho * d * d;"),
+    ("uniform_schedule_never_draws_the_last_unit",
+     "(uint64_t)t, 0)) * (double)U);",
+     "(uint64_t)t, 0)) * (double)(U - 1));"),
+    ("perm_schedule_keeps_the_identity",
+     "            ks[t].key = ph_word(s->seed, ST_PERM, (uint64_t)s->epoch, (uint64_t)t, 0);",
+     "            ks[t].key = (uint64_t)t;"),
     ("map_argmax_ties_to_higher_label",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] > mu[l]) l = a;",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] >= mu[l]) l = a;"),

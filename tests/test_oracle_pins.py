@@ -441,6 +441,32 @@ def test_mis_threshold_is_strict():
     assert np.nonzero(sol)[0].tolist() == [0]
 
 
+@pytest.mark.parametrize("schedule,stream", [(O.SCHED_PERM, 3), (O.SCHED_UNIFORM, 2)])
+def test_perm_and_uniform_schedules_follow_their_philox_words(schedule, stream):
+    """Reading R4/R13 for the oracle-only schedules: in epoch e, PERM visits
+    every unit once, in increasing order of the Philox word of counter
+    (e, unit, 0, 0) under key (seed, 3); UNIFORM draws unit floor(u U) with
+    u the 53-bit uniform of counter (e, step, 0, 0) under key (seed, 2)
+    (with replacement).  Two epochs equal the same steps made by hand."""
+    inst = I.vc_er(30, 70, seed=2)
+    lp = O.OracleLP(inst)
+    U = len(lp.units()[0])
+    seed = 7
+    a = O.OracleSolver(lp, beta=5.0, schedule=schedule, seed=seed)
+    a.run(2)
+    b = O.OracleSolver(lp, beta=5.0, seed=seed)
+    for e in range(2):
+        words = [numpy_philox_word((seed, stream), (e, t, 0, 0)) for t in range(U)]
+        if schedule == O.SCHED_PERM:
+            seq = sorted(range(U), key=lambda t: (words[t], t))
+        else:
+            seq = [min(int(((w >> 11) * 2.0 ** -53) * U), U - 1) for w in words]
+            assert len(set(seq)) < U                 # with replacement
+        for t in seq:
+            b.step_unit(t)
+    assert np.array_equal(a.y, b.y)
+
+
 @pytest.mark.parametrize("gamma", [1.0, 0.5, 0.25])
 def test_step_scale_scales_the_coordinate_step(gamma):
     """The scaled step y - gamma g / L (Algorithm 1 with a step factor):
