@@ -113,6 +113,15 @@ MUTANTS = [
     ("perm_schedule_keeps_the_identity",
      "            ks[t].key = ph_word(s->seed, ST_PERM, (uint64_t)s->epoch, (uint64_t)t, 0);",
      "            ks[t].key = (uint64_t)t;"),
+    ("lp_dual_block_ignores_fixed_label",
+     "            if (p->fixed[t] >= 0 && i != p->fixed[t]) continue;\n            int64_t j = p->bfirst[t] + i;\n            double red = p->c[j];\n            for (int64_t e = p->cptr[j]; e < p->cptr[j + 1]; ++e) red -= p->cval[e] * u[p->ridx[e]];\n            if (red < best) best = red;",
+     "            int64_t j = p->bfirst[t] + i;\n            double red = p->c[j];\n            for (int64_t e = p->cptr[j]; e < p->cptr[j + 1]; ++e) red -= p->cval[e] * u[p->ridx[e]];\n            if (red < best) best = red;"),
+    ("lp_dual_unclipped_multiplier",
+     "        double ui = s->ubar[i];\n        if (p->sense[i] > 0 && ui < 0.0) ui = 0.0;",
+     "        double ui = s->ubar[i];\n        if (0 && p->sense[i] > 0 && ui < 0.0) ui = 0.0;"),
+    ("map_energy_pair_transposed",
+     "(int64_t)lab[p->pw_ends[2 * e]] * p->k + lab[p->pw_ends[2 * e + 1]]",
+     "(int64_t)lab[p->pw_ends[2 * e + 1]] * p->k + lab[p->pw_ends[2 * e]]"),
     ("map_argmax_ties_to_higher_label",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] > mu[l]) l = a;",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] >= mu[l]) l = a;"),
