@@ -122,6 +122,15 @@ MUTANTS = [
     ("map_energy_pair_transposed",
      "(int64_t)lab[p->pw_ends[2 * e]] * p->k + lab[p->pw_ends[2 * e + 1]]",
      "(int64_t)lab[p->pw_ends[2 * e + 1]] * p->k + lab[p->pw_ends[2 * e]]"),
+    ("recomputed_residual_slack_sign",
+     "        if (p->sense[i] > 0) acc -= s->y[p->n + i];\n        else if (p->sense[i] < 0) acc += s->y[p->n + i];\n        s->r[i] = acc - p->b[i];",
+     "        if (p->sense[i] > 0) acc += s->y[p->n + i];\n        else if (p->sense[i] < 0) acc -= s->y[p->n + i];\n        s->r[i] = acc - p->b[i];"),
+    ("mis_keep_draw_other_counter",
+     "                pick[j] = u53(ph_word(seed, ST_ROUND, (uint64_t)rep, (uint64_t)j, 0)) < xt ? 1 : 0;\n                drop[j] = 0;\n            }\n            for (int64_t i = 0; i < m; ++i) {\n                int32_t a",
+     "                pick[j] = u53(ph_word(seed, ST_ROUND, (uint64_t)rep, (uint64_t)j, 5)) < xt ? 1 : 0;\n                drop[j] = 0;\n            }\n            for (int64_t i = 0; i < m; ++i) {\n                int32_t a"),
+    ("region_growing_radius_other_counter",
+     "double rad = u53(ph_word(seed, ST_ROUND, (uint64_t)rep, 0, 1));",
+     "double rad = u53(ph_word(seed, ST_ROUND, (uint64_t)rep, 1, 1));"),
     ("map_argmax_ties_to_higher_label",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] > mu[l]) l = a;",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] >= mu[l]) l = a;"),

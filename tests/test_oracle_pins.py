@@ -467,6 +467,62 @@ def test_perm_and_uniform_schedules_follow_their_philox_words(schedule, stream):
     assert np.array_equal(a.y, b.y)
 
 
+def u53(w):
+    return (w >> 11) * 2.0 ** -53
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_mis_random_rounding_follows_its_philox_draws(seed):
+    """Readings R8/R9/R13: alpha = max_e (x_u + x_v - 1)_+, keep v iff the
+    53-bit uniform of counter (rep, v, 0, 0) under key (seed, 4) is below
+    x_v / (1 + alpha), then drop both ends of every edge kept twice."""
+    inst = I.mis_regular(24, 3, seed=seed)
+    lp = O.OracleLP(inst)
+    x = np.random.default_rng(seed).uniform(0, 0.8, inst.n)
+    ends = inst.col_idx.reshape(-1, 2)
+    alpha = max(0.0, float(np.max(x[ends[:, 0]] + x[ends[:, 1]] - 1.0)))
+    pick = np.array([u53(numpy_philox_word((seed, 4), (0, v, 0, 0))) < x[v] / (1.0 + alpha)
+                     for v in range(inst.n)])
+    drop = np.zeros(inst.n, bool)
+    for a, b in ends:
+        if pick[a] and pick[b]:
+            drop[a] = drop[b] = True
+    sol, cost, aux = lp.round(x, O.RULE_MIS_RAND, seed=seed, reps=1)
+    assert aux[0] == pytest.approx(alpha, abs=1e-15)
+    assert np.array_equal(sol.astype(bool), pick & ~drop)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_region_growing_follows_its_philox_draws(seed):
+    """Readings R10/R13: radius = the uniform of counter (rep, 0, 1, 0), the
+    labels ordered by the words of counters (rep, i, 2, 0) (ties by label);
+    each block takes the first of the first k-1 labels in that order whose
+    x is >= 1 - radius, else the last label."""
+    inst = I.mc_grid(side=5, k=4, seed=seed)
+    lp = O.OracleLP(inst)
+    nb, k = len(inst.block_first_col), inst.block_k
+    X = np.random.default_rng(seed).dirichlet(np.full(k, 0.4), nb)
+    term = np.asarray(inst.meta["terminals"])
+    X[term] = np.eye(k)[inst.fixed_label[term]]
+    x = np.zeros(inst.n)
+    for t, f in enumerate(inst.block_first_col):
+        x[f: f + k] = X[t]
+    rad = u53(numpy_philox_word((seed, 4), (0, 0, 1, 0)))
+    words = [numpy_philox_word((seed, 4), (0, i, 2, 0)) for i in range(k)]
+    order = sorted(range(k), key=lambda i: (words[i], i))
+    want = []
+    for t in range(nb):
+        lab = order[k - 1]
+        for i in order[: k - 1]:
+            if X[t, i] >= 1.0 - rad:
+                lab = i
+                break
+        want.append(lab)
+    sol, cost, aux = lp.round(x, O.RULE_MC_CKR, seed=seed, reps=1)
+    assert aux[0] == rad
+    assert sol.tolist() == want
+
+
 @pytest.mark.parametrize("gamma", [1.0, 0.5, 0.25])
 def test_step_scale_scales_the_coordinate_step(gamma):
     """The scaled step y - gamma g / L (Algorithm 1 with a step factor):
