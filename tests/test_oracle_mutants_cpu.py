@@ -131,6 +131,15 @@ MUTANTS = [
     ("region_growing_radius_other_counter",
      "double rad = u53(ph_word(seed, ST_ROUND, (uint64_t)rep, 0, 1));",
      "double rad = u53(ph_word(seed, ST_ROUND, (uint64_t)rep, 1, 1));"),
+    ("packing_alpha_not_relative",
+     "            double v = (ax - p->b[i]) / p->b[i];\n            if (v > alpha) alpha = v;",
+     "            double v = ax - p->b[i];\n            if (v > alpha) alpha = v;"),
+    ("packing_alteration_capacity_two",
+     "                    if (tot > 1.0) drop[j] = 1;",
+     "                    if (tot > 2.0) drop[j] = 1;"),
+    ("covering_alpha_ignores_q",
+     "double alpha = isinf(q) ? 0.0 : eps / q;",
+     "double alpha = isinf(q) ? 0.0 : eps;"),
     ("map_argmax_ties_to_higher_label",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] > mu[l]) l = a;",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] >= mu[l]) l = a;"),

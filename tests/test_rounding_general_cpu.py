@@ -194,6 +194,18 @@ def test_cover_random_completes_short_rows_by_decreasing_x():
     assert 1 in seen and 2 in seen
 
 
+@pytest.mark.parametrize("x,alpha", [((0.75, 0.75), 0.5), ((0.6, 0.9), 0.5), ((0.9, 0.95), 0.15)])
+def test_cover_random_scales_by_eps_over_q(x, alpha):
+    """The covering lemma's alpha = eps / q(P): the row 2 x0 + 2 x1 >= 4 has
+    q = 4 - 2 = 2 (its subset sums are 0, 2, 4), so a violation eps gives
+    alpha = eps / 2."""
+    inst = lp_from_rows([{0: 2, 1: 2}], [4], [1, 1], 1)
+    lp = O.OracleLP(inst)
+    assert lp.cover_q() == 2.0
+    sol, cost, aux = lp.round(np.array(x), O.RULE_COVER_RAND, seed=0, reps=1)
+    assert aux[0] == pytest.approx(alpha, abs=1e-15)
+
+
 def test_cover_random_takes_the_union_of_ceil_ln_2m_rounds():
     """Four rows of two sets each (b = 1, x = 0.3 everywhere): the union is
     over t = ceil(ln 8) = 3 rounds of draws (reading R23: each row then stays
