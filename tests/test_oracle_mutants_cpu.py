@@ -9,8 +9,6 @@ import os
 import subprocess
 import sys
 
-import pytest
-
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "thetis_oracle.c")
 PINS = ["tests/test_oracle_pins.py", "tests/test_multipliers_cpu.py", "tests/test_rounding_general_cpu.py",
@@ -146,17 +144,33 @@ MUTANTS = [
 ]
 
 
-@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_pins_catch_a_planted_mistake(tmp_path, name, old, new):
+def run_mutant(tmp_path, name, old, new):
+    """Builds one mutant and runs the pins against it in a child process;
+    returns None when a pin failed, else a description of the survival."""
     src = open(SRC).read()
-    assert src.count(old) == 1, f"mutation site of {name} not unique"
-    mutated = tmp_path / "thetis_oracle_mutant.c"
+    if src.count(old) != 1:
+        return f"{name}: mutation site not unique"
+    d = tmp_path / name
+    d.mkdir()
+    mutated = d / "thetis_oracle_mutant.c"
     mutated.write_text(src.replace(old, new))
-    lib = tmp_path / "liborc_mutant.so"
+    lib = d / "liborc_mutant.so"
     subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-o",
                            str(lib), str(mutated), "-lm"])
     env = dict(os.environ, THETIS_ORACLE_LIB=str(lib))
     res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
                           *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     # 0: every pin passed (the mistake survived); 2-5: the run itself broke
-    assert res.returncode not in (0, 2, 3, 4, 5), f"{name}: rc {res.returncode}\n{res.stdout[-2000:]}"
+    if res.returncode in (0, 2, 3, 4, 5):
+        return f"{name}: rc {res.returncode}\n{res.stdout[-1500:]}"
+    return None
+
+
+def test_pins_catch_every_planted_mistake(tmp_path):
+    """The mutants run side by side (one child process each)."""
+    import concurrent.futures as cf
+    workers = max(1, min(8, os.cpu_count() or 1))
+    with cf.ThreadPoolExecutor(workers) as pool:
+        out = list(pool.map(lambda m: run_mutant(tmp_path, *m), MUTANTS))
+    survivors = [o for o in out if o is not None]
+    assert not survivors, "\n\n".join(survivors)
