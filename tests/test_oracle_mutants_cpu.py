@@ -138,6 +138,12 @@ MUTANTS = [
     ("covering_alpha_ignores_q",
      "double alpha = isinf(q) ? 0.0 : eps / q;",
      "double alpha = isinf(q) ? 0.0 : eps;"),
+    ("global_lmax_not_the_maximum",
+     "        if (s->L[t] > s->Lmax) s->Lmax = s->L[t];\n    }\n    return s;",
+     "        if (t == 0) s->Lmax = s->L[t];\n    }\n    return s;"),
+    ("colouring_ignores_earlier_conflicts",
+     "                    if (o >= 0 && o < t) stamp[p->ucolour[o]] = t;",
+     "                    if (o >= 0 && o < t - 1) stamp[p->ucolour[o]] = t;"),
     ("map_argmax_ties_to_higher_label",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] > mu[l]) l = a;",
      "for (int32_t a = 1; a < k; ++a) if (mu[a] >= mu[l]) l = a;"),
