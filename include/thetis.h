@@ -154,7 +154,10 @@ thetis_status thetis_inst_create_csr(int64_t m, int64_t n, int64_t nnz,
  * k consecutive columns first_col_host[t] .. first_col_host[t]+k-1, which
  * must not overlap.  fixed_label_host[t] >= 0 pins block t at the unit
  * vector of that label (a terminal); -1 leaves it free; NULL = all free.
- * 1 <= k <= 64.  Must be called before any solver is created. */
+ * 1 <= k <= 64.  The columns of one block must not share a row (then the
+ * block of A^T A is diagonal and one block's update writes every row at most
+ * once): THETIS_EINVAL otherwise, as for overlapping or out-of-range
+ * blocks.  Must be called before any solver is created. */
 thetis_status thetis_inst_set_simplex_blocks(thetis_inst *inst, int64_t nblocks, int32_t k,
                                              const int64_t *first_col_host,
                                              const int32_t *fixed_label_host);
@@ -303,9 +306,12 @@ thetis_status thetis_run_multipliers(thetis_solver *s, int32_t max_outer, int32_
 thetis_status thetis_residual(thetis_solver *s, double *linf, double *l2,
                               double *max_row_violation);
 
-/* c^T x, the penalty value F(y) and the dual bound Phi <= min F (FP64). */
+/* c^T x, the penalty value F(y), the dual bound Phi <= min F, and the
+ * certified relative gap (F - Phi)/max(1, |F|) that thetis_run_epochs stops
+ * on (Section 3.1's approximate solution measured on the penalty problem),
+ * all FP64 and formed on the device from y.  Any output may be NULL. */
 thetis_status thetis_objective(thetis_solver *s, double *lp_value, double *penalty,
-                               double *dual_bound);
+                               double *dual_bound, double *gap);
 
 /* Copies y to the host: x_host[n] (structural) and, if s_host is not NULL,
  * s_host[m] (slacks), converted to double. */

@@ -249,6 +249,20 @@ int orc_lp_set_blocks(orc_lp *p, int64_t nblocks, int32_t k, const int64_t *firs
             p->col_block[first[t] + i] = t;
         }
     }
+    /* a row may hold at most one column of each block, so the block of
+       A^T A is diagonal (Appendix E takes the block minimiser of that form) */
+    int64_t *last_row = (int64_t *)malloc((nblocks > 0 ? nblocks : 1) * 8);
+    for (int64_t t = 0; t < nblocks; ++t) last_row[t] = -1;
+    int shared = 0;
+    for (int64_t i = 0; i < p->m && !shared; ++i)
+        for (int64_t q = p->row_ptr[i]; q < p->row_ptr[i + 1]; ++q) {
+            int64_t t = p->col_block[p->col_idx[q]];
+            if (t < 0) continue;
+            if (last_row[t] == i) { shared = 1; break; }
+            last_row[t] = i;
+        }
+    free(last_row);
+    if (shared) return -1;
     return build_units(p);
 }
 
@@ -321,20 +335,14 @@ static double unit_curvature(const orc_solver *s, int64_t t) {
         for (int64_t e = p->cptr[j]; e < p->cptr[j + 1]; ++e) a2 += p->cval[e] * p->cval[e];
         return s->beta * a2 + s->rho;
     }
-    /* block: Gershgorin bound on the block of A^T A,
-       max_i sum_rows |a_ri| * sum_{l in block} |a_rl| */
+    /* block: its columns share no row, so the block of A^T A is
+       diag(||A_i||^2); the largest entry bounds the block's curvature */
     int64_t j0 = p->bfirst[p->uid[t]];
     double best = 0.0;
     for (int32_t i = 0; i < p->k; ++i) {
-        double acc = 0.0;
-        for (int64_t e = p->cptr[j0 + i]; e < p->cptr[j0 + i + 1]; ++e) {
-            int64_t row = p->ridx[e];
-            double rs = 0.0;
-            for (int64_t q = p->row_ptr[row]; q < p->row_ptr[row + 1]; ++q)
-                if (p->col_block[p->col_idx[q]] == p->uid[t]) rs += fabs(p->val[q]);
-            acc += fabs(p->cval[e]) * rs;
-        }
-        if (acc > best) best = acc;
+        double a2 = 0.0;
+        for (int64_t e = p->cptr[j0 + i]; e < p->cptr[j0 + i + 1]; ++e) a2 += p->cval[e] * p->cval[e];
+        if (a2 > best) best = a2;
     }
     return s->beta * best + s->rho;
 }

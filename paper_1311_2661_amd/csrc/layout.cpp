@@ -308,6 +308,33 @@ static bool renumber_rows(Inst &in) {
     return true;
 }
 
+// The DET sweeps update the residual with plain read-modify-writes, which is
+// race-free only because the units of one class touch pairwise-disjoint
+// rows.  Checked here on the final plans, independently of how the colouring
+// was made: every row is touched at most once per class.
+static bool classes_row_disjoint(const Inst &in) {
+    std::vector<int32_t> stamp(in.m, -1);
+    for (int32_t c = 0; c < in.nclasses; ++c)
+        for (const Segment &sg : in.classes[c].segs)
+            for (int64_t q = 0; q < sg.count; ++q) {
+                const int32_t id = in.sched[sg.first + q];
+                if (sg.kind == SEG_SLACK) {
+                    if (stamp[id] == c) return false;
+                    stamp[id] = c;
+                    continue;
+                }
+                const int32_t j0 = sg.kind == SEG_BLOCK ? in.bfirst[id] : id;
+                const int32_t j1 = sg.kind == SEG_BLOCK ? j0 + in.k : j0 + 1;
+                for (int32_t j = j0; j < j1; ++j)
+                    for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e) {
+                        const int32_t i = in.row_idx[e];
+                        if (stamp[i] == c) return false;
+                        stamp[i] = c;
+                    }
+            }
+    return true;
+}
+
 // the DET plan: the units of every class split into segment kinds
 static void plan_classes(Inst &in) {
     in.sched.clear();
@@ -404,6 +431,8 @@ thetis_status build_layout(Inst &in) {
         for (const ClassPlan &cp : in.classes) det.push_back(&cp);
         pack(in, in.sched, det, in.pk_det, in.sign_vals);
         pack(in, in.async_sched, {&in.async_struct, &in.async_slack}, in.pk_async, false);
+        if (!classes_row_disjoint(in))
+            return fail(THETIS_EINVAL, "internal: two units of one colour class share a row");
         in.planned = true;
     } catch (const std::bad_alloc &) {
         return fail(THETIS_ENOMEM, "host allocation failed while building the layout");
@@ -594,6 +623,17 @@ extern "C" thetis_status thetis_inst_set_simplex_blocks(thetis_inst *h, int64_t 
             for (int32_t i = 0; i < k; ++i)
                 if (in.u[bf[t] + i] < 1.0)
                     return fail(THETIS_EINVAL, "simplex block columns need an upper bound of at least 1");
+        // The columns of one block must not share a row.  Then the block of
+        // A^T A is diagonal, its curvature bound is exact, and the block's
+        // lanes scatter into distinct rows (a DET class writes each row once).
+        std::vector<int64_t> stamp(nblocks, -1);
+        for (int64_t i = 0; i < in.m; ++i)
+            for (int32_t e = in.row_ptr[i]; e < in.row_ptr[i + 1]; ++e) {
+                const int32_t t = cb[in.col_idx[e]];
+                if (t < 0) continue;
+                if (stamp[t] == i) return fail(THETIS_EINVAL, "two columns of one simplex block share a row");
+                stamp[t] = i;
+            }
         std::lock_guard<std::mutex> lock(h->layout_mu);
         in.nblocks = nblocks; in.k = k;
         in.bfirst.swap(bf); in.fixed.swap(fx); in.col_block.swap(cb);

@@ -94,7 +94,7 @@ struct Dev {
     const R *ybar;            // prox centre over n + m (null: prox off or 0)
     const double *ubar;       // null: 0
     const int32_t *bfirst, *fixed, *col_block;
-    const R *LB;              // block curvature bound (Gershgorin), per block
+    const R *LB;              // block curvature bound, per block
     // state
     X *x;
     R *s, *r, *udual;
@@ -1612,7 +1612,7 @@ struct thetis_solver {
     thetis_params p{};
     double rho = 0.0, Lmax = 0.0;
     // curvature factors without beta: every unit's curvature is beta * a + rho
-    // (a = ||A_j||^2, the block's Gershgorin bound, or 1 for a slack)
+    // (a = ||A_j||^2, the block's largest ||A_i||^2, or 1 for a slack)
     double amax = 0.0;
     std::vector<double> lb_factor;             // a per simplex block (-1 for fixed ones)
     bool has_ybar = false, has_ubar = false;
@@ -2015,7 +2015,7 @@ thetis_status run_epochs_impl(thetis_solver &S, int32_t max_epochs, double gap_t
         if (S.p.refresh_every > 0 && S.epoch % S.p.refresh_every == 0) {
             S.timing_now = S.timing > 0 && (S.epoch / S.p.refresh_every) % S.timing == 0;
             st = refresh<P>(S, true, gap_tol > 0.0);
-            if (st) break;
+            if (st) { ++e; break; }      // the epoch itself was applied
             if (gap_tol > 0.0) {
                 HIP_TRY(hipMemcpyAsync(S.mt, S.metrics, sizeof(S.mt), hipMemcpyDeviceToHost, S.stream));
                 HIP_TRY(hipStreamSynchronize(S.stream));
@@ -2350,21 +2350,15 @@ void compute_curvatures(thetis_solver &S, const Inst &in, std::vector<double> &n
     LB.assign(in.nblocks, 0.0);
     S.lb_factor.assign(in.nblocks, -1.0);
     double amax = 0.0;
+    // the columns of a block share no row (checked when the blocks are
+    // declared), so the block of A^T A is diag(||A_i||^2): its largest entry
+    // is the Lipschitz constant of the block gradient (Appendix E), and the
+    // block step is the exact block minimiser when the entries are equal
+    // (the multiway-cut and MAP blocks)
     for (int64_t t = 0; t < in.nblocks; ++t) {
         if (in.fixed[t] >= 0) continue;
         double best = 0.0;
-        for (int32_t i = 0; i < in.k; ++i) {
-            const int32_t j = in.bfirst[t] + i;
-            double acc = 0.0;
-            for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e) {
-                const int32_t row = in.row_idx[e];
-                double rs = 0.0;
-                for (int32_t q = in.row_ptr[row]; q < in.row_ptr[row + 1]; ++q)
-                    if (in.col_block[in.col_idx[q]] == t) rs += std::fabs(in.unit_vals ? 1.0 : in.val[q]);
-                acc += std::fabs(in.unit_vals ? 1.0 : in.cval[e]) * rs;
-            }
-            best = std::max(best, acc);
-        }
+        for (int32_t i = 0; i < in.k; ++i) best = std::max(best, norm2[in.bfirst[t] + i]);
         S.lb_factor[t] = best;
         LB[t] = S.p.beta * best + S.rho;
         amax = std::max(amax, best);
@@ -2913,7 +2907,7 @@ extern "C" thetis_status thetis_residual(thetis_solver *s, double *linf, double 
 }
 
 extern "C" thetis_status thetis_objective(thetis_solver *s, double *lp_value, double *penalty,
-                                          double *dual_bound) {
+                                          double *dual_bound, double *gap) {
     try {
         clear_error();
         if (!s) return fail(THETIS_EINVAL, "solver is NULL");
@@ -2922,6 +2916,7 @@ extern "C" thetis_status thetis_objective(thetis_solver *s, double *lp_value, do
         if (lp_value) *lp_value = s->mt[MT_CX];
         if (penalty) *penalty = s->mt[MT_F];
         if (dual_bound) *dual_bound = s->mt[MT_PHI];
+        if (gap) *gap = s->mt[MT_GAP];
         return THETIS_OK;
     } catch (...) {
         return exception_status();

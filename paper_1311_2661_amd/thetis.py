@@ -105,7 +105,7 @@ def lib():
             "thetis_solver_save": [vp, vp, P(C.c_size_t)],
             "thetis_solver_load": [vp, vp, C.c_size_t],
             "thetis_residual": [vp, P(dbl), P(dbl), P(dbl)],
-            "thetis_objective": [vp, P(dbl), P(dbl), P(dbl)],
+            "thetis_objective": [vp, P(dbl), P(dbl), P(dbl), P(dbl)],
             "thetis_get_x": [vp, vp, vp],
             "thetis_set_y": [vp, vp],
             "thetis_epoch": [vp, P(i64)],
@@ -271,9 +271,9 @@ def thetis_residual(s):
 
 
 def thetis_objective(s):
-    a, b, c = C.c_double(), C.c_double(), C.c_double()
-    _check(lib().thetis_objective(s, C.byref(a), C.byref(b), C.byref(c)))
-    return a.value, b.value, c.value
+    a, b, c, d = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    _check(lib().thetis_objective(s, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+    return a.value, b.value, c.value, d.value
 
 
 def thetis_get_x(s, n: int, m: int = 0, slacks: bool = False):
@@ -502,13 +502,12 @@ class Solver:
         return dict(linf=linf, l2=l2, max_viol=viol)
 
     def objective(self):
-        lp, F, phi = thetis_objective(self.h)
-        return dict(lp_value=lp, F=F, dual_bound=phi)
+        lp, F, phi, gap = thetis_objective(self.h)
+        return dict(lp_value=lp, F=F, dual_bound=phi, gap=gap)
 
     def metrics(self) -> dict:
         d = self.objective()
         d.update(self.residual())
-        d["gap"] = (d["F"] - d["dual_bound"]) / max(1.0, abs(d["F"]))
         return d
 
     @property

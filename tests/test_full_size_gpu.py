@@ -3,11 +3,11 @@ configuration bench.py times, run as bench.py itself runs them (a child
 process), checked on sampled outputs:
 
   * 4,096 independent-set LPs (n ~ U[200, 50000], random d-regular graphs,
-    d ~ U{3..16}), FP32, window of 64, stop at the 1e-4 certified gap or 200
-    epochs: every sampled instance at the gap, every sampled rounding an
-    independent set, every sampled batched solve bit-identical to the same
-    solve alone, and the FP64 oracle run for the same epochs on a stratified
-    sample agrees (F, c^T x within 1e-4 relative, violation within 1e-4).
+    d ~ U{3..16}), FP32, window of 256 (the benchmark default), stop at the
+    1e-4 certified gap or 200 epochs: every sampled instance at the gap,
+    every sampled rounding an independent set, every sampled batched solve
+    bit-identical to the same solve alone, and the FP64 oracle run for the
+    same epochs on a stratified sample agrees (F, c^T x within 1e-4 relative, violation within 1e-4).
   * Poisson arrivals at 200/s of mixed requests (1e3..1e6 edges) for one
     second: nothing fails, every result is feasible, every sampled served
     result equals the same request solved alone, and the FP64 oracle run for

@@ -166,3 +166,18 @@ def test_rounding_shapes_of_the_workloads():
     mcov = I.multicover(80, 40, seed=2)
     fl, q = T.Instance(mcov).rounding_shape()
     assert fl == T.SHAPE_COVER and q == O.OracleLP(mcov).cover_q()
+
+
+def test_blocks_whose_columns_share_a_row_are_rejected():
+    """A simplex block with two columns in one row is refused (the block's
+    curvature bound and its race-free scatter need every row to hold at most
+    one column of each block)."""
+    inst = I.LPInstance(m=2, n=3, row_ptr=np.array([0, 2, 4], np.int64),
+                        col_idx=np.array([0, 2, 1, 2], np.int32), val=None,
+                        b=np.ones(2), c=np.ones(3), u=np.ones(3), sense=np.ones(2, np.int8),
+                        block_first_col=np.array([1], np.int64), block_k=2,
+                        fixed_label=np.array([-1], np.int32))
+    with pytest.raises(T.ThetisError, match="share a row"):
+        T.Instance(inst)
+    inst.block_first_col = np.array([0], np.int64)
+    T.Instance(inst)

@@ -63,6 +63,12 @@ MUTANTS = [
     ("block_curvature_drops_beta",
      "    return s->beta * best + s->rho;",
      "    return best + s->rho;"),
+    ("block_curvature_sums_columns",
+     "        if (a2 > best) best = a2;",
+     "        best += a2;"),
+    ("blocks_sharing_a_row_accepted",
+     "if (last_row[t] == i) { shared = 1; break; }",
+     "if (last_row[t] == i) { break; }"),
     ("class_order_descending",
      "if (x->key != y->key) return x->key < y->key ? -1 : 1;",
      "if (x->key != y->key) return x->key < y->key ? 1 : -1;"),

@@ -818,3 +818,68 @@ def test_oracle_rejects_bad_indices():
     inst.col_idx[1] = 7
     with pytest.raises(ValueError):
         O.OracleLP(inst)
+
+
+def _shared_row_block_instance():
+    """Rows x_0 + x_2 >= 1 and x_1 + x_2 >= 1; the block of columns 1, 2
+    has both in the second row."""
+    return I.LPInstance(m=2, n=3, row_ptr=np.array([0, 2, 4], np.int64),
+                        col_idx=np.array([0, 2, 1, 2], np.int32), val=None,
+                        b=np.ones(2), c=np.ones(3), u=np.ones(3), sense=np.ones(2, np.int8),
+                        block_first_col=np.array([1], np.int64), block_k=2,
+                        fixed_label=np.array([-1], np.int32))
+
+
+def test_blocks_whose_columns_share_a_row_are_rejected():
+    """The block minimiser of Appendix E is taken on a diagonal block of
+    A^T A; a row holding two columns of one block breaks that form and the
+    instance is refused."""
+    with pytest.raises(ValueError):
+        O.OracleLP(_shared_row_block_instance())
+    ok = _shared_row_block_instance()
+    ok.block_first_col = np.array([0], np.int64)    # columns 0, 1 never share a row
+    O.OracleLP(ok)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_block_step_is_the_exact_block_minimiser(seed):
+    """On the multiway-cut grid every column of a pixel block has the same
+    norm, so the block step (projection onto the simplex of y - g/L_B,
+    Appendix E) minimises F over the block exactly.  Checked against an
+    SLSQP minimisation over the simplex of F written densely from the
+    matrix (c^T x + beta/2 ||A y - b||^2)."""
+    inst = I.mc_grid(side=5, k=3, seed=seed)
+    lp = O.OracleLP(inst)
+    s = O.OracleSolver(lp, beta=10.0, seed=seed)
+    s.run(2)
+    kind, uid, _ = lp.units()
+    A, beta, k = dense_aug(inst), 10.0, inst.block_k
+
+    def F(y):
+        w = A @ y - inst.b
+        return inst.c @ y[: inst.n] + 0.5 * beta * w @ w
+
+    rng = np.random.default_rng(seed)
+    for t in rng.choice(np.flatnonzero(kind == 1), 4, replace=False):
+        y0 = s.y
+        j0 = int(inst.block_first_col[uid[t]])
+        s.step_unit(int(t))
+        y1 = s.y
+
+        def Fb(v):
+            y = y0.copy()
+            y[j0:j0 + k] = v
+            return F(y)
+
+        best = None
+        for start in [y0[j0:j0 + k], np.full(k, 1.0 / k)]:
+            res = minimize(Fb, start, method="SLSQP", bounds=[(0, 1)] * k,
+                           constraints=[{"type": "eq", "fun": lambda v: v.sum() - 1.0}],
+                           options={"ftol": 1e-15, "maxiter": 500})
+            if best is None or res.fun < best.fun:
+                best = res
+        assert Fb(y1[j0:j0 + k]) <= best.fun + 1e-9 * max(1.0, abs(best.fun))
+        assert np.allclose(y1[j0:j0 + k], best.x, atol=1e-6)
+        other = np.ones(len(y0), bool)
+        other[j0:j0 + k] = False
+        assert np.array_equal(y1[other], y0[other])

@@ -358,19 +358,38 @@ def test_fp32_multiway_cut_parity():
     assert np.array_equal(sol[inst.meta["terminals"]], np.arange(8))
 
 
-def test_async_schedule_converges_to_the_oracle_value():
-    """ASYNC (atomics, nondeterministic order) at convergence: F within 1e-4."""
-    say("case async vc_er")
-    inst = I.vc_er(1000, 5000, seed=3)
-    g = gpu_solver(inst, beta=10.0, schedule=T.SCHED_ASYNC, step_scale=0.5, precision=T.PREC_FP32, seed=3)
-    lp, o = oracle_solver(inst, beta=10.0, seed=3)
-    g.run(600, gap_tol=1e-6)
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_async_schedule_converges_to_the_oracle_value(seed):
+    """ASYNC (atomics, nondeterministic order; P-ASYNC) on the small vertex
+    cover workload (G(1000, 5000), beta 10) at convergence: both runs to a
+    certified gap below 1e-6, F within 1e-4 relative, and the rounding equal
+    to the oracle's on every vertex whose oracle margin exceeds
+    max|x - x64| + |T - T64|; for these seeds no vertex is inside that band,
+    so the covers are identical."""
+    say(f"case async vc_er seed={seed}")
+    inst = I.vc_er(1000, 5000, seed=seed)
+    g = gpu_solver(inst, beta=10.0, schedule=T.SCHED_ASYNC, step_scale=0.5, precision=T.PREC_FP32, seed=seed)
+    lp, o = oracle_solver(inst, beta=10.0, seed=seed)
+    done = g.run(3000, gap_tol=1e-6)
     o.run(600)
     gm, om = g.metrics(), o.metrics()
     assert om["gap"] < 1e-6
+    assert gm["gap"] <= 1e-6 + 1e-12, (done, gm["gap"])
     assert rel(gm["F"], om["F"]) <= 1e-4
-    sol, _, _ = g.round(T.ROUND_VC_THRESH)
+    sol, cost, aux = g.round(T.ROUND_VC_THRESH)
     assert g.check(T.ROUND_VC_THRESH) == (True, 0)
+    ox = o.x
+    osol, ocost, oaux = lp.round(ox, O.RULE_VC_THRESH)
+    err = float(np.abs(g.x - ox).max())
+    dT = abs(aux[0] - oaux[0])
+    margin = np.abs(ox - oaux[0])
+    band = margin <= err + dT
+    diff = sol != osol
+    say(f"  epochs {done}; max|x-x64|={err:.3e} |dT|={dT:.2e} inside band={int(band.sum())} "
+        f"differing={int(diff.sum())}")
+    assert np.all(band[diff])
+    assert int(band.sum()) == 0
+    assert np.array_equal(sol, osol)
 
 
 def test_gap_stop_and_reset():
@@ -402,59 +421,107 @@ def test_degenerate_instances():
     assert g.metrics()["F"] == pytest.approx(1 - 1 / 20, abs=1e-12)
 
 
-@pytest.mark.timeout(600)
+@pytest.mark.timeout(900)
 def test_full_size_ba_config_parity():
     """The benchmark workload at full size and in the benchmark's launch
-    configuration (BA n = 2,000,000, FP32, refresh every 5, 100 epochs, DET)
-    against the FP64 oracle run in the same class order.  F and c^T x within
-    1e-4 relative, violation within 1e-4; the rounded cover equals the
-    oracle's on every vertex whose margin to the threshold exceeds its own
-    FP32 deviation plus the threshold's deviation."""
+    configuration (BA n = 2,000,000, refresh every 5, 100 epochs, DET)
+    against the FP64 oracle run once in the same class order.
+
+    FP64 storage (P-DET64): iterates within 1e-10, and every vertex's oracle
+    margin to the threshold T exceeds that deviation plus T's own, so the
+    rounded cover is bit-identical (asserted) and the smallest margin is
+    asserted above 1e-10.
+
+    FP32 storage (production): F and c^T x within 1e-4 relative, violation
+    within 1e-4; the rounded cover equals the oracle's on every vertex whose
+    margin exceeds its own FP32 deviation plus the threshold's deviation.
+    The count inside that band and the count that differ are asserted at
+    the values measured for this seed (recorded with the design notes)."""
     import time
-    say("case full-size vc_ba n=2000000, 100 epochs")
+    say("case full-size vc_ba n=2000000, 100 epochs: oracle")
     t0 = time.time()
     inst = I.vc_ba(2_000_000, seed=0)
+    lp, o = oracle_solver(inst, beta=10.0, seed=0)
+    o.run(100)
+    om = o.metrics()
+    ox = o.x
+    osol, ocost, oaux = lp.round(ox, O.RULE_VC_THRESH)
+    margin = np.abs(ox - oaux[0])
+    say(f"  oracle done {time.time() - t0:.1f} s; F {om['F']:.12g}; T {oaux[0]:.6g}; "
+        f"min margin {margin.min():.3e}")
+    e = inst.meta["edges"]
+
+    say("case full-size vc_ba n=2000000, 100 epochs: FP64 storage")
+    g = gpu_solver(inst, beta=10.0, precision=T.PREC_FP64, refresh_every=5, seed=0)
+    g.run(100)
+    gm = g.metrics()
+    gx = g.x
+    sol, cost, aux = g.round(T.ROUND_VC_THRESH)
+    dx = float(np.abs(gx - ox).max())
+    dT = abs(aux[0] - oaux[0])
+    say(f"  fp64: max|x-x64|={dx:.3e} |dT|={dT:.2e} min margin={margin.min():.3e} "
+        f"differing={int((sol != osol).sum())}")
+    assert dx <= 1e-10
+    assert margin.min() > 1e-10
+    assert margin.min() > dx + dT
+    assert np.array_equal(sol, osol)
+    assert cost == pytest.approx(ocost, rel=1e-12)
+    for k in ("F", "lp_value", "dual_bound", "max_viol"):
+        assert rel(gm[k], om[k]) < 1e-11, (k, gm[k], om[k])
+    assert g.check(T.ROUND_VC_THRESH) == lp.check(O.RULE_VC_THRESH, osol) == (True, 0)
+    g.close()
+    del g
+
+    say("case full-size vc_ba n=2000000, 100 epochs: FP32 storage")
     g = gpu_solver(inst, beta=10.0, precision=T.PREC_FP32, refresh_every=5, seed=0)
     g.run(100)
     gm = g.metrics()
     sol, cost, aux = g.round(T.ROUND_VC_THRESH)
     assert g.check(T.ROUND_VC_THRESH) == (True, 0)
     gx = g.x
-    say(f"  gpu done {time.time() - t0:.1f} s; F {gm['F']:.10g}")
-    lp, o = oracle_solver(inst, beta=10.0, seed=0)
-    o.run(100)
-    om = o.metrics()
-    say(f"  oracle done {time.time() - t0:.1f} s; F {om['F']:.10g}")
+    say(f"  fp32: F {gm['F']:.10g} vs {om['F']:.10g}; lp {gm['lp_value']:.10g} vs {om['lp_value']:.10g}; "
+        f"viol {gm['max_viol']:.4e} vs {om['max_viol']:.4e}")
     assert rel(gm["F"], om["F"]) <= 1e-4
     assert rel(gm["lp_value"], om["lp_value"]) <= 1e-4
     assert abs(gm["max_viol"] - om["max_viol"]) <= 1e-4
     assert gm["dual_bound"] <= gm["F"]
-    ox = o.x
-    osol, ocost, oaux = lp.round(ox, O.RULE_VC_THRESH)
     dx = np.abs(gx - ox)
     dT = abs(aux[0] - oaux[0])
-    margin = np.abs(ox - oaux[0])
     diff = sol != osol
-    say(f"  max|x-x64|={dx.max():.3e} |dT|={dT:.2e} differing vertices={int(diff.sum())} "
-        f"inside band={int((margin <= dx + dT).sum())}")
-    assert np.all(margin[diff] <= dx[diff] + dT)
+    band = margin <= dx + dT
+    say(f"  fp32: max|x-x64|={dx.max():.3e} |dT|={dT:.2e} differing vertices={int(diff.sum())} "
+        f"inside band={int(band.sum())}")
+    assert np.all(band[diff])
+    assert (int(band.sum()), int(diff.sum())) == FP32_BA_BAND_COUNTS
     assert cost == pytest.approx(ocost, rel=1e-4)
-    e = inst.meta["edges"]
     assert np.all(sol[e[:, 0]] | sol[e[:, 1]])
 
 
-@pytest.mark.timeout(600)
-def test_full_size_multiway_cut_one_epoch_from_the_same_state():
+# measured for seed 0 (BA n = 2M, 100 epochs, refresh 5): vertices whose
+# oracle margin lies inside |x - x64| + |T - T64|, and vertices whose
+# rounding differs (all of them inside the band)
+FP32_BA_BAND_COUNTS = (None, None)
+
+
+@pytest.mark.timeout(1200)
+def test_full_size_multiway_cut_200_epochs():
     """The multiway-cut workload at full size (1024 x 1024 grid, k = 8, FP32,
-    refresh every 5, DET) in the benchmark's launch configuration.  After 195
-    epochs (a refresh epoch: the residual is the FP64 one rounded once) the
+    refresh every 5, DET) in the benchmark's launch configuration.
+
+    One epoch from the same state: after 195 epochs (a refresh epoch) the
     GPU state goes to the FP64 oracle and both run epoch 196 in the same
-    class order: every coordinate agrees within 1e-4 and F within 1e-6
-    relative.  Then properties that hold at any size: every block on its
-    simplex, terminals fixed, the labelling valid, and its cut recomputed on
-    the host equal to the reported cost."""
+    class order: every coordinate within 1e-4 and F within 1e-6 relative.
+
+    Equal epochs: the GPU's 200 FP32 epochs against the FP64 oracle's 200
+    epochs from the start in the same class order: F and c^T x within 1e-4
+    relative, the row violation within 1e-4.
+
+    Rounding on a shared point: region growing (10 repetitions, seed 0) of
+    the GPU's final x on both sides: labels, cut weight, radius and winning
+    repetition identical.  Also, at any size: every block on its simplex,
+    terminals fixed, the labelling valid, its cut recomputed on the host."""
     import time
-    say("case full-size mc_grid 1024x1024 k=8, one epoch from the same state")
+    say("case full-size mc_grid 1024x1024 k=8: GPU 200 epochs")
     t0 = time.time()
     side, k = 1024, 8
     inst = I.mc_grid(side=side, k=k, seed=0)
@@ -463,27 +530,51 @@ def test_full_size_multiway_cut_one_epoch_from_the_same_state():
     y0 = g.y
     g.run(1)
     y1 = g.y
+    g1 = g.metrics()
+    g.run(4)
     gm = g.metrics()
-    say(f"  gpu done {time.time() - t0:.1f} s")
-    lp, o = oracle_solver(inst, beta=10.0, seed=0)
-    o.y = y0
-    o.epoch = 195
-    o.run(1)
-    yo = o.y
-    om = o.metrics()
+    gy = g.y
+    say(f"  gpu done {time.time() - t0:.1f} s; F(200) {gm['F']:.12g}")
+    lp = O.OracleLP(inst)
+    o1 = O.OracleSolver(lp, beta=10.0, seed=0)
+    o1.y = y0
+    o1.epoch = 195
+    o1.run(1)
+    yo = o1.y
+    om1 = o1.metrics()
+    del o1
     dy = float(np.abs(y1 - yo).max())
-    say(f"  oracle done {time.time() - t0:.1f} s; max|y_gpu - y_oracle| after one epoch = {dy:.3e}; "
-        f"F {gm['F']:.12g} vs {om['F']:.12g}")
+    say(f"  one epoch from the same state: max|y_gpu - y_oracle| = {dy:.3e}; "
+        f"F {g1['F']:.12g} vs {om1['F']:.12g}")
     assert dy <= 1e-4
-    assert rel(gm["F"], om["F"]) <= 1e-6
+    assert rel(g1["F"], om1["F"]) <= 1e-6
+
+    say("case full-size mc_grid 1024x1024 k=8: oracle 200 epochs")
+    o = O.OracleSolver(lp, beta=10.0, seed=0)
+    o.run(200)
+    om = o.metrics()
+    say(f"  oracle done {time.time() - t0:.1f} s; F {gm['F']:.12g} vs {om['F']:.12g}; "
+        f"lp {gm['lp_value']:.12g} vs {om['lp_value']:.12g}; viol {gm['max_viol']:.4e} vs {om['max_viol']:.4e}; "
+        f"max|y - y64| {float(np.abs(gy - o.y).max()):.3e}")
+    assert rel(gm["F"], om["F"]) <= 1e-4
+    assert rel(gm["lp_value"], om["lp_value"]) <= 1e-4
+    assert abs(gm["max_viol"] - om["max_viol"]) <= 1e-4
+    assert gm["dual_bound"] <= gm["F"]
+    del o
+
     nv = side * side
-    X = y1[: nv * k].reshape(nv, k)
+    X = gy[: nv * k].reshape(nv, k)
     assert np.abs(X.sum(axis=1) - 1.0).max() <= 1e-5
     assert X.min() >= 0.0
     term = inst.meta["terminals"]
     assert np.array_equal(X[term], np.eye(k)[np.arange(k)])
-    sol, cost, _ = g.round(T.ROUND_MC_CKR, seed=0, reps=10)
-    assert g.check(T.ROUND_MC_CKR) == (True, 0)
+    sol, cost, aux = g.round(T.ROUND_MC_CKR, seed=0, reps=10)
+    osol, ocost, oaux = lp.round(gy[: inst.n], O.RULE_MC_CKR, seed=0, reps=10)
+    say(f"  region growing on the GPU's x: cut {cost:.12g} vs {ocost:.12g}; rep {aux[1]:.0f} vs {oaux[1]:.0f}")
+    assert np.array_equal(sol, osol)
+    assert cost == pytest.approx(ocost, rel=1e-12)
+    assert (aux[0], aux[1]) == (oaux[0], oaux[1])
+    assert g.check(T.ROUND_MC_CKR) == lp.check(O.RULE_MC_CKR, osol) == (True, 0)
     assert np.array_equal(sol[term], np.arange(k))
     e = inst.meta["edges"]
     cut = float(inst.meta["edge_w"][sol[e[:, 0]] != sol[e[:, 1]]].sum())
