@@ -362,10 +362,15 @@ def test_fp32_multiway_cut_parity():
 def test_async_schedule_converges_to_the_oracle_value(seed):
     """ASYNC (atomics, nondeterministic order; P-ASYNC) on the small vertex
     cover workload (G(1000, 5000), beta 10) at convergence: both runs to a
-    certified gap below 1e-6, F within 1e-4 relative, and the rounding equal
-    to the oracle's on every vertex whose oracle margin exceeds
-    max|x - x64| + |T - T64|; for these seeds no vertex is inside that band,
-    so the covers are identical."""
+    certified gap below 1e-6, F within 1e-4 relative, and the covers
+    identical.  With prox off the minimiser in x need not be unique, so the
+    two runs can stop at different points of equal F (max|x - x64| up to a
+    few 1e-4 here); the band of the whole run, margin <= max|x - x64| +
+    |T - T64|, is reported (seed 2 had one vertex inside it, rounded the same
+    on both sides; the order of the atomics varies from run to run), and
+    every vertex's margin is asserted above its own deviation
+    |x_v - x64_v| + |T - T64|, which makes the equal rounding a consequence
+    of the measured error rather than of luck."""
     say(f"case async vc_er seed={seed}")
     inst = I.vc_er(1000, 5000, seed=seed)
     g = gpu_solver(inst, beta=10.0, schedule=T.SCHED_ASYNC, step_scale=0.5, precision=T.PREC_FP32, seed=seed)
@@ -384,11 +389,12 @@ def test_async_schedule_converges_to_the_oracle_value(seed):
     dT = abs(aux[0] - oaux[0])
     margin = np.abs(ox - oaux[0])
     band = margin <= err + dT
+    own = margin <= np.abs(g.x - ox) + dT
     diff = sol != osol
     say(f"  epochs {done}; max|x-x64|={err:.3e} |dT|={dT:.2e} inside band={int(band.sum())} "
-        f"differing={int(diff.sum())}")
+        f"inside own band={int(own.sum())} differing={int(diff.sum())}")
     assert np.all(band[diff])
-    assert int(band.sum()) == 0
+    assert int(own.sum()) == 0
     assert np.array_equal(sol, osol)
 
 
@@ -500,7 +506,7 @@ def test_full_size_ba_config_parity():
 # measured for seed 0 (BA n = 2M, 100 epochs, refresh 5): vertices whose
 # oracle margin lies inside |x - x64| + |T - T64|, and vertices whose
 # rounding differs (all of them inside the band)
-FP32_BA_BAND_COUNTS = (None, None)
+FP32_BA_BAND_COUNTS = (0, 0)
 
 
 @pytest.mark.timeout(1200)
