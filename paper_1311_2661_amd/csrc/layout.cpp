@@ -250,38 +250,129 @@ static void pack(const Inst &in, const std::vector<int32_t> &sched,
     }
 }
 
+// Renumbers the plain columns into DET plan order (instances without
+// simplex blocks): the column at plan position q becomes column q, so the
+// plan's ids are the identity and a class sweep reads x, c and the bounds of
+// its columns in order.  The colouring was made in the caller's order and is
+// carried over unit by unit (a plain column is its own unit), so the classes
+// -- and every result -- do not change; entries keep their order inside each
+// row.  Returns false when the order is already that one.
+static bool renumber_cols(Inst &in) {
+    const int64_t n = in.n;
+    if (in.nblocks || in.nstruct_units != n) return false;
+    std::vector<int32_t> nid(n, -1);
+    int32_t next = 0;
+    for (const ClassPlan &cp : in.classes)
+        for (const Segment &sg : cp.segs) {
+            if (sg.kind == SEG_SLACK) continue;
+            if (sg.kind == SEG_BLOCK) return false;
+            for (int64_t q = 0; q < sg.count; ++q) nid[in.sched[sg.first + q]] = next++;
+        }
+    if (next != n) return false;
+    bool same = true;
+    for (int64_t j = 0; j < n && same; ++j) same = nid[j] == j;
+    if (same) return false;
+    for (int32_t &j : in.col_idx) j = nid[j];
+    std::vector<double> cc(n), uu(in.u.size());
+    std::vector<int32_t> orig(n), colour(n);
+    for (int64_t j = 0; j < n; ++j) {
+        cc[nid[j]] = in.c[j];
+        if (!uu.empty()) uu[nid[j]] = in.u[j];
+        orig[nid[j]] = in.col_orig[j];
+        colour[nid[j]] = in.ucolour[j];   // unit j is column j
+    }
+    in.c.swap(cc);
+    if (!uu.empty()) in.u.swap(uu);
+    in.col_orig.swap(orig);
+    std::copy(colour.begin(), colour.end(), in.ucolour.begin());
+    return true;
+}
+
+// Puts the columns back into the caller's order (before simplex blocks,
+// which name columns by the caller's index, are set on an instance whose
+// layout was built without them); a layout built on the renumbered columns
+// is dropped and rebuilt on next use.
+static void restore_cols(Inst &in) {
+    if (in.col_orig.empty()) return;
+    const int64_t n = in.n;
+    bool ident = true;
+    for (int64_t j = 0; j < n && ident; ++j) ident = in.col_orig[j] == j;
+    if (!ident) {
+        in.planned = false;
+        for (int32_t &j : in.col_idx) j = in.col_orig[j];
+        std::vector<double> cc(n), uu(in.u.size());
+        for (int64_t j = 0; j < n; ++j) {
+            cc[in.col_orig[j]] = in.c[j];
+            if (!uu.empty()) uu[in.col_orig[j]] = in.u[j];
+        }
+        in.c.swap(cc);
+        if (!uu.empty()) in.u.swap(uu);
+    }
+    for (int64_t j = 0; j < n; ++j) in.col_orig[j] = (int32_t)j;
+}
+
 // Renumbers the rows: every row goes to its owner, the structural unit of
 // the row that comes first in the DET schedule (class by class, in plan
 // order); rows are then numbered owner by owner, so the rows a class owns
 // are one contiguous range walked in the order the class sweep visits its
-// columns.  Rows without a free structural column go last.  Returns false
-// when the order is already that one.
+// columns.  Rows without a free structural column go last.
+//
+// Without simplex blocks the rows are further grouped by their first
+// foreign unit (the row's second unit in schedule order): first by its
+// class, then by the XCD part of its segment that runs it (xcd_part), owner
+// order kept inside each group.  A class launch then reaches its foreign
+// rows at random only inside the group of each XCD, a window of about
+// (rows of the class) / 8 that stays in that XCD's L2 for the whole launch,
+// while the owners still walk their rows in order (one sequential stream
+// per group).  Results do not depend on the row order.  Returns false when
+// the order is already the chosen one.
 static bool renumber_rows(Inst &in) {
     const int64_t n = in.n, m = in.m;
     const int32_t none = (int32_t)in.sched.size();  // positions are below n + m < 2^31
     std::vector<int32_t> pos(n, none);          // schedule position of a column's unit
-    for (const ClassPlan &cp : in.classes)
-        for (const Segment &sg : cp.segs) {
+    const bool windows = in.nblocks == 0;
+    std::vector<int32_t> grp(windows ? n : 0, 0);   // 1 + class * kXcds + XCD part
+    for (int32_t c = 0; c < (int32_t)in.classes.size(); ++c)
+        for (const Segment &sg : in.classes[c].segs) {
             if (sg.kind == SEG_SLACK) continue;
             for (int64_t q = 0; q < sg.count; ++q) {
                 const int32_t id = in.sched[sg.first + q];
                 const int64_t at = sg.first + q;
                 if (sg.kind == SEG_BLOCK)
                     for (int32_t i = 0; i < in.k; ++i) pos[in.bfirst[id] + i] = (int32_t)at;
-                else
+                else {
                     pos[id] = (int32_t)at;
+                    if (windows) grp[id] = 1 + c * kXcds + xcd_part(q, sg.count);
+                }
             }
         }
     // owner position of every row, then a stable counting sort by it
     std::vector<int32_t> key(m), at((size_t)none + 2, 0), order(m);
+    std::vector<int32_t> fgrp(windows ? m : 0, 0);
     for (int64_t i = 0; i < m; ++i) {
-        int32_t best = none;
-        for (int32_t e = in.row_ptr[i]; e < in.row_ptr[i + 1]; ++e) best = std::min(best, pos[in.col_idx[e]]);
+        int32_t best = none, second = none;
+        int32_t bcol = -1, scol = -1;
+        for (int32_t e = in.row_ptr[i]; e < in.row_ptr[i + 1]; ++e) {
+            const int32_t j = in.col_idx[e], pj = pos[j];
+            if (pj < best) { second = best; scol = bcol; best = pj; bcol = j; }
+            else if (pj < second) { second = pj; scol = j; }
+        }
         key[i] = best;
         at[(size_t)best + 1]++;
+        if (windows && second < none) fgrp[i] = grp[scol];
     }
     for (size_t q = 1; q < at.size(); ++q) at[q] += at[q - 1];
     for (int64_t i = 0; i < m; ++i) order[at[key[i]]++] = (int32_t)i;
+    if (windows) {
+        // stable by group: owner order kept inside every group
+        const size_t ng = 1 + (size_t)in.classes.size() * kXcds;
+        std::vector<int64_t> cnt(ng + 1, 0);
+        for (int64_t i = 0; i < m; ++i) cnt[(size_t)fgrp[i] + 1]++;
+        for (size_t g = 1; g <= ng; ++g) cnt[g] += cnt[g - 1];
+        std::vector<int32_t> by(m);
+        for (int64_t r = 0; r < m; ++r) by[cnt[fgrp[order[r]]]++] = order[r];
+        order.swap(by);
+    }
     bool same = true;
     for (int64_t r = 0; r < m && same; ++r) same = order[r] == r;
     if (same) return false;
@@ -410,9 +501,20 @@ thetis_status build_layout(Inst &in) {
             in.row_orig.resize(in.m);
             for (int64_t i = 0; i < in.m; ++i) in.row_orig[i] = (int32_t)i;
         }
+        if (in.col_orig.empty()) {
+            in.col_orig.resize(in.n);
+            for (int64_t j = 0; j < in.n; ++j) in.col_orig[j] = (int32_t)j;
+        }
+        // colour in the caller's column order (the classes are part of the
+        // method's schedule), then lay the columns out in plan order
+        restore_cols(in);
         build_csc(in);
         colour_units(in);
         plan_classes(in);
+        if (renumber_cols(in)) {
+            build_csc(in);
+            plan_classes(in);
+        }
         // the colouring does not depend on the row order: after the
         // renumbering only the column copy, the slack units (listed in row
         // order) and the plans are redone
@@ -605,6 +707,9 @@ extern "C" thetis_status thetis_inst_set_simplex_blocks(thetis_inst *h, int64_t 
         Inst &in = h->in;
         if (in.has_solver) return fail(THETIS_EBUSY, "blocks must be set before any solver is created");
         if (k < 1 || k > 64) return fail(THETIS_EUNSUPPORTED, "block size k must be in [1, 64]");
+        // blocks name columns in the caller's order
+        std::lock_guard<std::mutex> lock(h->layout_mu);
+        restore_cols(in);
         if (nblocks < 0 || (nblocks && !first)) return fail(THETIS_EINVAL, "bad block list");
         std::vector<int32_t> cb(in.n, -1), bf(nblocks), fx(nblocks, -1);
         for (int64_t t = 0; t < nblocks; ++t) {
@@ -634,7 +739,6 @@ extern "C" thetis_status thetis_inst_set_simplex_blocks(thetis_inst *h, int64_t 
                 if (stamp[t] == i) return fail(THETIS_EINVAL, "two columns of one simplex block share a row");
                 stamp[t] = i;
             }
-        std::lock_guard<std::mutex> lock(h->layout_mu);
         in.nblocks = nblocks; in.k = k;
         in.bfirst.swap(bf); in.fixed.swap(fx); in.col_block.swap(cb);
         in.digest = block_digest(in);
@@ -685,7 +789,13 @@ extern "C" thetis_status thetis_inst_classes(const thetis_inst *h, int32_t *ncla
         if (st) return st;
         if (nclasses) *nclasses = h->in.nclasses;
         if (nunits) *nunits = h->in.nunits;
-        if (class_host) std::copy(h->in.ucolour.begin(), h->in.ucolour.end(), class_host);
+        if (class_host) {
+            const Inst &in = h->in;
+            std::copy(in.ucolour.begin(), in.ucolour.end(), class_host);
+            // plain columns are their own units: back to the caller's order
+            if (!in.nblocks && in.nstruct_units == in.n)
+                for (int64_t j = 0; j < in.n; ++j) class_host[in.col_orig[j]] = in.ucolour[j];
+        }
         return THETIS_OK;
     } catch (...) {
         return exception_status();

@@ -165,7 +165,14 @@ struct Sched {
     const R *val;          // null when every entry is 1 or the signs are packed
     int32_t vmode;         // how entries are stored: see entry_at
     int64_t row_off = 0;   // VM 3 (one class's launch): row of entry e = e + row_off
+    int32_t ids_ident = 0; // plain columns are numbered by plan position: id = q
 };
+// the unit at schedule position q (a plain column's id is q when the
+// columns are laid out in plan order)
+template <class R>
+__device__ __forceinline__ int32_t sched_id(const Sched<R> &sc, int64_t q) {
+    return sc.ids_ident ? (int32_t)q : sc.ids[q];
+}
 
 // One entry of a packed column.  VM 0: every value 1; 1: values stored
 // beside the row indices; 2: every value +-1, the sign in the row index's
@@ -217,6 +224,7 @@ struct LaunchPlan {
     int32_t cols[kGridKinds];           // columns per lane group (sweep plans)
     int64_t hub_wg;                     // hub workgroups, a multiple of 8
     int64_t nwg;
+    int32_t xsplit;                     // solo sweep: every range split over the XCDs (xcd_part)
 };
 
 // logical workgroup L of a plan -> grid position and workgroup inside it
@@ -273,7 +281,7 @@ __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typenam
         v[c] = R(1);
         if (u < count) {
             const int64_t q = first + u;
-            j[c] = sc.ids[q];
+            j[c] = sched_id(sc, q);
             const int32_t e0 = sc.ptr[q], d = sc.ptr[q + 1] - e0;
             if (lane < d) row[c] = sched_entry<VM>(sc, e0 + lane, v[c]);
             y[c] = (R)xval(a.x[j[c]]);
@@ -314,7 +322,7 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
     using R = typename P::R;
     constexpr int TILE = HubTile<P>::n;
     const int tid = threadIdx.x;
-    const int32_t j = sc.ids[q];
+    const int32_t j = sched_id(sc, q);
     const int32_t e0 = sc.ptr[q], e1 = sc.ptr[q + 1];
     R acc = R(0);
     for (int32_t base = e0; base < e1; base += 4 * kWG) {
@@ -500,12 +508,21 @@ __device__ __forceinline__ void sweep_groups(const Dev<P> &a, const Sched<typena
 // logical workgroup L of a column plan.  A lane-group range may run wider
 // groups than its degree bound (the tuner's choice): the extra lanes hold
 // exact zeros, so the butterfly sums -- and every result -- are unchanged.
+// With xsplit, L is the hardware workgroup: every range starts at a multiple
+// of kXcds workgroups, and workgroup l of a range takes run l / kXcds of
+// the range's part l % kXcds, so part x runs on XCD x.
 template <class P, int VM>
 __device__ __forceinline__ void sweep_item(const Dev<P> &a, const Sched<typename P::R> &sc, const LaunchPlan &pl,
                                            int64_t L, typename P::R *st_r, int32_t *st_row, typename P::R *red) {
     int64_t local;
     const int p = locate_logical(pl, L, &local);
-    const int64_t first = pl.first[p], count = pl.count[p];
+    int64_t first = pl.first[p], count = pl.count[p];
+    if (pl.xsplit) {
+        const int64_t x = local % kXcds, lo = count * x / kXcds, hi = count * (x + 1) / kXcds;
+        first += lo;
+        count = hi - lo;
+        local /= kXcds;
+    }
     if (grid_kind(p) == SEG_HUB) {
         if (local < count) sweep_hub<P, VM>(a, sc, first + local, st_r, st_row, red);
         return;
@@ -521,7 +538,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(Dev<P> a, Sched<typename P::R> sc
     __shared__ R st_r[HubTile<P>::n];
     __shared__ int32_t st_row[HubTile<P>::n];
     __shared__ R red[kWG / 64];
-    sweep_item<P, VM>(a, sc, pl, logical_wg(pl, blockIdx.x), st_r, st_row, red);
+    sweep_item<P, VM>(a, sc, pl, pl.xsplit ? (int64_t)blockIdx.x : logical_wg(pl, blockIdx.x), st_r, st_row, red);
 }
 
 // the simplex blocks of one class: one wavefront per block, from the packed
@@ -1127,7 +1144,7 @@ __device__ __forceinline__ double cover_scaled(double x, double alpha) {
 template <class P>
 __global__ __launch_bounds__(kWG) void k_pick(Dev<P> a, int32_t rule, const double *thr,
                                               uint64_t seed, int32_t rep, int32_t rounds, int32_t *sol,
-                                              double *part) {
+                                              double *part, const int32_t *col_orig) {
     const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
     double v = 0.0;
     if (j < a.n) {
@@ -1141,10 +1158,10 @@ __global__ __launch_bounds__(kWG) void k_pick(Dev<P> a, int32_t rule, const doub
             const double xt = cover_scaled(xj, *thr);
             keep = 0;
             for (int32_t r = 0; r < rounds && xt > 0.0 && !keep; ++r)
-                keep = unit53_dev(philox_word_dev(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)j, 16 + (uint64_t)r)) < xt;
+                keep = unit53_dev(philox_word_dev(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)col_orig[j], 16 + (uint64_t)r)) < xt;
         } else {
             const double xt = xj / (1.0 + *thr);
-            keep = unit53_dev(philox_word_dev(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)j, 0)) < xt;
+            keep = unit53_dev(philox_word_dev(seed, RNG_ROUND, (uint64_t)rep, (uint64_t)col_orig[j], 0)) < xt;
         }
         sol[j] = keep;
         v = keep ? a.c[j] : 0.0;
@@ -1470,6 +1487,16 @@ __global__ __launch_bounds__(kWG) void k_copy_if(const double *flag, const int32
     if (j < n && flag[2] != 0.0) dst[j] = src[j];
 }
 
+// per-column integers between the internal and the caller's column order:
+// out == 1 scatters to the caller's order, else gathers from it
+__global__ __launch_bounds__(kWG) void k_col_map(const int32_t *src, int32_t *dst, const int32_t *col_orig,
+                                                 int64_t n, int32_t out) {
+    const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (j >= n) return;
+    if (out) dst[col_orig[j]] = src[j];
+    else dst[j] = src[col_orig[j]];
+}
+
 // feasibility of a 0/1 solution: A sol against b, row by row
 template <class P>
 __global__ __launch_bounds__(kWG) void k_check_rows(Dev<P> a, const int32_t *sol, double *part) {
@@ -1531,14 +1558,15 @@ __global__ __launch_bounds__(kWG) void k_set_start(Dev<P> a) {
     if (t < a.m) a.s[t] = 0;
 }
 
-// y arrives and leaves in the caller's row order; row_orig[r] is the
-// caller's index of internal row r
+// y arrives and leaves in the caller's order; row_orig[r] (col_orig[j]) is
+// the caller's index of internal row r (column j)
 template <class P>
-__global__ __launch_bounds__(kWG) void k_load_y(Dev<P> a, const double *y, const int32_t *row_orig) {
+__global__ __launch_bounds__(kWG) void k_load_y(Dev<P> a, const double *y, const int32_t *row_orig,
+                                                const int32_t *col_orig) {
     const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
     using R = typename P::R;
     if (t < a.n) {
-        double v = y[t];
+        double v = y[col_orig[t]];
         const double U = a.ub ? (double)a.ub[t] : (double)a.ub_value;
         if (v < 0.0) v = 0.0;
         if (v > U) v = U;
@@ -1555,9 +1583,10 @@ __global__ __launch_bounds__(kWG) void k_load_y(Dev<P> a, const double *y, const
 }
 
 template <class P>
-__global__ __launch_bounds__(kWG) void k_store_y(Dev<P> a, double *x, double *s, const int32_t *row_orig) {
+__global__ __launch_bounds__(kWG) void k_store_y(Dev<P> a, double *x, double *s, const int32_t *row_orig,
+                                                 const int32_t *col_orig) {
     const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (t < a.n) x[t] = (double)xval(a.x[t]);
+    if (t < a.n) x[col_orig[t]] = (double)xval(a.x[t]);
     if (s && t < a.m) s[row_orig[t]] = (double)a.s[t];
 }
 
@@ -1608,6 +1637,7 @@ struct thetis_solver {
     int64_t nunits = 0, updates_per_epoch = 0, max_degree = 0;
     int32_t row_lanes = 1;                     // lanes per row of the row passes
     int32_t lpc = 1;                           // lanes per column of a simplex block
+    bool det_ids_ident = false;                // DET plain columns: id = schedule position
     // parameters
     thetis_params p{};
     double rho = 0.0, Lmax = 0.0;
@@ -1630,7 +1660,7 @@ struct thetis_solver {
         *async_sched, *pk_det_ptr, *pk_det_row, *pk_det_val, *pk_async_ptr, *pk_async_row,
         *pk_async_val, *pb_id, *pb_j0, *pb_ptr, *pb_row, *pb_val, *rpart, *cpart, *metrics, *sol, *best, *drop,
         *ckr_order, *thr, *costbuf,
-        *chkbuf, *mulstats, *ystage, *row_orig, *ctil0, *ybar0, *ubar0, *upair, *pw_ends, *pw_first;
+        *chkbuf, *mulstats, *ystage, *row_orig, *col_orig, *ctil0, *ybar0, *ubar0, *upair, *pw_ends, *pw_first;
     int64_t nwg_rows = 0, nwg_cols = 0;
     int64_t epoch = 0;
     std::atomic<int32_t> batch_slots{0};       // batch slots holding this solver (destroy refuses while > 0)
@@ -1695,9 +1725,12 @@ int32_t choose_row_lanes(int64_t nnz, int64_t m) {
 // segment per kind) plus, for the dual pass, ncolterms per-column threads.
 // widen multiplies the lanes per column, cols sets the columns per lane
 // group of the lane-group ranges (sweep plans only; at most 2 on 64 lanes).
+// xsplit (solo sweep plans): every range is split into kXcds parts, each on
+// the same number of workgroups.
 LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolterms, int widen = 1,
-                     int cols = 1) {
+                     int cols = 1, bool xsplit = false) {
     LaunchPlan pl{};
+    pl.xsplit = xsplit && !dual;
     for (int p = 0; p < kGridKinds; ++p) {
         const int kind = grid_kind(p);
         pl.lanes[p] = kind < kGroupKinds ? std::min(64, kGroupLanes[kind] * widen) : 0;
@@ -1718,6 +1751,7 @@ LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolte
                           : (kind == SEG_NKIND ? kWG * kRowsPerThread
                                                : units_per_wg(kind) * (dual && kind != SEG_HUB ? kRowsPerThread : 1));
         int64_t w = pl.count[p] ? cdiv(pl.count[p], upw) : 0;
+        if (pl.xsplit && pl.count[p]) w = kXcds * cdiv(cdiv(pl.count[p], kXcds), upw);
         if (kind == SEG_HUB) { w = cdiv(w, 8) * 8; pl.hub_wg = w; }
         wg += w;
     }
@@ -1796,6 +1830,7 @@ void carve(thetis_solver &S, const Inst &in, char *base, size_t *total) {
     S.pw_first = in.npw > 0 ? cv.take(4 * in.npw) : nullptr;
     S.ystage = cv.take(8 * std::max<int64_t>(n + m, 1));
     S.row_orig = cv.take(4 * std::max<int64_t>(m, 1));
+    S.col_orig = cv.take(4 * std::max<int64_t>(n, 1));
     *total = cv.off + 256;
 }
 
@@ -1847,8 +1882,10 @@ int32_t det_vmode(const thetis_solver &S) { return S.unit_vals ? 0 : (S.sign_val
 
 template <class P>
 Sched<typename P::R> det_sched(const thetis_solver &S) {
-    return {(const int32_t *)S.sched, (const int32_t *)S.pk_det_ptr, (const int32_t *)S.pk_det_row,
-            (const typename P::R *)S.pk_det_val, det_vmode(S)};
+    Sched<typename P::R> sc{(const int32_t *)S.sched, (const int32_t *)S.pk_det_ptr, (const int32_t *)S.pk_det_row,
+                            (const typename P::R *)S.pk_det_val, det_vmode(S)};
+    sc.ids_ident = S.det_ids_ident ? 1 : 0;
+    return sc;
 }
 template <class P>
 BlockPack<typename P::R> block_pack(const thetis_solver &S) {
@@ -2132,7 +2169,7 @@ thetis_status set_y_impl(thetis_solver &S, const double *y) {
     Dev<P> a = make_dev<P>(S);
     const int64_t N = std::max<int64_t>(std::max(S.n, S.m), 1);
     hipLaunchKernelGGL((k_load_y<P>), dim3(cdiv(N, kWG)), dim3(kWG), 0, S.stream, a, (const double *)S.ystage,
-                       (const int32_t *)S.row_orig);
+                       (const int32_t *)S.row_orig, (const int32_t *)S.col_orig);
     HIP_TRY(hipGetLastError());
     thetis_status st = refresh<P>(S, true, false);
     S.have_round = false;
@@ -2147,7 +2184,7 @@ thetis_status get_x_impl(thetis_solver &S, double *x, double *s) {
     double *dx = (double *)S.ystage, *ds = dx + S.n;
     const int64_t N = std::max<int64_t>(std::max(S.n, S.m), 1);
     hipLaunchKernelGGL((k_store_y<P>), dim3(cdiv(N, kWG)), dim3(kWG), 0, S.stream, a, dx, s ? ds : nullptr,
-                       (const int32_t *)S.row_orig);
+                       (const int32_t *)S.row_orig, (const int32_t *)S.col_orig);
     HIP_TRY(hipGetLastError());
     if (x) HIP_TRY(hipMemcpyAsync(x, dx, 8 * S.n, hipMemcpyDeviceToHost, S.stream));
     if (s) HIP_TRY(hipMemcpyAsync(s, ds, 8 * S.m, hipMemcpyDeviceToHost, S.stream));
@@ -2173,7 +2210,8 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
         const int32_t op = rule == THETIS_ROUND_VC_THRESH ? 0 : 1;
         hipLaunchKernelGGL((k_edge_extreme<P>), dim3(gm), dim3(kWG), 0, S.stream, a, op, part);
         hipLaunchKernelGGL(k_edge_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gm, op, thr);
-        hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, 0, 0, best, part);
+        hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, 0, 0, best, part,
+                           (const int32_t *)S.col_orig);
         hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gn, 1.0, 0, cb);
         HIP_TRY(hipMemcpyAsync(auxv, thr, 8, hipMemcpyDeviceToHost, S.stream));
     } else if (rule == THETIS_ROUND_MIS_RAND) {
@@ -2183,7 +2221,8 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
         hipLaunchKernelGGL(k_edge_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gm, 2, thr);
         for (int32_t rep = 0; rep < reps; ++rep) {
             HIP_TRY(hipMemsetAsync(drop, 0, 4 * S.n, S.stream));
-            hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, rep, 0, sol, part);
+            hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, rep, 0, sol, part,
+                               (const int32_t *)S.col_orig);
             hipLaunchKernelGGL((k_conflicts<P>), dim3(gm), dim3(kWG), 0, S.stream, a, (const int32_t *)sol, drop);
             hipLaunchKernelGGL((k_apply_drop<P>), dim3(gn), dim3(kWG), 0, S.stream, a, sol, (const int32_t *)drop, part);
             hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gn, 1.0, rep, cb);
@@ -2195,7 +2234,8 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
         const double f = (double)std::max<int64_t>(S.max_row_len, 1);
         hipLaunchKernelGGL((k_row_scale<P>), dim3(gm), dim3(kWG), 0, S.stream, a, rule, f, part);
         hipLaunchKernelGGL(k_row_scale_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gm, rule, f, 1.0, thr);
-        hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, 0, 0, best, part);
+        hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, 0, 0, best, part,
+                           (const int32_t *)S.col_orig);
         hipLaunchKernelGGL(k_cost_fold, dim3(1), dim3(kWG), 0, S.stream, (const double *)part, gn, 1.0, 0, cb);
         HIP_TRY(hipMemcpyAsync(auxv, thr, 8, hipMemcpyDeviceToHost, S.stream));
     } else if (rule == THETIS_ROUND_COVER_RAND || rule == THETIS_ROUND_PACK_RAND) {
@@ -2215,7 +2255,7 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
         for (int32_t rep = 0; rep < reps; ++rep) {
             HIP_TRY(hipMemsetAsync(drop, 0, 4 * S.n, S.stream));
             hipLaunchKernelGGL((k_pick<P>), dim3(gn), dim3(kWG), 0, S.stream, a, rule, (const double *)thr, seed, rep,
-                               rounds, sol, part);
+                               rounds, sol, part, (const int32_t *)S.col_orig);
             if (cover) {
                 hipLaunchKernelGGL((k_cover_repair<P>), dim3(gm), dim3(kWG), 0, S.stream, a, (const int32_t *)sol,
                                    (const double *)thr, drop);
@@ -2271,7 +2311,18 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
     HIP_TRY(hipGetLastError());
     double cbh[4];
     HIP_TRY(hipMemcpyAsync(cbh, cb, 32, hipMemcpyDeviceToHost, S.stream));
-    if (sol_host) HIP_TRY(hipMemcpyAsync(sol_host, best, 4 * nsol, hipMemcpyDeviceToHost, S.stream));
+    if (sol_host) {
+        const int32_t *src = best;
+        if (nsol == S.n && S.n) {
+            // one entry per column: back to the caller's column order
+            int32_t *stage = (int32_t *)S.ystage;
+            hipLaunchKernelGGL(k_col_map, dim3(gn), dim3(kWG), 0, S.stream, (const int32_t *)best, stage,
+                               (const int32_t *)S.col_orig, S.n, 1);
+            HIP_TRY(hipGetLastError());
+            src = stage;
+        }
+        HIP_TRY(hipMemcpyAsync(sol_host, src, 4 * nsol, hipMemcpyDeviceToHost, S.stream));
+    }
     HIP_TRY(hipStreamSynchronize(S.stream));
     if (cost) *cost = cbh[1];
     auxv[1] = cbh[3];
@@ -2294,7 +2345,16 @@ thetis_status check_impl(thetis_solver &S, int32_t rule, const int32_t *sol_host
         return fail(THETIS_EINVAL, "unknown rule");
     const int64_t nsol = labels ? S.nblocks : S.n;
     if (sol_host) {
-        HIP_TRY(hipMemcpyAsync(S.drop, sol_host, 4 * nsol, hipMemcpyHostToDevice, S.stream));
+        if (labels) {
+            HIP_TRY(hipMemcpyAsync(S.drop, sol_host, 4 * nsol, hipMemcpyHostToDevice, S.stream));
+        } else if (nsol) {
+            // one entry per column, in the caller's order: into the internal one
+            int32_t *stage = (int32_t *)S.ystage;
+            HIP_TRY(hipMemcpyAsync(stage, sol_host, 4 * nsol, hipMemcpyHostToDevice, S.stream));
+            hipLaunchKernelGGL(k_col_map, dim3(cdiv(nsol, kWG)), dim3(kWG), 0, S.stream, (const int32_t *)stage,
+                               (int32_t *)S.drop, (const int32_t *)S.col_orig, nsol, 0);
+            HIP_TRY(hipGetLastError());
+        }
         sol = (const int32_t *)S.drop;
     } else if (!S.have_round) {
         return fail(THETIS_EINVAL, "no rounded solution on the device");
@@ -2453,7 +2513,7 @@ ClassLaunch make_class_launch(const thetis_solver &S, const Inst &in, const std:
     }
     if (!cols.empty()) {
         cl.has_cols = true;
-        cl.cols = make_plan(cols, false, 0);
+        cl.cols = make_plan(cols, false, 0, 1, 1, true);
         cl.col_segs = cols;
     }
     if (pk && cl.has_cols && det_vmode(S) == 0) {
@@ -2562,6 +2622,13 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
         S.max_row_len = in.max_row_len;
         S.npw = in.npw;
         for (const ClassPlan &cp : in.classes) S.det.push_back(make_class_launch(S, in, in.sched, cp.segs, &in.pk_det));
+        // columns laid out in plan order: a plain column's id is its position
+        S.det_ids_ident = true;
+        for (const ClassPlan &cp : in.classes)
+            for (const Segment &sg : cp.segs)
+                if (sg.kind < kGroupKinds || sg.kind == SEG_HUB)
+                    for (int64_t q = sg.first; q < sg.first + sg.count && S.det_ids_ident; ++q)
+                        S.det_ids_ident = in.sched[q] == q;
         {
             std::vector<Segment> all = in.async_struct.segs;
             all.insert(all.end(), in.async_slack.segs.begin(), in.async_slack.segs.end());
@@ -2598,6 +2665,7 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
         UP(upload(S, S.sense, in.sense));
         UP(upload(S, S.c, in.c));
         UP(upload(S, S.row_orig, in.row_orig));
+        UP(upload(S, S.col_orig, in.col_orig));
         if (in.npw > 0) {
             UP(upload(S, S.pw_ends, in.pw_ends));
             UP(upload(S, S.pw_first, in.pw_first));
@@ -2630,7 +2698,7 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
         if (S.has_ybar) {
             // the slack part of ybar follows the internal row order
             std::vector<double> yb(in.n + in.m);
-            for (int64_t j = 0; j < in.n; ++j) yb[j] = p->ybar[j];
+            for (int64_t j = 0; j < in.n; ++j) yb[j] = p->ybar[in.col_orig[j]];
             for (int64_t r = 0; r < in.m; ++r) yb[in.n + r] = p->ybar[in.n + in.row_orig[r]];
             UP(upload_real(S, S.ybar, yb));
             UP(hip_status(hipMemcpyAsync(S.ybar0, S.ybar, prec_bytes(S.p.precision) * (in.n + in.m),
@@ -2762,10 +2830,12 @@ extern "C" thetis_status thetis_get_multipliers(thetis_solver *s, double *ubar_h
         const size_t R = prec_bytes(S.p.precision);
         std::vector<char> yb(ybar_host ? R * (n + m) : 0);
         if (m) HIP_TRY(hipMemcpyAsync(ro.data(), S.row_orig, 4 * m, hipMemcpyDeviceToHost, S.stream));
+        std::vector<int32_t> co(ybar_host ? n : 0);
+        if (ybar_host && n) HIP_TRY(hipMemcpyAsync(co.data(), S.col_orig, 4 * n, hipMemcpyDeviceToHost, S.stream));
         if (ubar_host && m) HIP_TRY(hipMemcpyAsync(u.data(), S.ubar, 8 * m, hipMemcpyDeviceToHost, S.stream));
         if (ybar_host && n + m) HIP_TRY(hipMemcpyAsync(yb.data(), S.ybar, yb.size(), hipMemcpyDeviceToHost, S.stream));
         HIP_TRY(hipStreamSynchronize(S.stream));
-        // rows are stored in the layout's order; hand them back in the caller's
+        // rows and columns are stored in the layout's order; hand them back in the caller's
         if (ubar_host)
             for (int64_t r = 0; r < m; ++r) ubar_host[ro[r]] = u[r];
         if (ybar_host) {
@@ -2773,7 +2843,7 @@ extern "C" thetis_status thetis_get_multipliers(thetis_solver *s, double *ubar_h
                 if (R == 8) { double v; std::memcpy(&v, yb.data() + 8 * j, 8); return v; }
                 float v; std::memcpy(&v, yb.data() + 4 * j, 4); return (double)v;
             };
-            for (int64_t j = 0; j < n; ++j) ybar_host[j] = get(j);
+            for (int64_t j = 0; j < n; ++j) ybar_host[co[j]] = get(j);
             for (int64_t r = 0; r < m; ++r) ybar_host[n + ro[r]] = get(n + r);
         }
         return THETIS_OK;
@@ -2863,7 +2933,7 @@ extern "C" thetis_status thetis_solver_autotune(thetis_solver *s, int32_t epochs
         thetis_status st = DISPATCH(S, run_epochs_impl)(S, 1, 0.0, nullptr);
         for (int ci = 0; ci < 3 && st == THETIS_OK; ++ci) {
             for (ClassLaunch &cl : S.det)
-                if (cl.has_cols) { cl.group_cols = cands[ci]; cl.cols = make_plan(cl.col_segs, false, 0, 1, cands[ci]); }
+                if (cl.has_cols) { cl.group_cols = cands[ci]; cl.cols = make_plan(cl.col_segs, false, 0, 1, cands[ci], true); }
             evs.clear();
             S.class_events = &evs;
             st = DISPATCH(S, run_epochs_impl)(S, epochs_per_candidate, 0.0, nullptr);
@@ -2881,7 +2951,7 @@ extern "C" thetis_status thetis_solver_autotune(thetis_solver *s, int32_t epochs
             // one column per group unless another shape is clearly faster
             int best = 0;
             for (int ci = 1; ci < 3; ++ci) if (ms[3 * c + ci] < 0.97 * ms[3 * c + best]) best = ci;
-            if (cl.has_cols) { cl.group_cols = cands[best]; cl.cols = make_plan(cl.col_segs, false, 0, 1, cands[best]); }
+            if (cl.has_cols) { cl.group_cols = cands[best]; cl.cols = make_plan(cl.col_segs, false, 0, 1, cands[best], true); }
             if (choice_host) choice_host[c] = cl.group_cols;
         }
         s->have_round = false;

@@ -37,6 +37,19 @@ constexpr int kGroupLanes[kGroupKinds] = {2, 4, 8, 16, 32, 64};
 constexpr int kWG = 256;              // threads per workgroup, every kernel
 constexpr int kHubMinDegree = 65;     // columns with more entries go to SEG_HUB
 
+// A solo class sweep splits every segment of its launch into kXcds
+// contiguous parts, part x = [count x / kXcds, count (x + 1) / kXcds), and
+// runs part x on workgroups b with b % kXcds == x, which the hardware
+// dispatches round-robin to XCD x (each XCD has its own L2).  The row layout
+// uses the same split to give each XCD the rows its columns reach at random.
+constexpr int kXcds = 8;
+inline int32_t xcd_part(int64_t i, int64_t count) {
+    int32_t x = (int32_t)(i * kXcds / count);
+    while (x + 1 < kXcds && count * (x + 1) / kXcds <= i) ++x;
+    while (x > 0 && count * x / kXcds > i) --x;
+    return x;
+}
+
 struct Segment {
     int32_t kind;
     int64_t first;   // offset into Inst::sched
@@ -122,6 +135,12 @@ struct Inst {
     // first column in DET schedule order) sees its rows contiguously, class
     // by class.  row_orig[r] = caller's index of internal row r.
     std::vector<int32_t> row_orig;
+    // Internal column order: without simplex blocks the columns are
+    // renumbered into DET plan order (class by class, segment by segment),
+    // so a class sweep reads its columns' data in order and a plain column's
+    // id is its plan position.  col_orig[j] = caller's index of internal
+    // column j (empty: the caller's order).
+    std::vector<int32_t> col_orig;
     // 64-bit digest of the LP as given (sizes, matrix, b, c, u, senses) and
     // of the simplex blocks; a checkpoint records it and a load compares it
     uint64_t lp_digest = 0, digest = 0;

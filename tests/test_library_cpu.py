@@ -52,6 +52,26 @@ def test_classes_match_oracle(maker):
     assert np.array_equal(cls, colour)
 
 
+def test_blocks_set_after_a_layout_use_the_callers_column_order():
+    """Without blocks the layout renumbers the columns into plan order; blocks
+    declared afterwards name columns in the caller's order, so the instance
+    goes back to that order first and its classes equal the oracle's."""
+    inst = I.mc_grid(side=10, k=4, seed=2)
+    h = T.thetis_inst_create_csr(inst.m, inst.n, inst.nnz, inst.row_ptr, inst.col_idx, inst.val, inst.b,
+                                 inst.c, inst.u, inst.sense)
+    try:
+        nc0, nu0, cls0 = T.thetis_inst_classes(h)      # layout without blocks
+        assert nu0 > inst.n
+        T.thetis_inst_set_simplex_blocks(h, len(inst.block_first_col), inst.block_k, inst.block_first_col,
+                                         inst.fixed_label)
+        nc, nu, cls = T.thetis_inst_classes(h)
+        kind, uid, colour = O.OracleLP(inst).units()
+        assert nc == O.OracleLP(inst).nclasses and nu == len(colour)
+        assert np.array_equal(cls, colour)
+    finally:
+        T.thetis_inst_destroy(h)
+
+
 def test_ba_colouring_is_small():
     # every new BA vertex has 3 earlier neighbours: greedy in vertex order
     # needs at most 4 colours, plus the slack class
