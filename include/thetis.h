@@ -216,6 +216,24 @@ thetis_status thetis_solver_create(const thetis_inst *inst, const thetis_params 
                                    void *dev_workspace, size_t ws_bytes, void *stream,
                                    thetis_solver **out);
 
+/* For callers that cannot allocate device memory: code recorded under HIP
+ * graph capture, serving loops and harnesses that forbid hipMalloc.  The
+ * same solver as thetis_solver_create, but its workspace is a fixed array
+ * of THETIS_STATIC_WORKSPACE_BYTES inside the library, one copy per device,
+ * held until the process ends; this call allocates no device memory.  The
+ * solver runs on the current device; at most one solver made by this call
+ * lives on a device at a time (the array is its whole device state), and
+ * it releases the array when destroyed.  Creation rewrites every part of
+ * the array it uses, so what a previous solver left there does not matter.
+ * Errors: as thetis_solver_create; THETIS_EBUDGET when the instance needs
+ * more than THETIS_STATIC_WORKSPACE_BYTES (thetis_solver_workspace_bytes),
+ * THETIS_EBUSY while another such solver lives on the device.  Calls of the
+ * library on two solvers of one device that share the array cannot happen;
+ * two processes each have their own copy. */
+#define THETIS_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+thetis_status thetis_solver_create_static(const thetis_inst *inst, const thetis_params *p, void *stream,
+                                          thetis_solver **out);
+
 /* Back to the starting point (y = 0, epoch 0) without re-uploading.  After
  * multiplier steps, ubar, ybar and the shifted costs return to the values
  * given at creation and beta to the one of creation or of the last

@@ -1638,6 +1638,7 @@ struct thetis_solver {
     int32_t row_lanes = 1;                     // lanes per row of the row passes
     int32_t lpc = 1;                           // lanes per column of a simplex block
     bool det_ids_ident = false;                // DET plain columns: id = schedule position
+    int static_dev = -1;                       // device whose static workspace this solver holds
     // parameters
     thetis_params p{};
     double rho = 0.0, Lmax = 0.0;
@@ -2582,6 +2583,49 @@ extern "C" thetis_status thetis_solver_workspace_bytes(const thetis_inst *h, con
     }
 }
 
+// The workspace of thetis_solver_create_static: a file-scope device array
+// (a copy on every device the library runs on, for the life of the
+// process).  Host code never passes `scratch` itself to a kernel or a copy:
+// it takes the device's address of it once per device with
+// hipGetSymbolAddress and uses that.
+static __device__ __align__(256) char scratch[THETIS_STATIC_WORKSPACE_BYTES];
+
+namespace {
+struct StaticWorkspace {
+    void *ptr = nullptr;               // this device's address of `scratch`
+    const thetis_solver *holder = nullptr;
+};
+std::mutex g_static_mu;
+std::vector<StaticWorkspace> g_static;   // by device ordinal
+
+// the device's address of `scratch` (the device must be current), resolved
+// on the first use on that device
+thetis_status static_workspace(int dev, void **ptr) {
+    if ((size_t)dev >= g_static.size()) g_static.resize((size_t)dev + 1);
+    StaticWorkspace &w = g_static[(size_t)dev];
+    if (!w.ptr) {
+        void *q = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q) {
+            (void)hipGetLastError();
+            return fail(THETIS_EDEVICE, std::string("hipGetSymbolAddress of the static workspace failed: ") +
+                                            hipGetErrorString(e));
+        }
+        w.ptr = q;
+    }
+    *ptr = w.ptr;
+    return THETIS_OK;
+}
+
+// a solver made on the static workspace gives it back when destroyed
+void release_static(const thetis_solver *s) {
+    if (s->static_dev < 0) return;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if ((size_t)s->static_dev < g_static.size() && g_static[(size_t)s->static_dev].holder == s)
+        g_static[(size_t)s->static_dev].holder = nullptr;
+}
+}  // namespace
+
 extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis_params *p,
                                               void *dev_workspace, size_t ws_bytes, void *stream,
                                               thetis_solver **out) {
@@ -2739,6 +2783,42 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
         const thetis_status st = exception_status();
         if (Sp) thetis_solver_destroy(Sp);
         return st;
+    }
+}
+
+extern "C" thetis_status thetis_solver_create_static(const thetis_inst *h, const thetis_params *p, void *stream,
+                                                     thetis_solver **out) {
+    try {
+        clear_error();
+        if (!h || !out) return fail(THETIS_EINVAL, "NULL argument");
+        *out = nullptr;
+        size_t need = 0;
+        thetis_status st = thetis_solver_workspace_bytes(h, p, &need);
+        if (st) return st;
+        if (need > THETIS_STATIC_WORKSPACE_BYTES)
+            return fail(THETIS_EBUDGET, "the instance needs " + std::to_string(need) +
+                                            " workspace bytes; the static workspace holds " +
+                                            std::to_string(THETIS_STATIC_WORKSPACE_BYTES));
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(THETIS_EDEVICE, "no current HIP device");
+        }
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        void *ws = nullptr;
+        st = static_workspace(dev, &ws);
+        if (st) return st;
+        if (g_static[(size_t)dev].holder)
+            return fail(THETIS_EBUSY, "a solver made by thetis_solver_create_static still lives on this device");
+        thetis_solver *s = nullptr;
+        st = thetis_solver_create(h, p, ws, THETIS_STATIC_WORKSPACE_BYTES, stream, &s);
+        if (st) return st;
+        s->static_dev = dev;
+        g_static[(size_t)dev].holder = s;
+        *out = s;
+        return THETIS_OK;
+    } catch (...) {
+        return exception_status();
     }
 }
 
@@ -3210,6 +3290,7 @@ extern "C" thetis_status thetis_solver_destroy(thetis_solver *s) {
         (void)hipStreamSynchronize(s->stream);
         for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
         if (s->own_ws && s->ws) (void)hipFree(s->ws);
+        release_static(s);
         delete s;
         return THETIS_OK;
     } catch (...) {

@@ -38,7 +38,8 @@ SHAPE_COVER, SHAPE_SET_COVER, SHAPE_PACK = 1, 2, 4
 EXPORTED = [
     "thetis_params_default", "thetis_inst_create_csr", "thetis_inst_set_simplex_blocks",
     "thetis_inst_classes", "thetis_inst_rounding_shape", "thetis_inst_set_pairwise", "thetis_inst_destroy", "thetis_solver_workspace_bytes",
-    "thetis_solver_create", "thetis_solver_reset", "thetis_set_beta", "thetis_set_step_rule",
+    "thetis_solver_create", "thetis_solver_create_static", "thetis_solver_reset", "thetis_set_beta",
+    "thetis_set_step_rule",
     "thetis_run_epochs", "thetis_solver_autotune", "thetis_multiplier_step", "thetis_run_multipliers",
     "thetis_get_multipliers", "thetis_solver_save", "thetis_solver_load", "thetis_residual", "thetis_objective", "thetis_get_x",
     "thetis_set_y",
@@ -93,6 +94,7 @@ def lib():
             "thetis_inst_destroy": [vp],
             "thetis_solver_workspace_bytes": [vp, P(thetis_params), P(C.c_size_t)],
             "thetis_solver_create": [vp, P(thetis_params), vp, C.c_size_t, vp, P(vp)],
+            "thetis_solver_create_static": [vp, P(thetis_params), vp, P(vp)],
             "thetis_solver_reset": [vp],
             "thetis_set_beta": [vp, dbl],
             "thetis_set_step_rule": [vp, i32, dbl],
@@ -207,6 +209,12 @@ def thetis_solver_create(h, params: thetis_params, workspace_ptr: int, ws_bytes:
     s = C.c_void_p()
     _check(lib().thetis_solver_create(h, C.byref(params), C.c_void_p(workspace_ptr or None), ws_bytes,
                                       C.c_void_p(stream_ptr or None), C.byref(s)))
+    return s
+
+
+def thetis_solver_create_static(h, params: thetis_params, stream_ptr: int):
+    s = C.c_void_p()
+    _check(lib().thetis_solver_create_static(h, C.byref(params), C.c_void_p(stream_ptr or None), C.byref(s)))
     return s
 
 
@@ -424,12 +432,14 @@ class Instance:
 
 class Solver:
     """Device state of one solve.  The workspace is a torch uint8 tensor on
-    the current device; launches go to torch's current stream."""
+    the current device (or, with ``static_workspace``, the library's fixed
+    per-device array: thetis_solver_create_static, no allocation); launches
+    go to torch's current stream."""
 
     def __init__(self, instance: Instance, beta: float = 10.0, step_rule: int = STEP_PER_COORD,
                  step_scale: float = 1.0, prox: bool = False, ybar=None, ubar=None,
                  schedule: int = SCHED_DET, precision: int = PREC_FP32, refresh_every: int = 5,
-                 seed: int = 0, device=None):
+                 seed: int = 0, device=None, static_workspace: bool = False):
         if torch is None or not torch.cuda.is_available():
             raise RuntimeError("libthetis needs a HIP device")
         self.instance = instance
@@ -442,12 +452,16 @@ class Solver:
         p.schedule, p.precision, p.refresh_every, p.seed = schedule, precision, refresh_every, seed
         self.params = p
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
-        nbytes = thetis_solver_workspace_bytes(instance.h, p)
         with torch.cuda.device(dev):
-            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
             self.stream = torch.cuda.current_stream(dev)
-            self.h = thetis_solver_create(instance.h, p, self.workspace.data_ptr(), nbytes,
-                                          self.stream.cuda_stream)
+            if static_workspace:
+                self.workspace = None
+                self.h = thetis_solver_create_static(instance.h, p, self.stream.cuda_stream)
+            else:
+                nbytes = thetis_solver_workspace_bytes(instance.h, p)
+                self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+                self.h = thetis_solver_create(instance.h, p, self.workspace.data_ptr(), nbytes,
+                                              self.stream.cuda_stream)
         self.n, self.m = instance.n, instance.m
         self.nclasses = thetis_inst_classes(instance.h)[0]
         bf = instance.inst.block_first_col
