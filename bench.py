@@ -639,7 +639,7 @@ def serve(args):
     free, total = torch.cuda.mem_get_info()
     budget = int(args.budget_gb * (1 << 30)) if args.budget_gb > 0 else int(0.5 * free)
     srv = SV.Server(hbm_budget=budget, gap_tol=args.gap, epoch_cap=args.cap, slots=args.slots,
-                    precision=T.PREC_FP32, builders=args.builders)
+                    precision=T.PREC_FP32, builders=args.builders, log_path=args.serve_log or None)
     # warm-up: one small request of each kind (kernels load, graphs capture)
     warm = [srv.submit(I.serving_expand(I.serving_compact(dict(kind=k, edges=2000, seed=10**6 + j))), k, seed=j)
             for j, k in enumerate(["vc", "mis", "mc"])]
@@ -681,12 +681,18 @@ def serve(args):
                                 p99_s=float(np.quantile([r.latency for r in rk], 0.99)),
                                 epochs_median=float(np.median([r.epochs for r in rk])),
                                 gap_reached=f"{sum(r.reached_gap for r in rk)}/{len(rk)}",
+                                gap_median=float(np.median([r.gap for r in rk])),
                                 feasible=f"{sum(r.feasible for r in rk)}/{len(rk)}")
-    value = len(res) / makespan
+    # solves at the gap are the metric; requests stopped by the epoch cap
+    # (the grid multiway cuts) are served and reported, not counted
+    at_gap = [r for r in res if r.reached_gap]
+    capped = [r for r in res if not r.reached_gap]
+    value = len(at_gap) / makespan
+    lat_gap = np.array([r.latency for r in at_gap]) if at_gap else np.zeros(1)
     # one request at a time, same solves: stratified sample by size
     order = np.argsort(edges)
     pick = [int(st[len(st) // 2]) for st in np.array_split(order, args.baseline_sample) if len(st)]
-    times, same = [], 0
+    times, same, pick_gap = [], 0, 0
     for k in pick:
         lp = I.serving_expand(compact[k])
         torch.cuda.synchronize()
@@ -695,12 +701,15 @@ def serve(args):
                              epoch_cap=args.cap)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - ta)
+        pick_gap += int(ref["gap"] <= args.gap)
         # the served result must be the solve alone
         r = futs[k].result()
         same += int(r.epochs == ref["epochs"] and r.F == ref["F"] and r.cost == ref["cost"]
                     and np.array_equal(r.sol, ref["sol"]))
     log(f"served == alone on {same}/{len(pick)} sampled requests")
-    alone = 1.0 / float(np.mean(times))
+    # one at a time, the same requests in sequence: solves at the gap per
+    # second of the stratified sample (its capped solves take their time too)
+    alone = pick_gap / float(np.sum(times))
     cpu = None
     if args.cpu_baseline_seconds > 0:
         cpu = serve_cpu_baseline(compact, trace, futs, pick, args)
@@ -712,10 +721,17 @@ def serve(args):
         "config": {"workload": f"serve_poisson{args.rate:g}_{args.duration:g}s_edges1e3-1e6_gap{args.gap:g}_cap{args.cap}",
                    "requests": n_req, "rate_per_s": args.rate, "budget_bytes": budget, "slots_per_kind": args.slots,
                    "epochs_per_tick": 5, "seed": args.seed},
-        "latency_s": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99)), "max": float(lat.max())},
+        "latency_s": {"p50": float(np.median(lat_gap)), "p99": float(np.quantile(lat_gap, 0.99)),
+                      "max": float(lat_gap.max()), "of": "solves at the gap"},
+        "latency_all_s": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99)), "max": float(lat.max())},
+        "solves_at_gap": len(at_gap),
+        "capped": {"n": len(capped), "kinds": {kd: sum(r.kind == kd for r in capped) for kd in ("vc", "mis", "mc")},
+                   "solves_per_s": len(capped) / makespan,
+                   "gap_median": float(np.median([r.gap for r in capped])) if capped else None,
+                   "note": "stopped by the epoch cap before the gap; served, rounded, checked, not counted in value"},
         "per_kind": per_kind, "failed": errs, "peak_budget_used_bytes": srv.peak_used,
         "one_at_a_time": {"solves_per_s": alone, "sample": f"{len(pick)} requests stratified by size, solved alone "
-                          f"in sequence, mean {1e3 / alone:.1f} ms"},
+                          f"in sequence ({pick_gap} reached the gap), mean {1e3 * float(np.mean(times)):.1f} ms"},
         "speedup_vs_one_at_a_time": value / alone,
         "served_equals_alone_sampled": f"{same}/{len(pick)}",
     }
@@ -796,6 +812,7 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serve: device-memory budget (0: half of free)")
     ap.add_argument("--slots", type=int, default=256, help="serve: slots per batch kind")
     ap.add_argument("--builders", type=int, default=12, help="serve: host layout threads")
+    ap.add_argument("--serve-log", default="", help="serve: append one JSON line per request to this file")
     ap.add_argument("--instances", type=int, default=4096, help="mis_batch: instance count")
     ap.add_argument("--precision", choices=["bf16", "fp32"], default="fp32", help="mis_batch: x storage")
     ap.add_argument("--gap", type=float, default=1e-4, help="mis_batch: certified gap to stop at")

@@ -16,10 +16,19 @@ reached the certified gap (or its epoch cap): rounding, feasibility check,
 result, slot and memory released.  Each solve computes exactly what it
 would compute alone (the batch guarantees it), so results do not depend on
 what else is being served.
+
+A request may carry a deadline (seconds after its arrival): one still
+waiting or being built when it passes fails with DeadlineExceeded; one
+already on the device is finished at the next tick from its current point
+(rounded and checked like any other, with reason "deadline").  Every
+finished or failed request can be appended as one JSON line to a log.
+Builders stop building while many built requests wait for a slot, so a
+backlog holds compact requests, not layouts.
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
+import json
 import threading
 import time
 from dataclasses import dataclass, field
@@ -48,10 +57,15 @@ class Result:
     t_arrival: float
     t_admitted: float
     t_done: float
+    reason: str = "gap"          # why it stopped: "gap", "cap", "deadline" or "diverged"
 
     @property
     def latency(self) -> float:
         return self.t_done - self.t_arrival
+
+
+class DeadlineExceeded(RuntimeError):
+    """The request's deadline passed before it reached the device."""
 
 
 @dataclass
@@ -62,6 +76,7 @@ class _Req:
     seed: int
     t_arrival: float
     future: cf.Future
+    deadline: Optional[float] = None      # absolute (perf_counter) time, or None
     instance: Optional[T.Instance] = None
     ws_bytes: int = 0
     solver: Optional[T.Solver] = None
@@ -95,10 +110,17 @@ class Server:
 
     def __init__(self, hbm_budget: int, gap_tol: float = 1e-4, epoch_cap: int = 200,
                  epochs_per_tick: int = 5, slots: int = 256, precision: int = T.PREC_FP32,
-                 builders: int = 4, beta: float = 10.0, reps: int = 10):
+                 builders: int = 4, beta: float = 10.0, reps: int = 10,
+                 deadline_s: Optional[float] = None, log_path: Optional[str] = None,
+                 max_built_waiting: Optional[int] = None):
         import torch
         if epoch_cap % epochs_per_tick:
             raise ValueError("epoch_cap must be a multiple of epochs_per_tick")
+        self.deadline_s = deadline_s
+        self.log = open(log_path, "a") if log_path else None
+        self.log_lock = threading.Lock()
+        # built requests allowed to wait for a slot before builders pause
+        self.max_built = max_built_waiting if max_built_waiting else 2 * slots
         self.budget = int(hbm_budget)
         self.gap_tol, self.cap, self.tick = gap_tol, epoch_cap, epochs_per_tick
         self.precision, self.beta, self.reps = precision, beta, reps
@@ -125,7 +147,10 @@ class Server:
             t.start()
 
     # -------------------------------------------------------------- client side
-    def submit(self, lp, kind: str, seed: int = 0, t_arrival: Optional[float] = None) -> cf.Future:
+    def submit(self, lp, kind: str, seed: int = 0, t_arrival: Optional[float] = None,
+               deadline_s: Optional[float] = None) -> cf.Future:
+        """Queues one request; `deadline_s` (else the server's default) is
+        counted from its arrival."""
         if kind not in RULES:
             raise ValueError(f"unknown request kind {kind}")
         fut = cf.Future()
@@ -135,11 +160,47 @@ class Server:
             rid = self.next_id
             self.next_id += 1
             self.pending_builds += 1
-        req = _Req(rid, kind, lp, seed, time.perf_counter() if t_arrival is None else t_arrival, fut)
+        t0 = time.perf_counter() if t_arrival is None else t_arrival
+        dl = deadline_s if deadline_s is not None else self.deadline_s
+        req = _Req(rid, kind, lp, seed, t0, fut, None if dl is None else t0 + dl)
         self.builders.submit(self._build, req)
         return fut
 
+    def _expired(self, r: _Req, now: float) -> bool:
+        return r.deadline is not None and now > r.deadline
+
+    def _record(self, r: _Req, res: Optional[Result], err: Optional[BaseException]):
+        """One JSON line per finished or failed request."""
+        if self.log is None:
+            return
+        rec = dict(id=r.rid, kind=r.kind, seed=r.seed, ws_bytes=r.ws_bytes, epochs=r.epochs,
+                   t_arrival=r.t_arrival, t_admitted=r.t_admitted or None)
+        if res is not None:
+            rec.update(reason=res.reason, gap=res.gap, F=res.F, lp_value=res.lp_value, cost=res.cost,
+                       feasible=bool(res.feasible), n_violated=int(res.n_violated), t_done=res.t_done,
+                       latency_s=res.latency)
+        else:
+            rec.update(reason="error", error=f"{type(err).__name__}: {err}", t_done=time.perf_counter())
+        with self.log_lock:
+            self.log.write(json.dumps(rec) + "\n")
+            self.log.flush()
+
+    def _fail(self, r: _Req, err: BaseException):
+        self._record(r, None, err)
+        r.future.set_exception(err)
+
     def _build(self, req: _Req):
+        with self.lock:
+            # backpressure: a backlog waits as compact requests, not as layouts
+            while len(self.waiting) >= self.max_built and not self.closed and not self._expired(
+                    req, time.perf_counter()):
+                self.cv.wait(timeout=0.05)
+        if self._expired(req, time.perf_counter()):
+            with self.lock:
+                self.pending_builds -= 1
+                self.cv.notify_all()
+            self._fail(req, DeadlineExceeded(f"request {req.rid}: deadline passed before it was built"))
+            return
         try:
             lp = req.lp() if callable(req.lp) else req.lp      # a request may carry a builder
             req.lp = None
@@ -154,7 +215,7 @@ class Server:
             with self.lock:
                 self.pending_builds -= 1
                 self.cv.notify_all()
-            req.future.set_exception(e)
+            self._fail(req, e)
             return
         with self.lock:
             self.pending_builds -= 1
@@ -170,8 +231,23 @@ class Server:
             for g in self.groups.values():
                 g["thread"].join()
         self.uploaders.shutdown(wait=wait)
+        if self.log is not None:
+            with self.log_lock:
+                self.log.close()
+                self.log = None
 
     # -------------------------------------------------------------- device side
+    def _expire_locked(self, g: str) -> list:
+        """Takes the waiting requests of group g whose deadline has passed
+        off the queue (they are failed outside the lock)."""
+        now = time.perf_counter()
+        gone = [r for r in self.waiting if GROUP[r.kind] == g and self._expired(r, now)]
+        for r in gone:
+            self.waiting.remove(r)
+        if gone:
+            self.cv.notify_all()
+        return gone
+
     def _admit_locked(self, g: str):
         grp = self.groups[g]
         reserved = {r.slot for r in grp["uploading"]}
@@ -197,6 +273,8 @@ class Server:
             out.append(r)
         for r in out:
             self.waiting.remove(r)
+        if out:
+            self.cv.notify_all()
         return out
 
     def _make_solver(self, r: _Req):
@@ -216,18 +294,27 @@ class Server:
         batch, stream = grp["batch"], grp["stream"]
         with torch.cuda.device(self.device), torch.cuda.stream(stream):
             while True:
+                expired, stop = [], False
                 with self.lock:
                     while True:
+                        expired += self._expire_locked(g)
                         for r in self._admit_locked(g):
                             r.upload = self.uploaders.submit(self._make_solver, r)
                             grp["uploading"].append(r)
                         busy = any(s is not None for s in grp["slots"])
-                        if busy or grp["uploading"]:
+                        if busy or grp["uploading"] or expired:
                             break
                         if self.closed and self.pending_builds == 0 and not any(
                                 GROUP[r.kind] == g for r in self.waiting):
-                            return
+                            stop = True
+                            break
                         self.cv.wait(timeout=0.05)
+                for r in expired:
+                    r.instance.close()
+                    r.instance = None
+                    self._fail(r, DeadlineExceeded(f"request {r.rid}: deadline passed while waiting for a slot"))
+                if stop:
+                    return
                 # uploaded requests join the batch
                 if grp["uploading"] and not busy:
                     cf.wait([r.upload for r in grp["uploading"]], timeout=0.05,
@@ -242,7 +329,7 @@ class Server:
                     except Exception as e:
                         grp["slots"][r.slot] = None
                         self._release(g, r)
-                        r.future.set_exception(e)
+                        self._fail(r, e)
                 if not any(s is not None for s in grp["slots"]):
                     continue
                 try:
@@ -252,15 +339,18 @@ class Server:
                     self._fail_all(g, e)
                     continue
                 status = batch.last_status
+                now = time.perf_counter()
                 for slot, r in enumerate(grp["slots"]):
                     if r is None:
                         continue
                     r.epochs += int(done[slot])
                     st = int(status[slot])
                     if st in (1, 3) or r.epochs >= self.cap:
-                        self._finish(g, r, reached=(st == 1))
+                        self._finish(g, r, reached=(st == 1), reason={1: "gap", 3: "diverged"}.get(st, "cap"))
+                    elif self._expired(r, now):
+                        self._finish(g, r, reached=False, reason="deadline")
 
-    def _finish(self, g: str, r: _Req, reached: bool):
+    def _finish(self, g: str, r: _Req, reached: bool, reason: str):
         grp = self.groups[g]
         try:
             s = r.solver
@@ -268,7 +358,7 @@ class Server:
             sol, cost, _ = s.round(RULES[r.kind], seed=r.seed, reps=self.reps)
             feas, nv = s.check(RULES[r.kind])
             res = Result(r.kind, sol, cost, feas, nv, r.epochs, m["F"], m["lp_value"], m["gap"], reached,
-                         r.t_arrival, r.t_admitted, time.perf_counter())
+                         r.t_arrival, r.t_admitted, time.perf_counter(), reason)
             err = None
         except Exception as e:
             err = e
@@ -276,9 +366,10 @@ class Server:
         grp["slots"][r.slot] = None
         self._release(g, r)
         if err is None:
+            self._record(r, res, None)
             r.future.set_result(res)
         else:
-            r.future.set_exception(err)
+            self._fail(r, err)
 
     def _fail_all(self, g: str, err: Exception):
         grp = self.groups[g]
@@ -288,7 +379,7 @@ class Server:
             grp["batch"].set(slot, None)
             grp["slots"][slot] = None
             self._release(g, r)
-            r.future.set_exception(err)
+            self._fail(r, err)
 
     def _release(self, g: str, r: _Req):
         if r.solver is not None:

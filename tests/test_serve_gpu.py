@@ -109,3 +109,39 @@ def test_failed_batch_call_fails_its_requests_and_serving_continues():
     ok = srv.submit(I.vc_er(150, 400, seed=2), "vc", seed=2)
     assert ok.result(timeout=60).feasible
     srv.close()
+
+
+def test_deadlines_and_the_per_solve_log(tmp_path):
+    """A request past its deadline on the device is finished from its current
+    point (reason "deadline", rounded and checked); one whose deadline passes
+    while it waits for memory fails with DeadlineExceeded; every finished or
+    failed request leaves one JSON line in the log."""
+    import json
+    say("case serve deadlines + JSONL log")
+    log = tmp_path / "serve.jsonl"
+    big = I.mc_grid(side=40, k=8, seed=9)       # far from the gap at the cap
+    p = T.thetis_params_default()
+    h = T.Instance(big)
+    need = T.thetis_solver_workspace_bytes(h.h, p)
+    h.close()
+    # room for one such request: the second waits for memory
+    srv = S.Server(hbm_budget=int(need * 1.5), epoch_cap=100000, slots=4, log_path=str(log))
+    f1 = srv.submit(big, "mc", seed=1, deadline_s=0.5)
+    time.sleep(0.05)
+    f2 = srv.submit(I.mc_grid(side=40, k=8, seed=10), "mc", seed=2, deadline_s=0.2)
+    f3 = srv.submit(I.vc_er(300, 1200, seed=3), "vc", seed=3)     # no deadline: reaches the gap
+    r1 = f1.result(timeout=120)
+    with pytest.raises(S.DeadlineExceeded):
+        f2.result(timeout=120)
+    r3 = f3.result(timeout=120)
+    srv.close()
+    assert r1.reason == "deadline" and not r1.reached_gap and r1.feasible
+    assert 0 < r1.epochs < 100000
+    assert r1.latency >= 0.5
+    assert r3.reason == "gap" and r3.reached_gap
+    lines = [json.loads(x) for x in log.read_text().splitlines()]
+    assert sorted(x["id"] for x in lines) == [0, 1, 2]
+    by = {x["id"]: x for x in lines}
+    assert by[0]["reason"] == "deadline" and by[0]["epochs"] == r1.epochs and by[0]["feasible"]
+    assert by[1]["reason"] == "error" and "DeadlineExceeded" in by[1]["error"]
+    assert by[2]["reason"] == "gap" and by[2]["gap"] <= 1e-4
