@@ -223,24 +223,30 @@ static void pack_blocks(Inst &in) {
         }
 }
 
+// Packs the plain columns' entries in schedule order.  With `pad`, every
+// column of a lane-group segment takes exactly its group width of slots
+// (the unused ones hold kNoRow), so a lane finds its entry from the
+// column's plan position alone, and the segment records its base and stride.
 static void pack(const Inst &in, const std::vector<int32_t> &sched,
-                 const std::vector<const ClassPlan *> &plans, Packed &pk, bool signs) {
-    std::vector<int8_t> plain(sched.size(), 0);
+                 const std::vector<ClassPlan *> &plans, Packed &pk, bool signs, bool pad) {
+    std::vector<int32_t> slots(sched.size(), -1);   // -1: not a plain column; else slots taken
     for (const ClassPlan *cp : plans)
         for (const Segment &sg : cp->segs)
             if (sg.kind < kGroupKinds || sg.kind == SEG_HUB)
-                for (int64_t q = 0; q < sg.count; ++q) plain[sg.first + q] = 1;
+                for (int64_t q = 0; q < sg.count; ++q)
+                    slots[sg.first + q] = pad && sg.kind < kGroupKinds ? kGroupLanes[sg.kind] : 0;
     pk.ptr.assign(sched.size() + 1, 0);
     for (size_t q = 0; q < sched.size(); ++q) {
         const int32_t j = sched[q];
-        pk.ptr[q + 1] = pk.ptr[q] + (plain[q] ? in.col_ptr[j + 1] - in.col_ptr[j] : 0);
+        const int32_t d = slots[q] < 0 ? 0 : in.col_ptr[j + 1] - in.col_ptr[j];
+        pk.ptr[q + 1] = pk.ptr[q] + std::max(d, slots[q]);
     }
-    pk.row.resize(pk.ptr.back());
+    pk.row.assign(pk.ptr.back(), kNoRow);
     pk.val.clear();
     const bool vals = !in.unit_vals && !signs;
-    if (vals) pk.val.resize(pk.ptr.back());
+    if (vals) pk.val.assign(pk.ptr.back(), 0.0);
     for (size_t q = 0; q < sched.size(); ++q) {
-        if (!plain[q]) continue;
+        if (slots[q] < 0) continue;
         const int32_t j = sched[q];
         int32_t w = pk.ptr[q];
         for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e, ++w) {
@@ -248,6 +254,15 @@ static void pack(const Inst &in, const std::vector<int32_t> &sched,
             if (vals) pk.val[w] = in.cval[e];
         }
     }
+    for (ClassPlan *cp : plans)
+        for (Segment &sg : cp->segs) {
+            sg.ebase = 0;
+            sg.stride = 0;
+            if (pad && sg.kind < kGroupKinds && sg.count) {
+                sg.ebase = pk.ptr[sg.first];
+                sg.stride = kGroupLanes[sg.kind];
+            }
+        }
 }
 
 // Renumbers the plain columns into DET plan order (instances without
@@ -529,10 +544,10 @@ thetis_status build_layout(Inst &in) {
         in.async_struct = plan_units(in, st, in.async_sched);
         in.async_slack = plan_units(in, sl, in.async_sched);
         pack_blocks(in);
-        std::vector<const ClassPlan *> det;
-        for (const ClassPlan &cp : in.classes) det.push_back(&cp);
-        pack(in, in.sched, det, in.pk_det, in.sign_vals);
-        pack(in, in.async_sched, {&in.async_struct, &in.async_slack}, in.pk_async, false);
+        std::vector<ClassPlan *> det;
+        for (ClassPlan &cp : in.classes) det.push_back(&cp);
+        pack(in, in.sched, det, in.pk_det, in.sign_vals, true);
+        pack(in, in.async_sched, {&in.async_struct, &in.async_slack}, in.pk_async, false, false);
         if (!classes_row_disjoint(in))
             return fail(THETIS_EINVAL, "internal: two units of one colour class share a row");
         in.planned = true;

@@ -201,6 +201,23 @@ __device__ __forceinline__ int32_t sched_entry(const Sched<R> &sc, int64_t e, R 
     return entry_at<VM>(sc.row, sc.val, e, v);
 }
 
+// entry e of a fixed-stride column: -1 for an unused slot (kNoRow)
+template <int VM, class R>
+__device__ __forceinline__ int32_t padded_entry(const Sched<R> &sc, int64_t e, R &v) {
+    if (VM == 3) {
+        v = R(1);
+        return (int32_t)(e + sc.row_off);
+    }
+    const int32_t raw = sc.row[e];
+    if (raw == kNoRow) return -1;
+    if (VM == 2) {
+        v = raw < 0 ? R(-1) : R(1);
+        return raw & 0x7fffffff;
+    }
+    v = VM == 1 ? sc.val[e] : R(1);
+    return raw;
+}
+
 // Grid layout of one fused launch: the workgroup ranges of the segment
 // kinds in this order (hubs first so their long gathers start early).
 constexpr int kGridKinds = SEG_NKIND + 1;   // + the per-column terms of the dual pass
@@ -225,6 +242,10 @@ struct LaunchPlan {
     int64_t hub_wg;                     // hub workgroups, a multiple of 8
     int64_t nwg;
     int32_t xsplit;                     // solo sweep: every range split over the XCDs (xcd_part)
+    // fixed-stride lane-group ranges (sweep plans of the DET copy): the
+    // entries of the range's i-th column start at ebase + i * stride
+    int64_t ebase[kGridKinds];
+    int32_t stride[kGridKinds];
 };
 
 // logical workgroup L of a plan -> grid position and workgroup inside it
@@ -264,9 +285,14 @@ __device__ __forceinline__ typename P::R curvature(const Dev<P> &a, int64_t j, i
 // column are exactly those of a lone column, so the results do not depend
 // on C.
 
+// With a fixed-stride range (sbase >= 0: entry l of the column at plan
+// position q is sbase + q * stride + l) no entry pointer is loaded: a lane
+// goes straight to its entry, and the column's degree, which the unit-value
+// curvature needs, is the count of the group's filled slots (a ballot).
 template <class P, int VM, int G, int C>
 __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typename P::R> &sc,
-                                            int64_t first, int64_t count, int64_t lwg) {
+                                            int64_t first, int64_t count, int64_t lwg, int64_t sbase,
+                                            int32_t stride) {
     using R = typename P::R;
     constexpr int NG = kWG / G;
     const int lane = threadIdx.x & (G - 1);
@@ -282,12 +308,26 @@ __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typenam
         if (u < count) {
             const int64_t q = first + u;
             j[c] = sched_id(sc, q);
-            const int32_t e0 = sc.ptr[q], d = sc.ptr[q + 1] - e0;
-            if (lane < d) row[c] = sched_entry<VM>(sc, e0 + lane, v[c]);
+            if (stride) {
+                if (lane < stride) row[c] = padded_entry<VM>(sc, sbase + q * stride + lane, v[c]);
+            } else {
+                const int32_t e0 = sc.ptr[q], d = sc.ptr[q + 1] - e0;
+                if (lane < d) row[c] = sched_entry<VM>(sc, e0 + lane, v[c]);
+                L[c] = curvature<P, VM>(a, j[c], d);
+            }
             y[c] = (R)xval(a.x[j[c]]);
             cj[c] = a.ctil ? a.ctil[j[c]] : (R)a.c[j[c]];
-            L[c] = curvature<P, VM>(a, j[c], d);
             U[c] = col_bound(a, j[c]);
+        }
+    }
+    if (stride) {
+        // degree = filled slots of the group (every lane of the wave takes part)
+        const int gbase = (threadIdx.x & 63) & ~(G - 1);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const uint64_t bal = __ballot(row[c] >= 0);
+            const uint64_t mine = G == 64 ? bal : (bal >> gbase) & ((uint64_t(1) << (G & 63)) - 1);
+            if (j[c] >= 0) L[c] = curvature<P, VM>(a, j[c], (int32_t)__popcll(mine));
         }
     }
 #pragma unroll
@@ -482,24 +522,26 @@ __device__ __forceinline__ void sweep_slack(const Dev<P> &a, int64_t i) {
 
 template <class P, int VM, int G>
 __device__ __forceinline__ void sweep_groups_c(const Dev<P> &a, const Sched<typename P::R> &sc, int cols,
-                                               int64_t first, int64_t count, int64_t lwg) {
+                                               int64_t first, int64_t count, int64_t lwg, int64_t sbase,
+                                               int32_t stride) {
     switch (cols) {
-        case 1: sweep_group<P, VM, G, 1>(a, sc, first, count, lwg); break;
-        case 2: sweep_group<P, VM, G, 2>(a, sc, first, count, lwg); break;
-        case 4: sweep_group<P, VM, G, 4>(a, sc, first, count, lwg); break;
+        case 1: sweep_group<P, VM, G, 1>(a, sc, first, count, lwg, sbase, stride); break;
+        case 2: sweep_group<P, VM, G, 2>(a, sc, first, count, lwg, sbase, stride); break;
+        case 4: sweep_group<P, VM, G, 4>(a, sc, first, count, lwg, sbase, stride); break;
         default: break;
     }
 }
 template <class P, int VM>
 __device__ __forceinline__ void sweep_groups(const Dev<P> &a, const Sched<typename P::R> &sc, int lanes, int cols,
-                                             int64_t first, int64_t count, int64_t lwg) {
+                                             int64_t first, int64_t count, int64_t lwg, int64_t sbase,
+                                             int32_t stride) {
     switch (lanes) {
-        case 2: sweep_groups_c<P, VM, 2>(a, sc, cols, first, count, lwg); break;
-        case 4: sweep_groups_c<P, VM, 4>(a, sc, cols, first, count, lwg); break;
-        case 8: sweep_groups_c<P, VM, 8>(a, sc, cols, first, count, lwg); break;
-        case 16: sweep_groups_c<P, VM, 16>(a, sc, cols, first, count, lwg); break;
-        case 32: sweep_groups_c<P, VM, 32>(a, sc, cols, first, count, lwg); break;
-        case 64: sweep_groups_c<P, VM, 64>(a, sc, cols, first, count, lwg); break;
+        case 2: sweep_groups_c<P, VM, 2>(a, sc, cols, first, count, lwg, sbase, stride); break;
+        case 4: sweep_groups_c<P, VM, 4>(a, sc, cols, first, count, lwg, sbase, stride); break;
+        case 8: sweep_groups_c<P, VM, 8>(a, sc, cols, first, count, lwg, sbase, stride); break;
+        case 16: sweep_groups_c<P, VM, 16>(a, sc, cols, first, count, lwg, sbase, stride); break;
+        case 32: sweep_groups_c<P, VM, 32>(a, sc, cols, first, count, lwg, sbase, stride); break;
+        case 64: sweep_groups_c<P, VM, 64>(a, sc, cols, first, count, lwg, sbase, stride); break;
         default: break;
     }
 }
@@ -517,6 +559,8 @@ __device__ __forceinline__ void sweep_item(const Dev<P> &a, const Sched<typename
     int64_t local;
     const int p = locate_logical(pl, L, &local);
     int64_t first = pl.first[p], count = pl.count[p];
+    // entry base such that column q's slots start at sbase + q * stride
+    const int64_t sbase = pl.ebase[p] - pl.first[p] * (int64_t)pl.stride[p];
     if (pl.xsplit) {
         const int64_t x = local % kXcds, lo = count * x / kXcds, hi = count * (x + 1) / kXcds;
         first += lo;
@@ -527,7 +571,7 @@ __device__ __forceinline__ void sweep_item(const Dev<P> &a, const Sched<typename
         if (local < count) sweep_hub<P, VM>(a, sc, first + local, st_r, st_row, red);
         return;
     }
-    sweep_groups<P, VM>(a, sc, pl.lanes[p], pl.cols[p], first, count, local);
+    sweep_groups<P, VM>(a, sc, pl.lanes[p], pl.cols[p], first, count, local, sbase, pl.stride[p]);
 }
 
 // The plain columns of one class (DET) or of a whole epoch (ASYNC) in one
@@ -1741,6 +1785,10 @@ LaunchPlan make_plan(const std::vector<Segment> &segs, bool dual, int64_t ncolte
         const int p = grid_pos(sg.kind);
         pl.first[p] = sg.first;
         pl.count[p] = sg.count;
+        if (!dual && sg.stride) {
+            pl.ebase[p] = sg.ebase;
+            pl.stride[p] = sg.stride;
+        }
     }
     pl.count[kGridKinds - 1] = ncolterms;
     int64_t wg = 0;

@@ -55,7 +55,14 @@ struct Segment {
     int64_t first;   // offset into Inst::sched
     int64_t count;   // units in this segment
     int64_t pb_first = -1;   // SEG_BLOCK of the DET plan: first block in Inst::pb_det
+    // lane-group segment of the DET plan: its columns' entries sit at a fixed
+    // stride (the group width), entry l of the segment's i-th column at
+    // ebase + i * stride + l, unused slots holding kNoRow; stride 0 = packed
+    int64_t ebase = 0;
+    int32_t stride = 0;
 };
+// an unused slot of a fixed-stride column (no row has this index)
+constexpr int32_t kNoRow = 0x7fffffff;
 
 struct ClassPlan {
     std::vector<Segment> segs;   // at most one segment per kind
