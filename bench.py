@@ -110,24 +110,38 @@ def access_split(inst, unit_class):
 
 
 def random_access_model(T, words: int, owned, foreign, ncols, sweep_ms_per_epoch: float):
-    """Times random 4-byte gathers / read-modify-writes and a copy over a
-    buffer the size of the residual (live, on this GPU) and prices one
-    epoch of plain-column sweeps with them: every foreign entry one random
-    read-modify-write, plus the sequential bytes (row index 4 B per entry,
-    residual read + write 8 B per owned entry, 20 B per column) at the copy
-    rate."""
+    """Prices one epoch of plain-column sweeps with rates timed live on this
+    GPU.  Sequential bytes (row index 4 B per entry, residual read + write
+    8 B per owned entry, 20 B per column) go at the copy rate in both
+    models.  Foreign entries (rows an earlier class owns) cost one random
+    4-byte read-modify-write each: in `model_us_per_epoch` at the rate of a
+    buffer the size of the residual touched anywhere (the row order without
+    XCD windows), in `window_model_us_per_epoch` at the rate of random
+    read-modify-writes that stay inside each XCD's eighth of a buffer whose
+    eighths are the size of a class's per-XCD window (the row layout's
+    windows)."""
     import math
-    k = max(10, min(28, int(round(math.log2(max(words, 1024))))))
-    g_ms, rmw_ms, cp_ms = T.thetis_calibrate_random(k, 10)
+    k = max(13, min(28, int(round(math.log2(max(words, 8192))))))
+    g_ms, rmw_ms, cp_ms, _ = T.thetis_calibrate_random(k, 10)
     w = float(1 << k)
     rmw_rate, gather_rate, copy_gbs = w / (rmw_ms * 1e-3), w / (g_ms * 1e-3), 8 * w / (cp_ms * 1e-3) / 1e9
     F, O, N = float(sum(foreign)), float(sum(owned)), float(sum(ncols))
+    # a class's foreign rows split over the 8 XCD windows: the buffer's eighths
+    per_class = max(foreign) if len(foreign) else 0
+    kw = max(13, min(28, int(round(math.log2(max(per_class, 8192))))))
+    xcd_ms = T.thetis_calibrate_random(kw, 10)[3]
+    xcd_rate = float(1 << kw) / (xcd_ms * 1e-3)
     seq_bytes = 4 * (F + O) + 8 * O + 20 * N
-    model_us = 1e6 * (F / rmw_rate) + 1e6 * seq_bytes / (copy_gbs * 1e9)
+    seq_us = 1e6 * seq_bytes / (copy_gbs * 1e9)
+    model_us = 1e6 * (F / rmw_rate) + seq_us
+    wmodel_us = 1e6 * (F / xcd_rate) + seq_us
+    meas_us = 1e3 * sweep_ms_per_epoch
     return {"buffer_words": int(w), "random_rmw_per_s": rmw_rate, "random_gather_per_s": gather_rate,
             "copy_gbs": copy_gbs, "owned_entries_per_epoch": int(O), "foreign_entries_per_epoch": int(F),
-            "model_us_per_epoch": model_us, "measured_us_per_epoch": 1e3 * sweep_ms_per_epoch,
-            "frac_of_model": model_us / (1e3 * sweep_ms_per_epoch) if sweep_ms_per_epoch > 0 else None}
+            "model_us_per_epoch": model_us, "window_buffer_words": 1 << kw, "xcd_window_rmw_per_s": xcd_rate,
+            "window_model_us_per_epoch": wmodel_us, "measured_us_per_epoch": meas_us,
+            "frac_of_model": model_us / meas_us if meas_us > 0 else None,
+            "frac_of_window_model": wmodel_us / meas_us if meas_us > 0 else None}
 
 
 def cpu_baseline(inst, epochs_cap: int, budget_s: float, seed: int):

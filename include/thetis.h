@@ -422,11 +422,14 @@ thetis_status thetis_solver_destroy(thetis_solver *s);
 
 /* Measurement aid (no part of the method): on `stream` (NULL: the null
  * stream) of the current device, times passes over a buffer of
- * 2^words_log2 4-byte words (words_log2 in [10, 28]) that touch every word
+ * 2^words_log2 4-byte words (words_log2 in [13, 28]) that touch every word
  * once: ms_host[0] a gather at random distinct addresses, ms_host[1] a
  * read-modify-write at random distinct addresses, ms_host[2] a plain copy
- * into a second buffer; each the mean of `iters` passes after one warm-up.
- * Allocates and frees its two buffers; synchronises the stream. */
+ * into a second buffer, ms_host[3] a read-modify-write at random distinct
+ * addresses where the workgroups of each XCD (workgroup b runs on XCD
+ * b mod 8) touch only their own eighth of the buffer; each the mean of
+ * `iters` passes after one warm-up.  ms_host needs 4 entries.  Allocates
+ * and frees its two buffers; synchronises the stream. */
 thetis_status thetis_calibrate_random(int32_t words_log2, int32_t iters, void *stream, double *ms_host);
 
 /* ----------------------------------------------------------------- batches */

@@ -1,8 +1,10 @@
 // Random-access calibration: the device's rate of 4-byte gathers and
-// read-modify-writes at distinct random word addresses of one buffer, and of
-// a plain copy, on the caller's stream.  A measurement aid for reading the
-// sweep kernels' times (their residual accesses are 4-byte and, for rows an
-// earlier class owns, random); nothing in the method calls it.
+// read-modify-writes at distinct random word addresses of one buffer, of a
+// plain copy, and of random read-modify-writes that stay inside one eighth
+// of the buffer per XCD, on the caller's stream.  A measurement aid for
+// reading the sweep kernels' times (their residual accesses are 4-byte and,
+// for rows an earlier class owns, random inside the XCD's window of the row
+// layout); nothing in the method calls it.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -39,6 +41,15 @@ __global__ __launch_bounds__(256) void k_cal_rmw(float *__restrict__ buf, uint32
     buf[j] = buf[j] + 1.0f;
 }
 
+// workgroup b runs on XCD b % 8 and touches only window b % 8 (an eighth of
+// the buffer), each word of it once per pass
+__global__ __launch_bounds__(256) void k_cal_rmw_xcd(float *__restrict__ buf, uint32_t wmask, int wk) {
+    const uint32_t x = blockIdx.x & 7u, i = (blockIdx.x >> 3) * 256u + threadIdx.x;
+    if (i > wmask) return;
+    const uint32_t j = x * (wmask + 1) + scramble(i, wmask, wk);
+    buf[j] = buf[j] + 1.0f;
+}
+
 __global__ __launch_bounds__(256) void k_cal_copy(const float *__restrict__ a, float *__restrict__ b, uint32_t mask) {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
     if (i <= mask) b[i] = a[i];
@@ -53,7 +64,7 @@ extern "C" thetis_status thetis_calibrate_random(int32_t words_log2, int32_t ite
                                                  double *ms_host) {
     try {
         thetis::clear_error();
-        if (words_log2 < 10 || words_log2 > 28) return fail(THETIS_EINVAL, "words_log2 must be in [10, 28]");
+        if (words_log2 < 13 || words_log2 > 28) return fail(THETIS_EINVAL, "words_log2 must be in [13, 28]");
         if (iters < 1) return fail(THETIS_EINVAL, "iters must be positive");
         if (!ms_host) return fail(THETIS_EINVAL, "ms_host is NULL");
         const uint32_t words = 1u << words_log2, mask = words - 1;
@@ -70,11 +81,12 @@ extern "C" thetis_status thetis_calibrate_random(int32_t words_log2, int32_t ite
             check(hipMemsetAsync(buf, 0, sizeof(float) * words, st), "hipMemsetAsync") &&
             check(hipEventCreate(&e0), "hipEventCreate") && check(hipEventCreate(&e1), "hipEventCreate")) {
             const dim3 grid(words / 256u), block(256);
-            for (int kind = 0; kind < 3 && rc == THETIS_OK; ++kind) {
+            for (int kind = 0; kind < 4 && rc == THETIS_OK; ++kind) {
                 auto launch = [&]() {
                     if (kind == 0) hipLaunchKernelGGL(k_cal_gather, grid, block, 0, st, buf, mask, words_log2, dst);
                     else if (kind == 1) hipLaunchKernelGGL(k_cal_rmw, grid, block, 0, st, buf, mask, words_log2);
-                    else hipLaunchKernelGGL(k_cal_copy, grid, block, 0, st, buf, dst, mask);
+                    else if (kind == 2) hipLaunchKernelGGL(k_cal_copy, grid, block, 0, st, buf, dst, mask);
+                    else hipLaunchKernelGGL(k_cal_rmw_xcd, grid, block, 0, st, buf, (words >> 3) - 1, words_log2 - 3);
                 };
                 launch();                                          // warm-up
                 if (!check(hipEventRecord(e0, st), "hipEventRecord")) break;

@@ -371,13 +371,14 @@ def thetis_batch_run(b, count: int, max_epochs: int, gap_tol: float = 0.0):
 
 def thetis_calibrate_random(words_log2: int, iters: int = 10):
     """Random-access calibration on the current torch stream: mean ms per pass
-    of (random gather, random read-modify-write, copy) over 2^words_log2
-    4-byte words."""
+    of (random gather, random read-modify-write, copy, random
+    read-modify-write inside each XCD's eighth) over 2^words_log2 4-byte
+    words."""
     import torch
-    out = np.zeros(3, np.float64)
+    out = np.zeros(4, np.float64)
     st = torch.cuda.current_stream().cuda_stream
     _check(lib().thetis_calibrate_random(words_log2, iters, C.c_void_p(st), _ptr(out)))
-    return float(out[0]), float(out[1]), float(out[2])
+    return tuple(float(v) for v in out)
 
 
 def thetis_batch_autotune(b, epochs_per_candidate: int = 2):
