@@ -724,6 +724,8 @@ def serve(args):
     # one at a time, the same requests in sequence: solves at the gap per
     # second of the stratified sample (its capped solves take their time too)
     alone = pick_gap / float(np.sum(times))
+    if alone <= 0.0:
+        raise RuntimeError("no sampled request reached the gap alone: the one-at-a-time rate is undefined")
     cpu = None
     if args.cpu_baseline_seconds > 0:
         cpu = serve_cpu_baseline(compact, trace, futs, pick, args)

@@ -182,8 +182,9 @@ class Server:
         else:
             rec.update(reason="error", error=f"{type(err).__name__}: {err}", t_done=time.perf_counter())
         with self.log_lock:
-            self.log.write(json.dumps(rec) + "\n")
-            self.log.flush()
+            if self.log is not None:      # closed meanwhile: the record is dropped with the log
+                self.log.write(json.dumps(rec) + "\n")
+                self.log.flush()
 
     def _fail(self, r: _Req, err: BaseException):
         self._record(r, None, err)
