@@ -403,12 +403,14 @@ thetis_status thetis_epoch_traffic(const thetis_solver *s, double *sweep_bytes,
 /* Checkpoint of a solver's state (not part of the method): x, s, the running
  * residual r, the epoch (which selects the next class orders), beta and,
  * when the solver holds them, ubar, the shifted costs and the prox centre,
- * all as stored on the device.  thetis_solver_save with host_buf NULL puts
- * the size in *bytes; otherwise *bytes gives the buffer's size (too small:
- * THETIS_EINVAL with the size in *bytes) and receives the bytes written.
- * thetis_solver_load restores such a checkpoint into a solver of the same
- * instance (the checkpoint carries a 64-bit digest of the LP and its simplex
- * blocks), precision and ubar/prox setting (THETIS_EINVAL otherwise); the
+ * all as stored on the device (in the library's internal row and column
+ * order).  thetis_solver_save with host_buf NULL puts the size in *bytes;
+ * otherwise *bytes gives the buffer's size (too small: THETIS_EINVAL with
+ * the size in *bytes) and receives the bytes written.  thetis_solver_load
+ * restores such a checkpoint into a solver of the same instance (the
+ * checkpoint carries 64-bit digests of the LP and its simplex blocks and of
+ * the internal orders, so a checkpoint of another library version's layout
+ * is refused), precision and ubar/prox setting (THETIS_EINVAL otherwise); the
  * solve then continues bit for bit as it would have from the save (DET).
  * A reset afterwards still returns to the creation values.  Both
  * synchronise the solver's stream; not while a batch holding the solver

@@ -609,6 +609,13 @@ uint64_t block_digest(const Inst &in) {
 
 }  // namespace
 
+// the internal row and column orders: a checkpoint stores y and r in them,
+// so it records this digest and is loaded only into the same layout
+uint64_t thetis::layout_digest(const Inst &in) {
+    uint64_t h = digest_vec(0x4C41594F55544F52ULL, in.row_orig);
+    return digest_vec(h, in.col_orig);
+}
+
 extern "C" const char *thetis_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" thetis_status thetis_params_default(thetis_params *p) {

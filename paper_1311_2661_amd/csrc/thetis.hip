@@ -1693,6 +1693,7 @@ struct thetis_solver {
     bool has_ybar = false, has_ubar = false;
     double beta0 = 0.0;                        // beta at creation
     uint64_t inst_digest = 0;                  // the instance's digest (checkpoints)
+    uint64_t layout_digest = 0;                // its internal row and column orders (checkpoints)
     bool mul_dirty = false;                    // ubar / ctil / ybar / beta moved since creation
     // device
     hipStream_t stream = nullptr;
@@ -2711,6 +2712,7 @@ extern "C" thetis_status thetis_solver_create(const thetis_inst *h, const thetis
         S.packing = in.packing;
         S.cover_q = in.cover_q;
         S.inst_digest = in.digest;
+        S.layout_digest = layout_digest(in);
         S.max_row_len = in.max_row_len;
         S.npw = in.npw;
         for (const ClassPlan &cp : in.classes) S.det.push_back(make_class_launch(S, in, in.sched, cp.segs, &in.pk_det));
@@ -3233,7 +3235,9 @@ struct CheckpointHeader {
     int64_t n, m, epoch;
     double beta;
     uint64_t inst_digest;
+    uint64_t layout_digest;    // the internal orders y and r are stored in
 };
+constexpr int32_t kCheckpointVersion = 2;
 constexpr char kCheckpointMagic[8] = {'T', 'H', 'E', 'T', 'I', 'S', 'C', 'K'};
 
 struct CheckpointPart {
@@ -3266,7 +3270,7 @@ extern "C" thetis_status thetis_solver_save(thetis_solver *s, void *host_buf, si
         if (*bytes < need) { *bytes = need; return fail(THETIS_EINVAL, "checkpoint buffer too small"); }
         CheckpointHeader h{};
         std::memcpy(h.magic, kCheckpointMagic, 8);
-        h.version = 1;
+        h.version = kCheckpointVersion;
         h.precision = S.p.precision;
         h.has_ubar = S.has_ubar;
         h.has_ybar = S.has_ybar;
@@ -3275,6 +3279,7 @@ extern "C" thetis_status thetis_solver_save(thetis_solver *s, void *host_buf, si
         h.epoch = S.epoch;
         h.beta = S.p.beta;
         h.inst_digest = S.inst_digest;
+        h.layout_digest = S.layout_digest;
         char *out = (char *)host_buf;
         std::memcpy(out, &h, sizeof(h));
         size_t off = sizeof(h);
@@ -3298,8 +3303,10 @@ extern "C" thetis_status thetis_solver_load(thetis_solver *s, const void *host_b
         if (bytes < sizeof(CheckpointHeader)) return fail(THETIS_EINVAL, "checkpoint too short");
         CheckpointHeader h;
         std::memcpy(&h, host_buf, sizeof(h));
-        if (std::memcmp(h.magic, kCheckpointMagic, 8) != 0 || h.version != 1)
-            return fail(THETIS_EINVAL, "not a checkpoint of this library");
+        if (std::memcmp(h.magic, kCheckpointMagic, 8) != 0 || h.version != kCheckpointVersion)
+            return fail(THETIS_EINVAL, "not a checkpoint of this library version");
+        if (h.layout_digest != S.layout_digest)
+            return fail(THETIS_EINVAL, "checkpoint of another internal layout (rows or columns ordered differently)");
         if (h.precision != S.p.precision || h.n != S.n || h.m != S.m || h.inst_digest != S.inst_digest ||
             h.has_ubar != (int32_t)S.has_ubar || h.has_ybar != (int32_t)S.has_ybar)
             return fail(THETIS_EINVAL, "checkpoint of a different instance, precision or parameter set");

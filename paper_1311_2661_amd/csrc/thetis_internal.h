@@ -154,6 +154,7 @@ struct Inst {
 };
 
 thetis_status build_layout(Inst &in);   // CSC, units, colouring, plans
+uint64_t layout_digest(const Inst &in);  // digest of the internal row and column orders
 
 // Philox4x64-10 (Salmon et al., SC'11), host and device.
 struct Philox4x64 {

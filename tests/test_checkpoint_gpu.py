@@ -90,3 +90,11 @@ def test_mismatched_checkpoints_are_refused():
         T.Solver(h1).load(blob[:-4])
     with pytest.raises(T.ThetisError):
         T.Solver(h1).load(b"x" * len(blob))
+    # a checkpoint stores y and r in the internal row and column order, and
+    # records a digest of it (bytes 64..71 of the header): another layout is
+    # refused
+    other_layout = bytearray(blob)
+    other_layout[64] ^= 0xFF
+    with pytest.raises(T.ThetisError) as e:
+        T.Solver(h1).load(bytes(other_layout))
+    assert e.value.code == T.EINVAL and "layout" in str(e.value)
