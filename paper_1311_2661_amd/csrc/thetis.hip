@@ -285,7 +285,7 @@ __device__ __forceinline__ typename P::R curvature(const Dev<P> &a, int64_t j, i
 // column are exactly those of a lone column, so the results do not depend
 // on C.
 
-// With a fixed-stride range (sbase >= 0: entry l of the column at plan
+// With a fixed-stride range (stride > 0: entry l of the column at plan
 // position q is sbase + q * stride + l) no entry pointer is loaded: a lane
 // goes straight to its entry, and the column's degree, which the unit-value
 // curvature needs, is the count of the group's filled slots (a ballot).
@@ -2251,7 +2251,8 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
     double *thr = (double *)S.thr, *cb = (double *)S.costbuf;
     int32_t *sol = (int32_t *)S.sol, *best = (int32_t *)S.best, *drop = (int32_t *)S.drop;
     double auxv[2] = {0, 0};
-    int64_t nsol = S.n;
+    int64_t nsol = S.n;          // a label per simplex block for the label rules (set below)
+    bool per_column = true;
     if (rule == THETIS_ROUND_VC_THRESH || rule == THETIS_ROUND_MIS_THRESH) {
         if (rule == THETIS_ROUND_VC_THRESH && !S.edge_shape_cover)
             return fail(THETIS_EINVAL, "VC rounding needs rows x_u + x_v >= 1");
@@ -2323,6 +2324,7 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
         const int32_t nrep = rule == THETIS_ROUND_MAP_ARGMAX ? 1 : reps;
         if (nrep < 1) return fail(THETIS_EINVAL, "reps must be >= 1");
         nsol = S.nblocks;
+        per_column = false;
         const int64_t gb = std::max<int64_t>(cdiv(S.nblocks, kWG), 1);
         const int64_t ge = std::max<int64_t>(cdiv(std::max(S.nblocks, S.npw), kWG), 1);
         for (int32_t rep = 0; rep < nrep; ++rep) {
@@ -2336,6 +2338,7 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
         if (S.nblocks <= 0) return fail(THETIS_EINVAL, "MC rounding needs simplex blocks");
         if (reps < 1 || reps > kMaxReps) return fail(THETIS_EINVAL, "reps must be in [1, 64]");
         nsol = S.nblocks;
+        per_column = false;
         const int64_t gb = std::max<int64_t>(cdiv(S.nblocks, kWG), 1);
         std::vector<int32_t> orders(64 * (size_t)reps);  // one label order per repetition
         std::vector<double> rads(reps);
@@ -2363,7 +2366,7 @@ thetis_status round_impl(thetis_solver &S, int32_t rule, uint64_t seed, int32_t 
     HIP_TRY(hipMemcpyAsync(cbh, cb, 32, hipMemcpyDeviceToHost, S.stream));
     if (sol_host) {
         const int32_t *src = best;
-        if (nsol == S.n && S.n) {
+        if (per_column && S.n) {
             // one entry per column: back to the caller's column order
             int32_t *stage = (int32_t *)S.ystage;
             hipLaunchKernelGGL(k_col_map, dim3(gn), dim3(kWG), 0, S.stream, (const int32_t *)best, stage,
