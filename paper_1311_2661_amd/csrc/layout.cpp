@@ -265,6 +265,77 @@ static void pack(const Inst &in, const std::vector<int32_t> &sched,
         }
 }
 
+// Orders the plain columns inside every (class, segment, XCD part) of the
+// DET plan, class by class, by the owner position of their first foreign
+// row (a row's owner is its first unit in schedule order, its foreign unit
+// the second).  The row layout keeps a window's rows in owner order, so
+// columns next to each other in a wavefront then reach neighbouring rows of
+// their window: their random accesses share cache lines.  Only the order
+// inside a part changes (not the classes, not the parts), and a DET class's
+// result does not depend on the order of its columns.
+static void order_parts_by_window(Inst &in) {
+    if (in.nblocks) return;
+    const int64_t n = in.n, m = in.m;
+    const int32_t none = INT32_MAX;
+    std::vector<int32_t> pos(n, none);
+    for (const ClassPlan &cp : in.classes)
+        for (const Segment &sg : cp.segs) {
+            if (sg.kind == SEG_SLACK || sg.kind == SEG_BLOCK) continue;
+            for (int64_t q = 0; q < sg.count; ++q) pos[in.sched[sg.first + q]] = (int32_t)(sg.first + q);
+        }
+    // the row's second unit in schedule order stays its second: classes come
+    // in schedule order and reordering inside a class keeps the class
+    std::vector<int32_t> first_of(m, -1), second_of(m, -1);
+    for (int64_t i = 0; i < m; ++i) {
+        int32_t b = none, s2 = none, bj = -1, sj = -1;
+        for (int32_t e = in.row_ptr[i]; e < in.row_ptr[i + 1]; ++e) {
+            const int32_t j = in.col_idx[e], pj = pos[j];
+            if (pj < b) { s2 = b; sj = bj; b = pj; bj = j; }
+            else if (pj < s2) { s2 = pj; sj = j; }
+        }
+        first_of[i] = bj;
+        second_of[i] = s2 < none ? sj : -1;
+    }
+    std::vector<int64_t> key(n, INT64_MAX);
+    std::vector<std::pair<int64_t, int32_t>> buf;
+    for (ClassPlan &cp : in.classes) {
+        // owners of this class's foreign rows are in earlier classes: final
+        for (const Segment &sg : cp.segs)
+            if (sg.kind != SEG_SLACK && sg.kind != SEG_BLOCK)
+                for (int64_t q = 0; q < sg.count; ++q) key[in.sched[sg.first + q]] = INT64_MAX;
+        for (const Segment &sg : cp.segs) {
+            if (sg.kind == SEG_SLACK || sg.kind == SEG_BLOCK) continue;
+            for (int64_t q = 0; q < sg.count; ++q) {
+                const int32_t v = in.sched[sg.first + q];
+                for (int32_t e = in.col_ptr[v]; e < in.col_ptr[v + 1]; ++e) {
+                    const int32_t i = in.row_idx[e];
+                    if (second_of[i] == v) key[v] = std::min<int64_t>(key[v], pos[first_of[i]]);
+                }
+            }
+        }
+        for (const Segment &sg : cp.segs) {
+            if (sg.kind == SEG_SLACK || sg.kind == SEG_BLOCK) continue;
+            for (int32_t x = 0; x < kXcds; ++x) {
+                const int64_t lo = sg.count * x / kXcds, hi = sg.count * (x + 1) / kXcds;
+                buf.clear();
+                for (int64_t q = lo; q < hi; ++q) {
+                    const int32_t v = in.sched[sg.first + q];
+                    buf.push_back({key[v], v});
+                }
+                std::stable_sort(buf.begin(), buf.end(),
+                                 [](const std::pair<int64_t, int32_t> &a, const std::pair<int64_t, int32_t> &b) {
+                                     return a.first < b.first;
+                                 });
+                for (int64_t q = lo; q < hi; ++q) {
+                    const int32_t v = buf[q - lo].second;
+                    in.sched[sg.first + q] = v;
+                    pos[v] = (int32_t)(sg.first + q);
+                }
+            }
+        }
+    }
+}
+
 // Renumbers the plain columns into DET plan order (instances without
 // simplex blocks): the column at plan position q becomes column q, so the
 // plan's ids are the identity and a class sweep reads x, c and the bounds of
@@ -526,6 +597,7 @@ thetis_status build_layout(Inst &in) {
         build_csc(in);
         colour_units(in);
         plan_classes(in);
+        order_parts_by_window(in);
         if (renumber_cols(in)) {
             build_csc(in);
             plan_classes(in);
