@@ -270,18 +270,25 @@ static void pack(const Inst &in, const std::vector<int32_t> &sched,
 // row (a row's owner is its first unit in schedule order, its foreign unit
 // the second).  The row layout keeps a window's rows in owner order, so
 // columns next to each other in a wavefront then reach neighbouring rows of
-// their window: their random accesses share cache lines.  Only the order
+// their window: their random accesses share cache lines.  Ties -- above all
+// the columns with no foreign row, such as the whole first class -- go by
+// the windows their owned rows fall in (the smallest three window ids), so
+// neighbouring owners write into the same few windows.  Only the order
 // inside a part changes (not the classes, not the parts), and a DET class's
 // result does not depend on the order of its columns.
 static void order_parts_by_window(Inst &in) {
     if (in.nblocks) return;
     const int64_t n = in.n, m = in.m;
     const int32_t none = INT32_MAX;
-    std::vector<int32_t> pos(n, none);
-    for (const ClassPlan &cp : in.classes)
-        for (const Segment &sg : cp.segs) {
+    std::vector<int32_t> pos(n, none), win(n, 0);   // win: 1 + class * kXcds + XCD part
+    for (int32_t c = 0; c < (int32_t)in.classes.size(); ++c)
+        for (const Segment &sg : in.classes[c].segs) {
             if (sg.kind == SEG_SLACK || sg.kind == SEG_BLOCK) continue;
-            for (int64_t q = 0; q < sg.count; ++q) pos[in.sched[sg.first + q]] = (int32_t)(sg.first + q);
+            for (int64_t q = 0; q < sg.count; ++q) {
+                const int32_t j = in.sched[sg.first + q];
+                pos[j] = (int32_t)(sg.first + q);
+                win[j] = 1 + c * kXcds + xcd_part(q, sg.count);
+            }
         }
     // the row's second unit in schedule order stays its second: classes come
     // in schedule order and reordering inside a class keeps the class
@@ -296,8 +303,24 @@ static void order_parts_by_window(Inst &in) {
         first_of[i] = bj;
         second_of[i] = s2 < none ? sj : -1;
     }
+    // the windows a column's owned rows fall in: the smallest three ids
+    // (10 bits each), a key that groups owners writing to the same windows
+    std::vector<int64_t> own_key(n, 0);
+    for (int64_t j = 0; j < n; ++j) {
+        int32_t w3[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+        for (int32_t e = in.col_ptr[j]; e < in.col_ptr[j + 1]; ++e) {
+            const int32_t i = in.row_idx[e];
+            if (first_of[i] != j || second_of[i] < 0) continue;
+            int32_t w = std::min<int32_t>(win[second_of[i]], 1023);
+            for (int t = 0; t < 3; ++t)
+                if (w < w3[t]) std::swap(w, w3[t]);
+        }
+        int64_t k = 0;
+        for (int t = 0; t < 3; ++t) k = (k << 10) | (w3[t] == INT32_MAX ? 1023 : w3[t]);
+        own_key[j] = k;
+    }
     std::vector<int64_t> key(n, INT64_MAX);
-    std::vector<std::pair<int64_t, int32_t>> buf;
+    std::vector<std::pair<std::pair<int64_t, int64_t>, int32_t>> buf;
     for (ClassPlan &cp : in.classes) {
         // owners of this class's foreign rows are in earlier classes: final
         for (const Segment &sg : cp.segs)
@@ -320,10 +343,11 @@ static void order_parts_by_window(Inst &in) {
                 buf.clear();
                 for (int64_t q = lo; q < hi; ++q) {
                     const int32_t v = in.sched[sg.first + q];
-                    buf.push_back({key[v], v});
+                    buf.push_back({{key[v], own_key[v]}, v});
                 }
                 std::stable_sort(buf.begin(), buf.end(),
-                                 [](const std::pair<int64_t, int32_t> &a, const std::pair<int64_t, int32_t> &b) {
+                                 [](const std::pair<std::pair<int64_t, int64_t>, int32_t> &a,
+                                    const std::pair<std::pair<int64_t, int64_t>, int32_t> &b) {
                                      return a.first < b.first;
                                  });
                 for (int64_t q = lo; q < hi; ++q) {
