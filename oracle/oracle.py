@@ -146,7 +146,8 @@ class OracleLP:
         self.m, self.n, self.N = inst.m, inst.n, inst.n + inst.m
 
     def __del__(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module's globals may already be gone
+        if getattr(self, "h", None) and callable(globals().get("lib")):
             lib().orc_lp_free(self.h)
             self.h = None
 
@@ -205,7 +206,8 @@ class OracleSolver:
             raise ValueError("oracle rejected the parameters")
 
     def __del__(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module's globals may already be gone
+        if getattr(self, "h", None) and callable(globals().get("lib")):
             lib().orc_solver_free(self.h)
             self.h = None
 
