@@ -3396,6 +3396,8 @@ struct BClass {
 };
 
 constexpr int kMaxBatchClasses = 64;
+// most epochs one captured batch graph runs
+constexpr int64_t kGraphEpochs = 8;
 // a batch work item covers one logical workgroup of plain columns, or this
 // many simplex blocks per wavefront, or this many slacks per thread (larger
 // items amortise the walk to the item's instance and plan)
@@ -3813,10 +3815,15 @@ struct thetis_batch {
     size_t bi_bytes = 0;
     std::vector<char> bi_host;          // host image of the BInst array
     int64_t nclass_total = 0;
-    // captured epoch
+    // captured epochs: graph_epochs copies of one epoch's launches
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int captured_widen = 0, captured_grid = -1, captured_strided = -1, captured_cols = 0, captured_window = -1;
+    int32_t graph_epochs = 1, captured_epochs = 0;
+    // instances left after a graph launch, copied to pinned host memory
+    // (two slots: the host reads one while the next launch runs)
+    int32_t *poll = nullptr;
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
     int64_t captured_most = 0;
     uint64_t signature = 0;
 };
@@ -3994,7 +4001,7 @@ template <class P>
 thetis_status batch_capture(thetis_batch &B) {
     batch_drop_graph(B);
     HIP_TRY(hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal));
-    batch_epoch_launches<P>(B);
+    for (int32_t k = 0; k < B.graph_epochs; ++k) batch_epoch_launches<P>(B);
     hipError_t e = hipStreamEndCapture(B.stream, &B.graph);
     if (e != hipSuccess) { B.graph = nullptr; return fail(THETIS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e)); }
     HIP_TRY(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
@@ -4004,6 +4011,7 @@ thetis_status batch_capture(thetis_batch &B) {
     B.captured_strided = B.strided;
     B.captured_cols = B.cols;
     B.captured_window = B.window;
+    B.captured_epochs = B.graph_epochs;
     return THETIS_OK;
 }
 
@@ -4013,9 +4021,22 @@ thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol
     for (thetis_solver *S : B.solvers) if (S) HIP_TRY(hipStreamSynchronize(S->stream));
     thetis_status st = batch_upload<P>(B, max_epochs, gap_tol);
     if (st) return st;
+    int32_t refresh_min = 1 << 30, occupied = 0;
+    for (thetis_solver *S : B.solvers)
+        if (S) { refresh_min = std::min(refresh_min, S->p.refresh_every); ++occupied; }
+    if (refresh_min == (1 << 30)) refresh_min = 1;
+    // with a window, instances run in turns: enough epochs for every turn
+    const bool windowed = B.window > 0 && B.window < occupied;
+    const int64_t epochs = windowed ? (int64_t)max_epochs * (cdiv(occupied, B.window) + 1) : max_epochs;
+    // One graph launch runs K epochs: the shortest refresh period (an
+    // instance can only stop at a refresh), at most kGraphEpochs, at most
+    // the epochs asked for.  An instance past its epoch cap or its stop is
+    // retired on the device, so the epochs of the last launch beyond what
+    // it needs leave it unchanged.
+    B.graph_epochs = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)refresh_min, kGraphEpochs, epochs}));
     if (!B.exec || B.captured_widen != B.widen || B.captured_grid != B.grid_mult || B.captured_strided != B.strided ||
         (B.grid_mult == 0 && B.captured_most != B.most_items) ||
-        B.captured_cols != B.cols || B.captured_window != B.window) {
+        B.captured_cols != B.cols || B.captured_window != B.window || B.captured_epochs != B.graph_epochs) {
         st = batch_capture<P>(B);
         if (st) return st;
     }
@@ -4025,21 +4046,23 @@ thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol
         HIP_TRY(hipEventCreate(&e1));
         HIP_TRY(hipEventRecord(e0, B.stream));
     }
-    int32_t refresh_min = 1 << 30, occupied = 0;
-    for (thetis_solver *S : B.solvers)
-        if (S) { refresh_min = std::min(refresh_min, S->p.refresh_every); ++occupied; }
-    if (refresh_min == (1 << 30)) refresh_min = 1;
-    // with a window, instances run in turns: enough epochs for every turn
-    const bool windowed = B.window > 0 && B.window < occupied;
-    const int64_t replays = windowed ? (int64_t)max_epochs * (cdiv(occupied, B.window) + 1) : max_epochs;
-    for (int64_t e = 0; e < replays; ++e) {
+    const int64_t K = B.graph_epochs, launches = cdiv(epochs, K);
+    const bool poll = gap_tol > 0.0 || windowed;
+    // After each launch that passes a refresh epoch the count of instances
+    // left is copied to pinned memory; the host reads it one launch later,
+    // while the next launch runs, and stops once none is left.
+    int64_t pending = -1;   // launch whose count is in flight
+    for (int64_t g = 0; g < launches; ++g) {
         HIP_TRY(hipGraphLaunch(B.exec, B.stream));
-        if ((gap_tol > 0.0 || windowed) && (e + 1) % refresh_min == 0 && e + 1 < replays) {
-            int32_t act = 0;
-            HIP_TRY(hipMemcpyAsync(&act, B.ctl + CTL_LEFT, 4, hipMemcpyDeviceToHost, B.stream));
-            HIP_TRY(hipStreamSynchronize(B.stream));
-            if (act == 0) break;
+        if (!poll || g + 1 >= launches) continue;
+        if ((g + 1) * K / refresh_min == g * K / refresh_min) continue;   // no refresh in this launch
+        if (pending >= 0) {
+            HIP_TRY(hipEventSynchronize(B.poll_ev[pending & 1]));
+            if (B.poll[pending & 1] == 0) break;
         }
+        HIP_TRY(hipMemcpyAsync(B.poll + (g & 1), B.ctl + CTL_LEFT, 4, hipMemcpyDeviceToHost, B.stream));
+        HIP_TRY(hipEventRecord(B.poll_ev[g & 1], B.stream));
+        pending = g;
     }
     if (ms_out) {
         HIP_TRY(hipEventRecord(e1, B.stream));
@@ -4166,6 +4189,9 @@ extern "C" thetis_status thetis_batch_create(int32_t capacity, thetis_solver *co
         if (e == hipSuccess) e = hipMalloc((void **)&B.alist, 4 * (size_t)count);
         if (e == hipSuccess) e = hipMalloc((void **)&B.ctl, 4 * CTL_N);
         if (e == hipSuccess) e = hipMalloc((void **)&B.order, (size_t)kMaxBatchClasses * count);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&B.poll, 8, hipHostMallocDefault);
+        for (hipEvent_t &ev : B.poll_ev)
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             thetis_batch_destroy(Bp);
@@ -4317,6 +4343,9 @@ extern "C" thetis_status thetis_batch_destroy(thetis_batch *b) {
             for (thetis_solver *S : b->solvers)
                 if (S) S->batch_slots--;
         batch_drop_graph(*b);
+        for (hipEvent_t &ev : b->poll_ev)
+            if (ev) (void)hipEventDestroy(ev);
+        if (b->poll) (void)hipHostFree(b->poll);
         (void)hipFree(b->bi);
         if (b->bc) (void)hipFree(b->bc);
         (void)hipFree(b->rows_wg);
