@@ -463,9 +463,13 @@ thetis_status thetis_batch_set(thetis_batch *b, int32_t slot, thetis_solver *s);
  * (gap_tol <= 0: never) or after max_epochs.  epochs_done_host (NULL or
  * `capacity` entries) receives the epochs each slot ran; status_host (NULL
  * or `capacity` entries) 0 still running, 1 gap reached, 2 max_epochs
- * reached, 3 NaN/Inf, -1 empty slot.  One epoch of launches is captured as a
- * HIP graph and replayed (re-captured when the slot contents change the
- * largest class count or the tables move). */
+ * reached, 3 NaN/Inf, -1 empty slot.  K epochs of launches (K = the
+ * shortest refresh period of the occupied slots, at most 8, at most the
+ * epochs asked for) are captured as one HIP graph and replayed
+ * (re-captured when K, the launch configuration, the slot contents' largest
+ * class count or the tables change); a slot that has retired is left
+ * unchanged by the epochs of the last replay it does not need.  The host
+ * stops replaying once no slot is left, read one replay late. */
 thetis_status thetis_batch_run(thetis_batch *b, int32_t max_epochs, double gap_tol,
                                int32_t *epochs_done_host, int32_t *status_host);
 
