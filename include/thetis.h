@@ -464,8 +464,8 @@ thetis_status thetis_batch_set(thetis_batch *b, int32_t slot, thetis_solver *s);
  * `capacity` entries) receives the epochs each slot ran; status_host (NULL
  * or `capacity` entries) 0 still running, 1 gap reached, 2 max_epochs
  * reached, 3 NaN/Inf, -1 empty slot.  K epochs of launches (K = the
- * shortest refresh period of the occupied slots, at most 8, at most the
- * epochs asked for) are captured as one HIP graph and replayed
+ * shortest refresh period of the occupied slots, at most 8; 1 when the call
+ * asks for at most K epochs) are captured as one HIP graph and replayed
  * (re-captured when K, the launch configuration, the slot contents' largest
  * class count or the tables change); a slot that has retired is left
  * unchanged by the epochs of the last replay it does not need.  The host

@@ -4029,11 +4029,16 @@ thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol
     const bool windowed = B.window > 0 && B.window < occupied;
     const int64_t epochs = windowed ? (int64_t)max_epochs * (cdiv(occupied, B.window) + 1) : max_epochs;
     // One graph launch runs K epochs: the shortest refresh period (an
-    // instance can only stop at a refresh), at most kGraphEpochs, at most
-    // the epochs asked for.  An instance past its epoch cap or its stop is
-    // retired on the device, so the epochs of the last launch beyond what
-    // it needs leave it unchanged.
-    B.graph_epochs = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)refresh_min, kGraphEpochs, epochs}));
+    // instance can only stop at a refresh), at most kGraphEpochs.  An
+    // instance past its epoch cap or its stop is retired on the device, so
+    // the epochs of the last launch beyond what it needs leave it unchanged.
+    // A call that one launch would cover (a serving tick) replays a
+    // one-epoch graph instead: there is nothing to overlap with the host's
+    // check, and a K-epoch graph costs K times the capture whenever the slot
+    // contents change.
+    int64_t K = std::max<int64_t>(1, std::min<int64_t>((int64_t)refresh_min, kGraphEpochs));
+    if (epochs <= K) K = 1;
+    B.graph_epochs = (int32_t)K;
     if (!B.exec || B.captured_widen != B.widen || B.captured_grid != B.grid_mult || B.captured_strided != B.strided ||
         (B.grid_mult == 0 && B.captured_most != B.most_items) ||
         B.captured_cols != B.cols || B.captured_window != B.window || B.captured_epochs != B.graph_epochs) {
@@ -4046,7 +4051,7 @@ thetis_status batch_run_impl(thetis_batch &B, int32_t max_epochs, double gap_tol
         HIP_TRY(hipEventCreate(&e1));
         HIP_TRY(hipEventRecord(e0, B.stream));
     }
-    const int64_t K = B.graph_epochs, launches = cdiv(epochs, K);
+    const int64_t launches = cdiv(epochs, K);
     const bool poll = gap_tol > 0.0 || windowed;
     // After each launch that passes a refresh epoch the count of instances
     // left is copied to pinned memory; the host reads it one launch later,
