@@ -398,6 +398,28 @@ def test_async_schedule_converges_to_the_oracle_value(seed):
     assert np.array_equal(sol, osol)
 
 
+@pytest.mark.parametrize("prox", [False, True])
+def test_set_beta_equals_a_solver_made_with_that_beta(prox):
+    """thetis_set_beta recomputes everything beta enters (the per-coordinate
+    curvatures beta ||A_j||^2 + rho, the blocks' stored bounds, Lmax and, with
+    the prox term, rho = 1/beta): a solver made with beta 10 and set to 3
+    before its first epoch follows the solver made with beta 3, bit for bit,
+    and so does the FP64 oracle made with beta 3."""
+    for name, inst in (("vc_er", I.vc_er(800, 4000, seed=6)), ("mc_grid", I.mc_grid(side=16, k=4, seed=6))):
+        say(f"case set_beta {name} prox={prox}")
+        a = gpu_solver(inst, beta=10.0, precision=T.PREC_FP64, prox=prox, seed=6)
+        T.thetis_set_beta(a.h, 3.0)
+        b = gpu_solver(inst, beta=3.0, precision=T.PREC_FP64, prox=prox, seed=6)
+        lp, o = oracle_solver(inst, beta=3.0, prox=prox, seed=6)
+        a.run(20)
+        b.run(20)
+        o.run(20)
+        assert np.array_equal(a.y, b.y)
+        assert np.abs(a.y - o.y).max() <= 1e-10
+        a.close()
+        b.close()
+
+
 def test_gap_stop_and_reset():
     inst = I.vc_er(600, 2400, seed=5)
     g = gpu_solver(inst, seed=5)
