@@ -214,3 +214,23 @@ def test_batch_rejects_mixed_kinds():
     d = T.Solver(T.Instance(I.mc_grid(side=5, k=3, seed=1)))
     with pytest.raises(T.ThetisError):
         T.Batch([a, d])
+
+
+def test_batch_run_lengths_around_the_graph_period():
+    """One captured graph runs several epochs (the refresh period): runs of
+    0 epochs, fewer than, exactly and more than a period, one after another
+    on the same batch, leave every instance where the same runs alone do."""
+    say("case batch run lengths 0, 3, 5, 7, 13")
+    insts = mixed_instances()[:4]
+    alone, batched = pair(insts, precision=T.PREC_FP64, refresh_every=5)
+    b = T.Batch(batched)
+    total = 0
+    for n in (0, 3, 5, 7, 13):
+        done = b.run(n)
+        assert list(done) == [n] * len(batched)
+        for s in alone:
+            s.run(n)
+        total += n
+        for sa, sb in zip(alone, batched):
+            assert sb.epoch == total
+            assert np.array_equal(sa.y, sb.y)
