@@ -531,6 +531,32 @@ def test_full_size_ba_config_parity():
 FP32_BA_BAND_COUNTS = (0, 0)
 
 
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+def test_full_size_det_runs_are_bit_reproducible(prec_name):
+    """DET at the benchmark's size and launch configuration: three solves
+    of 100 epochs (one solver reset and rerun, a second solver) end at the
+    same bits, as they must when every class launch covers each of its
+    columns once and the classes share no row."""
+    say(f"case full-size determinism vc_ba n=2000000 {prec_name}")
+    prec = T.PREC_FP64 if prec_name == "fp64" else T.PREC_FP32
+    inst = I.vc_ba(2_000_000, seed=0)
+    h = T.Instance(inst)
+    g = T.Solver(h, beta=10.0, precision=prec, refresh_every=5, seed=0)
+    g.run(100)
+    y1 = g.y
+    g.reset()
+    g.run(100)
+    y2 = g.y
+    g.close()
+    g2 = T.Solver(h, beta=10.0, precision=prec, refresh_every=5, seed=0)
+    g2.run(100)
+    y3 = g2.y
+    g2.close()
+    say(f"  max|y1-y2|={np.abs(y1 - y2).max():.3e} max|y1-y3|={np.abs(y1 - y3).max():.3e}")
+    assert np.array_equal(y1, y2)
+    assert np.array_equal(y1, y3)
+
+
 @pytest.mark.timeout(1200)
 def test_full_size_multiway_cut_200_epochs():
     """The multiway-cut workload at full size (1024 x 1024 grid, k = 8, FP32,
