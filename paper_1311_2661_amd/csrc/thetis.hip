@@ -398,17 +398,30 @@ __device__ __forceinline__ void sweep_hub(const Dev<P> &a, const Sched<typename 
     const R d = yn - y;
     if (tid == 0) store_x<P>(a.x + j, yn);
     if (d != R(0)) {
-        for (int32_t e = e0 + tid; e < e1; e += kWG) {
-            const int32_t o = e - e0;
+        // the staged entries: rows and old values from LDS, stores only
+        const int32_t staged = min(e1 - e0, (int32_t)TILE);
+        for (int32_t o = tid; o < staged; o += kWG) {
             R ve = R(1);
-            int32_t re = 0;
-            if (has_vals<VM>() || o >= TILE) re = sched_entry<VM>(sc, e, ve);
-            const R dv = has_vals<VM>() ? d * ve : d;
-            if (o < TILE) r_add(a.r + st_row[o], st_r[o], dv, a.async_mode);
-            else {
-                R *p = a.r + re;
-                r_add(p, a.async_mode ? R(0) : *p, dv, a.async_mode);
+            if (has_vals<VM>()) (void)sched_entry<VM>(sc, e0 + o, ve);
+            r_add(a.r + st_row[o], st_r[o], has_vals<VM>() ? d * ve : d, a.async_mode);
+        }
+        // the rest, four entries per thread in flight: their row loads, then
+        // their residual loads, then the stores (the column's rows are
+        // distinct, so no store feeds a later load)
+        for (int32_t base = e0 + TILE; base < e1; base += 4 * kWG) {
+            int32_t re[4];
+            R ve[4], rv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int32_t e = base + t * kWG + tid;
+                ve[t] = R(1);
+                re[t] = e < e1 ? sched_entry<VM>(sc, e, ve[t]) : -1;
             }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) rv[t] = re[t] >= 0 && !a.async_mode ? a.r[re[t]] : R(0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (re[t] >= 0) r_add(a.r + re[t], rv[t], has_vals<VM>() ? d * ve[t] : d, a.async_mode);
         }
     }
 }
