@@ -168,6 +168,39 @@ def test_fp64_hubs_beyond_the_lds_tile_and_every_lane_group():
     assert np.abs(g.y - o.y).max() < 1e-10
 
 
+@pytest.mark.parametrize("kind", ["valued", "signed"])
+def test_fp64_hub_with_values_beyond_the_lds_tile(kind):
+    """A hub column of 5000 entries (past the 2048-entry LDS tile) whose
+    entries carry general values or signs: rows a x_0 + b x_i >= 1 with
+    a, b in [0.5, 2] ("valued"), or x_0 - x_i >= -1/2 and x_0 + x_i >= 1/2
+    alternating ("signed", every value +-1).  Both the staged and the
+    re-read part of the hub's scatter run; FP64 DET iterates and every
+    reduction against the oracle's replay."""
+    say(f"case fp64 hub past the LDS tile, {kind} entries")
+    rng = np.random.default_rng(11)
+    leaves = 5000
+    n = leaves + 1
+    cols = np.stack([np.zeros(leaves, np.int32), np.arange(1, n, dtype=np.int32)], axis=1).ravel()
+    if kind == "valued":
+        val = rng.uniform(0.5, 2.0, 2 * leaves)
+        b = np.ones(leaves)
+    else:
+        val = np.ones(2 * leaves)
+        val[1::4] = -1.0                 # odd rows: x_0 - x_i >= -1/2
+        b = np.where(np.arange(leaves) % 2 == 0, 0.5, -0.5)
+    inst = I.LPInstance(m=leaves, n=n, row_ptr=np.arange(0, 2 * leaves + 1, 2, dtype=np.int64),
+                        col_idx=cols, val=val, b=b, c=rng.uniform(1, 10, n), u=np.ones(n),
+                        sense=np.ones(leaves, dtype=np.int8))
+    g = gpu_solver(inst, beta=10.0, precision=T.PREC_FP64, seed=2)
+    lp, o = oracle_solver(inst, beta=10.0, seed=2)
+    g.run(12)
+    o.run(12)
+    assert np.abs(g.y - o.y).max() < 1e-10
+    gm, om = g.metrics(), o.metrics()
+    for k in ("F", "lp_value", "linf", "max_viol", "dual_bound"):
+        assert rel(gm[k], om[k]) < 1e-10, k
+
+
 @pytest.mark.parametrize("seed", range(9))
 def test_fp64_random_lp_sweep(seed):
     """Seeded LPs of mixed shape (instances.mixed_lp), with the step rule and the
