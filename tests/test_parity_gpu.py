@@ -431,6 +431,36 @@ def test_async_schedule_converges_to_the_oracle_value(seed):
     assert np.array_equal(sol, osol)
 
 
+def test_async_schedule_with_a_hub_past_the_lds_tile():
+    """ASYNC with a 5000-entry hub (atomic scatter past the LDS tile) on a
+    star plus 20000 random edges among its leaves: a certified gap below
+    1e-5 and F within 1e-4 of the oracle's DET run to the same gap; the
+    rounded cover is valid."""
+    say("case async hub past the LDS tile")
+    rng = np.random.default_rng(21)
+    n = 5001
+    star = np.stack([np.zeros(n - 1, np.int64), np.arange(1, n, dtype=np.int64)], axis=1)
+    pairs = set()
+    while len(pairs) < 20000:
+        u, v = sorted(rng.integers(1, n, 2).tolist())
+        if u != v:
+            pairs.add((u, v))
+    edges = np.concatenate([star, np.array(sorted(pairs), dtype=np.int64)])
+    inst = I.vc_lp(n, edges, rng.uniform(1, 10, n))
+    g = gpu_solver(inst, beta=10.0, schedule=T.SCHED_ASYNC, step_scale=0.5, precision=T.PREC_FP32, seed=5)
+    lp, o = oracle_solver(inst, beta=10.0, seed=5)
+    done = g.run(10000, gap_tol=1e-5)
+    o.run(1500)
+    gm, om = g.metrics(), o.metrics()
+    say(f"  epochs {done}; gap {gm['gap']:.2e}; F {gm['F']:.8g} vs {om['F']:.8g}")
+    assert om["gap"] < 1e-5
+    assert gm["gap"] <= 1e-5 + 1e-12
+    assert rel(gm["F"], om["F"]) <= 1e-4
+    sol, cost, aux = g.round(T.ROUND_VC_THRESH)
+    assert g.check(T.ROUND_VC_THRESH) == (True, 0)
+    assert np.all(sol[edges[:, 0]] | sol[edges[:, 1]])
+
+
 @pytest.mark.parametrize("prox", [False, True])
 def test_set_beta_equals_a_solver_made_with_that_beta(prox):
     """thetis_set_beta recomputes everything beta enters (the per-coordinate
