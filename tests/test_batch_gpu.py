@@ -234,3 +234,26 @@ def test_batch_run_lengths_around_the_graph_period():
         for sa, sb in zip(alone, batched):
             assert sb.epoch == total
             assert np.array_equal(sa.y, sb.y)
+
+
+def test_batch_with_a_hub_past_the_lds_tile():
+    """A 5000-entry hub column (its scatter re-reads the entries past the
+    2048-entry LDS tile) batched with ordinary instances: every instance
+    equals its solve alone, bit for bit (FP32 and FP64)."""
+    say("case batch with a hub past the LDS tile")
+    rng = np.random.default_rng(31)
+    n = 5001
+    star = np.stack([np.zeros(n - 1, np.int64), np.arange(1, n, dtype=np.int64)], axis=1)
+    extra = rng.integers(1, n, (8000, 2))
+    extra = extra[extra[:, 0] != extra[:, 1]]
+    edges = np.unique(np.sort(np.concatenate([star, extra]), axis=1), axis=0)
+    hub = I.vc_lp(n, edges, rng.uniform(1, 10, n))
+    for prec in (T.PREC_FP32, T.PREC_FP64):
+        insts = [hub, I.vc_ba(5000, seed=2), I.mis_regular(800, 7, seed=3)]
+        alone, batched = pair(insts, precision=prec)
+        for s in alone:
+            s.run(17)
+        done = T.Batch(batched).run(17)
+        assert list(done) == [17] * len(insts)
+        for sa, sb in zip(alone, batched):
+            assert_same(sa, sb)
