@@ -45,9 +45,12 @@ def test_vertex_cover_threshold_lemma(g):
     assert aux[0] == pytest.approx(min(0.5, (1 - eps) / 2), abs=1e-15)
     assert cost == pytest.approx(float(w @ sol))
     if eps < 1:
+        # 1 - eps carries the rounding of eps (about one ulp of 1), which the
+        # division magnifies by 1/(1 - eps) when every edge is nearly empty
+        rel_err = 1e-12 + 4 * np.finfo(np.float64).eps / (1 - eps)
         xt = np.clip(x / (1 - eps), 0, 1)
-        assert np.all(xt[edges[:, 0]] + xt[edges[:, 1]] >= 1 - 1e-12)
-        assert cost <= 2 * float(w @ xt) + 1e-9
+        assert np.all(xt[edges[:, 0]] + xt[edges[:, 1]] >= 1 - rel_err)
+        assert cost <= 2 * float(w @ xt) * (1 + rel_err) + 1e-9
 
 
 @SETTINGS
@@ -91,3 +94,19 @@ def test_set_cover_threshold_covers_and_is_f_approximate_on_feasible_points(sys_
     f = max(len(r) for r in rows)
     if all(x[r].sum() >= 1.0 for r in map(np.array, rows)):
         assert cost <= f * float(c @ x) + 1e-9
+
+
+def test_vertex_cover_threshold_when_every_edge_is_nearly_empty():
+    """eps close to 1 (both ends of the edge near 0): the threshold rule still
+    returns a cover (T is formed from fl(x_u + x_v)/2 directly), while the
+    scaled point x/(1 - eps) meets its edge row only up to the rounding of
+    1 - eps magnified by 1/(1 - eps)."""
+    edges = np.array([[0, 1]])
+    x = np.array([1e-9, 1e-9 + 3e-17])
+    lp = O.OracleLP(I.vc_lp(2, edges, np.array([1.0, 2.0])))
+    sol, cost, aux = lp.round(x, O.RULE_VC_THRESH)
+    assert lp.check(O.RULE_VC_THRESH, sol) == (True, 0)
+    assert aux[0] == pytest.approx((x[0] + x[1]) / 2, rel=1e-15)
+    eps = 1 - x[0] - x[1]
+    xt = np.clip(x / (1 - eps), 0, 1)
+    assert abs(xt.sum() - 1) <= 4 * np.finfo(np.float64).eps / (1 - eps)
