@@ -19,7 +19,8 @@ from hypothesis import strategies as st
 from oracle import oracle as O
 from paper_1311_2661_amd import instances as I
 
-SETTINGS = settings(max_examples=150, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+SETTINGS = settings(max_examples=150, deadline=None, derandomize=True, database=None,
+                    suppress_health_check=[HealthCheck.too_slow])
 
 
 @st.composite
