@@ -348,8 +348,10 @@ __device__ __forceinline__ void sweep_group(const Dev<P> &a, const Sched<typenam
 }
 
 // High-degree column: one workgroup.  The gather is unrolled four deep so
-// each thread keeps four residual loads in flight; the gathered entries and
-// their rows are staged in LDS so the scatter does not re-read global memory.
+// each thread keeps four residual loads in flight; the first HubTile
+// gathered entries and their rows are staged in LDS so their scatter does not
+// re-read global memory, and the scatter of the rest keeps four entries per
+// thread in flight.
 template <class P>
 struct HubTile {
     static constexpr int n = sizeof(typename P::R) == 4 ? 2048 : 1024;
@@ -3846,6 +3848,9 @@ namespace {
 struct Choice {
     int widen, grid_mult, strided, cols;
 };
+// the tuner's choices by batch shape, for the life of the process; batches
+// made or tuned on different threads share it under this lock
+std::mutex g_tuned_mu;
 std::map<uint64_t, Choice> &tuned_choices() {
     static std::map<uint64_t, Choice> m;
     return m;
@@ -4148,6 +4153,7 @@ void batch_signature(thetis_batch &B) {
     mix((uint64_t)(maxdeg > 0 ? 64 - __builtin_clzll((uint64_t)maxdeg) : 0));
     mix((uint64_t)B.precision);
     B.signature = sig;
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
     auto it = tuned_choices().find(sig);
     if (it != tuned_choices().end()) {
         B.widen = it->second.widen;
@@ -4333,7 +4339,10 @@ extern "C" thetis_status thetis_batch_autotune(thetis_batch *b, int32_t epochs_p
         b->grid_mult = best.grid_mult;
         b->strided = best.strided;
         b->cols = best.cols;
-        tuned_choices()[b->signature] = best;
+        {
+            std::lock_guard<std::mutex> lock(g_tuned_mu);
+            tuned_choices()[b->signature] = best;
+        }
         if (choice) { choice[0] = best.widen; choice[1] = best.grid_mult; choice[2] = best.strided; choice[3] = best.cols; }
         return THETIS_OK;
     } catch (...) {
